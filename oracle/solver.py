@@ -1,0 +1,123 @@
+"""Correction field and time stepping (paper Secs. 2.1-2.4).
+
+Test infrastructure only (see the package docstring).
+
+Per theta-step n -> n+1 (t = (n+1) dt) for one scan path:
+  1. T~ and grad T~ at every boundary quadrature point (Eqs. 7-8).
+  2. Load vector (Eq. 18 with Eq. 10):
+        F_A = sum_{q on NEUMANN faces} R_A(x_q) (-k grad T~_q . n_q) w_q dS_q
+  3. Dirichlet data (Eq. 11, enforced on the control variables whose
+     functions live on the bottom face): the L2 projection of T_c - T~ on the
+     trace space of those functions,
+        M_D u_D = sum_{q on DIRICHLET faces} R_A(x_q) (T_c - T~_q) w_q dS_q.
+  4. Theta-scheme (Eq. 20):
+        (M/dt + theta K) u^{n+1} = (M/dt - (1-theta) K) u^n
+                                   + theta F^{n+1} + (1-theta) F^n,
+     with the Dirichlet unknowns set to u_D and eliminated (their columns
+     move to the right-hand side).  The reduced matrix is constant, so it is
+     factorised once by scipy's sparse LU (library primitive).
+  5. T = T~ + T^ (Eq. 21) for evaluation.
+
+Initial state: u^0 = T_c (T^(x, 0) = T_c, and T~(x, 0) = 0), F^0 = 0.
+
+Readings: Dirichlet values by L2 projection (the paper names no method);
+SOURCE_PLANE faces take no load (the kernel is adiabatic on the plane that
+holds the sources); with no Dirichlet face the problem is pure Neumann.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import bspline, iga, pointsource
+
+NEUMANN, DIRICHLET, SOURCE_PLANE = 0, 1, 2
+
+
+class Model:
+    def __init__(self, patch, material, scan, theta=0.5, kernel_scale=1.0, path=0,
+                 assemble=True):
+        self.patch, self.mat = patch, material
+        self.scan = scan.path(path) if scan.n_paths > 1 or path else scan
+        self.theta, self.s = theta, kernel_scale
+        self.dt = self.scan.dt
+        self.bt = iga.boundary_tables(patch)
+        face = self.bt["face"]
+        role = np.asarray(patch.face_role)[face]
+        self.neu = np.nonzero(role == NEUMANN)[0]
+        self.dir = np.nonzero(role == DIRICHLET)[0]
+        dfaces = [f for f in range(6) if patch.face_role[f] == DIRICHLET]
+        D = np.unique(np.concatenate([iga.dirichlet_dofs(patch, f) for f in dfaces])) \
+            if dfaces else np.zeros(0, int)
+        self.D = D
+        mask = np.ones(patch.n_dof, bool)
+        mask[D] = False
+        self.I = np.nonzero(mask)[0]
+        R = self.bt["R"]
+        if len(D):
+            Rd = R[self.dir][:, D]
+            self.M_D = (Rd.T @ sp.diags(self.bt["wdS"][self.dir]) @ Rd).tocsc()
+            self._lu_D = spla.splu(self.M_D)
+        self.u = np.full(patch.n_dof, material.T0)
+        self.F = np.zeros(patch.n_dof)
+        self.step = 0
+        if assemble:
+            self.M, self.K = iga.assemble_mk(patch, material)
+            self.A = (self.M / self.dt + theta * self.K).tocsr()
+            self.B = (self.M / self.dt - (1.0 - theta) * self.K).tocsr()
+            self._lu = spla.splu(self.A[self.I][:, self.I].tocsc())
+            self.A_ID = self.A[self.I][:, self.D].tocsr()
+
+    # -- Eqs. 7-8 at the boundary points --------------------------------------
+    def boundary_field(self, step, which=None):
+        x = self.bt["x"] if which is None else self.bt["x"][which]
+        sc = self.scan
+        return pointsource.field(x, sc.xyz, sc.tick, sc.energy, step, sc, self.mat, self.s)
+
+    # -- Eq. 18 with Eq. 10 ---------------------------------------------------
+    def load_vector(self, G_neu):
+        q = -self.mat.k * np.einsum("qi,qi->q", G_neu, self.bt["n"][self.neu]) \
+            * self.bt["wdS"][self.neu]
+        return self.bt["R"][self.neu].T @ q
+
+    # -- Eq. 11 by L2 projection ----------------------------------------------
+    def dirichlet_values(self, T_dir):
+        if len(self.D) == 0:
+            return np.zeros(0)
+        Rd = self.bt["R"][self.dir][:, self.D]
+        b = Rd.T @ ((self.mat.T0 - T_dir) * self.bt["wdS"][self.dir])
+        return self._lu_D.solve(b)
+
+    # -- Eq. 20 ---------------------------------------------------------------
+    def advance(self, n=1):
+        for _ in range(n):
+            s1 = self.step + 1
+            idx = np.concatenate([self.neu, self.dir])
+            T, G = self.boundary_field(s1, idx)
+            nn = len(self.neu)
+            F1 = self.load_vector(G[:nn])
+            uD = self.dirichlet_values(T[nn:])
+            rhs = self.B @ self.u + self.theta * F1 + (1.0 - self.theta) * self.F
+            u1 = np.empty_like(self.u)
+            u1[self.D] = uD
+            r_I = rhs[self.I] - self.A_ID @ uD
+            u1[self.I] = self._lu.solve(r_I)
+            self.u, self.F, self.step = u1, F1, s1
+        return self
+
+    # -- Eq. 21 ---------------------------------------------------------------
+    def evaluate(self, xi, u=None, step=None, correction_only=False):
+        """T and grad T at parametric points xi [Q, 3] (or only the
+        correction T^ and its gradient with correction_only)."""
+        u = self.u if u is None else u
+        step = self.step if step is None else step
+        x, J, idx, R, dR = bspline.geometry(self.patch, np.atleast_2d(xi))
+        uh = np.sum(R * u[idx], axis=1)
+        gxi = np.einsum("qlj,ql->qj", dR, u[idx])
+        gx = np.einsum("qji,qj->qi", np.linalg.inv(J), gxi)
+        if correction_only:
+            return uh, gx, x
+        sc = self.scan
+        Tt, Gt = pointsource.field(x, sc.xyz, sc.tick, sc.energy, step, sc, self.mat, self.s)
+        return Tt + uh, Gt + gx, x
