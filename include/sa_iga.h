@@ -1,0 +1,250 @@
+/*
+ * sa_iga.h - C ABI of the MI355X (gfx950) semi-analytical isogeometric
+ * thermal model for laser powder bed fusion.
+ *
+ * The model (Yang, Ji, Moeller, Ayas, "Efficient thermal simulation in metal
+ * additive manufacturing via semi-analytical isogeometric analysis"):
+ *
+ *   T = T~ + T^                                             (Eq. 6)
+ *   T~(x,t) = sum over switched-on point sources I of
+ *       s E_I / (rho c_p [4 pi alpha D_I]^{3/2}) exp(-|x - x_I|^2 / (4 alpha D_I)),
+ *       D_I = t - t_I + r^2/(8 alpha),  alpha = k/(rho c_p)   (Eqs. 2, 7, 8)
+ *   T^ solves the heat equation with the transferred data   (Eqs. 9-11)
+ *       -k dT^/dn = k dT~/dn on the lateral (NEUMANN) faces,
+ *       T^ = T_c - T~ on the bottom (DIRICHLET) face,
+ *   discretised with NURBS (Eqs. 13-18) and stepped with the theta-scheme
+ *       (M/dt + theta K) u^{n+1} = (M/dt - (1-theta) K) u^n
+ *                                  + theta F^{n+1} + (1-theta) F^n   (Eq. 20)
+ *   F_A = sum_q R_A(x_q) (-k grad T~(x_q) . n_q) w_q dS_q  over NEUMANN faces (Eq. 18).
+ *
+ * Every function returns an int status (sa_status).  On failure the message
+ * is available from sa_iga_last_error() (thread-local); objects are left in
+ * their previous state unless stated otherwise.  No C++ exception crosses
+ * this boundary.
+ *
+ * Conventions fixed by this interface (shared with the CPU reference):
+ *   - Units are SI (m, s, W, J, K).
+ *   - Parametric faces f = 0..5 are xi0=0, xi0=1, xi1=0, xi1=1, xi2=0, xi2=1.
+ *   - DOF (control point) index A = a0 + n0*(a1 + n1*a2).
+ *   - Boundary quadrature points: face 0 first, then 1, ..., 5; on face f
+ *     with fixed direction d and in-face directions a < b, the points form a
+ *     row-major grid over (b, a) (a fastest); along each in-face direction
+ *     they are ordered by element, then by the quad_face Gauss points of
+ *     that element.
+ *   - Source i of a path is switched on at tick_i * delta with
+ *     delta = dt / sources_per_step; theta-step n -> n+1 ends at
+ *     t = (n+1) dt and includes the sources with tick <= (n+1)*sources_per_step.
+ *     Causality is decided on these integers; the age t - t_i is formed as
+ *     ((n+1)*sources_per_step - tick_i) * delta.
+ *   - The initial state is u = T_c (every control value), F = 0.
+ *   - The Dirichlet values at t^{n+1} are the L2 projection of T_c - T~ on
+ *     the trace space of the control variables of the DIRICHLET faces.
+ */
+#ifndef SA_IGA_H
+#define SA_IGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sa_iga sa_iga;   /* opaque; owns its device memory */
+
+enum sa_status {
+  SA_OK = 0,
+  SA_EINVAL = -1,    /* invalid argument (NULL, sizes, knots, weights, ticks, theta) */
+  SA_ENOMEM = -2,    /* host or device allocation failed */
+  SA_EDEVICE = -3,   /* HIP runtime error or no gfx950 device */
+  SA_ENOCONV = -4,   /* PCG did not reach pcg_rtol within pcg_max_iter */
+  SA_ERANGE = -5,    /* query point outside [0,1]^3 or path index out of range */
+  SA_ESTATE = -6     /* object in a sticky error state (earlier ENOCONV / NaN) */
+};
+
+enum sa_face_role {
+  SA_FACE_NEUMANN = 0,       /* lateral, adiabatic: takes the flux load F (Eq. 10) */
+  SA_FACE_DIRICHLET = 1,     /* bottom: T = T_c (Eq. 11) */
+  SA_FACE_SOURCE_PLANE = 2   /* top: holds the sources; adiabatic by Eq. 8, no load */
+};
+
+enum sa_precision {
+  SA_PREC_FP64 = 0,          /* every source in FP64 */
+  SA_PREC_FP32_FAR = 1,      /* sources older than tau_near summed in FP32 (exp2),
+                                FP32 tile partials accumulated in FP64; near
+                                sources, loads and the solve in FP64 */
+  SA_PREC_SURROGATE = 2      /* far sources replaced by the learned network, near in FP64 */
+};
+
+enum sa_precond {
+  SA_PRECOND_JACOBI = 0,
+  SA_PRECOND_FD = 1          /* fast diagonalisation of a Kronecker approximation */
+};
+
+typedef struct {
+  int32_t degree[3];           /* p_d >= 1 */
+  int32_t n_ctrl[3];           /* n_d >= p_d + 1 */
+  const double *knots[3];      /* n_d + p_d + 1 values, non-decreasing, open
+                                  (p_d+1 repeated end knots), from 0 to 1 */
+  const double *ctrl_xyzw;     /* [n2][n1][n0][4]: x, y, z (m), weight > 0 */
+  int32_t face_role[6];        /* sa_face_role per parametric face */
+  int32_t quad_vol[3];         /* Gauss points per element per direction (1..16) */
+  int32_t quad_face;           /* Gauss points per direction on faces (1..16) */
+} sa_patch;
+
+typedef struct {
+  double k;                    /* conductivity W/(m K) > 0 */
+  double rho;                  /* density kg/m^3 > 0 */
+  double cp;                   /* heat capacity J/(kg K) > 0 */
+  double T0;                   /* platform and initial temperature T_c (K) */
+} sa_material;
+
+typedef struct {
+  double theta;                /* theta-scheme parameter in [0,1]; default 0.5 */
+  double kernel_scale;         /* s in the kernel; default 1 (Eq. 8 as printed) */
+  int32_t precision;           /* sa_precision; default SA_PREC_FP64 */
+  double tau_near;             /* near/far age split (s) for FP32_FAR/SURROGATE; default 2e-4 */
+  double pcg_rtol;             /* stop when |r| <= pcg_rtol |rhs|; default 1e-13 */
+  int32_t pcg_max_iter;        /* default 2000 */
+  int32_t preconditioner;      /* sa_precond; default SA_PRECOND_FD */
+  int32_t timing;              /* nonzero: time every stage with HIP events (sa_stats) */
+  int32_t points_per_lane;     /* kernel-sum register blocking (1, 2, 4); 0 = tuned default */
+  int32_t waves_per_group;     /* kernel-sum waves per workgroup (1..16); 0 = tuned default */
+  int32_t chunk_sources;       /* sources per source chunk of the sum; 0 = tuned default */
+} sa_solver_options;
+
+typedef struct {
+  int32_t n_paths;             /* independent scan strategies on the same patch */
+  const int64_t *src_offset;   /* [n_paths+1]; path p owns rows src_offset[p] .. src_offset[p+1]-1 */
+  const double *xyz;           /* [N][3] source positions (m) */
+  const int64_t *tick;         /* [N] activation ticks >= 1, non-decreasing within a path */
+  const double *energy;        /* [N] source energies (J) */
+  const int32_t *n_steps;      /* [n_paths] theta-steps of each path (>= 0) */
+  double dt;                   /* theta-step length (s) > 0 */
+  int32_t sources_per_step;    /* ticks per theta-step >= 1 */
+  double spot_radius;          /* r (m) >= 0: D = age + r^2/(8 alpha) */
+  const sa_solver_options *opt;  /* NULL = defaults */
+} sa_scan_path;
+
+typedef struct {
+  int32_t n_ctrl[3];
+  int64_t n_dof;
+  int64_t n_bpts;              /* boundary quadrature points (all six faces) */
+  int64_t face_offset[7];      /* points of face f: face_offset[f] .. face_offset[f+1]-1 */
+  int32_t n_paths;
+  int64_t n_sources;
+  int64_t n_dirichlet;         /* control variables fixed by DIRICHLET faces */
+} sa_info;
+
+enum sa_stage {
+  SA_STAGE_COEFF = 0,          /* per-step source coefficients */
+  SA_STAGE_SUM = 1,            /* kernel sum at the boundary points (dominant) */
+  SA_STAGE_REDUCE = 2,         /* chunk reduction, flux and Dirichlet densities */
+  SA_STAGE_LOAD = 3,           /* load-vector and projection right-hand-side gathers */
+  SA_STAGE_DIRICHLET = 4,      /* projection solve */
+  SA_STAGE_RHS = 5,            /* theta-scheme right-hand side */
+  SA_STAGE_PCG = 6,            /* theta-scheme solve */
+  SA_STAGE_OTHER = 7,
+  SA_N_STAGES = 8
+};
+
+typedef struct {
+  int64_t steps;               /* theta-steps advanced, summed over paths */
+  int64_t pairs;               /* source x point pairs evaluated, summed */
+  int64_t pairs_near;          /* of which in FP64 (all of them with SA_PREC_FP64) */
+  int64_t pcg_iterations;      /* summed over steps and paths */
+  int32_t pcg_last_iterations;
+  double pcg_last_relres;
+  int64_t dirichlet_iterations;
+  double stage_ms[SA_N_STAGES];        /* device time per stage (timing != 0) */
+  int64_t stage_launches[SA_N_STAGES]; /* kernel launches per stage (timing != 0) */
+} sa_stats;
+
+/* Fill *opt with the defaults listed above. */
+int sa_iga_default_options(sa_solver_options *opt);
+
+/*
+ * Build the model on the current HIP device: basis and quadrature tables,
+ * M and K (Eqs. 16-17), boundary tables (Eq. 18), source tables, state
+ * u^0 = T_c, F^0 = 0.  All input arrays are copied; the caller keeps
+ * ownership.  *out receives a new object (NULL on failure).
+ * Errors: SA_EINVAL (invalid patch/material/scan/options), SA_ENOMEM,
+ * SA_EDEVICE (no device or HIP failure).
+ */
+int sa_iga_setup(const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan,
+                 sa_iga **out);
+
+/*
+ * Advance every path by n_steps theta-steps (Eq. 20); a path that has done
+ * its n_steps[p] steps stays as it is.  Runs on the object's stream and
+ * returns after the last step is complete.  SA_ENOCONV if a solve did not
+ * converge (the object then enters the sticky error state SA_ESTATE).
+ */
+int sa_iga_step(sa_iga *h, int32_t n_steps);
+
+/* Steps done so far by path `path`. */
+int sa_iga_get_step(sa_iga *h, int32_t path, int64_t *step);
+
+/*
+ * Temperature T = T~ + T^ (Eq. 21) and optionally its gradient at n
+ * parametric points xi [n][3] in [0,1]^3 of path `path`, at its current
+ * time.  T [n] and gradT [n][3] (may be NULL) are host arrays.
+ * SA_ERANGE if a point lies outside [0,1]^3 or path is out of range.
+ */
+int sa_iga_eval_temperature(sa_iga *h, int32_t path, int64_t n, const double *xi,
+                            double *T, double *gradT);
+
+/*
+ * Copy the current fields of path `path` to host arrays (any may be NULL):
+ * T_gp [n_bpts] and grad_gp [3][n_bpts] (component-major) = T~ and
+ * grad T~ at the boundary points at the path's current time (as summed by
+ * the last step), F [n_dof] = the load vector F^n, du [n_dof] = the control
+ * values of T^ minus T_c at step n (the state is carried as this deviation,
+ * so it is returned without the T_c offset; add T_c for T^).
+ */
+int sa_iga_get_boundary_fields(sa_iga *h, int32_t path, double *T_gp, double *grad_gp,
+                               double *F, double *du);
+
+/* Boundary quadrature tables (host arrays, any may be NULL): x [n_bpts][3],
+ * outward unit normals n [n_bpts][3], weights w dS [n_bpts]. */
+int sa_iga_get_boundary_points(sa_iga *h, double *x, double *normal, double *wdS);
+
+/* y = M x (which = 0) or y = K x (which = 1) with the assembled matrices of
+ * Eqs. 16-17; x, y are host arrays of n_dof values. */
+int sa_iga_apply_operator(sa_iga *h, int32_t which, const double *x, double *y);
+
+/*
+ * Evaluate T~ and grad T~ (Eqs. 7-8) of path `path` at time step*dt at n
+ * physical points x [n][3] (host arrays), with the precision form of the
+ * object.  T [n], grad [3][n] (component-major, may be NULL).
+ */
+int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n,
+                             const double *x, double *T, double *grad);
+
+int sa_iga_get_info(sa_iga *h, sa_info *info);
+int sa_iga_get_stats(sa_iga *h, sa_stats *stats);
+int sa_iga_reset_stats(sa_iga *h);
+
+/*
+ * Checkpoint of the mutable state (steps, u^n, F^n of every path).  With
+ * buf == NULL, *len receives the size needed.  sa_iga_load restores a
+ * checkpoint taken from an object built from the same inputs (SA_EINVAL if
+ * the sizes differ) and clears the sticky error state.
+ */
+int sa_iga_save(sa_iga *h, void *buf, size_t *len);
+int sa_iga_load(sa_iga *h, const void *buf, size_t len);
+
+/* Use the given hipStream_t (NULL = the object's own stream) for all work. */
+int sa_iga_set_stream(sa_iga *h, void *hip_stream);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *sa_iga_last_error(void);
+
+/* Free the object and its device memory.  NULL is ignored. */
+void sa_iga_destroy(sa_iga *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SA_IGA_H */

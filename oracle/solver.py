@@ -20,6 +20,12 @@ Per theta-step n -> n+1 (t = (n+1) dt) for one scan path:
 
 Initial state: u^0 = T_c (T^(x, 0) = T_c, and T~(x, 0) = 0), F^0 = 0.
 
+The state is carried as w = u - T_c.  Eqs. 9-11 are linear and the constant
+T_c solves them with zero data (K 1 = 0, the projection of the constant
+T_c is T_c 1), so w obeys the same theta-scheme with Dirichlet data
+-T~ and w^0 = 0; u = T_c + w.  This keeps the T_c offset out of the
+rounding of small corrections.
+
 Readings: Dirichlet values by L2 projection (the paper names no method);
 SOURCE_PLANE faces take no load (the kernel is adiabatic on the plane that
 holds the sources); with no Dirichlet face the problem is pure Neumann.
@@ -59,7 +65,7 @@ class Model:
             Rd = R[self.dir][:, D]
             self.M_D = (Rd.T @ sp.diags(self.bt["wdS"][self.dir]) @ Rd).tocsc()
             self._lu_D = spla.splu(self.M_D)
-        self.u = np.full(patch.n_dof, material.T0)
+        self.w = np.zeros(patch.n_dof)
         self.F = np.zeros(patch.n_dof)
         self.step = 0
         if assemble:
@@ -81,12 +87,22 @@ class Model:
             * self.bt["wdS"][self.neu]
         return self.bt["R"][self.neu].T @ q
 
+    @property
+    def u(self):
+        """Control values of T^."""
+        return self.mat.T0 + self.w
+
+    @u.setter
+    def u(self, value):
+        self.w = np.asarray(value, float) - self.mat.T0
+
     # -- Eq. 11 by L2 projection ----------------------------------------------
     def dirichlet_values(self, T_dir):
+        """Projection of T_c - T~ minus T_c (the deviation of u_D from T_c)."""
         if len(self.D) == 0:
             return np.zeros(0)
         Rd = self.bt["R"][self.dir][:, self.D]
-        b = Rd.T @ ((self.mat.T0 - T_dir) * self.bt["wdS"][self.dir])
+        b = Rd.T @ ((-T_dir) * self.bt["wdS"][self.dir])
         return self._lu_D.solve(b)
 
     # -- Eq. 20 ---------------------------------------------------------------
@@ -97,13 +113,13 @@ class Model:
             T, G = self.boundary_field(s1, idx)
             nn = len(self.neu)
             F1 = self.load_vector(G[:nn])
-            uD = self.dirichlet_values(T[nn:])
-            rhs = self.B @ self.u + self.theta * F1 + (1.0 - self.theta) * self.F
-            u1 = np.empty_like(self.u)
-            u1[self.D] = uD
-            r_I = rhs[self.I] - self.A_ID @ uD
-            u1[self.I] = self._lu.solve(r_I)
-            self.u, self.F, self.step = u1, F1, s1
+            wD = self.dirichlet_values(T[nn:])
+            rhs = self.B @ self.w + self.theta * F1 + (1.0 - self.theta) * self.F
+            w1 = np.empty_like(self.w)
+            w1[self.D] = wD
+            r_I = rhs[self.I] - self.A_ID @ wD
+            w1[self.I] = self._lu.solve(r_I)
+            self.w, self.F, self.step = w1, F1, s1
         return self
 
     # -- Eq. 21 ---------------------------------------------------------------
@@ -112,9 +128,10 @@ class Model:
         correction T^ and its gradient with correction_only)."""
         u = self.u if u is None else u
         step = self.step if step is None else step
+        w = u - self.mat.T0
         x, J, idx, R, dR = bspline.geometry(self.patch, np.atleast_2d(xi))
-        uh = np.sum(R * u[idx], axis=1)
-        gxi = np.einsum("qlj,ql->qj", dR, u[idx])
+        uh = self.mat.T0 + np.sum(R * w[idx], axis=1)
+        gxi = np.einsum("qlj,ql->qj", dR, w[idx])
         gx = np.einsum("qji,qj->qi", np.linalg.inv(J), gxi)
         if correction_only:
             return uh, gx, x

@@ -1,0 +1,126 @@
+// Launch wrappers of the gfx950 kernels (device code in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sa {
+
+// per-source coefficient record (FP64: 8 doubles, FP32: 8 floats); the
+// exponent of source i at a point x (centred coordinates, q2 = |x|^2) is
+//   arg_i(x) = c_i q2 + u_i . x + K_i,   c_i = -1/(4 alpha D_i),
+//   u_i = -2 c_i x_i,  K_i = c_i |x_i|^2 + ln(s E_i / (rho c_p (4 pi alpha D_i)^{3/2}))
+// (in base 2 for the FP32 record), so that T~_i(x) = exp(arg_i) and
+// grad T~_i(x) = exp(arg_i) (2 c_i x + u_i).
+constexpr int kCoefStride = 8;
+
+struct CoeffParams {
+  int64_t now;            // (n+1) * sources_per_step
+  double delta;           // dt / sources_per_step
+  double shift;           // r^2 / (8 alpha)
+  double alpha;
+  double rc;              // rho c_p
+  double scale;           // kernel scale s
+};
+
+void launch_coeff(hipStream_t st, int64_t n_act, int64_t n_far32, const int64_t *tick, const double *sx,
+                  const double *sy, const double *sz, const double *E, const CoeffParams &cp,
+                  double *c64, float *c32);
+
+struct SumPlan {
+  int points_per_lane;    // 1, 2 or 4
+  int waves;              // waves per workgroup
+  int n_chunks_far, chunk_far;     // FP32 chunks over [0, n_far)
+  int n_chunks_near, chunk_near;   // FP64 chunks over [n_far, n_act)
+  int64_t n_far, n_act;
+  int64_t nq, part_stride;
+};
+
+void launch_sum(hipStream_t st, const SumPlan &pl, const double *px, const double *py, const double *pz,
+                const double *pq2, const float *fx, const float *fy, const float *fz, const float *fq2,
+                const double *c64, const float *c32, double *part);
+
+// reduce chunk partials; T, grad; per-point load density:
+//   NEUMANN: -k (grad . n) w dS,  DIRICHLET: -T~ w dS,  else 0
+void launch_finalize(hipStream_t st, int64_t nq, int n_chunks, int64_t part_stride, const double *part,
+                     const double *px, const double *py, const double *pz, const double *nx,
+                     const double *ny, const double *nz, const double *wdS, const int8_t *role,
+                     double kcond, double *T, double *gx, double *gy, double *gz, double *ld);
+
+// out[r] = sum_e val[e] * in[col[e]] over rows [0, nrow) of a CSR
+void launch_gather(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,
+                   const double *val, const double *in, double *out);
+
+// ---- solver --------------------------------------------------------------
+struct PcgScalars {
+  double bnorm2;          // |b_free|^2
+  double rz;              // r . z
+  double rr;              // r . r (latest)
+  double alpha, beta;
+  int32_t iter;
+  int32_t done;           // 1 = converged, 2 = breakdown
+  double rtol2;           // rtol^2
+  int32_t pad[2];
+};
+
+struct StencilOp {
+  int n[3];
+  int hw[3];
+  int n_off;
+  int64_t nrow;
+  const double *A;        // [n_off][nrow]
+  const uint8_t *free_mask;  // 1 = unknown row (NULL: all free)
+};
+
+struct CsrOp {
+  int64_t nrow;
+  const int64_t *rowptr;
+  const int32_t *col;
+  const double *val;
+};
+
+struct FdOp {
+  int n[3], lo[3], m[3];
+  const double *U[3];
+  const double *inv_diag;
+  double *t1, *t2;        // scratch [m0 m1 m2]
+};
+
+// theta-scheme initial residual:
+//   rhs = B v + theta F1 + (1-theta) F0 on free rows; x = v with fixed rows
+//   replaced by vD (scattered from dir_val over dir_dofs); r = rhs - A x on
+//   free rows, 0 on fixed rows; partials of |rhs_free|^2.
+void launch_theta_init(hipStream_t st, const StencilOp &A, const double *Bval, const double *v,
+                       const double *F1, const double *F0, double theta, double *x, double *r,
+                       double *part);
+void launch_scatter_dirichlet(hipStream_t st, int64_t nD, const int64_t *dofs, const double *vals,
+                              double *x);
+
+// generic PCG pieces (operator is either a stencil or a CSR)
+void launch_csr_init(hipStream_t st, const CsrOp &A, const double *b, const double *x, double *r,
+                     double *part);
+void launch_jacobi(hipStream_t st, int64_t n, const double *inv_diag, const double *r, double *z,
+                   double *part, PcgScalars *sc);
+void launch_fd(hipStream_t st, const FdOp &F, int64_t n, const double *r, double *z, double *part,
+               PcgScalars *sc);
+void launch_pcg_start(hipStream_t st, int64_t n, int n_part_b, const double *part_b, int n_part_rz,
+                      const double *part_rz, const double *z, double *p, PcgScalars *sc, double rtol);
+void launch_stencil_apply_dot(hipStream_t st, const StencilOp &A, const double *p, double *q, double *part,
+                              PcgScalars *sc);
+void launch_csr_apply_dot(hipStream_t st, const CsrOp &A, const double *p, double *q, double *part,
+                          PcgScalars *sc);
+// alpha = rz / sum(part_pq); x += alpha p; r -= alpha q; partials of r.r
+void launch_pcg_update(hipStream_t st, int64_t n, int n_part, const double *part_pq, const double *p,
+                       const double *q, double *x, double *r, double *part_rr, PcgScalars *sc);
+// convergence check on sum(part_rr); beta = sum(part_rz)/rz; p = z + beta p
+void launch_pcg_direction(hipStream_t st, int64_t n, int n_part_rr, int n_part_rz, const double *part_rr,
+                          const double *part_rz, const double *z, double *p, PcgScalars *sc);
+
+int parts_for(int64_t n);      // number of partials produced by a vector kernel over n rows
+
+// point evaluation: out[i] = sum_e val[e] * u[col[e]] + add
+void launch_csr_eval(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,
+                     const double *val, const double *u, double *out);
+
+}  // namespace sa

@@ -1,0 +1,659 @@
+// gfx950 kernels of the semi-analytical IGA thermal model.
+//
+//  * k_coeff     per-step source coefficients (Eq. 8 with the finite-spot
+//                shift): FP64 records for every active source, FP32 base-2
+//                records for the far (old) ones.
+//  * k_sum       the point-source superposition (Eq. 7) at the boundary
+//                quadrature points.  Points live in lanes (P per lane),
+//                sources are wave-uniform and stream through scalar loads;
+//                each workgroup column sums one chunk of the source history.
+//  * k_finalize  fixed-order reduction of the chunk partials, gradient, and
+//                the per-point load densities of Eqs. 10-11 and 18.
+//  * k_gather    transpose-CSR gathers (load vector, projection rhs).
+//  * stencil / CSR operators, Jacobi and fast-diagonalisation
+//                preconditioners and the PCG steps for the theta-scheme
+//                (Eq. 20); every PCG kernel is a no-op once the device flag
+//                says the solve has converged.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace sa {
+
+constexpr int kBlock = 256;
+constexpr int kMaxParts = 1024;
+
+int parts_for(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  return (int)(g > kMaxParts ? kMaxParts : g);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 exponential: Cody-Waite reduction a = k ln2 + r (|r| <= ln2/2, two-part
+// ln2), degree-13 Taylor polynomial of e^r (truncation < 5e-18 relative),
+// scaling by 2^k with ldexp (underflows to 0 below the subnormal range).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_f64(double a) {
+  a = fmax(a, -1080.0);
+  const double kInvLn2 = 1.4426950408889634;
+  const double kShift = 6755399441055744.0;       // 1.5 * 2^52
+  const double kLn2Hi = 6.93147180369123816490e-01;
+  const double kLn2Lo = 1.90821492927058770002e-10;
+  const double t = fma(a, kInvLn2, kShift);
+  const double kf = t - kShift;
+  double r = fma(kf, -kLn2Hi, a);
+  r = fma(kf, -kLn2Lo, r);
+  double p = 1.0 / 6227020800.0;                  // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  const int k = __double2loint(t);                 // low word of t holds rint(a / ln2)
+  return __builtin_ldexp(p, k);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// sum over the block; every thread gets the result
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ double tot;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    tot = s;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// fixed-order sum of partials[0..n) by one block
+__device__ __forceinline__ double reduce_parts(const double *part, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  return block_sum(s);
+}
+
+// ---------------------------------------------------------------------------
+// source coefficients
+// ---------------------------------------------------------------------------
+__global__ void k_coeff(int64_t n_act, int64_t n_far32, const int64_t *__restrict__ tick,
+                        const double *__restrict__ sx, const double *__restrict__ sy,
+                        const double *__restrict__ sz, const double *__restrict__ E, CoeffParams cp,
+                        double *__restrict__ c64, float *__restrict__ c32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_act) return;
+  const double D = (double)(cp.now - tick[i]) * cp.delta + cp.shift;
+  const double c = -1.0 / (4.0 * cp.alpha * D);
+  const double x = sx[i], y = sy[i], z = sz[i];
+  const double amp = cp.scale * E[i] / (cp.rc * pow(4.0 * M_PI * cp.alpha * D, 1.5));
+  const double K = c * (x * x + y * y + z * z) + log(amp);
+  double *o = c64 + i * kCoefStride;
+  o[0] = c;
+  o[1] = -2.0 * c * x;
+  o[2] = -2.0 * c * y;
+  o[3] = -2.0 * c * z;
+  o[4] = K;
+  o[5] = 0.0;
+  o[6] = 0.0;
+  o[7] = 0.0;
+  if (i < n_far32) {
+    const double l2e = 1.4426950408889634;
+    float *f = c32 + i * kCoefStride;
+    f[0] = (float)(c * l2e);
+    f[1] = (float)(-2.0 * c * x * l2e);
+    f[2] = (float)(-2.0 * c * y * l2e);
+    f[3] = (float)(-2.0 * c * z * l2e);
+    f[4] = (float)(K * l2e);
+    f[5] = 0.0f;
+    f[6] = 0.0f;
+    f[7] = 0.0f;
+  }
+}
+
+void launch_coeff(hipStream_t st, int64_t n_act, int64_t n_far32, const int64_t *tick, const double *sx,
+                  const double *sy, const double *sz, const double *E, const CoeffParams &cp,
+                  double *c64, float *c32) {
+  if (n_act <= 0) return;
+  dim3 g((unsigned)((n_act + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_coeff, g, dim3(kBlock), 0, st, n_act, n_far32, tick, sx, sy, sz, E, cp, c64, c32);
+}
+
+// ---------------------------------------------------------------------------
+// kernel sum
+// ---------------------------------------------------------------------------
+struct SumArgs {
+  const double *px, *py, *pz, *pq2;
+  const float *fx, *fy, *fz, *fq2;
+  const double *c64;
+  const float *c32;
+  double *part;
+  int64_t nq, stride;
+  int64_t n_far, n_act;
+  int n_chunks_far, chunk_far, chunk_near;
+};
+
+constexpr int kTile32 = 128;   // FP32 sources summed before folding into FP64
+
+template <int P>
+__global__ __launch_bounds__(512) void k_sum(SumArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (64 * P) + lane;
+  const int chunk = blockIdx.y;
+  double x[P], y[P], z[P], q2[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    int64_t q = base + 64 * j;
+    q = q < a.nq ? q : a.nq - 1;
+    x[j] = a.px[q];
+    y[j] = a.py[q];
+    z[j] = a.pz[q];
+    q2[j] = a.pq2[q];
+  }
+  double s0[P], s1[P], sx[P], sy[P], sz[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) s0[j] = s1[j] = sx[j] = sy[j] = sz[j] = 0.0;
+
+  if (chunk < a.n_chunks_far) {
+    const int64_t lo = (int64_t)chunk * a.chunk_far;
+    const int64_t hi = lo + a.chunk_far < a.n_far ? lo + a.chunk_far : a.n_far;
+    float xf[P], yf[P], zf[P], qf[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      int64_t q = base + 64 * j;
+      q = q < a.nq ? q : a.nq - 1;
+      xf[j] = a.fx[q];
+      yf[j] = a.fy[q];
+      zf[j] = a.fz[q];
+      qf[j] = a.fq2[q];
+    }
+    const double ln2 = 0.6931471805599453;
+    for (int64_t t0 = lo; t0 < hi; t0 += kTile32) {
+      const int64_t t1 = t0 + kTile32 < hi ? t0 + kTile32 : hi;
+      float f0[P], f1[P], fx_[P], fy_[P], fz_[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) f0[j] = f1[j] = fx_[j] = fy_[j] = fz_[j] = 0.0f;
+      for (int64_t i = t0; i < t1; ++i) {
+        const float *c = a.c32 + i * kCoefStride;
+        const float cc = c[0], ux = c[1], uy = c[2], uz = c[3], K = c[4];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          float arg = fmaf(cc, qf[j], K);
+          arg = fmaf(ux, xf[j], arg);
+          arg = fmaf(uy, yf[j], arg);
+          arg = fmaf(uz, zf[j], arg);
+          const float e = __builtin_amdgcn_exp2f(arg);
+          f0[j] += e;
+          f1[j] = fmaf(e, cc, f1[j]);
+          fx_[j] = fmaf(e, ux, fx_[j]);
+          fy_[j] = fmaf(e, uy, fy_[j]);
+          fz_[j] = fmaf(e, uz, fz_[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        s0[j] += (double)f0[j];
+        s1[j] += ln2 * (double)f1[j];
+        sx[j] += ln2 * (double)fx_[j];
+        sy[j] += ln2 * (double)fy_[j];
+        sz[j] += ln2 * (double)fz_[j];
+      }
+    }
+  } else {
+    const int c = chunk - a.n_chunks_far;
+    const int64_t lo = a.n_far + (int64_t)c * a.chunk_near;
+    const int64_t hi = lo + a.chunk_near < a.n_act ? lo + a.chunk_near : a.n_act;
+    for (int64_t i = lo; i < hi; ++i) {
+      const double *cr = a.c64 + i * kCoefStride;
+      const double cc = cr[0], ux = cr[1], uy = cr[2], uz = cr[3], K = cr[4];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        double arg = fma(cc, q2[j], K);
+        arg = fma(ux, x[j], arg);
+        arg = fma(uy, y[j], arg);
+        arg = fma(uz, z[j], arg);
+        const double e = exp_f64(arg);
+        s0[j] += e;
+        s1[j] = fma(e, cc, s1[j]);
+        sx[j] = fma(e, ux, sx[j]);
+        sy[j] = fma(e, uy, sy[j]);
+        sz[j] = fma(e, uz, sz[j]);
+      }
+    }
+  }
+  double *o = a.part + (int64_t)chunk * 5 * a.stride;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int64_t q = base + 64 * j;
+    if (q < a.nq) {
+      o[q] = s0[j];
+      o[a.stride + q] = s1[j];
+      o[2 * a.stride + q] = sx[j];
+      o[3 * a.stride + q] = sy[j];
+      o[4 * a.stride + q] = sz[j];
+    }
+  }
+}
+
+void launch_sum(hipStream_t st, const SumPlan &pl, const double *px, const double *py, const double *pz,
+                const double *pq2, const float *fx, const float *fy, const float *fz, const float *fq2,
+                const double *c64, const float *c32, double *part) {
+  const int nch = pl.n_chunks_far + pl.n_chunks_near;
+  if (nch <= 0 || pl.nq <= 0) return;
+  SumArgs a{px, py, pz, pq2, fx, fy, fz, fq2, c64, c32, part, pl.nq, pl.part_stride,
+            pl.n_far, pl.n_act, pl.n_chunks_far, pl.chunk_far, pl.chunk_near};
+  const int64_t per_block = (int64_t)64 * pl.points_per_lane * pl.waves;
+  dim3 g((unsigned)((pl.nq + per_block - 1) / per_block), (unsigned)nch);
+  dim3 b(64 * pl.waves);
+  switch (pl.points_per_lane) {
+    case 1: hipLaunchKernelGGL(k_sum<1>, g, b, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_sum<2>, g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL(k_sum<4>, g, b, 0, st, a); break;
+  }
+}
+
+__global__ void k_finalize(int64_t nq, int n_chunks, int64_t stride, const double *__restrict__ part,
+                           const double *__restrict__ px, const double *__restrict__ py,
+                           const double *__restrict__ pz, const double *__restrict__ nx,
+                           const double *__restrict__ ny, const double *__restrict__ nz,
+                           const double *__restrict__ wdS, const int8_t *__restrict__ role, double kcond,
+                           double *__restrict__ T, double *__restrict__ gx, double *__restrict__ gy,
+                           double *__restrict__ gz, double *__restrict__ ld) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  double s0 = 0, s1 = 0, sx = 0, sy = 0, sz = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    const double *o = part + (int64_t)c * 5 * stride;
+    s0 += o[q];
+    s1 += o[stride + q];
+    sx += o[2 * stride + q];
+    sy += o[3 * stride + q];
+    sz += o[4 * stride + q];
+  }
+  const double g0 = fma(2.0 * px[q], s1, sx);
+  const double g1 = fma(2.0 * py[q], s1, sy);
+  const double g2 = fma(2.0 * pz[q], s1, sz);
+  T[q] = s0;
+  gx[q] = g0;
+  gy[q] = g1;
+  gz[q] = g2;
+  const int r = role[q];
+  double d = 0.0;
+  if (r == 0) d = -kcond * (g0 * nx[q] + g1 * ny[q] + g2 * nz[q]) * wdS[q];
+  else if (r == 1) d = -s0 * wdS[q];
+  ld[q] = d;
+}
+
+void launch_finalize(hipStream_t st, int64_t nq, int n_chunks, int64_t part_stride, const double *part,
+                     const double *px, const double *py, const double *pz, const double *nx,
+                     const double *ny, const double *nz, const double *wdS, const int8_t *role,
+                     double kcond, double *T, double *gx, double *gy, double *gz, double *ld) {
+  if (nq <= 0) return;
+  dim3 g((unsigned)((nq + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_finalize, g, dim3(kBlock), 0, st, nq, n_chunks, part_stride, part, px, py, pz, nx,
+                     ny, nz, wdS, role, kcond, T, gx, gy, gz, ld);
+}
+
+__global__ void k_gather(int64_t nrow, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                         const double *__restrict__ val, const double *__restrict__ in,
+                         double *__restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrow) return;
+  double s = 0.0;
+  for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) s = fma(val[e], in[col[e]], s);
+  out[r] = s;
+}
+
+void launch_gather(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,
+                   const double *val, const double *in, double *out) {
+  if (nrow <= 0) return;
+  dim3 g((unsigned)((nrow + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_gather, g, dim3(kBlock), 0, st, nrow, rowptr, col, val, in, out);
+}
+
+void launch_csr_eval(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,
+                     const double *val, const double *u, double *out) {
+  launch_gather(st, nrow, rowptr, col, val, u, out);
+}
+
+// ---------------------------------------------------------------------------
+// stencil operator helpers
+// ---------------------------------------------------------------------------
+// y_row = sum_o S[o][row] x[row + offset(o)]; neighbour indices are clamped to
+// the array (their coefficients are zero), so no load leaves the vector.
+__device__ __forceinline__ double stencil_row(const StencilOp &S, const double *__restrict__ val,
+                                              const double *__restrict__ x, int64_t row) {
+  const int n0 = S.n[0], n1 = S.n[1];
+  const int64_t n01 = (int64_t)n0 * n1;
+  const int64_t nm1 = S.nrow - 1;
+  double s = 0.0;
+  int o = 0;
+  for (int d2 = -S.hw[2]; d2 <= S.hw[2]; ++d2)
+    for (int d1 = -S.hw[1]; d1 <= S.hw[1]; ++d1) {
+      const int64_t b = row + (int64_t)d1 * n0 + (int64_t)d2 * n01;
+      for (int d0 = -S.hw[0]; d0 <= S.hw[0]; ++d0, ++o) {
+        int64_t nb = b + d0;
+        nb = nb < 0 ? 0 : (nb > nm1 ? nm1 : nb);
+        s = fma(val[(int64_t)o * S.nrow + row], x[nb], s);
+      }
+    }
+  return s;
+}
+
+__global__ void k_theta_init(StencilOp A, const double *__restrict__ Bval, const double *__restrict__ v,
+                             const double *__restrict__ F1, const double *__restrict__ F0, double theta,
+                             const double *__restrict__ x, double *__restrict__ r, double *__restrict__ part) {
+  double acc = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.nrow;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    double rv = 0.0;
+    if (!A.free_mask || A.free_mask[row]) {
+      const double rhs = stencil_row(A, Bval, v, row) + theta * F1[row] + (1.0 - theta) * F0[row];
+      acc += rhs * rhs;
+      rv = rhs - stencil_row(A, A.A, x, row);
+    }
+    r[row] = rv;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_theta_init(hipStream_t st, const StencilOp &A, const double *Bval, const double *v,
+                       const double *F1, const double *F0, double theta, double *x, double *r,
+                       double *part) {
+  dim3 g((unsigned)parts_for(A.nrow));
+  hipLaunchKernelGGL(k_theta_init, g, dim3(kBlock), 0, st, A, Bval, v, F1, F0, theta, x, r, part);
+}
+
+__global__ void k_scatter(int64_t nD, const int64_t *__restrict__ dofs, const double *__restrict__ vals,
+                          double *__restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nD) x[dofs[i]] = vals[i];
+}
+
+void launch_scatter_dirichlet(hipStream_t st, int64_t nD, const int64_t *dofs, const double *vals,
+                              double *x) {
+  if (nD <= 0) return;
+  dim3 g((unsigned)((nD + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_scatter, g, dim3(kBlock), 0, st, nD, dofs, vals, x);
+}
+
+__global__ void k_csr_init(CsrOp A, const double *__restrict__ b, const double *__restrict__ x,
+                           double *__restrict__ r, double *__restrict__ part) {
+  double acc = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.nrow;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) s = fma(A.val[e], x[A.col[e]], s);
+    r[row] = b[row] - s;
+    acc += b[row] * b[row];
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_csr_init(hipStream_t st, const CsrOp &A, const double *b, const double *x, double *r,
+                     double *part) {
+  dim3 g((unsigned)parts_for(A.nrow));
+  hipLaunchKernelGGL(k_csr_init, g, dim3(kBlock), 0, st, A, b, x, r, part);
+}
+
+// ---------------------------------------------------------------------------
+// preconditioners (write z and partials of r.z)
+// ---------------------------------------------------------------------------
+__global__ void k_jacobi(int64_t n, const double *__restrict__ inv_diag, const double *__restrict__ r,
+                         double *__restrict__ z, double *__restrict__ part, const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double zi = inv_diag[i] * r[i];
+    z[i] = zi;
+    acc = fma(r[i], zi, acc);
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_jacobi(hipStream_t st, int64_t n, const double *inv_diag, const double *r, double *z,
+                   double *part, PcgScalars *sc) {
+  dim3 g((unsigned)parts_for(n));
+  hipLaunchKernelGGL(k_jacobi, g, dim3(kBlock), 0, st, n, inv_diag, r, z, part, sc);
+}
+
+// One mode product of the fast-diagonalisation solve.  The box of free
+// indices has sizes m[0..2]; "full" vectors use the n-grid with offset lo,
+// "compact" ones the m-box.  out[j along dim] = sum_k W[k, j] in[k along dim]
+// with W = U (transposed use: TR) ; optional scaling by inv_diag.
+template <bool IN_FULL, bool OUT_FULL, bool TR>
+__global__ void k_fd_mode(FdOp F, int dim, const double *__restrict__ in, double *__restrict__ out,
+                          const double *__restrict__ U, bool scale, const double *__restrict__ rdot,
+                          double *__restrict__ part, const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  const int m0 = F.m[0], m1 = F.m[1], m2 = F.m[2];
+  const int64_t nbox = (int64_t)m0 * m1 * m2;
+  const int md = F.m[dim];
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nbox;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int j[3] = {(int)(t % m0), (int)((t / m0) % m1), (int)(t / ((int64_t)m0 * m1))};
+    const int jd = j[dim];
+    double s = 0.0;
+    for (int k = 0; k < md; ++k) {
+      j[dim] = k;
+      int64_t src;
+      if (IN_FULL)
+        src = (int64_t)(j[0] + F.lo[0]) + (int64_t)F.n[0] * ((j[1] + F.lo[1]) + (int64_t)F.n[1] * (j[2] + F.lo[2]));
+      else
+        src = (int64_t)j[0] + (int64_t)m0 * (j[1] + (int64_t)m1 * j[2]);
+      const double w = TR ? U[(int64_t)k * md + jd] : U[(int64_t)jd * md + k];
+      s = fma(w, in[src], s);
+    }
+    j[dim] = jd;
+    if (scale) s *= F.inv_diag[t];
+    int64_t dst;
+    if (OUT_FULL)
+      dst = (int64_t)(j[0] + F.lo[0]) + (int64_t)F.n[0] * ((j[1] + F.lo[1]) + (int64_t)F.n[1] * (j[2] + F.lo[2]));
+    else
+      dst = t;
+    out[dst] = s;
+    if (rdot) acc = fma(rdot[dst], s, acc);
+  }
+  if (part) {
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_fill(int64_t n, double *__restrict__ z, double v, const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = v;
+}
+
+void launch_fd(hipStream_t st, const FdOp &F, int64_t n, const double *r, double *z, double *part,
+               PcgScalars *sc) {
+  const int64_t nbox = (int64_t)F.m[0] * F.m[1] * F.m[2];
+  const bool full_box = nbox == n;
+  dim3 b(kBlock);
+  dim3 gb((unsigned)parts_for(nbox));
+  // z outside the box stays zero (fixed rows)
+  if (!full_box) hipLaunchKernelGGL(k_fill, dim3(parts_for(n)), b, 0, st, n, z, 0.0, sc);
+  // forward: t1 = U0^T r, t2 = U1^T t1, t1 = D^{-1} U2^T t2
+  hipLaunchKernelGGL((k_fd_mode<true, false, true>), gb, b, 0, st, F, 0, r, F.t1, F.U[0], false,
+                     (const double *)nullptr, (double *)nullptr, sc);
+  hipLaunchKernelGGL((k_fd_mode<false, false, true>), gb, b, 0, st, F, 1, F.t1, F.t2, F.U[1], false,
+                     (const double *)nullptr, (double *)nullptr, sc);
+  hipLaunchKernelGGL((k_fd_mode<false, false, true>), gb, b, 0, st, F, 2, F.t2, F.t1, F.U[2], true,
+                     (const double *)nullptr, (double *)nullptr, sc);
+  // backward: t2 = U2 t1, t1 = U1 t2, z = U0 t1 (+ partials of r.z)
+  hipLaunchKernelGGL((k_fd_mode<false, false, false>), gb, b, 0, st, F, 2, F.t1, F.t2, F.U[2], false,
+                     (const double *)nullptr, (double *)nullptr, sc);
+  hipLaunchKernelGGL((k_fd_mode<false, false, false>), gb, b, 0, st, F, 1, F.t2, F.t1, F.U[1], false,
+                     (const double *)nullptr, (double *)nullptr, sc);
+  hipLaunchKernelGGL((k_fd_mode<false, true, false>), gb, b, 0, st, F, 0, F.t1, z, F.U[0], false, r, part,
+                     sc);
+  // partial slots beyond the box-kernel grid are unused by construction
+  (void)n;
+}
+
+// ---------------------------------------------------------------------------
+// PCG steps
+// ---------------------------------------------------------------------------
+__global__ void k_pcg_start(int64_t n, int n_part_b, const double *__restrict__ part_b, int n_part_rz,
+                            const double *__restrict__ part_rz, const double *__restrict__ z,
+                            double *__restrict__ p, PcgScalars *sc, double rtol) {
+  const double b2 = reduce_parts(part_b, n_part_b);
+  const double rz = reduce_parts(part_rz, n_part_rz);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->bnorm2 = b2;
+    sc->rz = rz;
+    sc->rr = -1.0;
+    sc->alpha = sc->beta = 0.0;
+    sc->iter = 0;
+    sc->rtol2 = rtol * rtol;
+    // zero right-hand side (or exact start): nothing to do
+    sc->done = (rz == 0.0) ? 1 : 0;
+  }
+}
+
+void launch_pcg_start(hipStream_t st, int64_t n, int n_part_b, const double *part_b, int n_part_rz,
+                      const double *part_rz, const double *z, double *p, PcgScalars *sc, double rtol) {
+  dim3 g((unsigned)parts_for(n));
+  hipLaunchKernelGGL(k_pcg_start, g, dim3(kBlock), 0, st, n, n_part_b, part_b, n_part_rz, part_rz, z, p, sc,
+                     rtol);
+}
+
+__global__ void k_stencil_apply_dot(StencilOp A, const double *__restrict__ p, double *__restrict__ q,
+                                    double *__restrict__ part, const PcgScalars *sc) {
+  if (sc->done) return;
+  double acc = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.nrow;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    double y = 0.0;
+    if (!A.free_mask || A.free_mask[row]) y = stencil_row(A, A.A, p, row);
+    q[row] = y;
+    acc = fma(p[row], y, acc);
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_stencil_apply_dot(hipStream_t st, const StencilOp &A, const double *p, double *q, double *part,
+                              PcgScalars *sc) {
+  dim3 g((unsigned)parts_for(A.nrow));
+  hipLaunchKernelGGL(k_stencil_apply_dot, g, dim3(kBlock), 0, st, A, p, q, part, sc);
+}
+
+__global__ void k_csr_apply_dot(CsrOp A, const double *__restrict__ p, double *__restrict__ q,
+                                double *__restrict__ part, const PcgScalars *sc) {
+  if (sc->done) return;
+  double acc = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.nrow;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) s = fma(A.val[e], p[A.col[e]], s);
+    q[row] = s;
+    acc = fma(p[row], s, acc);
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_csr_apply_dot(hipStream_t st, const CsrOp &A, const double *p, double *q, double *part,
+                          PcgScalars *sc) {
+  dim3 g((unsigned)parts_for(A.nrow));
+  hipLaunchKernelGGL(k_csr_apply_dot, g, dim3(kBlock), 0, st, A, p, q, part, sc);
+}
+
+__global__ void k_pcg_update(int64_t n, int n_part, const double *__restrict__ part_pq,
+                             const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ x,
+                             double *__restrict__ r, double *__restrict__ part_rr, PcgScalars *sc) {
+  if (sc->done) return;
+  const double pq = reduce_parts(part_pq, n_part);
+  if (!(pq > 0.0)) {  // breakdown: the operator is not positive on p
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
+    return;
+  }
+  const double alpha = sc->rz / pq;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    acc = fma(ri, ri, acc);
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha;
+}
+
+void launch_pcg_update(hipStream_t st, int64_t n, int n_part, const double *part_pq, const double *p,
+                       const double *q, double *x, double *r, double *part_rr, PcgScalars *sc) {
+  dim3 g((unsigned)parts_for(n));
+  hipLaunchKernelGGL(k_pcg_update, g, dim3(kBlock), 0, st, n, n_part, part_pq, p, q, x, r, part_rr, sc);
+}
+
+__global__ void k_pcg_direction(int64_t n, int n_part_rr, int n_part_rz, const double *__restrict__ part_rr,
+                                const double *__restrict__ part_rz, const double *__restrict__ z,
+                                double *__restrict__ p, PcgScalars *sc) {
+  if (sc->done) return;
+  const double rr = reduce_parts(part_rr, n_part_rr);
+  const double rz_new = reduce_parts(part_rz, n_part_rz);
+  const bool conv = rr <= sc->rtol2 * sc->bnorm2;
+  const double beta = rz_new / sc->rz;
+  if (!conv) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+      p[i] = fma(beta, p[i], z[i]);
+  }
+  // every block has read sc->rz above; make sure before block 0 overwrites it
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rr = rr;
+    sc->iter = sc->iter + 1;
+    if (conv) sc->done = 1;
+  }
+}
+
+// Direction update is split so that no block reads sc->rz after block 0 has
+// replaced it: the new r.z is stored into sc by a second tiny kernel.
+__global__ void k_pcg_commit(int n_part, const double *__restrict__ part_rz, PcgScalars *sc) {
+  if (sc->done) return;
+  const double rz_new = reduce_parts(part_rz, n_part);
+  if (threadIdx.x == 0) {
+    sc->beta = rz_new / sc->rz;
+    sc->rz = rz_new;
+  }
+}
+
+void launch_pcg_direction(hipStream_t st, int64_t n, int n_part_rr, int n_part_rz, const double *part_rr,
+                          const double *part_rz, const double *z, double *p, PcgScalars *sc) {
+  dim3 g((unsigned)parts_for(n));
+  hipLaunchKernelGGL(k_pcg_direction, g, dim3(kBlock), 0, st, n, n_part_rr, n_part_rz, part_rr, part_rz, z, p,
+                     sc);
+  hipLaunchKernelGGL(k_pcg_commit, dim3(1), dim3(kBlock), 0, st, n_part_rz, part_rz, sc);
+}
+
+}  // namespace sa

@@ -1,0 +1,976 @@
+// C ABI of the semi-analytical IGA thermal model on gfx950: object set-up,
+// the per-step device pipeline, PCG driver, evaluation, checkpoints, stats.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "sa_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct HipFail {
+  hipError_t e;
+  const char *what;
+};
+
+inline void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) throw HipFail{e, what};
+}
+
+template <class T>
+T *dev_alloc(std::vector<void *> &owned, size_t n) {
+  void *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw sa::SaError{SA_ENOMEM, "hipMalloc failed"};
+  owned.push_back(p);
+  return (T *)p;
+}
+
+template <class T>
+T *dev_upload(std::vector<void *> &owned, const std::vector<T> &h, hipStream_t st) {
+  T *p = dev_alloc<T>(owned, h.size());
+  if (!h.empty()) hip_check(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+  return p;
+}
+
+struct DevCsr {
+  int64_t nrow = 0;
+  int64_t *rowptr = nullptr;
+  int32_t *col = nullptr;
+  double *val = nullptr;
+  sa::CsrOp op() const { return sa::CsrOp{nrow, rowptr, col, val}; }
+};
+
+struct DevFd {
+  sa::FdOp op{};
+};
+
+struct PathState {
+  int64_t src0 = 0, src1 = 0;
+  int32_t n_steps = 0;
+  int64_t step = 0;
+  double *v = nullptr, *F = nullptr;     // v = u - T0 (control values), F^n
+  double *vD = nullptr;                  // Dirichlet values (deviation) of the last step
+  double *T = nullptr, *g = nullptr;     // boundary T~ [nq], grad [3][stride]
+};
+
+struct StageEvents {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, pool;
+};
+
+}  // namespace
+
+struct sa_iga {
+  sa::Model m;
+  int device = 0;
+  hipStream_t own_stream = nullptr, stream = nullptr;
+  std::vector<void *> owned;
+  int64_t nq = 0, stride = 0;
+  // boundary points (centred), normals, weights, roles
+  double *px = nullptr, *py = nullptr, *pz = nullptr, *pq2 = nullptr;
+  float *fx = nullptr, *fy = nullptr, *fz = nullptr, *fq2 = nullptr;
+  double *nx = nullptr, *ny = nullptr, *nz = nullptr, *wdS = nullptr;
+  int8_t *role = nullptr;
+  double *ld = nullptr;                  // per-point load densities
+  DevCsr load, dproj, mdir;
+  int64_t *dir_dofs = nullptr;
+  int64_t nD = 0;
+  double *mdir_invdiag = nullptr;
+  // theta-scheme operators
+  sa::StencilOp Aop{};
+  double *Bval = nullptr;
+  uint8_t *free_mask = nullptr;
+  double *A_invdiag = nullptr;
+  DevFd fd_main, fd_dir;
+  // sources (all paths), centred
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *sE = nullptr;
+  int64_t *stick = nullptr;
+  std::vector<int64_t> h_tick;
+  double *c64 = nullptr;
+  float *c32 = nullptr;
+  int64_t max_path_sources = 0;
+  // work buffers
+  double *part = nullptr;
+  int64_t part_chunks = 0;
+  double *Fnew = nullptr, *bD = nullptr, *xnew = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *rD = nullptr, *zD = nullptr, *pD = nullptr, *qD = nullptr;
+  double *part_b = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_rr = nullptr;
+  sa::PcgScalars *sc = nullptr, *h_sc = nullptr;
+  std::vector<PathState> paths;
+  double delta = 0, shift = 0, alpha = 0, rc = 0;
+  int64_t tau_ticks = 0;
+  int64_t ns = 1;                        // sources per theta-step (ticks per step)
+  sa_stats stats{};
+  int sticky = 0;
+  StageEvents ev[SA_N_STAGES];
+  ~sa_iga();
+};
+
+sa_iga::~sa_iga() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (auto &s : ev) {
+    for (auto &pr : s.pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto &pr : s.pool) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+  }
+  for (void *p : owned) (void)hipFree(p);
+  if (h_sc) (void)hipHostFree(h_sc);
+  if (own_stream) (void)hipStreamDestroy(own_stream);
+}
+
+namespace {
+
+int set_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const sa::SaError &e) {
+    return set_error(e.code, e.msg);
+  } catch (const HipFail &e) {
+    return set_error(SA_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc &) {
+    return set_error(SA_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(SA_EINVAL, "unexpected failure");
+  }
+}
+
+// ---- stage timing -----------------------------------------------------------
+struct StageScope {
+  sa_iga *h;
+  int stage;
+  hipEvent_t stop = nullptr;
+  StageScope(sa_iga *h_, int s) : h(h_), stage(s) {
+    if (!h->m.opt.timing) return;
+    auto &E = h->ev[s];
+    std::pair<hipEvent_t, hipEvent_t> pr;
+    if (!E.pool.empty()) {
+      pr = E.pool.back();
+      E.pool.pop_back();
+    } else {
+      hip_check(hipEventCreate(&pr.first), "event");
+      hip_check(hipEventCreate(&pr.second), "event");
+    }
+    hip_check(hipEventRecord(pr.first, h->stream), "event record");
+    E.pending.push_back(pr);
+    stop = pr.second;
+  }
+  ~StageScope() {
+    if (stop) {
+      (void)hipEventRecord(stop, h->stream);
+      h->stats.stage_launches[stage]++;
+    }
+  }
+};
+
+void collect_timing(sa_iga *h) {
+  if (!h->m.opt.timing) return;
+  for (int s = 0; s < SA_N_STAGES; ++s) {
+    auto &E = h->ev[s];
+    for (auto &pr : E.pending) {
+      float ms = 0.f;
+      hip_check(hipEventSynchronize(pr.second), "event sync");
+      hip_check(hipEventElapsedTime(&ms, pr.first, pr.second), "elapsed");
+      h->stats.stage_ms[s] += ms;
+      E.pool.push_back(pr);
+    }
+    E.pending.clear();
+  }
+}
+
+// ---- kernel-sum plan --------------------------------------------------------
+sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int64_t n_far, int64_t n_act) {
+  sa::SumPlan pl{};
+  const auto &o = h->m.opt;
+  pl.points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
+  pl.waves = o.waves_per_group ? std::min(o.waves_per_group, 8) : 4;
+  pl.nq = nq;
+  pl.part_stride = h->stride;
+  pl.n_far = n_far;
+  pl.n_act = n_act;
+  const int64_t per_blk = (int64_t)64 * pl.points_per_lane * pl.waves;
+  const int64_t n_pblk = std::max<int64_t>(1, (nq + per_blk - 1) / per_blk);
+  const int64_t n_near = n_act - n_far;
+  if (o.chunk_sources > 0) {
+    pl.chunk_far = o.chunk_sources;
+    pl.chunk_near = o.chunk_sources;
+    pl.n_chunks_far = (int)((n_far + pl.chunk_far - 1) / pl.chunk_far);
+    pl.n_chunks_near = (int)((n_near + pl.chunk_near - 1) / pl.chunk_near);
+    return pl;
+  }
+  const int64_t target_groups = 2048;
+  int64_t C = std::max<int64_t>(1, (target_groups + n_pblk - 1) / n_pblk);
+  const double wf = (double)n_far, wn = 3.0 * (double)n_near;
+  int64_t cf = 0, cn = 0;
+  if (n_far > 0 && n_near > 0) {
+    cf = std::max<int64_t>(1, (int64_t)std::llround(C * wf / (wf + wn)));
+    cn = std::max<int64_t>(1, C - cf);
+  } else if (n_far > 0) {
+    cf = C;
+  } else if (n_near > 0) {
+    cn = C;
+  }
+  const int64_t min_chunk = 32;
+  if (cf) {
+    int64_t len = std::max<int64_t>(min_chunk, (n_far + cf - 1) / cf);
+    pl.chunk_far = (int)len;
+    pl.n_chunks_far = (int)((n_far + len - 1) / len);
+  }
+  if (cn) {
+    int64_t len = std::max<int64_t>(min_chunk, (n_near + cn - 1) / cn);
+    pl.chunk_near = (int)len;
+    pl.n_chunks_near = (int)((n_near + len - 1) / len);
+  }
+  if (pl.chunk_far == 0) pl.chunk_far = 1;
+  if (pl.chunk_near == 0) pl.chunk_near = 1;
+  return pl;
+}
+
+// partial-sum buffer of at least `doubles` values
+void ensure_part(sa_iga *h, int64_t doubles) {
+  if (doubles <= h->part_chunks) return;
+  int64_t cap = std::max<int64_t>(doubles, 2 * h->part_chunks);
+  if (h->part) {
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    hip_check(hipFree(h->part), "free");
+    h->owned.erase(std::find(h->owned.begin(), h->owned.end(), (void *)h->part));
+    h->part = nullptr;
+  }
+  h->part = dev_alloc<double>(h->owned, (size_t)cap);
+  h->part_chunks = cap;
+}
+
+int64_t n_active(const sa_iga *h, const PathState &P, int64_t now) {
+  auto b = h->h_tick.begin() + P.src0, e = h->h_tick.begin() + P.src1;
+  return (int64_t)(std::upper_bound(b, e, now) - b);
+}
+
+
+// T~ and grad T~ of path P at time step*dt at nq points (centred arrays),
+// plus the per-point load densities (roles) into ld.
+void sum_at_points(sa_iga *h, const PathState &P, int64_t step, int64_t nq, int64_t stride, const double *px,
+                   const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
+                   const float *fz, const float *fq2, const int8_t *role, const double *nx,
+                   const double *ny, const double *nz, const double *wdS, double *T, double *g,
+                   double *ld) {
+  const int64_t now = step * h->ns;
+  const int64_t n_act = n_active(h, P, now);
+  int64_t n_far = 0;
+  if (h->m.opt.precision == SA_PREC_FP32_FAR && n_act > 0) {
+    const int64_t thr = now - h->tau_ticks;       // far iff tick < thr
+    auto b = h->h_tick.begin() + P.src0;
+    n_far = std::min<int64_t>(n_act, (int64_t)(std::lower_bound(b, b + n_act, thr) - b));
+  }
+  if (n_act > 0) {
+    StageScope s(h, SA_STAGE_COEFF);
+    sa::CoeffParams cp{now, h->delta, h->shift, h->alpha, h->rc, h->m.opt.kernel_scale};
+    sa::launch_coeff(h->stream, n_act, n_far, h->stick + P.src0, h->sx + P.src0, h->sy + P.src0,
+                     h->sz + P.src0, h->sE + P.src0, cp, h->c64, h->c32);
+  }
+  sa::SumPlan pl = make_plan(h, nq, n_far, n_act);
+  pl.part_stride = stride;
+  const int nch = pl.n_chunks_far + pl.n_chunks_near;
+  ensure_part(h, (int64_t)std::max(nch, 1) * 5 * stride);
+  if (nch > 0) {
+    StageScope s(h, SA_STAGE_SUM);
+    sa::launch_sum(h->stream, pl, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, h->part);
+  }
+  {
+    StageScope s(h, SA_STAGE_REDUCE);
+    sa::launch_finalize(h->stream, nq, nch, stride, h->part, px, py, pz, nx, ny, nz, wdS, role,
+                        h->m.mat.k, T, g, g + stride, g + 2 * stride, ld);
+  }
+  h->stats.pairs += n_act * nq;
+  h->stats.pairs_near += (n_act - n_far) * nq;
+}
+
+// ---- PCG driver --------------------------------------------------------------
+struct PcgSpec {
+  int64_t n = 0;
+  bool stencil = true;
+  sa::StencilOp st{};
+  sa::CsrOp csr{};
+  bool fd = false;
+  sa::FdOp fdop{};
+  const double *invdiag = nullptr;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  int n_part_b = 0;
+};
+
+int apply_precond(sa_iga *h, PcgSpec &s, const double *r, double *z, sa::PcgScalars *sc) {
+  if (s.fd) {
+    sa::launch_fd(h->stream, s.fdop, s.n, r, z, h->part_rz, sc);
+    return sa::parts_for((int64_t)s.fdop.m[0] * s.fdop.m[1] * s.fdop.m[2]);
+  }
+  sa::launch_jacobi(h->stream, s.n, s.invdiag, r, z, h->part_rz, sc);
+  return sa::parts_for(s.n);
+}
+
+// Solve on the prepared residual r = b - A x (partials of |b|^2 in part_b).
+// Returns iterations; throws SA_ENOCONV.
+int pcg_run(sa_iga *h, PcgSpec &s, double *relres) {
+  const int64_t n = s.n;
+  const int np = sa::parts_for(n);
+  int np_rz = apply_precond(h, s, s.r, s.z, nullptr);
+  sa::launch_pcg_start(h->stream, n, s.n_part_b, h->part_b, np_rz, h->part_rz, s.z, s.p, h->sc,
+                       h->m.opt.pcg_rtol);
+  int chunk = s.fd ? 2 : 8;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      if (s.stencil) sa::launch_stencil_apply_dot(h->stream, s.st, s.p, s.q, h->part_pq, h->sc);
+      else sa::launch_csr_apply_dot(h->stream, s.csr, s.p, s.q, h->part_pq, h->sc);
+      sa::launch_pcg_update(h->stream, n, np, h->part_pq, s.p, s.q, s.x, s.r, h->part_rr, h->sc);
+      np_rz = apply_precond(h, s, s.r, s.z, h->sc);
+      sa::launch_pcg_direction(h->stream, n, np, np_rz, h->part_rr, h->part_rz, s.z, s.p, h->sc);
+    }
+    hip_check(hipMemcpyAsync(h->h_sc, h->sc, sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
+              "status copy");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    const sa::PcgScalars st = *h->h_sc;
+    if (st.done == 1) {
+      *relres = st.bnorm2 > 0 ? std::sqrt(std::max(st.rr, 0.0) / st.bnorm2) : 0.0;
+      return st.iter;
+    }
+    if (st.done == 2) throw sa::SaError{SA_ENOCONV, "PCG breakdown (operator not positive definite)"};
+    if (!std::isfinite(st.rz) || !std::isfinite(st.rr)) throw sa::SaError{SA_ENOCONV, "PCG produced NaN/Inf"};
+    if (st.iter >= h->m.opt.pcg_max_iter)
+      throw sa::SaError{SA_ENOCONV, "PCG did not converge within pcg_max_iter"};
+    chunk = std::min(chunk * 2, 64);
+    chunk = std::min(chunk, std::max(1, h->m.opt.pcg_max_iter - st.iter));
+  }
+}
+
+void step_path(sa_iga *h, PathState &P) {
+  const int64_t s1 = P.step + 1;
+  sum_at_points(h, P, s1, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2,
+                h->role, h->nx, h->ny, h->nz, h->wdS, P.T, P.g, h->ld);
+  {
+    StageScope s(h, SA_STAGE_LOAD);
+    sa::launch_gather(h->stream, h->load.nrow, h->load.rowptr, h->load.col, h->load.val, h->ld, h->Fnew);
+    sa::launch_gather(h->stream, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->ld, h->bD);
+  }
+  if (h->nD > 0) {
+    StageScope s(h, SA_STAGE_DIRICHLET);
+    PcgSpec d;
+    d.n = h->nD;
+    d.stencil = false;
+    d.csr = h->mdir.op();
+    d.fd = h->m.opt.preconditioner == SA_PRECOND_FD && h->m.fd_dir_ok;
+    d.fdop = h->fd_dir.op;
+    d.invdiag = h->mdir_invdiag;
+    d.x = P.vD;
+    d.r = h->rD;
+    d.z = h->zD;
+    d.p = h->pD;
+    d.q = h->qD;
+    d.n_part_b = sa::parts_for(h->nD);
+    sa::launch_csr_init(h->stream, d.csr, h->bD, P.vD, h->rD, h->part_b);
+    double rr = 0;
+    h->stats.dirichlet_iterations += pcg_run(h, d, &rr);
+  }
+  {
+    StageScope s(h, SA_STAGE_RHS);
+    const int64_t nd = h->m.P.ndof;
+    hip_check(hipMemcpyAsync(h->xnew, P.v, nd * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "copy");
+    sa::launch_scatter_dirichlet(h->stream, h->nD, h->dir_dofs, P.vD, h->xnew);
+    sa::launch_theta_init(h->stream, h->Aop, h->Bval, P.v, h->Fnew, P.F, h->m.opt.theta, h->xnew, h->r,
+                          h->part_b);
+  }
+  {
+    StageScope s(h, SA_STAGE_PCG);
+    PcgSpec m;
+    m.n = h->m.P.ndof;
+    m.stencil = true;
+    m.st = h->Aop;
+    m.fd = h->m.opt.preconditioner == SA_PRECOND_FD;
+    m.fdop = h->fd_main.op;
+    m.invdiag = h->A_invdiag;
+    m.x = h->xnew;
+    m.r = h->r;
+    m.z = h->z;
+    m.p = h->p;
+    m.q = h->q;
+    m.n_part_b = sa::parts_for(m.n);
+    double rr = 0;
+    int it = pcg_run(h, m, &rr);
+    h->stats.pcg_iterations += it;
+    h->stats.pcg_last_iterations = it;
+    h->stats.pcg_last_relres = rr;
+  }
+  std::swap(P.v, h->xnew);
+  std::swap(P.F, h->Fnew);
+  P.step = s1;
+  h->stats.steps++;
+}
+
+std::vector<float> to_float(const std::vector<double> &v) {
+  std::vector<float> f(v.size());
+  for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+  return f;
+}
+
+void upload_fd(sa_iga *h, const sa::FdData &F, DevFd &D) {
+  D.op = sa::FdOp{};
+  for (int d = 0; d < 3; ++d) {
+    D.op.n[d] = F.n[d];
+    D.op.lo[d] = F.lo[d];
+    D.op.m[d] = F.m[d];
+    D.op.U[d] = dev_upload(h->owned, F.U[d], h->stream);
+  }
+  D.op.inv_diag = dev_upload(h->owned, F.inv_diag, h->stream);
+  const size_t nb = F.inv_diag.size();
+  D.op.t1 = dev_alloc<double>(h->owned, nb);
+  D.op.t2 = dev_alloc<double>(h->owned, nb);
+}
+
+DevCsr upload_csr(sa_iga *h, const sa::Csr &C) {
+  DevCsr d;
+  d.nrow = C.nrow;
+  d.rowptr = dev_upload(h->owned, C.rowptr, h->stream);
+  d.col = dev_upload(h->owned, C.col, h->stream);
+  d.val = dev_upload(h->owned, C.val, h->stream);
+  return d;
+}
+
+void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan) {
+  sa::Model &m = h->m;
+  // device and stream
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw sa::SaError{SA_EDEVICE, "no HIP device"};
+  hip_check(hipGetDevice(&h->device), "get device");
+  hipDeviceProp_t prop;
+  hip_check(hipGetDeviceProperties(&prop, h->device), "device properties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    throw sa::SaError{SA_EDEVICE, std::string("device is ") + prop.gcnArchName + ", built for gfx950"};
+  hip_check(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking), "stream");
+  h->stream = h->own_stream;
+
+  // model set-up (host)
+  sa::load_patch(patch, m.P);
+  m.mat = *mat;
+  m.dt = scan->dt;
+  sa::assemble_volume(m);
+  sa::build_boundary(m);
+  sa::build_fd(m);
+  const int64_t nd = m.P.ndof;
+  const double th = m.opt.theta;
+
+  // theta-scheme stencils A = M/dt + theta K, B = M/dt - (1-theta) K
+  {
+    std::vector<double> A(m.M.val.size()), B(m.M.val.size());
+    for (size_t i = 0; i < A.size(); ++i) {
+      A[i] = m.M.val[i] / m.dt + th * m.K.val[i];
+      B[i] = m.M.val[i] / m.dt - (1.0 - th) * m.K.val[i];
+    }
+    h->Aop = sa::StencilOp{};
+    for (int d = 0; d < 3; ++d) { h->Aop.n[d] = m.M.n[d]; h->Aop.hw[d] = m.M.hw[d]; }
+    h->Aop.n_off = m.M.n_off;
+    h->Aop.nrow = nd;
+    h->Aop.A = dev_upload(h->owned, A, h->stream);
+    h->Bval = dev_upload(h->owned, B, h->stream);
+    std::vector<uint8_t> fm(m.free_mask.begin(), m.free_mask.end());
+    h->free_mask = dev_upload(h->owned, fm, h->stream);
+    h->Aop.free_mask = h->free_mask;
+    std::vector<double> jd(nd, 0.0);
+    const int o0 = m.M.off_index(0, 0, 0);
+    for (int64_t i = 0; i < nd; ++i)
+      if (m.free_mask[i]) jd[i] = 1.0 / A[(size_t)o0 * nd + i];
+    h->A_invdiag = dev_upload(h->owned, jd, h->stream);
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+  }
+  upload_fd(h, m.fd_main, h->fd_main);
+  if (m.fd_dir_ok) upload_fd(h, m.fd_dir, h->fd_dir);
+
+  // boundary tables (centred coordinates)
+  const sa::BoundaryTables &bt = m.bt;
+  h->nq = bt.nq;
+  h->stride = (bt.nq + 63) / 64 * 64;
+  {
+    std::vector<double> x(bt.nq), y(bt.nq), z(bt.nq), q2(bt.nq), nx(bt.nq), ny(bt.nq), nz(bt.nq);
+    for (int64_t i = 0; i < bt.nq; ++i) {
+      x[i] = bt.x[3 * i] - m.P.center[0];
+      y[i] = bt.x[3 * i + 1] - m.P.center[1];
+      z[i] = bt.x[3 * i + 2] - m.P.center[2];
+      q2[i] = x[i] * x[i] + y[i] * y[i] + z[i] * z[i];
+      nx[i] = bt.nrm[3 * i];
+      ny[i] = bt.nrm[3 * i + 1];
+      nz[i] = bt.nrm[3 * i + 2];
+    }
+    h->px = dev_upload(h->owned, x, h->stream);
+    h->py = dev_upload(h->owned, y, h->stream);
+    h->pz = dev_upload(h->owned, z, h->stream);
+    h->pq2 = dev_upload(h->owned, q2, h->stream);
+    h->fx = dev_upload(h->owned, to_float(x), h->stream);
+    h->fy = dev_upload(h->owned, to_float(y), h->stream);
+    h->fz = dev_upload(h->owned, to_float(z), h->stream);
+    h->fq2 = dev_upload(h->owned, to_float(q2), h->stream);
+    h->nx = dev_upload(h->owned, nx, h->stream);
+    h->ny = dev_upload(h->owned, ny, h->stream);
+    h->nz = dev_upload(h->owned, nz, h->stream);
+    h->wdS = dev_upload(h->owned, bt.wdS, h->stream);
+    h->role = dev_upload(h->owned, bt.role, h->stream);
+    h->ld = dev_alloc<double>(h->owned, bt.nq);
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+  }
+  h->load = upload_csr(h, m.load);
+  h->dproj = upload_csr(h, m.dproj);
+  h->mdir = upload_csr(h, m.mass_dir);
+  h->nD = (int64_t)m.dir_dofs.size();
+  h->dir_dofs = dev_upload(h->owned, m.dir_dofs, h->stream);
+  {
+    std::vector<double> jd(std::max<int64_t>(h->nD, 1), 1.0);
+    for (int64_t j = 0; j < h->nD; ++j)
+      for (int64_t e = m.mass_dir.rowptr[j]; e < m.mass_dir.rowptr[j + 1]; ++e)
+        if (m.mass_dir.col[e] == j) jd[j] = 1.0 / m.mass_dir.val[e];
+    h->mdir_invdiag = dev_upload(h->owned, jd, h->stream);
+  }
+
+  // sources (centred)
+  const int64_t N = scan->src_offset[scan->n_paths];
+  {
+    std::vector<double> x(N), y(N), z(N), E(N);
+    h->h_tick.assign(scan->tick, scan->tick + N);
+    for (int64_t i = 0; i < N; ++i) {
+      x[i] = scan->xyz[3 * i] - m.P.center[0];
+      y[i] = scan->xyz[3 * i + 1] - m.P.center[1];
+      z[i] = scan->xyz[3 * i + 2] - m.P.center[2];
+      E[i] = scan->energy[i];
+    }
+    h->sx = dev_upload(h->owned, x, h->stream);
+    h->sy = dev_upload(h->owned, y, h->stream);
+    h->sz = dev_upload(h->owned, z, h->stream);
+    h->sE = dev_upload(h->owned, E, h->stream);
+    h->stick = dev_upload(h->owned, h->h_tick, h->stream);
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+  }
+  h->ns = scan->sources_per_step;
+  h->delta = scan->dt / scan->sources_per_step;
+  h->rc = mat->rho * mat->cp;
+  h->alpha = mat->k / h->rc;
+  h->shift = scan->spot_radius * scan->spot_radius / (8.0 * h->alpha);
+  h->tau_ticks = (int64_t)std::floor(m.opt.tau_near / h->delta + 1e-9);
+  int64_t maxs = 0;
+  for (int p = 0; p < scan->n_paths; ++p) maxs = std::max<int64_t>(maxs, scan->src_offset[p + 1] - scan->src_offset[p]);
+  h->max_path_sources = maxs;
+  h->c64 = dev_alloc<double>(h->owned, (size_t)std::max<int64_t>(maxs, 1) * sa::kCoefStride);
+  h->c32 = dev_alloc<float>(h->owned, (size_t)std::max<int64_t>(maxs, 1) * sa::kCoefStride);
+
+  // per-path state: u = T0 (v = 0), F = 0, vD = 0
+  h->paths.resize(scan->n_paths);
+  for (int p = 0; p < scan->n_paths; ++p) {
+    PathState &P = h->paths[p];
+    P.src0 = scan->src_offset[p];
+    P.src1 = scan->src_offset[p + 1];
+    P.n_steps = scan->n_steps[p];
+    P.step = 0;
+    P.v = dev_alloc<double>(h->owned, nd);
+    P.F = dev_alloc<double>(h->owned, nd);
+    P.vD = dev_alloc<double>(h->owned, std::max<int64_t>(h->nD, 1));
+    P.T = dev_alloc<double>(h->owned, h->stride);
+    P.g = dev_alloc<double>(h->owned, 3 * h->stride);
+    hip_check(hipMemsetAsync(P.v, 0, nd * sizeof(double), h->stream), "memset");
+    hip_check(hipMemsetAsync(P.F, 0, nd * sizeof(double), h->stream), "memset");
+    hip_check(hipMemsetAsync(P.vD, 0, std::max<int64_t>(h->nD, 1) * sizeof(double), h->stream), "memset");
+    hip_check(hipMemsetAsync(P.T, 0, h->stride * sizeof(double), h->stream), "memset");
+    hip_check(hipMemsetAsync(P.g, 0, 3 * h->stride * sizeof(double), h->stream), "memset");
+  }
+  // work buffers
+  h->Fnew = dev_alloc<double>(h->owned, nd);
+  h->xnew = dev_alloc<double>(h->owned, nd);
+  h->r = dev_alloc<double>(h->owned, nd);
+  h->z = dev_alloc<double>(h->owned, nd);
+  h->p = dev_alloc<double>(h->owned, nd);
+  h->q = dev_alloc<double>(h->owned, nd);
+  const int64_t nDa = std::max<int64_t>(h->nD, 1);
+  h->bD = dev_alloc<double>(h->owned, nDa);
+  h->rD = dev_alloc<double>(h->owned, nDa);
+  h->zD = dev_alloc<double>(h->owned, nDa);
+  h->pD = dev_alloc<double>(h->owned, nDa);
+  h->qD = dev_alloc<double>(h->owned, nDa);
+  h->part_b = dev_alloc<double>(h->owned, 1024);
+  h->part_rz = dev_alloc<double>(h->owned, 1024);
+  h->part_pq = dev_alloc<double>(h->owned, 1024);
+  h->part_rr = dev_alloc<double>(h->owned, 1024);
+  h->sc = dev_alloc<sa::PcgScalars>(h->owned, 1);
+  hip_check(hipMemsetAsync(h->sc, 0, sizeof(sa::PcgScalars), h->stream), "memset");
+  hip_check(hipHostMalloc((void **)&h->h_sc, sizeof(sa::PcgScalars), hipHostMallocDefault), "pinned");
+  ensure_part(h, 5 * h->stride * 16);
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+}
+
+// parametric query points -> device CSR rows of basis values (and gradients)
+struct EvalTables {
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> R, gx, gy, gz;
+  std::vector<double> x;  // physical points [n][3]
+};
+
+EvalTables eval_tables(const sa::PatchData &P, int64_t n, const double *xi) {
+  EvalTables t;
+  t.rowptr.assign(1, 0);
+  t.x.resize(3 * n);
+  sa::PointEval pe;
+  for (int64_t i = 0; i < n; ++i) {
+    double u[3];
+    int span[3];
+    for (int d = 0; d < 3; ++d) {
+      u[d] = xi[3 * i + d];
+      if (!(u[d] >= 0.0 && u[d] <= 1.0)) throw sa::SaError{SA_ERANGE, "query point outside [0,1]^3"};
+      span[d] = P.b[d].find_span(u[d]);
+    }
+    sa::eval_point(P, u, span, pe);
+    const double (&J)[3][3] = pe.J;
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    double id = 1.0 / det, Ji[3][3];
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    for (int l = 0; l < pe.L; ++l) {
+      t.col.push_back((int32_t)pe.idx[l]);
+      t.R.push_back(pe.R[l]);
+      double g[3];
+      for (int c = 0; c < 3; ++c) g[c] = pe.dR[l][0] * Ji[0][c] + pe.dR[l][1] * Ji[1][c] + pe.dR[l][2] * Ji[2][c];
+      t.gx.push_back(g[0]);
+      t.gy.push_back(g[1]);
+      t.gz.push_back(g[2]);
+    }
+    t.rowptr.push_back((int64_t)t.col.size());
+    for (int c = 0; c < 3; ++c) t.x[3 * i + c] = pe.x[c];
+  }
+  return t;
+}
+
+// temporary device buffers freed at scope exit
+struct TempBufs {
+  std::vector<void *> v;
+  template <class T>
+  T *alloc(size_t n) {
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) throw sa::SaError{SA_ENOMEM, "hipMalloc"};
+    v.push_back(p);
+    return (T *)p;
+  }
+  template <class T>
+  T *up(const std::vector<T> &h, hipStream_t st) {
+    T *p = alloc<T>(h.size());
+    if (!h.empty()) hip_check(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+    return p;
+  }
+  ~TempBufs() {
+    for (void *p : v) (void)hipFree(p);
+  }
+};
+
+// T~ and grad T~ at n physical points (host in / host out)
+void source_field_host(sa_iga *h, const PathState &P, int64_t step, int64_t n, const double *x, double *T,
+                       double *grad) {
+  if (n <= 0) return;
+  const int64_t stride = (n + 63) / 64 * 64;
+  std::vector<double> cx(n), cy(n), cz(n), q2(n);
+  for (int64_t i = 0; i < n; ++i) {
+    cx[i] = x[3 * i] - h->m.P.center[0];
+    cy[i] = x[3 * i + 1] - h->m.P.center[1];
+    cz[i] = x[3 * i + 2] - h->m.P.center[2];
+    q2[i] = cx[i] * cx[i] + cy[i] * cy[i] + cz[i] * cz[i];
+  }
+  TempBufs tb;
+  double *dx = tb.up(cx, h->stream), *dy = tb.up(cy, h->stream), *dz = tb.up(cz, h->stream),
+         *dq = tb.up(q2, h->stream);
+  float *fx = tb.up(to_float(cx), h->stream), *fy = tb.up(to_float(cy), h->stream),
+        *fz = tb.up(to_float(cz), h->stream), *fq = tb.up(to_float(q2), h->stream);
+  std::vector<int8_t> roles(n, (int8_t)SA_FACE_SOURCE_PLANE);
+  int8_t *drole = tb.up(roles, h->stream);
+  double *dT = tb.alloc<double>(stride), *dg = tb.alloc<double>(3 * stride), *dld = tb.alloc<double>(stride);
+  sum_at_points(h, P, step, n, stride, dx, dy, dz, dq, fx, fy, fz, fq, drole, dx, dy, dz, dx, dT, dg, dld);
+  hip_check(hipMemcpyAsync(T, dT, n * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+  if (grad)
+    for (int c = 0; c < 3; ++c)
+      hip_check(hipMemcpyAsync(grad + c * n, dg + c * stride, n * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                "download");
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+}
+
+PathState &path_of(sa_iga *h, int32_t path) {
+  if (path < 0 || path >= (int32_t)h->paths.size()) throw sa::SaError{SA_ERANGE, "path index out of range"};
+  return h->paths[path];
+}
+
+constexpr uint64_t kMagic = 0x5341494741434b31ull;  // checkpoint tag
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int sa_iga_default_options(sa_solver_options *opt) {
+  if (!opt) return set_error(SA_EINVAL, "NULL options");
+  std::memset(opt, 0, sizeof(*opt));
+  opt->theta = 0.5;
+  opt->kernel_scale = 1.0;
+  opt->precision = SA_PREC_FP64;
+  opt->tau_near = 2e-4;
+  opt->pcg_rtol = 1e-13;
+  opt->pcg_max_iter = 2000;
+  opt->preconditioner = SA_PRECOND_FD;
+  return SA_OK;
+}
+
+int sa_iga_setup(const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan, sa_iga **out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> int {
+    if (!out) throw sa::SaError{SA_EINVAL, "NULL output pointer"};
+    sa_solver_options opt;
+    sa_iga_default_options(&opt);
+    if (scan && scan->opt) opt = *scan->opt;
+    sa::validate_inputs(patch, mat, scan, opt);
+    std::unique_ptr<sa_iga> h(new sa_iga());
+    h->m.opt = opt;
+    build_object(h.get(), patch, mat, scan);
+    *out = h.release();
+    return SA_OK;
+  });
+}
+
+int sa_iga_step(sa_iga *h, int32_t n_steps) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    if (n_steps < 0) throw sa::SaError{SA_EINVAL, "n_steps must be >= 0"};
+    if (h->sticky) throw sa::SaError{SA_ESTATE, "object is in an error state (load a checkpoint)"};
+    try {
+      for (int32_t s = 0; s < n_steps; ++s)
+        for (auto &P : h->paths)
+          if (P.step < P.n_steps) step_path(h, P);
+      hip_check(hipStreamSynchronize(h->stream), "sync");
+      collect_timing(h);
+    } catch (const sa::SaError &e) {
+      if (e.code == SA_ENOCONV) h->sticky = 1;
+      (void)hipStreamSynchronize(h->stream);
+      collect_timing(h);
+      throw;
+    }
+    return SA_OK;
+  });
+}
+
+int sa_iga_get_step(sa_iga *h, int32_t path, int64_t *step) {
+  return guarded([&]() -> int {
+    if (!h || !step) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    *step = path_of(h, path).step;
+    return SA_OK;
+  });
+}
+
+int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n, const double *x, double *T,
+                             double *grad) {
+  return guarded([&]() -> int {
+    if (!h || (n > 0 && (!x || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (n < 0 || step < 0) throw sa::SaError{SA_EINVAL, "negative size or step"};
+    PathState &P = path_of(h, path);
+    source_field_host(h, P, step, n, x, T, grad);
+    return SA_OK;
+  });
+}
+
+int sa_iga_eval_temperature(sa_iga *h, int32_t path, int64_t n, const double *xi, double *T, double *gradT) {
+  return guarded([&]() -> int {
+    if (!h || (n > 0 && (!xi || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
+    PathState &P = path_of(h, path);
+    if (n == 0) return SA_OK;
+    EvalTables t = eval_tables(h->m.P, n, xi);
+    std::vector<double> Tt(n), Gt(3 * n);
+    source_field_host(h, P, P.step, n, t.x.data(), Tt.data(), Gt.data());
+    TempBufs tb;
+    int64_t *rp = tb.up(t.rowptr, h->stream);
+    int32_t *cl = tb.up(t.col, h->stream);
+    double *vals[4] = {tb.up(t.R, h->stream), tb.up(t.gx, h->stream), tb.up(t.gy, h->stream), tb.up(t.gz, h->stream)};
+    double *out = tb.alloc<double>(4 * n);
+    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(h->stream, n, rp, cl, vals[k], P.v, out + k * n);
+    std::vector<double> hv(4 * n);
+    hip_check(hipMemcpyAsync(hv.data(), out, 4 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    for (int64_t i = 0; i < n; ++i) {
+      T[i] = h->m.mat.T0 + hv[i] + Tt[i];
+      if (gradT)
+        for (int c = 0; c < 3; ++c) gradT[3 * i + c] = hv[(c + 1) * n + i] + Gt[c * n + i];
+    }
+    return SA_OK;
+  });
+}
+
+int sa_iga_get_boundary_fields(sa_iga *h, int32_t path, double *T_gp, double *grad_gp, double *F, double *du) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    PathState &P = path_of(h, path);
+    const int64_t nq = h->nq, nd = h->m.P.ndof;
+    if (T_gp) hip_check(hipMemcpyAsync(T_gp, P.T, nq * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+    if (grad_gp)
+      for (int c = 0; c < 3; ++c)
+        hip_check(hipMemcpyAsync(grad_gp + c * nq, P.g + c * h->stride, nq * sizeof(double), hipMemcpyDeviceToHost,
+                                 h->stream),
+                  "download");
+    if (F) hip_check(hipMemcpyAsync(F, P.F, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+    if (du) hip_check(hipMemcpyAsync(du, P.v, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    return SA_OK;
+  });
+}
+
+int sa_iga_get_boundary_points(sa_iga *h, double *x, double *normal, double *wdS) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    const auto &bt = h->m.bt;
+    if (x) std::memcpy(x, bt.x.data(), bt.x.size() * sizeof(double));
+    if (normal) std::memcpy(normal, bt.nrm.data(), bt.nrm.size() * sizeof(double));
+    if (wdS) std::memcpy(wdS, bt.wdS.data(), bt.wdS.size() * sizeof(double));
+    return SA_OK;
+  });
+}
+
+int sa_iga_apply_operator(sa_iga *h, int32_t which, const double *x, double *y) {
+  return guarded([&]() -> int {
+    if (!h || !x || !y) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (which == 0) h->m.M.apply(x, y);
+    else if (which == 1) h->m.K.apply(x, y);
+    else throw sa::SaError{SA_EINVAL, "which must be 0 (M) or 1 (K)"};
+    return SA_OK;
+  });
+}
+
+int sa_iga_get_info(sa_iga *h, sa_info *info) {
+  return guarded([&]() -> int {
+    if (!h || !info) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    std::memset(info, 0, sizeof(*info));
+    for (int d = 0; d < 3; ++d) info->n_ctrl[d] = h->m.P.n[d];
+    info->n_dof = h->m.P.ndof;
+    info->n_bpts = h->nq;
+    for (int f = 0; f < 7; ++f) info->face_offset[f] = h->m.bt.face_off[f];
+    info->n_paths = (int32_t)h->paths.size();
+    info->n_sources = (int64_t)h->h_tick.size();
+    info->n_dirichlet = h->nD;
+    return SA_OK;
+  });
+}
+
+int sa_iga_get_stats(sa_iga *h, sa_stats *stats) {
+  return guarded([&]() -> int {
+    if (!h || !stats) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    *stats = h->stats;
+    return SA_OK;
+  });
+}
+
+int sa_iga_reset_stats(sa_iga *h) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    h->stats = sa_stats{};
+    return SA_OK;
+  });
+}
+
+int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
+  return guarded([&]() -> int {
+    if (!h || !len) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    const int64_t nd = h->m.P.ndof, nDa = std::max<int64_t>(h->nD, 1);
+    const size_t per = sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
+    const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
+    if (!buf) {
+      *len = need;
+      return SA_OK;
+    }
+    if (*len < need) throw sa::SaError{SA_EINVAL, "checkpoint buffer too small"};
+    char *b = (char *)buf;
+    uint64_t hdr[4] = {kMagic, (uint64_t)h->paths.size(), (uint64_t)nd, (uint64_t)nDa};
+    std::memcpy(b, hdr, sizeof(hdr));
+    b += sizeof(hdr);
+    for (auto &P : h->paths) {
+      std::memcpy(b, &P.step, sizeof(int64_t));
+      b += sizeof(int64_t);
+      hip_check(hipMemcpyAsync(b, P.v, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+      b += nd * sizeof(double);
+      hip_check(hipMemcpyAsync(b, P.F, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+      b += nd * sizeof(double);
+      hip_check(hipMemcpyAsync(b, P.vD, nDa * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+      b += nDa * sizeof(double);
+    }
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    *len = need;
+    return SA_OK;
+  });
+}
+
+int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
+  return guarded([&]() -> int {
+    if (!h || !buf) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    const int64_t nd = h->m.P.ndof, nDa = std::max<int64_t>(h->nD, 1);
+    const size_t per = sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
+    const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
+    if (len < need) throw sa::SaError{SA_EINVAL, "checkpoint too short"};
+    const char *b = (const char *)buf;
+    uint64_t hdr[4];
+    std::memcpy(hdr, b, sizeof(hdr));
+    if (hdr[0] != kMagic || hdr[1] != h->paths.size() || hdr[2] != (uint64_t)nd || hdr[3] != (uint64_t)nDa)
+      throw sa::SaError{SA_EINVAL, "checkpoint does not match this object"};
+    b += sizeof(hdr);
+    for (auto &P : h->paths) {
+      int64_t st;
+      std::memcpy(&st, b, sizeof(int64_t));
+      if (st < 0 || st > P.n_steps) throw sa::SaError{SA_EINVAL, "checkpoint step out of range"};
+      b += sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
+    }
+    b = (const char *)buf + sizeof(hdr);
+    for (auto &P : h->paths) {
+      std::memcpy(&P.step, b, sizeof(int64_t));
+      b += sizeof(int64_t);
+      hip_check(hipMemcpyAsync(P.v, b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
+      b += nd * sizeof(double);
+      hip_check(hipMemcpyAsync(P.F, b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
+      b += nd * sizeof(double);
+      hip_check(hipMemcpyAsync(P.vD, b, nDa * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
+      b += nDa * sizeof(double);
+    }
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    h->sticky = 0;
+    return SA_OK;
+  });
+}
+
+int sa_iga_set_stream(sa_iga *h, void *hip_stream) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    h->stream = hip_stream ? (hipStream_t)hip_stream : h->own_stream;
+    return SA_OK;
+  });
+}
+
+const char *sa_iga_last_error(void) { return g_last_error.c_str(); }
+
+void sa_iga_destroy(sa_iga *h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal declarations of the sa_iga library (host side).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sa_iga.h"
+
+namespace sa {
+
+constexpr int kMaxDeg = 6;
+constexpr int kMaxLocal = (kMaxDeg + 1) * (kMaxDeg + 1) * (kMaxDeg + 1);
+
+struct SaError {
+  int code;
+  std::string msg;
+};
+
+// One knot vector with its non-empty intervals (elements).
+struct Basis1D {
+  int p = 0, n = 0;
+  std::vector<double> t;
+  std::vector<int> span;           // per element: index s of [t_s, t_{s+1})
+  int n_el() const { return (int)span.size(); }
+  // values N[0..p] and first derivatives dN[0..p] of the functions s-p..s at xi
+  void eval(int s, double xi, double *N, double *dN) const;
+  int find_span(double xi) const;  // span index holding xi (closed at the right end)
+};
+
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);  // on [-1, 1]
+
+struct PatchData {
+  Basis1D b[3];
+  int n[3] = {0, 0, 0};
+  int64_t ndof = 0;
+  std::vector<double> ctrl;        // [n2][n1][n0][4]
+  int role[6];
+  int qv[3], qf;
+  double center[3];                // bounding-box centre of the control net (m)
+};
+
+// Basis, geometry and Jacobian at one parametric point.
+struct PointEval {
+  int L = 0;
+  int64_t idx[kMaxLocal];
+  int loc[kMaxLocal][3];
+  double R[kMaxLocal];
+  double dR[kMaxLocal][3];
+  double x[3];
+  double J[3][3];                  // J[i][j] = dx_i / dxi_j
+};
+
+void eval_point(const PatchData &P, const double xi[3], const int span[3], PointEval &out);
+
+// Banded matrix on the control-point grid: row A, offset o <-> (d0, d1, d2)
+// in [-hw0, hw0] x [-hw1, hw1] x [-hw2, hw2], value val[o * nrow + A].
+struct Stencil {
+  int n[3] = {0, 0, 0};
+  int hw[3] = {0, 0, 0};
+  int n_off = 0;
+  int64_t nrow = 0;
+  std::vector<double> val;
+  void init(const int n_[3], const int hw_[3]);
+  int off_index(int d0, int d1, int d2) const {
+    return (d0 + hw[0]) + (2 * hw[0] + 1) * ((d1 + hw[1]) + (2 * hw[1] + 1) * (d2 + hw[2]));
+  }
+  void apply(const double *x, double *y) const;   // host y = S x
+};
+
+struct Csr {
+  int64_t nrow = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+struct BoundaryTables {
+  int64_t nq = 0;
+  int64_t face_off[7];
+  std::vector<double> x, nrm;      // [nq][3]
+  std::vector<double> wdS;         // [nq]
+  std::vector<int8_t> role;        // face role of each point
+  // non-zero functions of every point (the face layer), CSR by point
+  std::vector<int64_t> fptr;
+  std::vector<int64_t> fidx;
+  std::vector<double> fval;
+};
+
+// Fast-diagonalisation data of a Kronecker operator
+//   P = cM (M2 x M1 x M0) + c0 (M2 x M1 x K0) + c1 (M2 x K1 x M0) + c2 (K2 x M1 x M0)
+// on the box of free indices [lo_d, lo_d + m_d) of an n0 x n1 x n2 grid.
+struct FdData {
+  int n[3] = {1, 1, 1};
+  int lo[3] = {0, 0, 0};
+  int m[3] = {1, 1, 1};
+  std::vector<double> U[3];        // m_d x m_d, row-major U[k * m + j]
+  std::vector<double> inv_diag;    // [m2][m1][m0]
+};
+
+struct Model {
+  PatchData P;
+  sa_material mat;
+  sa_solver_options opt;
+  double dt = 0;
+  Stencil M, K;                    // Eqs. 16-17
+  double mean_detJ = 0, mean_metric[3] = {0, 0, 0};
+  BoundaryTables bt;
+  Csr load;                        // rows = DOFs, cols = NEUMANN points, val = R_A(x_q)
+  std::vector<int64_t> dir_dofs;   // sorted
+  std::vector<uint8_t> free_mask;  // 1 = unknown, 0 = Dirichlet
+  Csr dproj;                       // rows = Dirichlet DOFs, cols = DIRICHLET points, val = R_A(x_q)
+  Csr mass_dir;                    // trace mass matrix on the Dirichlet DOFs
+  FdData fd_main, fd_dir;
+  bool fd_dir_ok = false;
+  int free_box_ok = 0;             // Dirichlet set is a union of end layers (box of free DOFs)
+};
+
+void validate_inputs(const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan,
+                     const sa_solver_options &opt);
+void load_patch(const sa_patch *patch, PatchData &P);
+void assemble_volume(Model &m);
+void build_boundary(Model &m);
+void build_fd(Model &m);
+
+}  // namespace sa

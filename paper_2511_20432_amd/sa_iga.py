@@ -1,0 +1,283 @@
+"""ctypes binding of libsa_iga.so (include/sa_iga.h).
+
+Argument marshalling only: every step of the model runs in the library's
+HIP kernels.  The functions keep the C names; `Model` is a small owner of a
+handle for convenience.  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import workloads as W
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libsa_iga.so")
+
+SA_OK, SA_EINVAL, SA_ENOMEM, SA_EDEVICE, SA_ENOCONV, SA_ERANGE, SA_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "SA_OK", -1: "SA_EINVAL", -2: "SA_ENOMEM", -3: "SA_EDEVICE", -4: "SA_ENOCONV",
+                -5: "SA_ERANGE", -6: "SA_ESTATE"}
+STAGES = ["coeff", "sum", "reduce", "load", "dirichlet", "rhs", "pcg", "other"]
+
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+_i32p = C.POINTER(C.c_int32)
+
+
+class sa_patch(C.Structure):
+    _fields_ = [("degree", C.c_int32 * 3), ("n_ctrl", C.c_int32 * 3), ("knots", _dp * 3),
+                ("ctrl_xyzw", _dp), ("face_role", C.c_int32 * 6), ("quad_vol", C.c_int32 * 3),
+                ("quad_face", C.c_int32)]
+
+
+class sa_material(C.Structure):
+    _fields_ = [("k", C.c_double), ("rho", C.c_double), ("cp", C.c_double), ("T0", C.c_double)]
+
+
+class sa_solver_options(C.Structure):
+    _fields_ = [("theta", C.c_double), ("kernel_scale", C.c_double), ("precision", C.c_int32),
+                ("tau_near", C.c_double), ("pcg_rtol", C.c_double), ("pcg_max_iter", C.c_int32),
+                ("preconditioner", C.c_int32), ("timing", C.c_int32), ("points_per_lane", C.c_int32),
+                ("waves_per_group", C.c_int32), ("chunk_sources", C.c_int32)]
+
+
+class sa_scan_path(C.Structure):
+    _fields_ = [("n_paths", C.c_int32), ("src_offset", _i64p), ("xyz", _dp), ("tick", _i64p),
+                ("energy", _dp), ("n_steps", _i32p), ("dt", C.c_double), ("sources_per_step", C.c_int32),
+                ("spot_radius", C.c_double), ("opt", C.POINTER(sa_solver_options))]
+
+
+class sa_info(C.Structure):
+    _fields_ = [("n_ctrl", C.c_int32 * 3), ("n_dof", C.c_int64), ("n_bpts", C.c_int64),
+                ("face_offset", C.c_int64 * 7), ("n_paths", C.c_int32), ("n_sources", C.c_int64),
+                ("n_dirichlet", C.c_int64)]
+
+
+class sa_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("pairs", C.c_int64), ("pairs_near", C.c_int64),
+                ("pcg_iterations", C.c_int64), ("pcg_last_iterations", C.c_int32),
+                ("pcg_last_relres", C.c_double), ("dirichlet_iterations", C.c_int64),
+                ("stage_ms", C.c_double * 8), ("stage_launches", C.c_int64 * 8)]
+
+
+EXPORTS = {
+    "sa_iga_default_options": (C.c_int, [C.POINTER(sa_solver_options)]),
+    "sa_iga_setup": (C.c_int, [C.POINTER(sa_patch), C.POINTER(sa_material), C.POINTER(sa_scan_path),
+                               C.POINTER(C.c_void_p)]),
+    "sa_iga_step": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sa_iga_get_step": (C.c_int, [C.c_void_p, C.c_int32, _i64p]),
+    "sa_iga_eval_temperature": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, _dp, _dp, _dp]),
+    "sa_iga_get_boundary_fields": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, _dp, _dp]),
+    "sa_iga_get_boundary_points": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
+    "sa_iga_apply_operator": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp]),
+    "sa_iga_eval_source_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, _dp, _dp, _dp]),
+    "sa_iga_get_info": (C.c_int, [C.c_void_p, C.POINTER(sa_info)]),
+    "sa_iga_get_stats": (C.c_int, [C.c_void_p, C.POINTER(sa_stats)]),
+    "sa_iga_reset_stats": (C.c_int, [C.c_void_p]),
+    "sa_iga_save": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "sa_iga_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "sa_iga_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sa_iga_last_error": (C.c_char_p, []),
+    "sa_iga_destroy": (None, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library() -> C.CDLL:
+    """Load libsa_iga.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} not found: build it with paper_2511_20432_amd.build.build()")
+    lib = C.CDLL(_LIB_PATH)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code: int):
+    if code != SA_OK:
+        raise SaError(code, load_library().sa_iga_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def default_options() -> sa_solver_options:
+    o = sa_solver_options()
+    check(load_library().sa_iga_default_options(C.byref(o)))
+    return o
+
+
+class Model:
+    """Owner of one sa_iga handle built from a workload description."""
+
+    def __init__(self, patch: W.Patch, material: W.Material, scan: W.ScanPath,
+                 options: Optional[W.Options] = None, **opt_overrides):
+        lib = load_library()
+        self._lib = lib
+        self._keep = []
+
+        def keep(a, dtype):
+            a = np.ascontiguousarray(a, dtype=dtype)
+            self._keep.append(a)
+            return a
+
+        p = sa_patch()
+        for d in range(3):
+            p.degree[d] = patch.degree[d]
+            p.n_ctrl[d] = patch.n_ctrl[d]
+            p.knots[d] = _ptr(keep(patch.knots[d], np.float64), C.c_double)
+            p.quad_vol[d] = patch.quad_vol[d]
+        p.ctrl_xyzw = _ptr(keep(patch.ctrl, np.float64), C.c_double)
+        for f in range(6):
+            p.face_role[f] = patch.face_role[f]
+        p.quad_face = patch.quad_face
+        m = sa_material(material.k, material.rho, material.cp, material.T0)
+        o = default_options()
+        if options is not None:
+            o.theta = options.theta
+            o.kernel_scale = options.kernel_scale
+            o.precision = options.precision
+            o.tau_near = options.tau_near
+            o.pcg_rtol = options.pcg_rtol
+            o.pcg_max_iter = options.pcg_max_iter
+            o.preconditioner = options.preconditioner
+        for k, v in opt_overrides.items():
+            setattr(o, k, v)
+        self.options = o
+        s = sa_scan_path()
+        s.n_paths = scan.n_paths
+        s.src_offset = _ptr(keep(scan.src_offset, np.int64), C.c_int64)
+        s.xyz = _ptr(keep(scan.xyz.reshape(-1, 3) if len(scan.xyz) else np.zeros((1, 3)), np.float64), C.c_double)
+        s.tick = _ptr(keep(scan.tick if len(scan.tick) else np.ones(1, np.int64), np.int64), C.c_int64)
+        s.energy = _ptr(keep(scan.energy if len(scan.energy) else np.zeros(1), np.float64), C.c_double)
+        s.n_steps = _ptr(keep(scan.n_steps, np.int32), C.c_int32)
+        s.dt = scan.dt
+        s.sources_per_step = scan.sources_per_step
+        s.spot_radius = scan.spot_radius
+        s.opt = C.pointer(o)
+        h = C.c_void_p()
+        check(lib.sa_iga_setup(C.byref(p), C.byref(m), C.byref(s), C.byref(h)))
+        self._keep = []
+        self.h = h
+        self.T0 = material.T0
+        self.info = self.get_info()
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.sa_iga_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls -----------------------------------------------------------------
+    def step(self, n: int = 1):
+        check(self._lib.sa_iga_step(self.h, n))
+
+    def get_step(self, path: int = 0) -> int:
+        s = C.c_int64()
+        check(self._lib.sa_iga_get_step(self.h, path, C.byref(s)))
+        return s.value
+
+    def get_info(self) -> sa_info:
+        i = sa_info()
+        check(self._lib.sa_iga_get_info(self.h, C.byref(i)))
+        return i
+
+    def stats(self) -> dict:
+        s = sa_stats()
+        check(self._lib.sa_iga_get_stats(self.h, C.byref(s)))
+        d = {k: getattr(s, k) for k, _ in sa_stats._fields_ if k not in ("stage_ms", "stage_launches")}
+        d["stage_ms"] = {STAGES[i]: s.stage_ms[i] for i in range(8)}
+        d["stage_launches"] = {STAGES[i]: s.stage_launches[i] for i in range(8)}
+        return d
+
+    def reset_stats(self):
+        check(self._lib.sa_iga_reset_stats(self.h))
+
+    def boundary_fields(self, path: int = 0):
+        """T~ [nq], grad T~ [nq, 3] at the boundary points, F [n_dof] and
+        du [n_dof] = T^ - T_c at the control points."""
+        nq, nd = self.info.n_bpts, self.info.n_dof
+        T = np.empty(nq)
+        G = np.empty((3, nq))
+        F = np.empty(nd)
+        u = np.empty(nd)
+        check(self._lib.sa_iga_get_boundary_fields(self.h, path, _ptr(T, C.c_double), _ptr(G, C.c_double),
+                                                   _ptr(F, C.c_double), _ptr(u, C.c_double)))
+        return T, G.T.copy(), F, u
+
+    def boundary_points(self):
+        nq = self.info.n_bpts
+        x = np.empty((nq, 3))
+        n = np.empty((nq, 3))
+        w = np.empty(nq)
+        check(self._lib.sa_iga_get_boundary_points(self.h, _ptr(x, C.c_double), _ptr(n, C.c_double),
+                                                   _ptr(w, C.c_double)))
+        return x, n, w
+
+    def apply_operator(self, which: int, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.empty_like(x)
+        check(self._lib.sa_iga_apply_operator(self.h, which, _ptr(x, C.c_double), _ptr(y, C.c_double)))
+        return y
+
+    def source_field(self, x: np.ndarray, step: int, path: int = 0):
+        x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        n = len(x)
+        T = np.empty(n)
+        G = np.empty((3, n))
+        check(self._lib.sa_iga_eval_source_field(self.h, path, step, n, _ptr(x, C.c_double),
+                                                 _ptr(T, C.c_double), _ptr(G, C.c_double)))
+        return T, G.T.copy()
+
+    def eval_temperature(self, xi: np.ndarray, path: int = 0):
+        xi = np.ascontiguousarray(xi, np.float64).reshape(-1, 3)
+        n = len(xi)
+        T = np.empty(n)
+        G = np.empty((n, 3))
+        check(self._lib.sa_iga_eval_temperature(self.h, path, n, _ptr(xi, C.c_double), _ptr(T, C.c_double),
+                                                _ptr(G, C.c_double)))
+        return T, G
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        check(self._lib.sa_iga_save(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        check(self._lib.sa_iga_save(self.h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        check(self._lib.sa_iga_load(self.h, buf, len(blob)))
+
+    def set_stream(self, stream_handle: Optional[int]):
+        check(self._lib.sa_iga_set_stream(self.h, C.c_void_p(stream_handle) if stream_handle else None))
+
+
+def from_workload(w: W.Workload, **opt_overrides) -> Model:
+    return Model(w.patch, w.material, w.scan, w.options, **opt_overrides)

@@ -1,0 +1,87 @@
+"""The C-ABI library loads, exports every function include/sa_iga.h declares,
+and rejects invalid inputs before touching a device (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2511_20432_amd import sa_iga
+from paper_2511_20432_amd import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sa_iga.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sa_iga_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sa_iga.load_library()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sa_iga.EXPORTS)
+
+
+def test_default_options():
+    o = sa_iga.default_options()
+    assert o.theta == 0.5 and o.kernel_scale == 1.0 and o.pcg_rtol == 1e-13
+    assert o.precision == 0 and o.preconditioner == 1 and abs(o.tau_near - 2e-4) < 1e-18
+
+
+def _expect(code, patch, mat, scan, **kw):
+    with pytest.raises(sa_iga.SaError) as e:
+        sa_iga.Model(patch, mat, scan, None, **kw)
+    assert e.value.code == code, str(e.value)
+
+
+def test_invalid_inputs_rejected_before_device():
+    patch = W.small_block()
+    scan = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    bad = W.small_block()
+    bad.ctrl[0, 0, 0, 3] = -1.0
+    _expect(sa_iga.SA_EINVAL, bad, W.MAT_CFG, scan)
+    bad = W.small_block()
+    bad.knots = (bad.knots[0][::-1].copy(), bad.knots[1], bad.knots[2])
+    _expect(sa_iga.SA_EINVAL, bad, W.MAT_CFG, scan)
+    _expect(sa_iga.SA_EINVAL, patch, W.Material(-1.0, 1, 1, 1), scan)
+    s2 = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    s2.tick[5] = 2
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, s2)
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, theta=1.5)
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, points_per_lane=3)
+    s3 = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    s3.xyz[0, 0] = np.nan
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, s3)
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_gpu_present(), reason="a GPU is present")
+def test_setup_without_device_reports_edevice():
+    patch = W.small_block()
+    scan = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    _expect(sa_iga.SA_EDEVICE, patch, W.MAT_CFG, scan)
+
+
+def test_null_arguments():
+    lib = sa_iga.load_library()
+    assert lib.sa_iga_step(None, 1) == sa_iga.SA_EINVAL
+    assert lib.sa_iga_get_info(None, None) == sa_iga.SA_EINVAL
+    assert lib.sa_iga_default_options(None) == sa_iga.SA_EINVAL
+    out = C.c_void_p(1)
+    assert lib.sa_iga_setup(None, None, None, C.byref(out)) == sa_iga.SA_EINVAL
+    assert out.value is None
+    lib.sa_iga_destroy(None)
+    assert isinstance(lib.sa_iga_last_error(), bytes)

@@ -1,0 +1,242 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: FP64 form within 1e-9 normwise relative (max |a-b| / max |b| per
+array: T~, each gradient component, F, u - T_c); FP32 far-field form within
+0.05 K on the temperature at every boundary quadrature point.
+"""
+import numpy as np
+import pytest
+
+from oracle import iga, solver
+from paper_2511_20432_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _gpu_model(patch, mat, scan, **kw):
+    from paper_2511_20432_amd import sa_iga
+    opts = kw.pop("options", None)
+    return sa_iga.Model(patch, mat, scan, opts, **kw)
+
+
+def _compare(gm, om, label, check_u=True):
+    """Normwise relative errors per output array (the gradient is one array)."""
+    T, G, F, du = gm.boundary_fields()
+    Tr, Gr = om.boundary_field(om.step)
+    errs = {"T": rel(T, Tr), "grad": rel(G, Gr),
+            "F": rel(F, om.F) if np.abs(om.F).max() > 0 else np.abs(F).max()}
+    if check_u:
+        errs["du"] = rel(du, om.w) if np.abs(om.w).max() > 0 else np.abs(du).max()
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    return errs
+
+
+def test_boundary_tables_and_operators_match_oracle():
+    patch = W.annulus_patch(2e-3, 4e-3, 1e-3, (6, 3, 2), 2)
+    scan = W.single_track((0, 3e-3, 1e-3), (1e-4, 3e-3, 1e-3), 50.0, 1.0, 1e-5, 5)
+    gm = _gpu_model(patch, W.MAT_CFG, scan)
+    x, n, w = gm.boundary_points()
+    bt = iga.boundary_tables(patch)
+    assert np.abs(x - bt["x"]).max() < 1e-15
+    assert np.abs(n - bt["n"]).max() < 1e-13
+    assert rel(w, bt["wdS"]) < 1e-13
+    M, K = iga.assemble_mk(patch, W.MAT_CFG)
+    v = np.random.default_rng(0).normal(size=patch.n_dof)
+    assert rel(gm.apply_operator(0, v), M @ v) < 1e-13
+    assert rel(gm.apply_operator(1, v), K @ v) < 1e-13
+
+
+def test_small_block_fp64_steps():
+    """Ragged sizes (594 boundary points), several steps, FD preconditioner."""
+    patch = W.small_block()
+    scan = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    gm = _gpu_model(patch, W.MAT_CFG, scan)
+    om = solver.Model(patch, W.MAT_CFG, scan)
+    for n in (1, 3, 10):
+        gm.step(n)
+        om.advance(n)
+        errs = _compare(gm, om, f"small block step {om.step}")
+        assert max(errs.values()) <= TOL64, errs
+
+
+def test_thin_plate_dirichlet_data():
+    """Thin plate: the point-source field reaches the Dirichlet bottom within a
+    few steps, so the projected Dirichlet values are large."""
+    patch = W.block_patch((0, 0, 0), (0.8e-3, 0.6e-3, 0.15e-3), (6, 5, 2), 2)
+    scan = W.single_track((0.1e-3, 0.3e-3, 0.15e-3), (0.7e-3, 0.3e-3, 0.15e-3), 60.0, 1.0, 1e-5, 5)
+    gm = _gpu_model(patch, W.MAT_CFG, scan)
+    om = solver.Model(patch, W.MAT_CFG, scan)
+    for n in (2, 10, 25):
+        gm.step(n)
+        om.advance(n)
+        errs = _compare(gm, om, f"thin plate step {om.step}")
+        assert max(errs.values()) <= TOL64, errs
+    assert np.abs(om.w[om.D]).max() > 1e-2 * np.abs(om.w).max()
+
+
+def test_small_block_jacobi_and_theta():
+    patch = W.small_block()
+    scan = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    opts = W.Options(theta=0.7, preconditioner=W.PRECOND_JACOBI)
+    gm = _gpu_model(patch, W.MAT_CFG, scan, options=opts)
+    om = solver.Model(patch, W.MAT_CFG, scan, theta=0.7)
+    gm.step(6)
+    om.advance(6)
+    errs = _compare(gm, om, "jacobi theta=0.7")
+    assert max(errs.values()) <= TOL64, errs
+    assert gm.stats()["pcg_iterations"] > 6
+
+
+def test_annulus_nurbs_fp64():
+    """Curved NURBS patch (left-handed parametrisation): FD is only a
+    preconditioner there, so PCG iterates."""
+    patch = W.annulus_patch(2e-3, 4e-3, 1e-3, (8, 4, 3), 2)
+    segs = W.annulus_scan_segments(0)[:1]
+    src = W.sources_from_segments(segs, 1e-5 / 8)
+    scan = W.make_scan([src], 1e-5, 8, n_steps=[12])
+    gm = _gpu_model(patch, W.MAT_CFG, scan)
+    om = solver.Model(patch, W.MAT_CFG, scan)
+    gm.step(12)
+    om.advance(12)
+    errs = _compare(gm, om, "annulus")
+    assert max(errs.values()) <= TOL64, errs
+    assert gm.stats()["pcg_last_iterations"] > 1
+
+
+def test_cfg1_full_run_fp64(cfg1_workload):
+    w = cfg1_workload
+    gm = _gpu_model(w.patch, w.material, w.scan)
+    om = solver.Model(w.patch, w.material, w.scan)
+    done = 0
+    for target in (1, 10, 50, 150):
+        gm.step(target - done)
+        om.advance(target - done)
+        done = target
+        errs = _compare(gm, om, f"cfg1 step {target}")
+        assert max(errs.values()) <= TOL64, errs
+    assert gm.get_step() == 150
+    gm.step(5)                      # past the end of the scan: nothing moves
+    assert gm.get_step() == 150
+
+
+def test_cfg1_fp32_far_within_005K(cfg1_workload):
+    w = cfg1_workload
+    opts = W.Options(precision=W.PRECISION_FP32_FAR, tau_near=2e-4)
+    gm = _gpu_model(w.patch, w.material, w.scan, options=opts)
+    om = solver.Model(w.patch, w.material, w.scan)
+    R = om.bt["R"]
+    worst = 0.0
+    done = 0
+    for target in (30, 90, 150):
+        gm.step(target - done)
+        om.advance(target - done)
+        done = target
+        T, G, F, du = gm.boundary_fields()
+        Tr, Gr = om.boundary_field(target)
+        err = np.abs((T + R @ du) - (Tr + R @ om.w)).max()
+        worst = max(worst, err)
+        print(f"cfg1 fp32-far step {target}: max |T - T_ref| = {err:.3e} K", flush=True)
+    st = gm.stats()
+    assert st["pairs_near"] < st["pairs"]
+    assert worst <= 0.05
+
+
+def test_eval_temperature_matches_oracle(cfg1_workload):
+    w = cfg1_workload
+    gm = _gpu_model(w.patch, w.material, w.scan)
+    om = solver.Model(w.patch, w.material, w.scan)
+    gm.step(40)
+    om.advance(40)
+    rng = np.random.default_rng(7)
+    xi = rng.random((200, 3))
+    xi[:20, 2] = 1.0                 # on the top face
+    xi[20:30] = [0.0, 0.0, 0.0]      # a corner
+    T, G = gm.eval_temperature(xi)
+    Tr, Gr, _ = om.evaluate(xi)
+    assert rel(T - w.material.T0, Tr - w.material.T0) <= TOL64
+    assert rel(G, Gr) <= TOL64
+    with pytest.raises(Exception):
+        gm.eval_temperature(np.array([[0.5, 0.5, 1.5]]))
+
+
+def test_source_field_at_points():
+    w = W.cfg1()
+    gm = _gpu_model(w.patch, w.material, w.scan)
+    rng = np.random.default_rng(3)
+    x = np.column_stack([rng.uniform(0, 2e-3, 300), rng.uniform(0, 1e-3, 300), rng.uniform(0.8e-3, 1e-3, 300)])
+    from oracle import pointsource
+    for step in (0, 1, 77, 150):
+        T, G = gm.source_field(x, step)
+        Tr, Gr = pointsource.field(x, w.scan.xyz, w.scan.tick, w.scan.energy, step, w.scan, w.material)
+        if step == 0:
+            assert np.abs(T).max() == 0 and np.abs(G).max() == 0
+        else:
+            assert rel(T, Tr) <= TOL64 and rel(G, Gr) <= TOL64
+
+
+def test_deterministic_and_checkpoint_resume():
+    patch = W.small_block()
+    scan = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    a = _gpu_model(patch, W.MAT_CFG, scan)
+    b = _gpu_model(patch, W.MAT_CFG, scan)
+    a.step(8)
+    blob = a.save()
+    a.step(8)
+    b.step(8)
+    b.load(blob)
+    b.step(8)
+    fa, fb = a.boundary_fields(), b.boundary_fields()
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+    c = _gpu_model(patch, W.MAT_CFG, scan)
+    c.step(16)
+    for x, y in zip(fa, c.boundary_fields()):
+        assert np.array_equal(x, y)
+
+
+def test_empty_scan_and_zero_steps():
+    patch = W.small_block()
+    empty = W.make_scan([(np.zeros((0, 3)), np.zeros(0, np.int64), np.zeros(0))], 1e-5, 5, n_steps=[4])
+    gm = _gpu_model(patch, W.MAT_CFG, empty)
+    gm.step(0)
+    assert gm.get_step() == 0
+    gm.step(4)
+    T, G, F, du = gm.boundary_fields()
+    assert np.abs(T).max() == 0 and np.abs(F).max() == 0
+    assert np.abs(du).max() == 0
+
+
+def test_two_paths_match_separate_oracles():
+    patch = W.small_block()
+    s1 = W.sources_from_segments([W.Segment("line", 50.0, 1.0, p0=np.array([0.1e-3, 0.1e-3, 0.5e-3]),
+                                            p1=np.array([0.6e-3, 0.1e-3, 0.5e-3]))], 2e-6)
+    s2 = W.sources_from_segments([W.Segment("line", 90.0, 0.8, p0=np.array([0.9e-3, 0.5e-3, 0.5e-3]),
+                                            p1=np.array([0.2e-3, 0.3e-3, 0.5e-3]))], 2e-6)
+    scan = W.make_scan([s1, s2], 1e-5, 5, n_steps=[7, 11])
+    gm = _gpu_model(patch, W.MAT_CFG, scan)
+    gm.step(20)
+    assert gm.get_step(0) == 7 and gm.get_step(1) == 11
+    for p, n in ((0, 7), (1, 11)):
+        om = solver.Model(patch, W.MAT_CFG, scan, path=p)
+        om.advance(n)
+        T, G, F, du = gm.boundary_fields(p)
+        Tr, Gr = om.boundary_field(n)
+        assert rel(T, Tr) <= TOL64 and rel(F, om.F) <= TOL64
+        assert rel(du, om.w) <= TOL64
+
+
+def test_invalid_inputs_raise():
+    from paper_2511_20432_amd import sa_iga
+    patch = W.small_block()
+    scan = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    scan.tick[3] = 1                 # decreasing ticks
+    with pytest.raises(sa_iga.SaError) as e:
+        _gpu_model(patch, W.MAT_CFG, scan)
+    assert e.value.code == sa_iga.SA_EINVAL

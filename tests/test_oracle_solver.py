@@ -80,15 +80,16 @@ def test_load_vector_total_equals_box_mass_loss():
 
 
 def test_dirichlet_projection_reproduces_trace_functions():
-    """The L2 projection is exact on the trace space: data T0 - T~ equal to a
-    bottom-trace spline is returned as its coefficients."""
+    """The L2 projection is exact on the trace space: Dirichlet data whose
+    deviation -T~ from T_c is a bottom-trace spline is returned as its
+    coefficients."""
     patch = W.block_patch((0, 0, 0), (0.5e-3, 0.4e-3, 0.3e-3), (3, 3, 2), 2)
     m = solver.Model(patch, MAT, _empty_scan(1), assemble=False)
     rng = np.random.default_rng(4)
     c = rng.normal(size=len(m.D))
     Rd = m.bt["R"][m.dir][:, m.D]
     vals = Rd @ c
-    uD = m.dirichlet_values(MAT.T0 - vals)
+    uD = m.dirichlet_values(-vals)
     np.testing.assert_allclose(uD, c, atol=1e-12 * np.abs(c).max())
 
 
