@@ -1,0 +1,199 @@
+"""Benchmark of the semi-analytical IGA hot path on one MI355X.
+
+A step is one theta-step of the whole path: source coefficients, kernel sum
+at every boundary quadrature point (T~ and grad T~), flux and Dirichlet
+densities, load-vector and projection gathers, Dirichlet projection solve,
+theta-scheme right-hand side and PCG solve.
+
+Workload: the raster scan on the 4 x 2 x 1 mm cubic B-spline block
+(64 x 32 x 16 elements, 64,512 boundary points, 10 boustrophedon tracks,
+80 W, 1 m/s, 5 sources per 10 us step).  Both forms run over the same steps:
+the FP64 form and the FP32 far-field form (sources older than 0.2 ms in
+FP32).  `value` is the source x point pair rate of the FP32 far-field form
+with inputs resident in HBM; the FP64 form, the step rates, the speedup and
+the temperature difference between the forms are reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "source×point pairs/s + θ-steps/s; mixed+surrogate vs FP64 GPU at ≤0.5 K err"
+
+# gfx950: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = lane-operations per second
+LANE_OPS = 256 * 64 * 2.4e9
+# VALU issue slots per source x point pair of the two sum loops (from the
+# compiled loops: FP32 far: 4 FMA for the exponent, 5 for the
+# accumulations + per-source overhead; v_exp_f32 counted at 4 slots,
+# quarter rate); FP64: 4 FMA, clamp, 2 for rounding, 2 reduction, 13 Horner,
+# ldexp, 5 accumulations
+SLOTS_FP32 = 9 + 4
+SLOTS_FP64 = 28
+
+
+def _timed_run(model, warmup, steps, n_total):
+    """Advance warmup steps, then time `steps` theta-steps.  Reaching the end
+    of the scan restores the initial state (a checkpoint taken at step 0)."""
+    import torch
+    initial = model.save()
+    done = 0
+
+    def advance(n):
+        nonlocal done
+        while n > 0:
+            left = n_total - (done % n_total) if n_total > 0 else n
+            k = min(n, left)
+            model.step(k)
+            done += k
+            n -= k
+            if n_total > 0 and done % n_total == 0:
+                model.load(initial)
+
+    advance(warmup)
+    model.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    advance(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, model.stats()
+
+
+def run_form(w, precision, warmup, steps, timing=True):
+    from paper_2511_20432_amd import sa_iga
+    from paper_2511_20432_amd import workloads as W
+    opts = W.Options(precision=precision, tau_near=2e-4)
+    t0 = time.perf_counter()
+    m = sa_iga.Model(w.patch, w.material, w.scan, opts, timing=1 if timing else 0)
+    setup_s = time.perf_counter() - t0
+    n_total = int(w.scan.n_steps[0])
+    dt, st = _timed_run(m, warmup, steps, n_total)
+    return m, dt, st, setup_s
+
+
+def cpu_baseline(w, step, n_steps=16, threads=None):
+    """The oracle's kernel sum (Eqs. 7-8) at every boundary point over a
+    window of n_steps consecutive steps."""
+    from oracle import iga, pointsource
+    bt = iga.boundary_tables(w.patch)
+    x = bt["x"]
+    sc = w.scan
+    nthr = threads or pointsource.default_threads()
+    pairs = 0
+    t0 = time.perf_counter()
+    for s in range(step, step + n_steps):
+        pointsource.field(x, sc.xyz, sc.tick, sc.energy, s, sc, w.material, threads=nthr)
+        pairs += len(x) * int(np.searchsorted(sc.tick, s * sc.sources_per_step, side="right"))
+    dt = time.perf_counter() - t0
+    cpu = platform.processor() or platform.machine()
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": nthr, "kind": "oracle",
+            "sample": f"numpy FP64 kernel sum over steps {step}..{step + n_steps - 1} of the raster run at all "
+                      f"{len(x)} boundary points: {pairs:.3e} pairs in {dt:.1f} s on {nthr} threads ({cpu})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32far,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's sharding plan is "
+              "described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    from paper_2511_20432_amd import workloads as W
+
+    w = W.cfg2(seed=0)
+    n_total = int(w.scan.n_steps[0])
+    steps = args.steps if args.steps is not None else max(1, n_total - args.warmup)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    res = {}
+    models = {}
+    for f in forms:
+        prec = {"fp32far": W.PRECISION_FP32_FAR, "fp64": W.PRECISION_FP64}[f]
+        print(f"[bench] form {f}: setup + {args.warmup} warmup + {steps} timed steps", file=sys.stderr, flush=True)
+        m, dt, st, setup_s = run_form(w, prec, args.warmup, steps)
+        res[f] = {"seconds": dt, "stats": st, "setup_s": setup_s}
+        models[f] = m
+        print(f"[bench] form {f}: {dt:.3f} s, {st['pairs'] / dt:.3e} pairs/s, "
+              f"sum {st['stage_ms']['sum']:.1f} ms, pcg {st['stage_ms']['pcg']:.1f} ms", file=sys.stderr, flush=True)
+
+    # temperature difference between the forms at the end of the timed steps
+    max_err = None
+    if "fp32far" in models and "fp64" in models:
+        Ta, _, _, ua = models["fp32far"].boundary_fields()
+        Tb, _, _, ub = models["fp64"].boundary_fields()
+        # R_A >= 0 and sum_A R_A = 1 at every boundary point, so this bounds the
+        # difference of T = T~ + sum_A R_A u_A at the points
+        max_err = float(np.abs(Ta - Tb).max() + np.abs(ua - ub).max())
+
+    main_form = "fp32far" if "fp32far" in res else forms[0]
+    r = res[main_form]
+    st = r["stats"]
+    pairs_s = st["pairs"] / r["seconds"]
+    sum_ms = st["stage_ms"]["sum"]
+    launches = max(1, st["stage_launches"]["sum"])
+    slots = SLOTS_FP32 if main_form == "fp32far" else SLOTS_FP64
+    achieved = st["pairs"] / (sum_ms * 1e-3) if sum_ms > 0 else 0.0
+    peak = LANE_OPS / slots
+    out = {
+        "metric": METRIC, "value": pairs_s, "unit": "pairs/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * r["seconds"] / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if main_form == "fp32far" else "f64", "data": "synthetic",
+        "config": {"workload": "raster: 4x2x1 mm block, cubic B-splines 64x32x16 elements, 64512 boundary "
+                               "points, 10 tracks x 0.1 mm hatch, 80 W, 1 m/s, dt 10 us, 5 sources/step, "
+                               f"{n_total} steps, {len(w.scan.tick)} sources, seed 0",
+                   "form": main_form, "tau_near_s": 2e-4, "theta": 0.5, "pcg_rtol": 1e-13,
+                   "preconditioner": "fast diagonalisation"},
+        "steps_per_s": steps / r["seconds"],
+        "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Gpair/s",
+                     "frac": achieved / peak if peak else None, "traffic": None,
+                     "kernel": "k_sum", "avg_launch_ms": sum_ms / launches,
+                     "pairs_per_launch": st["pairs"] / launches},
+        "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
+        "setup_s": r["setup_s"],
+    }
+    if "fp64" in res and main_form != "fp64":
+        s64 = res["fp64"]["stats"]
+        t64 = res["fp64"]["seconds"]
+        out["fp64"] = {"value": s64["pairs"] / t64, "unit": "pairs/s", "steps_per_s": steps / t64,
+                       "ms_per_step": 1e3 * t64 / steps,
+                       "sum_gpair_s": s64["pairs"] / (s64["stage_ms"]["sum"] * 1e-3) / 1e9
+                       if s64["stage_ms"]["sum"] > 0 else None,
+                       "sum_frac_of_fp64_peak": (s64["pairs"] / (s64["stage_ms"]["sum"] * 1e-3))
+                       / (LANE_OPS / SLOTS_FP64) if s64["stage_ms"]["sum"] > 0 else None}
+        out["speedup_vs_fp64"] = t64 / r["seconds"]
+        out["max_err_K_vs_fp64"] = max_err
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle kernel sum)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, step=min(n_total - 16, 1900))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
