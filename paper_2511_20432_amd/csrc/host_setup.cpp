@@ -678,8 +678,13 @@ static void gen_eigen(const std::vector<double> &Mf, const std::vector<double> &
 
 void build_fd(Model &m) {
   PatchData &P = m.P;
-  std::vector<double> Mh[3], Kh[3];
-  for (int d = 0; d < 3; ++d) param_mats_1d(P.b[d], P.b[d].p + 2, Mh[d], Kh[d]);
+  // 1-D factors integrated with the rules the assembled matrices use, so that
+  // on an affine patch the Kronecker operator equals them exactly
+  std::vector<double> Mh[3], Kh[3], Mf[3], Kf[3];
+  for (int d = 0; d < 3; ++d) {
+    param_mats_1d(P.b[d], P.qv[d], Mh[d], Kh[d]);
+    param_mats_1d(P.b[d], P.qf, Mf[d], Kf[d]);
+  }
   // main operator A = M/dt + theta K on the box of free DOFs
   FdData &F = m.fd_main;
   std::vector<double> lam[3];
@@ -722,7 +727,7 @@ void build_fd(Model &m) {
       G.n[k] = P.n[dd];
       G.lo[k] = 0;
       G.m[k] = P.n[dd];
-      gen_eigen(Mh[dd], Kh[dd], P.n[dd], 0, P.n[dd], G.U[k], lm[k]);
+      gen_eigen(Mf[dd], Kf[dd], P.n[dd], 0, P.n[dd], G.U[k], lm[k]);
     }
     G.n[2] = G.m[2] = 1;
     G.lo[2] = 0;
@@ -730,6 +735,85 @@ void build_fd(Model &m) {
     G.inv_diag.assign((size_t)G.m[0] * G.m[1], 1.0 / area);
     m.fd_dir_ok = true;
   }
+}
+
+// z = P^{-1} r on the free box (host reference of the device FD solve);
+// r and z are full vectors on the n-grid, z is zero outside the box
+void fd_apply_host(const FdData &F, const double *r, double *z, int64_t n_full) {
+  const int m0 = F.m[0], m1 = F.m[1], m2 = F.m[2];
+  const int64_t nb = (int64_t)m0 * m1 * m2;
+  std::vector<double> t(nb), u(nb);
+  auto full = [&](int j0, int j1, int j2) {
+    return (int64_t)(j0 + F.lo[0]) + (int64_t)F.n[0] * ((j1 + F.lo[1]) + (int64_t)F.n[1] * (j2 + F.lo[2]));
+  };
+  auto cidx = [&](int j0, int j1, int j2) { return (int64_t)j0 + (int64_t)m0 * (j1 + (int64_t)m1 * j2); };
+  for (int j2 = 0; j2 < m2; ++j2)
+    for (int j1 = 0; j1 < m1; ++j1)
+      for (int j0 = 0; j0 < m0; ++j0) {
+        double s = 0;
+        for (int k = 0; k < m0; ++k) s += F.U[0][(size_t)k * m0 + j0] * r[full(k, j1, j2)];
+        t[cidx(j0, j1, j2)] = s;
+      }
+  for (int j2 = 0; j2 < m2; ++j2)
+    for (int j1 = 0; j1 < m1; ++j1)
+      for (int j0 = 0; j0 < m0; ++j0) {
+        double s = 0;
+        for (int k = 0; k < m1; ++k) s += F.U[1][(size_t)k * m1 + j1] * t[cidx(j0, k, j2)];
+        u[cidx(j0, j1, j2)] = s;
+      }
+  for (int j2 = 0; j2 < m2; ++j2)
+    for (int j1 = 0; j1 < m1; ++j1)
+      for (int j0 = 0; j0 < m0; ++j0) {
+        double s = 0;
+        for (int k = 0; k < m2; ++k) s += F.U[2][(size_t)k * m2 + j2] * u[cidx(j0, j1, k)];
+        t[cidx(j0, j1, j2)] = s * F.inv_diag[cidx(j0, j1, j2)];
+      }
+  for (int k2 = 0; k2 < m2; ++k2)
+    for (int j1 = 0; j1 < m1; ++j1)
+      for (int j0 = 0; j0 < m0; ++j0) {
+        double s = 0;
+        for (int j = 0; j < m2; ++j) s += F.U[2][(size_t)k2 * m2 + j] * t[cidx(j0, j1, j)];
+        u[cidx(j0, j1, k2)] = s;
+      }
+  for (int k2 = 0; k2 < m2; ++k2)
+    for (int k1 = 0; k1 < m1; ++k1)
+      for (int j0 = 0; j0 < m0; ++j0) {
+        double s = 0;
+        for (int j = 0; j < m1; ++j) s += F.U[1][(size_t)k1 * m1 + j] * u[cidx(j0, j, k2)];
+        t[cidx(j0, k1, k2)] = s;
+      }
+  for (int64_t i = 0; i < n_full; ++i) z[i] = 0.0;
+  for (int k2 = 0; k2 < m2; ++k2)
+    for (int k1 = 0; k1 < m1; ++k1)
+      for (int k0 = 0; k0 < m0; ++k0) {
+        double s = 0;
+        for (int j = 0; j < m0; ++j) s += F.U[0][(size_t)k0 * m0 + j] * t[cidx(j, k1, k2)];
+        z[full(k0, k1, k2)] = s;
+      }
+}
+
+// Is the FD solve an exact inverse of the operator S restricted to the free
+// box (affine axis-aligned geometry)?  Checked on a fixed pseudo-random vector.
+double fd_inverse_defect(const FdData &F, const Stencil &S, const std::vector<double> &Sval,
+                         const std::vector<uint8_t> &free_mask) {
+  const int64_t n = S.nrow;
+  std::vector<double> y(n, 0.0), z(n), w(n);
+  uint64_t st = 0x9e3779b97f4a7c15ull;
+  for (int64_t i = 0; i < n; ++i) {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    if (free_mask[i]) y[i] = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+  }
+  fd_apply_host(F, y.data(), z.data(), n);
+  Stencil T = S;
+  T.val = Sval;
+  T.apply(z.data(), w.data());
+  double num = 0, den = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (free_mask[i]) {
+      num = std::max(num, std::fabs(w[i] - y[i]));
+      den = std::max(den, std::fabs(y[i]));
+    }
+  return den > 0 ? num / den : 0.0;
 }
 
 }  // namespace sa

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -12,6 +14,7 @@
 
 #include "kernels.h"
 #include "sa_internal.h"
+#include "solver.h"
 
 namespace {
 
@@ -114,6 +117,21 @@ struct sa_iga {
   sa_stats stats{};
   int sticky = 0;
   StageEvents ev[SA_N_STAGES];
+  // fused solver path
+  sa::GatherRows grows{}, drows{};
+  bool dir_fused = false, dir_exact = false;
+  sa::FusedPcg fd_dirp{};                // direct Kronecker solve of the projection
+  sa::PcgScalars *sc_dir = nullptr;
+  sa::DirArgs dargs{};
+  bool pcg_fused = false, fd_exact = false;
+  int pcg_budget = 2;                    // fixed iterations when the FD solve is exact: the
+                                         // residual after the first is near kappa(A) eps
+  sa::FusedPcg fp{};
+  double *t_box = nullptr, *part_rz2 = nullptr, *part_rrs = nullptr, *part_pq2 = nullptr, *part_b2 = nullptr;
+  int hw0 = 1;
+  sa::SolveStatus *d_status = nullptr;   // ring of per-solve records
+  int64_t status_cap = 0, status_used = 0;
+  size_t lds_per_block = 65536;
   ~sa_iga();
 };
 
@@ -355,46 +373,127 @@ int pcg_run(sa_iga *h, PcgSpec &s, double *relres) {
   }
 }
 
+sa::SolveStatus *next_status(sa_iga *h);
+
 void step_path(sa_iga *h, PathState &P) {
   const int64_t s1 = P.step + 1;
+  const int64_t nd = h->m.P.ndof;
   sum_at_points(h, P, s1, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2,
                 h->role, h->nx, h->ny, h->nz, h->wdS, P.T, P.g, h->ld);
   {
     StageScope s(h, SA_STAGE_LOAD);
-    sa::launch_gather(h->stream, h->load.nrow, h->load.rowptr, h->load.col, h->load.val, h->ld, h->Fnew);
-    sa::launch_gather(h->stream, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->ld, h->bD);
+    // F^{n+1} on the non-empty rows, and x <- v (the theta-step iterate)
+    sa::launch_gather_rows(h->stream, h->grows, h->ld, h->Fnew, nd, P.v, h->xnew);
   }
   if (h->nD > 0) {
     StageScope s(h, SA_STAGE_DIRICHLET);
-    PcgSpec d;
-    d.n = h->nD;
-    d.stencil = false;
-    d.csr = h->mdir.op();
-    d.fd = h->m.opt.preconditioner == SA_PRECOND_FD && h->m.fd_dir_ok;
-    d.fdop = h->fd_dir.op;
-    d.invdiag = h->mdir_invdiag;
-    d.x = P.vD;
-    d.r = h->rD;
-    d.z = h->zD;
-    d.p = h->pD;
-    d.q = h->qD;
-    d.n_part_b = sa::parts_for(h->nD);
-    sa::launch_csr_init(h->stream, d.csr, h->bD, P.vD, h->rD, h->part_b);
-    double rr = 0;
-    h->stats.dirichlet_iterations += pcg_run(h, d, &rr);
+    if (h->dir_exact) {
+      sa::launch_gather_rows(h->stream, h->drows, h->ld, h->bD, 0, nullptr, nullptr);
+      sa::FusedPcg f = h->fd_dirp;
+      f.z = P.vD;
+      f.scatter_out = h->xnew;
+      sa::launch_fd_pass(h->stream, f, 0, false, false);
+    } else if (h->dir_fused) {
+      sa::launch_gather_rows(h->stream, h->drows, h->ld, h->bD, 0, nullptr, nullptr);
+      sa::DirArgs a = h->dargs;
+      a.b = h->bD;
+      a.vD = P.vD;
+      a.xfull = h->xnew;
+      a.status = next_status(h);
+      sa::launch_dirichlet(h->stream, a);
+    } else {
+      sa::launch_gather(h->stream, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->ld, h->bD);
+      PcgSpec d;
+      d.n = h->nD;
+      d.stencil = false;
+      d.csr = h->mdir.op();
+      d.fd = h->m.opt.preconditioner == SA_PRECOND_FD && h->m.fd_dir_ok;
+      d.fdop = h->fd_dir.op;
+      d.invdiag = h->mdir_invdiag;
+      d.x = P.vD;
+      d.r = h->rD;
+      d.z = h->zD;
+      d.p = h->pD;
+      d.q = h->qD;
+      d.n_part_b = sa::parts_for(h->nD);
+      sa::launch_csr_init(h->stream, d.csr, h->bD, P.vD, h->rD, h->part_b);
+      double rr = 0;
+      h->stats.dirichlet_iterations += pcg_run(h, d, &rr);
+      sa::launch_scatter_dirichlet(h->stream, h->nD, h->dir_dofs, P.vD, h->xnew);
+    }
   }
-  {
-    StageScope s(h, SA_STAGE_RHS);
-    const int64_t nd = h->m.P.ndof;
-    hip_check(hipMemcpyAsync(h->xnew, P.v, nd * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "copy");
-    sa::launch_scatter_dirichlet(h->stream, h->nD, h->dir_dofs, P.vD, h->xnew);
-    sa::launch_theta_init(h->stream, h->Aop, h->Bval, P.v, h->Fnew, P.F, h->m.opt.theta, h->xnew, h->r,
-                          h->part_b);
-  }
-  {
+  if (h->pcg_fused) {
+    {
+      StageScope s(h, SA_STAGE_RHS);
+      sa::SlArgs a{};
+      a.nrow = nd;
+      a.n0 = h->Aop.n[0];
+      a.n1 = h->Aop.n[1];
+      a.hw1 = h->Aop.hw[1];
+      a.hw2 = h->Aop.hw[2];
+      a.A = h->Aop.A;
+      a.B = h->Bval;
+      a.mask = h->free_mask;
+      a.x = h->xnew;
+      a.v = P.v;
+      a.F1 = h->Fnew;
+      a.F0 = P.F;
+      a.theta = h->m.opt.theta;
+      a.out = h->r;
+      a.part = h->part_b2;
+      a.sc_w = h->sc;
+      sa::launch_stencil_sl(h->stream, a, h->hw0, true);
+    }
+    StageScope s(h, SA_STAGE_PCG);
+    sa::FusedPcg f = h->fp;
+    f.x = h->xnew;
+    f.status = next_status(h);
+    sa::SlArgs ap{};
+    ap.nrow = nd;
+    ap.n0 = h->Aop.n[0];
+    ap.n1 = h->Aop.n[1];
+    ap.hw1 = h->Aop.hw[1];
+    ap.hw2 = h->Aop.hw[2];
+    ap.A = h->Aop.A;
+    ap.mask = h->free_mask;
+    ap.x = h->p;
+    ap.out = h->q;
+    ap.part = h->part_pq2;
+    ap.sc = h->sc;
+    sa::launch_fd_pass(h->stream, f, 0, true, false);
+    if (h->fd_exact) {
+      for (int k = 0; k < h->pcg_budget; ++k) {
+        sa::launch_stencil_sl(h->stream, ap, h->hw0, false);
+        sa::launch_fd_pass(h->stream, f, k, false, true);
+        sa::launch_pcg_dir(h->stream, f, k);
+      }
+    } else {
+      int k = 0, chunk = 4;
+      for (;;) {
+        for (int c = 0; c < chunk; ++c, ++k) {
+          sa::launch_stencil_sl(h->stream, ap, h->hw0, false);
+          sa::launch_fd_pass(h->stream, f, k, false, true);
+          sa::launch_pcg_dir(h->stream, f, k);
+        }
+        hip_check(hipMemcpyAsync(h->h_sc, h->sc, sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
+                  "status copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const sa::PcgScalars st = *h->h_sc;
+        if (st.done == 1) break;
+        if (st.done == 2) throw sa::SaError{SA_ENOCONV, "PCG breakdown (operator not positive definite)"};
+        if (k >= h->m.opt.pcg_max_iter) throw sa::SaError{SA_ENOCONV, "PCG did not converge within pcg_max_iter"};
+        chunk = std::min(chunk * 2, 32);
+      }
+    }
+  } else {
+    {
+      StageScope s(h, SA_STAGE_RHS);
+      sa::launch_theta_init(h->stream, h->Aop, h->Bval, P.v, h->Fnew, P.F, h->m.opt.theta, h->xnew, h->r,
+                            h->part_b);
+    }
     StageScope s(h, SA_STAGE_PCG);
     PcgSpec m;
-    m.n = h->m.P.ndof;
+    m.n = nd;
     m.stencil = true;
     m.st = h->Aop;
     m.fd = h->m.opt.preconditioner == SA_PRECOND_FD;
@@ -412,10 +511,51 @@ void step_path(sa_iga *h, PathState &P) {
     h->stats.pcg_last_iterations = it;
     h->stats.pcg_last_relres = rr;
   }
+  hip_check(hipGetLastError(), "kernel launch");
   std::swap(P.v, h->xnew);
   std::swap(P.F, h->Fnew);
   P.step = s1;
   h->stats.steps++;
+}
+
+// read back and check the device solve records of the steps run so far
+void check_statuses(sa_iga *h) {
+  if (h->status_used == 0) return;
+  std::vector<sa::SolveStatus> st(h->status_used);
+  hip_check(hipMemcpyAsync(st.data(), h->d_status, st.size() * sizeof(sa::SolveStatus), hipMemcpyDeviceToHost,
+                           h->stream),
+            "status copy");
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+  h->status_used = 0;
+  int bad = -1;
+  for (size_t i = 0; i < st.size(); ++i)
+    if (st[i].done != 1 && bad < 0) bad = (int)i;
+  // records alternate per step: Dirichlet (if any) then theta-step
+  const bool has_dir = h->nD > 0 && h->dir_fused && !h->dir_exact;
+  const bool main_rec = h->pcg_fused;
+  size_t i = 0;
+  while (i < st.size()) {
+    if (has_dir && i < st.size()) h->stats.dirichlet_iterations += st[i++].iter;
+    if (main_rec && i < st.size()) {
+      h->stats.pcg_iterations += st[i].iter;
+      h->stats.pcg_last_iterations = st[i].iter;
+      h->stats.pcg_last_relres = std::sqrt(std::max(st[i].relres2, 0.0));
+      ++i;
+    }
+    if (!has_dir && !main_rec) break;
+  }
+  if (bad >= 0)
+  {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "a solve did not converge within its iteration budget (record %d, done %d, |r|/|b| = %.3e)",
+                  bad, st[bad].done, std::sqrt(std::max(st[bad].relres2, 0.0)));
+    throw sa::SaError{SA_ENOCONV, msg};
+  }
+}
+
+sa::SolveStatus *next_status(sa_iga *h) {
+  if (h->status_used >= h->status_cap) check_statuses(h);
+  return h->d_status + h->status_used++;
 }
 
 std::vector<float> to_float(const std::vector<double> &v) {
@@ -492,6 +632,9 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
       if (m.free_mask[i]) jd[i] = 1.0 / A[(size_t)o0 * nd + i];
     h->A_invdiag = dev_upload(h->owned, jd, h->stream);
     hip_check(hipStreamSynchronize(h->stream), "sync");
+    // an exact FD solve (affine axis-aligned patch) needs no convergence loop
+    h->fd_exact = m.opt.preconditioner == SA_PRECOND_FD &&
+                  sa::fd_inverse_defect(m.fd_main, m.M, A, m.free_mask) < 1e-10;
   }
   upload_fd(h, m.fd_main, h->fd_main);
   if (m.fd_dir_ok) upload_fd(h, m.fd_dir, h->fd_dir);
@@ -610,7 +753,158 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   hip_check(hipMemsetAsync(h->sc, 0, sizeof(sa::PcgScalars), h->stream), "memset");
   hip_check(hipHostMalloc((void **)&h->h_sc, sizeof(sa::PcgScalars), hipHostMallocDefault), "pinned");
   ensure_part(h, 5 * h->stride * 16);
+  hip_check(hipMemsetAsync(h->r, 0, nd * sizeof(double), h->stream), "memset");
+  hip_check(hipMemsetAsync(h->z, 0, nd * sizeof(double), h->stream), "memset");
+  hip_check(hipMemsetAsync(h->p, 0, nd * sizeof(double), h->stream), "memset");
+  hip_check(hipMemsetAsync(h->q, 0, nd * sizeof(double), h->stream), "memset");
+  hip_check(hipMemsetAsync(h->Fnew, 0, nd * sizeof(double), h->stream), "memset");
+  h->lds_per_block = prop.sharedMemPerBlock;
+
+  // load gather over non-empty rows
+  {
+    std::vector<int32_t> rows;
+    std::vector<int64_t> rp(1, 0);
+    std::vector<int32_t> cl;
+    std::vector<double> vl;
+    for (int64_t A = 0; A < nd; ++A) {
+      if (m.load.rowptr[A + 1] == m.load.rowptr[A]) continue;
+      rows.push_back((int32_t)A);
+      for (int64_t e = m.load.rowptr[A]; e < m.load.rowptr[A + 1]; ++e) {
+        cl.push_back(m.load.col[e]);
+        vl.push_back(m.load.val[e]);
+      }
+      rp.push_back((int64_t)cl.size());
+    }
+    h->grows.nrows = (int64_t)rows.size();
+    h->grows.rows = dev_upload(h->owned, rows, h->stream);
+    h->grows.rowptr = dev_upload(h->owned, rp, h->stream);
+    h->grows.col = dev_upload(h->owned, cl, h->stream);
+    h->grows.val = dev_upload(h->owned, vl, h->stream);
+  }
+  // Dirichlet projection in one workgroup
+  h->dir_fused = h->nD > 0 && sa::dirichlet_fits(h->nD) &&
+                 (size_t)5 * h->nD * sizeof(double) + 1024 <= h->lds_per_block;
+  h->sc_dir = dev_alloc<sa::PcgScalars>(h->owned, 1);
+  hip_check(hipMemsetAsync(h->sc_dir, 0, sizeof(sa::PcgScalars), h->stream), "memset");
+  if (h->dir_fused) {
+    std::vector<int32_t> iota(h->nD);
+    for (int64_t j = 0; j < h->nD; ++j) iota[j] = (int32_t)j;
+    h->drows.nrows = h->nD;
+    h->drows.rows = dev_upload(h->owned, iota, h->stream);
+    h->drows.rowptr = h->dproj.rowptr;
+    h->drows.col = h->dproj.col;
+    h->drows.val = h->dproj.val;
+    sa::DirArgs &a = h->dargs;
+    a.nD = (int)h->nD;
+    if (m.opt.preconditioner == SA_PRECOND_FD && m.fd_dir_ok) {
+      // exactness of the Kronecker solve for the trace mass matrix
+      const int64_t nD = h->nD;
+      std::vector<double> y(nD), z(nD), w(nD, 0.0);
+      uint64_t st = 0x2545f4914f6cdd1dull;
+      for (int64_t i = 0; i < nD; ++i) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        y[i] = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+      }
+      sa::fd_apply_host(m.fd_dir, y.data(), z.data(), nD);
+      double num = 0, den = 0;
+      for (int64_t j = 0; j < nD; ++j) {
+        double sum = 0;
+        for (int64_t e = m.mass_dir.rowptr[j]; e < m.mass_dir.rowptr[j + 1]; ++e)
+          sum += m.mass_dir.val[e] * z[m.mass_dir.col[e]];
+        num = std::max(num, std::fabs(sum - y[j]));
+        den = std::max(den, std::fabs(y[j]));
+      }
+      h->dir_exact = den > 0 && num / den < 1e-10;
+    }
+    a.mrow = h->mdir.rowptr;
+    a.mcol = h->mdir.col;
+    a.mval = h->mdir.val;
+    a.fd = (m.opt.preconditioner == SA_PRECOND_FD && m.fd_dir_ok) ? 1 : 0;
+    a.na = m.fd_dir_ok ? m.fd_dir.m[0] : 0;
+    a.nb = m.fd_dir_ok ? m.fd_dir.m[1] : 0;
+    a.Ua = a.fd ? h->fd_dir.op.U[0] : nullptr;
+    a.Ub = a.fd ? h->fd_dir.op.U[1] : nullptr;
+    a.inv = a.fd ? h->fd_dir.op.inv_diag : nullptr;
+    a.jacobi = h->mdir_invdiag;
+    a.dofs = h->dir_dofs;
+    a.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
+    a.max_iter = m.opt.pcg_max_iter;
+    a.u_in_lds = 0;
+    if (a.fd) {
+      a.u_in_lds = 1;
+      if (sa::dirichlet_lds(a) + 1024 > h->lds_per_block) a.u_in_lds = 0;
+    }
+    if (sa::dirichlet_lds(a) + 1024 > h->lds_per_block) h->dir_fused = false;
+    const int dm[3] = {a.na, a.nb, 1};
+    if (h->dir_exact && !sa::fused_fits(dm)) h->dir_exact = false;
+    if (h->dir_exact) {
+      sa::FusedPcg &f = h->fd_dirp;
+      f = sa::FusedPcg{};
+      for (int d = 0; d < 3; ++d) {
+        f.n[d] = dm[d];
+        f.lo[d] = 0;
+        f.m[d] = dm[d];
+      }
+      f.U0 = h->fd_dir.op.U[0];
+      f.U1 = h->fd_dir.op.U[1];
+      f.U2 = h->fd_dir.op.U[2];
+      f.inv = h->fd_dir.op.inv_diag;
+      f.r = h->bD;
+      f.p = h->pD;
+      f.t = h->fd_dir.op.t1;
+      f.sc = h->sc_dir;
+      f.scatter_idx = h->dir_dofs;
+    }
+  }
+  // fused PCG on the box of free DOFs
+  h->hw0 = m.M.hw[0];
+  const auto &FM = m.fd_main;
+  const size_t slab_lds = (size_t)2 * FM.m[1] * FM.m[2] * sizeof(double);
+  h->pcg_fused = m.opt.preconditioner == SA_PRECOND_FD && sa::fused_fits(FM.m) &&
+                 slab_lds + 1024 <= h->lds_per_block && m.M.hw[2] <= 7 && m.M.hw[0] <= 6;
+  if (h->pcg_fused) {
+    sa::FusedPcg &f = h->fp;
+    for (int d = 0; d < 3; ++d) {
+      f.n[d] = FM.n[d];
+      f.lo[d] = FM.lo[d];
+      f.m[d] = FM.m[d];
+    }
+    f.U0 = h->fd_main.op.U[0];
+    f.U1 = h->fd_main.op.U[1];
+    f.U2 = h->fd_main.op.U[2];
+    f.inv = h->fd_main.op.inv_diag;
+    f.r = h->r;
+    f.z = h->z;
+    f.p = h->p;
+    f.q = h->q;
+    const int64_t nbox = (int64_t)FM.m[0] * FM.m[1] * FM.m[2];
+    h->t_box = dev_alloc<double>(h->owned, nbox);
+    f.t = h->t_box;
+    f.np_rz = FM.m[1] * FM.m[2];
+    h->part_rz2 = dev_alloc<double>(h->owned, 2 * f.np_rz);
+    h->part_rrs = dev_alloc<double>(h->owned, f.np_rz);
+    f.part_rz = h->part_rz2;
+    f.part_rr = h->part_rrs;
+    const int nbk = sa::stencil_blocks(nd);
+    h->part_pq2 = dev_alloc<double>(h->owned, nbk);
+    h->part_b2 = dev_alloc<double>(h->owned, nbk);
+    f.part_pq = h->part_pq2;
+    f.np_pq = nbk;
+    f.part_b = h->part_b2;
+    f.np_b = nbk;
+    f.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
+    f.sc = h->sc;
+  }
+  h->status_cap = 8192;
+  h->d_status = dev_alloc<sa::SolveStatus>(h->owned, h->status_cap);
+  hip_check(hipMemsetAsync(h->d_status, 0, h->status_cap * sizeof(sa::SolveStatus), h->stream), "memset");
   hip_check(hipStreamSynchronize(h->stream), "sync");
+  if (std::getenv("SA_IGA_VERBOSE"))
+    std::fprintf(stderr,
+                 "[sa_iga] ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: fused %d exact %d | "
+                 "theta-step: fused %d fd-exact %d budget %d\n",
+                 (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_fused,
+                 (int)h->dir_exact, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget);
 }
 
 // parametric query points -> device CSR rows of basis values (and gradients)
@@ -765,11 +1059,13 @@ int sa_iga_step(sa_iga *h, int32_t n_steps) {
       for (int32_t s = 0; s < n_steps; ++s)
         for (auto &P : h->paths)
           if (P.step < P.n_steps) step_path(h, P);
+      check_statuses(h);
       hip_check(hipStreamSynchronize(h->stream), "sync");
       collect_timing(h);
     } catch (const sa::SaError &e) {
       if (e.code == SA_ENOCONV) h->sticky = 1;
       (void)hipStreamSynchronize(h->stream);
+      h->status_used = 0;
       collect_timing(h);
       throw;
     }

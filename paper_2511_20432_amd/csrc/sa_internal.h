@@ -122,5 +122,8 @@ void load_patch(const sa_patch *patch, PatchData &P);
 void assemble_volume(Model &m);
 void build_boundary(Model &m);
 void build_fd(Model &m);
+void fd_apply_host(const FdData &F, const double *r, double *z, int64_t n_full);
+double fd_inverse_defect(const FdData &F, const Stencil &S, const std::vector<double> &Sval,
+                         const std::vector<uint8_t> &free_mask);
 
 }  // namespace sa

@@ -1,0 +1,498 @@
+// Fused solver kernels for the theta-scheme (Eq. 20) and the Dirichlet
+// projection (Eq. 11) on gfx950.
+//
+//  * k_gather_rows   load vector F (lane-parallel rows) + copy of v into x
+//  * k_dirichlet     one workgroup: projection rhs gather, then the whole
+//                    PCG for the trace mass matrix with the 2-D fast-
+//                    diagonalisation preconditioner held in LDS; writes the
+//                    Dirichlet values and scatters them into x
+//  * k_stencil_sl    banded stencil product, 64 rows per block and one wave
+//                    per z-offset slice (theta rhs/residual or A p with p.Ap)
+//  * k_fd_xfwd       (optional PCG update) + mode 0 of the FD solve, one
+//                    x-fiber of the free box per block
+//  * k_fd_plane      modes 1 and 2 and the eigenvalue scaling, one (y, z)
+//                    plane per block, in LDS
+//  * k_fd_xbwd       mode 0 back to z (+ p = z on the first pass)
+//  * k_pcg_dir       convergence test and p = z + beta p
+// The scalar recurrences are recomputed in every block from fixed-order
+// partial sums, so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+#include "solver.h"
+
+namespace sa {
+
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// block sum for any block size <= 1024; all threads get the result
+__device__ __forceinline__ double bsum(double v, double *sh) {
+  v = wsum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (int)(blockDim.x >> 6);
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double reduce_n(const double *part, int n, double *sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  return bsum(s, sh);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// load vector: 16 lanes per non-empty row
+// ---------------------------------------------------------------------------
+__global__ void k_gather_rows(int64_t nrows, const int32_t *__restrict__ rows,
+                              const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                              const double *__restrict__ val, const double *__restrict__ ld,
+                              double *__restrict__ F, int64_t ncopy, const double *__restrict__ v,
+                              double *__restrict__ x) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & 15;
+  const int64_t r = gt >> 4;
+  double s = 0.0;
+  if (r < nrows) {
+    for (int64_t e = rowptr[r] + sub; e < rowptr[r + 1]; e += 16) s = fma(val[e], ld[col[e]], s);
+  }
+  for (int off = 8; off > 0; off >>= 1) s += __shfl_down(s, off, 16);
+  if (r < nrows && sub == 0) F[rows[r]] = s;
+  for (int64_t i = gt; i < ncopy; i += (int64_t)gridDim.x * blockDim.x) x[i] = v[i];
+}
+
+void launch_gather_rows(hipStream_t st, const GatherRows &g, const double *ld, double *F, int64_t ncopy,
+                        const double *v, double *x) {
+  int64_t threads = g.nrows * 16;
+  int64_t blocks = (threads + kB - 1) / kB;
+  int64_t cb = (ncopy + kB - 1) / kB;
+  if (cb > blocks) blocks = cb;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks), dim3(kB), 0, st, g.nrows, g.rows, g.rowptr, g.col,
+                     g.val, ld, F, ncopy, v, x);
+}
+
+// ---------------------------------------------------------------------------
+// Dirichlet projection in one workgroup
+// ---------------------------------------------------------------------------
+constexpr int kDirThreads = 1024;
+
+// z = P^{-1} r for the 2-D Kronecker preconditioner (or Jacobi), in LDS
+__device__ void dir_precond(const DirArgs &a, const double *Ua, const double *Ub, const double *r, double *z,
+                            double *t1, double *t2) {
+  const int n = a.nD;
+  if (!a.fd) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) z[j] = a.jacobi[j] * r[j];
+    __syncthreads();
+    return;
+  }
+  const int na = a.na, nb = a.nb;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {       // t1 = Ua^T along a
+    const int ja = t % na, kb = t / na;
+    double s = 0.0;
+    for (int k = 0; k < na; ++k) s = fma(Ua[k * na + ja], r[k + na * kb], s);
+    t1[t] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {       // t2 = D^{-1} Ub^T along b
+    const int ja = t % na, jb = t / na;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s = fma(Ub[k * nb + jb], t1[ja + na * k], s);
+    t2[t] = s * a.inv[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {       // t1 = Ub along b
+    const int ja = t % na, kb = t / na;
+    double s = 0.0;
+    for (int j = 0; j < nb; ++j) s = fma(Ub[kb * nb + j], t2[ja + na * j], s);
+    t1[t] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {       // z = Ua along a
+    const int ka = t % na, kb = t / na;
+    double s = 0.0;
+    for (int j = 0; j < na; ++j) s = fma(Ua[ka * na + j], t1[j + na * kb], s);
+    z[t] = s;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kDirThreads) void k_dirichlet(DirArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double sh[16];
+  const int n = a.nD;
+  double *r = lds, *z = lds + n, *p = lds + 2 * n, *t1 = lds + 3 * n, *t2 = lds + 4 * n;
+  // the preconditioner's eigenvector matrices live in LDS when they fit
+  const double *Ua = a.Ua, *Ub = a.Ub;
+  if (a.fd && a.u_in_lds) {
+    double *ua = lds + 5 * n, *ub = ua + a.na * a.na;
+    for (int i = threadIdx.x; i < a.na * a.na; i += blockDim.x) ua[i] = a.Ua[i];
+    for (int i = threadIdx.x; i < a.nb * a.nb; i += blockDim.x) ub[i] = a.Ub[i];
+    Ua = ua;
+    Ub = ub;
+  }
+  double *x = a.vD;
+  // r = b - M x (warm start from the previous values)
+  double bb = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double b = a.b[j];
+    double mx = 0.0;
+#pragma unroll 4
+    for (int64_t e = a.mrow[j]; e < a.mrow[j + 1]; ++e) mx = fma(a.mval[e], x[a.mcol[e]], mx);
+    r[j] = b - mx;
+    bb = fma(b, b, bb);
+  }
+  bb = bsum(bb, sh);
+  dir_precond(a, Ua, Ub, r, z, t1, t2);
+  double rz = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    p[j] = z[j];
+    rz = fma(r[j], z[j], rz);
+  }
+  rz = bsum(rz, sh);
+  int it = 0, done = (rz == 0.0) ? 1 : 0;
+  double rr = 0.0;
+  constexpr int kMaxPer = 4;  // rows per thread (n <= kDirThreads * kMaxPer)
+  while (!done && it < a.max_iter) {
+    double q[kMaxPer];
+    double pq = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+      const int j = threadIdx.x + k * blockDim.x;
+      q[k] = 0.0;
+      if (j < n) {
+        double s = 0.0;
+#pragma unroll 4
+        for (int64_t e = a.mrow[j]; e < a.mrow[j + 1]; ++e) s = fma(a.mval[e], p[a.mcol[e]], s);
+        q[k] = s;
+        pq = fma(p[j], s, pq);
+      }
+    }
+    pq = bsum(pq, sh);
+    if (!(pq > 0.0)) { done = 2; break; }
+    const double alpha = rz / pq;
+    rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+      const int j = threadIdx.x + k * blockDim.x;
+      if (j < n) {
+        x[j] = fma(alpha, p[j], x[j]);
+        const double rj = fma(-alpha, q[k], r[j]);
+        r[j] = rj;
+        rr = fma(rj, rj, rr);
+      }
+    }
+    rr = bsum(rr, sh);
+    ++it;
+    if (rr <= a.rtol2 * bb) { done = 1; break; }
+    dir_precond(a, Ua, Ub, r, z, t1, t2);
+    double rzn = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) rzn = fma(r[j], z[j], rzn);
+    rzn = bsum(rzn, sh);
+    const double beta = rzn / rz;
+    rz = rzn;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) p[j] = fma(beta, p[j], z[j]);
+    __syncthreads();
+  }
+  // scatter the values into the theta-step iterate
+  for (int j = threadIdx.x; j < n; j += blockDim.x) a.xfull[a.dofs[j]] = x[j];
+  if (threadIdx.x == 0 && a.status) {
+    a.status->iter = it;
+    a.status->done = done;
+    a.status->relres2 = bb > 0 ? rr / bb : 0.0;
+  }
+}
+
+bool dirichlet_fits(int64_t nD) { return nD > 0 && nD <= 4 * kDirThreads; }
+
+size_t dirichlet_lds(const DirArgs &a) {
+  size_t n = (size_t)5 * a.nD;
+  if (a.fd && a.u_in_lds) n += (size_t)a.na * a.na + (size_t)a.nb * a.nb;
+  return n * sizeof(double);
+}
+
+void launch_dirichlet(hipStream_t st, const DirArgs &a) {
+  hipLaunchKernelGGL(k_dirichlet, dim3(1), dim3(kDirThreads), dirichlet_lds(a), st, a);
+}
+
+// ---------------------------------------------------------------------------
+// banded stencil products: 64 rows per block, one wave per z-offset
+// ---------------------------------------------------------------------------
+template <int HW0, bool THETA>
+__global__ void k_stencil_sl(SlArgs a) {
+  extern __shared__ double shr[];          // [waves][64]
+  __shared__ double sh[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = (int)(blockDim.x >> 6);
+  if (!THETA && a.sc && a.sc->done) return;
+  const int64_t row = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t nrow = a.nrow, nm1 = nrow - 1;
+  const int n0 = a.n0;
+  const int64_t n01 = (int64_t)a.n0 * a.n1;
+  const int hw1 = a.hw1;
+  const int d2 = w - a.hw2;
+  double acc = 0.0, accb = 0.0;
+  const bool active = row < nrow && (!a.mask || a.mask[row]);
+  if (active) {
+    const int span0 = 2 * HW0 + 1;
+    int o = ((w) * (2 * hw1 + 1)) * span0;
+    for (int d1 = -hw1; d1 <= hw1; ++d1) {
+      const int64_t base = row + (int64_t)d1 * n0 + (int64_t)d2 * n01;
+#pragma unroll
+      for (int d0 = -HW0; d0 <= HW0; ++d0) {
+        int64_t nb = base + d0;
+        nb = nb < 0 ? 0 : (nb > nm1 ? nm1 : nb);
+        const int64_t oi = (int64_t)(o + d0 + HW0) * nrow + row;
+        acc = fma(a.A[oi], a.x[nb], acc);
+        if (THETA) accb = fma(a.B[oi], a.v[nb], accb);
+      }
+      o += span0;
+    }
+  }
+  shr[w * 64 + lane] = acc;
+  if (THETA) shr[(nw + w) * 64 + lane] = accb;
+  __syncthreads();
+  double part = 0.0;
+  if (w == 0) {
+    double s = 0.0, sb = 0.0;
+    for (int k = 0; k < nw; ++k) {
+      s += shr[k * 64 + lane];
+      if (THETA) sb += shr[(nw + k) * 64 + lane];
+    }
+    if (row < nrow) {
+      if (THETA) {
+        double rv = 0.0;
+        if (active) {
+          const double rhs = sb + a.theta * a.F1[row] + (1.0 - a.theta) * a.F0[row];
+          part = rhs * rhs;
+          rv = rhs - s;
+        }
+        a.out[row] = rv;
+      } else {
+        a.out[row] = active ? s : 0.0;
+        part = active ? a.x[row] * s : 0.0;
+      }
+    }
+  }
+  part = bsum(part, sh);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = part;
+  if (THETA && blockIdx.x == 0 && threadIdx.x == 0 && a.sc_w) a.sc_w->done = 0;
+}
+
+int stencil_blocks(int64_t nrow) { return (int)((nrow + 63) / 64); }
+
+void launch_stencil_sl(hipStream_t st, const SlArgs &a, int hw0, bool theta) {
+  const int waves = 2 * a.hw2 + 1;
+  dim3 g((unsigned)stencil_blocks(a.nrow)), b(64 * waves);
+  const size_t lds = (size_t)(theta ? 2 : 1) * waves * 64 * sizeof(double);
+#define SA_SL_CASE(H)                                                                             \
+  case H:                                                                                         \
+    if (theta) hipLaunchKernelGGL((k_stencil_sl<H, true>), g, b, lds, st, a);                     \
+    else hipLaunchKernelGGL((k_stencil_sl<H, false>), g, b, lds, st, a);                          \
+    break;
+  switch (hw0) {
+    SA_SL_CASE(1)
+    SA_SL_CASE(2)
+    SA_SL_CASE(3)
+    SA_SL_CASE(4)
+    SA_SL_CASE(5)
+    default: SA_SL_CASE(6)
+  }
+#undef SA_SL_CASE
+}
+
+// ---------------------------------------------------------------------------
+// fast-diagonalisation solve on the box of free DOFs, fused with the PCG update
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t full_index(const FusedPcg &f, int j0, int j1, int j2) {
+  return (int64_t)(j0 + f.lo[0]) + (int64_t)f.n[0] * ((j1 + f.lo[1]) + (int64_t)f.n[1] * (j2 + f.lo[2]));
+}
+
+// The FD solve on the box of free DOFs, in three launches:
+//   k_fd_xfwd   block = x-fiber (k1, k2): optional PCG update of its rows,
+//               t[:, k1, k2] = U0^T r[:, k1, k2]
+//   k_fd_plane  block = plane j0: modes 1 and 2, eigenvalue scaling, back
+//   k_fd_xbwd   block = x-fiber: z = U0 t, partial r.z, p = z on the first pass
+// t is stored plane-major: t[j0 * (m1 m2) + k2 * m1 + k1].
+constexpr int kFib = 64;
+
+__global__ __launch_bounds__(kFib) void k_fd_xfwd(FusedPcg f, int k, int first) {
+  __shared__ double fib[256];
+  __shared__ double sh[16];
+  if (f.sc->done) return;
+  const int m0 = f.m[0], m1 = f.m[1];
+  const int64_t P = (int64_t)m1 * f.m[2];
+  const int b = blockIdx.x;
+  const int k1 = b % m1, k2 = b / m1;
+  const int64_t base = full_index(f, 0, k1, k2);
+  if (!first) {
+    const double rz = reduce_n(f.part_rz + (k & 1) * f.np_rz, f.np_rz, sh);
+    const double pq = reduce_n(f.part_pq, f.np_pq, sh);
+    if (rz == 0.0 || !(pq > 0.0)) {
+      // zero residual (nothing to solve) or breakdown: record the exit here
+      if (b == 0 && threadIdx.x == 0) {
+        const int d = (rz == 0.0) ? 1 : 2;
+        f.sc->done = d;
+        if (f.status) {
+          f.status->iter = k;
+          f.status->done = d;
+          f.status->relres2 = 0.0;
+        }
+      }
+      return;
+    }
+    const double alpha = rz / pq;
+    double rr = 0.0;
+    for (int i = threadIdx.x; i < m0; i += blockDim.x) {
+      const int64_t g = base + i;
+      f.x[g] = fma(alpha, f.p[g], f.x[g]);
+      const double ri = fma(-alpha, f.q[g], f.r[g]);
+      f.r[g] = ri;
+      fib[i] = ri;
+      rr = fma(ri, ri, rr);
+    }
+    rr = bsum(rr, sh);
+    if (threadIdx.x == 0) f.part_rr[b] = rr;
+  } else {
+    for (int i = threadIdx.x; i < m0; i += blockDim.x) fib[i] = f.r[base + i];
+    __syncthreads();
+  }
+  for (int j0 = threadIdx.x; j0 < m0; j0 += blockDim.x) {
+    double s = 0.0;
+    for (int kk = 0; kk < m0; ++kk) s = fma(f.U0[kk * m0 + j0], fib[kk], s);
+    f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1] = s;
+  }
+}
+
+__global__ void k_fd_plane(FusedPcg f) {
+  extern __shared__ double lds[];
+  if (f.sc->done) return;
+  const int m0 = f.m[0], m1 = f.m[1], m2 = f.m[2];
+  const int P = m1 * m2;
+  const int j0 = blockIdx.x;
+  double *A = lds, *Bv = lds + P;
+  double *t = f.t + (int64_t)j0 * P;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) A[i] = t[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 1: U1^T along y
+    const int j1 = i % m1, k2 = i / m1;
+    double s = 0.0;
+    for (int kk = 0; kk < m1; ++kk) s = fma(f.U1[kk * m1 + j1], A[k2 * m1 + kk], s);
+    Bv[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 2: U2^T along z, scale
+    const int j1 = i % m1, j2 = i / m1;
+    double s = 0.0;
+    for (int kk = 0; kk < m2; ++kk) s = fma(f.U2[kk * m2 + j2], Bv[kk * m1 + j1], s);
+    A[i] = s * f.inv[j0 + (int64_t)m0 * (j1 + (int64_t)m1 * j2)];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 2 back
+    const int j1 = i % m1, k2 = i / m1;
+    double s = 0.0;
+    for (int j = 0; j < m2; ++j) s = fma(f.U2[k2 * m2 + j], A[j * m1 + j1], s);
+    Bv[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 1 back
+    const int k1 = i % m1, k2 = i / m1;
+    double s = 0.0;
+    for (int j = 0; j < m1; ++j) s = fma(f.U1[k1 * m1 + j], Bv[k2 * m1 + j], s);
+    t[i] = s;
+  }
+}
+
+__global__ __launch_bounds__(kFib) void k_fd_xbwd(FusedPcg f, int slot, int first) {
+  __shared__ double fib[256];
+  __shared__ double sh[16];
+  if (f.sc->done) return;
+  const int m0 = f.m[0], m1 = f.m[1];
+  const int64_t P = (int64_t)m1 * f.m[2];
+  const int b = blockIdx.x;
+  const int k1 = b % m1, k2 = b / m1;
+  const int64_t base = full_index(f, 0, k1, k2);
+  for (int j = threadIdx.x; j < m0; j += blockDim.x) fib[j] = f.t[(int64_t)j * P + (int64_t)k2 * m1 + k1];
+  __syncthreads();
+  double rz = 0.0;
+  for (int k0 = threadIdx.x; k0 < m0; k0 += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < m0; ++j) s = fma(f.U0[k0 * m0 + j], fib[j], s);
+    const int64_t g = base + k0;
+    f.z[g] = s;
+    if (first) f.p[g] = s;
+    if (f.scatter_out) f.scatter_out[f.scatter_idx[g]] = s;
+    rz = fma(f.r[g], s, rz);
+  }
+  if (!f.part_rz) return;
+  rz = bsum(rz, sh);
+  if (threadIdx.x == 0) f.part_rz[slot * f.np_rz + b] = rz;
+}
+
+// convergence test on r.r; p = z + beta p on the box
+__global__ void k_pcg_dir(FusedPcg f, int k) {
+  __shared__ double sh[16];
+  if (f.sc->done) return;
+  const double rr = reduce_n(f.part_rr, f.np_rz, sh);
+  const double bb = reduce_n(f.part_b, f.np_b, sh);
+  const double rz_old = reduce_n(f.part_rz + (k & 1) * f.np_rz, f.np_rz, sh);
+  const double rz_new = reduce_n(f.part_rz + ((k + 1) & 1) * f.np_rz, f.np_rz, sh);
+  // |b| below 1e-140 lies at the FP64 underflow edge: relative accuracy is
+  // not attainable there and the solution is zero to that precision
+  const bool conv = rr <= f.rtol2 * bb || bb <= 1e-280;
+  if (!conv) {
+    const double beta = rz_new / rz_old;
+    const int m0 = f.m[0], m1 = f.m[1];
+    const int64_t nbox = (int64_t)m0 * m1 * f.m[2];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nbox; t += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t i = full_index(f, (int)(t % m0), (int)((t / m0) % m1), (int)(t / ((int64_t)m0 * m1)));
+      f.p[i] = fma(beta, f.p[i], f.z[i]);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    f.sc->iter = k + 1;
+    f.sc->rr = rr;
+    f.sc->bnorm2 = bb;
+    if (conv) f.sc->done = 1;
+    if (f.status) {
+      f.status->iter = k + 1;
+      f.status->done = conv ? 1 : 0;
+      f.status->relres2 = bb > 0 ? rr / bb : 0.0;
+    }
+  }
+}
+
+bool fused_fits(const int m[3]) { return m[0] <= 256 && (int64_t)m[1] * m[2] <= 4096; }
+
+void launch_fd_pass(hipStream_t st, const FusedPcg &f, int k, bool first, bool update) {
+  const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
+  hipLaunchKernelGGL(k_fd_xfwd, dim3(nfib), dim3(kFib), 0, st, f, k, update ? 0 : 1);
+  const size_t lds = (size_t)2 * f.m[1] * f.m[2] * sizeof(double);
+  hipLaunchKernelGGL(k_fd_plane, dim3(f.m[0]), dim3(kB), lds, st, f);
+  const int slot = first ? 0 : ((k + 1) & 1);
+  hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib), dim3(kFib), 0, st, f, slot, first ? 1 : 0);
+}
+
+void launch_pcg_dir(hipStream_t st, const FusedPcg &f, int k) {
+  const int64_t nbox = (int64_t)f.m[0] * f.m[1] * f.m[2];
+  int64_t blocks = (nbox + kB - 1) / kB;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)blocks), dim3(kB), 0, st, f, k);
+}
+
+}  // namespace sa
