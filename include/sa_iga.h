@@ -229,7 +229,10 @@ int sa_iga_reset_stats(sa_iga *h);
  * Checkpoint of the mutable state (steps, u^n, F^n of every path).  With
  * buf == NULL, *len receives the size needed.  sa_iga_load restores a
  * checkpoint taken from an object built from the same inputs (SA_EINVAL if
- * the sizes differ) and clears the sticky error state.
+ * the sizes differ) and clears the sticky error state.  It recomputes T~
+ * and grad T~ at the boundary points of every path at its restored step, so
+ * sa_iga_get_boundary_fields afterwards returns what it returned when the
+ * checkpoint was taken.  Neither call changes the statistics.
  */
 int sa_iga_save(sa_iga *h, void *buf, size_t *len);
 int sa_iga_load(sa_iga *h, const void *buf, size_t len);

@@ -15,6 +15,19 @@ namespace sa {
 // grad T~_i(x) = exp(arg_i) (2 c_i x + u_i).
 constexpr int kCoefStride = 8;
 
+// Paths advanced by one launch (by value in the kernel arguments).  Slot s
+// holds path `path[s]`, whose sources start at row src0[s] of the global
+// source arrays; its first n_act[s] sources are switched on and the first
+// n_far[s] of those are summed in FP32.
+constexpr int kMaxBatch = 64;
+struct PathTab {
+  int count;
+  int32_t path[kMaxBatch];
+  int64_t src0[kMaxBatch];
+  int32_t n_act[kMaxBatch];
+  int32_t n_far[kMaxBatch];
+};
+
 struct CoeffParams {
   int64_t now;            // (n+1) * sources_per_step
   double delta;           // dt / sources_per_step
@@ -24,29 +37,34 @@ struct CoeffParams {
   double scale;           // kernel scale s
 };
 
-void launch_coeff(hipStream_t st, int64_t n_act, int64_t n_far32, const int64_t *tick, const double *sx,
+// coefficient records of the switched-on sources of every slot (written at
+// the sources' global rows); max_act = max over slots of n_act
+void launch_coeff(hipStream_t st, const PathTab &tab, int64_t max_act, const int64_t *tick, const double *sx,
                   const double *sy, const double *sz, const double *E, const CoeffParams &cp,
                   double *c64, float *c32);
 
 struct SumPlan {
   int points_per_lane;    // 1, 2 or 4
   int waves;              // waves per workgroup
-  int n_chunks_far, chunk_far;     // FP32 chunks over [0, n_far)
+  int n_chunks_far, chunk_far;     // FP32 chunks over [0, n_far) of each path
   int n_chunks_near, chunk_near;   // FP64 chunks over [n_far, n_act)
-  int64_t n_far, n_act;
   int64_t nq, part_stride;
 };
 
-void launch_sum(hipStream_t st, const SumPlan &pl, const double *px, const double *py, const double *pz,
-                const double *pq2, const float *fx, const float *fy, const float *fz, const float *fq2,
-                const double *c64, const float *c32, double *part);
+// partials part[(slot * n_chunks + chunk) * 5 + k][part_stride]; chunks past a
+// path's own range write zeros
+void launch_sum(hipStream_t st, const SumPlan &pl, const PathTab &tab, const double *px, const double *py,
+                const double *pz, const double *pq2, const float *fx, const float *fy, const float *fz,
+                const float *fq2, const double *c64, const float *c32, double *part);
 
 // reduce chunk partials; T, grad; per-point load density:
 //   NEUMANN: -k (grad . n) w dS,  DIRICHLET: -T~ w dS,  else 0
-void launch_finalize(hipStream_t st, int64_t nq, int n_chunks, int64_t part_stride, const double *part,
-                     const double *px, const double *py, const double *pz, const double *nx,
-                     const double *ny, const double *nz, const double *wdS, const int8_t *role,
-                     double kcond, double *T, double *gx, double *gy, double *gz, double *ld);
+// outputs of slot s go to index o = (by_slot ? s : path[s]): T + o*ostride,
+// grad + o*3*ostride (component-major), ld + o*ostride
+void launch_finalize(hipStream_t st, const PathTab &tab, bool by_slot, int64_t nq, int n_chunks,
+                     int64_t part_stride, const double *part, const double *px, const double *py,
+                     const double *pz, const double *nx, const double *ny, const double *nz, const double *wdS,
+                     const int8_t *role, double kcond, int64_t ostride, double *T, double *g, double *ld);
 
 // out[r] = sum_e val[e] * in[col[e]] over rows [0, nrow) of a CSR
 void launch_gather(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,

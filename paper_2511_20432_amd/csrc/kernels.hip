@@ -97,12 +97,14 @@ __device__ __forceinline__ double reduce_parts(const double *part, int n) {
 // ---------------------------------------------------------------------------
 // source coefficients
 // ---------------------------------------------------------------------------
-__global__ void k_coeff(int64_t n_act, int64_t n_far32, const int64_t *__restrict__ tick,
-                        const double *__restrict__ sx, const double *__restrict__ sy,
-                        const double *__restrict__ sz, const double *__restrict__ E, CoeffParams cp,
-                        double *__restrict__ c64, float *__restrict__ c32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_act) return;
+__global__ void k_coeff(PathTab tab, const int64_t *__restrict__ tick, const double *__restrict__ sx,
+                        const double *__restrict__ sy, const double *__restrict__ sz,
+                        const double *__restrict__ E, CoeffParams cp, double *__restrict__ c64,
+                        float *__restrict__ c32) {
+  const int slot = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= tab.n_act[slot]) return;
+  const int64_t i = tab.src0[slot] + j;
   const double D = (double)(cp.now - tick[i]) * cp.delta + cp.shift;
   const double c = -1.0 / (4.0 * cp.alpha * D);
   const double x = sx[i], y = sy[i], z = sz[i];
@@ -117,7 +119,7 @@ __global__ void k_coeff(int64_t n_act, int64_t n_far32, const int64_t *__restric
   o[5] = 0.0;
   o[6] = 0.0;
   o[7] = 0.0;
-  if (i < n_far32) {
+  if (j < tab.n_far[slot]) {
     const double l2e = 1.4426950408889634;
     float *f = c32 + i * kCoefStride;
     f[0] = (float)(c * l2e);
@@ -131,12 +133,12 @@ __global__ void k_coeff(int64_t n_act, int64_t n_far32, const int64_t *__restric
   }
 }
 
-void launch_coeff(hipStream_t st, int64_t n_act, int64_t n_far32, const int64_t *tick, const double *sx,
+void launch_coeff(hipStream_t st, const PathTab &tab, int64_t max_act, const int64_t *tick, const double *sx,
                   const double *sy, const double *sz, const double *E, const CoeffParams &cp,
                   double *c64, float *c32) {
-  if (n_act <= 0) return;
-  dim3 g((unsigned)((n_act + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL(k_coeff, g, dim3(kBlock), 0, st, n_act, n_far32, tick, sx, sy, sz, E, cp, c64, c32);
+  if (max_act <= 0 || tab.count <= 0) return;
+  dim3 g((unsigned)((max_act + kBlock - 1) / kBlock), (unsigned)tab.count);
+  hipLaunchKernelGGL(k_coeff, g, dim3(kBlock), 0, st, tab, tick, sx, sy, sz, E, cp, c64, c32);
 }
 
 // ---------------------------------------------------------------------------
@@ -149,18 +151,21 @@ struct SumArgs {
   const float *c32;
   double *part;
   int64_t nq, stride;
-  int64_t n_far, n_act;
-  int n_chunks_far, chunk_far, chunk_near;
+  int n_chunks_far, n_chunks, chunk_far, chunk_near;
 };
 
 constexpr int kTile32 = 128;   // FP32 sources summed before folding into FP64
 
 template <int P>
-__global__ __launch_bounds__(512) void k_sum(SumArgs a) {
+__global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (64 * P) + lane;
   const int chunk = blockIdx.y;
+  const int slot = blockIdx.z;
+  const int n_far = tab.n_far[slot], n_act = tab.n_act[slot];
+  const double *c64 = a.c64 + tab.src0[slot] * kCoefStride;
+  const float *c32 = a.c32 + tab.src0[slot] * kCoefStride;
   double x[P], y[P], z[P], q2[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -176,8 +181,8 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a) {
   for (int j = 0; j < P; ++j) s0[j] = s1[j] = sx[j] = sy[j] = sz[j] = 0.0;
 
   if (chunk < a.n_chunks_far) {
-    const int64_t lo = (int64_t)chunk * a.chunk_far;
-    const int64_t hi = lo + a.chunk_far < a.n_far ? lo + a.chunk_far : a.n_far;
+    const int lo = chunk * a.chunk_far;
+    const int hi = lo + a.chunk_far < n_far ? lo + a.chunk_far : n_far;
     float xf[P], yf[P], zf[P], qf[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -189,13 +194,13 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a) {
       qf[j] = a.fq2[q];
     }
     const double ln2 = 0.6931471805599453;
-    for (int64_t t0 = lo; t0 < hi; t0 += kTile32) {
-      const int64_t t1 = t0 + kTile32 < hi ? t0 + kTile32 : hi;
+    for (int t0 = lo; t0 < hi; t0 += kTile32) {
+      const int t1 = t0 + kTile32 < hi ? t0 + kTile32 : hi;
       float f0[P], f1[P], fx_[P], fy_[P], fz_[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) f0[j] = f1[j] = fx_[j] = fy_[j] = fz_[j] = 0.0f;
-      for (int64_t i = t0; i < t1; ++i) {
-        const float *c = a.c32 + i * kCoefStride;
+      for (int i = t0; i < t1; ++i) {
+        const float *c = c32 + (int64_t)i * kCoefStride;
         const float cc = c[0], ux = c[1], uy = c[2], uz = c[3], K = c[4];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -222,10 +227,10 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a) {
     }
   } else {
     const int c = chunk - a.n_chunks_far;
-    const int64_t lo = a.n_far + (int64_t)c * a.chunk_near;
-    const int64_t hi = lo + a.chunk_near < a.n_act ? lo + a.chunk_near : a.n_act;
-    for (int64_t i = lo; i < hi; ++i) {
-      const double *cr = a.c64 + i * kCoefStride;
+    const int lo = n_far + c * a.chunk_near;
+    const int hi = lo + a.chunk_near < n_act ? lo + a.chunk_near : n_act;
+    for (int i = lo; i < hi; ++i) {
+      const double *cr = c64 + (int64_t)i * kCoefStride;
       const double cc = cr[0], ux = cr[1], uy = cr[2], uz = cr[3], K = cr[4];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -242,7 +247,7 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a) {
       }
     }
   }
-  double *o = a.part + (int64_t)chunk * 5 * a.stride;
+  double *o = a.part + ((int64_t)slot * a.n_chunks + chunk) * 5 * a.stride;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t q = base + 64 * j;
@@ -256,35 +261,38 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a) {
   }
 }
 
-void launch_sum(hipStream_t st, const SumPlan &pl, const double *px, const double *py, const double *pz,
-                const double *pq2, const float *fx, const float *fy, const float *fz, const float *fq2,
-                const double *c64, const float *c32, double *part) {
+void launch_sum(hipStream_t st, const SumPlan &pl, const PathTab &tab, const double *px, const double *py,
+                const double *pz, const double *pq2, const float *fx, const float *fy, const float *fz,
+                const float *fq2, const double *c64, const float *c32, double *part) {
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
-  if (nch <= 0 || pl.nq <= 0) return;
+  if (nch <= 0 || pl.nq <= 0 || tab.count <= 0) return;
   SumArgs a{px, py, pz, pq2, fx, fy, fz, fq2, c64, c32, part, pl.nq, pl.part_stride,
-            pl.n_far, pl.n_act, pl.n_chunks_far, pl.chunk_far, pl.chunk_near};
+            pl.n_chunks_far, nch, pl.chunk_far, pl.chunk_near};
   const int64_t per_block = (int64_t)64 * pl.points_per_lane * pl.waves;
-  dim3 g((unsigned)((pl.nq + per_block - 1) / per_block), (unsigned)nch);
+  dim3 g((unsigned)((pl.nq + per_block - 1) / per_block), (unsigned)nch, (unsigned)tab.count);
   dim3 b(64 * pl.waves);
   switch (pl.points_per_lane) {
-    case 1: hipLaunchKernelGGL(k_sum<1>, g, b, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_sum<2>, g, b, 0, st, a); break;
-    default: hipLaunchKernelGGL(k_sum<4>, g, b, 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_sum<1>, g, b, 0, st, a, tab); break;
+    case 2: hipLaunchKernelGGL(k_sum<2>, g, b, 0, st, a, tab); break;
+    default: hipLaunchKernelGGL(k_sum<4>, g, b, 0, st, a, tab); break;
   }
 }
 
-__global__ void k_finalize(int64_t nq, int n_chunks, int64_t stride, const double *__restrict__ part,
-                           const double *__restrict__ px, const double *__restrict__ py,
-                           const double *__restrict__ pz, const double *__restrict__ nx,
-                           const double *__restrict__ ny, const double *__restrict__ nz,
-                           const double *__restrict__ wdS, const int8_t *__restrict__ role, double kcond,
-                           double *__restrict__ T, double *__restrict__ gx, double *__restrict__ gy,
-                           double *__restrict__ gz, double *__restrict__ ld) {
+__global__ void k_finalize(PathTab tab, int by_slot, int64_t nq, int n_chunks, int64_t stride,
+                           const double *__restrict__ part, const double *__restrict__ px,
+                           const double *__restrict__ py, const double *__restrict__ pz,
+                           const double *__restrict__ nx, const double *__restrict__ ny,
+                           const double *__restrict__ nz, const double *__restrict__ wdS,
+                           const int8_t *__restrict__ role, double kcond, int64_t ostride,
+                           double *__restrict__ Tb, double *__restrict__ gb, double *__restrict__ ldb) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
+  const int slot = blockIdx.y;
+  const int64_t oi = by_slot ? slot : tab.path[slot];
   double s0 = 0, s1 = 0, sx = 0, sy = 0, sz = 0;
+  const double *pb = part + (int64_t)slot * n_chunks * 5 * stride;
   for (int c = 0; c < n_chunks; ++c) {
-    const double *o = part + (int64_t)c * 5 * stride;
+    const double *o = pb + (int64_t)c * 5 * stride;
     s0 += o[q];
     s1 += o[stride + q];
     sx += o[2 * stride + q];
@@ -294,10 +302,11 @@ __global__ void k_finalize(int64_t nq, int n_chunks, int64_t stride, const doubl
   const double g0 = fma(2.0 * px[q], s1, sx);
   const double g1 = fma(2.0 * py[q], s1, sy);
   const double g2 = fma(2.0 * pz[q], s1, sz);
+  double *T = Tb + oi * ostride, *g = gb + oi * 3 * ostride, *ld = ldb + oi * ostride;
   T[q] = s0;
-  gx[q] = g0;
-  gy[q] = g1;
-  gz[q] = g2;
+  g[q] = g0;
+  g[ostride + q] = g1;
+  g[2 * ostride + q] = g2;
   const int r = role[q];
   double d = 0.0;
   if (r == 0) d = -kcond * (g0 * nx[q] + g1 * ny[q] + g2 * nz[q]) * wdS[q];
@@ -305,14 +314,14 @@ __global__ void k_finalize(int64_t nq, int n_chunks, int64_t stride, const doubl
   ld[q] = d;
 }
 
-void launch_finalize(hipStream_t st, int64_t nq, int n_chunks, int64_t part_stride, const double *part,
-                     const double *px, const double *py, const double *pz, const double *nx,
-                     const double *ny, const double *nz, const double *wdS, const int8_t *role,
-                     double kcond, double *T, double *gx, double *gy, double *gz, double *ld) {
-  if (nq <= 0) return;
-  dim3 g((unsigned)((nq + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL(k_finalize, g, dim3(kBlock), 0, st, nq, n_chunks, part_stride, part, px, py, pz, nx,
-                     ny, nz, wdS, role, kcond, T, gx, gy, gz, ld);
+void launch_finalize(hipStream_t st, const PathTab &tab, bool by_slot, int64_t nq, int n_chunks,
+                     int64_t part_stride, const double *part, const double *px, const double *py,
+                     const double *pz, const double *nx, const double *ny, const double *nz, const double *wdS,
+                     const int8_t *role, double kcond, int64_t ostride, double *T, double *g, double *ld) {
+  if (nq <= 0 || tab.count <= 0) return;
+  dim3 gr((unsigned)((nq + kBlock - 1) / kBlock), (unsigned)tab.count);
+  hipLaunchKernelGGL(k_finalize, gr, dim3(kBlock), 0, st, tab, by_slot ? 1 : 0, nq, n_chunks, part_stride, part,
+                     px, py, pz, nx, ny, nz, wdS, role, kcond, ostride, T, g, ld);
 }
 
 __global__ void k_gather(int64_t nrow, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,

@@ -1,5 +1,6 @@
 // C ABI of the semi-analytical IGA thermal model on gfx950: object set-up,
-// the per-step device pipeline, PCG driver, evaluation, checkpoints, stats.
+// the per-step device pipeline (all live scan paths advance together), PCG
+// drivers, evaluation, checkpoints and statistics.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -62,9 +64,6 @@ struct PathState {
   int64_t src0 = 0, src1 = 0;
   int32_t n_steps = 0;
   int64_t step = 0;
-  double *v = nullptr, *F = nullptr;     // v = u - T0 (control values), F^n
-  double *vD = nullptr;                  // Dirichlet values (deviation) of the last step
-  double *T = nullptr, *g = nullptr;     // boundary T~ [nq], grad [3][stride]
 };
 
 struct StageEvents {
@@ -78,13 +77,13 @@ struct sa_iga {
   int device = 0;
   hipStream_t own_stream = nullptr, stream = nullptr;
   std::vector<void *> owned;
-  int64_t nq = 0, stride = 0;
+  int64_t nq = 0, stride = 0, nd = 0, nDa = 1, nbox = 1;
+  int S = 0;                              // number of paths
   // boundary points (centred), normals, weights, roles
   double *px = nullptr, *py = nullptr, *pz = nullptr, *pq2 = nullptr;
   float *fx = nullptr, *fy = nullptr, *fz = nullptr, *fq2 = nullptr;
   double *nx = nullptr, *ny = nullptr, *nz = nullptr, *wdS = nullptr;
   int8_t *role = nullptr;
-  double *ld = nullptr;                  // per-point load densities
   DevCsr load, dproj, mdir;
   int64_t *dir_dofs = nullptr;
   int64_t nD = 0;
@@ -101,36 +100,46 @@ struct sa_iga {
   std::vector<int64_t> h_tick;
   double *c64 = nullptr;
   float *c32 = nullptr;
-  int64_t max_path_sources = 0;
-  // work buffers
-  double *part = nullptr;
-  int64_t part_chunks = 0;
-  double *Fnew = nullptr, *bD = nullptr, *xnew = nullptr;
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-  double *rD = nullptr, *zD = nullptr, *pD = nullptr, *qD = nullptr;
+  // per-path state: v = u - T0 and F in double buffers selected by step parity
+  double *V[2] = {nullptr, nullptr}, *Fb[2] = {nullptr, nullptr};
+  double *vD = nullptr, *bD = nullptr;   // [S][nDa]
+  double *Tb = nullptr, *Gb = nullptr, *LD = nullptr;  // [S][stride], [S][3 stride], [S][stride]
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;  // [S][nd]
+  double *t_box = nullptr;               // [S][nbox]
+  double *pD = nullptr;                  // [S][nDa]
+  double *part_b2 = nullptr, *part_pq2 = nullptr, *part_rz2 = nullptr, *part_rrs = nullptr;
+  int np_st = 0, np_fd = 0;
+  sa::PcgScalars *sc = nullptr;          // [S]
+  sa::PcgScalars *h_sc = nullptr;        // pinned [S]
+  // generic (unfused) solver work vectors
+  double *gr = nullptr, *gz = nullptr, *gp = nullptr, *gq = nullptr;
+  double *rD = nullptr, *zD = nullptr, *pDg = nullptr, *qD = nullptr;
   double *part_b = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_rr = nullptr;
-  sa::PcgScalars *sc = nullptr, *h_sc = nullptr;
+  sa::PcgScalars *sc_gen = nullptr;
+  // kernel-sum partials
+  double *part = nullptr;
+  int64_t part_cap = 0;
   std::vector<PathState> paths;
   double delta = 0, shift = 0, alpha = 0, rc = 0;
   int64_t tau_ticks = 0;
-  int64_t ns = 1;                        // sources per theta-step (ticks per step)
+  int64_t ns = 1;                        // sources per theta-step
   sa_stats stats{};
   int sticky = 0;
   StageEvents ev[SA_N_STAGES];
   // fused solver path
   sa::GatherRows grows{}, drows{};
   bool dir_fused = false, dir_exact = false;
-  sa::FusedPcg fd_dirp{};                // direct Kronecker solve of the projection
-  sa::PcgScalars *sc_dir = nullptr;
   sa::DirArgs dargs{};
+  sa::FusedPcg fd_dirp{};                // direct Kronecker solve of the projection
+  sa::PcgScalars *sc_dir = nullptr;      // [S], never set: the direct solve always runs
   bool pcg_fused = false, fd_exact = false;
   int pcg_budget = 2;                    // fixed iterations when the FD solve is exact: the
                                          // residual after the first is near kappa(A) eps
   sa::FusedPcg fp{};
-  double *t_box = nullptr, *part_rz2 = nullptr, *part_rrs = nullptr, *part_pq2 = nullptr, *part_b2 = nullptr;
   int hw0 = 1;
   sa::SolveStatus *d_status = nullptr;   // ring of per-solve records
-  int64_t status_cap = 0, status_used = 0;
+  std::vector<int8_t> status_kind;       // 0 projection, 1 theta-step
+  int64_t status_cap = 0;
   size_t lds_per_block = 65536;
   ~sa_iga();
 };
@@ -167,6 +176,13 @@ int guarded(F &&f) {
     return set_error(SA_EINVAL, "unexpected failure");
   }
 }
+
+// ---- path state accessors -------------------------------------------------------
+inline double *path_v(sa_iga *h, int p) { return h->V[h->paths[p].step & 1] + (int64_t)p * h->nd; }
+inline double *path_F(sa_iga *h, int p) { return h->Fb[h->paths[p].step & 1] + (int64_t)p * h->nd; }
+inline double *path_vD(sa_iga *h, int p) { return h->vD + (int64_t)p * h->nDa; }
+inline double *path_T(sa_iga *h, int p) { return h->Tb + (int64_t)p * h->stride; }
+inline double *path_G(sa_iga *h, int p) { return h->Gb + (int64_t)p * 3 * h->stride; }
 
 // ---- stage timing -----------------------------------------------------------
 struct StageScope {
@@ -211,58 +227,53 @@ void collect_timing(sa_iga *h) {
   }
 }
 
-// ---- kernel-sum plan --------------------------------------------------------
-sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int64_t n_far, int64_t n_act) {
+// ---- kernel sum --------------------------------------------------------------
+// chunking of the source history: enough workgroups to fill the chip, the
+// FP64 sources weighted by their cost
+sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int count, int64_t max_far, int64_t max_near) {
   sa::SumPlan pl{};
   const auto &o = h->m.opt;
   pl.points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
   pl.waves = o.waves_per_group ? std::min(o.waves_per_group, 8) : 4;
   pl.nq = nq;
-  pl.part_stride = h->stride;
-  pl.n_far = n_far;
-  pl.n_act = n_act;
   const int64_t per_blk = (int64_t)64 * pl.points_per_lane * pl.waves;
   const int64_t n_pblk = std::max<int64_t>(1, (nq + per_blk - 1) / per_blk);
-  const int64_t n_near = n_act - n_far;
+  pl.chunk_far = pl.chunk_near = 1;
   if (o.chunk_sources > 0) {
-    pl.chunk_far = o.chunk_sources;
-    pl.chunk_near = o.chunk_sources;
-    pl.n_chunks_far = (int)((n_far + pl.chunk_far - 1) / pl.chunk_far);
-    pl.n_chunks_near = (int)((n_near + pl.chunk_near - 1) / pl.chunk_near);
+    pl.chunk_far = pl.chunk_near = o.chunk_sources;
+    pl.n_chunks_far = (int)((max_far + pl.chunk_far - 1) / pl.chunk_far);
+    pl.n_chunks_near = (int)((max_near + pl.chunk_near - 1) / pl.chunk_near);
     return pl;
   }
   const int64_t target_groups = 2048;
-  int64_t C = std::max<int64_t>(1, (target_groups + n_pblk - 1) / n_pblk);
-  const double wf = (double)n_far, wn = 3.0 * (double)n_near;
+  const int64_t C = std::max<int64_t>(1, (target_groups + n_pblk * count - 1) / (n_pblk * count));
+  const double wf = (double)max_far, wn = 3.0 * (double)max_near;
   int64_t cf = 0, cn = 0;
-  if (n_far > 0 && n_near > 0) {
+  if (max_far > 0 && max_near > 0) {
     cf = std::max<int64_t>(1, (int64_t)std::llround(C * wf / (wf + wn)));
     cn = std::max<int64_t>(1, C - cf);
-  } else if (n_far > 0) {
+  } else if (max_far > 0) {
     cf = C;
-  } else if (n_near > 0) {
+  } else if (max_near > 0) {
     cn = C;
   }
   const int64_t min_chunk = 32;
   if (cf) {
-    int64_t len = std::max<int64_t>(min_chunk, (n_far + cf - 1) / cf);
+    const int64_t len = std::max<int64_t>(min_chunk, (max_far + cf - 1) / cf);
     pl.chunk_far = (int)len;
-    pl.n_chunks_far = (int)((n_far + len - 1) / len);
+    pl.n_chunks_far = (int)((max_far + len - 1) / len);
   }
   if (cn) {
-    int64_t len = std::max<int64_t>(min_chunk, (n_near + cn - 1) / cn);
+    const int64_t len = std::max<int64_t>(min_chunk, (max_near + cn - 1) / cn);
     pl.chunk_near = (int)len;
-    pl.n_chunks_near = (int)((n_near + len - 1) / len);
+    pl.n_chunks_near = (int)((max_near + len - 1) / len);
   }
-  if (pl.chunk_far == 0) pl.chunk_far = 1;
-  if (pl.chunk_near == 0) pl.chunk_near = 1;
   return pl;
 }
 
-// partial-sum buffer of at least `doubles` values
 void ensure_part(sa_iga *h, int64_t doubles) {
-  if (doubles <= h->part_chunks) return;
-  int64_t cap = std::max<int64_t>(doubles, 2 * h->part_chunks);
+  if (doubles <= h->part_cap) return;
+  const int64_t cap = std::max<int64_t>(doubles, 2 * h->part_cap);
   if (h->part) {
     hip_check(hipStreamSynchronize(h->stream), "sync");
     hip_check(hipFree(h->part), "free");
@@ -270,54 +281,60 @@ void ensure_part(sa_iga *h, int64_t doubles) {
     h->part = nullptr;
   }
   h->part = dev_alloc<double>(h->owned, (size_t)cap);
-  h->part_chunks = cap;
+  h->part_cap = cap;
 }
 
-int64_t n_active(const sa_iga *h, const PathState &P, int64_t now) {
-  auto b = h->h_tick.begin() + P.src0, e = h->h_tick.begin() + P.src1;
-  return (int64_t)(std::upper_bound(b, e, now) - b);
-}
-
-
-// T~ and grad T~ of path P at time step*dt at nq points (centred arrays),
-// plus the per-point load densities (roles) into ld.
-void sum_at_points(sa_iga *h, const PathState &P, int64_t step, int64_t nq, int64_t stride, const double *px,
-                   const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
-                   const float *fz, const float *fq2, const int8_t *role, const double *nx,
-                   const double *ny, const double *nz, const double *wdS, double *T, double *g,
-                   double *ld) {
+// switched-on and far-field counts of path P at the end of step `step`
+void active_counts(const sa_iga *h, const PathState &P, int64_t step, int32_t &n_act, int32_t &n_far) {
   const int64_t now = step * h->ns;
-  const int64_t n_act = n_active(h, P, now);
-  int64_t n_far = 0;
-  if (h->m.opt.precision == SA_PREC_FP32_FAR && n_act > 0) {
-    const int64_t thr = now - h->tau_ticks;       // far iff tick < thr
-    auto b = h->h_tick.begin() + P.src0;
-    n_far = std::min<int64_t>(n_act, (int64_t)(std::lower_bound(b, b + n_act, thr) - b));
+  auto b = h->h_tick.begin() + P.src0, e = h->h_tick.begin() + P.src1;
+  const int64_t a = (int64_t)(std::upper_bound(b, e, now) - b);
+  int64_t f = 0;
+  if (h->m.opt.precision == SA_PREC_FP32_FAR && a > 0) {
+    const int64_t thr = now - h->tau_ticks;  // far iff tick < thr
+    f = std::min<int64_t>(a, (int64_t)(std::lower_bound(b, b + a, thr) - b));
   }
-  if (n_act > 0) {
+  n_act = (int32_t)a;
+  n_far = (int32_t)f;
+}
+
+// T~ and grad T~ of the slots of `tab` at time step*dt at nq points (centred
+// arrays); outputs indexed by path (boundary tables) or by slot (query points)
+void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t step, int64_t nq, int64_t stride, const double *px,
+                const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
+                const float *fz, const float *fq2, const int8_t *role, const double *nx, const double *ny,
+                const double *nz, const double *wdS, bool by_slot, int64_t ostride, double *T, double *G,
+                double *ld) {
+  const int64_t now = step * h->ns;
+  int64_t max_act = 0, max_far = 0, max_near = 0;
+  for (int s = 0; s < tab.count; ++s) {
+    max_act = std::max<int64_t>(max_act, tab.n_act[s]);
+    max_far = std::max<int64_t>(max_far, tab.n_far[s]);
+    max_near = std::max<int64_t>(max_near, tab.n_act[s] - tab.n_far[s]);
+    h->stats.pairs += (int64_t)tab.n_act[s] * nq;
+    h->stats.pairs_near += (int64_t)(tab.n_act[s] - tab.n_far[s]) * nq;
+  }
+  if (max_act > 0) {
     StageScope s(h, SA_STAGE_COEFF);
     sa::CoeffParams cp{now, h->delta, h->shift, h->alpha, h->rc, h->m.opt.kernel_scale};
-    sa::launch_coeff(h->stream, n_act, n_far, h->stick + P.src0, h->sx + P.src0, h->sy + P.src0,
-                     h->sz + P.src0, h->sE + P.src0, cp, h->c64, h->c32);
+    sa::launch_coeff(h->stream, tab, max_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
   }
-  sa::SumPlan pl = make_plan(h, nq, n_far, n_act);
+  sa::SumPlan pl = make_plan(h, nq, tab.count, max_far, max_near);
   pl.part_stride = stride;
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
-  ensure_part(h, (int64_t)std::max(nch, 1) * 5 * stride);
+  ensure_part(h, (int64_t)tab.count * std::max(nch, 1) * 5 * stride);
   if (nch > 0) {
     StageScope s(h, SA_STAGE_SUM);
-    sa::launch_sum(h->stream, pl, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, h->part);
+    sa::launch_sum(h->stream, pl, tab, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, h->part);
   }
   {
     StageScope s(h, SA_STAGE_REDUCE);
-    sa::launch_finalize(h->stream, nq, nch, stride, h->part, px, py, pz, nx, ny, nz, wdS, role,
-                        h->m.mat.k, T, g, g + stride, g + 2 * stride, ld);
+    sa::launch_finalize(h->stream, tab, by_slot, nq, nch, stride, h->part, px, py, pz, nx, ny, nz, wdS, role,
+                        h->m.mat.k, ostride, T, G, ld);
   }
-  h->stats.pairs += n_act * nq;
-  h->stats.pairs_near += (n_act - n_far) * nq;
 }
 
-// ---- PCG driver --------------------------------------------------------------
+// ---- generic PCG driver (single path; Jacobi or oversize problems) ---------------
 struct PcgSpec {
   int64_t n = 0;
   bool stencil = true;
@@ -340,23 +357,22 @@ int apply_precond(sa_iga *h, PcgSpec &s, const double *r, double *z, sa::PcgScal
 }
 
 // Solve on the prepared residual r = b - A x (partials of |b|^2 in part_b).
-// Returns iterations; throws SA_ENOCONV.
 int pcg_run(sa_iga *h, PcgSpec &s, double *relres) {
   const int64_t n = s.n;
   const int np = sa::parts_for(n);
   int np_rz = apply_precond(h, s, s.r, s.z, nullptr);
-  sa::launch_pcg_start(h->stream, n, s.n_part_b, h->part_b, np_rz, h->part_rz, s.z, s.p, h->sc,
+  sa::launch_pcg_start(h->stream, n, s.n_part_b, h->part_b, np_rz, h->part_rz, s.z, s.p, h->sc_gen,
                        h->m.opt.pcg_rtol);
   int chunk = s.fd ? 2 : 8;
   for (;;) {
     for (int k = 0; k < chunk; ++k) {
-      if (s.stencil) sa::launch_stencil_apply_dot(h->stream, s.st, s.p, s.q, h->part_pq, h->sc);
-      else sa::launch_csr_apply_dot(h->stream, s.csr, s.p, s.q, h->part_pq, h->sc);
-      sa::launch_pcg_update(h->stream, n, np, h->part_pq, s.p, s.q, s.x, s.r, h->part_rr, h->sc);
-      np_rz = apply_precond(h, s, s.r, s.z, h->sc);
-      sa::launch_pcg_direction(h->stream, n, np, np_rz, h->part_rr, h->part_rz, s.z, s.p, h->sc);
+      if (s.stencil) sa::launch_stencil_apply_dot(h->stream, s.st, s.p, s.q, h->part_pq, h->sc_gen);
+      else sa::launch_csr_apply_dot(h->stream, s.csr, s.p, s.q, h->part_pq, h->sc_gen);
+      sa::launch_pcg_update(h->stream, n, np, h->part_pq, s.p, s.q, s.x, s.r, h->part_rr, h->sc_gen);
+      np_rz = apply_precond(h, s, s.r, s.z, h->sc_gen);
+      sa::launch_pcg_direction(h->stream, n, np, np_rz, h->part_rr, h->part_rz, s.z, s.p, h->sc_gen);
     }
-    hip_check(hipMemcpyAsync(h->h_sc, h->sc, sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
+    hip_check(hipMemcpyAsync(h->h_sc, h->sc_gen, sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
               "status copy");
     hip_check(hipStreamSynchronize(h->stream), "sync");
     const sa::PcgScalars st = *h->h_sc;
@@ -373,60 +389,120 @@ int pcg_run(sa_iga *h, PcgSpec &s, double *relres) {
   }
 }
 
-sa::SolveStatus *next_status(sa_iga *h);
-
-void step_path(sa_iga *h, PathState &P) {
-  const int64_t s1 = P.step + 1;
-  const int64_t nd = h->m.P.ndof;
-  sum_at_points(h, P, s1, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2,
-                h->role, h->nx, h->ny, h->nz, h->wdS, P.T, P.g, h->ld);
-  {
-    StageScope s(h, SA_STAGE_LOAD);
-    // F^{n+1} on the non-empty rows, and x <- v (the theta-step iterate)
-    sa::launch_gather_rows(h->stream, h->grows, h->ld, h->Fnew, nd, P.v, h->xnew);
-  }
-  if (h->nD > 0) {
-    StageScope s(h, SA_STAGE_DIRICHLET);
-    if (h->dir_exact) {
-      sa::launch_gather_rows(h->stream, h->drows, h->ld, h->bD, 0, nullptr, nullptr);
-      sa::FusedPcg f = h->fd_dirp;
-      f.z = P.vD;
-      f.scatter_out = h->xnew;
-      sa::launch_fd_pass(h->stream, f, 0, false, false);
-    } else if (h->dir_fused) {
-      sa::launch_gather_rows(h->stream, h->drows, h->ld, h->bD, 0, nullptr, nullptr);
-      sa::DirArgs a = h->dargs;
-      a.b = h->bD;
-      a.vD = P.vD;
-      a.xfull = h->xnew;
-      a.status = next_status(h);
-      sa::launch_dirichlet(h->stream, a);
+// ---- device solve records ----------------------------------------------------
+void check_statuses(sa_iga *h) {
+  const size_t used = h->status_kind.size();
+  if (used == 0) return;
+  std::vector<sa::SolveStatus> st(used);
+  hip_check(hipMemcpyAsync(st.data(), h->d_status, used * sizeof(sa::SolveStatus), hipMemcpyDeviceToHost,
+                           h->stream),
+            "status copy");
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+  std::vector<int8_t> kind;
+  kind.swap(h->status_kind);
+  int bad = -1;
+  for (size_t i = 0; i < used; ++i) {
+    if (st[i].done != 1 && bad < 0) bad = (int)i;
+    if (kind[i] == 0) {
+      h->stats.dirichlet_iterations += st[i].iter;
     } else {
-      sa::launch_gather(h->stream, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->ld, h->bD);
-      PcgSpec d;
-      d.n = h->nD;
-      d.stencil = false;
-      d.csr = h->mdir.op();
-      d.fd = h->m.opt.preconditioner == SA_PRECOND_FD && h->m.fd_dir_ok;
-      d.fdop = h->fd_dir.op;
-      d.invdiag = h->mdir_invdiag;
-      d.x = P.vD;
-      d.r = h->rD;
-      d.z = h->zD;
-      d.p = h->pD;
-      d.q = h->qD;
-      d.n_part_b = sa::parts_for(h->nD);
-      sa::launch_csr_init(h->stream, d.csr, h->bD, P.vD, h->rD, h->part_b);
-      double rr = 0;
-      h->stats.dirichlet_iterations += pcg_run(h, d, &rr);
-      sa::launch_scatter_dirichlet(h->stream, h->nD, h->dir_dofs, P.vD, h->xnew);
+      h->stats.pcg_iterations += st[i].iter;
+      h->stats.pcg_last_iterations = st[i].iter;
+      h->stats.pcg_last_relres = std::sqrt(std::max(st[i].relres2, 0.0));
     }
   }
+  if (bad >= 0) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "a solve did not converge within its iteration budget (record %d, %s, done %d, |r|/|b| = %.3e)",
+                  bad, kind[bad] ? "theta-step" : "projection", st[bad].done,
+                  std::sqrt(std::max(st[bad].relres2, 0.0)));
+    throw sa::SaError{SA_ENOCONV, msg};
+  }
+}
+
+// reserve n consecutive records of the given kind
+sa::SolveStatus *next_status(sa_iga *h, int n, int8_t kind) {
+  if ((int64_t)h->status_kind.size() + n > h->status_cap) check_statuses(h);
+  sa::SolveStatus *s = h->d_status + h->status_kind.size();
+  for (int i = 0; i < n; ++i) h->status_kind.push_back(kind);
+  return s;
+}
+
+// ---- one theta-step of a set of paths (same step, at most kMaxBatch) -------------
+void step_batch(sa_iga *h, const std::vector<int> &pids) {
+  const int count = (int)pids.size();
+  const int64_t step = h->paths[pids[0]].step, s1 = step + 1;
+  const int cur = (int)(step & 1), nxt = cur ^ 1;
+  const int64_t nd = h->nd;
+  sa::PathTab tab{};
+  sa::SlotMap sm{};
+  tab.count = sm.count = count;
+  for (int s = 0; s < count; ++s) {
+    const PathState &P = h->paths[pids[s]];
+    tab.path[s] = sm.path[s] = pids[s];
+    tab.src0[s] = P.src0;
+    active_counts(h, P, s1, tab.n_act[s], tab.n_far[s]);
+  }
+  // T~, grad T~ and load densities at every boundary point (Eqs. 7-8, 10-11)
+  sum_points(h, tab, s1, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
+             h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD);
+  double *Vc = h->V[cur], *Vn = h->V[nxt], *Fc = h->Fb[cur], *Fn = h->Fb[nxt];
+  {
+    StageScope s(h, SA_STAGE_LOAD);
+    // F^{n+1} on the non-empty rows (Eq. 18), and the iterate u^{n+1} <- u^n
+    sa::launch_gather_rows(h->stream, sm, h->grows, h->LD, h->stride, Fn, nd, nd, Vc, Vn);
+  }
+  // Dirichlet values (Eq. 11), scattered into the iterate
+  if (h->nD > 0) {
+    StageScope s(h, SA_STAGE_DIRICHLET);
+    if (h->dir_exact || h->dir_fused)
+      sa::launch_gather_rows(h->stream, sm, h->drows, h->LD, h->stride, h->bD, h->nDa, 0, nullptr, nullptr);
+    if (h->dir_exact) {
+      sa::FusedPcg f = h->fd_dirp;
+      f.scatter_out = Vn;
+      sa::launch_fd_pass(h->stream, sm, f, 0, false, false);
+    } else if (h->dir_fused) {
+      sa::DirArgs a = h->dargs;
+      a.b = h->bD;
+      a.vD = h->vD;
+      a.xfull = Vn;
+      a.xs = nd;
+      a.status = next_status(h, count, 0);
+      sa::launch_dirichlet(h->stream, sm, a);
+    } else {
+      for (int s = 0; s < count; ++s) {
+        const int p = pids[s];
+        sa::launch_gather(h->stream, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val,
+                          h->LD + (int64_t)p * h->stride, h->bD + (int64_t)p * h->nDa);
+        PcgSpec d;
+        d.n = h->nD;
+        d.stencil = false;
+        d.csr = h->mdir.op();
+        d.fd = h->m.opt.preconditioner == SA_PRECOND_FD && h->m.fd_dir_ok;
+        d.fdop = h->fd_dir.op;
+        d.invdiag = h->mdir_invdiag;
+        d.x = path_vD(h, p);
+        d.r = h->rD;
+        d.z = h->zD;
+        d.p = h->pDg;
+        d.q = h->qD;
+        d.n_part_b = sa::parts_for(h->nD);
+        sa::launch_csr_init(h->stream, d.csr, h->bD + (int64_t)p * h->nDa, d.x, h->rD, h->part_b);
+        double rr = 0;
+        h->stats.dirichlet_iterations += pcg_run(h, d, &rr);
+        sa::launch_scatter_dirichlet(h->stream, h->nD, h->dir_dofs, d.x, Vn + (int64_t)p * nd);
+      }
+    }
+  }
+  // theta-scheme (Eq. 20)
   if (h->pcg_fused) {
     {
       StageScope s(h, SA_STAGE_RHS);
       sa::SlArgs a{};
       a.nrow = nd;
+      a.vs = nd;
+      a.np = h->np_st;
       a.n0 = h->Aop.n[0];
       a.n1 = h->Aop.n[1];
       a.hw1 = h->Aop.hw[1];
@@ -434,22 +510,24 @@ void step_path(sa_iga *h, PathState &P) {
       a.A = h->Aop.A;
       a.B = h->Bval;
       a.mask = h->free_mask;
-      a.x = h->xnew;
-      a.v = P.v;
-      a.F1 = h->Fnew;
-      a.F0 = P.F;
+      a.x = Vn;
+      a.v = Vc;
+      a.F1 = Fn;
+      a.F0 = Fc;
       a.theta = h->m.opt.theta;
       a.out = h->r;
       a.part = h->part_b2;
       a.sc_w = h->sc;
-      sa::launch_stencil_sl(h->stream, a, h->hw0, true);
+      sa::launch_stencil_sl(h->stream, sm, a, h->hw0, true);
     }
     StageScope s(h, SA_STAGE_PCG);
     sa::FusedPcg f = h->fp;
-    f.x = h->xnew;
-    f.status = next_status(h);
+    f.x = Vn;
+    f.status = next_status(h, count, 1);
     sa::SlArgs ap{};
     ap.nrow = nd;
+    ap.vs = nd;
+    ap.np = h->np_st;
     ap.n0 = h->Aop.n[0];
     ap.n1 = h->Aop.n[1];
     ap.hw1 = h->Aop.hw[1];
@@ -460,102 +538,82 @@ void step_path(sa_iga *h, PathState &P) {
     ap.out = h->q;
     ap.part = h->part_pq2;
     ap.sc = h->sc;
-    sa::launch_fd_pass(h->stream, f, 0, true, false);
+    sa::launch_fd_pass(h->stream, sm, f, 0, true, false);
     if (h->fd_exact) {
       for (int k = 0; k < h->pcg_budget; ++k) {
-        sa::launch_stencil_sl(h->stream, ap, h->hw0, false);
-        sa::launch_fd_pass(h->stream, f, k, false, true);
-        sa::launch_pcg_dir(h->stream, f, k);
+        sa::launch_stencil_sl(h->stream, sm, ap, h->hw0, false);
+        sa::launch_fd_pass(h->stream, sm, f, k, false, true);
+        sa::launch_pcg_dir(h->stream, sm, f, k);
       }
     } else {
       int k = 0, chunk = 4;
       for (;;) {
         for (int c = 0; c < chunk; ++c, ++k) {
-          sa::launch_stencil_sl(h->stream, ap, h->hw0, false);
-          sa::launch_fd_pass(h->stream, f, k, false, true);
-          sa::launch_pcg_dir(h->stream, f, k);
+          sa::launch_stencil_sl(h->stream, sm, ap, h->hw0, false);
+          sa::launch_fd_pass(h->stream, sm, f, k, false, true);
+          sa::launch_pcg_dir(h->stream, sm, f, k);
         }
-        hip_check(hipMemcpyAsync(h->h_sc, h->sc, sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
+        hip_check(hipMemcpyAsync(h->h_sc, h->sc, h->S * sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
                   "status copy");
         hip_check(hipStreamSynchronize(h->stream), "sync");
-        const sa::PcgScalars st = *h->h_sc;
-        if (st.done == 1) break;
-        if (st.done == 2) throw sa::SaError{SA_ENOCONV, "PCG breakdown (operator not positive definite)"};
+        bool all = true;
+        for (int s = 0; s < count; ++s) {
+          const sa::PcgScalars &st = h->h_sc[pids[s]];
+          if (st.done == 2) throw sa::SaError{SA_ENOCONV, "PCG breakdown (operator not positive definite)"};
+          if (st.done != 1) all = false;
+        }
+        if (all) break;
         if (k >= h->m.opt.pcg_max_iter) throw sa::SaError{SA_ENOCONV, "PCG did not converge within pcg_max_iter"};
         chunk = std::min(chunk * 2, 32);
       }
     }
   } else {
-    {
-      StageScope s(h, SA_STAGE_RHS);
-      sa::launch_theta_init(h->stream, h->Aop, h->Bval, P.v, h->Fnew, P.F, h->m.opt.theta, h->xnew, h->r,
-                            h->part_b);
+    for (int s = 0; s < count; ++s) {
+      const int p = pids[s];
+      double *x = Vn + (int64_t)p * nd;
+      {
+        StageScope sc(h, SA_STAGE_RHS);
+        sa::launch_theta_init(h->stream, h->Aop, h->Bval, Vc + (int64_t)p * nd, Fn + (int64_t)p * nd,
+                              Fc + (int64_t)p * nd, h->m.opt.theta, x, h->gr, h->part_b);
+      }
+      StageScope sc(h, SA_STAGE_PCG);
+      PcgSpec m;
+      m.n = nd;
+      m.stencil = true;
+      m.st = h->Aop;
+      m.fd = h->m.opt.preconditioner == SA_PRECOND_FD;
+      m.fdop = h->fd_main.op;
+      m.invdiag = h->A_invdiag;
+      m.x = x;
+      m.r = h->gr;
+      m.z = h->gz;
+      m.p = h->gp;
+      m.q = h->gq;
+      m.n_part_b = sa::parts_for(m.n);
+      double rr = 0;
+      const int it = pcg_run(h, m, &rr);
+      h->stats.pcg_iterations += it;
+      h->stats.pcg_last_iterations = it;
+      h->stats.pcg_last_relres = rr;
     }
-    StageScope s(h, SA_STAGE_PCG);
-    PcgSpec m;
-    m.n = nd;
-    m.stencil = true;
-    m.st = h->Aop;
-    m.fd = h->m.opt.preconditioner == SA_PRECOND_FD;
-    m.fdop = h->fd_main.op;
-    m.invdiag = h->A_invdiag;
-    m.x = h->xnew;
-    m.r = h->r;
-    m.z = h->z;
-    m.p = h->p;
-    m.q = h->q;
-    m.n_part_b = sa::parts_for(m.n);
-    double rr = 0;
-    int it = pcg_run(h, m, &rr);
-    h->stats.pcg_iterations += it;
-    h->stats.pcg_last_iterations = it;
-    h->stats.pcg_last_relres = rr;
   }
   hip_check(hipGetLastError(), "kernel launch");
-  std::swap(P.v, h->xnew);
-  std::swap(P.F, h->Fnew);
-  P.step = s1;
-  h->stats.steps++;
+  for (int s = 0; s < count; ++s) h->paths[pids[s]].step = s1;
+  h->stats.steps += count;
 }
 
-// read back and check the device solve records of the steps run so far
-void check_statuses(sa_iga *h) {
-  if (h->status_used == 0) return;
-  std::vector<sa::SolveStatus> st(h->status_used);
-  hip_check(hipMemcpyAsync(st.data(), h->d_status, st.size() * sizeof(sa::SolveStatus), hipMemcpyDeviceToHost,
-                           h->stream),
-            "status copy");
-  hip_check(hipStreamSynchronize(h->stream), "sync");
-  h->status_used = 0;
-  int bad = -1;
-  for (size_t i = 0; i < st.size(); ++i)
-    if (st[i].done != 1 && bad < 0) bad = (int)i;
-  // records alternate per step: Dirichlet (if any) then theta-step
-  const bool has_dir = h->nD > 0 && h->dir_fused && !h->dir_exact;
-  const bool main_rec = h->pcg_fused;
-  size_t i = 0;
-  while (i < st.size()) {
-    if (has_dir && i < st.size()) h->stats.dirichlet_iterations += st[i++].iter;
-    if (main_rec && i < st.size()) {
-      h->stats.pcg_iterations += st[i].iter;
-      h->stats.pcg_last_iterations = st[i].iter;
-      h->stats.pcg_last_relres = std::sqrt(std::max(st[i].relres2, 0.0));
-      ++i;
+// advance every live path by one step: lockstep groups of at most kMaxBatch
+void step_all(sa_iga *h) {
+  std::map<int64_t, std::vector<int>> groups;
+  for (int p = 0; p < (int)h->paths.size(); ++p)
+    if (h->paths[p].step < h->paths[p].n_steps) groups[h->paths[p].step].push_back(p);
+  for (auto &g : groups) {
+    const auto &ids = g.second;
+    for (size_t i = 0; i < ids.size(); i += sa::kMaxBatch) {
+      std::vector<int> b(ids.begin() + i, ids.begin() + std::min(ids.size(), i + (size_t)sa::kMaxBatch));
+      step_batch(h, b);
     }
-    if (!has_dir && !main_rec) break;
   }
-  if (bad >= 0)
-  {
-    char msg[160];
-    std::snprintf(msg, sizeof msg, "a solve did not converge within its iteration budget (record %d, done %d, |r|/|b| = %.3e)",
-                  bad, st[bad].done, std::sqrt(std::max(st[bad].relres2, 0.0)));
-    throw sa::SaError{SA_ENOCONV, msg};
-  }
-}
-
-sa::SolveStatus *next_status(sa_iga *h) {
-  if (h->status_used >= h->status_cap) check_statuses(h);
-  return h->d_status + h->status_used++;
 }
 
 std::vector<float> to_float(const std::vector<double> &v) {
@@ -587,6 +645,13 @@ DevCsr upload_csr(sa_iga *h, const sa::Csr &C) {
   return d;
 }
 
+template <class T>
+T *dev_zeros(sa_iga *h, size_t n) {
+  T *p = dev_alloc<T>(h->owned, n);
+  hip_check(hipMemsetAsync(p, 0, std::max<size_t>(n, 1) * sizeof(T), h->stream), "memset");
+  return p;
+}
+
 void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan) {
   sa::Model &m = h->m;
   // device and stream
@@ -599,6 +664,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     throw sa::SaError{SA_EDEVICE, std::string("device is ") + prop.gcnArchName + ", built for gfx950"};
   hip_check(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking), "stream");
   h->stream = h->own_stream;
+  h->lds_per_block = prop.sharedMemPerBlock;
 
   // model set-up (host)
   sa::load_patch(patch, m.P);
@@ -608,7 +674,10 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   sa::build_boundary(m);
   sa::build_fd(m);
   const int64_t nd = m.P.ndof;
+  h->nd = nd;
   const double th = m.opt.theta;
+  const int S = scan->n_paths;
+  h->S = S;
 
   // theta-scheme stencils A = M/dt + theta K, B = M/dt - (1-theta) K
   {
@@ -667,16 +736,16 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     h->nz = dev_upload(h->owned, nz, h->stream);
     h->wdS = dev_upload(h->owned, bt.wdS, h->stream);
     h->role = dev_upload(h->owned, bt.role, h->stream);
-    h->ld = dev_alloc<double>(h->owned, bt.nq);
     hip_check(hipStreamSynchronize(h->stream), "sync");
   }
   h->load = upload_csr(h, m.load);
   h->dproj = upload_csr(h, m.dproj);
   h->mdir = upload_csr(h, m.mass_dir);
   h->nD = (int64_t)m.dir_dofs.size();
+  h->nDa = std::max<int64_t>(h->nD, 1);
   h->dir_dofs = dev_upload(h->owned, m.dir_dofs, h->stream);
   {
-    std::vector<double> jd(std::max<int64_t>(h->nD, 1), 1.0);
+    std::vector<double> jd(h->nDa, 1.0);
     for (int64_t j = 0; j < h->nD; ++j)
       for (int64_t e = m.mass_dir.rowptr[j]; e < m.mass_dir.rowptr[j + 1]; ++e)
         if (m.mass_dir.col[e] == j) jd[j] = 1.0 / m.mass_dir.val[e];
@@ -707,58 +776,49 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   h->alpha = mat->k / h->rc;
   h->shift = scan->spot_radius * scan->spot_radius / (8.0 * h->alpha);
   h->tau_ticks = (int64_t)std::floor(m.opt.tau_near / h->delta + 1e-9);
-  int64_t maxs = 0;
-  for (int p = 0; p < scan->n_paths; ++p) maxs = std::max<int64_t>(maxs, scan->src_offset[p + 1] - scan->src_offset[p]);
-  h->max_path_sources = maxs;
-  h->c64 = dev_alloc<double>(h->owned, (size_t)std::max<int64_t>(maxs, 1) * sa::kCoefStride);
-  h->c32 = dev_alloc<float>(h->owned, (size_t)std::max<int64_t>(maxs, 1) * sa::kCoefStride);
+  for (int p = 0; p < S; ++p)
+    if (scan->src_offset[p + 1] - scan->src_offset[p] > 2000000000)
+      throw sa::SaError{SA_EINVAL, "a path holds more than 2e9 sources"};
+  h->c64 = dev_alloc<double>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
+  h->c32 = dev_alloc<float>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
 
-  // per-path state: u = T0 (v = 0), F = 0, vD = 0
-  h->paths.resize(scan->n_paths);
-  for (int p = 0; p < scan->n_paths; ++p) {
+  // per-path state: u = T0 (v = 0), F = 0, Dirichlet values 0
+  h->paths.resize(S);
+  for (int p = 0; p < S; ++p) {
     PathState &P = h->paths[p];
     P.src0 = scan->src_offset[p];
     P.src1 = scan->src_offset[p + 1];
     P.n_steps = scan->n_steps[p];
     P.step = 0;
-    P.v = dev_alloc<double>(h->owned, nd);
-    P.F = dev_alloc<double>(h->owned, nd);
-    P.vD = dev_alloc<double>(h->owned, std::max<int64_t>(h->nD, 1));
-    P.T = dev_alloc<double>(h->owned, h->stride);
-    P.g = dev_alloc<double>(h->owned, 3 * h->stride);
-    hip_check(hipMemsetAsync(P.v, 0, nd * sizeof(double), h->stream), "memset");
-    hip_check(hipMemsetAsync(P.F, 0, nd * sizeof(double), h->stream), "memset");
-    hip_check(hipMemsetAsync(P.vD, 0, std::max<int64_t>(h->nD, 1) * sizeof(double), h->stream), "memset");
-    hip_check(hipMemsetAsync(P.T, 0, h->stride * sizeof(double), h->stream), "memset");
-    hip_check(hipMemsetAsync(P.g, 0, 3 * h->stride * sizeof(double), h->stream), "memset");
   }
-  // work buffers
-  h->Fnew = dev_alloc<double>(h->owned, nd);
-  h->xnew = dev_alloc<double>(h->owned, nd);
-  h->r = dev_alloc<double>(h->owned, nd);
-  h->z = dev_alloc<double>(h->owned, nd);
-  h->p = dev_alloc<double>(h->owned, nd);
-  h->q = dev_alloc<double>(h->owned, nd);
-  const int64_t nDa = std::max<int64_t>(h->nD, 1);
-  h->bD = dev_alloc<double>(h->owned, nDa);
-  h->rD = dev_alloc<double>(h->owned, nDa);
-  h->zD = dev_alloc<double>(h->owned, nDa);
-  h->pD = dev_alloc<double>(h->owned, nDa);
-  h->qD = dev_alloc<double>(h->owned, nDa);
-  h->part_b = dev_alloc<double>(h->owned, 1024);
-  h->part_rz = dev_alloc<double>(h->owned, 1024);
-  h->part_pq = dev_alloc<double>(h->owned, 1024);
-  h->part_rr = dev_alloc<double>(h->owned, 1024);
-  h->sc = dev_alloc<sa::PcgScalars>(h->owned, 1);
-  hip_check(hipMemsetAsync(h->sc, 0, sizeof(sa::PcgScalars), h->stream), "memset");
-  hip_check(hipHostMalloc((void **)&h->h_sc, sizeof(sa::PcgScalars), hipHostMallocDefault), "pinned");
-  ensure_part(h, 5 * h->stride * 16);
-  hip_check(hipMemsetAsync(h->r, 0, nd * sizeof(double), h->stream), "memset");
-  hip_check(hipMemsetAsync(h->z, 0, nd * sizeof(double), h->stream), "memset");
-  hip_check(hipMemsetAsync(h->p, 0, nd * sizeof(double), h->stream), "memset");
-  hip_check(hipMemsetAsync(h->q, 0, nd * sizeof(double), h->stream), "memset");
-  hip_check(hipMemsetAsync(h->Fnew, 0, nd * sizeof(double), h->stream), "memset");
-  h->lds_per_block = prop.sharedMemPerBlock;
+  for (int b = 0; b < 2; ++b) {
+    h->V[b] = dev_zeros<double>(h, (size_t)S * nd);
+    h->Fb[b] = dev_zeros<double>(h, (size_t)S * nd);
+  }
+  h->vD = dev_zeros<double>(h, (size_t)S * h->nDa);
+  h->bD = dev_zeros<double>(h, (size_t)S * h->nDa);
+  h->pD = dev_zeros<double>(h, (size_t)S * h->nDa);
+  h->Tb = dev_zeros<double>(h, (size_t)S * h->stride);
+  h->Gb = dev_zeros<double>(h, (size_t)S * 3 * h->stride);
+  h->LD = dev_zeros<double>(h, (size_t)S * h->stride);
+  h->sc = dev_zeros<sa::PcgScalars>(h, S);
+  h->sc_dir = dev_zeros<sa::PcgScalars>(h, S);
+  hip_check(hipHostMalloc((void **)&h->h_sc, (size_t)S * sizeof(sa::PcgScalars), hipHostMallocDefault), "pinned");
+  // generic solver work vectors
+  h->gr = dev_zeros<double>(h, nd);
+  h->gz = dev_zeros<double>(h, nd);
+  h->gp = dev_zeros<double>(h, nd);
+  h->gq = dev_zeros<double>(h, nd);
+  h->rD = dev_zeros<double>(h, h->nDa);
+  h->zD = dev_zeros<double>(h, h->nDa);
+  h->pDg = dev_zeros<double>(h, h->nDa);
+  h->qD = dev_zeros<double>(h, h->nDa);
+  h->part_b = dev_zeros<double>(h, 1024);
+  h->part_rz = dev_zeros<double>(h, 1024);
+  h->part_pq = dev_zeros<double>(h, 1024);
+  h->part_rr = dev_zeros<double>(h, 1024);
+  h->sc_gen = dev_zeros<sa::PcgScalars>(h, 1);
+  ensure_part(h, (int64_t)5 * h->stride * 16);
 
   // load gather over non-empty rows
   {
@@ -781,12 +841,8 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     h->grows.col = dev_upload(h->owned, cl, h->stream);
     h->grows.val = dev_upload(h->owned, vl, h->stream);
   }
-  // Dirichlet projection in one workgroup
-  h->dir_fused = h->nD > 0 && sa::dirichlet_fits(h->nD) &&
-                 (size_t)5 * h->nD * sizeof(double) + 1024 <= h->lds_per_block;
-  h->sc_dir = dev_alloc<sa::PcgScalars>(h->owned, 1);
-  hip_check(hipMemsetAsync(h->sc_dir, 0, sizeof(sa::PcgScalars), h->stream), "memset");
-  if (h->dir_fused) {
+  // Dirichlet projection: direct Kronecker solve, one-workgroup PCG, or generic
+  if (h->nD > 0) {
     std::vector<int32_t> iota(h->nD);
     for (int64_t j = 0; j < h->nD; ++j) iota[j] = (int32_t)j;
     h->drows.nrows = h->nD;
@@ -794,76 +850,85 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     h->drows.rowptr = h->dproj.rowptr;
     h->drows.col = h->dproj.col;
     h->drows.val = h->dproj.val;
-    sa::DirArgs &a = h->dargs;
-    a.nD = (int)h->nD;
     if (m.opt.preconditioner == SA_PRECOND_FD && m.fd_dir_ok) {
       // exactness of the Kronecker solve for the trace mass matrix
-      const int64_t nD = h->nD;
-      std::vector<double> y(nD), z(nD), w(nD, 0.0);
+      const int64_t n = h->nD;
+      std::vector<double> y(n), zz(n);
       uint64_t st = 0x2545f4914f6cdd1dull;
-      for (int64_t i = 0; i < nD; ++i) {
+      for (int64_t i = 0; i < n; ++i) {
         st = st * 6364136223846793005ull + 1442695040888963407ull;
         y[i] = (double)(st >> 11) / 9007199254740992.0 - 0.5;
       }
-      sa::fd_apply_host(m.fd_dir, y.data(), z.data(), nD);
+      sa::fd_apply_host(m.fd_dir, y.data(), zz.data(), n);
       double num = 0, den = 0;
-      for (int64_t j = 0; j < nD; ++j) {
+      for (int64_t j = 0; j < n; ++j) {
         double sum = 0;
         for (int64_t e = m.mass_dir.rowptr[j]; e < m.mass_dir.rowptr[j + 1]; ++e)
-          sum += m.mass_dir.val[e] * z[m.mass_dir.col[e]];
+          sum += m.mass_dir.val[e] * zz[m.mass_dir.col[e]];
         num = std::max(num, std::fabs(sum - y[j]));
         den = std::max(den, std::fabs(y[j]));
       }
-      h->dir_exact = den > 0 && num / den < 1e-10;
-    }
-    a.mrow = h->mdir.rowptr;
-    a.mcol = h->mdir.col;
-    a.mval = h->mdir.val;
-    a.fd = (m.opt.preconditioner == SA_PRECOND_FD && m.fd_dir_ok) ? 1 : 0;
-    a.na = m.fd_dir_ok ? m.fd_dir.m[0] : 0;
-    a.nb = m.fd_dir_ok ? m.fd_dir.m[1] : 0;
-    a.Ua = a.fd ? h->fd_dir.op.U[0] : nullptr;
-    a.Ub = a.fd ? h->fd_dir.op.U[1] : nullptr;
-    a.inv = a.fd ? h->fd_dir.op.inv_diag : nullptr;
-    a.jacobi = h->mdir_invdiag;
-    a.dofs = h->dir_dofs;
-    a.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
-    a.max_iter = m.opt.pcg_max_iter;
-    a.u_in_lds = 0;
-    if (a.fd) {
-      a.u_in_lds = 1;
-      if (sa::dirichlet_lds(a) + 1024 > h->lds_per_block) a.u_in_lds = 0;
-    }
-    if (sa::dirichlet_lds(a) + 1024 > h->lds_per_block) h->dir_fused = false;
-    const int dm[3] = {a.na, a.nb, 1};
-    if (h->dir_exact && !sa::fused_fits(dm)) h->dir_exact = false;
-    if (h->dir_exact) {
-      sa::FusedPcg &f = h->fd_dirp;
-      f = sa::FusedPcg{};
-      for (int d = 0; d < 3; ++d) {
-        f.n[d] = dm[d];
-        f.lo[d] = 0;
-        f.m[d] = dm[d];
+      const int dm[3] = {m.fd_dir.m[0], m.fd_dir.m[1], 1};
+      h->dir_exact = den > 0 && num / den < 1e-10 && sa::fused_fits(dm);
+      if (h->dir_exact) {
+        sa::FusedPcg &f = h->fd_dirp;
+        f = sa::FusedPcg{};
+        for (int d = 0; d < 3; ++d) {
+          f.n[d] = dm[d];
+          f.lo[d] = 0;
+          f.m[d] = dm[d];
+        }
+        f.U0 = h->fd_dir.op.U[0];
+        f.U1 = h->fd_dir.op.U[1];
+        f.U2 = h->fd_dir.op.U[2];
+        f.inv = h->fd_dir.op.inv_diag;
+        f.r = h->bD;
+        f.z = h->vD;
+        f.p = h->pD;
+        f.vs = h->nDa;
+        f.t = dev_zeros<double>(h, (size_t)S * h->nD);
+        f.ts = h->nD;
+        f.sc = h->sc_dir;
+        f.scatter_idx = h->dir_dofs;
+        f.sos = nd;
       }
-      f.U0 = h->fd_dir.op.U[0];
-      f.U1 = h->fd_dir.op.U[1];
-      f.U2 = h->fd_dir.op.U[2];
-      f.inv = h->fd_dir.op.inv_diag;
-      f.r = h->bD;
-      f.p = h->pD;
-      f.t = h->fd_dir.op.t1;
-      f.sc = h->sc_dir;
-      f.scatter_idx = h->dir_dofs;
+    }
+    if (!h->dir_exact && sa::dirichlet_fits(h->nD)) {
+      sa::DirArgs &a = h->dargs;
+      a = sa::DirArgs{};
+      a.nD = (int)h->nD;
+      a.mrow = h->mdir.rowptr;
+      a.mcol = h->mdir.col;
+      a.mval = h->mdir.val;
+      a.fd = (m.opt.preconditioner == SA_PRECOND_FD && m.fd_dir_ok) ? 1 : 0;
+      a.na = m.fd_dir_ok ? m.fd_dir.m[0] : 0;
+      a.nb = m.fd_dir_ok ? m.fd_dir.m[1] : 0;
+      a.Ua = a.fd ? h->fd_dir.op.U[0] : nullptr;
+      a.Ub = a.fd ? h->fd_dir.op.U[1] : nullptr;
+      a.inv = a.fd ? h->fd_dir.op.inv_diag : nullptr;
+      a.jacobi = h->mdir_invdiag;
+      a.dofs = h->dir_dofs;
+      a.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
+      a.max_iter = m.opt.pcg_max_iter;
+      a.u_in_lds = a.fd ? 1 : 0;
+      if (sa::dirichlet_lds(a) + 1024 > h->lds_per_block) a.u_in_lds = 0;
+      h->dir_fused = sa::dirichlet_lds(a) + 1024 <= h->lds_per_block;
     }
   }
   // fused PCG on the box of free DOFs
   h->hw0 = m.M.hw[0];
   const auto &FM = m.fd_main;
-  const size_t slab_lds = (size_t)2 * FM.m[1] * FM.m[2] * sizeof(double);
+  const size_t plane_lds = (size_t)2 * FM.m[1] * FM.m[2] * sizeof(double);
   h->pcg_fused = m.opt.preconditioner == SA_PRECOND_FD && sa::fused_fits(FM.m) &&
-                 slab_lds + 1024 <= h->lds_per_block && m.M.hw[2] <= 7 && m.M.hw[0] <= 6;
+                 plane_lds + 1024 <= h->lds_per_block && m.M.hw[2] <= 7 && m.M.hw[0] <= 6;
+  h->np_st = sa::stencil_blocks(nd);
   if (h->pcg_fused) {
+    h->r = dev_zeros<double>(h, (size_t)S * nd);
+    h->z = dev_zeros<double>(h, (size_t)S * nd);
+    h->p = dev_zeros<double>(h, (size_t)S * nd);
+    h->q = dev_zeros<double>(h, (size_t)S * nd);
     sa::FusedPcg &f = h->fp;
+    f = sa::FusedPcg{};
     for (int d = 0; d < 3; ++d) {
       f.n[d] = FM.n[d];
       f.lo[d] = FM.lo[d];
@@ -877,34 +942,35 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     f.z = h->z;
     f.p = h->p;
     f.q = h->q;
-    const int64_t nbox = (int64_t)FM.m[0] * FM.m[1] * FM.m[2];
-    h->t_box = dev_alloc<double>(h->owned, nbox);
+    f.vs = nd;
+    h->nbox = (int64_t)FM.m[0] * FM.m[1] * FM.m[2];
+    h->t_box = dev_zeros<double>(h, (size_t)S * h->nbox);
     f.t = h->t_box;
+    f.ts = h->nbox;
     f.np_rz = FM.m[1] * FM.m[2];
-    h->part_rz2 = dev_alloc<double>(h->owned, 2 * f.np_rz);
-    h->part_rrs = dev_alloc<double>(h->owned, f.np_rz);
+    h->np_fd = f.np_rz;
+    h->part_rz2 = dev_zeros<double>(h, (size_t)S * 2 * f.np_rz);
+    h->part_rrs = dev_zeros<double>(h, (size_t)S * f.np_rz);
     f.part_rz = h->part_rz2;
     f.part_rr = h->part_rrs;
-    const int nbk = sa::stencil_blocks(nd);
-    h->part_pq2 = dev_alloc<double>(h->owned, nbk);
-    h->part_b2 = dev_alloc<double>(h->owned, nbk);
+    h->part_pq2 = dev_zeros<double>(h, (size_t)S * h->np_st);
+    h->part_b2 = dev_zeros<double>(h, (size_t)S * h->np_st);
     f.part_pq = h->part_pq2;
-    f.np_pq = nbk;
+    f.np_pq = h->np_st;
     f.part_b = h->part_b2;
-    f.np_b = nbk;
+    f.np_b = h->np_st;
     f.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
     f.sc = h->sc;
   }
   h->status_cap = 8192;
-  h->d_status = dev_alloc<sa::SolveStatus>(h->owned, h->status_cap);
-  hip_check(hipMemsetAsync(h->d_status, 0, h->status_cap * sizeof(sa::SolveStatus), h->stream), "memset");
+  h->d_status = dev_zeros<sa::SolveStatus>(h, h->status_cap);
   hip_check(hipStreamSynchronize(h->stream), "sync");
   if (std::getenv("SA_IGA_VERBOSE"))
     std::fprintf(stderr,
-                 "[sa_iga] ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: fused %d exact %d | "
+                 "[sa_iga] paths %d ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: exact %d one-wg %d | "
                  "theta-step: fused %d fd-exact %d budget %d\n",
-                 (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_fused,
-                 (int)h->dir_exact, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget);
+                 S, (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_exact,
+                 (int)h->dir_fused, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget);
 }
 
 // parametric query points -> device CSR rows of basis values (and gradients)
@@ -978,9 +1044,8 @@ struct TempBufs {
   }
 };
 
-// T~ and grad T~ at n physical points (host in / host out)
-void source_field_host(sa_iga *h, const PathState &P, int64_t step, int64_t n, const double *x, double *T,
-                       double *grad) {
+// T~ and grad T~ of path p at time step*dt at n physical points (host in / host out)
+void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *x, double *T, double *grad) {
   if (n <= 0) return;
   const int64_t stride = (n + 63) / 64 * 64;
   std::vector<double> cx(n), cy(n), cz(n), q2(n);
@@ -998,21 +1063,59 @@ void source_field_host(sa_iga *h, const PathState &P, int64_t step, int64_t n, c
   std::vector<int8_t> roles(n, (int8_t)SA_FACE_SOURCE_PLANE);
   int8_t *drole = tb.up(roles, h->stream);
   double *dT = tb.alloc<double>(stride), *dg = tb.alloc<double>(3 * stride), *dld = tb.alloc<double>(stride);
-  sum_at_points(h, P, step, n, stride, dx, dy, dz, dq, fx, fy, fz, fq, drole, dx, dy, dz, dx, dT, dg, dld);
+  sa::PathTab tab{};
+  tab.count = 1;
+  tab.path[0] = p;
+  tab.src0[0] = h->paths[p].src0;
+  active_counts(h, h->paths[p], step, tab.n_act[0], tab.n_far[0]);
+  const sa_stats keep = h->stats;
+  sum_points(h, tab, step, n, stride, dx, dy, dz, dq, fx, fy, fz, fq, drole, dx, dy, dz, dx, true, stride, dT, dg,
+             dld);
+  h->stats.pairs = keep.pairs;
+  h->stats.pairs_near = keep.pairs_near;
   hip_check(hipMemcpyAsync(T, dT, n * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
   if (grad)
     for (int c = 0; c < 3; ++c)
       hip_check(hipMemcpyAsync(grad + c * n, dg + c * stride, n * sizeof(double), hipMemcpyDeviceToHost, h->stream),
                 "download");
   hip_check(hipStreamSynchronize(h->stream), "sync");
+  hip_check(hipGetLastError(), "kernel launch");
 }
 
-PathState &path_of(sa_iga *h, int32_t path) {
+// T~, grad T~ at the boundary points of every path at its current step
+// (after a checkpoint load; the step's load densities are recomputed too)
+void refresh_boundary_fields(sa_iga *h) {
+  std::map<int64_t, std::vector<int>> groups;
+  for (int p = 0; p < (int)h->paths.size(); ++p) groups[h->paths[p].step].push_back(p);
+  const sa_stats keep = h->stats;
+  for (auto &g : groups) {
+    const auto &ids = g.second;
+    for (size_t i = 0; i < ids.size(); i += sa::kMaxBatch) {
+      sa::PathTab tab{};
+      const size_t e = std::min(ids.size(), i + (size_t)sa::kMaxBatch);
+      tab.count = (int)(e - i);
+      for (size_t k = i; k < e; ++k) {
+        const int s = (int)(k - i), p = ids[k];
+        tab.path[s] = p;
+        tab.src0[s] = h->paths[p].src0;
+        active_counts(h, h->paths[p], g.first, tab.n_act[s], tab.n_far[s]);
+      }
+      sum_points(h, tab, g.first, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2,
+                 h->role, h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD);
+    }
+  }
+  hip_check(hipGetLastError(), "kernel launch");
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+  collect_timing(h);
+  h->stats = keep;                 // not a step: counters and stage times unchanged
+}
+
+int path_index(sa_iga *h, int32_t path) {
   if (path < 0 || path >= (int32_t)h->paths.size()) throw sa::SaError{SA_ERANGE, "path index out of range"};
-  return h->paths[path];
+  return path;
 }
 
-constexpr uint64_t kMagic = 0x5341494741434b31ull;  // checkpoint tag
+constexpr uint64_t kMagic = 0x5341494741434b32ull;  // checkpoint tag
 
 }  // namespace
 
@@ -1056,16 +1159,14 @@ int sa_iga_step(sa_iga *h, int32_t n_steps) {
     if (n_steps < 0) throw sa::SaError{SA_EINVAL, "n_steps must be >= 0"};
     if (h->sticky) throw sa::SaError{SA_ESTATE, "object is in an error state (load a checkpoint)"};
     try {
-      for (int32_t s = 0; s < n_steps; ++s)
-        for (auto &P : h->paths)
-          if (P.step < P.n_steps) step_path(h, P);
+      for (int32_t s = 0; s < n_steps; ++s) step_all(h);
       check_statuses(h);
       hip_check(hipStreamSynchronize(h->stream), "sync");
       collect_timing(h);
     } catch (const sa::SaError &e) {
       if (e.code == SA_ENOCONV) h->sticky = 1;
       (void)hipStreamSynchronize(h->stream);
-      h->status_used = 0;
+      h->status_kind.clear();
       collect_timing(h);
       throw;
     }
@@ -1076,7 +1177,7 @@ int sa_iga_step(sa_iga *h, int32_t n_steps) {
 int sa_iga_get_step(sa_iga *h, int32_t path, int64_t *step) {
   return guarded([&]() -> int {
     if (!h || !step) throw sa::SaError{SA_EINVAL, "NULL argument"};
-    *step = path_of(h, path).step;
+    *step = h->paths[path_index(h, path)].step;
     return SA_OK;
   });
 }
@@ -1086,8 +1187,7 @@ int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n, c
   return guarded([&]() -> int {
     if (!h || (n > 0 && (!x || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
     if (n < 0 || step < 0) throw sa::SaError{SA_EINVAL, "negative size or step"};
-    PathState &P = path_of(h, path);
-    source_field_host(h, P, step, n, x, T, grad);
+    source_field_host(h, path_index(h, path), step, n, x, T, grad);
     return SA_OK;
   });
 }
@@ -1096,17 +1196,17 @@ int sa_iga_eval_temperature(sa_iga *h, int32_t path, int64_t n, const double *xi
   return guarded([&]() -> int {
     if (!h || (n > 0 && (!xi || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
     if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
-    PathState &P = path_of(h, path);
+    const int p = path_index(h, path);
     if (n == 0) return SA_OK;
     EvalTables t = eval_tables(h->m.P, n, xi);
     std::vector<double> Tt(n), Gt(3 * n);
-    source_field_host(h, P, P.step, n, t.x.data(), Tt.data(), Gt.data());
+    source_field_host(h, p, h->paths[p].step, n, t.x.data(), Tt.data(), Gt.data());
     TempBufs tb;
     int64_t *rp = tb.up(t.rowptr, h->stream);
     int32_t *cl = tb.up(t.col, h->stream);
     double *vals[4] = {tb.up(t.R, h->stream), tb.up(t.gx, h->stream), tb.up(t.gy, h->stream), tb.up(t.gz, h->stream)};
     double *out = tb.alloc<double>(4 * n);
-    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(h->stream, n, rp, cl, vals[k], P.v, out + k * n);
+    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(h->stream, n, rp, cl, vals[k], path_v(h, p), out + k * n);
     std::vector<double> hv(4 * n);
     hip_check(hipMemcpyAsync(hv.data(), out, 4 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
     hip_check(hipStreamSynchronize(h->stream), "sync");
@@ -1122,16 +1222,17 @@ int sa_iga_eval_temperature(sa_iga *h, int32_t path, int64_t n, const double *xi
 int sa_iga_get_boundary_fields(sa_iga *h, int32_t path, double *T_gp, double *grad_gp, double *F, double *du) {
   return guarded([&]() -> int {
     if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
-    PathState &P = path_of(h, path);
-    const int64_t nq = h->nq, nd = h->m.P.ndof;
-    if (T_gp) hip_check(hipMemcpyAsync(T_gp, P.T, nq * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+    const int p = path_index(h, path);
+    const int64_t nq = h->nq, nd = h->nd;
+    if (T_gp) hip_check(hipMemcpyAsync(T_gp, path_T(h, p), nq * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                        "download");
     if (grad_gp)
       for (int c = 0; c < 3; ++c)
-        hip_check(hipMemcpyAsync(grad_gp + c * nq, P.g + c * h->stride, nq * sizeof(double), hipMemcpyDeviceToHost,
-                                 h->stream),
+        hip_check(hipMemcpyAsync(grad_gp + c * nq, path_G(h, p) + c * h->stride, nq * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream),
                   "download");
-    if (F) hip_check(hipMemcpyAsync(F, P.F, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
-    if (du) hip_check(hipMemcpyAsync(du, P.v, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+    if (F) hip_check(hipMemcpyAsync(F, path_F(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+    if (du) hip_check(hipMemcpyAsync(du, path_v(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
     hip_check(hipStreamSynchronize(h->stream), "sync");
     return SA_OK;
   });
@@ -1163,7 +1264,7 @@ int sa_iga_get_info(sa_iga *h, sa_info *info) {
     if (!h || !info) throw sa::SaError{SA_EINVAL, "NULL argument"};
     std::memset(info, 0, sizeof(*info));
     for (int d = 0; d < 3; ++d) info->n_ctrl[d] = h->m.P.n[d];
-    info->n_dof = h->m.P.ndof;
+    info->n_dof = h->nd;
     info->n_bpts = h->nq;
     for (int f = 0; f < 7; ++f) info->face_offset[f] = h->m.bt.face_off[f];
     info->n_paths = (int32_t)h->paths.size();
@@ -1192,7 +1293,7 @@ int sa_iga_reset_stats(sa_iga *h) {
 int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
   return guarded([&]() -> int {
     if (!h || !len) throw sa::SaError{SA_EINVAL, "NULL argument"};
-    const int64_t nd = h->m.P.ndof, nDa = std::max<int64_t>(h->nD, 1);
+    const int64_t nd = h->nd, nDa = h->nDa;
     const size_t per = sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
     const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
     if (!buf) {
@@ -1204,14 +1305,14 @@ int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
     uint64_t hdr[4] = {kMagic, (uint64_t)h->paths.size(), (uint64_t)nd, (uint64_t)nDa};
     std::memcpy(b, hdr, sizeof(hdr));
     b += sizeof(hdr);
-    for (auto &P : h->paths) {
-      std::memcpy(b, &P.step, sizeof(int64_t));
+    for (int p = 0; p < (int)h->paths.size(); ++p) {
+      std::memcpy(b, &h->paths[p].step, sizeof(int64_t));
       b += sizeof(int64_t);
-      hip_check(hipMemcpyAsync(b, P.v, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+      hip_check(hipMemcpyAsync(b, path_v(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
       b += nd * sizeof(double);
-      hip_check(hipMemcpyAsync(b, P.F, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+      hip_check(hipMemcpyAsync(b, path_F(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
       b += nd * sizeof(double);
-      hip_check(hipMemcpyAsync(b, P.vD, nDa * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+      hip_check(hipMemcpyAsync(b, path_vD(h, p), nDa * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
       b += nDa * sizeof(double);
     }
     hip_check(hipStreamSynchronize(h->stream), "sync");
@@ -1223,7 +1324,7 @@ int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
 int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
   return guarded([&]() -> int {
     if (!h || !buf) throw sa::SaError{SA_EINVAL, "NULL argument"};
-    const int64_t nd = h->m.P.ndof, nDa = std::max<int64_t>(h->nD, 1);
+    const int64_t nd = h->nd, nDa = h->nDa;
     const size_t per = sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
     const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
     if (len < need) throw sa::SaError{SA_EINVAL, "checkpoint too short"};
@@ -1240,17 +1341,17 @@ int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
       b += sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
     }
     b = (const char *)buf + sizeof(hdr);
-    for (auto &P : h->paths) {
-      std::memcpy(&P.step, b, sizeof(int64_t));
+    for (int p = 0; p < (int)h->paths.size(); ++p) {
+      std::memcpy(&h->paths[p].step, b, sizeof(int64_t));
       b += sizeof(int64_t);
-      hip_check(hipMemcpyAsync(P.v, b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
+      hip_check(hipMemcpyAsync(path_v(h, p), b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
       b += nd * sizeof(double);
-      hip_check(hipMemcpyAsync(P.F, b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
+      hip_check(hipMemcpyAsync(path_F(h, p), b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
       b += nd * sizeof(double);
-      hip_check(hipMemcpyAsync(P.vD, b, nDa * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
+      hip_check(hipMemcpyAsync(path_vD(h, p), b, nDa * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
       b += nDa * sizeof(double);
     }
-    hip_check(hipStreamSynchronize(h->stream), "sync");
+    refresh_boundary_fields(h);
     h->sticky = 0;
     return SA_OK;
   });

@@ -16,6 +16,12 @@ struct SolveStatus {
   double relres2;    // |r|^2 / |b|^2 at exit
 };
 
+// paths of one batched launch: slot s works on path path[s]
+struct SlotMap {
+  int count;
+  int32_t path[kMaxBatch];
+};
+
 // load-vector gather over the non-empty rows of the transpose CSR
 struct GatherRows {
   int64_t nrows;
@@ -24,8 +30,9 @@ struct GatherRows {
   const int32_t *col;        // boundary point
   const double *val;         // R_A(x_q)
 };
-void launch_gather_rows(hipStream_t st, const GatherRows &g, const double *ld, double *F, int64_t ncopy,
-                        const double *v, double *x);
+// per slot (path p): F[p*fs + rows[r]] = sum val * ld[p*ls + col]; x[p*fs + i] = v[p*fs + i], i < ncopy
+void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, const double *ld, int64_t ls,
+                        double *F, int64_t fs, int64_t ncopy, const double *v, double *x);
 
 // Dirichlet projection solved by one workgroup
 struct DirArgs {
@@ -36,20 +43,23 @@ struct DirArgs {
   int fd;                                     // 1: Kronecker FD, 0: Jacobi
   int na, nb;
   const double *Ua, *Ub, *inv, *jacobi;
-  double *vD;                                 // in: warm start, out: values
+  double *vD;                                 // in: warm start, out: values (stride nD per path)
   const int64_t *dofs;                        // DOF of each Dirichlet value
-  double *xfull;                              // theta-step iterate: receives the values
+  double *xfull;                              // theta-step iterates: receive the values
+  int64_t xs;                                 // stride of xfull per path
   double rtol2;
   int max_iter;
   SolveStatus *status;
 };
 bool dirichlet_fits(int64_t nD);
 size_t dirichlet_lds(const DirArgs &a);
-void launch_dirichlet(hipStream_t st, const DirArgs &a);
+void launch_dirichlet(hipStream_t st, const SlotMap &sm, const DirArgs &a);
 
 // banded stencil product (theta-step residual or A p)
 struct SlArgs {
   int64_t nrow;
+  int64_t vs;             // stride per path of x, v, F1, F0, out
+  int np;                 // partials per path (= stencil_blocks(nrow))
   int n0, n1, hw1, hw2;
   const double *A, *B;
   const uint8_t *mask;
@@ -59,19 +69,23 @@ struct SlArgs {
   double theta;
   double *out;            // r (theta) or q (apply)
   double *part;           // |rhs|^2 (theta) or p.q (apply), one per block
-  const PcgScalars *sc;   // apply: skip when done
-  PcgScalars *sc_w;       // theta: resets the done flag
+  const PcgScalars *sc;   // apply: skip when done (one per path)
+  PcgScalars *sc_w;       // theta: resets the done flags (one per path)
 };
 int stencil_blocks(int64_t nrow);
-void launch_stencil_sl(hipStream_t st, const SlArgs &a, int hw0, bool theta);
+void launch_stencil_sl(hipStream_t st, const SlotMap &sm, const SlArgs &a, int hw0, bool theta);
 
 // fused PCG with the fast-diagonalisation preconditioner on the free box
+// Per-path data of path p: x, r, z, p, q at + p*vs; t at + p*ts; partials
+// part_rz at + p*2*np_rz, part_rr at + p*np_rz, part_pq at + p*np_pq,
+// part_b at + p*np_b; sc at + p; status at + slot; scatter_out at + p*sos.
 struct FusedPcg {
   int n[3], lo[3], m[3];
   const double *U0, *U1, *U2, *inv;
   double *x, *r, *z, *p, *q, *t;
-  double *part_rz;        // [2][np_rz]
-  double *part_rr;        // [np_rz]
+  int64_t vs, ts;
+  double *part_rz;        // [2][np_rz] per path
+  double *part_rr;        // [np_rz] per path
   const double *part_pq;  int np_pq;
   const double *part_b;   int np_b;
   int np_rz;              // = m[1] m[2] (one partial per x-fiber)
@@ -80,9 +94,10 @@ struct FusedPcg {
   SolveStatus *status;
   const int64_t *scatter_idx;   // optional: scatter_out[scatter_idx[g]] = z[g]
   double *scatter_out;
+  int64_t sos;
 };
 bool fused_fits(const int m[3]);
-void launch_fd_pass(hipStream_t st, const FusedPcg &f, int k, bool first, bool update);
-void launch_pcg_dir(hipStream_t st, const FusedPcg &f, int k);
+void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update);
+void launch_pcg_dir(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k);
 
 }  // namespace sa

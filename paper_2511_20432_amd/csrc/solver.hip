@@ -59,11 +59,14 @@ __device__ __forceinline__ double reduce_n(const double *part, int n, double *sh
 // ---------------------------------------------------------------------------
 // load vector: 16 lanes per non-empty row
 // ---------------------------------------------------------------------------
-__global__ void k_gather_rows(int64_t nrows, const int32_t *__restrict__ rows,
+__global__ void k_gather_rows(SlotMap sm, int64_t nrows, const int32_t *__restrict__ rows,
                               const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                              const double *__restrict__ val, const double *__restrict__ ld,
-                              double *__restrict__ F, int64_t ncopy, const double *__restrict__ v,
-                              double *__restrict__ x) {
+                              const double *__restrict__ val, const double *__restrict__ ldb, int64_t ls,
+                              double *__restrict__ Fb, int64_t fs, int64_t ncopy, const double *__restrict__ vb,
+                              double *__restrict__ xb) {
+  const int64_t pth = sm.path[blockIdx.y];
+  const double *ld = ldb + pth * ls;
+  double *F = Fb + pth * fs;
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int sub = threadIdx.x & 15;
   const int64_t r = gt >> 4;
@@ -73,18 +76,23 @@ __global__ void k_gather_rows(int64_t nrows, const int32_t *__restrict__ rows,
   }
   for (int off = 8; off > 0; off >>= 1) s += __shfl_down(s, off, 16);
   if (r < nrows && sub == 0) F[rows[r]] = s;
-  for (int64_t i = gt; i < ncopy; i += (int64_t)gridDim.x * blockDim.x) x[i] = v[i];
+  if (ncopy > 0) {
+    const double *v = vb + pth * fs;
+    double *x = xb + pth * fs;
+    for (int64_t i = gt; i < ncopy; i += (int64_t)gridDim.x * blockDim.x) x[i] = v[i];
+  }
 }
 
-void launch_gather_rows(hipStream_t st, const GatherRows &g, const double *ld, double *F, int64_t ncopy,
-                        const double *v, double *x) {
+void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, const double *ld, int64_t ls,
+                        double *F, int64_t fs, int64_t ncopy, const double *v, double *x) {
+  if (sm.count <= 0) return;
   int64_t threads = g.nrows * 16;
   int64_t blocks = (threads + kB - 1) / kB;
   int64_t cb = (ncopy + kB - 1) / kB;
   if (cb > blocks) blocks = cb;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks), dim3(kB), 0, st, g.nrows, g.rows, g.rowptr, g.col,
-                     g.val, ld, F, ncopy, v, x);
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks, (unsigned)sm.count), dim3(kB), 0, st, sm, g.nrows,
+                     g.rows, g.rowptr, g.col, g.val, ld, ls, F, fs, ncopy, v, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,10 +140,17 @@ __device__ void dir_precond(const DirArgs &a, const double *Ua, const double *Ub
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kDirThreads) void k_dirichlet(DirArgs a) {
+__global__ __launch_bounds__(kDirThreads) void k_dirichlet(SlotMap sm, DirArgs a) {
   extern __shared__ double lds[];
   __shared__ double sh[16];
   const int n = a.nD;
+  {
+    const int64_t pth = sm.path[blockIdx.x];
+    a.b += pth * n;
+    a.vD += pth * n;
+    a.xfull += pth * a.xs;
+    if (a.status) a.status += blockIdx.x;
+  }
   double *r = lds, *z = lds + n, *p = lds + 2 * n, *t1 = lds + 3 * n, *t2 = lds + 4 * n;
   // the preconditioner's eigenvector matrices live in LDS when they fit
   const double *Ua = a.Ua, *Ub = a.Ub;
@@ -226,19 +241,35 @@ size_t dirichlet_lds(const DirArgs &a) {
   return n * sizeof(double);
 }
 
-void launch_dirichlet(hipStream_t st, const DirArgs &a) {
-  hipLaunchKernelGGL(k_dirichlet, dim3(1), dim3(kDirThreads), dirichlet_lds(a), st, a);
+void launch_dirichlet(hipStream_t st, const SlotMap &sm, const DirArgs &a) {
+  if (sm.count <= 0) return;
+  hipLaunchKernelGGL(k_dirichlet, dim3((unsigned)sm.count), dim3(kDirThreads), dirichlet_lds(a), st, sm, a);
 }
 
 // ---------------------------------------------------------------------------
 // banded stencil products: 64 rows per block, one wave per z-offset
 // ---------------------------------------------------------------------------
 template <int HW0, bool THETA>
-__global__ void k_stencil_sl(SlArgs a) {
+__global__ void k_stencil_sl(SlotMap sm, SlArgs a) {
   extern __shared__ double shr[];          // [waves][64]
   __shared__ double sh[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nw = (int)(blockDim.x >> 6);
+  {
+    const int64_t pth = sm.path[blockIdx.y];
+    const int64_t off = pth * a.vs;
+    a.x += off;
+    a.out += off;
+    a.part += pth * a.np;
+    if (THETA) {
+      a.v += off;
+      a.F1 += off;
+      a.F0 += off;
+      if (a.sc_w) a.sc_w += pth;
+    } else if (a.sc) {
+      a.sc += pth;
+    }
+  }
   if (!THETA && a.sc && a.sc->done) return;
   const int64_t row = (int64_t)blockIdx.x * 64 + lane;
   const int64_t nrow = a.nrow, nm1 = nrow - 1;
@@ -296,14 +327,15 @@ __global__ void k_stencil_sl(SlArgs a) {
 
 int stencil_blocks(int64_t nrow) { return (int)((nrow + 63) / 64); }
 
-void launch_stencil_sl(hipStream_t st, const SlArgs &a, int hw0, bool theta) {
+void launch_stencil_sl(hipStream_t st, const SlotMap &sm, const SlArgs &a, int hw0, bool theta) {
+  if (sm.count <= 0) return;
   const int waves = 2 * a.hw2 + 1;
-  dim3 g((unsigned)stencil_blocks(a.nrow)), b(64 * waves);
+  dim3 g((unsigned)stencil_blocks(a.nrow), (unsigned)sm.count), b(64 * waves);
   const size_t lds = (size_t)(theta ? 2 : 1) * waves * 64 * sizeof(double);
 #define SA_SL_CASE(H)                                                                             \
   case H:                                                                                         \
-    if (theta) hipLaunchKernelGGL((k_stencil_sl<H, true>), g, b, lds, st, a);                     \
-    else hipLaunchKernelGGL((k_stencil_sl<H, false>), g, b, lds, st, a);                          \
+    if (theta) hipLaunchKernelGGL((k_stencil_sl<H, true>), g, b, lds, st, sm, a);                 \
+    else hipLaunchKernelGGL((k_stencil_sl<H, false>), g, b, lds, st, sm, a);                      \
     break;
   switch (hw0) {
     SA_SL_CASE(1)
@@ -319,6 +351,26 @@ void launch_stencil_sl(hipStream_t st, const SlArgs &a, int hw0, bool theta) {
 // ---------------------------------------------------------------------------
 // fast-diagonalisation solve on the box of free DOFs, fused with the PCG update
 // ---------------------------------------------------------------------------
+// the data of the path handled by launch slot `slot`
+__device__ __forceinline__ FusedPcg at_path(const FusedPcg &f, const SlotMap &sm, int slot) {
+  FusedPcg g = f;
+  const int64_t p = sm.path[slot];
+  if (g.x) g.x += p * f.vs;
+  if (g.r) g.r += p * f.vs;
+  if (g.z) g.z += p * f.vs;
+  if (g.p) g.p += p * f.vs;
+  if (g.q) g.q += p * f.vs;
+  if (g.t) g.t += p * f.ts;
+  if (g.part_rz) g.part_rz += p * 2 * f.np_rz;
+  if (g.part_rr) g.part_rr += p * f.np_rz;
+  if (g.part_pq) g.part_pq += p * f.np_pq;
+  if (g.part_b) g.part_b += p * f.np_b;
+  g.sc += p;
+  if (g.status) g.status += slot;
+  if (g.scatter_out) g.scatter_out += p * f.sos;
+  return g;
+}
+
 __device__ __forceinline__ int64_t full_index(const FusedPcg &f, int j0, int j1, int j2) {
   return (int64_t)(j0 + f.lo[0]) + (int64_t)f.n[0] * ((j1 + f.lo[1]) + (int64_t)f.n[1] * (j2 + f.lo[2]));
 }
@@ -331,9 +383,10 @@ __device__ __forceinline__ int64_t full_index(const FusedPcg &f, int j0, int j1,
 // t is stored plane-major: t[j0 * (m1 m2) + k2 * m1 + k1].
 constexpr int kFib = 64;
 
-__global__ __launch_bounds__(kFib) void k_fd_xfwd(FusedPcg f, int k, int first) {
+__global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k, int first) {
   __shared__ double fib[256];
   __shared__ double sh[16];
+  const FusedPcg f = at_path(f0, sm, blockIdx.y);
   if (f.sc->done) return;
   const int m0 = f.m[0], m1 = f.m[1];
   const int64_t P = (int64_t)m1 * f.m[2];
@@ -345,7 +398,7 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(FusedPcg f, int k, int first) 
     const double pq = reduce_n(f.part_pq, f.np_pq, sh);
     if (rz == 0.0 || !(pq > 0.0)) {
       // zero residual (nothing to solve) or breakdown: record the exit here
-      if (b == 0 && threadIdx.x == 0) {
+      if (b == 0 && threadIdx.x == 0) {   // first fiber block of this path
         const int d = (rz == 0.0) ? 1 : 2;
         f.sc->done = d;
         if (f.status) {
@@ -379,8 +432,9 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(FusedPcg f, int k, int first) 
   }
 }
 
-__global__ void k_fd_plane(FusedPcg f) {
+__global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
   extern __shared__ double lds[];
+  const FusedPcg f = at_path(f0, sm, blockIdx.y);
   if (f.sc->done) return;
   const int m0 = f.m[0], m1 = f.m[1], m2 = f.m[2];
   const int P = m1 * m2;
@@ -418,9 +472,10 @@ __global__ void k_fd_plane(FusedPcg f) {
   }
 }
 
-__global__ __launch_bounds__(kFib) void k_fd_xbwd(FusedPcg f, int slot, int first) {
+__global__ __launch_bounds__(kFib) void k_fd_xbwd(SlotMap sm, FusedPcg f0, int slot, int first) {
   __shared__ double fib[256];
   __shared__ double sh[16];
+  const FusedPcg f = at_path(f0, sm, blockIdx.y);
   if (f.sc->done) return;
   const int m0 = f.m[0], m1 = f.m[1];
   const int64_t P = (int64_t)m1 * f.m[2];
@@ -445,8 +500,9 @@ __global__ __launch_bounds__(kFib) void k_fd_xbwd(FusedPcg f, int slot, int firs
 }
 
 // convergence test on r.r; p = z + beta p on the box
-__global__ void k_pcg_dir(FusedPcg f, int k) {
+__global__ void k_pcg_dir(SlotMap sm, FusedPcg f0, int k) {
   __shared__ double sh[16];
+  const FusedPcg f = at_path(f0, sm, blockIdx.y);
   if (f.sc->done) return;
   const double rr = reduce_n(f.part_rr, f.np_rz, sh);
   const double bb = reduce_n(f.part_b, f.np_b, sh);
@@ -479,20 +535,22 @@ __global__ void k_pcg_dir(FusedPcg f, int k) {
 
 bool fused_fits(const int m[3]) { return m[0] <= 256 && (int64_t)m[1] * m[2] <= 4096; }
 
-void launch_fd_pass(hipStream_t st, const FusedPcg &f, int k, bool first, bool update) {
+void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update) {
+  if (sm.count <= 0) return;
   const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
-  hipLaunchKernelGGL(k_fd_xfwd, dim3(nfib), dim3(kFib), 0, st, f, k, update ? 0 : 1);
+  hipLaunchKernelGGL(k_fd_xfwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, k, update ? 0 : 1);
   const size_t lds = (size_t)2 * f.m[1] * f.m[2] * sizeof(double);
-  hipLaunchKernelGGL(k_fd_plane, dim3(f.m[0]), dim3(kB), lds, st, f);
+  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(kB), lds, st, sm, f);
   const int slot = first ? 0 : ((k + 1) & 1);
-  hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib), dim3(kFib), 0, st, f, slot, first ? 1 : 0);
+  hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, slot, first ? 1 : 0);
 }
 
-void launch_pcg_dir(hipStream_t st, const FusedPcg &f, int k) {
+void launch_pcg_dir(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k) {
+  if (sm.count <= 0) return;
   const int64_t nbox = (int64_t)f.m[0] * f.m[1] * f.m[2];
   int64_t blocks = (nbox + kB - 1) / kB;
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)blocks), dim3(kB), 0, st, f, k);
+  hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)blocks, (unsigned)sm.count), dim3(kB), 0, st, sm, f, k);
 }
 
 }  // namespace sa

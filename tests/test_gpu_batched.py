@@ -1,0 +1,123 @@
+"""Batched form: many independent scan strategies of uneven length on one
+patch, advanced together by the HIP path, each checked against its own FP64
+oracle run (or against a single-path HIP run where an oracle run per path
+would be too slow)."""
+import numpy as np
+import pytest
+
+from oracle import solver
+from paper_2511_20432_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _model(patch, scan, **kw):
+    from paper_2511_20432_amd import sa_iga
+    return sa_iga.Model(patch, W.MAT_CFG, scan, kw.pop("options", None), **kw)
+
+
+def _track(i, n_s=5, dt=1e-5):
+    """Short straight track i on the small block: direction, power and speed vary with i."""
+    rng = np.random.default_rng(100 + i)
+    ang = rng.uniform(0, 2 * np.pi)
+    c = np.array([0.5e-3, 0.3e-3, 0.5e-3])
+    d = np.array([np.cos(ang), np.sin(ang) * 0.6, 0.0]) * 0.35e-3
+    seg = W.Segment("line", float(rng.uniform(40, 120)), float(rng.uniform(0.6, 1.5)), p0=c - d, p1=c + d)
+    return W.sources_from_segments([seg], dt / n_s)
+
+
+def _check_path(gm, scan, p, n):
+    om = solver.Model(W.small_block(), W.MAT_CFG, scan, path=p)
+    om.advance(n)
+    T, G, F, du = gm.boundary_fields(p)
+    Tr, Gr = om.boundary_field(n)
+    errs = {"T": rel(T, Tr), "grad": rel(G, Gr)}
+    if np.abs(om.F).max() > 0:
+        errs["F"] = rel(F, om.F)
+        errs["du"] = rel(du, om.w)
+    else:
+        errs["F"] = float(np.abs(F).max())
+        errs["du"] = float(np.abs(du).max())
+    print(f"path {p} step {n}", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= TOL64, errs
+
+
+def test_uneven_paths_match_oracle():
+    """Five strategies, lengths 3..14 steps, one with no sources: paths drop
+    out of the lockstep batch as they finish."""
+    tracks = [_track(i) for i in range(4)]
+    empty = (np.zeros((0, 3)), np.zeros(0, np.int64), np.zeros(0))
+    scan = W.make_scan([tracks[0], tracks[1], empty, tracks[2], tracks[3]], 1e-5, 5,
+                       n_steps=[3, 9, 5, 14, 12])
+    gm = _model(W.small_block(), scan)
+    gm.step(4)
+    assert [gm.get_step(p) for p in range(5)] == [3, 4, 4, 4, 4]
+    _check_path(gm, scan, 0, 3)
+    gm.step(20)
+    assert [gm.get_step(p) for p in range(5)] == [3, 9, 5, 14, 12]
+    for p, n in ((1, 9), (2, 5), (3, 14), (4, 12)):
+        _check_path(gm, scan, p, n)
+
+
+def test_batched_equals_single_path_runs():
+    """More paths than one launch holds (two lockstep groups), each path's
+    result matches a separate one-path HIP run of the same strategy."""
+    n_paths = 67
+    tracks = [_track(i) for i in range(n_paths)]
+    steps = [2 + (i % 3) for i in range(n_paths)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=steps)
+    gm = _model(W.small_block(), scan)
+    gm.step(5)
+    st = gm.stats()
+    assert st["steps"] == sum(steps)
+    for p in (0, 1, 63, 64, 65, 66):
+        one = _model(W.small_block(), scan.path(p))
+        one.step(steps[p])
+        for a, b, name in zip(gm.boundary_fields(p), one.boundary_fields(), ("T", "grad", "F", "du")):
+            # the chunking of the source history depends on the batch size
+            assert rel(a, b) <= 1e-12, (p, name, rel(a, b))
+    _check_path(gm, scan, 65, steps[65])
+
+
+def test_batched_fp32_far_within_005K():
+    """FP32 far field with per-path far/near splits in one launch."""
+    tracks = [_track(i) for i in range(3)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=[40, 25, 33])
+    opts = W.Options(precision=W.PRECISION_FP32_FAR, tau_near=5e-5)
+    gm = _model(W.small_block(), scan, options=opts)
+    gm.step(40)
+    st = gm.stats()
+    assert 0 < st["pairs_near"] < st["pairs"]
+    for p, n in ((0, 40), (1, 25), (2, 33)):
+        om = solver.Model(W.small_block(), W.MAT_CFG, scan, path=p)
+        om.advance(n)
+        R = om.bt["R"]
+        T, G, F, du = gm.boundary_fields(p)
+        Tr, Gr = om.boundary_field(n)
+        err = np.abs((T + R @ du) - (Tr + R @ om.w)).max()
+        print(f"fp32-far path {p}: max |T - T_ref| = {err:.3e} K", flush=True)
+        assert err <= 0.05
+
+
+def test_batched_checkpoint_resume_bitwise():
+    tracks = [_track(i) for i in range(3)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=[6, 11, 9])
+    a = _model(W.small_block(), scan)
+    b = _model(W.small_block(), scan)
+    a.step(7)                       # path 0 has finished; the others are mid-scan
+    blob = a.save()
+    a.step(6)
+    b.step(3)
+    b.load(blob)
+    b.step(6)
+    for p in range(3):
+        assert a.get_step(p) == b.get_step(p)
+        for x, y in zip(a.boundary_fields(p), b.boundary_fields(p)):
+            assert np.array_equal(x, y)
