@@ -78,9 +78,63 @@ def run_form(w, precision, warmup, steps, timing=True):
     t0 = time.perf_counter()
     m = sa_iga.Model(w.patch, w.material, w.scan, opts, timing=1 if timing else 0)
     setup_s = time.perf_counter() - t0
+    tune = m.autotune(reps=3)
     n_total = int(w.scan.n_steps[0])
     dt, st = _timed_run(m, warmup, steps, n_total)
+    st["autotune"] = tune
     return m, dt, st, setup_s
+
+
+def jump_to_steps(model, steps):
+    """Put path p at step steps[p] with a zeroed state (u = T_c, F = 0, no
+    source field yet): the steps timed from there do the full work of a
+    mid-scan step (every switched-on source of every path is summed).  Uses
+    the checkpoint layout: a 32-byte header, then per path its step (int64)
+    followed by its arrays."""
+    blob = bytearray(model.save())
+    per = (len(blob) - 32) // len(steps)
+    for p, st in enumerate(steps):
+        off = 32 + p * per
+        blob[off:off + 8] = int(st).to_bytes(8, "little", signed=True)
+    model.load(bytes(blob))
+
+
+def run_batched(window, form, seed=0):
+    """The batch of 128 scan strategies on the raster block: every strategy
+    starts the timed window at a seeded step in [0, L - window)."""
+    import torch
+    from paper_2511_20432_amd import sa_iga
+    from paper_2511_20432_amd import workloads as W
+    w = W.cfg4(seed=seed)
+    prec = {"fp32far": W.PRECISION_FP32_FAR, "fp64": W.PRECISION_FP64}[form]
+    t0 = time.perf_counter()
+    m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=prec, tau_near=2e-4), timing=1)
+    setup_s = time.perf_counter() - t0
+    L = w.scan.n_steps.astype(np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    start = (rng.random(len(L)) * np.maximum(L - window, 0)).astype(np.int64)
+    jump_to_steps(m, start)
+    tune = m.autotune(reps=2)
+    m.step(2)                               # warm-up
+    m.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(window)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = m.stats()
+    sum_ms = st["stage_ms"]["sum"]
+    return {
+        "workload": f"{w.scan.n_paths} strategies on the raster block (64x32x16 cubic, 64512 boundary points), "
+                    f"lengths U[500,4000] steps (sum {int(L.sum())}), {len(w.scan.tick)} sources, seed {seed}",
+        "form": form, "window_steps": window,
+        "start": "each strategy at a seeded step in [0, L - window) with a zeroed state; full work per step",
+        "pairs_per_s": st["pairs"] / dt, "path_steps_per_s": st["steps"] / dt,
+        "ms_per_batched_step": 1e3 * dt / window, "path_steps": st["steps"],
+        "sum_gpair_s": st["pairs"] / (sum_ms * 1e-3) / 1e9 if sum_ms > 0 else None,
+        "stage_ms_per_batched_step": {k: v / window for k, v in st["stage_ms"].items()},
+        "autotune": tune, "setup_s": setup_s,
+    }
 
 
 def cpu_baseline(w, step, n_steps=16, threads=None):
@@ -117,6 +171,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32far,fp64")
+    ap.add_argument("--batched-window", type=int, default=60,
+                    help="timed steps of the 128-strategy batch (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's sharding plan is "
@@ -129,7 +185,9 @@ def main():
 
     w = W.cfg2(seed=0)
     n_total = int(w.scan.n_steps[0])
-    steps = args.steps if args.steps is not None else max(1, n_total - args.warmup)
+    # by default the run stops one step short of the scan's end, where the
+    # forms are compared (reaching the end would restore the initial state)
+    steps = args.steps if args.steps is not None else max(1, n_total - args.warmup - 1)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {}
     models = {}
@@ -143,13 +201,14 @@ def main():
               f"sum {st['stage_ms']['sum']:.1f} ms, pcg {st['stage_ms']['pcg']:.1f} ms", file=sys.stderr, flush=True)
 
     # temperature difference between the forms at the end of the timed steps
-    max_err = None
+    max_err = err_step = None
     if "fp32far" in models and "fp64" in models:
         Ta, _, _, ua = models["fp32far"].boundary_fields()
         Tb, _, _, ub = models["fp64"].boundary_fields()
         # R_A >= 0 and sum_A R_A = 1 at every boundary point, so this bounds the
         # difference of T = T~ + sum_A R_A u_A at the points
         max_err = float(np.abs(Ta - Tb).max() + np.abs(ua - ub).max())
+        err_step = models["fp64"].get_step()
 
     main_form = "fp32far" if "fp32far" in res else forms[0]
     r = res[main_form]
@@ -177,6 +236,7 @@ def main():
                      "pairs_per_launch": st["pairs"] / launches},
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
         "setup_s": r["setup_s"],
+        "autotune": st["autotune"],
     }
     if "fp64" in res and main_form != "fp64":
         s64 = res["fp64"]["stats"]
@@ -189,6 +249,19 @@ def main():
                        / (LANE_OPS / SLOTS_FP64) if s64["stage_ms"]["sum"] > 0 else None}
         out["speedup_vs_fp64"] = t64 / r["seconds"]
         out["max_err_K_vs_fp64"] = max_err
+        out["max_err_at_step"] = err_step
+    if args.batched_window > 0:
+        out["batched"] = {}
+        for f in forms:
+            print(f"[bench] batched form {f}: {args.batched_window} steps of 128 strategies", file=sys.stderr,
+                  flush=True)
+            b = run_batched(args.batched_window, f)
+            out["batched"][f] = b
+            print(f"[bench] batched {f}: {b['pairs_per_s']:.3e} pairs/s, {b['path_steps_per_s']:.1f} path-steps/s",
+                  file=sys.stderr, flush=True)
+        if "fp32far" in out["batched"] and "fp64" in out["batched"]:
+            out["batched"]["speedup_vs_fp64"] = (out["batched"]["fp32far"]["path_steps_per_s"]
+                                                 / out["batched"]["fp64"]["path_steps_per_s"])
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle kernel sum)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, step=min(n_total - 16, 1900))

@@ -109,7 +109,7 @@ typedef struct {
   int32_t preconditioner;      /* sa_precond; default SA_PRECOND_FD */
   int32_t timing;              /* nonzero: time every stage with HIP events (sa_stats) */
   int32_t points_per_lane;     /* kernel-sum register blocking (1, 2, 4); 0 = tuned default */
-  int32_t waves_per_group;     /* kernel-sum waves per workgroup (1..16); 0 = tuned default */
+  int32_t waves_per_group;     /* kernel-sum waves per workgroup (1, 2, 4, 8); 0 = tuned default */
   int32_t chunk_sources;       /* sources per source chunk of the sum; 0 = tuned default */
 } sa_solver_options;
 
@@ -221,18 +221,33 @@ int sa_iga_apply_operator(sa_iga *h, int32_t which, const double *x, double *y);
 int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n,
                              const double *x, double *T, double *grad);
 
+/*
+ * Tile-shape tuner of the kernel sum (Eqs. 7-8).  Times the sum over the whole
+ * source history of the first min(n_paths, 64) paths (each at the end of its
+ * scan, the heaviest load it will see) for every tile shape: points per lane
+ * 1, 2, 4 x waves per workgroup 1, 2, 4, 8, `reps` launches each (reps >= 1),
+ * and keeps the fastest as the object's points_per_lane and waves_per_group.
+ * The split of the source history into chunks does not depend on the tile
+ * shape, so later results are bitwise those of any other shape.  The model
+ * state is not changed.  Outputs (each may be NULL): the chosen shape and its
+ * mean launch time in ms (0 when no path has a source: nothing to time).
+ */
+int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *waves_per_group,
+                    double *ms_per_launch);
+
 int sa_iga_get_info(sa_iga *h, sa_info *info);
 int sa_iga_get_stats(sa_iga *h, sa_stats *stats);
 int sa_iga_reset_stats(sa_iga *h);
 
 /*
- * Checkpoint of the mutable state (steps, u^n, F^n of every path).  With
+ * Checkpoint of the mutable state of every path: its step, u^n, F^n, the
+ * Dirichlet values, and T~, grad T~ at the boundary points.  With
  * buf == NULL, *len receives the size needed.  sa_iga_load restores a
- * checkpoint taken from an object built from the same inputs (SA_EINVAL if
- * the sizes differ) and clears the sticky error state.  It recomputes T~
- * and grad T~ at the boundary points of every path at its restored step, so
- * sa_iga_get_boundary_fields afterwards returns what it returned when the
- * checkpoint was taken.  Neither call changes the statistics.
+ * checkpoint taken from an object with the same patch and number of paths
+ * (SA_EINVAL if the sizes differ or a step exceeds that path's n_steps) and
+ * clears the sticky error state; sa_iga_get_boundary_fields then returns
+ * bitwise what it returned when the checkpoint was taken.  Neither call
+ * changes the statistics.
  */
 int sa_iga_save(sa_iga *h, void *buf, size_t *len);
 int sa_iga_load(sa_iga *h, const void *buf, size_t len);

@@ -164,7 +164,9 @@ void validate_inputs(const sa_patch *patch, const sa_material *mat, const sa_sca
   if (opt.points_per_lane != 0 && opt.points_per_lane != 1 && opt.points_per_lane != 2 &&
       opt.points_per_lane != 4)
     fail(SA_EINVAL, "points_per_lane must be 0, 1, 2 or 4");
-  if (opt.waves_per_group < 0 || opt.waves_per_group > 16) fail(SA_EINVAL, "waves_per_group in 0..16");
+  if (opt.waves_per_group != 0 && opt.waves_per_group != 1 && opt.waves_per_group != 2 &&
+      opt.waves_per_group != 4 && opt.waves_per_group != 8)
+    fail(SA_EINVAL, "waves_per_group must be 0, 1, 2, 4 or 8");
   if (opt.chunk_sources < 0) fail(SA_EINVAL, "chunk_sources must be >= 0");
 }
 

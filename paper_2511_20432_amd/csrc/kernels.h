@@ -18,7 +18,9 @@ constexpr int kCoefStride = 8;
 // Paths advanced by one launch (by value in the kernel arguments).  Slot s
 // holds path `path[s]`, whose sources start at row src0[s] of the global
 // source arrays; its first n_act[s] sources are switched on and the first
-// n_far[s] of those are summed in FP32.
+// n_far[s] of those are summed in FP32.  now[s] = (n+1) * sources_per_step is
+// the tick count at the end of the slot's step, so slots may sit at
+// different steps.
 constexpr int kMaxBatch = 64;
 struct PathTab {
   int count;
@@ -26,10 +28,10 @@ struct PathTab {
   int64_t src0[kMaxBatch];
   int32_t n_act[kMaxBatch];
   int32_t n_far[kMaxBatch];
+  int64_t now[kMaxBatch];
 };
 
 struct CoeffParams {
-  int64_t now;            // (n+1) * sources_per_step
   double delta;           // dt / sources_per_step
   double shift;           // r^2 / (8 alpha)
   double alpha;

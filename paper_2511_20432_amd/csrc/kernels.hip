@@ -105,7 +105,7 @@ __global__ void k_coeff(PathTab tab, const int64_t *__restrict__ tick, const dou
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= tab.n_act[slot]) return;
   const int64_t i = tab.src0[slot] + j;
-  const double D = (double)(cp.now - tick[i]) * cp.delta + cp.shift;
+  const double D = (double)(tab.now[slot] - tick[i]) * cp.delta + cp.shift;
   const double c = -1.0 / (4.0 * cp.alpha * D);
   const double x = sx[i], y = sy[i], z = sz[i];
   const double amp = cp.scale * E[i] / (cp.rc * pow(4.0 * M_PI * cp.alpha * D, 1.5));

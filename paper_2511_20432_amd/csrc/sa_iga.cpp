@@ -229,15 +229,19 @@ void collect_timing(sa_iga *h) {
 
 // ---- kernel sum --------------------------------------------------------------
 // chunking of the source history: enough workgroups to fill the chip, the
-// FP64 sources weighted by their cost
+// FP64 sources weighted by their cost.  The chunk lengths depend on the point
+// count, the batch and the source counts only, never on the tile shape
+// (points per lane, waves per group), so every tile shape gives bitwise the
+// same sums.
+constexpr int64_t kRefBlockPoints = 512;
+constexpr int64_t kTargetGroups = 2048;
+
 sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int count, int64_t max_far, int64_t max_near) {
   sa::SumPlan pl{};
   const auto &o = h->m.opt;
   pl.points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
   pl.waves = o.waves_per_group ? std::min(o.waves_per_group, 8) : 4;
   pl.nq = nq;
-  const int64_t per_blk = (int64_t)64 * pl.points_per_lane * pl.waves;
-  const int64_t n_pblk = std::max<int64_t>(1, (nq + per_blk - 1) / per_blk);
   pl.chunk_far = pl.chunk_near = 1;
   if (o.chunk_sources > 0) {
     pl.chunk_far = pl.chunk_near = o.chunk_sources;
@@ -245,8 +249,8 @@ sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int count, int64_t max_far, i
     pl.n_chunks_near = (int)((max_near + pl.chunk_near - 1) / pl.chunk_near);
     return pl;
   }
-  const int64_t target_groups = 2048;
-  const int64_t C = std::max<int64_t>(1, (target_groups + n_pblk * count - 1) / (n_pblk * count));
+  const int64_t n_ref = std::max<int64_t>(1, (nq + kRefBlockPoints - 1) / kRefBlockPoints);
+  const int64_t C = std::max<int64_t>(1, (kTargetGroups + n_ref * count - 1) / (n_ref * count));
   const double wf = (double)max_far, wn = 3.0 * (double)max_near;
   int64_t cf = 0, cn = 0;
   if (max_far > 0 && max_near > 0) {
@@ -284,8 +288,10 @@ void ensure_part(sa_iga *h, int64_t doubles) {
   h->part_cap = cap;
 }
 
-// switched-on and far-field counts of path P at the end of step `step`
-void active_counts(const sa_iga *h, const PathState &P, int64_t step, int32_t &n_act, int32_t &n_far) {
+// slot s of `tab` <- path p at the end of step `step`: its switched-on and
+// far-field source counts
+void fill_slot(const sa_iga *h, sa::PathTab &tab, int s, int p, int64_t step) {
+  const PathState &P = h->paths[p];
   const int64_t now = step * h->ns;
   auto b = h->h_tick.begin() + P.src0, e = h->h_tick.begin() + P.src1;
   const int64_t a = (int64_t)(std::upper_bound(b, e, now) - b);
@@ -294,18 +300,21 @@ void active_counts(const sa_iga *h, const PathState &P, int64_t step, int32_t &n
     const int64_t thr = now - h->tau_ticks;  // far iff tick < thr
     f = std::min<int64_t>(a, (int64_t)(std::lower_bound(b, b + a, thr) - b));
   }
-  n_act = (int32_t)a;
-  n_far = (int32_t)f;
+  tab.path[s] = p;
+  tab.src0[s] = P.src0;
+  tab.now[s] = now;
+  tab.n_act[s] = (int32_t)a;
+  tab.n_far[s] = (int32_t)f;
 }
 
-// T~ and grad T~ of the slots of `tab` at time step*dt at nq points (centred
-// arrays); outputs indexed by path (boundary tables) or by slot (query points)
-void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t step, int64_t nq, int64_t stride, const double *px,
+// T~ and grad T~ of the slots of `tab` (each at its own time) at nq points
+// (centred arrays); outputs indexed by path (boundary tables) or by slot
+// (query points)
+void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, const double *px,
                 const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
                 const float *fz, const float *fq2, const int8_t *role, const double *nx, const double *ny,
                 const double *nz, const double *wdS, bool by_slot, int64_t ostride, double *T, double *G,
                 double *ld) {
-  const int64_t now = step * h->ns;
   int64_t max_act = 0, max_far = 0, max_near = 0;
   for (int s = 0; s < tab.count; ++s) {
     max_act = std::max<int64_t>(max_act, tab.n_act[s]);
@@ -316,7 +325,7 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t step, int64_t nq, int
   }
   if (max_act > 0) {
     StageScope s(h, SA_STAGE_COEFF);
-    sa::CoeffParams cp{now, h->delta, h->shift, h->alpha, h->rc, h->m.opt.kernel_scale};
+    sa::CoeffParams cp{h->delta, h->shift, h->alpha, h->rc, h->m.opt.kernel_scale};
     sa::launch_coeff(h->stream, tab, max_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
   }
   sa::SumPlan pl = make_plan(h, nq, tab.count, max_far, max_near);
@@ -429,23 +438,25 @@ sa::SolveStatus *next_status(sa_iga *h, int n, int8_t kind) {
   return s;
 }
 
-// ---- one theta-step of a set of paths (same step, at most kMaxBatch) -------------
+// ---- one theta-step of a set of paths (at most kMaxBatch) -------------------------
+// The paths may sit at different steps; their steps share one parity, which
+// selects the state buffers (u^n, F^n read from one, u^{n+1}, F^{n+1} written
+// to the other).
 void step_batch(sa_iga *h, const std::vector<int> &pids) {
   const int count = (int)pids.size();
-  const int64_t step = h->paths[pids[0]].step, s1 = step + 1;
-  const int cur = (int)(step & 1), nxt = cur ^ 1;
+  const int cur = (int)(h->paths[pids[0]].step & 1), nxt = cur ^ 1;
   const int64_t nd = h->nd;
   sa::PathTab tab{};
   sa::SlotMap sm{};
   tab.count = sm.count = count;
   for (int s = 0; s < count; ++s) {
     const PathState &P = h->paths[pids[s]];
-    tab.path[s] = sm.path[s] = pids[s];
-    tab.src0[s] = P.src0;
-    active_counts(h, P, s1, tab.n_act[s], tab.n_far[s]);
+    if ((int)(P.step & 1) != cur) throw sa::SaError{SA_EINVAL, "internal: mixed step parity in a batch"};
+    sm.path[s] = pids[s];
+    fill_slot(h, tab, s, pids[s], P.step + 1);
   }
   // T~, grad T~ and load densities at every boundary point (Eqs. 7-8, 10-11)
-  sum_points(h, tab, s1, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
+  sum_points(h, tab, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
              h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD);
   double *Vc = h->V[cur], *Vn = h->V[nxt], *Fc = h->Fb[cur], *Fn = h->Fb[nxt];
   {
@@ -598,20 +609,23 @@ void step_batch(sa_iga *h, const std::vector<int> &pids) {
     }
   }
   hip_check(hipGetLastError(), "kernel launch");
-  for (int s = 0; s < count; ++s) h->paths[pids[s]].step = s1;
+  for (int s = 0; s < count; ++s) h->paths[pids[s]].step++;
   h->stats.steps += count;
 }
 
-// advance every live path by one step: lockstep groups of at most kMaxBatch
+// advance every live path by one step: launches of at most kMaxBatch paths,
+// grouped by the parity of their steps
 void step_all(sa_iga *h) {
-  std::map<int64_t, std::vector<int>> groups;
+  std::vector<int> ids[2];
   for (int p = 0; p < (int)h->paths.size(); ++p)
-    if (h->paths[p].step < h->paths[p].n_steps) groups[h->paths[p].step].push_back(p);
-  for (auto &g : groups) {
-    const auto &ids = g.second;
-    for (size_t i = 0; i < ids.size(); i += sa::kMaxBatch) {
-      std::vector<int> b(ids.begin() + i, ids.begin() + std::min(ids.size(), i + (size_t)sa::kMaxBatch));
-      step_batch(h, b);
+    if (h->paths[p].step < h->paths[p].n_steps) ids[h->paths[p].step & 1].push_back(p);
+  for (int par = 0; par < 2; ++par) {
+    const auto &v = ids[par];
+    const size_t nb = (v.size() + sa::kMaxBatch - 1) / sa::kMaxBatch;
+    for (size_t b = 0; b < nb; ++b) {
+      // equal shares: 65 paths go as 33 + 32, not 64 + 1
+      const size_t i0 = v.size() * b / nb, i1 = v.size() * (b + 1) / nb;
+      step_batch(h, std::vector<int>(v.begin() + i0, v.begin() + i1));
     }
   }
 }
@@ -1065,11 +1079,9 @@ void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *
   double *dT = tb.alloc<double>(stride), *dg = tb.alloc<double>(3 * stride), *dld = tb.alloc<double>(stride);
   sa::PathTab tab{};
   tab.count = 1;
-  tab.path[0] = p;
-  tab.src0[0] = h->paths[p].src0;
-  active_counts(h, h->paths[p], step, tab.n_act[0], tab.n_far[0]);
+  fill_slot(h, tab, 0, p, step);
   const sa_stats keep = h->stats;
-  sum_points(h, tab, step, n, stride, dx, dy, dz, dq, fx, fy, fz, fq, drole, dx, dy, dz, dx, true, stride, dT, dg,
+  sum_points(h, tab, n, stride, dx, dy, dz, dq, fx, fy, fz, fq, drole, dx, dy, dz, dx, true, stride, dT, dg,
              dld);
   h->stats.pairs = keep.pairs;
   h->stats.pairs_near = keep.pairs_near;
@@ -1080,34 +1092,6 @@ void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *
                 "download");
   hip_check(hipStreamSynchronize(h->stream), "sync");
   hip_check(hipGetLastError(), "kernel launch");
-}
-
-// T~, grad T~ at the boundary points of every path at its current step
-// (after a checkpoint load; the step's load densities are recomputed too)
-void refresh_boundary_fields(sa_iga *h) {
-  std::map<int64_t, std::vector<int>> groups;
-  for (int p = 0; p < (int)h->paths.size(); ++p) groups[h->paths[p].step].push_back(p);
-  const sa_stats keep = h->stats;
-  for (auto &g : groups) {
-    const auto &ids = g.second;
-    for (size_t i = 0; i < ids.size(); i += sa::kMaxBatch) {
-      sa::PathTab tab{};
-      const size_t e = std::min(ids.size(), i + (size_t)sa::kMaxBatch);
-      tab.count = (int)(e - i);
-      for (size_t k = i; k < e; ++k) {
-        const int s = (int)(k - i), p = ids[k];
-        tab.path[s] = p;
-        tab.src0[s] = h->paths[p].src0;
-        active_counts(h, h->paths[p], g.first, tab.n_act[s], tab.n_far[s]);
-      }
-      sum_points(h, tab, g.first, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2,
-                 h->role, h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD);
-    }
-  }
-  hip_check(hipGetLastError(), "kernel launch");
-  hip_check(hipStreamSynchronize(h->stream), "sync");
-  collect_timing(h);
-  h->stats = keep;                 // not a step: counters and stage times unchanged
 }
 
 int path_index(sa_iga *h, int32_t path) {
@@ -1259,6 +1243,74 @@ int sa_iga_apply_operator(sa_iga *h, int32_t which, const double *x, double *y) 
   });
 }
 
+int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *waves_per_group,
+                    double *ms_per_launch) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    if (reps < 1) throw sa::SaError{SA_EINVAL, "reps must be >= 1"};
+    auto &o = h->m.opt;
+    sa::PathTab tab{};
+    tab.count = std::min((int)h->paths.size(), sa::kMaxBatch);
+    int64_t max_act = 0, max_far = 0, max_near = 0;
+    for (int s = 0; s < tab.count; ++s) {
+      fill_slot(h, tab, s, s, h->paths[s].n_steps);
+      max_act = std::max<int64_t>(max_act, tab.n_act[s]);
+      max_far = std::max<int64_t>(max_far, tab.n_far[s]);
+      max_near = std::max<int64_t>(max_near, tab.n_act[s] - tab.n_far[s]);
+    }
+    double best_ms = 0.0;
+    if (max_act > 0) {
+      sa::CoeffParams cp{h->delta, h->shift, h->alpha, h->rc, o.kernel_scale};
+      // the coefficient records are rewritten by every step before use
+      sa::launch_coeff(h->stream, tab, max_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
+      sa::SumPlan pl = make_plan(h, h->nq, tab.count, max_far, max_near);
+      pl.part_stride = h->stride;
+      ensure_part(h, (int64_t)tab.count * std::max(pl.n_chunks_far + pl.n_chunks_near, 1) * 5 * h->stride);
+      hipEvent_t e0, e1;
+      hip_check(hipEventCreate(&e0), "event");
+      hip_check(hipEventCreate(&e1), "event");
+      int bp = 2, bw = 4;
+      best_ms = -1.0;
+      try {
+        for (int P : {1, 2, 4})
+          for (int w : {1, 2, 4, 8}) {
+            pl.points_per_lane = P;
+            pl.waves = w;
+            sa::launch_sum(h->stream, pl, tab, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->c64,
+                           h->c32, h->part);
+            hip_check(hipEventRecord(e0, h->stream), "event record");
+            for (int r = 0; r < reps; ++r)
+              sa::launch_sum(h->stream, pl, tab, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2,
+                             h->c64, h->c32, h->part);
+            hip_check(hipEventRecord(e1, h->stream), "event record");
+            hip_check(hipEventSynchronize(e1), "event sync");
+            hip_check(hipGetLastError(), "kernel launch");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            const double per = ms / reps;
+            if (best_ms < 0 || per < best_ms) {
+              best_ms = per;
+              bp = P;
+              bw = w;
+            }
+          }
+      } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      o.points_per_lane = bp;
+      o.waves_per_group = bw;
+    }
+    if (points_per_lane) *points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
+    if (waves_per_group) *waves_per_group = o.waves_per_group ? o.waves_per_group : 4;
+    if (ms_per_launch) *ms_per_launch = best_ms;
+    return SA_OK;
+  });
+}
+
 int sa_iga_get_info(sa_iga *h, sa_info *info) {
   return guarded([&]() -> int {
     if (!h || !info) throw sa::SaError{SA_EINVAL, "NULL argument"};
@@ -1293,8 +1345,8 @@ int sa_iga_reset_stats(sa_iga *h) {
 int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
   return guarded([&]() -> int {
     if (!h || !len) throw sa::SaError{SA_EINVAL, "NULL argument"};
-    const int64_t nd = h->nd, nDa = h->nDa;
-    const size_t per = sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
+    const int64_t nd = h->nd, nDa = h->nDa, nq = h->nq;
+    const size_t per = sizeof(int64_t) + (2 * nd + nDa + 4 * nq) * sizeof(double);
     const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
     if (!buf) {
       *len = need;
@@ -1314,6 +1366,14 @@ int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
       b += nd * sizeof(double);
       hip_check(hipMemcpyAsync(b, path_vD(h, p), nDa * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
       b += nDa * sizeof(double);
+      hip_check(hipMemcpyAsync(b, path_T(h, p), nq * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
+      b += nq * sizeof(double);
+      for (int c = 0; c < 3; ++c) {
+        hip_check(hipMemcpyAsync(b, path_G(h, p) + c * h->stride, nq * sizeof(double), hipMemcpyDeviceToHost,
+                                 h->stream),
+                  "download");
+        b += nq * sizeof(double);
+      }
     }
     hip_check(hipStreamSynchronize(h->stream), "sync");
     *len = need;
@@ -1324,8 +1384,8 @@ int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
 int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
   return guarded([&]() -> int {
     if (!h || !buf) throw sa::SaError{SA_EINVAL, "NULL argument"};
-    const int64_t nd = h->nd, nDa = h->nDa;
-    const size_t per = sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
+    const int64_t nd = h->nd, nDa = h->nDa, nq = h->nq;
+    const size_t per = sizeof(int64_t) + (2 * nd + nDa + 4 * nq) * sizeof(double);
     const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
     if (len < need) throw sa::SaError{SA_EINVAL, "checkpoint too short"};
     const char *b = (const char *)buf;
@@ -1338,7 +1398,7 @@ int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
       int64_t st;
       std::memcpy(&st, b, sizeof(int64_t));
       if (st < 0 || st > P.n_steps) throw sa::SaError{SA_EINVAL, "checkpoint step out of range"};
-      b += sizeof(int64_t) + (2 * nd + nDa) * sizeof(double);
+      b += per;
     }
     b = (const char *)buf + sizeof(hdr);
     for (int p = 0; p < (int)h->paths.size(); ++p) {
@@ -1350,8 +1410,16 @@ int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
       b += nd * sizeof(double);
       hip_check(hipMemcpyAsync(path_vD(h, p), b, nDa * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
       b += nDa * sizeof(double);
+      hip_check(hipMemcpyAsync(path_T(h, p), b, nq * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
+      b += nq * sizeof(double);
+      for (int c = 0; c < 3; ++c) {
+        hip_check(hipMemcpyAsync(path_G(h, p) + c * h->stride, b, nq * sizeof(double), hipMemcpyHostToDevice,
+                                 h->stream),
+                  "upload");
+        b += nq * sizeof(double);
+      }
     }
-    refresh_boundary_fields(h);
+    hip_check(hipStreamSynchronize(h->stream), "sync");
     h->sticky = 0;
     return SA_OK;
   });

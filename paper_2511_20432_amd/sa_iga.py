@@ -73,6 +73,8 @@ EXPORTS = {
     "sa_iga_get_boundary_points": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "sa_iga_apply_operator": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp]),
     "sa_iga_eval_source_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, _dp, _dp, _dp]),
+    "sa_iga_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_double)]),
     "sa_iga_get_info": (C.c_int, [C.c_void_p, C.POINTER(sa_info)]),
     "sa_iga_get_stats": (C.c_int, [C.c_void_p, C.POINTER(sa_stats)]),
     "sa_iga_reset_stats": (C.c_int, [C.c_void_p]),
@@ -218,6 +220,12 @@ class Model:
 
     def reset_stats(self):
         check(self._lib.sa_iga_reset_stats(self.h))
+
+    def autotune(self, reps: int = 3) -> dict:
+        """Pick the fastest kernel-sum tile shape; results stay bitwise the same."""
+        p, w, ms = C.c_int32(), C.c_int32(), C.c_double()
+        check(self._lib.sa_iga_autotune(self.h, reps, C.byref(p), C.byref(w), C.byref(ms)))
+        return {"points_per_lane": p.value, "waves_per_group": w.value, "ms_per_launch": ms.value}
 
     def boundary_fields(self, path: int = 0):
         """T~ [nq], grad T~ [nq, 3] at the boundary points, F [n_dof] and

@@ -121,3 +121,49 @@ def test_batched_checkpoint_resume_bitwise():
         assert a.get_step(p) == b.get_step(p)
         for x, y in zip(a.boundary_fields(p), b.boundary_fields(p)):
             assert np.array_equal(x, y)
+
+
+def test_paths_at_different_steps_share_launches():
+    """A checkpoint with paths at steps 3, 5, 2, 5 continued under longer
+    scans: paths at different steps (same parity) advance in one launch."""
+    tracks = [_track(i) for i in range(4)]
+    short = W.make_scan(tracks, 1e-5, 5, n_steps=[3, 5, 2, 8])
+    a = _model(W.small_block(), short)
+    a.step(5)
+    assert [a.get_step(p) for p in range(4)] == [3, 5, 2, 5]
+    long = W.make_scan(tracks, 1e-5, 5, n_steps=[10, 10, 10, 10])
+    b = _model(W.small_block(), long)
+    b.load(a.save())
+    for p in range(4):
+        for x, y in zip(a.boundary_fields(p), b.boundary_fields(p)):
+            assert np.array_equal(x, y)
+    b.step(4)
+    assert [b.get_step(p) for p in range(4)] == [7, 9, 6, 9]
+    for p, n in ((0, 7), (1, 9), (2, 6), (3, 9)):
+        _check_path(b, long, p, n)
+
+
+def test_tile_shapes_bitwise_equal_and_autotune():
+    """The kernel-sum tile shape changes no bit of any result; the tuner
+    picks a valid shape and leaves the state alone."""
+    tracks = [_track(i) for i in range(3)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=[12, 9, 12])
+    for prec in (W.PRECISION_FP64, W.PRECISION_FP32_FAR):
+        opts = W.Options(precision=prec, tau_near=5e-5)
+        a = _model(W.small_block(), scan, options=opts, points_per_lane=1, waves_per_group=1)
+        b = _model(W.small_block(), scan, options=opts, points_per_lane=4, waves_per_group=8)
+        a.step(6)
+        b.step(6)
+        before = [b.boundary_fields(p) for p in range(3)]
+        t = b.autotune(reps=2)
+        print("autotune", prec, t, flush=True)
+        assert t["points_per_lane"] in (1, 2, 4) and t["waves_per_group"] in (1, 2, 4, 8)
+        assert t["ms_per_launch"] > 0
+        for p in range(3):
+            for x, y in zip(before[p], b.boundary_fields(p)):
+                assert np.array_equal(x, y)
+        a.step(6)
+        b.step(6)
+        for p in range(3):
+            for x, y in zip(a.boundary_fields(p), b.boundary_fields(p)):
+                assert np.array_equal(x, y)
