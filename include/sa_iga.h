@@ -73,7 +73,8 @@ enum sa_precision {
   SA_PREC_FP32_FAR = 1,      /* sources older than tau_near summed in FP32 (exp2),
                                 FP32 tile partials accumulated in FP64; near
                                 sources, loads and the solve in FP64 */
-  SA_PREC_SURROGATE = 2      /* far sources replaced by the learned network, near in FP64 */
+  SA_PREC_SURROGATE = 2      /* far sources replaced by the learned network (sa_mlp), near
+                                sources in FP64; audited against the exact far sum */
 };
 
 enum sa_precond {
@@ -111,6 +112,14 @@ typedef struct {
   int32_t points_per_lane;     /* kernel-sum register blocking (1, 2, 4); 0 = tuned default */
   int32_t waves_per_group;     /* kernel-sum waves per workgroup (1, 2, 4, 8); 0 = tuned default */
   int32_t chunk_sources;       /* sources per source chunk of the sum; 0 = tuned default */
+  /* SA_PREC_SURROGATE only: the far-history network (see sa_mlp below).
+   * surrogate_weights [surrogate_len] = {T_scale (K), G_scale (K/m),
+   * E_scale (J), then the sa_mlp_n_params() FP32 parameters}; copied at set-up. */
+  const float *surrogate_weights;
+  int64_t surrogate_len;
+  int32_t audit_every;         /* audit a path's network every this many steps; default 50 */
+  double audit_frac;           /* fraction of the boundary points audited; default 0.01 */
+  double audit_tol;            /* K: fall back to the exact far sum above this error; default 0.5 */
 } sa_solver_options;
 
 typedef struct {
@@ -144,7 +153,7 @@ enum sa_stage {
   SA_STAGE_DIRICHLET = 4,      /* projection solve */
   SA_STAGE_RHS = 5,            /* theta-scheme right-hand side */
   SA_STAGE_PCG = 6,            /* theta-scheme solve */
-  SA_STAGE_OTHER = 7,
+  SA_STAGE_NET = 7,            /* far-history network and its audits (SA_PREC_SURROGATE) */
   SA_N_STAGES = 8
 };
 
@@ -158,6 +167,12 @@ typedef struct {
   int64_t dirichlet_iterations;
   double stage_ms[SA_N_STAGES];        /* device time per stage (timing != 0) */
   int64_t stage_launches[SA_N_STAGES]; /* kernel launches per stage (timing != 0) */
+  /* SA_PREC_SURROGATE */
+  int64_t net_steps;           /* path-steps whose far part came from the network */
+  int64_t pairs_net;           /* far source x point pairs the network replaced */
+  int64_t audits;              /* audits run */
+  int64_t audit_failures;      /* audits above audit_tol (the path then uses the exact sum) */
+  double audit_max_err;        /* largest audited error of the far temperature (K) */
 } sa_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -252,6 +267,19 @@ int sa_iga_reset_stats(sa_iga *h);
 int sa_iga_save(sa_iga *h, void *buf, size_t *len);
 int sa_iga_load(sa_iga *h, const void *buf, size_t len);
 
+/*
+ * Far-history data of path `path` at time step*dt (training set generation
+ * for the network): the exact FP64 far field (sources with tick <
+ * step*sources_per_step - floor(tau_near/delta), Eqs. 7-8) at every boundary
+ * point, T [n_bpts] and grad [3][n_bpts] (component-major), and the network
+ * inputs X [n_bpts][70] (FP32): normalised position, normal, far energy per
+ * 4 x 4 x 4 bin of the control-net bounding box divided by e_scale.  All three
+ * are DEVICE pointers on the object's stream (X may be NULL); the call returns
+ * when they are written.
+ */
+int sa_iga_far_field(sa_iga *h, int32_t path, int64_t step, double e_scale, float *X, double *T,
+                     double *grad);
+
 /* Use the given hipStream_t (NULL = the object's own stream) for all work. */
 int sa_iga_set_stream(sa_iga *h, void *hip_stream);
 
@@ -260,6 +288,34 @@ const char *sa_iga_last_error(void);
 
 /* Free the object and its device memory.  NULL is ignored. */
 void sa_iga_destroy(sa_iga *h);
+
+/*
+ * Far-history network (surrogate form).  Inputs x [70] as documented for
+ * sa_iga_far_field; outputs y [4] = (T~_far / T_scale, grad T~_far / G_scale).
+ *   z1 = W1 x + b1, h1 = gelu(z1)            W1 [256][70], FP32
+ *   z_l = W_l h_{l-1} + b_l, h_l = gelu(z_l)  l = 2, 3, 4; W_l [256][256]
+ *   y = W5 h4 + b5                           W5 [4][256], FP32
+ * gelu(z) = z (1 + erf(z / sqrt 2)) / 2.  The layers 2..4 run on the matrix
+ * cores with bfloat16 operands (h_{l-1} and W_l rounded to nearest even) and
+ * FP32 accumulation, h1..h4 are stored in bfloat16.  Parameters are one FP32
+ * vector in the order W1, b1, W2, b2, W3, b3, W4, b4, W5, b5 (row-major,
+ * sa_mlp_n_params() values).  The trainer holds FP32 master weights and Adam
+ * moments (beta1 0.9, beta2 0.999, eps 1e-8) on the current device; its
+ * loss is the mean of (y - t)^2 over rows and outputs.  X, Y, T below are
+ * DEVICE pointers (row-major [B][70], [B][4], [B][4]) used on the trainer's
+ * stream; every call returns when its results are written.
+ */
+typedef struct sa_mlp sa_mlp;
+int64_t sa_mlp_n_params(void);
+int sa_mlp_create(const float *params, int64_t n, sa_mlp **out);      /* params: host */
+int sa_mlp_get_params(sa_mlp *h, float *params, int64_t n);           /* params: host */
+int sa_mlp_forward(sa_mlp *h, int64_t B, const float *X, float *Y);
+/* gradients of the loss (host grad [n_params] in parameter order, may be NULL) */
+int sa_mlp_gradients(sa_mlp *h, int64_t B, const float *X, const float *T, float *grad, double *loss);
+/* one Adam step with learning rate lr on the batch; *loss = loss before the step */
+int sa_mlp_train_step(sa_mlp *h, int64_t B, const float *X, const float *T, float lr, double *loss);
+int sa_mlp_set_stream(sa_mlp *h, void *hip_stream);
+void sa_mlp_destroy(sa_mlp *h);
 
 #ifdef __cplusplus
 }

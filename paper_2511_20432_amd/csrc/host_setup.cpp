@@ -156,7 +156,19 @@ void validate_inputs(const sa_patch *patch, const sa_material *mat, const sa_sca
     }
   }
   if (!(opt.theta >= 0.0 && opt.theta <= 1.0)) fail(SA_EINVAL, "theta must be in [0, 1]");
-  if (opt.precision < 0 || opt.precision > 1) fail(SA_EINVAL, "precision must be SA_PREC_FP64 or SA_PREC_FP32_FAR");
+  if (opt.precision < 0 || opt.precision > 2) fail(SA_EINVAL, "precision must be an sa_precision value");
+  if (opt.precision == SA_PREC_SURROGATE) {
+    if (!opt.surrogate_weights) fail(SA_EINVAL, "SA_PREC_SURROGATE needs surrogate_weights");
+    if (opt.surrogate_len != 3 + kNetParams)
+      fail(SA_EINVAL, "surrogate_len must be 3 + sa_mlp_n_params()");
+    for (int64_t i = 0; i < opt.surrogate_len; ++i)
+      if (!std::isfinite(opt.surrogate_weights[i])) fail(SA_EINVAL, "non-finite surrogate weight");
+    if (!(opt.surrogate_weights[0] > 0) || !(opt.surrogate_weights[1] > 0) || !(opt.surrogate_weights[2] > 0))
+      fail(SA_EINVAL, "surrogate scales must be positive");
+    if (opt.audit_every < 1) fail(SA_EINVAL, "audit_every must be >= 1");
+    if (!(opt.audit_frac > 0 && opt.audit_frac <= 1)) fail(SA_EINVAL, "audit_frac must be in (0, 1]");
+    if (!(opt.audit_tol >= 0)) fail(SA_EINVAL, "audit_tol must be >= 0");
+  }
   if (!(opt.pcg_rtol > 0) || opt.pcg_max_iter < 1) fail(SA_EINVAL, "bad PCG options");
   if (opt.preconditioner < 0 || opt.preconditioner > 1) fail(SA_EINVAL, "bad preconditioner");
   if (!(opt.tau_near >= 0)) fail(SA_EINVAL, "tau_near must be >= 0");

@@ -29,6 +29,7 @@ struct PathTab {
   int32_t n_act[kMaxBatch];
   int32_t n_far[kMaxBatch];
   int64_t now[kMaxBatch];
+  uint8_t mode[kMaxBatch];   // 1: the far sources are supplied by the network (not summed here)
 };
 
 struct CoeffParams {
@@ -62,11 +63,14 @@ void launch_sum(hipStream_t st, const SumPlan &pl, const PathTab &tab, const dou
 // reduce chunk partials; T, grad; per-point load density:
 //   NEUMANN: -k (grad . n) w dS,  DIRICHLET: -T~ w dS,  else 0
 // outputs of slot s go to index o = (by_slot ? s : path[s]): T + o*ostride,
-// grad + o*3*ostride (component-major), ld + o*ostride
+// grad + o*3*ostride (component-major), ld + o*ostride.  Slots with mode 1
+// add the network's far field net[(s*4 + c) * net_stride + q] (c = 0: T,
+// 1..3: gradient) before the densities are formed.
 void launch_finalize(hipStream_t st, const PathTab &tab, bool by_slot, int64_t nq, int n_chunks,
                      int64_t part_stride, const double *part, const double *px, const double *py,
                      const double *pz, const double *nx, const double *ny, const double *nz, const double *wdS,
-                     const int8_t *role, double kcond, int64_t ostride, double *T, double *g, double *ld);
+                     const int8_t *role, double kcond, int64_t ostride, double *T, double *g, double *ld,
+                     const double *net, int64_t net_stride);
 
 // out[r] = sum_e val[e] * in[col[e]] over rows [0, nrow) of a CSR
 void launch_gather(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,

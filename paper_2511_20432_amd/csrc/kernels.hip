@@ -182,7 +182,7 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
 
   if (chunk < a.n_chunks_far) {
     const int lo = chunk * a.chunk_far;
-    const int hi = lo + a.chunk_far < n_far ? lo + a.chunk_far : n_far;
+    const int hi = tab.mode[slot] ? lo : (lo + a.chunk_far < n_far ? lo + a.chunk_far : n_far);
     float xf[P], yf[P], zf[P], qf[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -284,7 +284,8 @@ __global__ void k_finalize(PathTab tab, int by_slot, int64_t nq, int n_chunks, i
                            const double *__restrict__ nx, const double *__restrict__ ny,
                            const double *__restrict__ nz, const double *__restrict__ wdS,
                            const int8_t *__restrict__ role, double kcond, int64_t ostride,
-                           double *__restrict__ Tb, double *__restrict__ gb, double *__restrict__ ldb) {
+                           double *__restrict__ Tb, double *__restrict__ gb, double *__restrict__ ldb,
+                           const double *__restrict__ net, int64_t net_stride) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   const int slot = blockIdx.y;
@@ -299,9 +300,16 @@ __global__ void k_finalize(PathTab tab, int by_slot, int64_t nq, int n_chunks, i
     sy += o[3 * stride + q];
     sz += o[4 * stride + q];
   }
-  const double g0 = fma(2.0 * px[q], s1, sx);
-  const double g1 = fma(2.0 * py[q], s1, sy);
-  const double g2 = fma(2.0 * pz[q], s1, sz);
+  double g0 = fma(2.0 * px[q], s1, sx);
+  double g1 = fma(2.0 * py[q], s1, sy);
+  double g2 = fma(2.0 * pz[q], s1, sz);
+  if (net && tab.mode[slot]) {
+    const double *nf = net + (int64_t)slot * 4 * net_stride + q;
+    s0 += nf[0];
+    g0 += nf[net_stride];
+    g1 += nf[2 * net_stride];
+    g2 += nf[3 * net_stride];
+  }
   double *T = Tb + oi * ostride, *g = gb + oi * 3 * ostride, *ld = ldb + oi * ostride;
   T[q] = s0;
   g[q] = g0;
@@ -317,11 +325,12 @@ __global__ void k_finalize(PathTab tab, int by_slot, int64_t nq, int n_chunks, i
 void launch_finalize(hipStream_t st, const PathTab &tab, bool by_slot, int64_t nq, int n_chunks,
                      int64_t part_stride, const double *part, const double *px, const double *py,
                      const double *pz, const double *nx, const double *ny, const double *nz, const double *wdS,
-                     const int8_t *role, double kcond, int64_t ostride, double *T, double *g, double *ld) {
+                     const int8_t *role, double kcond, int64_t ostride, double *T, double *g, double *ld,
+                     const double *net, int64_t net_stride) {
   if (nq <= 0 || tab.count <= 0) return;
   dim3 gr((unsigned)((nq + kBlock - 1) / kBlock), (unsigned)tab.count);
   hipLaunchKernelGGL(k_finalize, gr, dim3(kBlock), 0, st, tab, by_slot ? 1 : 0, nq, n_chunks, part_stride, part,
-                     px, py, pz, nx, ny, nz, wdS, role, kcond, ostride, T, g, ld);
+                     px, py, pz, nx, ny, nz, wdS, role, kcond, ostride, T, g, ld, net, net_stride);
 }
 
 __global__ void k_gather(int64_t nrow, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,

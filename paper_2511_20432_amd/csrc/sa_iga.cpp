@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "mlp.h"
 #include "sa_internal.h"
 #include "solver.h"
 
@@ -141,6 +142,28 @@ struct sa_iga {
   std::vector<int8_t> status_kind;       // 0 projection, 1 theta-step
   int64_t status_cap = 0;
   size_t lds_per_block = 65536;
+  // far-history network inputs (every precision: also used for training data)
+  double box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};   // control-net bounding box
+  float *pf = nullptr;                  // [nq][6] normalised position, normal
+  int8_t *sbin = nullptr;               // [N] 4 x 4 x 4 bin of each source
+  float *bins = nullptr;                // [kMaxBatch][64]
+  // surrogate form
+  bool net = false;
+  double net_T = 1, net_G = 1, net_E = 1;   // output and input scales
+  float *nw = nullptr;                  // FP32 parameters
+  sa::bf16_t *nWb[3] = {};              // layers 2..4 in bfloat16
+  float *cvec = nullptr;                // [kMaxBatch][256] first-layer constants
+  double *netf = nullptr;               // [kMaxBatch][4][stride] network far field
+  sa::bf16_t *hA = nullptr, *hB = nullptr;  // [net_rows][256] activations
+  int64_t net_rows = 0;
+  std::vector<uint8_t> use_exact;       // per path: the last audit failed
+  // audit points: a fixed seeded subset of the boundary points
+  int64_t na = 0, stride_a = 0;
+  double *ax = nullptr, *ay = nullptr, *az = nullptr, *aq2 = nullptr;
+  float *afx = nullptr, *afy = nullptr, *afz = nullptr, *afq2 = nullptr;
+  int8_t *arole = nullptr;
+  float *apf = nullptr;
+  double *aT = nullptr, *aG = nullptr, *aLD = nullptr, *anet = nullptr;
   ~sa_iga();
 };
 
@@ -161,6 +184,12 @@ int set_error(int code, const std::string &msg) {
   g_last_error = msg;
   return code;
 }
+
+}  // namespace
+
+void sa::set_last_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
 
 template <class F>
 int guarded(F &&f) {
@@ -296,7 +325,7 @@ void fill_slot(const sa_iga *h, sa::PathTab &tab, int s, int p, int64_t step) {
   auto b = h->h_tick.begin() + P.src0, e = h->h_tick.begin() + P.src1;
   const int64_t a = (int64_t)(std::upper_bound(b, e, now) - b);
   int64_t f = 0;
-  if (h->m.opt.precision == SA_PREC_FP32_FAR && a > 0) {
+  if (h->m.opt.precision != SA_PREC_FP64 && a > 0) {
     const int64_t thr = now - h->tau_ticks;  // far iff tick < thr
     f = std::min<int64_t>(a, (int64_t)(std::lower_bound(b, b + a, thr) - b));
   }
@@ -305,6 +334,7 @@ void fill_slot(const sa_iga *h, sa::PathTab &tab, int s, int p, int64_t step) {
   tab.now[s] = now;
   tab.n_act[s] = (int32_t)a;
   tab.n_far[s] = (int32_t)f;
+  tab.mode[s] = 0;
 }
 
 // T~ and grad T~ of the slots of `tab` (each at its own time) at nq points
@@ -314,14 +344,16 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
                 const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
                 const float *fz, const float *fq2, const int8_t *role, const double *nx, const double *ny,
                 const double *nz, const double *wdS, bool by_slot, int64_t ostride, double *T, double *G,
-                double *ld) {
+                double *ld, const double *net = nullptr, int64_t net_stride = 0) {
   int64_t max_act = 0, max_far = 0, max_near = 0;
   for (int s = 0; s < tab.count; ++s) {
+    const int64_t nf = tab.mode[s] ? 0 : tab.n_far[s];      // far sources summed here
     max_act = std::max<int64_t>(max_act, tab.n_act[s]);
-    max_far = std::max<int64_t>(max_far, tab.n_far[s]);
+    max_far = std::max<int64_t>(max_far, nf);
     max_near = std::max<int64_t>(max_near, tab.n_act[s] - tab.n_far[s]);
-    h->stats.pairs += (int64_t)tab.n_act[s] * nq;
+    h->stats.pairs += (int64_t)(tab.n_act[s] - tab.n_far[s] + nf) * nq;
     h->stats.pairs_near += (int64_t)(tab.n_act[s] - tab.n_far[s]) * nq;
+    if (tab.mode[s]) h->stats.pairs_net += (int64_t)tab.n_far[s] * nq;
   }
   if (max_act > 0) {
     StageScope s(h, SA_STAGE_COEFF);
@@ -339,7 +371,7 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
   {
     StageScope s(h, SA_STAGE_REDUCE);
     sa::launch_finalize(h->stream, tab, by_slot, nq, nch, stride, h->part, px, py, pz, nx, ny, nz, wdS, role,
-                        h->m.mat.k, ostride, T, G, ld);
+                        h->m.mat.k, ostride, T, G, ld, net, net_stride);
   }
 }
 
@@ -438,26 +470,139 @@ sa::SolveStatus *next_status(sa_iga *h, int n, int8_t kind) {
   return s;
 }
 
+// ---- far-history network ------------------------------------------------------------
+// network far field of the first `tab.count` slots at nq points (point inputs
+// pf [nq][6]) into out[(s*4 + c) * ostride + q]; rows go through the layers
+// in chunks of net_rows so the activations stay cache-sized
+void run_network(sa_iga *h, const sa::PathTab &tab, int64_t nq, const float *pf, int64_t ostride, double *out) {
+  if (tab.count <= 0 || nq <= 0) return;
+  StageScope sc(h, SA_STAGE_NET);
+  const float *W1 = h->nw + sa::MlpLayout::W1, *b1 = h->nw + sa::MlpLayout::b1;
+  sa::launch_far_bins(h->stream, tab, h->sbin, h->sE, h->net_E, h->bins);
+  sa::launch_layer1_const(h->stream, tab.count, h->bins, W1, b1, h->cvec);
+  const int64_t total = (int64_t)tab.count * nq, H = sa::kMlpHid;
+  const int64_t bias[3] = {sa::MlpLayout::b2, sa::MlpLayout::b3, sa::MlpLayout::b4};
+  for (int64_t r0 = 0; r0 < total; r0 += h->net_rows) {
+    const int64_t rows = std::min(h->net_rows, total - r0);
+    sa::launch_layer1_points(h->stream, r0, rows, nq, pf, h->cvec, W1, h->hA);
+    sa::bf16_t *in = h->hA, *outb = h->hB;
+    for (int l = 0; l < 3; ++l) {
+      sa::GemmArgs g{};
+      g.M = rows;
+      g.N = H;
+      g.K = H;
+      g.A = in;
+      g.a_sm = H;
+      g.a_sk = 1;
+      g.B = h->nWb[l];
+      g.b_sk = 1;
+      g.b_sn = H;
+      g.bias = h->nw + bias[l];
+      g.act = 1;
+      g.out = outb;
+      g.ldo = H;
+      sa::launch_gemm_bf16(h->stream, g);
+      std::swap(in, outb);
+    }
+    sa::launch_layer_out_field(h->stream, r0, rows, nq, in, h->nw + sa::MlpLayout::W5, h->nw + sa::MlpLayout::b5,
+                               h->net_T, h->net_G, ostride, out);
+  }
+}
+
+// Audit of the slots `aud` of `tab` (their steps' far parts): the exact FP64
+// far sum and the network at the audit points; a path whose largest error of
+// the far temperature exceeds audit_tol uses the exact far sum until an audit
+// passes again.
+void audit_slots(sa_iga *h, const sa::PathTab &tab, const std::vector<int> &aud) {
+  if (aud.empty()) return;
+  sa::PathTab ex{}, nt{};
+  ex.count = nt.count = (int)aud.size();
+  for (int i = 0; i < ex.count; ++i) {
+    const int s = aud[i];
+    ex.path[i] = nt.path[i] = tab.path[s];
+    ex.src0[i] = nt.src0[i] = tab.src0[s];
+    ex.now[i] = nt.now[i] = tab.now[s];
+    ex.n_act[i] = tab.n_far[s];       // the far sources only, all in FP64
+    ex.n_far[i] = 0;
+    ex.mode[i] = 0;
+    nt.n_act[i] = tab.n_act[s];
+    nt.n_far[i] = tab.n_far[s];
+    nt.mode[i] = 1;
+  }
+  const sa_stats keep = h->stats;
+  sum_points(h, ex, h->na, h->stride_a, h->ax, h->ay, h->az, h->aq2, h->afx, h->afy, h->afz, h->afq2, h->arole,
+             h->ax, h->ay, h->az, h->ax, true, h->stride_a, h->aT, h->aG, h->aLD);
+  h->stats.pairs = keep.pairs;              // audit work is not part of the step's sum
+  h->stats.pairs_near = keep.pairs_near;
+  h->stats.pairs_net = keep.pairs_net;
+  run_network(h, nt, h->na, h->apf, h->stride_a, h->anet);
+  const int64_t n = h->na, sa_ = h->stride_a;
+  std::vector<double> te((size_t)ex.count * sa_), tn((size_t)ex.count * 4 * sa_);
+  hip_check(hipMemcpyAsync(te.data(), h->aT, te.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            "download");
+  hip_check(hipMemcpyAsync(tn.data(), h->anet, tn.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            "download");
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+  for (int i = 0; i < ex.count; ++i) {
+    double err = 0.0;
+    for (int64_t q = 0; q < n; ++q)
+      err = std::max(err, std::fabs(tn[(size_t)i * 4 * sa_ + q] - te[(size_t)i * sa_ + q]));
+    if (!std::isfinite(err)) err = INFINITY;
+    const bool fail = !(err <= h->m.opt.audit_tol);
+    h->use_exact[ex.path[i]] = fail ? 1 : 0;
+    h->stats.audits++;
+    if (fail) h->stats.audit_failures++;
+    h->stats.audit_max_err = std::max(h->stats.audit_max_err, err);
+  }
+}
+
 // ---- one theta-step of a set of paths (at most kMaxBatch) -------------------------
 // The paths may sit at different steps; their steps share one parity, which
 // selects the state buffers (u^n, F^n read from one, u^{n+1}, F^{n+1} written
 // to the other).
-void step_batch(sa_iga *h, const std::vector<int> &pids) {
+void step_batch(sa_iga *h, std::vector<int> pids) {
   const int count = (int)pids.size();
   const int cur = (int)(h->paths[pids[0]].step & 1), nxt = cur ^ 1;
   const int64_t nd = h->nd;
   sa::PathTab tab{};
   sa::SlotMap sm{};
   tab.count = sm.count = count;
+  int n_net = 0;
+  if (h->net) {
+    // audits due at this step decide the far part of this step already
+    sa::PathTab at{};
+    at.count = count;
+    std::vector<int> aud;
+    for (int s = 0; s < count; ++s) {
+      fill_slot(h, at, s, pids[s], h->paths[pids[s]].step + 1);
+      if ((h->paths[pids[s]].step + 1) % h->m.opt.audit_every == 0) aud.push_back(s);
+    }
+    audit_slots(h, at, aud);
+    // paths on the network first: their slots index the network's output
+    std::stable_partition(pids.begin(), pids.end(), [h](int p) { return !h->use_exact[p]; });
+    for (int p : pids) n_net += h->use_exact[p] ? 0 : 1;
+  }
   for (int s = 0; s < count; ++s) {
     const PathState &P = h->paths[pids[s]];
     if ((int)(P.step & 1) != cur) throw sa::SaError{SA_EINVAL, "internal: mixed step parity in a batch"};
     sm.path[s] = pids[s];
     fill_slot(h, tab, s, pids[s], P.step + 1);
+    if (h->net) {
+      if (s < n_net) tab.mode[s] = 1;
+      else tab.n_far[s] = 0;               // exact fallback: every source in FP64
+    }
+  }
+  const double *net = nullptr;
+  if (n_net > 0) {
+    sa::PathTab nt = tab;
+    nt.count = n_net;
+    run_network(h, nt, h->nq, h->pf, h->stride, h->netf);
+    net = h->netf;
+    h->stats.net_steps += n_net;
   }
   // T~, grad T~ and load densities at every boundary point (Eqs. 7-8, 10-11)
   sum_points(h, tab, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
-             h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD);
+             h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD, net, h->stride);
   double *Vc = h->V[cur], *Vn = h->V[nxt], *Fc = h->Fb[cur], *Fn = h->Fb[nxt];
   {
     StageScope s(h, SA_STAGE_LOAD);
@@ -664,6 +809,110 @@ T *dev_zeros(sa_iga *h, size_t n) {
   T *p = dev_alloc<T>(h->owned, n);
   hip_check(hipMemsetAsync(p, 0, std::max<size_t>(n, 1) * sizeof(T), h->stream), "memset");
   return p;
+}
+
+// splitmix64: the audit subset is drawn from this fixed sequence
+uint64_t splitmix64(uint64_t &x) {
+  uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// network inputs (box, point features, source bins) for every object; the
+// weights, buffers and audit points of the surrogate form
+void build_network_state(sa_iga *h, const sa_patch *patch, const sa_scan_path *scan) {
+  const sa::Model &m = h->m;
+  const int64_t nctrl = (int64_t)patch->n_ctrl[0] * patch->n_ctrl[1] * patch->n_ctrl[2];
+  for (int d = 0; d < 3; ++d) {
+    h->box_lo[d] = INFINITY;
+    h->box_hi[d] = -INFINITY;
+  }
+  for (int64_t i = 0; i < nctrl; ++i)
+    for (int d = 0; d < 3; ++d) {
+      h->box_lo[d] = std::min(h->box_lo[d], patch->ctrl_xyzw[4 * i + d]);
+      h->box_hi[d] = std::max(h->box_hi[d], patch->ctrl_xyzw[4 * i + d]);
+    }
+  const sa::BoundaryTables &bt = m.bt;
+  std::vector<float> pf((size_t)bt.nq * sa::kMlpPoint);
+  for (int64_t q = 0; q < bt.nq; ++q)
+    for (int d = 0; d < 3; ++d) {
+      const double ext = h->box_hi[d] - h->box_lo[d];
+      pf[q * 6 + d] = (float)(ext > 0 ? 2.0 * (bt.x[3 * q + d] - h->box_lo[d]) / ext - 1.0 : 0.0);
+      pf[q * 6 + 3 + d] = (float)bt.nrm[3 * q + d];
+    }
+  h->pf = dev_upload(h->owned, pf, h->stream);
+  const int64_t N = scan->src_offset[scan->n_paths];
+  std::vector<int8_t> sb(std::max<int64_t>(N, 1), 0);
+  for (int64_t i = 0; i < N; ++i) {
+    int idx[3];
+    for (int d = 0; d < 3; ++d) {
+      const double ext = h->box_hi[d] - h->box_lo[d];
+      const double u = ext > 0 ? std::floor(4.0 * (scan->xyz[3 * i + d] - h->box_lo[d]) / ext) : 0.0;
+      idx[d] = u < 0 ? 0 : (u > 3 ? 3 : (int)u);
+    }
+    sb[i] = (int8_t)(idx[0] + 4 * idx[1] + 16 * idx[2]);
+  }
+  h->sbin = dev_upload(h->owned, sb, h->stream);
+  h->bins = dev_zeros<float>(h, (size_t)sa::kMaxBatch * sa::kMlpBins);
+  if (m.opt.precision != SA_PREC_SURROGATE) return;
+
+  h->net = true;
+  const float *wb = m.opt.surrogate_weights;
+  h->net_T = wb[0];
+  h->net_G = wb[1];
+  h->net_E = wb[2];
+  std::vector<float> w(wb + 3, wb + 3 + sa::kNetParams);
+  h->nw = dev_upload(h->owned, w, h->stream);
+  const int64_t off[3] = {sa::MlpLayout::W2, sa::MlpLayout::W3, sa::MlpLayout::W4};
+  for (int l = 0; l < 3; ++l) {
+    h->nWb[l] = dev_alloc<sa::bf16_t>(h->owned, (size_t)sa::kMlpHid * sa::kMlpHid);
+    sa::launch_to_bf16(h->stream, (int64_t)sa::kMlpHid * sa::kMlpHid, h->nw + off[l], h->nWb[l]);
+  }
+  h->cvec = dev_zeros<float>(h, (size_t)sa::kMaxBatch * sa::kMlpHid);
+  h->netf = dev_zeros<double>(h, (size_t)sa::kMaxBatch * 4 * h->stride);
+  h->net_rows = std::min<int64_t>(131072, (int64_t)sa::kMaxBatch * h->stride);
+  h->hA = dev_alloc<sa::bf16_t>(h->owned, (size_t)h->net_rows * sa::kMlpHid);
+  h->hB = dev_alloc<sa::bf16_t>(h->owned, (size_t)h->net_rows * sa::kMlpHid);
+  h->use_exact.assign(h->paths.size(), 0);
+  // audit points: ceil(audit_frac nq) of the boundary points, drawn once
+  const int64_t nq = bt.nq;
+  h->na = std::min<int64_t>(nq, std::max<int64_t>(1, (int64_t)std::ceil(m.opt.audit_frac * (double)nq)));
+  std::vector<int64_t> perm(nq);
+  for (int64_t i = 0; i < nq; ++i) perm[i] = i;
+  uint64_t st = 0x5a17a0d17ull;
+  for (int64_t i = 0; i < h->na; ++i) {
+    const int64_t j = i + (int64_t)(splitmix64(st) % (uint64_t)(nq - i));
+    std::swap(perm[i], perm[j]);
+  }
+  std::sort(perm.begin(), perm.begin() + h->na);
+  h->stride_a = (h->na + 63) / 64 * 64;
+  std::vector<double> x(h->na), y(h->na), z(h->na), q2(h->na);
+  std::vector<float> apf((size_t)h->na * 6);
+  for (int64_t i = 0; i < h->na; ++i) {
+    const int64_t q = perm[i];
+    x[i] = bt.x[3 * q] - m.P.center[0];
+    y[i] = bt.x[3 * q + 1] - m.P.center[1];
+    z[i] = bt.x[3 * q + 2] - m.P.center[2];
+    q2[i] = x[i] * x[i] + y[i] * y[i] + z[i] * z[i];
+    for (int j = 0; j < 6; ++j) apf[i * 6 + j] = pf[q * 6 + j];
+  }
+  h->ax = dev_upload(h->owned, x, h->stream);
+  h->ay = dev_upload(h->owned, y, h->stream);
+  h->az = dev_upload(h->owned, z, h->stream);
+  h->aq2 = dev_upload(h->owned, q2, h->stream);
+  h->afx = dev_upload(h->owned, to_float(x), h->stream);
+  h->afy = dev_upload(h->owned, to_float(y), h->stream);
+  h->afz = dev_upload(h->owned, to_float(z), h->stream);
+  h->afq2 = dev_upload(h->owned, to_float(q2), h->stream);
+  h->arole = dev_upload(h->owned, std::vector<int8_t>(h->na, (int8_t)SA_FACE_SOURCE_PLANE), h->stream);
+  h->apf = dev_upload(h->owned, apf, h->stream);
+  h->aT = dev_zeros<double>(h, (size_t)sa::kMaxBatch * h->stride_a);
+  h->aG = dev_zeros<double>(h, (size_t)sa::kMaxBatch * 3 * h->stride_a);
+  h->aLD = dev_zeros<double>(h, (size_t)sa::kMaxBatch * h->stride_a);
+  h->anet = dev_zeros<double>(h, (size_t)sa::kMaxBatch * 4 * h->stride_a);
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+  hip_check(hipGetLastError(), "kernel launch");
 }
 
 void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan) {
@@ -976,6 +1225,8 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     f.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
     f.sc = h->sc;
   }
+  build_network_state(h, patch, scan);
+  h->m.opt.surrogate_weights = nullptr;   // copied; the caller's array is not kept
   h->status_cap = 8192;
   h->d_status = dev_zeros<sa::SolveStatus>(h, h->status_cap);
   hip_check(hipStreamSynchronize(h->stream), "sync");
@@ -1118,6 +1369,9 @@ int sa_iga_default_options(sa_solver_options *opt) {
   opt->pcg_rtol = 1e-13;
   opt->pcg_max_iter = 2000;
   opt->preconditioner = SA_PRECOND_FD;
+  opt->audit_every = 50;
+  opt->audit_frac = 0.01;
+  opt->audit_tol = 0.5;
   return SA_OK;
 }
 
@@ -1421,6 +1675,43 @@ int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
     }
     hip_check(hipStreamSynchronize(h->stream), "sync");
     h->sticky = 0;
+    return SA_OK;
+  });
+}
+
+int sa_iga_far_field(sa_iga *h, int32_t path, int64_t step, double e_scale, float *X, double *T, double *grad) {
+  return guarded([&]() -> int {
+    if (!h || !T || !grad) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (step < 0) throw sa::SaError{SA_EINVAL, "negative step"};
+    if (!(e_scale > 0) || !std::isfinite(e_scale)) throw sa::SaError{SA_EINVAL, "e_scale must be positive"};
+    const int p = path_index(h, path);
+    const PathState &P = h->paths[p];
+    const int64_t now = step * h->ns;
+    auto b = h->h_tick.begin() + P.src0, e = h->h_tick.begin() + P.src1;
+    const int64_t a = (int64_t)(std::upper_bound(b, e, now) - b);
+    const int64_t f = std::min<int64_t>(a, (int64_t)(std::lower_bound(b, b + a, now - h->tau_ticks) - b));
+    sa::PathTab ex{};
+    ex.count = 1;
+    ex.path[0] = p;
+    ex.src0[0] = P.src0;
+    ex.now[0] = now;
+    ex.n_act[0] = (int32_t)f;                 // the far sources, all in FP64
+    ex.n_far[0] = 0;
+    ex.mode[0] = 0;
+    const sa_stats keep = h->stats;
+    // T and grad written directly in the caller's layout (slot 0, stride n_bpts)
+    sum_points(h, ex, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
+               h->nx, h->ny, h->nz, h->wdS, true, h->nq, T, grad, h->LD);
+    h->stats.pairs = keep.pairs;
+    h->stats.pairs_near = keep.pairs_near;
+    if (X) {
+      sa::PathTab ft = ex;
+      ft.n_far[0] = (int32_t)f;
+      sa::launch_far_bins(h->stream, ft, h->sbin, h->sE, e_scale, h->bins);
+      sa::launch_net_inputs(h->stream, h->nq, h->pf, h->bins, X);
+    }
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    hip_check(hipGetLastError(), "kernel launch");
     return SA_OK;
   });
 }

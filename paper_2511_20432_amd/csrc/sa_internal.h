@@ -123,6 +123,12 @@ void assemble_volume(Model &m);
 void build_boundary(Model &m);
 void build_fd(Model &m);
 void fd_apply_host(const FdData &F, const double *r, double *z, int64_t n_full);
+
+// parameters of the far-history network (layout in mlp.h)
+constexpr int64_t kNetParams = 256 * 70 + 256 + 3 * (256 * 256 + 256) + 4 * 256 + 4;
+
+// message of the last failure on this thread (read by sa_iga_last_error)
+void set_last_error(const std::string &msg);
 double fd_inverse_defect(const FdData &F, const Stencil &S, const std::vector<double> &Sval,
                          const std::vector<uint8_t> &free_mask);
 

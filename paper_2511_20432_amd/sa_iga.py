@@ -19,7 +19,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 SA_OK, SA_EINVAL, SA_ENOMEM, SA_EDEVICE, SA_ENOCONV, SA_ERANGE, SA_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "SA_OK", -1: "SA_EINVAL", -2: "SA_ENOMEM", -3: "SA_EDEVICE", -4: "SA_ENOCONV",
                 -5: "SA_ERANGE", -6: "SA_ESTATE"}
-STAGES = ["coeff", "sum", "reduce", "load", "dirichlet", "rhs", "pcg", "other"]
+STAGES = ["coeff", "sum", "reduce", "load", "dirichlet", "rhs", "pcg", "net"]
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -40,7 +40,9 @@ class sa_solver_options(C.Structure):
     _fields_ = [("theta", C.c_double), ("kernel_scale", C.c_double), ("precision", C.c_int32),
                 ("tau_near", C.c_double), ("pcg_rtol", C.c_double), ("pcg_max_iter", C.c_int32),
                 ("preconditioner", C.c_int32), ("timing", C.c_int32), ("points_per_lane", C.c_int32),
-                ("waves_per_group", C.c_int32), ("chunk_sources", C.c_int32)]
+                ("waves_per_group", C.c_int32), ("chunk_sources", C.c_int32),
+                ("surrogate_weights", C.POINTER(C.c_float)), ("surrogate_len", C.c_int64),
+                ("audit_every", C.c_int32), ("audit_frac", C.c_double), ("audit_tol", C.c_double)]
 
 
 class sa_scan_path(C.Structure):
@@ -59,7 +61,9 @@ class sa_stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("pairs", C.c_int64), ("pairs_near", C.c_int64),
                 ("pcg_iterations", C.c_int64), ("pcg_last_iterations", C.c_int32),
                 ("pcg_last_relres", C.c_double), ("dirichlet_iterations", C.c_int64),
-                ("stage_ms", C.c_double * 8), ("stage_launches", C.c_int64 * 8)]
+                ("stage_ms", C.c_double * 8), ("stage_launches", C.c_int64 * 8),
+                ("net_steps", C.c_int64), ("pairs_net", C.c_int64), ("audits", C.c_int64),
+                ("audit_failures", C.c_int64), ("audit_max_err", C.c_double)]
 
 
 EXPORTS = {
@@ -81,6 +85,18 @@ EXPORTS = {
     "sa_iga_save": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
     "sa_iga_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "sa_iga_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sa_iga_far_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    "sa_mlp_n_params": (C.c_int64, []),
+    "sa_mlp_create": (C.c_int, [C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_void_p)]),
+    "sa_mlp_get_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_int64]),
+    "sa_mlp_forward": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "sa_mlp_gradients": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
+                                   C.POINTER(C.c_double)]),
+    "sa_mlp_train_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_float,
+                                    C.POINTER(C.c_double)]),
+    "sa_mlp_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sa_mlp_destroy": (None, [C.c_void_p]),
     "sa_iga_last_error": (C.c_char_p, []),
     "sa_iga_destroy": (None, [C.c_void_p]),
 }
@@ -163,6 +179,11 @@ class Model:
             o.pcg_rtol = options.pcg_rtol
             o.pcg_max_iter = options.pcg_max_iter
             o.preconditioner = options.preconditioner
+        weights = opt_overrides.pop("surrogate_weights", None)
+        if weights is not None:
+            weights = keep(weights, np.float32)
+            o.surrogate_weights = _ptr(weights, C.c_float)
+            o.surrogate_len = len(weights)
         for k, v in opt_overrides.items():
             setattr(o, k, v)
         self.options = o
@@ -285,6 +306,80 @@ class Model:
 
     def set_stream(self, stream_handle: Optional[int]):
         check(self._lib.sa_iga_set_stream(self.h, C.c_void_p(stream_handle) if stream_handle else None))
+
+    def far_field(self, step: int, e_scale: float, path: int = 0):
+        """Exact far field at every boundary point and the network inputs, as
+        device tensors: X [n_bpts, 70] float32, T [n_bpts], G [3, n_bpts] float64."""
+        import torch
+        nq = self.info.n_bpts
+        X = torch.empty((nq, 70), dtype=torch.float32, device="cuda")
+        T = torch.empty(nq, dtype=torch.float64, device="cuda")
+        G = torch.empty((3, nq), dtype=torch.float64, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        check(self._lib.sa_iga_far_field(self.h, path, step, e_scale, C.c_void_p(X.data_ptr()),
+                                         C.c_void_p(T.data_ptr()), C.c_void_p(G.data_ptr())))
+        return X, T, G
+
+
+def _dev(t):
+    """Device pointer of a contiguous CUDA tensor (torch's work on it finished)."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """Owner of one sa_mlp handle (the far-history network trainer)."""
+
+    def __init__(self, params: np.ndarray):
+        lib = load_library()
+        self._lib = lib
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        h = C.c_void_p()
+        check(lib.sa_mlp_create(_ptr(p, C.c_float), len(p), C.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def n_params() -> int:
+        return int(load_library().sa_mlp_n_params())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.sa_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params(), dtype=np.float32)
+        check(self._lib.sa_mlp_get_params(self.h, _ptr(out, C.c_float), len(out)))
+        return out
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], 4), dtype=torch.float32, device=X.device)
+        torch.cuda.current_stream().synchronize()
+        check(self._lib.sa_mlp_forward(self.h, X.shape[0], _dev(X), _dev(Y)))
+        return Y
+
+    def gradients(self, X, T):
+        import torch
+        g = np.empty(self.n_params(), dtype=np.float32)
+        loss = C.c_double()
+        torch.cuda.current_stream().synchronize()
+        check(self._lib.sa_mlp_gradients(self.h, X.shape[0], _dev(X), _dev(T), _ptr(g, C.c_float), C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, X, T, lr: float) -> float:
+        import torch
+        loss = C.c_double()
+        torch.cuda.current_stream().synchronize()
+        check(self._lib.sa_mlp_train_step(self.h, X.shape[0], _dev(X), _dev(T), lr, C.byref(loss)))
+        return loss.value
 
 
 def from_workload(w: W.Workload, **opt_overrides) -> Model:

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sa
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sa_iga_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(sa_(?:iga|mlp)_\w+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -32,6 +32,12 @@ def test_default_options():
     o = sa_iga.default_options()
     assert o.theta == 0.5 and o.kernel_scale == 1.0 and o.pcg_rtol == 1e-13
     assert o.precision == 0 and o.preconditioner == 1 and abs(o.tau_near - 2e-4) < 1e-18
+    assert o.audit_every == 50 and o.audit_frac == 0.01 and o.audit_tol == 0.5
+
+
+def test_network_parameter_count_matches_oracle():
+    from oracle import mlp
+    assert sa_iga.Mlp.n_params() == mlp.n_params()
 
 
 def _expect(code, patch, mat, scan, **kw):
@@ -55,6 +61,16 @@ def test_invalid_inputs_rejected_before_device():
     _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, s2)
     _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, theta=1.5)
     _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, points_per_lane=3)
+    # the surrogate form needs a weight vector of the network's size
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, precision=2)
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, precision=2,
+            surrogate_weights=np.ones(10, np.float32))
+    w = np.ones(3 + sa_iga.Mlp.n_params(), np.float32)
+    w[5] = np.inf
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, precision=2, surrogate_weights=w)
+    w[5] = 0.0
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, precision=2, surrogate_weights=w, audit_every=0)
+    _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, scan, precision=3)
     s3 = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
     s3.xyz[0, 0] = np.nan
     _expect(sa_iga.SA_EINVAL, patch, W.MAT_CFG, s3)

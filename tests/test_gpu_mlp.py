@@ -1,0 +1,174 @@
+"""The far-history network on the GPU (matrix-core forward, backward and
+Adam through the C ABI) against the FP64 oracle of the same network, the
+library's far-field training data against the oracle's kernel sum, and the
+surrogate form of the step: network far field, audits and exact fallback."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import iga, mlp, pointsource, solver
+from paper_2511_20432_amd import surrogate
+from paper_2511_20432_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _net(seed=0, bias=0.1):
+    from paper_2511_20432_amd import sa_iga
+    p = surrogate.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    # nonzero biases so that every term of the backward pass is exercised
+    q = mlp.unflatten(p.astype(np.float64))
+    for k in ("b1", "b2", "b3", "b4", "b5"):
+        q[k] = rng.normal(size=q[k].shape) * bias
+    p = mlp.flatten(q).astype(np.float32)
+    return sa_iga.Mlp(p), p
+
+
+def _inputs(B, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(B, 70)).astype(np.float32)
+    T = rng.normal(size=(B, 4)).astype(np.float32)
+    return X, T
+
+
+def test_forward_matches_oracle_ragged_batches():
+    net, p = _net(0)
+    P = mlp.unflatten(p.astype(np.float64))
+    for B in (1, 37, 300, 1029):
+        X, _ = _inputs(B, B)
+        Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+        Yr, _ = mlp.forward(P, X, bf16=True)
+        e = rel(Y, Yr)
+        print(f"forward B={B}: rel {e:.2e}", flush=True)
+        assert e <= 1e-2
+
+
+def test_gradients_match_oracle():
+    net, p = _net(2)
+    P = mlp.unflatten(p.astype(np.float64))
+    X, T = _inputs(515, 3)
+    g, loss = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    y, cache = mlp.forward(P, X, bf16=True)
+    gr = mlp.backward(P, cache, y, T.astype(np.float64), bf16=True)
+    assert abs(loss - mlp.mse(y, T)) <= 1e-2 * mlp.mse(y, T)
+    G = mlp.unflatten(g.astype(np.float64))
+    for k, _ in mlp.LAYERS:
+        e = rel(G[k], gr[k])
+        print(f"grad {k}: rel {e:.2e}", flush=True)
+        assert e <= 1e-2, k
+
+
+def test_adam_step_and_training_reduce_loss():
+    net, p = _net(4)
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(4096, 70)).astype(np.float32)
+    # a smooth target the network can fit
+    T = np.stack([np.tanh(X[:, 0] + 0.5 * X[:, 6]), np.sin(X[:, 1]), X[:, 2] * X[:, 3] * 0.3,
+                  0.2 * X[:, 7]], axis=1).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    # one Adam step moves every weight by about lr (bias-corrected first step)
+    before = net.params()
+    l0 = net.train_step(Xd, Td, 1e-3)
+    after = net.params()
+    d = np.abs(after - before)
+    g, _ = net.gradients(Xd, Td)
+    moved = d[np.abs(g) > 1e-6]
+    assert np.median(moved) == pytest.approx(1e-3, rel=0.05)
+    losses = [net.train_step(Xd, Td, 1e-3) for _ in range(300)]
+    print(f"loss {l0:.3e} -> {losses[-1]:.3e}", flush=True)
+    assert losses[-1] < 0.2 * l0
+
+
+def test_far_field_and_inputs_match_oracle():
+    from paper_2511_20432_amd import sa_iga
+    patch = W.small_block()
+    tr = surrogate_track()
+    scan = W.make_scan([tr], 1e-5, 5, n_steps=[40])
+    tau = 5e-5
+    m = sa_iga.Model(patch, W.MAT_CFG, scan, W.Options(tau_near=tau))
+    bt = iga.boundary_tables(patch)
+    lo, hi = mlp.box_of(patch.ctrl)
+    tau_ticks = int(np.floor(tau / (scan.dt / scan.sources_per_step) + 1e-9))
+    for step in (3, 17, 40):
+        X, T, G = m.far_field(step, 1e-3)
+        now = step * scan.sources_per_step
+        far = scan.tick < now - tau_ticks
+        Tr, Gr = pointsource.field(bt["x"], scan.xyz[far], scan.tick[far], scan.energy[far], step, scan, W.MAT_CFG)
+        if far.sum() == 0:
+            assert T.abs().max().item() == 0.0
+        else:
+            assert rel(T.cpu().numpy(), Tr) <= 1e-9
+            assert rel(G.cpu().numpy().T, Gr) <= 1e-9
+        bins = mlp.far_bins(scan.xyz, scan.tick, scan.energy, now, tau_ticks, lo, hi, 1e-3)
+        Xr = mlp.features(bt["x"], bt["n"], bins, lo, hi).astype(np.float32)
+        Xg = X.cpu().numpy()
+        assert np.abs(Xg[:, :6] - Xr[:, :6]).max() <= 1e-6
+        assert np.abs(Xg[:, 6:] - Xr[:, 6:]).max() <= 1e-6 * max(1.0, np.abs(Xr[:, 6:]).max())
+
+
+def surrogate_track():
+    seg = W.Segment("line", 80.0, 1.0, p0=np.array([0.1e-3, 0.3e-3, 0.5e-3]), p1=np.array([0.9e-3, 0.3e-3, 0.5e-3]))
+    return W.sources_from_segments([seg], 2e-6)
+
+
+def _surrogate_model(scan, params, tau, t_scale=50.0, **kw):
+    from paper_2511_20432_amd import sa_iga
+    blob = surrogate.weights_blob(params, t_scale, 2e5, 1e-3)
+    return sa_iga.Model(W.small_block(), W.MAT_CFG, scan, W.Options(precision=W.PRECISION_SURROGATE, tau_near=tau),
+                        surrogate_weights=blob, **kw)
+
+
+def test_surrogate_step_uses_network_far_field():
+    """With an audit that always passes, T~ at the boundary points is the
+    exact FP64 near sum plus T_scale times the network's first output."""
+    tr = surrogate_track()
+    scan = W.make_scan([tr], 1e-5, 5, n_steps=[30])
+    tau = 5e-5
+    _, p = _net(6)
+    gm = _surrogate_model(scan, p, tau, audit_tol=1e30, audit_every=7)
+    gm.step(30)
+    st = gm.stats()
+    assert st["net_steps"] == 30 and st["audits"] == 4 and st["audit_failures"] == 0
+    assert st["pairs_net"] > 0
+    T, G, F, du = gm.boundary_fields()
+    patch = W.small_block()
+    bt = iga.boundary_tables(patch)
+    lo, hi = mlp.box_of(patch.ctrl)
+    now = 30 * scan.sources_per_step
+    tau_ticks = int(np.floor(tau / (scan.dt / scan.sources_per_step) + 1e-9))
+    near = (scan.tick <= now) & (scan.tick >= now - tau_ticks)
+    Tn, Gn = pointsource.field(bt["x"], scan.xyz[near], scan.tick[near], scan.energy[near], 30, scan, W.MAT_CFG)
+    bins = mlp.far_bins(scan.xyz, scan.tick, scan.energy, now, tau_ticks, lo, hi, 1e-3)
+    X = mlp.features(bt["x"], bt["n"], bins, lo, hi)
+    y, _ = mlp.forward(mlp.unflatten(p.astype(np.float64)), X, bf16=True)
+    e_T = rel(T - Tn, 50.0 * y[:, 0])
+    e_G = rel(G - Gn, 2e5 * y[:, 1:])
+    print(f"network far field: T rel {e_T:.2e}, grad rel {e_G:.2e}", flush=True)
+    assert e_T <= 1e-2 and e_G <= 1e-2
+
+
+def test_surrogate_audit_falls_back_to_exact():
+    """An untrained network fails its first audit; from then on the path is
+    summed exactly and matches the FP64 form bitwise."""
+    from paper_2511_20432_amd import sa_iga
+    tr = surrogate_track()
+    scan = W.make_scan([tr], 1e-5, 5, n_steps=[24])
+    tau = 5e-5
+    _, p = _net(7)
+    gm = _surrogate_model(scan, p, tau, t_scale=1e4, audit_every=1)   # off by ~1000 K
+    ref = sa_iga.Model(W.small_block(), W.MAT_CFG, scan, W.Options(tau_near=tau))
+    gm.step(24)
+    ref.step(24)
+    st = gm.stats()
+    print("surrogate stats", {k: st[k] for k in ("net_steps", "audits", "audit_failures", "audit_max_err")},
+          flush=True)
+    assert st["audits"] == 24 and st["audit_failures"] == 24 and st["net_steps"] == 0
+    # after the failed audits the far part is exact: the last step is the FP64 form's
+    for a, b in zip(gm.boundary_fields(), ref.boundary_fields()):
+        assert np.array_equal(a, b)
