@@ -99,23 +99,16 @@ def jump_to_steps(model, steps):
     model.load(bytes(blob))
 
 
-def run_batched(window, form, seed=0):
-    """The batch of 128 scan strategies on the raster block: every strategy
-    starts the timed window at a seeded step in [0, L - window)."""
+def _batched_window(w, precision, window, start, **kw):
+    """Time `window` steps of every strategy of w from the given start steps."""
     import torch
     from paper_2511_20432_amd import sa_iga
     from paper_2511_20432_amd import workloads as W
-    w = W.cfg4(seed=seed)
-    prec = {"fp32far": W.PRECISION_FP32_FAR, "fp64": W.PRECISION_FP64}[form]
     t0 = time.perf_counter()
-    m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=prec, tau_near=2e-4), timing=1)
+    m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=precision, tau_near=2e-4), timing=1, **kw)
     setup_s = time.perf_counter() - t0
-    L = w.scan.n_steps.astype(np.int64)
-    rng = np.random.Generator(np.random.PCG64(seed + 7))
-    start = (rng.random(len(L)) * np.maximum(L - window, 0)).astype(np.int64)
     jump_to_steps(m, start)
     tune = m.autotune(reps=2)
-    m.step(2)                               # warm-up
     m.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -123,10 +116,15 @@ def run_batched(window, form, seed=0):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = m.stats()
+    return m, dt, st, tune, setup_s
+
+
+def _window_report(w, form, window, dt, st, tune, setup_s, seed):
     sum_ms = st["stage_ms"]["sum"]
     return {
         "workload": f"{w.scan.n_paths} strategies on the raster block (64x32x16 cubic, 64512 boundary points), "
-                    f"lengths U[500,4000] steps (sum {int(L.sum())}), {len(w.scan.tick)} sources, seed {seed}",
+                    f"lengths U[500,4000] steps (sum {int(w.scan.n_steps.sum())}), {len(w.scan.tick)} sources, "
+                    f"seed {seed}",
         "form": form, "window_steps": window,
         "start": "each strategy at a seeded step in [0, L - window) with a zeroed state; full work per step",
         "pairs_per_s": st["pairs"] / dt, "path_steps_per_s": st["steps"] / dt,
@@ -135,6 +133,71 @@ def run_batched(window, form, seed=0):
         "stage_ms_per_batched_step": {k: v / window for k, v in st["stage_ms"].items()},
         "autotune": tune, "setup_s": setup_s,
     }
+
+
+def _start_steps(w, window, seed):
+    L = w.scan.n_steps.astype(np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    return (rng.random(len(L)) * np.maximum(L - window, 0)).astype(np.int64)
+
+
+def run_batched(window, form, seed=0):
+    """The batch of 128 scan strategies on the raster block: every strategy
+    starts the timed window at a seeded step in [0, L - window)."""
+    from paper_2511_20432_amd import workloads as W
+    w = W.cfg4(seed=seed)
+    prec = {"fp32far": W.PRECISION_FP32_FAR, "fp64": W.PRECISION_FP64}[form]
+    m, dt, st, tune, setup_s = _batched_window(w, prec, window, _start_steps(w, window, seed))
+    return _window_report(w, form, window, dt, st, tune, setup_s, seed)
+
+
+def _max_err(a, b):
+    """Bound of max |T - T_ref| at the boundary points over all paths (R_A >= 0, sum R_A = 1)."""
+    worst = 0.0
+    for p in range(a.info.n_paths):
+        Ta, _, _, ua = a.boundary_fields(p)
+        Tb, _, _, ub = b.boundary_fields(p)
+        worst = max(worst, float(np.abs(Ta - Tb).max() + np.abs(ua - ub).max()))
+    return worst
+
+
+def run_surrogate(window, n_train=2_000_000, epochs=4, seed=1):
+    """Surrogate form on held-out strategies (seed 1) of the batched workload:
+    the network is trained here, on the GPU, on exact far sums of strategies
+    with seeds 1000..1063; then the audited form, the network forced on every
+    step (audit tolerance infinite) and the FP64 form run the same window."""
+    import torch
+    from paper_2511_20432_amd import sa_iga, surrogate
+    from paper_2511_20432_amd import workloads as W
+    t0 = time.perf_counter()
+    w = W.cfg4(seed=seed)
+    e_scale = 0.1
+    X, T, G = surrogate.training_set(w.patch, surrogate.strategy_scan(range(1000, 1064)), n_train, e_scale, seed=0)
+    ts, gs = surrogate.scales_of(T, G)
+    Y = surrogate.targets(T, G, ts, gs)
+    del T, G
+    net = sa_iga.Mlp(surrogate.init_params(0))
+    hist = surrogate.train(net, X, Y, epochs=epochs, batch=4096, lr=1e-3)
+    blob = surrogate.weights_blob(net.params(), ts, gs, e_scale)
+    del X, Y, net
+    torch.cuda.empty_cache()
+    train_s = time.perf_counter() - t0
+    start = _start_steps(w, window, seed)
+    out = {"training": {"samples": n_train, "epochs": epochs, "loss_per_epoch": hist, "seconds": train_s,
+                        "t_scale_K": ts, "g_scale_K_per_m": gs, "e_scale_J": e_scale,
+                        "train_seeds": "1000..1063", "eval_seed": seed}}
+    ref, dt, st, tune, su = _batched_window(w, W.PRECISION_FP64, window, start)
+    out["fp64"] = _window_report(w, "fp64", window, dt, st, tune, su, seed)
+    for form, kw in (("surrogate_audited", {}), ("surrogate_forced", {"audit_tol": 1e30})):
+        print(f"[bench] {form}: {window} steps of {w.scan.n_paths} strategies", file=sys.stderr, flush=True)
+        m, dt, st, tune, su = _batched_window(w, W.PRECISION_SURROGATE, window, start, surrogate_weights=blob, **kw)
+        r = _window_report(w, form, window, dt, st, tune, su, seed)
+        r.update({k: st[k] for k in ("net_steps", "pairs_net", "audits", "audit_failures", "audit_max_err")})
+        r["max_err_K_vs_fp64"] = _max_err(m, ref)
+        r["speedup_vs_fp64"] = out["fp64"]["ms_per_batched_step"] / r["ms_per_batched_step"]
+        out[form] = r
+        del m
+    return out
 
 
 def cpu_baseline(w, step, n_steps=16, threads=None):
@@ -173,6 +236,8 @@ def main():
     ap.add_argument("--forms", default="fp32far,fp64")
     ap.add_argument("--batched-window", type=int, default=60,
                     help="timed steps of the 128-strategy batch (0: skip)")
+    ap.add_argument("--surrogate-window", type=int, default=60,
+                    help="timed steps of the surrogate form on held-out strategies (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's sharding plan is "
@@ -262,6 +327,9 @@ def main():
         if "fp32far" in out["batched"] and "fp64" in out["batched"]:
             out["batched"]["speedup_vs_fp64"] = (out["batched"]["fp32far"]["path_steps_per_s"]
                                                  / out["batched"]["fp64"]["path_steps_per_s"])
+    if args.surrogate_window > 0:
+        print("[bench] surrogate form: training the far-history network", file=sys.stderr, flush=True)
+        out["surrogate"] = run_surrogate(args.surrogate_window)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle kernel sum)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, step=min(n_total - 16, 1900))
