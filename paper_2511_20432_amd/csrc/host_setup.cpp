@@ -698,6 +698,8 @@ void build_fd(Model &m) {
   for (int d = 0; d < 3; ++d) {
     param_mats_1d(P.b[d], P.qv[d], Mh[d], Kh[d]);
     param_mats_1d(P.b[d], P.qf, Mf[d], Kf[d]);
+    m.M1[d] = Mh[d];
+    m.K1[d] = Kh[d];
   }
   // main operator A = M/dt + theta K on the box of free DOFs
   FdData &F = m.fd_main;

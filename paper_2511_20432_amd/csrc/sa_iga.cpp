@@ -137,6 +137,8 @@ struct sa_iga {
   int pcg_budget = 2;                    // fixed iterations when the FD solve is exact: the
                                          // residual after the first is near kappa(A) eps
   sa::FusedPcg fp{};
+  bool kron = false;                     // matrix-free Kronecker A and B (affine patch)
+  sa::KronArgs kargs{};
   int hw0 = 1;
   sa::SolveStatus *d_status = nullptr;   // ring of per-solve records
   std::vector<int8_t> status_kind;       // 0 projection, 1 theta-step
@@ -674,7 +676,20 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       a.out = h->r;
       a.part = h->part_b2;
       a.sc_w = h->sc;
-      sa::launch_stencil_sl(h->stream, sm, a, h->hw0, true);
+      if (h->kron) {
+        sa::KronArgs k = h->kargs;
+        k.x = Vn;
+        k.v = Vc;
+        k.F1 = Fn;
+        k.F0 = Fc;
+        k.out = h->r;
+        k.part = h->part_b2;
+        k.sc = nullptr;
+        k.sc_w = h->sc;
+        sa::launch_kron(h->stream, sm, k, true);
+      } else {
+        sa::launch_stencil_sl(h->stream, sm, a, h->hw0, true);
+      }
     }
     StageScope s(h, SA_STAGE_PCG);
     sa::FusedPcg f = h->fp;
@@ -694,10 +709,20 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     ap.out = h->q;
     ap.part = h->part_pq2;
     ap.sc = h->sc;
+    sa::KronArgs kp = h->kargs;
+    kp.x = h->p;
+    kp.out = h->q;
+    kp.part = h->part_pq2;
+    kp.sc = h->sc;
+    kp.sc_w = nullptr;
+    auto apply = [&]() {
+      if (h->kron) sa::launch_kron(h->stream, sm, kp, false);
+      else sa::launch_stencil_sl(h->stream, sm, ap, h->hw0, false);
+    };
     sa::launch_fd_pass(h->stream, sm, f, 0, true, false);
     if (h->fd_exact) {
       for (int k = 0; k < h->pcg_budget; ++k) {
-        sa::launch_stencil_sl(h->stream, sm, ap, h->hw0, false);
+        apply();
         sa::launch_fd_pass(h->stream, sm, f, k, false, true);
         sa::launch_pcg_dir(h->stream, sm, f, k);
       }
@@ -705,7 +730,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       int k = 0, chunk = 4;
       for (;;) {
         for (int c = 0; c < chunk; ++c, ++k) {
-          sa::launch_stencil_sl(h->stream, sm, ap, h->hw0, false);
+          apply();
           sa::launch_fd_pass(h->stream, sm, f, k, false, true);
           sa::launch_pcg_dir(h->stream, sm, f, k);
         }
@@ -811,12 +836,98 @@ T *dev_zeros(sa_iga *h, size_t n) {
   return p;
 }
 
-// splitmix64: the audit subset is drawn from this fixed sequence
+// splitmix64: fixed pseudo-random sequences (audit subset, operator checks)
 uint64_t splitmix64(uint64_t &x) {
   uint64_t z = (x += 0x9e3779b97f4a7c15ull);
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
   z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
   return z ^ (z >> 31);
+}
+
+// y = cM (M2 x M1 x M0) x + c0 (M2 x M1 x K0) x + c1 (M2 x K1 x M0) x + c2 (K2 x M1 x M0) x
+// with dense 1-D factors (host check of the matrix-free device operator)
+void kron_apply_host(const int n[3], const std::vector<double> *M1, const std::vector<double> *K1, double cM,
+                     const double c[3], const std::vector<double> &x, std::vector<double> &y) {
+  const int64_t N = (int64_t)n[0] * n[1] * n[2];
+  const int64_t st[3] = {1, n[0], (int64_t)n[0] * n[1]};
+  auto pass = [&](int d, const std::vector<double> &F, const std::vector<double> &in, std::vector<double> &out) {
+    out.assign(N, 0.0);
+    for (int64_t r = 0; r < N; ++r) {
+      const int i = (int)((r / st[d]) % n[d]);
+      double s = 0.0;
+      for (int j = 0; j < n[d]; ++j) s += F[(size_t)i * n[d] + j] * in[r + (int64_t)(j - i) * st[d]];
+      out[r] = s;
+    }
+  };
+  std::vector<double> t0, t1, a, b, c1v, s(N), w(N), z0, z1;
+  pass(0, M1[0], x, t0);
+  pass(0, K1[0], x, t1);
+  pass(1, M1[1], t0, a);
+  pass(1, M1[1], t1, b);
+  pass(1, K1[1], t0, c1v);
+  for (int64_t r = 0; r < N; ++r) {
+    s[r] = cM * a[r] + c[0] * b[r] + c[1] * c1v[r];
+    w[r] = c[2] * a[r];
+  }
+  pass(2, M1[2], s, z0);
+  pass(2, K1[2], w, z1);
+  y.resize(N);
+  for (int64_t r = 0; r < N; ++r) y[r] = z0[r] + z1[r];
+}
+
+// matrix-free A and B when the Kronecker form reproduces the assembled A
+void build_kron(sa_iga *h) {
+  const sa::Model &m = h->m;
+  const int n[3] = {m.P.n[0], m.P.n[1], m.P.n[2]};
+  const double th = m.opt.theta;
+  const double cM = m.mat.rho * m.mat.cp * m.mean_detJ / m.dt;
+  double cA[3], cB[3];
+  for (int d = 0; d < 3; ++d) {
+    cA[d] = th * m.mat.k * m.mean_metric[d];
+    cB[d] = -(1.0 - th) * m.mat.k * m.mean_metric[d];
+  }
+  const int64_t N = h->nd;
+  std::vector<double> x(N), y, ym(N), yk(N);
+  uint64_t st = 0x243f6a8885a308d3ull;
+  for (int64_t i = 0; i < N; ++i) x[i] = (double)(splitmix64(st) >> 11) / 9007199254740992.0 - 0.5;
+  kron_apply_host(n, m.M1, m.K1, cM, cA, x, y);
+  m.M.apply(x.data(), ym.data());
+  m.K.apply(x.data(), yk.data());
+  double num = 0.0, den = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    const double ya = ym[i] / m.dt + th * yk[i];
+    num = std::max(num, std::fabs(y[i] - ya));
+    den = std::max(den, std::fabs(ya));
+  }
+  if (!(den > 0 && num <= 1e-12 * den)) return;
+  sa::KronArgs &k = h->kargs;
+  k = sa::KronArgs{};
+  for (int d = 0; d < 3; ++d) {
+    const int nd = n[d], p = m.P.b[d].p, w = 2 * p + 1;
+    std::vector<double> Mb((size_t)nd * w, 0.0), Kb((size_t)nd * w, 0.0);
+    for (int i = 0; i < nd; ++i)
+      for (int kk = 0; kk < w; ++kk) {
+        const int j = i - p + kk;
+        if (j < 0 || j >= nd) continue;
+        Mb[(size_t)i * w + kk] = m.M1[d][(size_t)i * nd + j];
+        Kb[(size_t)i * w + kk] = m.K1[d][(size_t)i * nd + j];
+      }
+    k.op.n[d] = nd;
+    k.op.p[d] = p;
+    k.op.Mb[d] = dev_upload(h->owned, Mb, h->stream);
+    k.op.Kb[d] = dev_upload(h->owned, Kb, h->stream);
+    k.op.cA[d] = cA[d];
+    k.op.cB[d] = cB[d];
+  }
+  k.op.cM = cM;
+  k.nrow = N;
+  k.vs = N;
+  k.np = h->np_st;
+  k.mask = h->free_mask;
+  k.theta = th;
+  k.ts = 8 * N;
+  k.t = dev_zeros<double>(h, (size_t)h->S * 8 * N);
+  h->kron = true;
 }
 
 // network inputs (box, point features, source bins) for every object; the
@@ -1225,6 +1336,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     f.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
     f.sc = h->sc;
   }
+  if (h->pcg_fused) build_kron(h);
   build_network_state(h, patch, scan);
   h->m.opt.surrogate_weights = nullptr;   // copied; the caller's array is not kept
   h->status_cap = 8192;
@@ -1233,9 +1345,9 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   if (std::getenv("SA_IGA_VERBOSE"))
     std::fprintf(stderr,
                  "[sa_iga] paths %d ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: exact %d one-wg %d | "
-                 "theta-step: fused %d fd-exact %d budget %d\n",
+                 "theta-step: fused %d fd-exact %d budget %d kron %d\n",
                  S, (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_exact,
-                 (int)h->dir_fused, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget);
+                 (int)h->dir_fused, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget, (int)h->kron);
 }
 
 // parametric query points -> device CSR rows of basis values (and gradients)

@@ -112,6 +112,7 @@ struct Model {
   Csr dproj;                       // rows = Dirichlet DOFs, cols = DIRICHLET points, val = R_A(x_q)
   Csr mass_dir;                    // trace mass matrix on the Dirichlet DOFs
   FdData fd_main, fd_dir;
+  std::vector<double> M1[3], K1[3];  // 1-D parametric mass / stiffness (volume rule), n_d x n_d
   bool fd_dir_ok = false;
   int free_box_ok = 0;             // Dirichlet set is a union of end layers (box of free DOFs)
 };

@@ -75,6 +75,34 @@ struct SlArgs {
 int stencil_blocks(int64_t nrow);
 void launch_stencil_sl(hipStream_t st, const SlotMap &sm, const SlArgs &a, int hw0, bool theta);
 
+// Matrix-free theta-scheme operators on an affine axis-aligned patch, where
+//   A = cM (M2 x M1 x M0) + sum_d cA[d] K_d-term,  B = cM (M2 x M1 x M0) + sum_d cB[d] K_d-term,
+//   K_0-term = M2 x M1 x K0, K_1-term = M2 x K1 x M0, K_2-term = K2 x M1 x M0
+// with banded 1-D factors (band[d][i][k] = factor[i][i - p_d + k]).  Applied in
+// three passes (x, y, z), each a banded product along one axis, through the
+// scratch t (8 vectors per path).  Same outputs and partials as
+// launch_stencil_sl (theta: r = B v + theta F1 + (1-theta) F0 - A x on the
+// free rows, partial sums of rhs^2; apply: q = A p, partial sums of p.q; one
+// partial per 64 rows).
+struct KronOp {
+  int n[3], p[3];
+  const double *Mb[3], *Kb[3];
+  double cM, cA[3], cB[3];
+};
+struct KronArgs {
+  KronOp op;
+  int64_t nrow, vs;       // stride per path of x, v, F1, F0, out
+  int np;                 // partials per path
+  const uint8_t *mask;
+  const double *x, *v, *F1, *F0;
+  double theta;
+  double *t;  int64_t ts; // scratch, stride per path (>= 8 nrow)
+  double *out, *part;
+  const PcgScalars *sc;   // apply: skip when done
+  PcgScalars *sc_w;       // theta: resets the done flags
+};
+void launch_kron(hipStream_t st, const SlotMap &sm, const KronArgs &a, bool theta);
+
 // fused PCG with the fast-diagonalisation preconditioner on the free box
 // Per-path data of path p: x, r, z, p, q at + p*vs; t at + p*ts; partials
 // part_rz at + p*2*np_rz, part_rr at + p*np_rz, part_pq at + p*np_pq,

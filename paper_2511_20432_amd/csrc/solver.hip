@@ -325,6 +325,116 @@ __global__ void k_stencil_sl(SlotMap sm, SlArgs a) {
   if (THETA && blockIdx.x == 0 && threadIdx.x == 0 && a.sc_w) a.sc_w->done = 0;
 }
 
+// ---------------------------------------------------------------------------
+// matrix-free Kronecker operators: one banded product along one axis per pass,
+// thread per row
+// ---------------------------------------------------------------------------
+// sum_j f[i][j] in[base + (j - i) stride] over the band j in [i - p, i + p] of 0..n-1
+__device__ __forceinline__ double band_dot(const double *__restrict__ band, int p, int i, int n,
+                                           const double *__restrict__ in, int64_t base, int64_t stride) {
+  const double *b = band + (int64_t)i * (2 * p + 1);
+  const int j0 = i - p < 0 ? 0 : i - p, j1 = i + p > n - 1 ? n - 1 : i + p;
+  double s = 0.0;
+  for (int j = j0; j <= j1; ++j) s = fma(b[j - i + p], in[base + (int64_t)(j - i) * stride], s);
+  return s;
+}
+
+template <bool THETA>
+__global__ void k_kron_x(SlotMap sm, KronArgs a) {
+  const int64_t pth = sm.path[blockIdx.y];
+  if (!THETA && a.sc && a.sc[pth].done) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = a.nrow;
+  if (r >= N) return;
+  const int n0 = a.op.n[0], p = a.op.p[0], i0 = (int)(r % n0);
+  const double *x = a.x + pth * a.vs;
+  double *t = a.t + pth * a.ts;
+  t[r] = band_dot(a.op.Mb[0], p, i0, n0, x, r, 1);
+  t[N + r] = band_dot(a.op.Kb[0], p, i0, n0, x, r, 1);
+  if (THETA) {
+    const double *v = a.v + pth * a.vs;
+    t[2 * N + r] = band_dot(a.op.Mb[0], p, i0, n0, v, r, 1);
+    t[3 * N + r] = band_dot(a.op.Kb[0], p, i0, n0, v, r, 1);
+  }
+}
+
+template <bool THETA>
+__global__ void k_kron_y(SlotMap sm, KronArgs a) {
+  const int64_t pth = sm.path[blockIdx.y];
+  if (!THETA && a.sc && a.sc[pth].done) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = a.nrow;
+  if (r >= N) return;
+  const int n0 = a.op.n[0], n1 = a.op.n[1], p = a.op.p[1];
+  const int i1 = (int)((r / n0) % n1);
+  const double *Mb = a.op.Mb[1], *Kb = a.op.Kb[1];
+  double *t = a.t + pth * a.ts;
+  // A: (M y M x) x, (M y K x) x, (K y M x) x  ->  the parts taken by M z and K z
+  const double mm = band_dot(Mb, p, i1, n1, t, r, n0);
+  const double mk = band_dot(Mb, p, i1, n1, t + N, r, n0);
+  const double km = band_dot(Kb, p, i1, n1, t, r, n0);
+  t[4 * N + r] = a.op.cM * mm + a.op.cA[0] * mk + a.op.cA[1] * km;
+  t[5 * N + r] = a.op.cA[2] * mm;
+  if (THETA) {
+    const double bmm = band_dot(Mb, p, i1, n1, t + 2 * N, r, n0);
+    const double bmk = band_dot(Mb, p, i1, n1, t + 3 * N, r, n0);
+    const double bkm = band_dot(Kb, p, i1, n1, t + 2 * N, r, n0);
+    t[6 * N + r] = a.op.cM * bmm + a.op.cB[0] * bmk + a.op.cB[1] * bkm;
+    t[7 * N + r] = a.op.cB[2] * bmm;
+  }
+}
+
+template <bool THETA>
+__global__ __launch_bounds__(kB) void k_kron_z(SlotMap sm, KronArgs a) {
+  const int64_t pth = sm.path[blockIdx.y];
+  if (!THETA && a.sc && a.sc[pth].done) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = a.nrow;
+  const int n0 = a.op.n[0], n1 = a.op.n[1], n2 = a.op.n[2], p = a.op.p[2];
+  const int64_t n01 = (int64_t)n0 * n1;
+  const double *t = a.t + pth * a.ts;
+  double part = 0.0;
+  if (r < N) {
+    const int i2 = (int)(r / n01);
+    const bool active = !a.mask || a.mask[r];
+    const double ax = band_dot(a.op.Mb[2], p, i2, n2, t + 4 * N, r, n01) +
+                      band_dot(a.op.Kb[2], p, i2, n2, t + 5 * N, r, n01);
+    double *out = a.out + pth * a.vs;
+    if (THETA) {
+      double rv = 0.0;
+      if (active) {
+        const double bv = band_dot(a.op.Mb[2], p, i2, n2, t + 6 * N, r, n01) +
+                          band_dot(a.op.Kb[2], p, i2, n2, t + 7 * N, r, n01);
+        const double rhs = bv + a.theta * a.F1[pth * a.vs + r] + (1.0 - a.theta) * a.F0[pth * a.vs + r];
+        part = rhs * rhs;
+        rv = rhs - ax;
+      }
+      out[r] = rv;
+    } else {
+      out[r] = active ? ax : 0.0;
+      part = active ? a.x[pth * a.vs + r] * ax : 0.0;
+    }
+  }
+  part = wsum(part);                       // lane 0: the sum over these 64 rows
+  const int64_t wi = r >> 6;
+  if ((threadIdx.x & 63) == 0 && wi < a.np) a.part[pth * a.np + wi] = part;
+  if (THETA && blockIdx.x == 0 && threadIdx.x == 0 && a.sc_w) a.sc_w[pth].done = 0;
+}
+
+void launch_kron(hipStream_t st, const SlotMap &sm, const KronArgs &a, bool theta) {
+  if (sm.count <= 0 || a.nrow <= 0) return;
+  dim3 g((unsigned)((a.nrow + kB - 1) / kB), (unsigned)sm.count), b(kB);
+  if (theta) {
+    hipLaunchKernelGGL(k_kron_x<true>, g, b, 0, st, sm, a);
+    hipLaunchKernelGGL(k_kron_y<true>, g, b, 0, st, sm, a);
+    hipLaunchKernelGGL(k_kron_z<true>, g, b, 0, st, sm, a);
+  } else {
+    hipLaunchKernelGGL(k_kron_x<false>, g, b, 0, st, sm, a);
+    hipLaunchKernelGGL(k_kron_y<false>, g, b, 0, st, sm, a);
+    hipLaunchKernelGGL(k_kron_z<false>, g, b, 0, st, sm, a);
+  }
+}
+
 int stencil_blocks(int64_t nrow) { return (int)((nrow + 63) / 64); }
 
 void launch_stencil_sl(hipStream_t st, const SlotMap &sm, const SlArgs &a, int hw0, bool theta) {
