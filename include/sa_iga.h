@@ -250,6 +250,9 @@ int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n,
 int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *waves_per_group,
                     double *ms_per_launch);
 
+/* Turn the per-stage HIP-event timing of later steps on (nonzero) or off. */
+int sa_iga_set_timing(sa_iga *h, int32_t on);
+
 int sa_iga_get_info(sa_iga *h, sa_info *info);
 int sa_iga_get_stats(sa_iga *h, sa_stats *stats);
 int sa_iga_reset_stats(sa_iga *h);

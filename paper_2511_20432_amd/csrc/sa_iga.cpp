@@ -132,11 +132,14 @@ struct sa_iga {
   bool dir_fused = false, dir_exact = false;
   sa::DirArgs dargs{};
   sa::FusedPcg fd_dirp{};                // direct Kronecker solve of the projection
+  bool dir_direct = false;               // ... by one workgroup per path (dense 1-D inverses in LDS)
+  sa::DirDirect ddir{};
   sa::PcgScalars *sc_dir = nullptr;      // [S], never set: the direct solve always runs
   bool pcg_fused = false, fd_exact = false;
   int pcg_budget = 2;                    // fixed iterations when the FD solve is exact: the
                                          // residual after the first is near kappa(A) eps
   sa::FusedPcg fp{};
+  double bw2 = 0.0;                      // (64 eps |A|_inf)^2, attainable-accuracy test
   bool kron = false;                     // matrix-free Kronecker A and B (affine patch)
   sa::KronArgs kargs{};
   int hw0 = 1;
@@ -616,7 +619,11 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     StageScope s(h, SA_STAGE_DIRICHLET);
     if (h->dir_exact || h->dir_fused)
       sa::launch_gather_rows(h->stream, sm, h->drows, h->LD, h->stride, h->bD, h->nDa, 0, nullptr, nullptr);
-    if (h->dir_exact) {
+    if (h->dir_direct) {
+      sa::DirDirect a = h->ddir;
+      a.xfull = Vn;
+      sa::launch_dir_direct(h->stream, sm, a);
+    } else if (h->dir_exact) {
       sa::FusedPcg f = h->fd_dirp;
       f.scatter_out = Vn;
       sa::launch_fd_pass(h->stream, sm, f, 0, false, false);
@@ -723,8 +730,13 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     if (h->fd_exact) {
       for (int k = 0; k < h->pcg_budget; ++k) {
         apply();
-        sa::launch_fd_pass(h->stream, sm, f, k, false, true);
-        sa::launch_pcg_dir(h->stream, sm, f, k);
+        if (k + 1 < h->pcg_budget) {
+          sa::launch_fd_pass(h->stream, sm, f, k, false, true);
+          sa::launch_pcg_dir(h->stream, sm, f, k, false);
+        } else {
+          sa::launch_pcg_last_update(h->stream, sm, f, k);
+          sa::launch_pcg_dir(h->stream, sm, f, k, true);
+        }
       }
     } else {
       int k = 0, chunk = 4;
@@ -732,7 +744,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
         for (int c = 0; c < chunk; ++c, ++k) {
           apply();
           sa::launch_fd_pass(h->stream, sm, f, k, false, true);
-          sa::launch_pcg_dir(h->stream, sm, f, k);
+          sa::launch_pcg_dir(h->stream, sm, f, k, false);
         }
         hip_check(hipMemcpyAsync(h->h_sc, h->sc, h->S * sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
                   "status copy");
@@ -1078,6 +1090,16 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     // an exact FD solve (affine axis-aligned patch) needs no convergence loop
     h->fd_exact = m.opt.preconditioner == SA_PRECOND_FD &&
                   sa::fd_inverse_defect(m.fd_main, m.M, A, m.free_mask) < 1e-10;
+    // |A|_inf over the free rows: scale of the attainable residual
+    double anorm = 0.0;
+    for (int64_t i = 0; i < nd; ++i) {
+      if (!m.free_mask[i]) continue;
+      double rs = 0.0;
+      for (int o = 0; o < m.M.n_off; ++o) rs += std::fabs(A[(size_t)o * nd + i]);
+      anorm = std::max(anorm, rs);
+    }
+    const double bw = 64.0 * 2.220446049250313e-16 * anorm;
+    h->bw2 = bw * bw;
   }
   upload_fd(h, m.fd_main, h->fd_main);
   if (m.fd_dir_ok) upload_fd(h, m.fd_dir, h->fd_dir);
@@ -1265,6 +1287,37 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
         f.sc = h->sc_dir;
         f.scatter_idx = h->dir_dofs;
         f.sos = nd;
+        // with a constant scaling the solve is inv (U1 U1^T x U0 U0^T): two dense passes
+        const int na = dm[0], nb = dm[1];
+        if (sa::dir_direct_lds(na, nb) + 1024 <= h->lds_per_block &&
+            sa::dir_direct_prepare(sa::dir_direct_lds(na, nb))) {
+          std::vector<double> Ia((size_t)na * na), Ib((size_t)nb * nb);
+          const auto &U0 = m.fd_dir.U[0], &U1 = m.fd_dir.U[1];
+          for (int i = 0; i < na; ++i)
+            for (int j = 0; j < na; ++j) {
+              double acc = 0.0;
+              for (int q = 0; q < na; ++q) acc += U0[(size_t)i * na + q] * U0[(size_t)j * na + q];
+              Ia[(size_t)i * na + j] = acc;
+            }
+          for (int i = 0; i < nb; ++i)
+            for (int j = 0; j < nb; ++j) {
+              double acc = 0.0;
+              for (int q = 0; q < nb; ++q) acc += U1[(size_t)i * nb + q] * U1[(size_t)j * nb + q];
+              Ib[(size_t)i * nb + j] = acc;
+            }
+          sa::DirDirect &a = h->ddir;
+          a.na = na;
+          a.nb = nb;
+          a.Ia = dev_upload(h->owned, Ia, h->stream);
+          a.Ib = dev_upload(h->owned, Ib, h->stream);
+          a.inv_area = m.fd_dir.inv_diag[0];
+          a.b = h->bD;
+          a.vD = h->vD;
+          a.vs = h->nDa;
+          a.dofs = h->dir_dofs;
+          a.xs = nd;
+          h->dir_direct = true;
+        }
       }
     }
     if (!h->dir_exact && sa::dirichlet_fits(h->nD)) {
@@ -1334,6 +1387,8 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     f.part_b = h->part_b2;
     f.np_b = h->np_st;
     f.rtol2 = m.opt.pcg_rtol * m.opt.pcg_rtol;
+    f.part_xx = dev_zeros<double>(h, (size_t)S * f.np_rz);
+    f.bw2 = h->bw2;
     f.sc = h->sc;
   }
   if (h->pcg_fused) build_kron(h);
@@ -1344,9 +1399,9 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   hip_check(hipStreamSynchronize(h->stream), "sync");
   if (std::getenv("SA_IGA_VERBOSE"))
     std::fprintf(stderr,
-                 "[sa_iga] paths %d ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: exact %d one-wg %d | "
+                 "[sa_iga] paths %d ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: exact %d direct %d one-wg %d | "
                  "theta-step: fused %d fd-exact %d budget %d kron %d\n",
-                 S, (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_exact,
+                 S, (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_exact, (int)h->dir_direct,
                  (int)h->dir_fused, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget, (int)h->kron);
 }
 
@@ -1673,6 +1728,14 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
     if (points_per_lane) *points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
     if (waves_per_group) *waves_per_group = o.waves_per_group ? o.waves_per_group : 4;
     if (ms_per_launch) *ms_per_launch = best_ms;
+    return SA_OK;
+  });
+}
+
+int sa_iga_set_timing(sa_iga *h, int32_t on) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    h->m.opt.timing = on ? 1 : 0;
     return SA_OK;
   });
 }

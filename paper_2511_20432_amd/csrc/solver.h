@@ -114,10 +114,12 @@ struct FusedPcg {
   int64_t vs, ts;
   double *part_rz;        // [2][np_rz] per path
   double *part_rr;        // [np_rz] per path
+  double *part_xx;        // [np_rz] per path: |x|^2 on the box (attainable-accuracy test)
   const double *part_pq;  int np_pq;
   const double *part_b;   int np_b;
   int np_rz;              // = m[1] m[2] (one partial per x-fiber)
   double rtol2;
+  double bw2;             // (64 eps |A|_inf)^2: also converged when |r|^2 <= bw2 |x|^2
   PcgScalars *sc;
   SolveStatus *status;
   const int64_t *scatter_idx;   // optional: scatter_out[scatter_idx[g]] = z[g]
@@ -126,6 +128,29 @@ struct FusedPcg {
 };
 bool fused_fits(const int m[3]);
 void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update);
-void launch_pcg_dir(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k);
+// convergence test and p = z + beta p; `last` (the final iteration of a fixed
+// budget) records the status without updating p
+void launch_pcg_dir(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool last);
+// the final iteration's x, r update and |r|^2 partials, without the
+// preconditioned residual (nothing uses it)
+void launch_pcg_last_update(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k);
+
+// Dirichlet projection solved exactly: vD = inv_area (Ib x Ia) b with the dense
+// inverses of the two 1-D trace mass factors, one workgroup per path; the
+// values are also scattered into the theta-step iterate (xfull[dofs[i]])
+struct DirDirect {
+  int na, nb;
+  const double *Ia, *Ib;   // na x na, nb x nb (symmetric)
+  double inv_area;
+  const double *b;         // gathered right-hand side, stride vs per path
+  double *vD;              // values, stride vs per path
+  int64_t vs;
+  const int64_t *dofs;
+  double *xfull;
+  int64_t xs;
+};
+size_t dir_direct_lds(int na, int nb);
+bool dir_direct_prepare(size_t lds);   // allow that much dynamic LDS for the kernel
+void launch_dir_direct(hipStream_t st, const SlotMap &sm, const DirDirect &a);
 
 }  // namespace sa

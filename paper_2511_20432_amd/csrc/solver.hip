@@ -473,6 +473,7 @@ __device__ __forceinline__ FusedPcg at_path(const FusedPcg &f, const SlotMap &sm
   if (g.t) g.t += p * f.ts;
   if (g.part_rz) g.part_rz += p * 2 * f.np_rz;
   if (g.part_rr) g.part_rr += p * f.np_rz;
+  if (g.part_xx) g.part_xx += p * f.np_rz;
   if (g.part_pq) g.part_pq += p * f.np_pq;
   if (g.part_b) g.part_b += p * f.np_b;
   g.sc += p;
@@ -520,17 +521,24 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k
       return;
     }
     const double alpha = rz / pq;
-    double rr = 0.0;
+    double rr = 0.0, xx = 0.0;
     for (int i = threadIdx.x; i < m0; i += blockDim.x) {
       const int64_t g = base + i;
-      f.x[g] = fma(alpha, f.p[g], f.x[g]);
+      const double xi = fma(alpha, f.p[g], f.x[g]);
+      f.x[g] = xi;
+      xx = fma(xi, xi, xx);
       const double ri = fma(-alpha, f.q[g], f.r[g]);
       f.r[g] = ri;
       fib[i] = ri;
       rr = fma(ri, ri, rr);
     }
     rr = bsum(rr, sh);
-    if (threadIdx.x == 0) f.part_rr[b] = rr;
+    xx = bsum(xx, sh);
+    if (threadIdx.x == 0) {
+      f.part_rr[b] = rr;
+      if (f.part_xx) f.part_xx[b] = xx;
+    }
+    if (first == 2) return;                 // last iteration: no preconditioned residual needed
   } else {
     for (int i = threadIdx.x; i < m0; i += blockDim.x) fib[i] = f.r[base + i];
     __syncthreads();
@@ -610,18 +618,21 @@ __global__ __launch_bounds__(kFib) void k_fd_xbwd(SlotMap sm, FusedPcg f0, int s
 }
 
 // convergence test on r.r; p = z + beta p on the box
-__global__ void k_pcg_dir(SlotMap sm, FusedPcg f0, int k) {
+__global__ void k_pcg_dir(SlotMap sm, FusedPcg f0, int k, int last) {
   __shared__ double sh[16];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
   if (f.sc->done) return;
   const double rr = reduce_n(f.part_rr, f.np_rz, sh);
   const double bb = reduce_n(f.part_b, f.np_b, sh);
-  const double rz_old = reduce_n(f.part_rz + (k & 1) * f.np_rz, f.np_rz, sh);
-  const double rz_new = reduce_n(f.part_rz + ((k + 1) & 1) * f.np_rz, f.np_rz, sh);
-  // |b| below 1e-140 lies at the FP64 underflow edge: relative accuracy is
-  // not attainable there and the solution is zero to that precision
-  const bool conv = rr <= f.rtol2 * bb || bb <= 1e-280;
-  if (!conv) {
+  const double xx = f.part_xx ? reduce_n(f.part_xx, f.np_rz, sh) : 0.0;
+  // converged: relative residual at the tolerance; or the residual at the
+  // FP64 rounding floor of the system (normwise backward error 64 eps), below
+  // which no iteration can go; or |b| at the FP64 underflow edge, where the
+  // solution is zero to that precision
+  const bool conv = rr <= f.rtol2 * bb || rr <= f.bw2 * xx || bb <= 1e-280;
+  if (!conv && !last) {
+    const double rz_old = reduce_n(f.part_rz + (k & 1) * f.np_rz, f.np_rz, sh);
+    const double rz_new = reduce_n(f.part_rz + ((k + 1) & 1) * f.np_rz, f.np_rz, sh);
     const double beta = rz_new / rz_old;
     const int m0 = f.m[0], m1 = f.m[1];
     const int64_t nbox = (int64_t)m0 * m1 * f.m[2];
@@ -655,12 +666,67 @@ void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k,
   hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, slot, first ? 1 : 0);
 }
 
-void launch_pcg_dir(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k) {
+void launch_pcg_dir(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool last) {
   if (sm.count <= 0) return;
   const int64_t nbox = (int64_t)f.m[0] * f.m[1] * f.m[2];
-  int64_t blocks = (nbox + kB - 1) / kB;
+  int64_t blocks = last ? 1 : (nbox + kB - 1) / kB;
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)blocks, (unsigned)sm.count), dim3(kB), 0, st, sm, f, k);
+  hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)blocks, (unsigned)sm.count), dim3(kB), 0, st, sm, f, k,
+                     last ? 1 : 0);
+}
+
+void launch_pcg_last_update(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k) {
+  if (sm.count <= 0) return;
+  const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
+  hipLaunchKernelGGL(k_fd_xfwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, k, 2);
+}
+
+// ---------------------------------------------------------------------------
+// Dirichlet projection by the exact inverse of a Kronecker trace mass matrix,
+// one workgroup per path, everything in LDS
+// ---------------------------------------------------------------------------
+constexpr int kDD = 1024;
+
+__global__ __launch_bounds__(kDD) void k_dir_direct(SlotMap sm, DirDirect a) {
+  extern __shared__ double lds[];
+  const int64_t pth = sm.path[blockIdx.x];
+  const int na = a.na, nb = a.nb, n = na * nb;
+  double *B = lds, *T = lds + n, *Ia = lds + 2 * n, *Ib = Ia + na * na;
+  const double *b = a.b + pth * a.vs;
+  for (int i = threadIdx.x; i < n; i += kDD) B[i] = b[i];
+  for (int i = threadIdx.x; i < na * na; i += kDD) Ia[i] = a.Ia[i];
+  for (int i = threadIdx.x; i < nb * nb; i += kDD) Ib[i] = a.Ib[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kDD) {          // along the first in-face direction
+    const int j0 = i % na, k1 = i / na;
+    double s = 0.0;
+    for (int k0 = 0; k0 < na; ++k0) s = fma(Ia[j0 * na + k0], B[k0 + na * k1], s);
+    T[i] = s;
+  }
+  __syncthreads();
+  double *vD = a.vD + pth * a.vs, *x = a.xfull + pth * a.xs;
+  for (int i = threadIdx.x; i < n; i += kDD) {          // along the second, scaled
+    const int j0 = i % na, j1 = i / na;
+    double s = 0.0;
+    for (int k1 = 0; k1 < nb; ++k1) s = fma(Ib[j1 * nb + k1], T[j0 + na * k1], s);
+    s *= a.inv_area;
+    vD[i] = s;
+    x[a.dofs[i]] = s;
+  }
+}
+
+size_t dir_direct_lds(int na, int nb) {
+  return (size_t)(2 * na * nb + na * na + nb * nb) * sizeof(double);
+}
+
+bool dir_direct_prepare(size_t lds) {
+  return hipFuncSetAttribute((const void *)k_dir_direct, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+         hipSuccess;
+}
+
+void launch_dir_direct(hipStream_t st, const SlotMap &sm, const DirDirect &a) {
+  if (sm.count <= 0) return;
+  hipLaunchKernelGGL(k_dir_direct, dim3((unsigned)sm.count), dim3(kDD), dir_direct_lds(a.na, a.nb), st, sm, a);
 }
 
 }  // namespace sa

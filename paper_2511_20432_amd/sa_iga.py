@@ -79,6 +79,7 @@ EXPORTS = {
     "sa_iga_eval_source_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, _dp, _dp, _dp]),
     "sa_iga_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_double)]),
+    "sa_iga_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "sa_iga_get_info": (C.c_int, [C.c_void_p, C.POINTER(sa_info)]),
     "sa_iga_get_stats": (C.c_int, [C.c_void_p, C.POINTER(sa_stats)]),
     "sa_iga_reset_stats": (C.c_int, [C.c_void_p]),
@@ -241,6 +242,9 @@ class Model:
 
     def reset_stats(self):
         check(self._lib.sa_iga_reset_stats(self.h))
+
+    def set_timing(self, on: bool):
+        check(self._lib.sa_iga_set_timing(self.h, 1 if on else 0))
 
     def autotune(self, reps: int = 3) -> dict:
         """Pick the fastest kernel-sum tile shape; results stay bitwise the same."""
