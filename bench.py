@@ -41,6 +41,12 @@ LANE_OPS = 256 * 64 * 2.4e9
 # ldexp, 5 accumulations
 SLOTS_FP32 = 9 + 4
 SLOTS_FP64 = 28
+# HBM bytes per k_sum launch of this workload's FP32 far-field form, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE over steps 1480..1779, scaled by the same
+# counters on a 256 MiB copy (profiles/k_sum_raster_fp32far.md).  Valid for
+# the kernel as profiled; a changed k_sum must set this to None until the
+# counters are taken again.
+K_SUM_TRAFFIC = {"read_bytes": 7.27e6, "written_bytes": 42.43e6}
 
 
 def _timed_run(model, warmup, steps, n_total):
@@ -309,7 +315,10 @@ def main():
                    "preconditioner": "fast diagonalisation"},
         "steps_per_s": steps / r["seconds"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Gpair/s",
-                     "frac": achieved / peak if peak else None, "traffic": None,
+                     "frac": achieved / peak if peak else None,
+                     "traffic": (K_SUM_TRAFFIC["read_bytes"] + K_SUM_TRAFFIC["written_bytes"])
+                     if (K_SUM_TRAFFIC and main_form == "fp32far") else None,
+                     "traffic_unit": "bytes per launch (HBM, read + written)",
                      "kernel": "k_sum", "avg_launch_ms": sum_ms / launches,
                      "pairs_per_launch": st["pairs"] / launches},
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
