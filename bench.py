@@ -212,6 +212,15 @@ def run_surrogate(window, n_train=2_000_000, epochs=4, seed=1):
         m, dt, st, tune, su = _batched_window(w, W.PRECISION_SURROGATE, window, start, surrogate_weights=blob, **kw)
         r = _window_report(w, form, window, dt, st, tune, su, seed)
         r.update({k: st[k] for k in ("net_steps", "pairs_net", "audits", "audit_failures", "audit_max_err")})
+        # network stage against the dense bf16 matrix-core peak: hidden-layer
+        # flops (3 layers of 256 x 256 per point) over the stage's device time
+        net_ms = st["stage_ms"]["net"]
+        flops = st["net_steps"] * 64512 * 3 * 2 * 256 * 256
+        if net_ms > 0 and flops > 0:
+            r["net_roofline"] = {"bound": "mfma", "achieved": flops / (net_ms * 1e-3) / 1e12,
+                                 "peak": 2500.0, "unit": "TFLOP/s",
+                                 "frac": flops / (net_ms * 1e-3) / 2.5e15,
+                                 "note": "stage time includes the far-energy bins, first-layer constants and audits"}
         r["max_err_K_vs_fp64"] = _max_err(m, ref)
         r["speedup_vs_fp64"] = out["fp64"]["ms_per_batched_step"] / r["ms_per_batched_step"]
         out[form] = r

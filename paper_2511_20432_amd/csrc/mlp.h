@@ -99,6 +99,30 @@ double reduce_loss_host(hipStream_t st, const double *loss_part, int n);
 void launch_adam(hipStream_t st, int64_t n, float *w, const float *g, float *m, float *v, float lr, float b1,
                  float b2, float eps, int t);
 
+// Whole network on boundary rows r0 .. r0+rows of the slot-major row space
+// (row r: slot r / nq, point r % nq), activations kept in registers: each
+// wave computes D = W H^T for 64 points (two 32-point MFMA column tiles),
+// and the 32 x 32 accumulator layout of one layer is the next layer's B
+// operand once the columns of W3 and W4 are permuted within 16-blocks
+// (launch_net_permute).  Writes the scaled far field like
+// launch_layer_out_field.
+struct NetArgs {
+  int64_t r0, rows, nq;
+  const float *pf;              // [nq][6]
+  const float *c;               // [slot][256] first-layer constants
+  const float *W1;              // [256][70] FP32
+  const bf16_t *W2, *W3p, *W4p; // [256][256] bfloat16 (W3, W4 column-permuted)
+  const float *b2, *b3, *b4, *W5, *b5;
+  double ts, gs;
+  int64_t ostride;
+  double *net;
+};
+size_t net_fused_lds();
+bool net_fused_prepare();
+void launch_net_fused(hipStream_t st, const NetArgs &a);
+// Wp[i][16 s + k] = W[i][16 s + swap23(k)] (bfloat16), swap23 exchanging bits 2 and 3
+void launch_net_permute(hipStream_t st, const bf16_t *W, bf16_t *Wp);
+
 // network inputs of one slot at nq points: X[q] = [pf[q] (6), bins (64)]
 void launch_net_inputs(hipStream_t st, int64_t nq, const float *pf, const float *bins, float *X);
 

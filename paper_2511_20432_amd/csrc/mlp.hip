@@ -14,19 +14,28 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kT = 256;
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return 0x7FC0;   // NaN
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// FP32 -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26:
+// erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2), t = 1 / (1 + p x),
+// |error| <= 1.5e-7 for x >= 0; odd extension for x < 0
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly =
+      fmaf(fmaf(fmaf(fmaf(1.061405429f, t, -1.453152027f), t, 1.421413741f), t, -0.284496736f), t, 0.254829592f) * t;
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * ax * ax);
+  return copysignf(fmaf(-poly, e, 1.0f), x);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,6 +339,148 @@ __global__ void k_net_inputs(int64_t nq, const float *__restrict__ pf, const flo
   X[i] = j < kMlpPoint ? pf[q * kMlpPoint + j] : bins[j - kMlpPoint];
 }
 
+// ---------------------------------------------------------------------------
+// fused network: registers hold the activations, LDS holds one weight matrix
+// ---------------------------------------------------------------------------
+constexpr int kNW = 4;                  // waves per workgroup (one per SIMD: 444 registers per wave)
+constexpr int kNRows = kNW * 32;        // rows per workgroup: 32 points per wave
+constexpr int kLdsLd = kMlpHid + 8;     // bfloat16 per LDS row of W (16 B padding)
+
+__device__ __forceinline__ int swap23(int k) { return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1); }
+
+__global__ void k_net_permute(const bf16_t *__restrict__ W, bf16_t *__restrict__ Wp) {
+  const int i = blockIdx.x, k = threadIdx.x;   // row, column
+  Wp[i * kMlpHid + k] = W[i * kMlpHid + (k & ~15) + swap23(k & 15)];
+}
+
+// stage W [256][256] into LDS rows of kLdsLd
+__device__ __forceinline__ void stage_w(const bf16_t *__restrict__ W, bf16_t *lw) {
+  __syncthreads();
+  for (int id = threadIdx.x; id < kMlpHid * (kMlpHid / 8); id += blockDim.x) {
+    const int row = id >> 5, c8 = id & 31;
+    *reinterpret_cast<u16x8_t *>(lw + row * kLdsLd + c8 * 8) =
+        *reinterpret_cast<const u16x8_t *>(W + row * kMlpHid + c8 * 8);
+  }
+  __syncthreads();
+}
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16); }
+
+// two 32-row output tiles t, t + 1 of a hidden layer: W rows 32 t .. 32 t + 63
+// times the 32 points' activations B (16 k-slices of 8 bfloat16 as 4 packed
+// words); two independent accumulator chains keep the matrix pipe busy
+__device__ __forceinline__ void net_tiles(const bf16_t *lw, const u32x4_t (&B)[16], int t, int li, int hh,
+                                          f32x16_t &acc0, f32x16_t &acc1) {
+  acc0 = f32x16_t{};
+  acc1 = f32x16_t{};
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const u16x8_t a0 = *reinterpret_cast<const u16x8_t *>(lw + (32 * t + li) * kLdsLd + 16 * s + 8 * hh);
+    const u16x8_t a1 = *reinterpret_cast<const u16x8_t *>(lw + (32 * t + 32 + li) * kLdsLd + 16 * s + 8 * hh);
+    const bf16x8_t b = __builtin_bit_cast(bf16x8_t, B[s]);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a0), b, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a1), b, acc1, 0, 0, 0);
+  }
+}
+
+// bias + GELU + bfloat16 of tile t into the next layer's B operand: element
+// 4 ((r/4) & 1) + r % 4 of slice 2 t + r / 8 holds feature 32 t + 8 (r/4) + 4 hh + r % 4
+// (the order the permuted W3, W4 columns expect)
+__device__ __forceinline__ void net_store(const f32x16_t &acc, const float *__restrict__ bias, int t, int hh,
+                                          u32x4_t (&Bn)[16]) {
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) {
+    const int f = 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3);
+    Bn[2 * t + (r >> 3)][(4 * ((r >> 2) & 1) + (r & 3)) >> 1] =
+        pack2(gelu(acc[r] + bias[f]), gelu(acc[r + 1] + bias[f + 1]));
+  }
+}
+
+__device__ __forceinline__ void net_hidden(const bf16_t *lw, const u32x4_t (&B)[16], const float *__restrict__ bias,
+                                           int li, int hh, u32x4_t (&Bn)[16]) {
+#pragma unroll
+  for (int t = 0; t < 8; t += 2) {
+    f32x16_t acc0, acc1;
+    net_tiles(lw, B, t, li, hh, acc0, acc1);
+    net_store(acc0, bias, t, hh, Bn);
+    net_store(acc1, bias, t + 1, hh, Bn);
+  }
+}
+
+// last hidden layer: h4 = bf16(gelu(z4)) of tile t into the FP32 output layer
+__device__ __forceinline__ void net_out_acc(const f32x16_t &acc, const float *__restrict__ b4,
+                                            const float *__restrict__ W5, int t, int hh, float (&y)[4]) {
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    const int f = 32 * t + 8 * (rr >> 2) + 4 * hh + (rr & 3);
+    const float h = bf2f(f2bf(gelu(acc[rr] + b4[f])));
+#pragma unroll
+    for (int o = 0; o < 4; ++o) y[o] = fmaf(W5[o * kMlpHid + f], h, y[o]);
+  }
+}
+
+__global__ __launch_bounds__(kNW * 64, 1) void k_net_fused(NetArgs a) {
+  extern __shared__ __align__(16) unsigned char net_lds[];
+  bf16_t *lw = reinterpret_cast<bf16_t *>(net_lds);
+  float *w1 = reinterpret_cast<float *>(net_lds + (size_t)kMlpHid * kLdsLd * sizeof(bf16_t));   // [256][6]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 31, hh = lane >> 5;
+  for (int i = threadIdx.x; i < kMlpHid * kMlpPoint; i += blockDim.x)
+    w1[i] = a.W1[(i / kMlpPoint) * kMlpIn + i % kMlpPoint];
+  __syncthreads();
+
+  // first layer (FP32): lane holds features 16 s + 8 hh + e of its point
+  const int64_t lr = (int64_t)blockIdx.x * kNRows + 32 * w + li;
+  const bool valid = lr < a.rows;
+  const int64_t r = a.r0 + (valid ? lr : 0);
+  const int64_t slot = r / a.nq, q = r % a.nq;
+  float x[kMlpPoint];
+#pragma unroll
+  for (int d = 0; d < kMlpPoint; ++d) x[d] = valid ? a.pf[q * kMlpPoint + d] : 0.0f;
+  const float *cs = a.c + slot * kMlpHid;
+  u32x4_t B[16], Bn[16];
+#pragma unroll
+  for (int sl = 0; sl < 16; ++sl)
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      float v[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int f = 16 * sl + 8 * hh + e + k;
+        v[k] = cs[f];
+#pragma unroll
+        for (int d = 0; d < kMlpPoint; ++d) v[k] = fmaf(w1[f * kMlpPoint + d], x[d], v[k]);
+      }
+      B[sl][e >> 1] = pack2(gelu(v[0]), gelu(v[1]));
+    }
+
+  stage_w(a.W2, lw);
+  net_hidden(lw, B, a.b2, li, hh, Bn);
+  stage_w(a.W3p, lw);
+  net_hidden(lw, Bn, a.b3, li, hh, B);
+  stage_w(a.W4p, lw);
+  // last hidden layer: h4 = bf16(gelu(z4)) straight into the FP32 output layer
+  float y[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int t = 0; t < 8; t += 2) {
+    f32x16_t acc0, acc1;
+    net_tiles(lw, B, t, li, hh, acc0, acc1);
+    net_out_acc(acc0, a.b4, a.W5, t, hh, y);
+    net_out_acc(acc1, a.b4, a.W5, t + 1, hh, y);
+  }
+#pragma unroll
+  for (int o = 0; o < 4; ++o) y[o] += __shfl_xor(y[o], 32, 64);   // the two lane halves hold one point
+  if (hh == 0 && valid) {
+    double *out = a.net + slot * 4 * a.ostride + q;
+    out[0] = a.ts * (double)(y[0] + a.b5[0]);
+    out[a.ostride] = a.gs * (double)(y[1] + a.b5[1]);
+    out[2 * a.ostride] = a.gs * (double)(y[2] + a.b5[2]);
+    out[3 * a.ostride] = a.gs * (double)(y[3] + a.b5[3]);
+  }
+}
+
 inline unsigned nblk(int64_t n, int b = kT) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -416,6 +567,24 @@ void launch_adam(hipStream_t st, int64_t n, float *w, const float *g, float *m, 
                  float b2, float eps, int t) {
   const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
   if (n > 0) hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(kT), 0, st, n, w, g, m, v, lr, b1, b2, eps, c1, c2);
+}
+
+size_t net_fused_lds() {
+  return (size_t)kMlpHid * kLdsLd * sizeof(bf16_t) + (size_t)kMlpHid * kMlpPoint * sizeof(float);
+}
+
+bool net_fused_prepare() {
+  return hipFuncSetAttribute((const void *)k_net_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)net_fused_lds()) == hipSuccess;
+}
+
+void launch_net_fused(hipStream_t st, const NetArgs &a) {
+  if (a.rows <= 0) return;
+  hipLaunchKernelGGL(k_net_fused, dim3(nblk(a.rows, kNRows)), dim3(kNW * 64), net_fused_lds(), st, a);
+}
+
+void launch_net_permute(hipStream_t st, const bf16_t *W, bf16_t *Wp) {
+  hipLaunchKernelGGL(k_net_permute, dim3(kMlpHid), dim3(kMlpHid), 0, st, W, Wp);
 }
 
 void launch_net_inputs(hipStream_t st, int64_t nq, const float *pf, const float *bins, float *X) {

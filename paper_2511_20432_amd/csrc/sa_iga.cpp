@@ -157,6 +157,8 @@ struct sa_iga {
   double net_T = 1, net_G = 1, net_E = 1;   // output and input scales
   float *nw = nullptr;                  // FP32 parameters
   sa::bf16_t *nWb[3] = {};              // layers 2..4 in bfloat16
+  sa::bf16_t *nW3p = nullptr, *nW4p = nullptr;   // W3, W4 with columns permuted for the fused kernel
+  bool net_fused = false;
   float *cvec = nullptr;                // [kMaxBatch][256] first-layer constants
   double *netf = nullptr;               // [kMaxBatch][4][stride] network far field
   sa::bf16_t *hA = nullptr, *hB = nullptr;  // [net_rows][256] activations
@@ -486,6 +488,29 @@ void run_network(sa_iga *h, const sa::PathTab &tab, int64_t nq, const float *pf,
   sa::launch_far_bins(h->stream, tab, h->sbin, h->sE, h->net_E, h->bins);
   sa::launch_layer1_const(h->stream, tab.count, h->bins, W1, b1, h->cvec);
   const int64_t total = (int64_t)tab.count * nq, H = sa::kMlpHid;
+  if (h->net_fused) {
+    sa::NetArgs na{};
+    na.r0 = 0;
+    na.rows = total;
+    na.nq = nq;
+    na.pf = pf;
+    na.c = h->cvec;
+    na.W1 = W1;
+    na.W2 = h->nWb[0];
+    na.W3p = h->nW3p;
+    na.W4p = h->nW4p;
+    na.b2 = h->nw + sa::MlpLayout::b2;
+    na.b3 = h->nw + sa::MlpLayout::b3;
+    na.b4 = h->nw + sa::MlpLayout::b4;
+    na.W5 = h->nw + sa::MlpLayout::W5;
+    na.b5 = h->nw + sa::MlpLayout::b5;
+    na.ts = h->net_T;
+    na.gs = h->net_G;
+    na.ostride = ostride;
+    na.net = out;
+    sa::launch_net_fused(h->stream, na);
+    return;
+  }
   const int64_t bias[3] = {sa::MlpLayout::b2, sa::MlpLayout::b3, sa::MlpLayout::b4};
   for (int64_t r0 = 0; r0 < total; r0 += h->net_rows) {
     const int64_t rows = std::min(h->net_rows, total - r0);
@@ -992,6 +1017,12 @@ void build_network_state(sa_iga *h, const sa_patch *patch, const sa_scan_path *s
     h->nWb[l] = dev_alloc<sa::bf16_t>(h->owned, (size_t)sa::kMlpHid * sa::kMlpHid);
     sa::launch_to_bf16(h->stream, (int64_t)sa::kMlpHid * sa::kMlpHid, h->nw + off[l], h->nWb[l]);
   }
+  h->nW3p = dev_alloc<sa::bf16_t>(h->owned, (size_t)sa::kMlpHid * sa::kMlpHid);
+  h->nW4p = dev_alloc<sa::bf16_t>(h->owned, (size_t)sa::kMlpHid * sa::kMlpHid);
+  sa::launch_net_permute(h->stream, h->nWb[1], h->nW3p);
+  sa::launch_net_permute(h->stream, h->nWb[2], h->nW4p);
+  h->net_fused = sa::net_fused_lds() + 1024 <= h->lds_per_block && sa::net_fused_prepare() &&
+                 !std::getenv("SA_IGA_NET_LAYERWISE");
   h->cvec = dev_zeros<float>(h, (size_t)sa::kMaxBatch * sa::kMlpHid);
   h->netf = dev_zeros<double>(h, (size_t)sa::kMaxBatch * 4 * h->stride);
   h->net_rows = std::min<int64_t>(131072, (int64_t)sa::kMaxBatch * h->stride);

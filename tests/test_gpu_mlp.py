@@ -172,3 +172,22 @@ def test_surrogate_audit_falls_back_to_exact():
     # after the failed audits the far part is exact: the last step is the FP64 form's
     for a, b in zip(gm.boundary_fields(), ref.boundary_fields()):
         assert np.array_equal(a, b)
+
+
+def test_fused_network_matches_layerwise(monkeypatch):
+    """The register-resident fused network and the layer-by-layer GEMM path
+    give the same far field (to bfloat16 rounding of the activations)."""
+    tr = surrogate_track()
+    scan = W.make_scan([tr], 1e-5, 5, n_steps=[20])
+    tau = 5e-5
+    _, p = _net(9)
+    a = _surrogate_model(scan, p, tau, audit_tol=1e30, audit_every=100)
+    monkeypatch.setenv("SA_IGA_NET_LAYERWISE", "1")
+    b = _surrogate_model(scan, p, tau, audit_tol=1e30, audit_every=100)
+    a.step(20)
+    b.step(20)
+    Ta, Ga = a.boundary_fields()[:2]
+    Tb, Gb = b.boundary_fields()[:2]
+    e_T, e_G = rel(Ta, Tb), rel(Ga, Gb)
+    print(f"fused vs layer-wise: T rel {e_T:.2e}, grad rel {e_G:.2e}", flush=True)
+    assert e_T <= 1e-2 and e_G <= 1e-2
