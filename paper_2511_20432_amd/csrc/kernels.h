@@ -14,6 +14,10 @@ namespace sa {
 // (in base 2 for the FP32 record), so that T~_i(x) = exp(arg_i) and
 // grad T~_i(x) = exp(arg_i) (2 c_i x + u_i).
 constexpr int kCoefStride = 8;
+// FP32 far-field tile: the sources summed in FP32 before folding into FP64,
+// and the aligned block whose first source is the origin of its FP32 records.
+// Far-field chunks start at multiples of it.
+constexpr int kTile32 = 128;
 
 // Paths advanced by one launch (by value in the kernel arguments).  Slot s
 // holds path `path[s]`, whose sources start at row src0[s] of the global

@@ -120,16 +120,23 @@ __global__ void k_coeff(PathTab tab, const int64_t *__restrict__ tick, const dou
   o[6] = 0.0;
   o[7] = 0.0;
   if (j < tab.n_far[slot]) {
+    // FP32 record in base 2, relative to the origin o of its aligned block of
+    // kTile32 sources (the block's first source, rounded to FP32): the
+    // exponent c |x - o|^2 + u'.(x - o) + K' then cancels little for the
+    // points near the block, where its terms matter
+    const int64_t ib = tab.src0[slot] + (j & ~(int64_t)(kTile32 - 1));
+    const float ofx = (float)sx[ib], ofy = (float)sy[ib], ofz = (float)sz[ib];
+    const double rx = x - (double)ofx, ry = y - (double)ofy, rz = z - (double)ofz;
     const double l2e = 1.4426950408889634;
     float *f = c32 + i * kCoefStride;
     f[0] = (float)(c * l2e);
-    f[1] = (float)(-2.0 * c * x * l2e);
-    f[2] = (float)(-2.0 * c * y * l2e);
-    f[3] = (float)(-2.0 * c * z * l2e);
-    f[4] = (float)(K * l2e);
-    f[5] = 0.0f;
-    f[6] = 0.0f;
-    f[7] = 0.0f;
+    f[1] = (float)(-2.0 * c * rx * l2e);
+    f[2] = (float)(-2.0 * c * ry * l2e);
+    f[3] = (float)(-2.0 * c * rz * l2e);
+    f[4] = (float)((c * (rx * rx + ry * ry + rz * rz) + log(amp)) * l2e);
+    f[5] = ofx;
+    f[6] = ofy;
+    f[7] = ofz;
   }
 }
 
@@ -154,7 +161,6 @@ struct SumArgs {
   int n_chunks_far, n_chunks, chunk_far, chunk_near;
 };
 
-constexpr int kTile32 = 128;   // FP32 sources summed before folding into FP64
 
 template <int P>
 __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
   if (chunk < a.n_chunks_far) {
     const int lo = chunk * a.chunk_far;
     const int hi = tab.mode[slot] ? lo : (lo + a.chunk_far < n_far ? lo + a.chunk_far : n_far);
-    float xf[P], yf[P], zf[P], qf[P];
+    float xf[P], yf[P], zf[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       int64_t q = base + 64 * j;
@@ -191,23 +197,32 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
       xf[j] = a.fx[q];
       yf[j] = a.fy[q];
       zf[j] = a.fz[q];
-      qf[j] = a.fq2[q];
     }
     const double ln2 = 0.6931471805599453;
+    // tiles are the aligned blocks of the FP32 records (lo is a multiple of kTile32)
     for (int t0 = lo; t0 < hi; t0 += kTile32) {
       const int t1 = t0 + kTile32 < hi ? t0 + kTile32 : hi;
+      const float *ob = c32 + (int64_t)t0 * kCoefStride;
+      const float ox = ob[5], oy = ob[6], oz = ob[7];
+      float rxf[P], ryf[P], rzf[P], qf[P];
       float f0[P], f1[P], fx_[P], fy_[P], fz_[P];
 #pragma unroll
-      for (int j = 0; j < P; ++j) f0[j] = f1[j] = fx_[j] = fy_[j] = fz_[j] = 0.0f;
+      for (int j = 0; j < P; ++j) {
+        rxf[j] = xf[j] - ox;
+        ryf[j] = yf[j] - oy;
+        rzf[j] = zf[j] - oz;
+        qf[j] = fmaf(rxf[j], rxf[j], fmaf(ryf[j], ryf[j], rzf[j] * rzf[j]));
+        f0[j] = f1[j] = fx_[j] = fy_[j] = fz_[j] = 0.0f;
+      }
       for (int i = t0; i < t1; ++i) {
         const float *c = c32 + (int64_t)i * kCoefStride;
         const float cc = c[0], ux = c[1], uy = c[2], uz = c[3], K = c[4];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           float arg = fmaf(cc, qf[j], K);
-          arg = fmaf(ux, xf[j], arg);
-          arg = fmaf(uy, yf[j], arg);
-          arg = fmaf(uz, zf[j], arg);
+          arg = fmaf(ux, rxf[j], arg);
+          arg = fmaf(uy, ryf[j], arg);
+          arg = fmaf(uz, rzf[j], arg);
           const float e = __builtin_amdgcn_exp2f(arg);
           f0[j] += e;
           f1[j] = fmaf(e, cc, f1[j]);
@@ -216,13 +231,16 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
           fz_[j] = fmaf(e, uz, fz_[j]);
         }
       }
+      // back to the centred form grad = 2 x S1 + S_u of the partials:
+      // sum e u = sum e u' - 2 o sum e c
 #pragma unroll
       for (int j = 0; j < P; ++j) {
+        const double g1 = (double)f1[j];
         s0[j] += (double)f0[j];
-        s1[j] += ln2 * (double)f1[j];
-        sx[j] += ln2 * (double)fx_[j];
-        sy[j] += ln2 * (double)fy_[j];
-        sz[j] += ln2 * (double)fz_[j];
+        s1[j] += ln2 * g1;
+        sx[j] += ln2 * ((double)fx_[j] - 2.0 * (double)ox * g1);
+        sy[j] += ln2 * ((double)fy_[j] - 2.0 * (double)oy * g1);
+        sz[j] += ln2 * ((double)fz_[j] - 2.0 * (double)oz * g1);
       }
     }
   } else {

@@ -279,8 +279,10 @@ sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int count, int64_t max_far, i
   pl.waves = o.waves_per_group ? std::min(o.waves_per_group, 8) : 4;
   pl.nq = nq;
   pl.chunk_far = pl.chunk_near = 1;
+  auto tile_up = [](int64_t n) { return (n + sa::kTile32 - 1) / sa::kTile32 * sa::kTile32; };
   if (o.chunk_sources > 0) {
-    pl.chunk_far = pl.chunk_near = o.chunk_sources;
+    pl.chunk_near = o.chunk_sources;
+    pl.chunk_far = (int)tile_up(o.chunk_sources);   // far chunks start on FP32 record blocks
     pl.n_chunks_far = (int)((max_far + pl.chunk_far - 1) / pl.chunk_far);
     pl.n_chunks_near = (int)((max_near + pl.chunk_near - 1) / pl.chunk_near);
     return pl;
@@ -299,7 +301,7 @@ sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int count, int64_t max_far, i
   }
   const int64_t min_chunk = 32;
   if (cf) {
-    const int64_t len = std::max<int64_t>(min_chunk, (max_far + cf - 1) / cf);
+    const int64_t len = tile_up(std::max<int64_t>(min_chunk, (max_far + cf - 1) / cf));
     pl.chunk_far = (int)len;
     pl.n_chunks_far = (int)((max_far + len - 1) / len);
   }
