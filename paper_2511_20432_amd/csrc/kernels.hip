@@ -214,6 +214,8 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
         qf[j] = fmaf(rxf[j], rxf[j], fmaf(ryf[j], ryf[j], rzf[j] * rzf[j]));
         f0[j] = f1[j] = fx_[j] = fy_[j] = fz_[j] = 0.0f;
       }
+      // unrolled so that the scalar loads of the next records are in flight
+#pragma unroll 8
       for (int i = t0; i < t1; ++i) {
         const float *c = c32 + (int64_t)i * kCoefStride;
         const float cc = c[0], ux = c[1], uy = c[2], uz = c[3], K = c[4];
