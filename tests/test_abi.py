@@ -101,3 +101,22 @@ def test_null_arguments():
     assert out.value is None
     lib.sa_iga_destroy(None)
     assert isinstance(lib.sa_iga_last_error(), bytes)
+    p, w, ms = C.c_int32(), C.c_int32(), C.c_double()
+    assert lib.sa_iga_autotune(None, 1, C.byref(p), C.byref(w), C.byref(ms)) == sa_iga.SA_EINVAL
+    assert lib.sa_iga_set_timing(None, 1) == sa_iga.SA_EINVAL
+    assert lib.sa_iga_far_field(None, 0, 1, 0.1, None, None, None) == sa_iga.SA_EINVAL
+    assert lib.sa_iga_save(None, None, None) == sa_iga.SA_EINVAL
+    assert lib.sa_iga_load(None, None, 0) == sa_iga.SA_EINVAL
+    # the network trainer: NULL and size checks come before any device call
+    h = C.c_void_p(1)
+    assert lib.sa_mlp_create(None, 0, C.byref(h)) == sa_iga.SA_EINVAL
+    assert h.value is None
+    prm = np.zeros(10, np.float32)
+    assert lib.sa_mlp_create(prm.ctypes.data_as(C.POINTER(C.c_float)), 10, C.byref(h)) == sa_iga.SA_EINVAL
+    bad = np.zeros(sa_iga.Mlp.n_params(), np.float32)
+    bad[3] = np.nan
+    assert lib.sa_mlp_create(bad.ctypes.data_as(C.POINTER(C.c_float)), len(bad), C.byref(h)) == sa_iga.SA_EINVAL
+    assert lib.sa_mlp_forward(None, 1, None, None) == sa_iga.SA_EINVAL
+    assert lib.sa_mlp_train_step(None, 1, None, None, 1e-3, None) == sa_iga.SA_EINVAL
+    assert lib.sa_mlp_gradients(None, 1, None, None, None, None) == sa_iga.SA_EINVAL
+    lib.sa_mlp_destroy(None)

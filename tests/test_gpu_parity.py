@@ -94,6 +94,22 @@ def test_small_block_jacobi_and_theta():
     assert gm.stats()["pcg_iterations"] > 6
 
 
+@pytest.mark.parametrize("theta,scale", [(1.0, 1.0), (0.5, 2.0), (0.0, 1.0)])
+def test_theta_and_kernel_scale_options(theta, scale):
+    """Fully implicit and explicit theta-steps with the exact Kronecker
+    preconditioner, and the kernel scale s = 2 (the whole absorbed energy
+    in the half-space), against the oracle."""
+    patch = W.small_block()
+    scan = W.single_track((0.1e-3, 0.2e-3, 0.5e-3), (0.9e-3, 0.25e-3, 0.5e-3), 60.0, 1.0, 1e-5, 5)
+    opts = W.Options(theta=theta, kernel_scale=scale)
+    gm = _gpu_model(patch, W.MAT_CFG, scan, options=opts)
+    om = solver.Model(patch, W.MAT_CFG, scan, theta=theta, kernel_scale=scale)
+    gm.step(7)
+    om.advance(7)
+    errs = _compare(gm, om, f"theta={theta} s={scale}")
+    assert max(errs.values()) <= TOL64, errs
+
+
 def test_annulus_nurbs_fp64():
     """Curved NURBS patch (left-handed parametrisation): FD is only a
     preconditioner there, so PCG iterates."""
