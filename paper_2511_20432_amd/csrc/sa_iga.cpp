@@ -1349,6 +1349,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
           a.vs = h->nDa;
           a.dofs = h->dir_dofs;
           a.xs = nd;
+          a.tmp = dev_zeros<double>(h, (size_t)S * na * nb);
           h->dir_direct = true;
         }
       }

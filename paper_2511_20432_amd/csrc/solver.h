@@ -148,6 +148,7 @@ struct DirDirect {
   const int64_t *dofs;
   double *xfull;
   int64_t xs;
+  double *tmp;             // optional [path][na nb] scratch: two passes over many workgroups
 };
 size_t dir_direct_lds(int na, int nb);
 bool dir_direct_prepare(size_t lds);   // allow that much dynamic LDS for the kernel

@@ -715,6 +715,41 @@ __global__ __launch_bounds__(kDD) void k_dir_direct(SlotMap sm, DirDirect a) {
   }
 }
 
+// the same two passes spread over the chip: one workgroup per column of the
+// first in-face direction, then one per row of the second
+__global__ __launch_bounds__(64) void k_dir_cols(SlotMap sm, DirDirect a) {
+  __shared__ double col[256];
+  const int64_t pth = sm.path[blockIdx.y];
+  const int na = a.na, k1 = blockIdx.x;
+  const double *b = a.b + pth * a.vs + (int64_t)na * k1;
+  for (int i = threadIdx.x; i < na; i += 64) col[i] = b[i];
+  __syncthreads();
+  double *T = a.tmp + pth * (int64_t)na * a.nb + (int64_t)na * k1;
+  for (int j0 = threadIdx.x; j0 < na; j0 += 64) {
+    double s = 0.0;
+    for (int k0 = 0; k0 < na; ++k0) s = fma(a.Ia[j0 * na + k0], col[k0], s);
+    T[j0] = s;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_dir_rows(SlotMap sm, DirDirect a) {
+  __shared__ double row[256];
+  const int64_t pth = sm.path[blockIdx.y];
+  const int na = a.na, nb = a.nb, j0 = blockIdx.x;
+  const double *T = a.tmp + pth * (int64_t)na * nb;
+  for (int k = threadIdx.x; k < nb; k += 64) row[k] = T[j0 + (int64_t)na * k];
+  __syncthreads();
+  double *vD = a.vD + pth * a.vs, *x = a.xfull + pth * a.xs;
+  for (int j1 = threadIdx.x; j1 < nb; j1 += 64) {
+    double s = 0.0;
+    for (int k1 = 0; k1 < nb; ++k1) s = fma(a.Ib[j1 * nb + k1], row[k1], s);
+    s *= a.inv_area;
+    const int64_t i = j0 + (int64_t)na * j1;
+    vD[i] = s;
+    x[a.dofs[i]] = s;
+  }
+}
+
 size_t dir_direct_lds(int na, int nb) {
   return (size_t)(2 * na * nb + na * na + nb * nb) * sizeof(double);
 }
@@ -726,6 +761,11 @@ bool dir_direct_prepare(size_t lds) {
 
 void launch_dir_direct(hipStream_t st, const SlotMap &sm, const DirDirect &a) {
   if (sm.count <= 0) return;
+  if (a.tmp && a.na <= 256 && a.nb <= 256) {
+    hipLaunchKernelGGL(k_dir_cols, dim3((unsigned)a.nb, (unsigned)sm.count), dim3(64), 0, st, sm, a);
+    hipLaunchKernelGGL(k_dir_rows, dim3((unsigned)a.na, (unsigned)sm.count), dim3(64), 0, st, sm, a);
+    return;
+  }
   hipLaunchKernelGGL(k_dir_direct, dim3((unsigned)sm.count), dim3(kDD), dir_direct_lds(a.na, a.nb), st, sm, a);
 }
 
