@@ -755,14 +755,16 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     };
     sa::launch_fd_pass(h->stream, sm, f, 0, true, false);
     if (h->fd_exact) {
+      // with the exact preconditioner the first iteration nearly always
+      // converges: test |r| right after the update, and run the FD solve and
+      // the new direction only for paths still going (the others exit at once)
       for (int k = 0; k < h->pcg_budget; ++k) {
         apply();
+        sa::launch_pcg_last_update(h->stream, sm, f, k);
+        sa::launch_pcg_dir(h->stream, sm, f, k, true);
         if (k + 1 < h->pcg_budget) {
-          sa::launch_fd_pass(h->stream, sm, f, k, false, true);
+          sa::launch_fd_pass(h->stream, sm, f, k, false, false);
           sa::launch_pcg_dir(h->stream, sm, f, k, false);
-        } else {
-          sa::launch_pcg_last_update(h->stream, sm, f, k);
-          sa::launch_pcg_dir(h->stream, sm, f, k, true);
         }
       }
     } else {

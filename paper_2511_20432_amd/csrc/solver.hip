@@ -504,7 +504,8 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k
   const int b = blockIdx.x;
   const int k1 = b % m1, k2 = b / m1;
   const int64_t base = full_index(f, 0, k1, k2);
-  if (!first) {
+  // first: 1 = transform r only; 0 = PCG update, then transform; 2 = update only
+  if (first != 1) {
     const double rz = reduce_n(f.part_rz + (k & 1) * f.np_rz, f.np_rz, sh);
     const double pq = reduce_n(f.part_pq, f.np_pq, sh);
     if (rz == 0.0 || !(pq > 0.0)) {
