@@ -43,10 +43,20 @@ SLOTS_FP32 = 9 + 4
 SLOTS_FP64 = 28
 # HBM bytes per k_sum launch of this workload's FP32 far-field form, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE over steps 1480..1779, scaled by the same
-# counters on a 256 MiB copy (profiles/k_sum_raster_fp32far.md).  Valid for
-# the kernel as profiled; a changed k_sum must set this to None until the
-# counters are taken again.
-K_SUM_TRAFFIC = None
+# counters on a 256 MiB copy (profiles/k_sum_raster_fp32far.md), with the
+# tile shape fixed at 2 points per lane and 2 waves per group.  Valid for the
+# kernel as profiled and only when the tuner picks that shape; a changed k_sum
+# must set this to None until the counters are taken again.  Most of the
+# written bytes are the per-chunk FP64 partial sums that k_finalize reads.
+K_SUM_TRAFFIC = {"read_bytes": 6.74e6, "written_bytes": 35.79e6, "points_per_lane": 2, "waves_per_group": 2}
+
+
+def _k_sum_traffic(form, tune):
+    t = K_SUM_TRAFFIC
+    if not t or form != "fp32far" or (tune.get("points_per_lane"), tune.get("waves_per_group")) != \
+            (t["points_per_lane"], t["waves_per_group"]):
+        return None
+    return t["read_bytes"] + t["written_bytes"]
 
 
 def _timed_run(model, warmup, steps, n_total):
@@ -77,7 +87,7 @@ def _timed_run(model, warmup, steps, n_total):
     return dt, model.stats()
 
 
-def run_form(w, precision, warmup, steps):
+def run_form(w, precision, warmup, steps, tile=None):
     """The timed steps run twice from the same state: without per-stage
     events (the throughput) and with them (the stage times and the kernel-sum
     launch durations of the roofline)."""
@@ -85,9 +95,11 @@ def run_form(w, precision, warmup, steps):
     from paper_2511_20432_amd import workloads as W
     opts = W.Options(precision=precision, tau_near=2e-4)
     t0 = time.perf_counter()
-    m = sa_iga.Model(w.patch, w.material, w.scan, opts, timing=0)
+    shape = {} if tile is None else {"points_per_lane": tile[0], "waves_per_group": tile[1]}
+    m = sa_iga.Model(w.patch, w.material, w.scan, opts, timing=0, **shape)
     setup_s = time.perf_counter() - t0
-    tune = m.autotune(reps=3)
+    tune = m.autotune(reps=3) if tile is None else {"points_per_lane": tile[0], "waves_per_group": tile[1],
+                                                     "ms_per_launch": None, "fixed": True}
     n_total = int(w.scan.n_steps[0])
     initial = m.save()
     dt, st = _timed_run(m, warmup, steps, n_total)
@@ -262,6 +274,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32far,fp64")
+    ap.add_argument("--tile", default=None,
+                    help="kernel-sum tile shape 'P,W' (points per lane, waves per group) instead of the tuner")
     ap.add_argument("--batched-window", type=int, default=60,
                     help="timed steps of the 128-strategy batch (0: skip)")
     ap.add_argument("--surrogate-window", type=int, default=60,
@@ -287,7 +301,8 @@ def main():
     for f in forms:
         prec = {"fp32far": W.PRECISION_FP32_FAR, "fp64": W.PRECISION_FP64}[f]
         print(f"[bench] form {f}: setup + {args.warmup} warmup + {steps} timed steps", file=sys.stderr, flush=True)
-        m, dt, st, setup_s = run_form(w, prec, args.warmup, steps)
+        tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+        m, dt, st, setup_s = run_form(w, prec, args.warmup, steps, tile)
         res[f] = {"seconds": dt, "stats": st, "setup_s": setup_s}
         models[f] = m
         print(f"[bench] form {f}: {dt:.3f} s, {st['pairs'] / dt:.3e} pairs/s, "
@@ -325,8 +340,7 @@ def main():
         "steps_per_s": steps / r["seconds"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Gpair/s",
                      "frac": achieved / peak if peak else None,
-                     "traffic": (K_SUM_TRAFFIC["read_bytes"] + K_SUM_TRAFFIC["written_bytes"])
-                     if (K_SUM_TRAFFIC and main_form == "fp32far") else None,
+                     "traffic": _k_sum_traffic(main_form, st["autotune"]),
                      "traffic_unit": "bytes per launch (HBM, read + written)",
                      "kernel": "k_sum", "avg_launch_ms": sum_ms / launches,
                      "pairs_per_launch": st["pairs"] / launches},
