@@ -98,8 +98,8 @@ def run_form(w, precision, warmup, steps, tile=None):
     shape = {} if tile is None else {"points_per_lane": tile[0], "waves_per_group": tile[1]}
     m = sa_iga.Model(w.patch, w.material, w.scan, opts, timing=0, **shape)
     setup_s = time.perf_counter() - t0
-    tune = m.autotune(reps=3) if tile is None else {"points_per_lane": tile[0], "waves_per_group": tile[1],
-                                                     "ms_per_launch": None, "fixed": True}
+    tune = m.autotune(reps=16) if tile is None else {"points_per_lane": tile[0], "waves_per_group": tile[1],
+                                                      "ms_per_step": None, "fixed": True}
     n_total = int(w.scan.n_steps[0])
     initial = m.save()
     dt, st = _timed_run(m, warmup, steps, n_total)
@@ -357,7 +357,9 @@ def main():
                        "sum_gpair_s": s64["pairs"] / (s64["stage_ms"]["sum"] * 1e-3) / 1e9
                        if s64["stage_ms"]["sum"] > 0 else None,
                        "sum_frac_of_fp64_peak": (s64["pairs"] / (s64["stage_ms"]["sum"] * 1e-3))
-                       / (LANE_OPS / SLOTS_FP64) if s64["stage_ms"]["sum"] > 0 else None}
+                       / (LANE_OPS / SLOTS_FP64) if s64["stage_ms"]["sum"] > 0 else None,
+                       "stage_ms_per_step": {k: v / steps for k, v in s64["stage_ms"].items()},
+                       "autotune": s64["autotune"]}
         out["speedup_vs_fp64"] = t64 / r["seconds"]
         out["max_err_K_vs_fp64"] = max_err
         out["max_err_at_step"] = err_step

@@ -191,9 +191,14 @@ int sa_iga_setup(const sa_patch *patch, const sa_material *mat, const sa_scan_pa
 
 /*
  * Advance every path by n_steps theta-steps (Eq. 20); a path that has done
- * its n_steps[p] steps stays as it is.  Runs on the object's stream and
- * returns after the last step is complete.  SA_ENOCONV if a solve did not
- * converge (the object then enters the sticky error state SA_ESTATE).
+ * its n_steps[p] steps stays as it is.  Starts after the work already queued
+ * on the object's stream and returns after the last step is complete.  With
+ * the fused solvers the source side of each step (kernel sum; reduction, load
+ * vector and Dirichlet data) runs on two internal streams, one step ahead of
+ * the theta-step solves on the object's stream; the results are bitwise those
+ * of the serial order (environment variable SA_IGA_SERIAL at set-up selects
+ * that order).  SA_ENOCONV if a solve did not converge (the object then
+ * enters the sticky error state SA_ESTATE).
  */
 int sa_iga_step(sa_iga *h, int32_t n_steps);
 
@@ -237,18 +242,21 @@ int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n,
                              const double *x, double *T, double *grad);
 
 /*
- * Tile-shape tuner of the kernel sum (Eqs. 7-8).  Times the sum over the whole
- * source history of the first min(n_paths, 64) paths (each at the end of its
- * scan, the heaviest load it will see) for every tile shape: points per lane
- * 1, 2, 4 x waves per workgroup 1, 2, 4, 8, `reps` launches each (reps >= 1),
- * and keeps the fastest as the object's points_per_lane and waves_per_group.
- * The split of the source history into chunks does not depend on the tile
- * shape, so later results are bitwise those of any other shape.  The model
- * state is not changed.  Outputs (each may be NULL): the chosen shape and its
- * mean launch time in ms (0 when no path has a source: nothing to time).
+ * Tile-shape tuner of the kernel sum (Eqs. 7-8).  For every tile shape
+ * (points per lane 1, 2, 4 x waves per workgroup 1, 2, 4, 8) it runs one
+ * untimed and `reps` timed theta-steps (reps >= 1) of all paths from the
+ * middle of their scans through the whole step pipeline, so the timing holds
+ * the overlap of the sum with the solves; the fastest shape becomes the
+ * object's points_per_lane and waves_per_group.  The state (steps, u, F,
+ * Dirichlet values, boundary fields, statistics, audit flags) is restored
+ * afterwards.  The split of the source history into chunks does not depend on
+ * the tile shape, so later results are bitwise those of any other shape.
+ * Outputs (each may be NULL): the chosen shape and its time per step of all
+ * paths in ms (0 when no path has sources and more than one step: nothing to
+ * time).  SA_ESTATE in the sticky error state.
  */
 int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *waves_per_group,
-                    double *ms_per_launch);
+                    double *ms_per_step);
 
 /* Turn the per-stage HIP-event timing of later steps on (nonzero) or off. */
 int sa_iga_set_timing(sa_iga *h, int32_t on);
@@ -283,7 +291,12 @@ int sa_iga_load(sa_iga *h, const void *buf, size_t len);
 int sa_iga_far_field(sa_iga *h, int32_t path, int64_t step, double e_scale, float *X, double *T,
                      double *grad);
 
-/* Use the given hipStream_t (NULL = the object's own stream) for all work. */
+/* Use the given hipStream_t (NULL = the object's own stream) for all work;
+ * sa_iga_step also uses internal streams, ordered after the work queued on
+ * this stream before the call and joined back into it at the end.  The own
+ * stream and the internal streams are a set of three per device that the
+ * library shares among all its objects (work of different objects on them is
+ * ordered, never concurrent) and keeps until the process ends. */
 int sa_iga_set_stream(sa_iga *h, void *hip_stream);
 
 /* Message of the last failure on this thread ("" if none). */

@@ -4,12 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -76,7 +78,21 @@ struct StageEvents {
 struct sa_iga {
   sa::Model m;
   int device = 0;
-  hipStream_t own_stream = nullptr, stream = nullptr;
+  hipStream_t own_stream = nullptr, stream = nullptr;   // own_stream: the device's shared solve stream
+  // The source side of a step (coefficients, kernel sum, load vector,
+  // Dirichlet data) runs on its own stream `ss`, one step ahead of the
+  // theta-step solves on `stream`: the sum of step n+2 overlaps the solve of
+  // step n+1, which it does not depend on.
+  // With the exact sum (no network) the reduction of the chunk partials,
+  // the load vector and the Dirichlet data of step n+1 run on a third
+  // stream `ps`, beside the sum of step n+2 (two partial buffers).
+  hipStream_t ss = nullptr, ps = nullptr;   // sum; reduction, loads and Dirichlet data
+  bool verbose = false;                    // SA_IGA_VERBOSE: set-up and host enqueue times on stderr
+  bool overlap = false, in_step = false;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  std::vector<hipEvent_t> ev_src, ev_rhs;   // rings: one event per batch
+  int64_t ev_next = 0;
+  std::vector<int> path_rhs;               // per path: ev_rhs slot of its last theta right-hand side, -1 none
   std::vector<void *> owned;
   int64_t nq = 0, stride = 0, nd = 0, nDa = 1, nbox = 1;
   int S = 0;                              // number of paths
@@ -117,9 +133,14 @@ struct sa_iga {
   double *rD = nullptr, *zD = nullptr, *pDg = nullptr, *qD = nullptr;
   double *part_b = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_rr = nullptr;
   sa::PcgScalars *sc_gen = nullptr;
-  // kernel-sum partials
-  double *part = nullptr;
+  // kernel-sum partials: two buffers used in turn, so that the sum of the
+  // next batch can run while the last one is reduced
+  double *partb[2] = {nullptr, nullptr};
   int64_t part_cap = 0;
+  int part_next = 0;
+  hipEvent_t ev_sum[2] = {nullptr, nullptr};   // the sum into partb[b] is done
+  hipEvent_t ev_part[2] = {nullptr, nullptr};  // the reduction of partb[b] is done
+  bool part_live[2] = {false, false};
   std::vector<PathState> paths;
   double delta = 0, shift = 0, alpha = 0, rc = 0;
   int64_t tau_ticks = 0;
@@ -175,14 +196,22 @@ struct sa_iga {
 };
 
 sa_iga::~sa_iga() {
+  if (ss) (void)hipStreamSynchronize(ss);
+  if (ps) (void)hipStreamSynchronize(ps);
   if (stream) (void)hipStreamSynchronize(stream);
+  for (hipEvent_t e : ev_src) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ev_rhs) (void)hipEventDestroy(e);
+  if (ev_start) (void)hipEventDestroy(ev_start);
+  for (hipEvent_t e : ev_sum) if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ev_part) if (e) (void)hipEventDestroy(e);
+  if (ev_end) (void)hipEventDestroy(ev_end);
   for (auto &s : ev) {
     for (auto &pr : s.pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto &pr : s.pool) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
   }
   for (void *p : owned) (void)hipFree(p);
   if (h_sc) (void)hipHostFree(h_sc);
-  if (own_stream) (void)hipStreamDestroy(own_stream);
+  // the streams belong to the per-device set shared by all objects
 }
 
 namespace {
@@ -220,12 +249,29 @@ inline double *path_vD(sa_iga *h, int p) { return h->vD + (int64_t)p * h->nDa; }
 inline double *path_T(sa_iga *h, int p) { return h->Tb + (int64_t)p * h->stride; }
 inline double *path_G(sa_iga *h, int p) { return h->Gb + (int64_t)p * 3 * h->stride; }
 
+// stream of the source-side work: its own while steps run overlapped
+inline hipStream_t src_stream(const sa_iga *h) { return h->in_step && h->overlap ? h->ss : h->stream; }
+// stream of the theta-step solves: the object's stream, which holds the
+// state u^n at the end of every call
+inline hipStream_t solve_stream(const sa_iga *h) { return h->stream; }
+// stream of the reduction, load vector and Dirichlet data of a step
+inline hipStream_t post_stream(const sa_iga *h) {
+  return h->in_step && h->overlap && !h->net ? h->ps : src_stream(h);
+}
+
+void sync_all(sa_iga *h) {
+  if (h->ss) hip_check(hipStreamSynchronize(h->ss), "sync");
+  if (h->ps) hip_check(hipStreamSynchronize(h->ps), "sync");
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+}
+
 // ---- stage timing -----------------------------------------------------------
 struct StageScope {
   sa_iga *h;
   int stage;
+  hipStream_t st;
   hipEvent_t stop = nullptr;
-  StageScope(sa_iga *h_, int s) : h(h_), stage(s) {
+  StageScope(sa_iga *h_, int s, hipStream_t st_) : h(h_), stage(s), st(st_) {
     if (!h->m.opt.timing) return;
     auto &E = h->ev[s];
     std::pair<hipEvent_t, hipEvent_t> pr;
@@ -236,13 +282,13 @@ struct StageScope {
       hip_check(hipEventCreate(&pr.first), "event");
       hip_check(hipEventCreate(&pr.second), "event");
     }
-    hip_check(hipEventRecord(pr.first, h->stream), "event record");
+    hip_check(hipEventRecord(pr.first, st), "event record");
     E.pending.push_back(pr);
     stop = pr.second;
   }
   ~StageScope() {
     if (stop) {
-      (void)hipEventRecord(stop, h->stream);
+      (void)hipEventRecord(stop, st);
       h->stats.stage_launches[stage]++;
     }
   }
@@ -316,14 +362,16 @@ sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int count, int64_t max_far, i
 void ensure_part(sa_iga *h, int64_t doubles) {
   if (doubles <= h->part_cap) return;
   const int64_t cap = std::max<int64_t>(doubles, 2 * h->part_cap);
-  if (h->part) {
-    hip_check(hipStreamSynchronize(h->stream), "sync");
-    hip_check(hipFree(h->part), "free");
-    h->owned.erase(std::find(h->owned.begin(), h->owned.end(), (void *)h->part));
-    h->part = nullptr;
+  sync_all(h);
+  for (double *&b : h->partb) {
+    if (!b) continue;
+    hip_check(hipFree(b), "free");
+    h->owned.erase(std::find(h->owned.begin(), h->owned.end(), (void *)b));
+    b = nullptr;
   }
-  h->part = dev_alloc<double>(h->owned, (size_t)cap);
+  for (double *&b : h->partb) b = dev_alloc<double>(h->owned, (size_t)cap);
   h->part_cap = cap;
+  h->part_live[0] = h->part_live[1] = false;
 }
 
 // slot s of `tab` <- path p at the end of step `step`: its switched-on and
@@ -353,7 +401,7 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
                 const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
                 const float *fz, const float *fq2, const int8_t *role, const double *nx, const double *ny,
                 const double *nz, const double *wdS, bool by_slot, int64_t ostride, double *T, double *G,
-                double *ld, const double *net = nullptr, int64_t net_stride = 0) {
+                double *ld, const double *net = nullptr, int64_t net_stride = 0, hipStream_t post = nullptr) {
   int64_t max_act = 0, max_far = 0, max_near = 0;
   for (int s = 0; s < tab.count; ++s) {
     const int64_t nf = tab.mode[s] ? 0 : tab.n_far[s];      // far sources summed here
@@ -364,24 +412,37 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
     h->stats.pairs_near += (int64_t)(tab.n_act[s] - tab.n_far[s]) * nq;
     if (tab.mode[s]) h->stats.pairs_net += (int64_t)tab.n_far[s] * nq;
   }
+  const hipStream_t st = src_stream(h);
   if (max_act > 0) {
-    StageScope s(h, SA_STAGE_COEFF);
+    StageScope s(h, SA_STAGE_COEFF, st);
     sa::CoeffParams cp{h->delta, h->shift, h->alpha, h->rc, h->m.opt.kernel_scale};
-    sa::launch_coeff(h->stream, tab, max_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
+    sa::launch_coeff(st, tab, max_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
   }
   sa::SumPlan pl = make_plan(h, nq, tab.count, max_far, max_near);
   pl.part_stride = stride;
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
   ensure_part(h, (int64_t)tab.count * std::max(nch, 1) * 5 * stride);
+  // the partials go to the buffer whose last reduction is longest done
+  const int b = h->part_next;
+  h->part_next ^= 1;
+  double *part = h->partb[b];
+  const hipStream_t fs = post ? post : st;
+  if (h->part_live[b]) hip_check(hipStreamWaitEvent(st, h->ev_part[b], 0), "stream wait");
   if (nch > 0) {
-    StageScope s(h, SA_STAGE_SUM);
-    sa::launch_sum(h->stream, pl, tab, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, h->part);
+    StageScope s(h, SA_STAGE_SUM, st);
+    sa::launch_sum(st, pl, tab, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, part);
+  }
+  if (fs != st) {
+    hip_check(hipEventRecord(h->ev_sum[b], st), "event record");
+    hip_check(hipStreamWaitEvent(fs, h->ev_sum[b], 0), "stream wait");
   }
   {
-    StageScope s(h, SA_STAGE_REDUCE);
-    sa::launch_finalize(h->stream, tab, by_slot, nq, nch, stride, h->part, px, py, pz, nx, ny, nz, wdS, role,
+    StageScope s(h, SA_STAGE_REDUCE, fs);
+    sa::launch_finalize(fs, tab, by_slot, nq, nch, stride, part, px, py, pz, nx, ny, nz, wdS, role,
                         h->m.mat.k, ostride, T, G, ld, net, net_stride);
   }
+  hip_check(hipEventRecord(h->ev_part[b], fs), "event record");
+  h->part_live[b] = true;
 }
 
 // ---- generic PCG driver (single path; Jacobi or oversize problems) ---------------
@@ -443,6 +504,7 @@ int pcg_run(sa_iga *h, PcgSpec &s, double *relres) {
 void check_statuses(sa_iga *h) {
   const size_t used = h->status_kind.size();
   if (used == 0) return;
+  if (h->ps) hip_check(hipStreamSynchronize(h->ps), "sync");   // records of the projection solves
   std::vector<sa::SolveStatus> st(used);
   hip_check(hipMemcpyAsync(st.data(), h->d_status, used * sizeof(sa::SolveStatus), hipMemcpyDeviceToHost,
                            h->stream),
@@ -485,10 +547,11 @@ sa::SolveStatus *next_status(sa_iga *h, int n, int8_t kind) {
 // in chunks of net_rows so the activations stay cache-sized
 void run_network(sa_iga *h, const sa::PathTab &tab, int64_t nq, const float *pf, int64_t ostride, double *out) {
   if (tab.count <= 0 || nq <= 0) return;
-  StageScope sc(h, SA_STAGE_NET);
+  const hipStream_t st = src_stream(h);
+  StageScope sc(h, SA_STAGE_NET, st);
   const float *W1 = h->nw + sa::MlpLayout::W1, *b1 = h->nw + sa::MlpLayout::b1;
-  sa::launch_far_bins(h->stream, tab, h->sbin, h->sE, h->net_E, h->bins);
-  sa::launch_layer1_const(h->stream, tab.count, h->bins, W1, b1, h->cvec);
+  sa::launch_far_bins(st, tab, h->sbin, h->sE, h->net_E, h->bins);
+  sa::launch_layer1_const(st, tab.count, h->bins, W1, b1, h->cvec);
   const int64_t total = (int64_t)tab.count * nq, H = sa::kMlpHid;
   if (h->net_fused) {
     sa::NetArgs na{};
@@ -510,13 +573,13 @@ void run_network(sa_iga *h, const sa::PathTab &tab, int64_t nq, const float *pf,
     na.gs = h->net_G;
     na.ostride = ostride;
     na.net = out;
-    sa::launch_net_fused(h->stream, na);
+    sa::launch_net_fused(st, na);
     return;
   }
   const int64_t bias[3] = {sa::MlpLayout::b2, sa::MlpLayout::b3, sa::MlpLayout::b4};
   for (int64_t r0 = 0; r0 < total; r0 += h->net_rows) {
     const int64_t rows = std::min(h->net_rows, total - r0);
-    sa::launch_layer1_points(h->stream, r0, rows, nq, pf, h->cvec, W1, h->hA);
+    sa::launch_layer1_points(st, r0, rows, nq, pf, h->cvec, W1, h->hA);
     sa::bf16_t *in = h->hA, *outb = h->hB;
     for (int l = 0; l < 3; ++l) {
       sa::GemmArgs g{};
@@ -533,10 +596,10 @@ void run_network(sa_iga *h, const sa::PathTab &tab, int64_t nq, const float *pf,
       g.act = 1;
       g.out = outb;
       g.ldo = H;
-      sa::launch_gemm_bf16(h->stream, g);
+      sa::launch_gemm_bf16(st, g);
       std::swap(in, outb);
     }
-    sa::launch_layer_out_field(h->stream, r0, rows, nq, in, h->nw + sa::MlpLayout::W5, h->nw + sa::MlpLayout::b5,
+    sa::launch_layer_out_field(st, r0, rows, nq, in, h->nw + sa::MlpLayout::W5, h->nw + sa::MlpLayout::b5,
                                h->net_T, h->net_G, ostride, out);
   }
 }
@@ -561,6 +624,7 @@ void audit_slots(sa_iga *h, const sa::PathTab &tab, const std::vector<int> &aud)
     nt.n_far[i] = tab.n_far[s];
     nt.mode[i] = 1;
   }
+  const hipStream_t st = src_stream(h);
   const sa_stats keep = h->stats;
   sum_points(h, ex, h->na, h->stride_a, h->ax, h->ay, h->az, h->aq2, h->afx, h->afy, h->afz, h->afq2, h->arole,
              h->ax, h->ay, h->az, h->ax, true, h->stride_a, h->aT, h->aG, h->aLD);
@@ -570,11 +634,11 @@ void audit_slots(sa_iga *h, const sa::PathTab &tab, const std::vector<int> &aud)
   run_network(h, nt, h->na, h->apf, h->stride_a, h->anet);
   const int64_t n = h->na, sa_ = h->stride_a;
   std::vector<double> te((size_t)ex.count * sa_), tn((size_t)ex.count * 4 * sa_);
-  hip_check(hipMemcpyAsync(te.data(), h->aT, te.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+  hip_check(hipMemcpyAsync(te.data(), h->aT, te.size() * sizeof(double), hipMemcpyDeviceToHost, st),
             "download");
-  hip_check(hipMemcpyAsync(tn.data(), h->anet, tn.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+  hip_check(hipMemcpyAsync(tn.data(), h->anet, tn.size() * sizeof(double), hipMemcpyDeviceToHost, st),
             "download");
-  hip_check(hipStreamSynchronize(h->stream), "sync");
+  hip_check(hipStreamSynchronize(st), "sync");
   for (int i = 0; i < ex.count; ++i) {
     double err = 0.0;
     for (int64_t q = 0; q < n; ++q)
@@ -633,27 +697,40 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     h->stats.net_steps += n_net;
   }
   // T~, grad T~ and load densities at every boundary point (Eqs. 7-8, 10-11)
+  const hipStream_t as = post_stream(h);
   sum_points(h, tab, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
-             h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD, net, h->stride);
+             h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD, net, h->stride, as);
   double *Vc = h->V[cur], *Vn = h->V[nxt], *Fc = h->Fb[cur], *Fn = h->Fb[nxt];
-  {
-    StageScope s(h, SA_STAGE_LOAD);
-    // F^{n+1} on the non-empty rows (Eq. 18), and the iterate u^{n+1} <- u^n
-    sa::launch_gather_rows(h->stream, sm, h->grows, h->LD, h->stride, Fn, nd, nd, Vc, Vn);
+  if (h->overlap) {
+    // F^{n+1} and the Dirichlet values of u^{n+1} overwrite F^{n-1} and
+    // entries of u^{n-1}: wait until the right-hand side of step n of these
+    // paths has read them
+    int last = -1;
+    for (int s = 0; s < count; ++s) last = std::max(last, h->path_rhs[pids[s]]);
+    for (int s = 0; s < count; ++s) {
+      const int e = h->path_rhs[pids[s]];
+      if (e >= 0 && e != last) hip_check(hipStreamWaitEvent(as, h->ev_rhs[e], 0), "stream wait");
+    }
+    if (last >= 0) hip_check(hipStreamWaitEvent(as, h->ev_rhs[last], 0), "stream wait");
   }
-  // Dirichlet values (Eq. 11), scattered into the iterate
+  {
+    StageScope s(h, SA_STAGE_LOAD, as);
+    // F^{n+1} on the non-empty rows (Eq. 18)
+    sa::launch_gather_rows(as, sm, h->grows, h->LD, h->stride, Fn, nd, 0, nullptr, nullptr);
+  }
+  // Dirichlet values (Eq. 11), scattered into the Dirichlet DOFs of u^{n+1}
   if (h->nD > 0) {
-    StageScope s(h, SA_STAGE_DIRICHLET);
+    StageScope s(h, SA_STAGE_DIRICHLET, as);
     if (h->dir_exact || h->dir_fused)
-      sa::launch_gather_rows(h->stream, sm, h->drows, h->LD, h->stride, h->bD, h->nDa, 0, nullptr, nullptr);
+      sa::launch_gather_rows(as, sm, h->drows, h->LD, h->stride, h->bD, h->nDa, 0, nullptr, nullptr);
     if (h->dir_direct) {
       sa::DirDirect a = h->ddir;
       a.xfull = Vn;
-      sa::launch_dir_direct(h->stream, sm, a);
+      sa::launch_dir_direct(as, sm, a);
     } else if (h->dir_exact) {
       sa::FusedPcg f = h->fd_dirp;
       f.scatter_out = Vn;
-      sa::launch_fd_pass(h->stream, sm, f, 0, false, false);
+      sa::launch_fd_pass(as, sm, f, 0, false, false);
     } else if (h->dir_fused) {
       sa::DirArgs a = h->dargs;
       a.b = h->bD;
@@ -661,8 +738,9 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       a.xfull = Vn;
       a.xs = nd;
       a.status = next_status(h, count, 0);
-      sa::launch_dirichlet(h->stream, sm, a);
+      sa::launch_dirichlet(as, sm, a);
     } else {
+      // generic projection solve (never overlapped: as is the main stream)
       for (int s = 0; s < count; ++s) {
         const int p = pids[s];
         sa::launch_gather(h->stream, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val,
@@ -687,10 +765,26 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       }
     }
   }
+  // the theta-step of these paths: on the solver stream
+  const hipStream_t bsx = solve_stream(h);
+  if (h->overlap) {
+    const hipEvent_t e = h->ev_src[h->ev_next % (int64_t)h->ev_src.size()];
+    hip_check(hipEventRecord(e, as), "event record");
+    hip_check(hipStreamWaitEvent(bsx, e, 0), "stream wait");
+  }
+  // first iterate: u^n on the free DOFs
+  sa::launch_copy_free(bsx, sm, nd, h->free_mask, Vc, Vn);
   // theta-scheme (Eq. 20)
+  const int ev_slot = (int)(h->ev_next % (int64_t)std::max<size_t>(h->ev_rhs.size(), 1));
+  h->ev_next++;
+  auto rhs_done = [&]() {
+    if (!h->overlap) return;
+    hip_check(hipEventRecord(h->ev_rhs[ev_slot], bsx), "event record");
+    for (int s = 0; s < count; ++s) h->path_rhs[pids[s]] = ev_slot;
+  };
   if (h->pcg_fused) {
     {
-      StageScope s(h, SA_STAGE_RHS);
+      StageScope s(h, SA_STAGE_RHS, bsx);
       sa::SlArgs a{};
       a.nrow = nd;
       a.vs = nd;
@@ -720,12 +814,13 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
         k.part = h->part_b2;
         k.sc = nullptr;
         k.sc_w = h->sc;
-        sa::launch_kron(h->stream, sm, k, true);
+        sa::launch_kron(bsx, sm, k, true);
       } else {
-        sa::launch_stencil_sl(h->stream, sm, a, h->hw0, true);
+        sa::launch_stencil_sl(bsx, sm, a, h->hw0, true);
       }
     }
-    StageScope s(h, SA_STAGE_PCG);
+    rhs_done();
+    StageScope s(h, SA_STAGE_PCG, bsx);
     sa::FusedPcg f = h->fp;
     f.x = Vn;
     f.status = next_status(h, count, 1);
@@ -750,21 +845,21 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     kp.sc = h->sc;
     kp.sc_w = nullptr;
     auto apply = [&]() {
-      if (h->kron) sa::launch_kron(h->stream, sm, kp, false);
-      else sa::launch_stencil_sl(h->stream, sm, ap, h->hw0, false);
+      if (h->kron) sa::launch_kron(bsx, sm, kp, false);
+      else sa::launch_stencil_sl(bsx, sm, ap, h->hw0, false);
     };
-    sa::launch_fd_pass(h->stream, sm, f, 0, true, false);
+    sa::launch_fd_pass(bsx, sm, f, 0, true, false);
     if (h->fd_exact) {
       // with the exact preconditioner the first iteration nearly always
       // converges: test |r| right after the update, and run the FD solve and
       // the new direction only for paths still going (the others exit at once)
       for (int k = 0; k < h->pcg_budget; ++k) {
         apply();
-        sa::launch_pcg_last_update(h->stream, sm, f, k);
-        sa::launch_pcg_dir(h->stream, sm, f, k, true);
+        sa::launch_pcg_last_update(bsx, sm, f, k);
+        sa::launch_pcg_dir(bsx, sm, f, k, true);
         if (k + 1 < h->pcg_budget) {
-          sa::launch_fd_pass(h->stream, sm, f, k, false, false);
-          sa::launch_pcg_dir(h->stream, sm, f, k, false);
+          sa::launch_fd_pass(bsx, sm, f, k, false, false);
+          sa::launch_pcg_dir(bsx, sm, f, k, false);
         }
       }
     } else {
@@ -772,12 +867,12 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       for (;;) {
         for (int c = 0; c < chunk; ++c, ++k) {
           apply();
-          sa::launch_fd_pass(h->stream, sm, f, k, false, true);
-          sa::launch_pcg_dir(h->stream, sm, f, k, false);
+          sa::launch_fd_pass(bsx, sm, f, k, false, true);
+          sa::launch_pcg_dir(bsx, sm, f, k, false);
         }
-        hip_check(hipMemcpyAsync(h->h_sc, h->sc, h->S * sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, h->stream),
+        hip_check(hipMemcpyAsync(h->h_sc, h->sc, h->S * sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, bsx),
                   "status copy");
-        hip_check(hipStreamSynchronize(h->stream), "sync");
+        hip_check(hipStreamSynchronize(bsx), "sync");
         bool all = true;
         for (int s = 0; s < count; ++s) {
           const sa::PcgScalars &st = h->h_sc[pids[s]];
@@ -794,11 +889,11 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       const int p = pids[s];
       double *x = Vn + (int64_t)p * nd;
       {
-        StageScope sc(h, SA_STAGE_RHS);
+        StageScope sc(h, SA_STAGE_RHS, h->stream);
         sa::launch_theta_init(h->stream, h->Aop, h->Bval, Vc + (int64_t)p * nd, Fn + (int64_t)p * nd,
                               Fc + (int64_t)p * nd, h->m.opt.theta, x, h->gr, h->part_b);
       }
-      StageScope sc(h, SA_STAGE_PCG);
+      StageScope sc(h, SA_STAGE_PCG, h->stream);
       PcgSpec m;
       m.n = nd;
       m.stencil = true;
@@ -1073,6 +1168,29 @@ void build_network_state(sa_iga *h, const sa_patch *patch, const sa_scan_path *s
   hip_check(hipGetLastError(), "kernel launch");
 }
 
+// Three streams per device, shared by every object and kept until the
+// process ends: the solves (an object's own stream), the sums and the
+// post-processing.  Hardware queues are few (four per process by default);
+// streams per object would make the objects' streams share queues, and two
+// streams of one object on one queue would run its overlapped steps in queue
+// order.  Objects stepped one after the other lose nothing by sharing.
+struct DeviceStreams {
+  hipStream_t solve = nullptr, sum = nullptr, post = nullptr;
+};
+
+const DeviceStreams &device_streams(int device) {
+  static std::mutex mu;
+  static std::map<int, DeviceStreams> pool;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pool.find(device);
+  if (it != pool.end()) return it->second;
+  DeviceStreams d;
+  hip_check(hipStreamCreateWithFlags(&d.solve, hipStreamNonBlocking), "stream");
+  hip_check(hipStreamCreateWithFlags(&d.sum, hipStreamNonBlocking), "stream");
+  hip_check(hipStreamCreateWithFlags(&d.post, hipStreamNonBlocking), "stream");
+  return pool.emplace(device, d).first->second;
+}
+
 void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan) {
   sa::Model &m = h->m;
   // device and stream
@@ -1083,7 +1201,8 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   hip_check(hipGetDeviceProperties(&prop, h->device), "device properties");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     throw sa::SaError{SA_EDEVICE, std::string("device is ") + prop.gcnArchName + ", built for gfx950"};
-  hip_check(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking), "stream");
+  const DeviceStreams &ds = device_streams(h->device);
+  h->own_stream = ds.solve;
   h->stream = h->own_stream;
   h->lds_per_block = prop.sharedMemPerBlock;
 
@@ -1432,8 +1551,33 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   h->m.opt.surrogate_weights = nullptr;   // copied; the caller's array is not kept
   h->status_cap = 8192;
   h->d_status = dev_zeros<sa::SolveStatus>(h, h->status_cap);
+  // overlapped steps: the source side on a stream of its own (default
+  // priority, like every stream here). Only with the fused solvers, whose
+  // work buffers the two sides do not share.
+  h->overlap = h->pcg_fused && (h->nD == 0 || h->dir_direct || h->dir_exact || h->dir_fused) &&
+               !std::getenv("SA_IGA_SERIAL");
+  for (int b = 0; b < 2; ++b) {
+    hip_check(hipEventCreateWithFlags(&h->ev_sum[b], hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&h->ev_part[b], hipEventDisableTiming), "event");
+  }
+  if (h->overlap) {
+    h->ss = ds.sum;
+    h->ps = ds.post;
+    hip_check(hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming), "event");
+    // batches per step: at most two parity groups of ceil(S / kMaxBatch) batches each
+    const size_t ring = 2 * (2 * (size_t)((S + sa::kMaxBatch - 1) / sa::kMaxBatch) + 2);
+    h->ev_src.resize(ring, nullptr);
+    h->ev_rhs.resize(ring, nullptr);
+    for (size_t i = 0; i < ring; ++i) {
+      hip_check(hipEventCreateWithFlags(&h->ev_src[i], hipEventDisableTiming), "event");
+      hip_check(hipEventCreateWithFlags(&h->ev_rhs[i], hipEventDisableTiming), "event");
+    }
+    h->path_rhs.assign(S, -1);
+  }
   hip_check(hipStreamSynchronize(h->stream), "sync");
-  if (std::getenv("SA_IGA_VERBOSE"))
+  h->verbose = std::getenv("SA_IGA_VERBOSE") != nullptr;
+  if (h->verbose)
     std::fprintf(stderr,
                  "[sa_iga] paths %d ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: exact %d direct %d one-wg %d | "
                  "theta-step: fused %d fd-exact %d budget %d kron %d\n",
@@ -1560,6 +1704,53 @@ constexpr uint64_t kMagic = 0x5341494741434b32ull;  // checkpoint tag
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// n_steps steps of every live path, overlapped where the object allows it;
+// returns when they are complete (the status records checked)
+void run_steps(sa_iga *h, int32_t n_steps) {
+  struct InStep {
+    sa_iga *h;
+    explicit InStep(sa_iga *h_) : h(h_) { h->in_step = true; }
+    ~InStep() { h->in_step = false; }
+  };
+  {
+    InStep guard(h);
+    if (h->overlap) {
+      // the source side starts after everything queued so far
+      hip_check(hipEventRecord(h->ev_start, h->stream), "event record");
+      hip_check(hipStreamWaitEvent(h->ss, h->ev_start, 0), "stream wait");
+      hip_check(hipStreamWaitEvent(h->ps, h->ev_start, 0), "stream wait");
+      std::fill(h->path_rhs.begin(), h->path_rhs.end(), -1);
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int32_t s = 0; s < n_steps; ++s) step_all(h);
+    if (h->verbose && n_steps > 0) {
+      const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+      std::fprintf(stderr, "[sa_iga] %d steps enqueued in %.1f us per step\n", n_steps, us / n_steps);
+    }
+    if (h->overlap) {
+      hip_check(hipEventRecord(h->ev_end, h->ss), "event record");
+      hip_check(hipStreamWaitEvent(h->stream, h->ev_end, 0), "stream wait");
+      hip_check(hipEventRecord(h->ev_end, h->ps), "event record");
+      hip_check(hipStreamWaitEvent(h->stream, h->ev_end, 0), "stream wait");
+    }
+  }
+  check_statuses(h);
+  sync_all(h);
+  collect_timing(h);
+}
+
+// after a failed run_steps: drain the streams, drop pending records
+void abandon_steps(sa_iga *h) {
+  if (h->ss) (void)hipStreamSynchronize(h->ss);
+  if (h->ps) (void)hipStreamSynchronize(h->ps);
+  (void)hipStreamSynchronize(h->stream);
+  h->status_kind.clear();
+  try {
+    collect_timing(h);
+  } catch (...) {
+  }
+}
+
 extern "C" {
 
 int sa_iga_default_options(sa_solver_options *opt) {
@@ -1600,15 +1791,10 @@ int sa_iga_step(sa_iga *h, int32_t n_steps) {
     if (n_steps < 0) throw sa::SaError{SA_EINVAL, "n_steps must be >= 0"};
     if (h->sticky) throw sa::SaError{SA_ESTATE, "object is in an error state (load a checkpoint)"};
     try {
-      for (int32_t s = 0; s < n_steps; ++s) step_all(h);
-      check_statuses(h);
-      hip_check(hipStreamSynchronize(h->stream), "sync");
-      collect_timing(h);
+      run_steps(h, n_steps);
     } catch (const sa::SaError &e) {
       if (e.code == SA_ENOCONV) h->sticky = 1;
-      (void)hipStreamSynchronize(h->stream);
-      h->status_kind.clear();
-      collect_timing(h);
+      abandon_steps(h);
       throw;
     }
     return SA_OK;
@@ -1701,69 +1887,86 @@ int sa_iga_apply_operator(sa_iga *h, int32_t which, const double *x, double *y) 
 }
 
 int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *waves_per_group,
-                    double *ms_per_launch) {
+                    double *ms_per_step) {
   return guarded([&]() -> int {
     if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
     if (reps < 1) throw sa::SaError{SA_EINVAL, "reps must be >= 1"};
+    if (h->sticky) throw sa::SaError{SA_ESTATE, "object is in an error state (load a checkpoint)"};
     auto &o = h->m.opt;
-    sa::PathTab tab{};
-    tab.count = std::min((int)h->paths.size(), sa::kMaxBatch);
-    int64_t max_act = 0, max_far = 0, max_near = 0;
-    for (int s = 0; s < tab.count; ++s) {
-      fill_slot(h, tab, s, s, h->paths[s].n_steps);
-      max_act = std::max<int64_t>(max_act, tab.n_act[s]);
-      max_far = std::max<int64_t>(max_far, tab.n_far[s]);
-      max_near = std::max<int64_t>(max_near, tab.n_act[s] - tab.n_far[s]);
-    }
+    bool any = false;
+    for (const PathState &P : h->paths) any = any || (P.n_steps > 1 && P.src1 > P.src0);
     double best_ms = 0.0;
-    if (max_act > 0) {
-      sa::CoeffParams cp{h->delta, h->shift, h->alpha, h->rc, o.kernel_scale};
-      // the coefficient records are rewritten by every step before use
-      sa::launch_coeff(h->stream, tab, max_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
-      sa::SumPlan pl = make_plan(h, h->nq, tab.count, max_far, max_near);
-      pl.part_stride = h->stride;
-      ensure_part(h, (int64_t)tab.count * std::max(pl.n_chunks_far + pl.n_chunks_near, 1) * 5 * h->stride);
-      hipEvent_t e0, e1;
-      hip_check(hipEventCreate(&e0), "event");
-      hip_check(hipEventCreate(&e1), "event");
+    if (any) {
+      // the state the trial steps overwrite, kept on the device
+      const int S = h->S;
+      const int64_t nd = h->nd;
+      struct Saved {
+        double *dst;
+        size_t n;
+      };
+      const Saved arr[] = {{h->V[0], (size_t)S * nd},        {h->V[1], (size_t)S * nd},
+                           {h->Fb[0], (size_t)S * nd},       {h->Fb[1], (size_t)S * nd},
+                           {h->vD, (size_t)S * h->nDa},      {h->Tb, (size_t)S * h->stride},
+                           {h->Gb, (size_t)S * 3 * h->stride}, {h->LD, (size_t)S * h->stride}};
+      TempBufs tb;
+      std::vector<double *> keep;
+      for (const Saved &a : arr) {
+        double *c = tb.alloc<double>(a.n);
+        hip_check(hipMemcpyAsync(c, a.dst, a.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "copy");
+        keep.push_back(c);
+      }
+      std::vector<int64_t> steps(S);
+      for (int p = 0; p < S; ++p) steps[p] = h->paths[p].step;
+      const sa_stats stats = h->stats;
+      const std::vector<uint8_t> use_exact = h->use_exact;
+      const int keep_timing = o.timing;
+      auto restore = [&]() {
+        for (int p = 0; p < S; ++p) h->paths[p].step = steps[p];
+        h->stats = stats;
+        h->use_exact = use_exact;
+        o.timing = keep_timing;
+        for (size_t k = 0; k < keep.size(); ++k)
+          hip_check(hipMemcpyAsync(arr[k].dst, keep[k], arr[k].n * sizeof(double), hipMemcpyDeviceToDevice,
+                                   h->stream),
+                    "copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+      };
+      // every shape runs one untimed and `reps` timed steps of all paths
+      // from the middle of their scans, through the whole step pipeline
+      static const int kP[3] = {1, 2, 4}, kW[4] = {1, 2, 4, 8};
+      double best = -1.0;
       int bp = 2, bw = 4;
-      best_ms = -1.0;
+      o.timing = 0;
       try {
-        for (int P : {1, 2, 4})
-          for (int w : {1, 2, 4, 8}) {
-            pl.points_per_lane = P;
-            pl.waves = w;
-            sa::launch_sum(h->stream, pl, tab, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->c64,
-                           h->c32, h->part);
-            hip_check(hipEventRecord(e0, h->stream), "event record");
-            for (int r = 0; r < reps; ++r)
-              sa::launch_sum(h->stream, pl, tab, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2,
-                             h->c64, h->c32, h->part);
-            hip_check(hipEventRecord(e1, h->stream), "event record");
-            hip_check(hipEventSynchronize(e1), "event sync");
-            hip_check(hipGetLastError(), "kernel launch");
-            float ms = 0.f;
-            hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-            const double per = ms / reps;
-            if (best_ms < 0 || per < best_ms) {
-              best_ms = per;
+        for (int P : kP)
+          for (int w : kW) {
+            o.points_per_lane = P;
+            o.waves_per_group = w;
+            for (int p = 0; p < S; ++p)
+              h->paths[p].step = std::max<int64_t>(0, h->paths[p].n_steps / 2 - 1 - reps);
+            run_steps(h, 1);
+            const auto t0 = std::chrono::steady_clock::now();
+            run_steps(h, reps);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (best < 0 || ms < best) {
+              best = ms;
               bp = P;
               bw = w;
             }
           }
       } catch (...) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        abandon_steps(h);
+        restore();
         throw;
       }
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
+      restore();
       o.points_per_lane = bp;
       o.waves_per_group = bw;
+      best_ms = best / reps;
     }
     if (points_per_lane) *points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
     if (waves_per_group) *waves_per_group = o.waves_per_group ? o.waves_per_group : 4;
-    if (ms_per_launch) *ms_per_launch = best_ms;
+    if (ms_per_step) *ms_per_step = best_ms;
     return SA_OK;
   });
 }
@@ -1930,7 +2133,7 @@ int sa_iga_far_field(sa_iga *h, int32_t path, int64_t step, double e_scale, floa
 int sa_iga_set_stream(sa_iga *h, void *hip_stream) {
   return guarded([&]() -> int {
     if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
-    hip_check(hipStreamSynchronize(h->stream), "sync");
+    sync_all(h);
     h->stream = hip_stream ? (hipStream_t)hip_stream : h->own_stream;
     return SA_OK;
   });

@@ -34,6 +34,11 @@ struct GatherRows {
 void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, const double *ld, int64_t ls,
                         double *F, int64_t fs, int64_t ncopy, const double *v, double *x);
 
+// per slot (path p): x[p*n + i] = v[p*n + i] for the free DOFs i (mask[i] != 0);
+// the entries of the Dirichlet DOFs of x are left as they are
+void launch_copy_free(hipStream_t st, const SlotMap &sm, int64_t n, const uint8_t *mask, const double *v,
+                      double *x);
+
 // Dirichlet projection solved by one workgroup
 struct DirArgs {
   int nD;

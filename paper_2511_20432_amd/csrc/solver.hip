@@ -2,6 +2,7 @@
 // projection (Eq. 11) on gfx950.
 //
 //  * k_gather_rows   load vector F (lane-parallel rows) + copy of v into x
+//  * k_copy_free     first iterate: v on the free DOFs
 //  * k_dirichlet     one workgroup: projection rhs gather, then the whole
 //                    PCG for the trace mass matrix with the 2-D fast-
 //                    diagonalisation preconditioner held in LDS; writes the
@@ -93,6 +94,26 @@ void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, 
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks, (unsigned)sm.count), dim3(kB), 0, st, sm, g.nrows,
                      g.rows, g.rowptr, g.col, g.val, ld, ls, F, fs, ncopy, v, x);
+}
+
+// ---------------------------------------------------------------------------
+// first iterate of the theta-step: u^n on the free DOFs, the new Dirichlet
+// values (already in x) on the others
+// ---------------------------------------------------------------------------
+__global__ void k_copy_free(SlotMap sm, int64_t n, const uint8_t *__restrict__ mask, const double *__restrict__ vb,
+                            double *__restrict__ xb) {
+  const int64_t pth = sm.path[blockIdx.y];
+  const double *v = vb + pth * n;
+  double *x = xb + pth * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (mask[i]) x[i] = v[i];
+}
+
+void launch_copy_free(hipStream_t st, const SlotMap &sm, int64_t n, const uint8_t *mask, const double *v,
+                      double *x) {
+  if (sm.count <= 0 || n <= 0) return;
+  const int64_t blocks = (n + kB - 1) / kB;
+  hipLaunchKernelGGL(k_copy_free, dim3((unsigned)blocks, (unsigned)sm.count), dim3(kB), 0, st, sm, n, mask, v, x);
 }
 
 // ---------------------------------------------------------------------------

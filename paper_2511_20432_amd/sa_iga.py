@@ -247,10 +247,11 @@ class Model:
         check(self._lib.sa_iga_set_timing(self.h, 1 if on else 0))
 
     def autotune(self, reps: int = 3) -> dict:
-        """Pick the fastest kernel-sum tile shape; results stay bitwise the same."""
+        """Pick the kernel-sum tile shape with the fastest whole steps (timed
+        from mid-scan, state restored); results stay bitwise the same."""
         p, w, ms = C.c_int32(), C.c_int32(), C.c_double()
         check(self._lib.sa_iga_autotune(self.h, reps, C.byref(p), C.byref(w), C.byref(ms)))
-        return {"points_per_lane": p.value, "waves_per_group": w.value, "ms_per_launch": ms.value}
+        return {"points_per_lane": p.value, "waves_per_group": w.value, "ms_per_step": ms.value}
 
     def boundary_fields(self, path: int = 0):
         """T~ [nq], grad T~ [nq, 3] at the boundary points, F [n_dof] and
