@@ -32,31 +32,38 @@ import numpy as np  # noqa: E402
 
 METRIC = "source×point pairs/s + θ-steps/s; mixed+surrogate vs FP64 GPU at ≤0.5 K err"
 
-# gfx950: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = lane-operations per second
-LANE_OPS = 256 * 64 * 2.4e9
-# VALU issue slots per source x point pair of the two sum loops (from the
-# compiled loops: FP32 far: 4 FMA for the exponent, 5 for the
-# accumulations + per-source overhead; v_exp_f32 counted at 4 slots,
-# quarter rate); FP64: 4 FMA, clamp, 2 for rounding, 2 reduction, 13 Horner,
-# ldexp, 5 accumulations
-SLOTS_FP32 = 9 + 4
-SLOTS_FP64 = 28
-# HBM bytes per k_sum launch of this workload's FP32 far-field form, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE over steps 1480..1779, scaled by the same
-# counters on a 256 MiB copy (profiles/k_sum_raster_fp32far.md), with the
-# tile shape fixed at 2 points per lane and 2 waves per group.  Valid for the
-# kernel as profiled and only when the tuner picks that shape; a changed k_sum
-# must set this to None until the counters are taken again.  Most of the
-# written bytes are the per-chunk FP64 partial sums that k_finalize reads.
-K_SUM_TRAFFIC = {"read_bytes": 6.74e6, "written_bytes": 35.79e6, "points_per_lane": 2, "waves_per_group": 2}
+# The kernel sum on the faces of the block runs as matrix products on the
+# matrix cores: per source x point pair 4 products (T~ and the three gradient
+# components) of 2 flops; far pairs in FP32, near pairs in FP64.  Dense
+# matrix-core peaks of MI355X:
+MFMA_FP32 = 157.3e12
+MFMA_FP64 = 78.6e12
+FLOPS_PER_PAIR = 8
+# HBM bytes per step of the sum kernels of this workload's FP32 far-field
+# form, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the same counters on
+# a 256 MiB copy.  None until the counters are taken on the current kernels.
+K_SUM_TRAFFIC = None
 
 
-def _k_sum_traffic(form, tune):
+def _k_sum_traffic(form):
     t = K_SUM_TRAFFIC
-    if not t or form != "fp32far" or (tune.get("points_per_lane"), tune.get("waves_per_group")) != \
-            (t["points_per_lane"], t["waves_per_group"]):
+    if not t or form != "fp32far":
         return None
     return t["read_bytes"] + t["written_bytes"]
+
+
+def _sum_roofline(st, sum_ms):
+    """Matrix-core roofline of the sum stage: the algorithmic flops over its
+    device time, against the peak of the mix of FP32 (far) and FP64 (near)
+    pairs."""
+    pairs, near = st["pairs"], st["pairs_near"]
+    flops = FLOPS_PER_PAIR * pairs
+    t_peak = FLOPS_PER_PAIR * ((pairs - near) / MFMA_FP32 + near / MFMA_FP64)
+    if sum_ms <= 0 or flops <= 0:
+        return {"bound": "mfma", "achieved": None, "peak": None, "unit": "TFLOP/s", "frac": None}
+    t = sum_ms * 1e-3
+    return {"bound": "mfma", "achieved": flops / t / 1e12, "peak": flops / t_peak / 1e12, "unit": "TFLOP/s",
+            "frac": t_peak / t}
 
 
 def _timed_run(model, warmup, steps, n_total):
@@ -324,9 +331,7 @@ def main():
     pairs_s = st["pairs"] / r["seconds"]
     sum_ms = st["stage_ms"]["sum"]
     launches = max(1, st["stage_launches"]["sum"])
-    slots = SLOTS_FP32 if main_form == "fp32far" else SLOTS_FP64
-    achieved = st["pairs"] / (sum_ms * 1e-3) if sum_ms > 0 else 0.0
-    peak = LANE_OPS / slots
+    roof = _sum_roofline(st, sum_ms)
     out = {
         "metric": METRIC, "value": pairs_s, "unit": "pairs/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * r["seconds"] / steps, "higher_is_better": True,
@@ -338,12 +343,11 @@ def main():
                    "form": main_form, "tau_near_s": 2e-4, "theta": 0.5, "pcg_rtol": 1e-13,
                    "preconditioner": "fast diagonalisation"},
         "steps_per_s": steps / r["seconds"],
-        "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Gpair/s",
-                     "frac": achieved / peak if peak else None,
-                     "traffic": _k_sum_traffic(main_form, st["autotune"]),
-                     "traffic_unit": "bytes per launch (HBM, read + written)",
-                     "kernel": "k_sum", "avg_launch_ms": sum_ms / launches,
-                     "pairs_per_launch": st["pairs"] / launches},
+        "roofline": dict(roof, traffic=_k_sum_traffic(main_form),
+                         traffic_unit="HBM bytes per step of the sum kernels (read + written)",
+                         kernel="k_sum_tensor (far chunks FP32, near chunks FP64)",
+                         avg_ms_per_step=sum_ms / steps, launches_per_step=launches / steps,
+                         pairs_per_step=st["pairs"] / steps),
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
         "ms_per_step_with_stage_events": 1e3 * st["seconds_with_events"] / steps,
         "setup_s": r["setup_s"],
@@ -356,8 +360,7 @@ def main():
                        "ms_per_step": 1e3 * t64 / steps,
                        "sum_gpair_s": s64["pairs"] / (s64["stage_ms"]["sum"] * 1e-3) / 1e9
                        if s64["stage_ms"]["sum"] > 0 else None,
-                       "sum_frac_of_fp64_peak": (s64["pairs"] / (s64["stage_ms"]["sum"] * 1e-3))
-                       / (LANE_OPS / SLOTS_FP64) if s64["stage_ms"]["sum"] > 0 else None,
+                       "sum_roofline": _sum_roofline(s64, s64["stage_ms"]["sum"]),
                        "stage_ms_per_step": {k: v / steps for k, v in s64["stage_ms"].items()},
                        "autotune": s64["autotune"]}
         out["speedup_vs_fp64"] = t64 / r["seconds"]

@@ -59,10 +59,37 @@ struct SumPlan {
 };
 
 // partials part[(slot * n_chunks + chunk) * 5 + k][part_stride]; chunks past a
-// path's own range write zeros
+// path's own range write zeros.  With qidx, the kernel sums pl.nq points
+// whose indices (into the point arrays and the partials) are qidx[0..nq).
 void launch_sum(hipStream_t st, const SumPlan &pl, const PathTab &tab, const double *px, const double *py,
                 const double *pz, const double *pq2, const float *fx, const float *fy, const float *fz,
-                const float *fq2, const double *c64, const float *c32, double *part);
+                const float *fq2, const double *c64, const float *c32, double *part,
+                const int32_t *qidx = nullptr);
+
+// A planar face whose points form the grid x[ax_a] = sa[a], x[ax_b] = sb[b],
+// x[ax_n] = sn (centred coordinates), point index off + b * na + a.
+struct TFace {
+  int na, nb, ax_a, ax_b, ax_n;
+  int64_t off;
+  double sn;
+  const double *sa, *sb;
+};
+// 32 x 32 point tiles of the tensor faces: {face, b0, a0, 0}
+struct TensorArgs {
+  const TFace *faces;
+  const int4 *tiles;
+  int n_tiles;
+  const double *sx, *sy, *sz;    // centred source positions (all paths)
+  const double *c64;             // coefficient records (c, ..., ln A at [5])
+  double *part;
+  int64_t stride;
+  int max_groups;                // workgroups of a launch (0: one per work item)
+};
+constexpr int kTensorTile = 32;
+// the kernel sum at the points of the tensor faces as matrix products over
+// the sources (matrix cores): FP32 for the far chunks, FP64 for the near
+// chunks, the same chunks and partial layout as launch_sum
+void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, const TensorArgs &a);
 
 // reduce chunk partials; T, grad; per-point load density:
 //   NEUMANN: -k (grad . n) w dS,  DIRICHLET: -T~ w dS,  else 0

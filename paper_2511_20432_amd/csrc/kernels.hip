@@ -116,7 +116,7 @@ __global__ void k_coeff(PathTab tab, const int64_t *__restrict__ tick, const dou
   o[2] = -2.0 * c * y;
   o[3] = -2.0 * c * z;
   o[4] = K;
-  o[5] = 0.0;
+  o[5] = log(amp);
   o[6] = 0.0;
   o[7] = 0.0;
   if (j < tab.n_far[slot]) {
@@ -149,6 +149,176 @@ void launch_coeff(hipStream_t st, const PathTab &tab, int64_t max_act, const int
 }
 
 // ---------------------------------------------------------------------------
+// kernel sum on tensor faces (matrix cores)
+//
+// On a face whose points form the grid (sa[a], sb[b], sn) along Cartesian
+// axes, the Gaussian of Eq. 8 factorises over the axes:
+//   A e^{c |x - x_i|^2} = L_i[b] R_i[a],  L = A e^{c (sb - x_ib)^2 + c (sn - x_in)^2},
+//                                         R = e^{c (sa - x_ia)^2},
+// and its gradient A e^{c r^2} 2c (x - x_i) has the components
+//   along a: L (2c da R),  along b: (2c db L) R,  along n: (2c dn L) R.
+// Over the sources of a chunk the four sums at the points of a 32 x 32 tile
+// are therefore matrix products [b x i] [i x a]: 16 x 16 x 4 matrix-core
+// steps, 4 sources per step, with the operands formed in the lanes (one
+// exponential per row or column and source instead of one per pair).  The
+// four waves of a workgroup take the four 16 x 16 blocks of a tile and share
+// the chunk's sources, staged in LDS 256 at a time.
+// Operand layout of the 16 x 16 x 4 steps: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element r of lane l is D[4 (l / 16) + r][l % 16] for
+// FP32 and D[4 r + l / 16][l % 16] for FP64 (checked on the device).
+// Far chunks: FP32 operands and accumulation, folded into FP64 every 8 steps;
+// near chunks: FP64.
+// ---------------------------------------------------------------------------
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kStage = 256;   // sources staged in LDS at a time
+
+template <bool FAR>
+__global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
+                                                    int chunk_far, int chunk_near) {
+  __shared__ double src[5][kStage];   // c, x_a, x_b, 2 c dn, ln A + c dn^2 of the staged sources
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, k = lane >> 4;
+  // work items (tile, chunk of this kind, slot), taken in turn by the
+  // workgroups of a grid sized to leave room on the compute units
+  const int n_kind = FAR ? n_chunks_far : n_chunks - n_chunks_far;
+  const int n_items = ta.n_tiles * n_kind * tab.count;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const int tile = item % ta.n_tiles;
+  const int ck = (item / ta.n_tiles) % n_kind;
+  const int slot = item / (ta.n_tiles * n_kind);
+  const int4 tl = ta.tiles[tile];
+  const TFace F = ta.faces[tl.x];
+  // this wave's 16 x 16 block of the tile: rows b, columns a
+  const int b0 = tl.y + 16 * (wave >> 1), a0 = tl.z + 16 * (wave & 1);
+  const int chunk = FAR ? ck : n_chunks_far + ck;
+  int lo, hi;
+  if (FAR) {
+    lo = ck * chunk_far;
+    const int e = lo + chunk_far < tab.n_far[slot] ? lo + chunk_far : tab.n_far[slot];
+    hi = tab.mode[slot] ? lo : e;
+  } else {
+    lo = tab.n_far[slot] + ck * chunk_near;
+    hi = lo + chunk_near < tab.n_act[slot] ? lo + chunk_near : tab.n_act[slot];
+  }
+  const int64_t s0 = tab.src0[slot];
+  const double *c64 = ta.c64 + s0 * kCoefStride;
+  const double *pa = (F.ax_a == 0 ? ta.sx : (F.ax_a == 1 ? ta.sy : ta.sz)) + s0;
+  const double *pb = (F.ax_b == 0 ? ta.sx : (F.ax_b == 1 ? ta.sy : ta.sz)) + s0;
+  const double *pn = (F.ax_n == 0 ? ta.sx : (F.ax_n == 1 ? ta.sy : ta.sz)) + s0;
+  const int bi = b0 + j, ai = a0 + j;
+  const bool vb = bi < F.nb, va = ai < F.na;
+  const double sb = F.sb[vb ? bi : 0], sa = F.sa[va ? ai : 0];
+  // acc[g]: g = 0 T, 1 along a, 2 along b, 3 along n
+  dx4 acc[4];
+  fx4 accf[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    acc[g] = dx4{0.0, 0.0, 0.0, 0.0};
+    accf[g] = fx4{0.f, 0.f, 0.f, 0.f};
+  }
+  const double l2e = 1.4426950408889634;
+  for (int blk = lo; blk < hi; blk += kStage) {
+    const int n_in = hi - blk < kStage ? hi - blk : kStage;
+    __syncthreads();
+    if ((int)threadIdx.x < n_in) {
+      const int i = blk + (int)threadIdx.x;
+      const double c = c64[(int64_t)i * kCoefStride], lnA = c64[(int64_t)i * kCoefStride + 5];
+      const double dn = F.sn - pn[i];
+      src[0][threadIdx.x] = c;
+      src[1][threadIdx.x] = pa[i];
+      src[2][threadIdx.x] = pb[i];
+      src[3][threadIdx.x] = 2.0 * c * dn;
+      src[4][threadIdx.x] = fma(c * dn, dn, lnA);
+    }
+    __syncthreads();
+    if (FAR) {
+      // groups of 8 steps (32 sources), then into FP64; the steps past the
+      // staged sources contribute zeros
+      for (int g8 = 0; g8 < n_in; g8 += 32) {
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          int t = g8 + 4 * s8 + k;
+          const bool vi = t < n_in;
+          t = vi ? t : n_in - 1;
+          const double c = src[0][t], xa = src[1][t], xb = src[2][t], tn = src[3][t], base = src[4][t];
+          const double db = sb - xb, da = sa - xa;
+          const float e = __builtin_amdgcn_exp2f((float)(fma(c * db, db, base) * l2e));
+          const float L0 = (vi && vb) ? e : 0.f;
+          const float Lb = L0 * (float)(2.0 * c * db);
+          const float Ln = L0 * (float)tn;
+          const float r = __builtin_amdgcn_exp2f((float)(c * da * da * l2e));
+          const float R0 = va ? r : 0.f;
+          const float Ra = R0 * (float)(2.0 * c * da);
+          accf[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, R0, accf[0], 0, 0, 0);
+          accf[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, Ra, accf[1], 0, 0, 0);
+          accf[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(Lb, R0, accf[2], 0, 0, 0);
+          accf[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ln, R0, accf[3], 0, 0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+#pragma unroll
+          for (int r2 = 0; r2 < 4; ++r2) acc[g][r2] += (double)accf[g][r2];
+          accf[g] = fx4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    } else {
+      const int n_steps = (n_in + 3) / 4;
+      for (int st = 0; st < n_steps; ++st) {
+        int t = 4 * st + k;
+        const bool vi = t < n_in;
+        t = vi ? t : n_in - 1;
+        const double c = src[0][t], xa = src[1][t], xb = src[2][t], tn = src[3][t], base = src[4][t];
+        const double db = sb - xb, da = sa - xa;
+        const double e = exp_f64(fma(c * db, db, base));
+        const double L0 = (vi && vb) ? e : 0.0;
+        const double Lb = L0 * (2.0 * c * db);
+        const double Ln = L0 * tn;
+        const double r = exp_f64(c * da * da);
+        const double R0 = va ? r : 0.0;
+        const double Ra = R0 * (2.0 * c * da);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, R0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, Ra, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lb, R0, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ln, R0, acc[3], 0, 0, 0);
+      }
+    }
+  }
+  double *o = ta.part + ((int64_t)slot * n_chunks + chunk) * 5 * ta.stride;
+  const int64_t S = ta.stride;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    // row of element r of this lane: 4 (l / 16) + r for FP32 steps, 4 r + l / 16 for FP64 steps
+    const int br = b0 + (FAR ? 4 * k + r : 4 * r + k);
+    if (br >= F.nb || !va) continue;
+    const int64_t q = F.off + (int64_t)br * F.na + ai;
+    o[q] = acc[0][r];
+    o[S + q] = 0.0;
+    o[(2 + F.ax_a) * S + q] = acc[1][r];
+    o[(2 + F.ax_b) * S + q] = acc[2][r];
+    o[(2 + F.ax_n) * S + q] = acc[3][r];
+  }
+  __syncthreads();   // the staged sources of this item are no longer read
+  }
+}
+
+void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, const TensorArgs &a) {
+  if (a.n_tiles <= 0 || tab.count <= 0) return;
+  const int nch = pl.n_chunks_far + pl.n_chunks_near;
+  auto grid = [&](int n_kind) {
+    const int64_t items = (int64_t)a.n_tiles * n_kind * tab.count;
+    return (unsigned)(a.max_groups > 0 && items > a.max_groups ? a.max_groups : items);
+  };
+  if (pl.n_chunks_far > 0)
+    hipLaunchKernelGGL(k_sum_tensor<true>, dim3(grid(pl.n_chunks_far)), dim3(256), 0, st, a, tab, pl.n_chunks_far,
+                       nch, pl.chunk_far, pl.chunk_near);
+  if (pl.n_chunks_near > 0)
+    hipLaunchKernelGGL(k_sum_tensor<false>, dim3(grid(pl.n_chunks_near)), dim3(256), 0, st, a, tab,
+                       pl.n_chunks_far, nch, pl.chunk_far, pl.chunk_near);
+}
+
+// ---------------------------------------------------------------------------
 // kernel sum
 // ---------------------------------------------------------------------------
 struct SumArgs {
@@ -159,6 +329,7 @@ struct SumArgs {
   double *part;
   int64_t nq, stride;
   int n_chunks_far, n_chunks, chunk_far, chunk_near;
+  const int32_t *qidx;    // optional point indices (nq of them)
 };
 
 
@@ -173,10 +344,13 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
   const double *c64 = a.c64 + tab.src0[slot] * kCoefStride;
   const float *c32 = a.c32 + tab.src0[slot] * kCoefStride;
   double x[P], y[P], z[P], q2[P];
+  int64_t qq[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     int64_t q = base + 64 * j;
     q = q < a.nq ? q : a.nq - 1;
+    q = a.qidx ? a.qidx[q] : q;
+    qq[j] = q;
     x[j] = a.px[q];
     y[j] = a.py[q];
     z[j] = a.pz[q];
@@ -192,11 +366,9 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
     float xf[P], yf[P], zf[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      int64_t q = base + 64 * j;
-      q = q < a.nq ? q : a.nq - 1;
-      xf[j] = a.fx[q];
-      yf[j] = a.fy[q];
-      zf[j] = a.fz[q];
+      xf[j] = a.fx[qq[j]];
+      yf[j] = a.fy[qq[j]];
+      zf[j] = a.fz[qq[j]];
     }
     const double ln2 = 0.6931471805599453;
     // tiles are the aligned blocks of the FP32 records (lo is a multiple of kTile32)
@@ -270,8 +442,8 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
   double *o = a.part + ((int64_t)slot * a.n_chunks + chunk) * 5 * a.stride;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const int64_t q = base + 64 * j;
-    if (q < a.nq) {
+    if (base + 64 * j < a.nq) {
+      const int64_t q = qq[j];
       o[q] = s0[j];
       o[a.stride + q] = s1[j];
       o[2 * a.stride + q] = sx[j];
@@ -283,11 +455,11 @@ __global__ __launch_bounds__(512) void k_sum(SumArgs a, PathTab tab) {
 
 void launch_sum(hipStream_t st, const SumPlan &pl, const PathTab &tab, const double *px, const double *py,
                 const double *pz, const double *pq2, const float *fx, const float *fy, const float *fz,
-                const float *fq2, const double *c64, const float *c32, double *part) {
+                const float *fq2, const double *c64, const float *c32, double *part, const int32_t *qidx) {
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
   if (nch <= 0 || pl.nq <= 0 || tab.count <= 0) return;
   SumArgs a{px, py, pz, pq2, fx, fy, fz, fq2, c64, c32, part, pl.nq, pl.part_stride,
-            pl.n_chunks_far, nch, pl.chunk_far, pl.chunk_near};
+            pl.n_chunks_far, nch, pl.chunk_far, pl.chunk_near, qidx};
   const int64_t per_block = (int64_t)64 * pl.points_per_lane * pl.waves;
   dim3 g((unsigned)((pl.nq + per_block - 1) / per_block), (unsigned)nch, (unsigned)tab.count);
   dim3 b(64 * pl.waves);

@@ -133,6 +133,12 @@ struct sa_iga {
   double *rD = nullptr, *zD = nullptr, *pDg = nullptr, *qD = nullptr;
   double *part_b = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_rr = nullptr;
   sa::PcgScalars *sc_gen = nullptr;
+  // boundary points on tensor faces: their kernel sums run as matrix
+  // products; the points of the other faces go through the generic kernel
+  bool use_tensor = false;
+  sa::TensorArgs tens{};
+  int32_t *gen_idx = nullptr;
+  int64_t n_gen = 0;
   // kernel-sum partials: two buffers used in turn, so that the sum of the
   // next batch can run while the last one is reduced
   double *partb[2] = {nullptr, nullptr};
@@ -401,7 +407,8 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
                 const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
                 const float *fz, const float *fq2, const int8_t *role, const double *nx, const double *ny,
                 const double *nz, const double *wdS, bool by_slot, int64_t ostride, double *T, double *G,
-                double *ld, const double *net = nullptr, int64_t net_stride = 0, hipStream_t post = nullptr) {
+                double *ld, const double *net = nullptr, int64_t net_stride = 0, hipStream_t post = nullptr,
+                bool boundary = false) {
   int64_t max_act = 0, max_far = 0, max_near = 0;
   for (int s = 0; s < tab.count; ++s) {
     const int64_t nf = tab.mode[s] ? 0 : tab.n_far[s];      // far sources summed here
@@ -430,7 +437,20 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
   if (h->part_live[b]) hip_check(hipStreamWaitEvent(st, h->ev_part[b], 0), "stream wait");
   if (nch > 0) {
     StageScope s(h, SA_STAGE_SUM, st);
-    sa::launch_sum(st, pl, tab, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, part);
+    if (boundary && h->use_tensor) {
+      sa::TensorArgs ta = h->tens;
+      ta.c64 = h->c64;
+      ta.part = part;
+      ta.stride = stride;
+      sa::launch_sum_tensor(st, pl, tab, ta);
+      if (h->n_gen > 0) {
+        sa::SumPlan pg = pl;
+        pg.nq = h->n_gen;
+        sa::launch_sum(st, pg, tab, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, part, h->gen_idx);
+      }
+    } else {
+      sa::launch_sum(st, pl, tab, px, py, pz, pq2, fx, fy, fz, fq2, h->c64, h->c32, part);
+    }
   }
   if (fs != st) {
     hip_check(hipEventRecord(h->ev_sum[b], st), "event record");
@@ -699,7 +719,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
   // T~, grad T~ and load densities at every boundary point (Eqs. 7-8, 10-11)
   const hipStream_t as = post_stream(h);
   sum_points(h, tab, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
-             h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD, net, h->stride, as);
+             h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD, net, h->stride, as, true);
   double *Vc = h->V[cur], *Vn = h->V[nxt], *Fc = h->Fb[cur], *Fn = h->Fb[nxt];
   if (h->overlap) {
     // F^{n+1} and the Dirichlet values of u^{n+1} overwrite F^{n-1} and
@@ -1168,6 +1188,115 @@ void build_network_state(sa_iga *h, const sa_patch *patch, const sa_scan_path *s
   hip_check(hipGetLastError(), "kernel launch");
 }
 
+// Faces whose boundary points form a grid along Cartesian axes: the points of
+// face f are stored as off + b * na + a (a the faster parametric direction of
+// the face, Gauss points within elements), so the check is that coordinate
+// ax_a depends on a only, ax_b on b only and ax_n is constant, each within
+// 1e-14 of the patch size (a few units in the last place).
+void build_tensor_faces(sa_iga *h) {
+  const sa::Model &m = h->m;
+  const sa::BoundaryTables &bt = m.bt;
+  const sa::PatchData &P = m.P;
+  std::vector<sa::TFace> faces;
+  std::vector<int32_t> tiles, gen;
+  std::vector<double> coords;
+  std::vector<std::pair<size_t, size_t>> where;   // per tensor face: offsets of sa, sb in coords
+  double ext = 0.0;
+  for (int64_t q = 0; q < bt.nq; ++q)
+    for (int c = 0; c < 3; ++c) ext = std::max(ext, std::fabs(bt.x[3 * q + c] - P.center[c]));
+  const double tol = 1e-14 * std::max(ext, 1e-300);
+  const bool allow = !std::getenv("SA_IGA_NO_TENSOR");
+  for (int f = 0; f < 6; ++f) {
+    const int64_t off = bt.face_off[f], n = bt.face_off[f + 1] - off;
+    if (n <= 0) continue;
+    const int d = f / 2, pa = (d == 0) ? 1 : 0, pb = (d == 2) ? 1 : 2;
+    const int na = P.b[pa].n_el() * P.qf, nb = P.b[pb].n_el() * P.qf;
+    auto X = [&](int64_t q, int c) { return bt.x[3 * q + c] - P.center[c]; };
+    bool ok = allow && (int64_t)na * nb == n && na > 1 && nb > 1;
+    int ax[3] = {-1, -1, -1};   // a, b, n
+    if (ok) {
+      // the normal axis: the coordinate with the smallest spread over the face
+      double spread[3];
+      for (int c = 0; c < 3; ++c) {
+        double lo = X(off, c), hi = lo;
+        for (int64_t q = off; q < off + n; ++q) {
+          lo = std::min(lo, X(q, c));
+          hi = std::max(hi, X(q, c));
+        }
+        spread[c] = hi - lo;
+      }
+      ax[2] = (int)(std::min_element(spread, spread + 3) - spread);
+      // along a (first row) the coordinate that moves most
+      double best = -1.0;
+      for (int c = 0; c < 3; ++c) {
+        if (c == ax[2]) continue;
+        const double v = std::fabs(X(off + na - 1, c) - X(off, c));
+        if (v > best) { best = v; ax[0] = c; }
+      }
+      ax[1] = 3 - ax[0] - ax[2];
+      const double sn = X(off, ax[2]);
+      for (int b = 0; b < nb && ok; ++b)
+        for (int a = 0; a < na && ok; ++a) {
+          const int64_t q = off + (int64_t)b * na + a;
+          ok = std::fabs(X(q, ax[0]) - X(off + a, ax[0])) <= tol && std::fabs(X(q, ax[1]) - X(off + (int64_t)b * na, ax[1])) <= tol &&
+               std::fabs(X(q, ax[2]) - sn) <= tol;
+        }
+    }
+    if (!ok) {
+      for (int64_t q = off; q < off + n; ++q) gen.push_back((int32_t)q);
+      continue;
+    }
+    sa::TFace F{};
+    F.na = na;
+    F.nb = nb;
+    F.ax_a = ax[0];
+    F.ax_b = ax[1];
+    F.ax_n = ax[2];
+    F.off = off;
+    F.sn = X(off, ax[2]);
+    where.push_back({coords.size(), coords.size() + (size_t)na});
+    for (int a = 0; a < na; ++a) coords.push_back(X(off + a, ax[0]));
+    for (int b = 0; b < nb; ++b) coords.push_back(X(off + (int64_t)b * na, ax[1]));
+    const int fi = (int)faces.size();
+    faces.push_back(F);
+    for (int b0 = 0; b0 < nb; b0 += sa::kTensorTile)
+      for (int a0 = 0; a0 < na; a0 += sa::kTensorTile) {
+        tiles.push_back(fi);
+        tiles.push_back(b0);
+        tiles.push_back(a0);
+        tiles.push_back(0);
+      }
+  }
+  if (faces.empty()) return;
+  const double *dc = dev_upload(h->owned, coords, h->stream);
+  for (size_t i = 0; i < faces.size(); ++i) {
+    faces[i].sa = dc + where[i].first;
+    faces[i].sb = dc + where[i].second;
+  }
+  std::vector<uint8_t> raw(faces.size() * sizeof(sa::TFace));
+  std::memcpy(raw.data(), faces.data(), raw.size());
+  h->tens = sa::TensorArgs{};
+  h->tens.faces = (const sa::TFace *)dev_upload(h->owned, raw, h->stream);
+  h->tens.tiles = (const int4 *)dev_upload(h->owned, tiles, h->stream);
+  h->tens.n_tiles = (int)(tiles.size() / 4);
+  h->tens.sx = h->sx;
+  h->tens.sy = h->sy;
+  h->tens.sz = h->sz;
+  {
+    // workgroups per compute unit of the sum: room is left for the solver
+    // kernels that run beside it
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, h->device), "device properties");
+    const char *g = std::getenv("SA_IGA_SUM_GROUPS_PER_CU");
+    const int per_cu = g ? std::max(0, std::atoi(g)) : 2;
+    h->tens.max_groups = per_cu * prop.multiProcessorCount;
+  }
+  h->n_gen = (int64_t)gen.size();
+  if (!gen.empty()) h->gen_idx = dev_upload(h->owned, gen, h->stream);
+  h->use_tensor = true;
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+}
+
 // Three streams per device, shared by every object and kept until the
 // process ends: the solves (an object's own stream), the sums and the
 // post-processing.  Hardware queues are few (four per process by default);
@@ -1331,6 +1460,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
       throw sa::SaError{SA_EINVAL, "a path holds more than 2e9 sources"};
   h->c64 = dev_alloc<double>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
   h->c32 = dev_alloc<float>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
+  build_tensor_faces(h);
 
   // per-path state: u = T0 (v = 0), F = 0, Dirichlet values 0
   h->paths.resize(S);
@@ -1580,9 +1710,10 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   if (h->verbose)
     std::fprintf(stderr,
                  "[sa_iga] paths %d ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: exact %d direct %d one-wg %d | "
-                 "theta-step: fused %d fd-exact %d budget %d kron %d\n",
+                 "theta-step: fused %d fd-exact %d budget %d kron %d | tensor tiles %d, generic points %lld\n",
                  S, (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_exact, (int)h->dir_direct,
-                 (int)h->dir_fused, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget, (int)h->kron);
+                 (int)h->dir_fused, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget, (int)h->kron,
+                 h->use_tensor ? h->tens.n_tiles : 0, (long long)(h->use_tensor ? h->n_gen : h->nq));
 }
 
 // parametric query points -> device CSR rows of basis values (and gradients)
@@ -2115,7 +2246,7 @@ int sa_iga_far_field(sa_iga *h, int32_t path, int64_t step, double e_scale, floa
     const sa_stats keep = h->stats;
     // T and grad written directly in the caller's layout (slot 0, stride n_bpts)
     sum_points(h, ex, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
-               h->nx, h->ny, h->nz, h->wdS, true, h->nq, T, grad, h->LD);
+               h->nx, h->ny, h->nz, h->wdS, true, h->nq, T, grad, h->LD, nullptr, 0, nullptr, true);
     h->stats.pairs = keep.pairs;
     h->stats.pairs_near = keep.pairs_near;
     if (X) {
