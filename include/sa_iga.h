@@ -143,6 +143,9 @@ typedef struct {
   int32_t n_paths;
   int64_t n_sources;
   int64_t n_dirichlet;         /* control variables fixed by DIRICHLET faces */
+  int32_t tensor_faces;        /* planar faces whose points form a grid along Cartesian axes: their
+                                  kernel sums run as matrix products (the Gaussian of Eq. 8 factorises) */
+  int64_t generic_points;      /* boundary points of the other faces (summed pair by pair) */
 } sa_info;
 
 enum sa_stage {

@@ -136,6 +136,7 @@ struct sa_iga {
   // boundary points on tensor faces: their kernel sums run as matrix
   // products; the points of the other faces go through the generic kernel
   bool use_tensor = false;
+  int n_tfaces = 0;
   sa::TensorArgs tens{};
   int32_t *gen_idx = nullptr;
   int64_t n_gen = 0;
@@ -1292,6 +1293,7 @@ void build_tensor_faces(sa_iga *h) {
     h->tens.max_groups = per_cu * prop.multiProcessorCount;
   }
   h->n_gen = (int64_t)gen.size();
+  h->n_tfaces = (int)faces.size();
   if (!gen.empty()) h->gen_idx = dev_upload(h->owned, gen, h->stream);
   h->use_tensor = true;
   hip_check(hipStreamSynchronize(h->stream), "sync");
@@ -2121,6 +2123,8 @@ int sa_iga_get_info(sa_iga *h, sa_info *info) {
     info->n_paths = (int32_t)h->paths.size();
     info->n_sources = (int64_t)h->h_tick.size();
     info->n_dirichlet = h->nD;
+    info->tensor_faces = h->use_tensor ? h->n_tfaces : 0;
+    info->generic_points = h->use_tensor ? h->n_gen : h->nq;
     return SA_OK;
   });
 }
