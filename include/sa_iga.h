@@ -176,6 +176,8 @@ typedef struct {
   int64_t audits;              /* audits run */
   int64_t audit_failures;      /* audits above audit_tol (the path then uses the exact sum) */
   double audit_max_err;        /* largest audited error of the far temperature (K) */
+  int64_t rollbacks;           /* calls whose steps were run again with a second PCG iteration
+                                  (one iteration did not reach the tolerance on some step) */
 } sa_stats;
 
 /* Fill *opt with the defaults listed above. */

@@ -164,8 +164,13 @@ struct sa_iga {
   sa::DirDirect ddir{};
   sa::PcgScalars *sc_dir = nullptr;      // [S], never set: the direct solve always runs
   bool pcg_fused = false, fd_exact = false;
-  int pcg_budget = 2;                    // fixed iterations when the FD solve is exact: the
-                                         // residual after the first is near kappa(A) eps
+  // PCG iterations launched per theta-step when the FD solve is exact.  One
+  // nearly always reaches the tolerance; the steps of a call run with one,
+  // and if any step needed more, the call is run again from its start with
+  // two (a device checkpoint of the state is kept for that).
+  int pcg_budget = 1;
+  bool force_rollback = false;           // SA_IGA_FORCE_ROLLBACK: fail the one-iteration pass (tests)
+  std::vector<double *> ckpt;            // V[0], V[1], Fb[0], Fb[1], vD
   sa::FusedPcg fp{};
   double bw2 = 0.0;                      // (64 eps |A|_inf)^2, attainable-accuracy test
   bool kron = false;                     // matrix-free Kronecker A and B (affine patch)
@@ -522,6 +527,10 @@ int pcg_run(sa_iga *h, PcgSpec &s, double *relres) {
 }
 
 // ---- device solve records ----------------------------------------------------
+// a theta-step that one PCG iteration did not bring to the tolerance (the
+// call is then run again with two)
+struct BudgetExceeded {};
+
 void check_statuses(sa_iga *h) {
   const size_t used = h->status_kind.size();
   if (used == 0) return;
@@ -544,6 +553,8 @@ void check_statuses(sa_iga *h) {
       h->stats.pcg_last_relres = std::sqrt(std::max(st[i].relres2, 0.0));
     }
   }
+  if (bad >= 0 && kind[bad] == 1 && st[bad].done == 0 && h->fd_exact && h->pcg_budget == 1)
+    throw BudgetExceeded{};
   if (bad >= 0) {
     char msg[200];
     std::snprintf(msg, sizeof msg,
@@ -870,6 +881,10 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       else sa::launch_stencil_sl(bsx, sm, ap, h->hw0, false);
     };
     sa::launch_fd_pass(bsx, sm, f, 0, true, false);
+    if (h->fd_exact && h->pcg_budget == 1 && h->force_rollback) {
+      f.rtol2 = 0.0;   // no residual passes: the one-iteration pass fails
+      f.bw2 = 0.0;
+    }
     if (h->fd_exact) {
       // with the exact preconditioner the first iteration nearly always
       // converges: test |r| right after the update, and run the FD solve and
@@ -1688,6 +1703,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   // work buffers the two sides do not share.
   h->overlap = h->pcg_fused && (h->nD == 0 || h->dir_direct || h->dir_exact || h->dir_fused) &&
                !std::getenv("SA_IGA_SERIAL");
+  h->force_rollback = std::getenv("SA_IGA_FORCE_ROLLBACK") != nullptr;
   for (int b = 0; b < 2; ++b) {
     hip_check(hipEventCreateWithFlags(&h->ev_sum[b], hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&h->ev_part[b], hipEventDisableTiming), "event");
@@ -1873,6 +1889,64 @@ void run_steps(sa_iga *h, int32_t n_steps) {
 }
 
 // after a failed run_steps: drain the streams, drop pending records
+void abandon_steps(sa_iga *h);
+
+// the per-path state a call changes: kept on the device while the steps run
+// with one PCG iteration
+struct HostState {
+  std::vector<int64_t> steps;
+  sa_stats stats{};
+  std::vector<uint8_t> use_exact;
+};
+
+void save_state(sa_iga *h, HostState &c) {
+  const size_t S = (size_t)h->S, nd = (size_t)h->nd, nDa = (size_t)h->nDa;
+  double *src[5] = {h->V[0], h->V[1], h->Fb[0], h->Fb[1], h->vD};
+  const size_t n[5] = {S * nd, S * nd, S * nd, S * nd, S * nDa};
+  if (h->ckpt.empty())
+    for (int b = 0; b < 5; ++b) h->ckpt.push_back(dev_alloc<double>(h->owned, n[b]));
+  for (int b = 0; b < 5; ++b)
+    hip_check(hipMemcpyAsync(h->ckpt[b], src[b], n[b] * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "copy");
+  c.steps.resize(h->paths.size());
+  for (size_t p = 0; p < h->paths.size(); ++p) c.steps[p] = h->paths[p].step;
+  c.stats = h->stats;
+  c.use_exact = h->use_exact;
+}
+
+void restore_state(sa_iga *h, const HostState &c) {
+  const size_t S = (size_t)h->S, nd = (size_t)h->nd, nDa = (size_t)h->nDa;
+  double *dst[5] = {h->V[0], h->V[1], h->Fb[0], h->Fb[1], h->vD};
+  const size_t n[5] = {S * nd, S * nd, S * nd, S * nd, S * nDa};
+  for (int b = 0; b < 5; ++b)
+    hip_check(hipMemcpyAsync(dst[b], h->ckpt[b], n[b] * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "copy");
+  hip_check(hipStreamSynchronize(h->stream), "sync");
+  for (size_t p = 0; p < h->paths.size(); ++p) h->paths[p].step = c.steps[p];
+  h->stats = c.stats;
+  h->use_exact = c.use_exact;
+}
+
+// run_steps with one PCG iteration per theta-step where that is the budget;
+// if a step needed more, the state goes back to the call's start and the
+// steps run again with two
+void run_steps_checked(sa_iga *h, int32_t n_steps) {
+  if (!(h->fd_exact && h->pcg_budget == 1) || n_steps <= 0) {
+    run_steps(h, n_steps);
+    return;
+  }
+  HostState c;
+  save_state(h, c);
+  try {
+    run_steps(h, n_steps);
+  } catch (const BudgetExceeded &) {
+    abandon_steps(h);
+    restore_state(h, c);
+    h->pcg_budget = 2;
+    h->force_rollback = false;
+    h->stats.rollbacks++;
+    run_steps(h, n_steps);
+  }
+}
+
 void abandon_steps(sa_iga *h) {
   if (h->ss) (void)hipStreamSynchronize(h->ss);
   if (h->ps) (void)hipStreamSynchronize(h->ps);
@@ -1924,7 +1998,7 @@ int sa_iga_step(sa_iga *h, int32_t n_steps) {
     if (n_steps < 0) throw sa::SaError{SA_EINVAL, "n_steps must be >= 0"};
     if (h->sticky) throw sa::SaError{SA_ESTATE, "object is in an error state (load a checkpoint)"};
     try {
-      run_steps(h, n_steps);
+      run_steps_checked(h, n_steps);
     } catch (const sa::SaError &e) {
       if (e.code == SA_ENOCONV) h->sticky = 1;
       abandon_steps(h);
@@ -2077,9 +2151,9 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
             o.waves_per_group = w;
             for (int p = 0; p < S; ++p)
               h->paths[p].step = std::max<int64_t>(0, h->paths[p].n_steps / 2 - 1 - reps);
-            run_steps(h, 1);
+            run_steps_checked(h, 1);
             const auto t0 = std::chrono::steady_clock::now();
-            run_steps(h, reps);
+            run_steps_checked(h, reps);
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             if (best < 0 || ms < best) {
               best = ms;

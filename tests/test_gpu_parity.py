@@ -217,6 +217,33 @@ def test_deterministic_and_checkpoint_resume():
         assert np.array_equal(x, y)
 
 
+def test_forced_rollback_equals_normal_run(monkeypatch):
+    """A theta-step runs one PCG iteration (the fast-diagonalisation solve is
+    exact on the block); when a step needs more, the call runs again from its
+    start with two.  Forcing the one-iteration pass to fail gives bitwise the
+    results of the normal run, through one rollback."""
+    patch = W.small_block()
+    tracks = [W.sources_from_segments([W.Segment("line", 50.0 + 20 * i, 1.0, p0=np.array([0.1e-3, 0.2e-3 + 0.1e-3 * i, 0.5e-3]),
+                                                 p1=np.array([0.9e-3, 0.25e-3 + 0.1e-3 * i, 0.5e-3]))], 2e-6)
+              for i in range(3)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=[14, 9, 14])
+    normal = _gpu_model(patch, W.MAT_CFG, scan)
+    normal.step(14)
+    monkeypatch.setenv("SA_IGA_FORCE_ROLLBACK", "1")
+    forced = _gpu_model(patch, W.MAT_CFG, scan)
+    monkeypatch.delenv("SA_IGA_FORCE_ROLLBACK")
+    forced.step(6)
+    forced.step(8)
+    sn, sf = normal.stats(), forced.stats()
+    print(f"rollbacks normal {sn['rollbacks']} forced {sf['rollbacks']}; PCG iterations {sn['pcg_iterations']} "
+          f"vs {sf['pcg_iterations']} over {sn['steps']} path-steps", flush=True)
+    assert sn["rollbacks"] == 0 and sf["rollbacks"] == 1
+    assert sn["steps"] == sf["steps"]
+    for p in range(3):
+        for x, y in zip(normal.boundary_fields(p), forced.boundary_fields(p)):
+            assert np.array_equal(x, y)
+
+
 def test_empty_scan_and_zero_steps():
     patch = W.small_block()
     empty = W.make_scan([(np.zeros((0, 3)), np.zeros(0, np.int64), np.zeros(0))], 1e-5, 5, n_steps=[4])
