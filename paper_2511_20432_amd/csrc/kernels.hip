@@ -166,8 +166,8 @@ void launch_coeff(hipStream_t st, const PathTab &tab, int64_t max_act, const int
 // Operand layout of the 16 x 16 x 4 steps: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; element r of lane l is D[4 (l / 16) + r][l % 16] for
 // FP32 and D[4 r + l / 16][l % 16] for FP64 (checked on the device).
-// Far chunks: FP32 operands and accumulation, folded into FP64 every 8 steps;
-// near chunks: FP64.
+// Far chunks: FP32 operands (coordinates relative to the tile) and
+// accumulation, folded into FP64 every 16 steps; near chunks: FP64.
 // ---------------------------------------------------------------------------
 typedef double dx4 __attribute__((ext_vector_type(4)));
 typedef float fx4 __attribute__((ext_vector_type(4)));
@@ -177,7 +177,12 @@ constexpr int kStage = 256;   // sources staged in LDS at a time
 template <bool FAR>
 __global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
                                                     int chunk_far, int chunk_near) {
-  __shared__ double src[5][kStage];   // c, x_a, x_b, 2 c dn, ln A + c dn^2 of the staged sources
+  // staged per source.  FP64 steps: c, x_a, x_b, 2 c dn, ln A + c dn^2.
+  // FP32 steps (base 2, coordinates relative to the tile's first point, where
+  // they are small for the sources near the tile, the ones that matter):
+  // c log2 e, x_a - o_a, x_b - o_b, 2 c dn, (ln A + c dn^2) log2 e, 2 c.
+  __shared__ double src[5][kStage];
+  __shared__ float srf[6][kStage];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, k = lane >> 4;
   // work items (tile, chunk of this kind, slot), taken in turn by the
@@ -210,6 +215,8 @@ __global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, 
   const int bi = b0 + j, ai = a0 + j;
   const bool vb = bi < F.nb, va = ai < F.na;
   const double sb = F.sb[vb ? bi : 0], sa = F.sa[va ? ai : 0];
+  const double ob = F.sb[tl.y], oa = F.sa[tl.z];
+  const float sbr = (float)(sb - ob), sar = (float)(sa - oa);
   // acc[g]: g = 0 T, 1 along a, 2 along b, 3 along n
   dx4 acc[4];
   fx4 accf[4];
@@ -226,31 +233,42 @@ __global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, 
       const int i = blk + (int)threadIdx.x;
       const double c = c64[(int64_t)i * kCoefStride], lnA = c64[(int64_t)i * kCoefStride + 5];
       const double dn = F.sn - pn[i];
-      src[0][threadIdx.x] = c;
-      src[1][threadIdx.x] = pa[i];
-      src[2][threadIdx.x] = pb[i];
-      src[3][threadIdx.x] = 2.0 * c * dn;
-      src[4][threadIdx.x] = fma(c * dn, dn, lnA);
+      const double base = fma(c * dn, dn, lnA);
+      if (FAR) {
+        srf[0][threadIdx.x] = (float)(c * l2e);
+        srf[1][threadIdx.x] = (float)(pa[i] - oa);
+        srf[2][threadIdx.x] = (float)(pb[i] - ob);
+        srf[3][threadIdx.x] = (float)(2.0 * c * dn);
+        srf[4][threadIdx.x] = (float)(base * l2e);
+        srf[5][threadIdx.x] = (float)(2.0 * c);
+      } else {
+        src[0][threadIdx.x] = c;
+        src[1][threadIdx.x] = pa[i];
+        src[2][threadIdx.x] = pb[i];
+        src[3][threadIdx.x] = 2.0 * c * dn;
+        src[4][threadIdx.x] = base;
+      }
     }
     __syncthreads();
     if (FAR) {
-      // groups of 8 steps (32 sources), then into FP64; the steps past the
+      // groups of 16 steps (64 sources), then into FP64; the steps past the
       // staged sources contribute zeros
-      for (int g8 = 0; g8 < n_in; g8 += 32) {
+      for (int g16 = 0; g16 < n_in; g16 += 64) {
 #pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) {
-          int t = g8 + 4 * s8 + k;
+        for (int s16 = 0; s16 < 16; ++s16) {
+          int t = g16 + 4 * s16 + k;
           const bool vi = t < n_in;
           t = vi ? t : n_in - 1;
-          const double c = src[0][t], xa = src[1][t], xb = src[2][t], tn = src[3][t], base = src[4][t];
-          const double db = sb - xb, da = sa - xa;
-          const float e = __builtin_amdgcn_exp2f((float)(fma(c * db, db, base) * l2e));
+          const float cl = srf[0][t], xa = srf[1][t], xb = srf[2][t], tn = srf[3][t], base = srf[4][t],
+                      c2 = srf[5][t];
+          const float db = sbr - xb, da = sar - xa;
+          const float e = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
           const float L0 = (vi && vb) ? e : 0.f;
-          const float Lb = L0 * (float)(2.0 * c * db);
-          const float Ln = L0 * (float)tn;
-          const float r = __builtin_amdgcn_exp2f((float)(c * da * da * l2e));
+          const float Lb = L0 * (c2 * db);
+          const float Ln = L0 * tn;
+          const float r = __builtin_amdgcn_exp2f(cl * (da * da));
           const float R0 = va ? r : 0.f;
-          const float Ra = R0 * (float)(2.0 * c * da);
+          const float Ra = R0 * (c2 * da);
           accf[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, R0, accf[0], 0, 0, 0);
           accf[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, Ra, accf[1], 0, 0, 0);
           accf[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(Lb, R0, accf[2], 0, 0, 0);
