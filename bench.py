@@ -39,10 +39,14 @@ METRIC = "source×point pairs/s + θ-steps/s; mixed+surrogate vs FP64 GPU at ≤
 MFMA_FP32 = 157.3e12
 MFMA_FP64 = 78.6e12
 FLOPS_PER_PAIR = 8
-# HBM bytes per step of the sum kernels of this workload's FP32 far-field
-# form, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the same counters on
-# a 256 MiB copy.  None until the counters are taken on the current kernels.
-K_SUM_TRAFFIC = None
+# HBM bytes per step of the sum kernels (one launch each of k_sum_tensor<true>
+# and <false>) of this workload's FP32 far-field form, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE over steps 1480..1779, scaled by the same counters
+# on a 256 MiB copy (profiles/k_sum_tensor_raster_fp32far.md).  Valid for the
+# kernels as profiled; a changed sum kernel must set this to None until the
+# counters are taken again.  The written bytes are the FP64 chunk partials
+# (5 x 8 B per point and chunk) that k_finalize reads.
+K_SUM_TRAFFIC = {"read_bytes": 3.62e6, "written_bytes": 36.43e6}
 
 
 def _k_sum_traffic(form):
