@@ -174,22 +174,18 @@ typedef float fx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kStage = 256;   // sources staged in LDS at a time
 
+// one work item (tile, chunk of this kind, slot).  Staged per source in
+// LDS.  FP64 steps: c, x_a, x_b, 2 c dn, ln A + c dn^2.  FP32 steps (base 2,
+// coordinates relative to the tile's first point, where they are small for
+// the sources near the tile, the ones that matter): c log2 e, x_a - o_a,
+// x_b - o_b, 2 c dn, (ln A + c dn^2) log2 e, 2 c.
 template <bool FAR>
-__global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
-                                                    int chunk_far, int chunk_near) {
-  // staged per source.  FP64 steps: c, x_a, x_b, 2 c dn, ln A + c dn^2.
-  // FP32 steps (base 2, coordinates relative to the tile's first point, where
-  // they are small for the sources near the tile, the ones that matter):
-  // c log2 e, x_a - o_a, x_b - o_b, 2 c dn, (ln A + c dn^2) log2 e, 2 c.
-  __shared__ double src[5][kStage];
-  __shared__ float srf[6][kStage];
+__device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
+                                            int n_chunks, int chunk_far, int chunk_near, double (*src)[kStage],
+                                            float (*srf)[kStage]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, k = lane >> 4;
-  // work items (tile, chunk of this kind, slot), taken in turn by the
-  // workgroups of a grid sized to leave room on the compute units
   const int n_kind = FAR ? n_chunks_far : n_chunks - n_chunks_far;
-  const int n_items = ta.n_tiles * n_kind * tab.count;
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
   const int tile = item % ta.n_tiles;
   const int ck = (item / ta.n_tiles) % n_kind;
   const int slot = item / (ta.n_tiles * n_kind);
@@ -318,22 +314,32 @@ __global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, 
     o[(2 + F.ax_n) * S + q] = acc[3][r];
   }
   __syncthreads();   // the staged sources of this item are no longer read
+}
+
+// the far items (FP32) first, then the near ones (FP64), taken in turn by the
+// workgroups of a grid sized to leave room on the compute units
+__global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
+                                                    int chunk_far, int chunk_near) {
+  __shared__ double src[5][kStage];
+  __shared__ float srf[6][kStage];
+  const int n_far_items = ta.n_tiles * n_chunks_far * tab.count;
+  const int n_items = ta.n_tiles * n_chunks * tab.count;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    if (item < n_far_items)
+      tensor_item<true>(ta, tab, item, n_chunks_far, n_chunks, chunk_far, chunk_near, src, srf);
+    else
+      tensor_item<false>(ta, tab, item - n_far_items, n_chunks_far, n_chunks, chunk_far, chunk_near, src, srf);
   }
 }
 
 void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, const TensorArgs &a) {
   if (a.n_tiles <= 0 || tab.count <= 0) return;
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
-  auto grid = [&](int n_kind) {
-    const int64_t items = (int64_t)a.n_tiles * n_kind * tab.count;
-    return (unsigned)(a.max_groups > 0 && items > a.max_groups ? a.max_groups : items);
-  };
-  if (pl.n_chunks_far > 0)
-    hipLaunchKernelGGL(k_sum_tensor<true>, dim3(grid(pl.n_chunks_far)), dim3(256), 0, st, a, tab, pl.n_chunks_far,
-                       nch, pl.chunk_far, pl.chunk_near);
-  if (pl.n_chunks_near > 0)
-    hipLaunchKernelGGL(k_sum_tensor<false>, dim3(grid(pl.n_chunks_near)), dim3(256), 0, st, a, tab,
-                       pl.n_chunks_far, nch, pl.chunk_far, pl.chunk_near);
+  if (nch <= 0) return;
+  const int64_t items = (int64_t)a.n_tiles * nch * tab.count;
+  const unsigned grid = (unsigned)(a.max_groups > 0 && items > a.max_groups ? a.max_groups : items);
+  hipLaunchKernelGGL(k_sum_tensor, dim3(grid), dim3(256), 0, st, a, tab, pl.n_chunks_far, nch, pl.chunk_far,
+                     pl.chunk_near);
 }
 
 // ---------------------------------------------------------------------------

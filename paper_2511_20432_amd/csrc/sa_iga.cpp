@@ -745,16 +745,19 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     }
     if (last >= 0) hip_check(hipStreamWaitEvent(as, h->ev_rhs[last], 0), "stream wait");
   }
+  const bool dir_rhs = h->nD > 0 && (h->dir_exact || h->dir_fused);
   {
     StageScope s(h, SA_STAGE_LOAD, as);
-    // F^{n+1} on the non-empty rows (Eq. 18)
-    sa::launch_gather_rows(as, sm, h->grows, h->LD, h->stride, Fn, nd, 0, nullptr, nullptr);
+    // F^{n+1} on the non-empty rows (Eq. 18), with the right-hand side of the
+    // projection (Eq. 11) in the same launch
+    if (dir_rhs)
+      sa::launch_gather_rows2(as, sm, h->grows, Fn, nd, h->drows, h->bD, h->nDa, h->LD, h->stride);
+    else
+      sa::launch_gather_rows(as, sm, h->grows, h->LD, h->stride, Fn, nd, 0, nullptr, nullptr);
   }
   // Dirichlet values (Eq. 11), scattered into the Dirichlet DOFs of u^{n+1}
   if (h->nD > 0) {
     StageScope s(h, SA_STAGE_DIRICHLET, as);
-    if (h->dir_exact || h->dir_fused)
-      sa::launch_gather_rows(as, sm, h->drows, h->LD, h->stride, h->bD, h->nDa, 0, nullptr, nullptr);
     if (h->dir_direct) {
       sa::DirDirect a = h->ddir;
       a.xfull = Vn;
@@ -804,8 +807,9 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     hip_check(hipEventRecord(e, as), "event record");
     hip_check(hipStreamWaitEvent(bsx, e, 0), "stream wait");
   }
-  // first iterate: u^n on the free DOFs
-  sa::launch_copy_free(bsx, sm, nd, h->free_mask, Vc, Vn);
+  // first iterate: u^n on the free DOFs (in the first pass of the
+  // right-hand side on affine patches)
+  if (!(h->pcg_fused && h->kron)) sa::launch_copy_free(bsx, sm, nd, h->free_mask, Vc, Vn);
   // theta-scheme (Eq. 20)
   const int ev_slot = (int)(h->ev_next % (int64_t)std::max<size_t>(h->ev_rhs.size(), 1));
   h->ev_next++;
@@ -846,6 +850,8 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
         k.part = h->part_b2;
         k.sc = nullptr;
         k.sc_w = h->sc;
+        k.init_x = 1;
+        k.x_init = Vn;
         sa::launch_kron(bsx, sm, k, true);
       } else {
         sa::launch_stencil_sl(bsx, sm, a, h->hw0, true);

@@ -34,6 +34,10 @@ struct GatherRows {
 void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, const double *ld, int64_t ls,
                         double *F, int64_t fs, int64_t ncopy, const double *v, double *x);
 
+// two gathers of the same densities in one launch: F1 from g1, F2 from g2
+void launch_gather_rows2(hipStream_t st, const SlotMap &sm, const GatherRows &g1, double *F1, int64_t fs1,
+                         const GatherRows &g2, double *F2, int64_t fs2, const double *ld, int64_t ls);
+
 // per slot (path p): x[p*n + i] = v[p*n + i] for the free DOFs i (mask[i] != 0);
 // the entries of the Dirichlet DOFs of x are left as they are
 void launch_copy_free(hipStream_t st, const SlotMap &sm, int64_t n, const uint8_t *mask, const double *v,
@@ -105,6 +109,8 @@ struct KronArgs {
   double *out, *part;
   const PcgScalars *sc;   // apply: skip when done
   PcgScalars *sc_w;       // theta: resets the done flags
+  int init_x;             // theta: form the first iterate x = v on the free DOFs (mask) in the x pass
+  double *x_init;         // ... writable alias of x
 };
 void launch_kron(hipStream_t st, const SlotMap &sm, const KronArgs &a, bool theta);
 

@@ -19,6 +19,7 @@
 // partial sums, so results are deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -82,6 +83,36 @@ __global__ void k_gather_rows(SlotMap sm, int64_t nrows, const int32_t *__restri
     double *x = xb + pth * fs;
     for (int64_t i = gt; i < ncopy; i += (int64_t)gridDim.x * blockDim.x) x[i] = v[i];
   }
+}
+
+// two gathers of the same densities in one launch: the first blocks1 blocks
+// take g1 -> F1, the rest g2 -> F2
+__global__ void k_gather_rows2(SlotMap sm, int64_t blocks1, GatherRows g1, double *__restrict__ F1b, int64_t fs1,
+                               GatherRows g2, double *__restrict__ F2b, int64_t fs2,
+                               const double *__restrict__ ldb, int64_t ls) {
+  const int64_t pth = sm.path[blockIdx.y];
+  const double *ld = ldb + pth * ls;
+  const bool second = (int64_t)blockIdx.x >= blocks1;
+  const GatherRows &g = second ? g2 : g1;
+  double *F = second ? F2b + pth * fs2 : F1b + pth * fs1;
+  const int64_t gt = ((int64_t)blockIdx.x - (second ? blocks1 : 0)) * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & 15;
+  const int64_t r = gt >> 4;
+  double s = 0.0;
+  if (r < g.nrows) {
+    for (int64_t e = g.rowptr[r] + sub; e < g.rowptr[r + 1]; e += 16) s = fma(g.val[e], ld[g.col[e]], s);
+  }
+  for (int off = 8; off > 0; off >>= 1) s += __shfl_down(s, off, 16);
+  if (r < g.nrows && sub == 0) F[g.rows[r]] = s;
+}
+
+void launch_gather_rows2(hipStream_t st, const SlotMap &sm, const GatherRows &g1, double *F1, int64_t fs1,
+                         const GatherRows &g2, double *F2, int64_t fs2, const double *ld, int64_t ls) {
+  if (sm.count <= 0) return;
+  const int64_t b1 = std::max<int64_t>(1, (g1.nrows * 16 + kB - 1) / kB);
+  const int64_t b2 = std::max<int64_t>(1, (g2.nrows * 16 + kB - 1) / kB);
+  hipLaunchKernelGGL(k_gather_rows2, dim3((unsigned)(b1 + b2), (unsigned)sm.count), dim3(kB), 0, st, sm, b1, g1, F1,
+                     fs1, g2, F2, fs2, ld, ls);
 }
 
 void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, const double *ld, int64_t ls,
@@ -360,6 +391,25 @@ __device__ __forceinline__ double band_dot(const double *__restrict__ band, int 
   return s;
 }
 
+// band product of the first iterate: v on the free DOFs, x (the new Dirichlet
+// values) on the others
+__device__ __forceinline__ void band_dot_init(const double *__restrict__ Mb, const double *__restrict__ Kb, int p,
+                                              int i, int n, const uint8_t *__restrict__ mask,
+                                              const double *__restrict__ v, const double *x, int64_t base,
+                                              double &sm_, double &sk) {
+  const double *bm = Mb + (int64_t)i * (2 * p + 1), *bk = Kb + (int64_t)i * (2 * p + 1);
+  const int j0 = i - p < 0 ? 0 : i - p, j1 = i + p > n - 1 ? n - 1 : i + p;
+  double s0 = 0.0, s1 = 0.0;
+  for (int j = j0; j <= j1; ++j) {
+    const int64_t q = base + (j - i);
+    const double xv = mask[q] ? v[q] : x[q];
+    s0 = fma(bm[j - i + p], xv, s0);
+    s1 = fma(bk[j - i + p], xv, s1);
+  }
+  sm_ = s0;
+  sk = s1;
+}
+
 template <bool THETA>
 __global__ void k_kron_x(SlotMap sm, KronArgs a) {
   const int64_t pth = sm.path[blockIdx.y];
@@ -368,10 +418,21 @@ __global__ void k_kron_x(SlotMap sm, KronArgs a) {
   const int64_t N = a.nrow;
   if (r >= N) return;
   const int n0 = a.op.n[0], p = a.op.p[0], i0 = (int)(r % n0);
-  const double *x = a.x + pth * a.vs;
   double *t = a.t + pth * a.ts;
-  t[r] = band_dot(a.op.Mb[0], p, i0, n0, x, r, 1);
-  t[N + r] = band_dot(a.op.Kb[0], p, i0, n0, x, r, 1);
+  if (THETA && a.init_x) {
+    // first iterate formed here: no thread reads x at a free DOF, where it is written
+    double *x = a.x_init + pth * a.vs;
+    const double *v = a.v + pth * a.vs;
+    double s0, s1;
+    band_dot_init(a.op.Mb[0], a.op.Kb[0], p, i0, n0, a.mask, v, x, r, s0, s1);
+    t[r] = s0;
+    t[N + r] = s1;
+    if (a.mask[r]) x[r] = v[r];
+  } else {
+    const double *x = a.x + pth * a.vs;
+    t[r] = band_dot(a.op.Mb[0], p, i0, n0, x, r, 1);
+    t[N + r] = band_dot(a.op.Kb[0], p, i0, n0, x, r, 1);
+  }
   if (THETA) {
     const double *v = a.v + pth * a.vs;
     t[2 * N + r] = band_dot(a.op.Mb[0], p, i0, n0, v, r, 1);
