@@ -222,29 +222,43 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
     accf[g] = fx4{0.f, 0.f, 0.f, 0.f};
   }
   const double l2e = 1.4426950408889634;
+  // the next block's source data is loaded into registers while the current
+  // block is summed
+  double pc = 0.0, plnA = 0.0, ppa = 0.0, ppb = 0.0, ppn = 0.0;
+  auto fetch = [&](int blk) {
+    const int i = blk + (int)threadIdx.x;
+    if (i < hi) {
+      pc = c64[(int64_t)i * kCoefStride];
+      plnA = c64[(int64_t)i * kCoefStride + 5];
+      ppa = pa[i];
+      ppb = pb[i];
+      ppn = pn[i];
+    }
+  };
+  if (lo < hi) fetch(lo);
   for (int blk = lo; blk < hi; blk += kStage) {
     const int n_in = hi - blk < kStage ? hi - blk : kStage;
     __syncthreads();
     if ((int)threadIdx.x < n_in) {
-      const int i = blk + (int)threadIdx.x;
-      const double c = c64[(int64_t)i * kCoefStride], lnA = c64[(int64_t)i * kCoefStride + 5];
-      const double dn = F.sn - pn[i];
+      const double c = pc, lnA = plnA;
+      const double dn = F.sn - ppn;
       const double base = fma(c * dn, dn, lnA);
       if (FAR) {
         srf[0][threadIdx.x] = (float)(c * l2e);
-        srf[1][threadIdx.x] = (float)(pa[i] - oa);
-        srf[2][threadIdx.x] = (float)(pb[i] - ob);
+        srf[1][threadIdx.x] = (float)(ppa - oa);
+        srf[2][threadIdx.x] = (float)(ppb - ob);
         srf[3][threadIdx.x] = (float)(2.0 * c * dn);
         srf[4][threadIdx.x] = (float)(base * l2e);
         srf[5][threadIdx.x] = (float)(2.0 * c);
       } else {
         src[0][threadIdx.x] = c;
-        src[1][threadIdx.x] = pa[i];
-        src[2][threadIdx.x] = pb[i];
+        src[1][threadIdx.x] = ppa;
+        src[2][threadIdx.x] = ppb;
         src[3][threadIdx.x] = 2.0 * c * dn;
         src[4][threadIdx.x] = base;
       }
     }
+    if (blk + kStage < hi) fetch(blk + kStage);
     __syncthreads();
     if (FAR) {
       // groups of 16 steps (64 sources), then into FP64; the steps past the
