@@ -83,7 +83,8 @@ struct TensorArgs {
   const double *c64;             // coefficient records (c, ..., ln A at [5])
   double *part;
   int64_t stride;
-  int max_groups;                // workgroups of a launch (0: one per work item)
+  int max_groups;                // workgroups of a launch of one to three paths (0: one per work item)
+  int max_groups_batch;          // ... of four paths or more, where the sum dominates the step
 };
 constexpr int kTensorTile = 32;
 // the kernel sum at the points of the tensor faces as matrix products over

@@ -351,7 +351,8 @@ void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, co
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
   if (nch <= 0) return;
   const int64_t items = (int64_t)a.n_tiles * nch * tab.count;
-  const unsigned grid = (unsigned)(a.max_groups > 0 && items > a.max_groups ? a.max_groups : items);
+  const int cap = tab.count >= 4 ? a.max_groups_batch : a.max_groups;
+  const unsigned grid = (unsigned)(cap > 0 && items > cap ? cap : items);
   hipLaunchKernelGGL(k_sum_tensor, dim3(grid), dim3(256), 0, st, a, tab, pl.n_chunks_far, nch, pl.chunk_far,
                      pl.chunk_near);
 }

@@ -1305,13 +1305,16 @@ void build_tensor_faces(sa_iga *h) {
   h->tens.sy = h->sy;
   h->tens.sz = h->sz;
   {
-    // workgroups per compute unit of the sum: room is left for the solver
-    // kernels that run beside it
+    // workgroups per compute unit of the sum: with one path, room is left
+    // for the solver kernels that run beside it (two per unit); a batch is
+    // dominated by its sum, which then takes the whole device (eight per
+    // unit, more than fit at once)
     hipDeviceProp_t prop;
     hip_check(hipGetDeviceProperties(&prop, h->device), "device properties");
     const char *g = std::getenv("SA_IGA_SUM_GROUPS_PER_CU");
-    const int per_cu = g ? std::max(0, std::atoi(g)) : 2;
-    h->tens.max_groups = per_cu * prop.multiProcessorCount;
+    const char *gb = std::getenv("SA_IGA_SUM_GROUPS_PER_CU_BATCH");
+    h->tens.max_groups = (g ? std::max(0, std::atoi(g)) : 2) * prop.multiProcessorCount;
+    h->tens.max_groups_batch = (gb ? std::max(0, std::atoi(gb)) : 8) * prop.multiProcessorCount;
   }
   h->n_gen = (int64_t)gen.size();
   h->n_tfaces = (int)faces.size();
