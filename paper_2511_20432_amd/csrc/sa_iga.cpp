@@ -1575,7 +1575,8 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
         den = std::max(den, std::fabs(y[j]));
       }
       const int dm[3] = {m.fd_dir.m[0], m.fd_dir.m[1], 1};
-      h->dir_exact = den > 0 && num / den < 1e-10 && sa::fused_fits(dm);
+      h->dir_exact = den > 0 && num / den < 1e-10 && sa::fused_fits(dm) &&
+                     sa::fd_plane_lds(dm) + 1024 <= h->lds_per_block;
       if (h->dir_exact) {
         sa::FusedPcg &f = h->fd_dirp;
         f = sa::FusedPcg{};
@@ -1656,7 +1657,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   // fused PCG on the box of free DOFs
   h->hw0 = m.M.hw[0];
   const auto &FM = m.fd_main;
-  const size_t plane_lds = (size_t)2 * FM.m[1] * FM.m[2] * sizeof(double);
+  const size_t plane_lds = sa::fd_plane_lds(FM.m);
   h->pcg_fused = m.opt.preconditioner == SA_PRECOND_FD && sa::fused_fits(FM.m) &&
                  plane_lds + 1024 <= h->lds_per_block && m.M.hw[2] <= 7 && m.M.hw[0] <= 6;
   h->np_st = sa::stencil_blocks(nd);

@@ -138,6 +138,8 @@ struct FusedPcg {
   int64_t sos;
 };
 bool fused_fits(const int m[3]);
+// LDS bytes of the plane pass of the FD solve (two planes, the y and z eigenvectors)
+size_t fd_plane_lds(const int m[3]);
 void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update);
 // convergence test and p = z + beta p; `last` (the final iteration of a fixed
 // budget) records the status without updating p

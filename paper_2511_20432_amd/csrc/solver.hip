@@ -640,35 +640,38 @@ __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
   const int m0 = f.m[0], m1 = f.m[1], m2 = f.m[2];
   const int P = m1 * m2;
   const int j0 = blockIdx.x;
-  double *A = lds, *Bv = lds + P;
+  // the plane twice and the y and z eigenvector matrices, all in LDS
+  double *A = lds, *Bv = lds + P, *U1 = lds + 2 * P, *U2 = U1 + m1 * m1;
   double *t = f.t + (int64_t)j0 * P;
   for (int i = threadIdx.x; i < P; i += blockDim.x) A[i] = t[i];
+  for (int i = threadIdx.x; i < m1 * m1; i += blockDim.x) U1[i] = f.U1[i];
+  for (int i = threadIdx.x; i < m2 * m2; i += blockDim.x) U2[i] = f.U2[i];
   __syncthreads();
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 1: U1^T along y
     const int j1 = i % m1, k2 = i / m1;
     double s = 0.0;
-    for (int kk = 0; kk < m1; ++kk) s = fma(f.U1[kk * m1 + j1], A[k2 * m1 + kk], s);
+    for (int kk = 0; kk < m1; ++kk) s = fma(U1[kk * m1 + j1], A[k2 * m1 + kk], s);
     Bv[i] = s;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 2: U2^T along z, scale
     const int j1 = i % m1, j2 = i / m1;
     double s = 0.0;
-    for (int kk = 0; kk < m2; ++kk) s = fma(f.U2[kk * m2 + j2], Bv[kk * m1 + j1], s);
+    for (int kk = 0; kk < m2; ++kk) s = fma(U2[kk * m2 + j2], Bv[kk * m1 + j1], s);
     A[i] = s * f.inv[j0 + (int64_t)m0 * (j1 + (int64_t)m1 * j2)];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 2 back
     const int j1 = i % m1, k2 = i / m1;
     double s = 0.0;
-    for (int j = 0; j < m2; ++j) s = fma(f.U2[k2 * m2 + j], A[j * m1 + j1], s);
+    for (int j = 0; j < m2; ++j) s = fma(U2[k2 * m2 + j], A[j * m1 + j1], s);
     Bv[i] = s;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 1 back
     const int k1 = i % m1, k2 = i / m1;
     double s = 0.0;
-    for (int j = 0; j < m1; ++j) s = fma(f.U1[k1 * m1 + j], Bv[k2 * m1 + j], s);
+    for (int j = 0; j < m1; ++j) s = fma(U1[k1 * m1 + j], Bv[k2 * m1 + j], s);
     t[i] = s;
   }
 }
@@ -739,12 +742,15 @@ __global__ void k_pcg_dir(SlotMap sm, FusedPcg f0, int k, int last) {
 
 bool fused_fits(const int m[3]) { return m[0] <= 256 && (int64_t)m[1] * m[2] <= 4096; }
 
+size_t fd_plane_lds(const int m[3]) {
+  return ((size_t)2 * m[1] * m[2] + (size_t)m[1] * m[1] + (size_t)m[2] * m[2]) * sizeof(double);
+}
+
 void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update) {
   if (sm.count <= 0) return;
   const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
   hipLaunchKernelGGL(k_fd_xfwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, k, update ? 0 : 1);
-  const size_t lds = (size_t)2 * f.m[1] * f.m[2] * sizeof(double);
-  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(kB), lds, st, sm, f);
+  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(kB), fd_plane_lds(f.m), st, sm, f);
   const int slot = first ? 0 : ((k + 1) & 1);
   hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, slot, first ? 1 : 0);
 }
