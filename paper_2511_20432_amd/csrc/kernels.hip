@@ -213,6 +213,7 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
   const double sb = F.sb[vb ? bi : 0], sa = F.sa[va ? ai : 0];
   const double ob = F.sb[tl.y], oa = F.sa[tl.z];
   const float sbr = (float)(sb - ob), sar = (float)(sa - oa);
+  const bool full_tile = b0 + 16 <= F.nb && a0 + 16 <= F.na;
   // acc[g]: g = 0 T, 1 along a, 2 along b, 3 along n
   dx4 acc[4];
   fx4 accf[4];
@@ -264,6 +265,25 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
       // groups of 16 steps (64 sources), then into FP64; the steps past the
       // staged sources contribute zeros
       for (int g16 = 0; g16 < n_in; g16 += 64) {
+        if (g16 + 64 <= n_in && full_tile) {
+          // every source and every point of the block valid: no masks
+#pragma unroll
+          for (int s16 = 0; s16 < 16; ++s16) {
+            const int t = g16 + 4 * s16 + k;
+            const float cl = srf[0][t], xa = srf[1][t], xb = srf[2][t], tn = srf[3][t], base = srf[4][t],
+                        c2 = srf[5][t];
+            const float db = sbr - xb, da = sar - xa;
+            const float L0 = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
+            const float Lb = L0 * (c2 * db);
+            const float Ln = L0 * tn;
+            const float R0 = __builtin_amdgcn_exp2f(cl * (da * da));
+            const float Ra = R0 * (c2 * da);
+            accf[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, R0, accf[0], 0, 0, 0);
+            accf[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, Ra, accf[1], 0, 0, 0);
+            accf[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(Lb, R0, accf[2], 0, 0, 0);
+            accf[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ln, R0, accf[3], 0, 0, 0);
+          }
+        } else {
 #pragma unroll
         for (int s16 = 0; s16 < 16; ++s16) {
           int t = g16 + 4 * s16 + k;
@@ -283,6 +303,7 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
           accf[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, Ra, accf[1], 0, 0, 0);
           accf[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(Lb, R0, accf[2], 0, 0, 0);
           accf[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ln, R0, accf[3], 0, 0, 0);
+        }
         }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
