@@ -1313,7 +1313,7 @@ void build_tensor_faces(sa_iga *h) {
     hip_check(hipGetDeviceProperties(&prop, h->device), "device properties");
     const char *g = std::getenv("SA_IGA_SUM_GROUPS_PER_CU");
     const char *gb = std::getenv("SA_IGA_SUM_GROUPS_PER_CU_BATCH");
-    h->tens.max_groups = (g ? std::max(0, std::atoi(g)) : 2) * prop.multiProcessorCount;
+    h->tens.max_groups = (int)((g ? std::max(0.0, std::atof(g)) : 2.0) * prop.multiProcessorCount);
     h->tens.max_groups_batch = (gb ? std::max(0, std::atoi(gb)) : 8) * prop.multiProcessorCount;
   }
   h->n_gen = (int64_t)gen.size();
