@@ -191,3 +191,29 @@ def test_fused_network_matches_layerwise(monkeypatch):
     e_T, e_G = rel(Ta, Tb), rel(Ga, Gb)
     print(f"fused vs layer-wise: T rel {e_T:.2e}, grad rel {e_G:.2e}", flush=True)
     assert e_T <= 1e-2 and e_G <= 1e-2
+
+
+def test_surrogate_overlapped_equals_serial(monkeypatch):
+    """The surrogate form (network far field, audits with host decisions)
+    through the overlapped step pipeline gives bitwise the serial order's
+    results, with audits that fail on some steps and pass on others."""
+    tracks = [surrogate_track(), W.sources_from_segments(
+        [W.Segment("line", 60.0, 0.8, p0=np.array([0.2e-3, 0.1e-3, 0.5e-3]),
+                   p1=np.array([0.8e-3, 0.5e-3, 0.5e-3]))], 2e-6)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=[26, 19])
+    tau = 5e-5
+    _, p = _net(11)
+    monkeypatch.setenv("SA_IGA_SERIAL", "1")
+    ser = _surrogate_model(scan, p, tau, audit_every=4, audit_tol=40.0)
+    monkeypatch.delenv("SA_IGA_SERIAL")
+    ovl = _surrogate_model(scan, p, tau, audit_every=4, audit_tol=40.0)
+    for k in (3, 9, 14):
+        ser.step(k)
+        ovl.step(k)
+    a, b = ser.stats(), ovl.stats()
+    print("surrogate stats", {k: (a[k], b[k]) for k in ("net_steps", "audits", "audit_failures")}, flush=True)
+    for k in ("net_steps", "audits", "audit_failures", "pairs", "pairs_net"):
+        assert a[k] == b[k]
+    for path in range(2):
+        for x, y in zip(ser.boundary_fields(path), ovl.boundary_fields(path)):
+            assert np.array_equal(x, y)
