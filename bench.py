@@ -39,14 +39,14 @@ METRIC = "source×point pairs/s + θ-steps/s; mixed+surrogate vs FP64 GPU at ≤
 MFMA_FP32 = 157.3e12
 MFMA_FP64 = 78.6e12
 FLOPS_PER_PAIR = 8
-# HBM bytes per step of the sum kernels (one launch each of k_sum_tensor<true>
-# and <false>) of this workload's FP32 far-field form, from rocprofv3
+# HBM bytes per step of the sum kernel (one k_sum_tensor launch: far and near
+# items) of this workload's FP32 far-field form, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE over steps 1480..1779, scaled by the same counters
 # on a 256 MiB copy (profiles/k_sum_tensor_raster_fp32far.md).  Valid for the
 # kernels as profiled; a changed sum kernel must set this to None until the
 # counters are taken again.  The written bytes are the FP64 chunk partials
 # (5 x 8 B per point and chunk) that k_finalize reads.
-K_SUM_TRAFFIC = {"read_bytes": 3.62e6, "written_bytes": 36.43e6}
+K_SUM_TRAFFIC = {"read_bytes": 3.56e6, "written_bytes": 36.09e6}
 
 
 def _k_sum_traffic(form):
@@ -349,7 +349,7 @@ def main():
         "steps_per_s": steps / r["seconds"],
         "roofline": dict(roof, traffic=_k_sum_traffic(main_form),
                          traffic_unit="HBM bytes per step of the sum kernels (read + written)",
-                         kernel="k_sum_tensor (far chunks FP32, near chunks FP64)",
+                         kernel="k_sum_tensor (far chunks FP32, near chunks FP64, one launch)",
                          avg_ms_per_step=sum_ms / steps, launches_per_step=launches / steps,
                          pairs_per_step=st["pairs"] / steps),
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
