@@ -177,12 +177,12 @@ constexpr int kStage = 256;   // sources staged in LDS at a time
 // one work item (tile, chunk of this kind, slot).  Staged per source in
 // LDS.  FP64 steps: c, x_a, x_b, 2 c dn, ln A + c dn^2.  FP32 steps (base 2,
 // coordinates relative to the tile's first point, where they are small for
-// the sources near the tile, the ones that matter): c log2 e, x_a - o_a,
-// x_b - o_b, 2 c dn, (ln A + c dn^2) log2 e, 2 c.
+// the sources near the tile, the ones that matter), one 32-byte record per
+// source: c log2 e, x_a - o_a, x_b - o_b, 2 c dn, (ln A + c dn^2) log2 e, 2 c.
 template <bool FAR>
 __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
                                             int n_chunks, int chunk_far, int chunk_near, double (*src)[kStage],
-                                            float (*srf)[kStage]) {
+                                            float4 (*srf)[2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, k = lane >> 4;
   const int n_kind = FAR ? n_chunks_far : n_chunks - n_chunks_far;
@@ -245,12 +245,9 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
       const double dn = F.sn - ppn;
       const double base = fma(c * dn, dn, lnA);
       if (FAR) {
-        srf[0][threadIdx.x] = (float)(c * l2e);
-        srf[1][threadIdx.x] = (float)(ppa - oa);
-        srf[2][threadIdx.x] = (float)(ppb - ob);
-        srf[3][threadIdx.x] = (float)(2.0 * c * dn);
-        srf[4][threadIdx.x] = (float)(base * l2e);
-        srf[5][threadIdx.x] = (float)(2.0 * c);
+        srf[threadIdx.x][0] = make_float4((float)(c * l2e), (float)(ppa - oa), (float)(ppb - ob),
+                                          (float)(2.0 * c * dn));
+        srf[threadIdx.x][1] = make_float4((float)(base * l2e), (float)(2.0 * c), 0.f, 0.f);
       } else {
         src[0][threadIdx.x] = c;
         src[1][threadIdx.x] = ppa;
@@ -270,8 +267,8 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
 #pragma unroll
           for (int s16 = 0; s16 < 16; ++s16) {
             const int t = g16 + 4 * s16 + k;
-            const float cl = srf[0][t], xa = srf[1][t], xb = srf[2][t], tn = srf[3][t], base = srf[4][t],
-                        c2 = srf[5][t];
+            const float4 u0 = srf[t][0], u1 = srf[t][1];
+            const float cl = u0.x, xa = u0.y, xb = u0.z, tn = u0.w, base = u1.x, c2 = u1.y;
             const float db = sbr - xb, da = sar - xa;
             const float L0 = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
             const float Lb = L0 * (c2 * db);
@@ -283,14 +280,21 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
             accf[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(Lb, R0, accf[2], 0, 0, 0);
             accf[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ln, R0, accf[3], 0, 0, 0);
           }
+          // scheduling: each matrix-core step interleaved with three VALU
+          // operations of the steps that follow
+#pragma unroll
+          for (int q = 0; q < 64; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+          }
         } else {
 #pragma unroll
         for (int s16 = 0; s16 < 16; ++s16) {
           int t = g16 + 4 * s16 + k;
           const bool vi = t < n_in;
           t = vi ? t : n_in - 1;
-          const float cl = srf[0][t], xa = srf[1][t], xb = srf[2][t], tn = srf[3][t], base = srf[4][t],
-                      c2 = srf[5][t];
+          const float4 u0 = srf[t][0], u1 = srf[t][1];
+          const float cl = u0.x, xa = u0.y, xb = u0.z, tn = u0.w, base = u1.x, c2 = u1.y;
           const float db = sbr - xb, da = sar - xa;
           const float e = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
           const float L0 = (vi && vb) ? e : 0.f;
@@ -356,7 +360,7 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
 __global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
                                                     int chunk_far, int chunk_near) {
   __shared__ double src[5][kStage];
-  __shared__ float srf[6][kStage];
+  __shared__ float4 srf[kStage][2];
   const int n_far_items = ta.n_tiles * n_chunks_far * tab.count;
   const int n_items = ta.n_tiles * n_chunks * tab.count;
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
