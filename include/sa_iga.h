@@ -256,9 +256,12 @@ int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n,
  * Dirichlet values, boundary fields, statistics, audit flags) is restored
  * afterwards.  The split of the source history into chunks does not depend on
  * the tile shape, so later results are bitwise those of any other shape.
- * Outputs (each may be NULL): the chosen shape and its time per step of all
- * paths in ms (0 when no path has sources and more than one step: nothing to
- * time).  SA_ESTATE in the sticky error state.
+ * When every boundary point lies on a tensor face (sa_info.generic_points
+ * == 0) the pair-by-pair kernel does not run and only the default shape
+ * (2 points per lane, 4 waves) is timed.  Outputs (each may be NULL): the
+ * chosen shape and its time per step of all paths in ms (0 when no path has
+ * sources and more than one step: nothing to time).  SA_ESTATE in the sticky
+ * error state.
  */
 int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *waves_per_group,
                     double *ms_per_step);

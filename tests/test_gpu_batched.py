@@ -143,15 +143,23 @@ def test_paths_at_different_steps_share_launches():
         _check_path(b, long, p, n)
 
 
-def test_tile_shapes_bitwise_equal_and_autotune():
-    """The kernel-sum tile shape changes no bit of any result; the tuner
-    picks a valid shape and leaves the state alone."""
+def test_tile_shapes_bitwise_equal_and_autotune(monkeypatch):
+    """The pair-by-pair kernel's tile shape changes no bit of any result; the
+    tuner picks a valid shape and leaves the state alone.  The block's faces
+    are tensor faces, so the pair-by-pair kernel is forced on them here
+    (SA_IGA_NO_TENSOR); with the matrix-core sum the tuner times one shape."""
     tracks = [_track(i) for i in range(3)]
     scan = W.make_scan(tracks, 1e-5, 5, n_steps=[12, 9, 12])
+    tens = _model(W.small_block(), scan)
+    assert tens.info.generic_points == 0
+    t = tens.autotune(reps=2)
+    assert (t["points_per_lane"], t["waves_per_group"]) == (2, 4) and t["ms_per_step"] > 0
+    monkeypatch.setenv("SA_IGA_NO_TENSOR", "1")
     for prec in (W.PRECISION_FP64, W.PRECISION_FP32_FAR):
         opts = W.Options(precision=prec, tau_near=5e-5)
         a = _model(W.small_block(), scan, options=opts, points_per_lane=1, waves_per_group=1)
         b = _model(W.small_block(), scan, options=opts, points_per_lane=4, waves_per_group=8)
+        assert b.info.generic_points == b.info.n_bpts
         a.step(6)
         b.step(6)
         before = [b.boundary_fields(p) for p in range(3)]
