@@ -173,6 +173,7 @@ def _window_report(w, form, window, dt, st, tune, setup_s, seed):
         "ms_per_batched_step": 1e3 * dt / window, "path_steps": st["steps"],
         "sum_gpair_s": st["pairs"] / (sum_ms * 1e-3) / 1e9 if sum_ms > 0 else None,
         "stage_ms_per_batched_step": {k: v / window for k, v in st["stage_ms"].items()},
+        "rollbacks": st["rollbacks"],
         "autotune": tune, "setup_s": setup_s,
     }
 
@@ -354,6 +355,7 @@ def main():
                          pairs_per_step=st["pairs"] / steps),
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
         "ms_per_step_with_stage_events": 1e3 * st["seconds_with_events"] / steps,
+        "rollbacks": st["rollbacks"],
         "setup_s": r["setup_s"],
         "autotune": st["autotune"],
     }
@@ -366,6 +368,7 @@ def main():
                        if s64["stage_ms"]["sum"] > 0 else None,
                        "sum_roofline": _sum_roofline(s64, s64["stage_ms"]["sum"]),
                        "stage_ms_per_step": {k: v / steps for k, v in s64["stage_ms"].items()},
+                       "rollbacks": s64["rollbacks"],
                        "autotune": s64["autotune"]}
         out["speedup_vs_fp64"] = t64 / r["seconds"]
         out["max_err_K_vs_fp64"] = max_err

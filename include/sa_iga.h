@@ -202,8 +202,15 @@ int sa_iga_setup(const sa_patch *patch, const sa_material *mat, const sa_scan_pa
  * vector and Dirichlet data) runs on two internal streams, one step ahead of
  * the theta-step solves on the object's stream; the results are bitwise those
  * of the serial order (environment variable SA_IGA_SERIAL at set-up selects
- * that order).  SA_ENOCONV if a solve did not converge (the object then
- * enters the sticky error state SA_ESTATE).
+ * that order).  Where the fast-diagonalisation solve is exact (an affine
+ * axis-aligned block with the FD preconditioner) a theta-step is one
+ * application of it, u^{n+1} = x0 + P r0; its residual against the tolerance
+ * is formed by the next step's right-hand side passes or, for a path's last
+ * step of the call, by a check pass before the call returns.  If a step
+ * missed the tolerance, the state goes back to the call's start and the
+ * steps run again with two PCG iterations each (sa_stats.rollbacks), which
+ * stays the object's form from then on.  SA_ENOCONV if a solve did not
+ * converge (the object then enters the sticky error state SA_ESTATE).
  */
 int sa_iga_step(sa_iga *h, int32_t n_steps);
 

@@ -175,6 +175,14 @@ struct sa_iga {
   double bw2 = 0.0;                      // (64 eps |A|_inf)^2, attainable-accuracy test
   bool kron = false;                     // matrix-free Kronecker A and B (affine patch)
   sa::KronArgs kargs{};
+  // Checked update (exact FD solve on a Kronecker operator, one iteration):
+  // the theta-step is u^{n+1} = x0 + P r0, and its residual b - A u^{n+1} is
+  // formed by the next step's right-hand side passes (which read u^{n+1}
+  // anyway), or by a check pass at the end of the call.  bprev holds each
+  // path's last right-hand side, chk_pending marks the paths whose last step
+  // is still to be checked (never set between calls).
+  double *bprev = nullptr, *part_chk = nullptr;
+  std::vector<uint8_t> chk_pending;
   int hw0 = 1;
   sa::SolveStatus *d_status = nullptr;   // ring of per-solve records
   std::vector<int8_t> status_kind;       // 0 projection, 1 theta-step
@@ -545,6 +553,7 @@ void check_statuses(sa_iga *h) {
   int bad = -1;
   for (size_t i = 0; i < used; ++i) {
     if (st[i].done != 1 && bad < 0) bad = (int)i;
+    if (st[i].iter < 0) continue;          // a checked update with no previous step to check
     if (kind[i] == 0) {
       h->stats.dirichlet_iterations += st[i].iter;
     } else {
@@ -818,6 +827,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     hip_check(hipEventRecord(h->ev_rhs[ev_slot], bsx), "event record");
     for (int s = 0; s < count; ++s) h->path_rhs[pids[s]] = ev_slot;
   };
+  const bool checked = h->pcg_fused && h->kron && h->fd_exact && h->pcg_budget == 1;
   if (h->pcg_fused) {
     {
       StageScope s(h, SA_STAGE_RHS, bsx);
@@ -852,6 +862,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
         k.sc_w = h->sc;
         k.init_x = 1;
         k.x_init = Vn;
+        k.check = checked ? 1 : 0;
         sa::launch_kron(bsx, sm, k, true);
       } else {
         sa::launch_stencil_sl(bsx, sm, a, h->hw0, true);
@@ -886,44 +897,59 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       if (h->kron) sa::launch_kron(bsx, sm, kp, false);
       else sa::launch_stencil_sl(bsx, sm, ap, h->hw0, false);
     };
-    sa::launch_fd_pass(bsx, sm, f, 0, true, false);
-    if (h->fd_exact && h->pcg_budget == 1 && h->force_rollback) {
-      f.rtol2 = 0.0;   // no residual passes: the one-iteration pass fails
-      f.bw2 = 0.0;
-    }
-    if (h->fd_exact) {
-      // with the exact preconditioner the first iteration nearly always
-      // converges: test |r| right after the update, and run the FD solve and
-      // the new direction only for paths still going (the others exit at once)
-      for (int k = 0; k < h->pcg_budget; ++k) {
-        apply();
-        sa::launch_pcg_last_update(bsx, sm, f, k);
-        sa::launch_pcg_dir(bsx, sm, f, k, true);
-        if (k + 1 < h->pcg_budget) {
-          sa::launch_fd_pass(bsx, sm, f, k, false, false);
-          sa::launch_pcg_dir(bsx, sm, f, k, false);
-        }
-      }
+    if (checked) {
+      // x += P r; the first pass also writes the record of the previous
+      // step's residual check of each path that has one pending
+      f.update_x = 1;
+      f.check_mask = 0;
+      for (int s = 0; s < count; ++s)
+        if (h->chk_pending[pids[s]]) f.check_mask |= 1ull << s;
+      f.part_chk = h->part_chk;
+      f.np_chk = h->np_st;
+      f.chk_rtol2 = h->force_rollback ? 0.0 : f.rtol2;   // forced: every check fails
+      f.chk_bw2 = h->force_rollback ? 0.0 : f.bw2;
+      sa::launch_fd_pass(bsx, sm, f, 0, true, false);
+      for (int s = 0; s < count; ++s) h->chk_pending[pids[s]] = 1;
     } else {
-      int k = 0, chunk = 4;
-      for (;;) {
-        for (int c = 0; c < chunk; ++c, ++k) {
+      sa::launch_fd_pass(bsx, sm, f, 0, true, false);
+      if (h->fd_exact && h->pcg_budget == 1 && h->force_rollback) {
+        f.rtol2 = 0.0;   // no residual passes: the one-iteration pass fails
+        f.bw2 = 0.0;
+      }
+      if (h->fd_exact) {
+        // with the exact preconditioner the first iteration nearly always
+        // converges: test |r| right after the update, and run the FD solve and
+        // the new direction only for paths still going (the others exit at once)
+        for (int k = 0; k < h->pcg_budget; ++k) {
           apply();
-          sa::launch_fd_pass(bsx, sm, f, k, false, true);
-          sa::launch_pcg_dir(bsx, sm, f, k, false);
+          sa::launch_pcg_last_update(bsx, sm, f, k);
+          sa::launch_pcg_dir(bsx, sm, f, k, true);
+          if (k + 1 < h->pcg_budget) {
+            sa::launch_fd_pass(bsx, sm, f, k, false, false);
+            sa::launch_pcg_dir(bsx, sm, f, k, false);
+          }
         }
-        hip_check(hipMemcpyAsync(h->h_sc, h->sc, h->S * sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, bsx),
-                  "status copy");
-        hip_check(hipStreamSynchronize(bsx), "sync");
-        bool all = true;
-        for (int s = 0; s < count; ++s) {
-          const sa::PcgScalars &st = h->h_sc[pids[s]];
-          if (st.done == 2) throw sa::SaError{SA_ENOCONV, "PCG breakdown (operator not positive definite)"};
-          if (st.done != 1) all = false;
+      } else {
+        int k = 0, chunk = 4;
+        for (;;) {
+          for (int c = 0; c < chunk; ++c, ++k) {
+            apply();
+            sa::launch_fd_pass(bsx, sm, f, k, false, true);
+            sa::launch_pcg_dir(bsx, sm, f, k, false);
+          }
+          hip_check(hipMemcpyAsync(h->h_sc, h->sc, h->S * sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, bsx),
+                    "status copy");
+          hip_check(hipStreamSynchronize(bsx), "sync");
+          bool all = true;
+          for (int s = 0; s < count; ++s) {
+            const sa::PcgScalars &st = h->h_sc[pids[s]];
+            if (st.done == 2) throw sa::SaError{SA_ENOCONV, "PCG breakdown (operator not positive definite)"};
+            if (st.done != 1) all = false;
+          }
+          if (all) break;
+          if (k >= h->m.opt.pcg_max_iter) throw sa::SaError{SA_ENOCONV, "PCG did not converge within pcg_max_iter"};
+          chunk = std::min(chunk * 2, 32);
         }
-        if (all) break;
-        if (k >= h->m.opt.pcg_max_iter) throw sa::SaError{SA_ENOCONV, "PCG did not converge within pcg_max_iter"};
-        chunk = std::min(chunk * 2, 32);
       }
     }
   } else {
@@ -959,6 +985,35 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
   hip_check(hipGetLastError(), "kernel launch");
   for (int s = 0; s < count; ++s) h->paths[pids[s]].step++;
   h->stats.steps += count;
+}
+
+// the residual checks of checked updates still pending at the end of a call:
+// A u^n from u^n alone (in V[n & 1]), against the stored right-hand side,
+// per parity of the paths' steps
+void flush_checks(sa_iga *h) {
+  std::vector<int> ids[2];
+  for (int p = 0; p < (int)h->chk_pending.size(); ++p)
+    if (h->chk_pending[p]) ids[h->paths[p].step & 1].push_back(p);
+  if (ids[0].empty() && ids[1].empty()) return;
+  const hipStream_t bsx = solve_stream(h);
+  StageScope sc(h, SA_STAGE_PCG, bsx);
+  const double rt = h->force_rollback ? 0.0 : h->fp.rtol2, bw = h->force_rollback ? 0.0 : h->fp.bw2;
+  for (int par = 0; par < 2; ++par)
+    for (size_t i0 = 0; i0 < ids[par].size(); i0 += sa::kMaxBatch) {
+      const size_t i1 = std::min(ids[par].size(), i0 + (size_t)sa::kMaxBatch);
+      sa::SlotMap sm{};
+      sm.count = (int)(i1 - i0);
+      for (size_t i = i0; i < i1; ++i) sm.path[i - i0] = ids[par][i];
+      sa::KronArgs k = h->kargs;
+      k.v = h->V[par];
+      k.check = 1;
+      k.check_only = 1;
+      k.sc = nullptr;
+      k.sc_w = nullptr;
+      sa::launch_kron(bsx, sm, k, true);
+      sa::launch_check_status(bsx, sm, h->part_chk, h->np_st, rt, bw, next_status(h, sm.count, 1));
+    }
+  std::fill(h->chk_pending.begin(), h->chk_pending.end(), 0);
 }
 
 // advance every live path by one step: launches of at most kMaxBatch paths,
@@ -1103,8 +1158,16 @@ void build_kron(sa_iga *h) {
   k.np = h->np_st;
   k.mask = h->free_mask;
   k.theta = th;
-  k.ts = 8 * N;
-  k.t = dev_zeros<double>(h, (size_t)h->S * 8 * N);
+  const bool chk = h->fd_exact;
+  k.ts = (chk ? 10 : 8) * N;
+  k.t = dev_zeros<double>(h, (size_t)h->S * k.ts);
+  if (chk) {
+    h->bprev = dev_zeros<double>(h, (size_t)h->S * N);
+    h->part_chk = dev_zeros<double>(h, (size_t)h->S * 3 * h->np_st);
+    k.bprev = h->bprev;
+    k.part_chk = h->part_chk;
+  }
+  h->chk_pending.assign((size_t)h->S, 0);
   h->kron = true;
 }
 
@@ -1714,6 +1777,8 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   h->overlap = h->pcg_fused && (h->nD == 0 || h->dir_direct || h->dir_exact || h->dir_fused) &&
                !std::getenv("SA_IGA_SERIAL");
   h->force_rollback = std::getenv("SA_IGA_FORCE_ROLLBACK") != nullptr;
+  if (const char *e = std::getenv("SA_IGA_PCG_BUDGET"))   // 2: the two-iteration form from the start (tests)
+    h->pcg_budget = std::atoi(e) >= 2 ? 2 : 1;
   for (int b = 0; b < 2; ++b) {
     hip_check(hipEventCreateWithFlags(&h->ev_sum[b], hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&h->ev_part[b], hipEventDisableTiming), "event");
@@ -1882,6 +1947,7 @@ void run_steps(sa_iga *h, int32_t n_steps) {
     }
     const auto t0 = std::chrono::steady_clock::now();
     for (int32_t s = 0; s < n_steps; ++s) step_all(h);
+    flush_checks(h);
     if (h->verbose && n_steps > 0) {
       const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
       std::fprintf(stderr, "[sa_iga] %d steps enqueued in %.1f us per step\n", n_steps, us / n_steps);
@@ -1933,6 +1999,7 @@ void restore_state(sa_iga *h, const HostState &c) {
   for (size_t p = 0; p < h->paths.size(); ++p) h->paths[p].step = c.steps[p];
   h->stats = c.stats;
   h->use_exact = c.use_exact;
+  std::fill(h->chk_pending.begin(), h->chk_pending.end(), 0);
 }
 
 // run_steps with one PCG iteration per theta-step where that is the budget;
@@ -1962,6 +2029,7 @@ void abandon_steps(sa_iga *h) {
   if (h->ps) (void)hipStreamSynchronize(h->ps);
   (void)hipStreamSynchronize(h->stream);
   h->status_kind.clear();
+  std::fill(h->chk_pending.begin(), h->chk_pending.end(), 0);
   try {
     collect_timing(h);
   } catch (...) {

@@ -111,8 +111,20 @@ struct KronArgs {
   PcgScalars *sc_w;       // theta: resets the done flags
   int init_x;             // theta: form the first iterate x = v on the free DOFs (mask) in the x pass
   double *x_init;         // ... writable alias of x
+  // theta, checked update: also r_prev = bprev - A v on the free rows (the
+  // residual of the step that produced v = u^n, whose right-hand side bprev
+  // holds), with partials of |r_prev|^2, |bprev|^2, |v|^2 in
+  // part_chk[(p * 3 + c) * np + wave]; then bprev <- this step's right-hand side.
+  // check_only: those partials alone (no other output).  t needs 10 nrow.
+  int check, check_only;
+  double *bprev;          // [paths][vs]
+  double *part_chk;       // [paths][3][np]
 };
 void launch_kron(hipStream_t st, const SlotMap &sm, const KronArgs &a, bool theta);
+// status records from the check partials of KronArgs (check_only pass): one
+// block per slot, record at status + slot
+void launch_check_status(hipStream_t st, const SlotMap &sm, const double *part_chk, int np, double rtol2,
+                         double bw2, SolveStatus *status);
 
 // fused PCG with the fast-diagonalisation preconditioner on the free box
 // Per-path data of path p: x, r, z, p, q at + p*vs; t at + p*ts; partials
@@ -136,6 +148,14 @@ struct FusedPcg {
   const int64_t *scatter_idx;   // optional: scatter_out[scatter_idx[g]] = z[g]
   double *scatter_out;
   int64_t sos;
+  // checked update (one FD application, x += P r): k_fd_xbwd adds z to x on
+  // the box instead of writing z and p; k_fd_xfwd's first block of a path
+  // writes the status record of the previous step's check when bit s of
+  // check_mask is set (slot s), else a record that there was none
+  int update_x;
+  uint64_t check_mask;
+  const double *part_chk; int np_chk;   // as in KronArgs, per path
+  double chk_rtol2, chk_bw2;
 };
 bool fused_fits(const int m[3]);
 // LDS bytes of the plane pass of the FD solve (two planes, the y and z eigenvectors)

@@ -419,7 +419,9 @@ __global__ void k_kron_x(SlotMap sm, KronArgs a) {
   if (r >= N) return;
   const int n0 = a.op.n[0], p = a.op.p[0], i0 = (int)(r % n0);
   double *t = a.t + pth * a.ts;
-  if (THETA && a.init_x) {
+  if (THETA && a.check_only) {
+    // residual check alone: products of v only
+  } else if (THETA && a.init_x) {
     // first iterate formed here: no thread reads x at a free DOF, where it is written
     double *x = a.x_init + pth * a.vs;
     const double *v = a.v + pth * a.vs;
@@ -451,6 +453,14 @@ __global__ void k_kron_y(SlotMap sm, KronArgs a) {
   const int i1 = (int)((r / n0) % n1);
   const double *Mb = a.op.Mb[1], *Kb = a.op.Kb[1];
   double *t = a.t + pth * a.ts;
+  if (THETA && a.check_only) {
+    const double bmm = band_dot(Mb, p, i1, n1, t + 2 * N, r, n0);
+    const double bmk = band_dot(Mb, p, i1, n1, t + 3 * N, r, n0);
+    const double bkm = band_dot(Kb, p, i1, n1, t + 2 * N, r, n0);
+    t[8 * N + r] = a.op.cM * bmm + a.op.cA[0] * bmk + a.op.cA[1] * bkm;
+    t[9 * N + r] = a.op.cA[2] * bmm;
+    return;
+  }
   // A: (M y M x) x, (M y K x) x, (K y M x) x  ->  the parts taken by M z and K z
   const double mm = band_dot(Mb, p, i1, n1, t, r, n0);
   const double mk = band_dot(Mb, p, i1, n1, t + N, r, n0);
@@ -463,6 +473,10 @@ __global__ void k_kron_y(SlotMap sm, KronArgs a) {
     const double bkm = band_dot(Kb, p, i1, n1, t + 2 * N, r, n0);
     t[6 * N + r] = a.op.cM * bmm + a.op.cB[0] * bmk + a.op.cB[1] * bkm;
     t[7 * N + r] = a.op.cB[2] * bmm;
+    if (a.check) {   // the same products of v, combined as A
+      t[8 * N + r] = a.op.cM * bmm + a.op.cA[0] * bmk + a.op.cA[1] * bkm;
+      t[9 * N + r] = a.op.cA[2] * bmm;
+    }
   }
 }
 
@@ -475,31 +489,58 @@ __global__ __launch_bounds__(kB) void k_kron_z(SlotMap sm, KronArgs a) {
   const int n0 = a.op.n[0], n1 = a.op.n[1], n2 = a.op.n[2], p = a.op.p[2];
   const int64_t n01 = (int64_t)n0 * n1;
   const double *t = a.t + pth * a.ts;
-  double part = 0.0;
+  const bool chk = THETA && a.check;
+  double part = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
   if (r < N) {
     const int i2 = (int)(r / n01);
     const bool active = !a.mask || a.mask[r];
-    const double ax = band_dot(a.op.Mb[2], p, i2, n2, t + 4 * N, r, n01) +
-                      band_dot(a.op.Kb[2], p, i2, n2, t + 5 * N, r, n01);
-    double *out = a.out + pth * a.vs;
+    const int64_t g = pth * a.vs + r;
     if (THETA) {
-      double rv = 0.0;
-      if (active) {
+      double rhs = 0.0, rv = 0.0;
+      if (active && !a.check_only) {
+        const double ax = band_dot(a.op.Mb[2], p, i2, n2, t + 4 * N, r, n01) +
+                          band_dot(a.op.Kb[2], p, i2, n2, t + 5 * N, r, n01);
         const double bv = band_dot(a.op.Mb[2], p, i2, n2, t + 6 * N, r, n01) +
                           band_dot(a.op.Kb[2], p, i2, n2, t + 7 * N, r, n01);
-        const double rhs = bv + a.theta * a.F1[pth * a.vs + r] + (1.0 - a.theta) * a.F0[pth * a.vs + r];
+        rhs = bv + a.theta * a.F1[g] + (1.0 - a.theta) * a.F0[g];
         part = rhs * rhs;
         rv = rhs - ax;
       }
-      out[r] = rv;
+      if (chk && active) {
+        // residual of the step that produced v, against its right-hand side
+        const double av = band_dot(a.op.Mb[2], p, i2, n2, t + 8 * N, r, n01) +
+                          band_dot(a.op.Kb[2], p, i2, n2, t + 9 * N, r, n01);
+        const double bp = a.bprev[g], vv = a.v[g], d = bp - av;
+        c0 = d * d;
+        c1 = bp * bp;
+        c2 = vv * vv;
+        if (!a.check_only) a.bprev[g] = rhs;
+      }
+      if (!a.check_only) a.out[g] = rv;
     } else {
-      out[r] = active ? ax : 0.0;
-      part = active ? a.x[pth * a.vs + r] * ax : 0.0;
+      const double ax = band_dot(a.op.Mb[2], p, i2, n2, t + 4 * N, r, n01) +
+                        band_dot(a.op.Kb[2], p, i2, n2, t + 5 * N, r, n01);
+      a.out[g] = active ? ax : 0.0;
+      part = active ? a.x[g] * ax : 0.0;
     }
   }
-  part = wsum(part);                       // lane 0: the sum over these 64 rows
   const int64_t wi = r >> 6;
-  if ((threadIdx.x & 63) == 0 && wi < a.np) a.part[pth * a.np + wi] = part;
+  const bool lead = (threadIdx.x & 63) == 0 && wi < a.np;
+  if (!(THETA && a.check_only)) {
+    part = wsum(part);                     // lane 0: the sum over these 64 rows
+    if (lead) a.part[pth * a.np + wi] = part;
+  }
+  if (chk) {
+    c0 = wsum(c0);
+    c1 = wsum(c1);
+    c2 = wsum(c2);
+    if (lead) {
+      double *pc = a.part_chk + pth * 3 * a.np + wi;
+      pc[0] = c0;
+      pc[a.np] = c1;
+      pc[2 * a.np] = c2;
+    }
+  }
   if (THETA && blockIdx.x == 0 && threadIdx.x == 0 && a.sc_w) a.sc_w[pth].done = 0;
 }
 
@@ -558,10 +599,27 @@ __device__ __forceinline__ FusedPcg at_path(const FusedPcg &f, const SlotMap &sm
   if (g.part_xx) g.part_xx += p * f.np_rz;
   if (g.part_pq) g.part_pq += p * f.np_pq;
   if (g.part_b) g.part_b += p * f.np_b;
+  if (g.part_chk) g.part_chk += p * 3 * f.np_chk;
   g.sc += p;
   if (g.status) g.status += slot;
   if (g.scatter_out) g.scatter_out += p * f.sos;
   return g;
+}
+
+// status record of a theta-step whose residual was formed afterwards (by the
+// next right-hand side pass or a check pass): pc holds the partials of
+// |b - A u|^2, |b|^2 and |u|^2 over the free rows, np of each; the test is
+// that of k_pcg_dir
+__device__ void check_record(const double *pc, int np, double rtol2, double bw2, SolveStatus *st, double *sh) {
+  const double rr = reduce_n(pc, np, sh);
+  const double bb = reduce_n(pc + np, np, sh);
+  const double xx = reduce_n(pc + 2 * np, np, sh);
+  if (threadIdx.x == 0) {
+    const bool conv = rr <= rtol2 * bb || rr <= bw2 * xx || bb <= 1e-280;
+    st->iter = 1;
+    st->done = conv ? 1 : 0;
+    st->relres2 = bb > 0 ? rr / bb : 0.0;
+  }
 }
 
 __device__ __forceinline__ int64_t full_index(const FusedPcg &f, int j0, int j1, int j2) {
@@ -623,6 +681,16 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k
     }
     if (first == 2) return;                 // last iteration: no preconditioned residual needed
   } else {
+    if (f.update_x && b == 0 && f.status) {
+      // checked update: the record of this path's previous theta-step
+      if ((f.check_mask >> blockIdx.y) & 1) {
+        check_record(f.part_chk, f.np_chk, f.chk_rtol2, f.chk_bw2, f.status, sh);
+      } else if (threadIdx.x == 0) {
+        f.status->iter = -1;               // nothing to check
+        f.status->done = 1;
+        f.status->relres2 = 0.0;
+      }
+    }
     for (int i = threadIdx.x; i < m0; i += blockDim.x) fib[i] = f.r[base + i];
     __syncthreads();
   }
@@ -688,6 +756,14 @@ __global__ __launch_bounds__(kFib) void k_fd_xbwd(SlotMap sm, FusedPcg f0, int s
   const int64_t base = full_index(f, 0, k1, k2);
   for (int j = threadIdx.x; j < m0; j += blockDim.x) fib[j] = f.t[(int64_t)j * P + (int64_t)k2 * m1 + k1];
   __syncthreads();
+  if (f.update_x) {   // x += P r: one application of the exact inverse
+    for (int k0 = threadIdx.x; k0 < m0; k0 += blockDim.x) {
+      double s = 0.0;
+      for (int j = 0; j < m0; ++j) s = fma(f.U0[k0 * m0 + j], fib[j], s);
+      f.x[base + k0] += s;
+    }
+    return;
+  }
   double rz = 0.0;
   for (int k0 = threadIdx.x; k0 < m0; k0 += blockDim.x) {
     double s = 0.0;
@@ -762,6 +838,20 @@ void launch_pcg_dir(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k,
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)blocks, (unsigned)sm.count), dim3(kB), 0, st, sm, f, k,
                      last ? 1 : 0);
+}
+
+__global__ __launch_bounds__(256) void k_check_status(SlotMap sm, const double *part_chk, int np, double rtol2,
+                                                      double bw2, SolveStatus *status) {
+  __shared__ double sh[16];
+  const int64_t p = sm.path[blockIdx.y];
+  check_record(part_chk + p * 3 * np, np, rtol2, bw2, status + blockIdx.y, sh);
+}
+
+void launch_check_status(hipStream_t st, const SlotMap &sm, const double *part_chk, int np, double rtol2,
+                         double bw2, SolveStatus *status) {
+  if (sm.count <= 0) return;
+  hipLaunchKernelGGL(k_check_status, dim3(1, (unsigned)sm.count), dim3(256), 0, st, sm, part_chk, np, rtol2, bw2,
+                     status);
 }
 
 void launch_pcg_last_update(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k) {

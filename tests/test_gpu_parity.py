@@ -217,11 +217,14 @@ def test_deterministic_and_checkpoint_resume():
         assert np.array_equal(x, y)
 
 
-def test_forced_rollback_equals_normal_run(monkeypatch):
-    """A theta-step runs one PCG iteration (the fast-diagonalisation solve is
-    exact on the block); when a step needs more, the call runs again from its
-    start with two.  Forcing the one-iteration pass to fail gives bitwise the
-    results of the normal run, through one rollback."""
+def test_forced_rollback_equals_two_iteration_run(monkeypatch):
+    """A theta-step is one application of the fast-diagonalisation solve
+    (exact on the block), u^{n+1} = x0 + P r0; its residual is formed by the
+    next step's right-hand side passes, or by a check pass at the end of the
+    call, and if any step of a call misses the tolerance the call runs again
+    from its start with two PCG iterations per step.  Forcing every check to
+    fail gives bitwise the results of a run with two iterations from the
+    start, through one rollback; the checked run agrees with both to rounding."""
     patch = W.small_block()
     tracks = [W.sources_from_segments([W.Segment("line", 50.0 + 20 * i, 1.0, p0=np.array([0.1e-3, 0.2e-3 + 0.1e-3 * i, 0.5e-3]),
                                                  p1=np.array([0.9e-3, 0.25e-3 + 0.1e-3 * i, 0.5e-3]))], 2e-6)
@@ -229,19 +232,45 @@ def test_forced_rollback_equals_normal_run(monkeypatch):
     scan = W.make_scan(tracks, 1e-5, 5, n_steps=[14, 9, 14])
     normal = _gpu_model(patch, W.MAT_CFG, scan)
     normal.step(14)
+    monkeypatch.setenv("SA_IGA_PCG_BUDGET", "2")
+    two = _gpu_model(patch, W.MAT_CFG, scan)
+    monkeypatch.delenv("SA_IGA_PCG_BUDGET")
+    two.step(14)
     monkeypatch.setenv("SA_IGA_FORCE_ROLLBACK", "1")
     forced = _gpu_model(patch, W.MAT_CFG, scan)
     monkeypatch.delenv("SA_IGA_FORCE_ROLLBACK")
     forced.step(6)
     forced.step(8)
-    sn, sf = normal.stats(), forced.stats()
+    sn, s2, sf = normal.stats(), two.stats(), forced.stats()
     print(f"rollbacks normal {sn['rollbacks']} forced {sf['rollbacks']}; PCG iterations {sn['pcg_iterations']} "
-          f"vs {sf['pcg_iterations']} over {sn['steps']} path-steps", flush=True)
-    assert sn["rollbacks"] == 0 and sf["rollbacks"] == 1
-    assert sn["steps"] == sf["steps"]
+          f"vs {sf['pcg_iterations']} over {sn['steps']} path-steps; last |r|/|b| {sn['pcg_last_relres']:.2e}",
+          flush=True)
+    assert sn["rollbacks"] == 0 and s2["rollbacks"] == 0 and sf["rollbacks"] == 1
+    assert sn["pcg_iterations"] == sn["steps"] == sf["steps"] == s2["steps"]
     for p in range(3):
-        for x, y in zip(normal.boundary_fields(p), forced.boundary_fields(p)):
+        for x, y, z in zip(two.boundary_fields(p), forced.boundary_fields(p), normal.boundary_fields(p)):
             assert np.array_equal(x, y)
+            assert rel(z, x) <= 1e-12
+
+
+def test_forced_rollback_from_the_end_of_call_check(monkeypatch):
+    """A one-step call: its only residual check is the end-of-call pass."""
+    patch = W.small_block()
+    src = W.sources_from_segments([W.Segment("line", 60.0, 1.0, p0=np.array([0.1e-3, 0.2e-3, 0.5e-3]),
+                                             p1=np.array([0.9e-3, 0.25e-3, 0.5e-3]))], 2e-6)
+    scan = W.make_scan([src], 1e-5, 5, n_steps=[6])
+    monkeypatch.setenv("SA_IGA_PCG_BUDGET", "2")
+    two = _gpu_model(patch, W.MAT_CFG, scan)
+    monkeypatch.delenv("SA_IGA_PCG_BUDGET")
+    monkeypatch.setenv("SA_IGA_FORCE_ROLLBACK", "1")
+    forced = _gpu_model(patch, W.MAT_CFG, scan)
+    monkeypatch.delenv("SA_IGA_FORCE_ROLLBACK")
+    for k in (1, 1, 4):
+        two.step(k)
+        forced.step(k)
+    assert forced.stats()["rollbacks"] == 1
+    for x, y in zip(two.boundary_fields(), forced.boundary_fields()):
+        assert np.array_equal(x, y)
 
 
 def test_empty_scan_and_zero_steps():
