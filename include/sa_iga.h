@@ -146,6 +146,9 @@ typedef struct {
   int32_t tensor_faces;        /* planar faces whose points form a grid along Cartesian axes: their
                                   kernel sums run as matrix products (the Gaussian of Eq. 8 factorises) */
   int64_t generic_points;      /* boundary points of the other faces (summed pair by pair) */
+  int32_t blocked_steps;       /* steps per source-side block of a one-path call (1: every step alone):
+                                  the sums, load vectors and Dirichlet data of that many steps go
+                                  through one launch each */
 } sa_info;
 
 enum sa_stage {

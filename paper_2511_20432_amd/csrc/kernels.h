@@ -81,6 +81,11 @@ struct TensorArgs {
   int n_tiles;
   const double *sx, *sy, *sz;    // centred source positions (all paths)
   const double *c64;             // coefficient records (c, ..., ln A at [5])
+  // or, where age_c is set, the coefficients from the source's age a = now -
+  // tick (an integer number of source intervals): c = age_c[a],
+  // ln A = src_le[i] + age_l[a] (no coefficient records needed)
+  const int64_t *tick;
+  const double *age_c, *age_l, *src_le;
   double *part;
   int64_t stride;
   int max_groups;                // workgroups of a launch of one to three paths (0: one per work item)

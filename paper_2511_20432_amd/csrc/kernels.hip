@@ -203,7 +203,7 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
     lo = tab.n_far[slot] + ck * chunk_near;
     hi = lo + chunk_near < tab.n_act[slot] ? lo + chunk_near : tab.n_act[slot];
   }
-  const int64_t s0 = tab.src0[slot];
+  const int64_t s0 = tab.src0[slot], now = tab.now[slot];
   const double *c64 = ta.c64 + s0 * kCoefStride;
   const double *pa = (F.ax_a == 0 ? ta.sx : (F.ax_a == 1 ? ta.sy : ta.sz)) + s0;
   const double *pb = (F.ax_b == 0 ? ta.sx : (F.ax_b == 1 ? ta.sy : ta.sz)) + s0;
@@ -229,8 +229,14 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
   auto fetch = [&](int blk) {
     const int i = blk + (int)threadIdx.x;
     if (i < hi) {
-      pc = c64[(int64_t)i * kCoefStride];
-      plnA = c64[(int64_t)i * kCoefStride + 5];
+      if (ta.age_c) {
+        const int64_t a = now - ta.tick[s0 + i];
+        pc = ta.age_c[a];
+        plnA = ta.src_le[s0 + i] + ta.age_l[a];
+      } else {
+        pc = c64[(int64_t)i * kCoefStride];
+        plnA = c64[(int64_t)i * kCoefStride + 5];
+      }
       ppa = pa[i];
       ppb = pb[i];
       ppn = pn[i];

@@ -73,6 +73,9 @@ struct StageEvents {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, pool;
 };
 
+// slots (steps x paths) of one block of the blocked source side
+constexpr int kBlockSlots = 8;
+
 }  // namespace
 
 struct sa_iga {
@@ -88,6 +91,7 @@ struct sa_iga {
   // stream `ps`, beside the sum of step n+2 (two partial buffers).
   hipStream_t ss = nullptr, ps = nullptr;   // sum; reduction, loads and Dirichlet data
   bool verbose = false;                    // SA_IGA_VERBOSE: set-up and host enqueue times on stderr
+  double host_us[5] = {0, 0, 0, 0, 0};     // verbose: host time of the enqueue sections of the steps
   bool overlap = false, in_step = false;
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   std::vector<hipEvent_t> ev_src, ev_rhs;   // rings: one event per batch
@@ -151,6 +155,7 @@ struct sa_iga {
   std::vector<PathState> paths;
   double delta = 0, shift = 0, alpha = 0, rc = 0;
   int64_t tau_ticks = 0;
+  int64_t age_max = -1;                    // the tensor sum's age tables cover ages 0..age_max
   int64_t ns = 1;                        // sources per theta-step
   sa_stats stats{};
   int sticky = 0;
@@ -183,6 +188,20 @@ struct sa_iga {
   // is still to be checked (never set between calls).
   double *bprev = nullptr, *part_chk = nullptr;
   std::vector<uint8_t> chk_pending;
+  // Blocked source side (one path, or a few at one step parity): the sums,
+  // reductions, load vectors and Dirichlet data of K steps go through one
+  // launch each, as K x paths slots, into staging buffers (two sets, one per
+  // block in flight); the theta-steps of the block then read them by slot.
+  // At the block's end the last step's F, Dirichlet values, T~ and grad T~
+  // are copied into the paths' state.
+  bool blk_ok = false;
+  double *bF[2] = {nullptr, nullptr}, *bT[2] = {nullptr, nullptr}, *bG[2] = {nullptr, nullptr};
+  double *bvD[2] = {nullptr, nullptr};
+  double *bLD = nullptr, *bbD = nullptr, *btmp = nullptr;
+  int32_t *didx = nullptr;                 // DOF -> index of its Dirichlet value (-1: free)
+  hipEvent_t ev_blk_src = nullptr, ev_blk_done[2] = {nullptr, nullptr};
+  bool blk_live[2] = {false, false};
+  int blk_next = 0;
   int hw0 = 1;
   sa::SolveStatus *d_status = nullptr;   // ring of per-solve records
   std::vector<int8_t> status_kind;       // 0 projection, 1 theta-step
@@ -225,6 +244,8 @@ sa_iga::~sa_iga() {
   for (hipEvent_t e : ev_sum) if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : ev_part) if (e) (void)hipEventDestroy(e);
   if (ev_end) (void)hipEventDestroy(ev_end);
+  if (ev_blk_src) (void)hipEventDestroy(ev_blk_src);
+  for (hipEvent_t e : ev_blk_done) if (e) (void)hipEventDestroy(e);
   for (auto &s : ev) {
     for (auto &pr : s.pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto &pr : s.pool) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
@@ -422,7 +443,7 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
                 const float *fz, const float *fq2, const int8_t *role, const double *nx, const double *ny,
                 const double *nz, const double *wdS, bool by_slot, int64_t ostride, double *T, double *G,
                 double *ld, const double *net = nullptr, int64_t net_stride = 0, hipStream_t post = nullptr,
-                bool boundary = false) {
+                bool boundary = false, int plan_count = 0) {
   int64_t max_act = 0, max_far = 0, max_near = 0;
   for (int s = 0; s < tab.count; ++s) {
     const int64_t nf = tab.mode[s] ? 0 : tab.n_far[s];      // far sources summed here
@@ -434,12 +455,18 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
     if (tab.mode[s]) h->stats.pairs_net += (int64_t)tab.n_far[s] * nq;
   }
   const hipStream_t st = src_stream(h);
-  if (max_act > 0) {
+  // the tensor sum takes its coefficients from the age tables when it is the
+  // only sum of this call and they cover every slot's time
+  bool tables = boundary && h->use_tensor && h->n_gen == 0;
+  for (int s = 0; s < tab.count && tables; ++s) tables = tab.now[s] <= h->age_max;
+  if (max_act > 0 && !tables) {
     StageScope s(h, SA_STAGE_COEFF, st);
     sa::CoeffParams cp{h->delta, h->shift, h->alpha, h->rc, h->m.opt.kernel_scale};
     sa::launch_coeff(st, tab, max_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
   }
-  sa::SumPlan pl = make_plan(h, nq, tab.count, max_far, max_near);
+  // the chunking follows plan_count paths (the slots of a blocked call cut
+  // their histories as one-step calls do)
+  sa::SumPlan pl = make_plan(h, nq, plan_count > 0 ? plan_count : tab.count, max_far, max_near);
   pl.part_stride = stride;
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
   ensure_part(h, (int64_t)tab.count * std::max(nch, 1) * 5 * stride);
@@ -454,6 +481,9 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
     if (boundary && h->use_tensor) {
       sa::TensorArgs ta = h->tens;
       ta.c64 = h->c64;
+      if (!tables) ta.age_c = nullptr;
+      // a blocked call of one to three paths keeps their grid size
+      if (plan_count > 0 && plan_count < 4) ta.max_groups_batch = ta.max_groups;
       ta.part = part;
       ta.stride = stride;
       sa::launch_sum_tensor(st, pl, tab, ta);
@@ -697,7 +727,23 @@ void audit_slots(sa_iga *h, const sa::PathTab &tab, const std::vector<int> &aud)
 // The paths may sit at different steps; their steps share one parity, which
 // selects the state buffers (u^n, F^n read from one, u^{n+1}, F^{n+1} written
 // to the other).
+// verbose: host time between marks, added to h->host_us[section]
+struct HostLap {
+  sa_iga *h;
+  std::chrono::steady_clock::time_point t;
+  explicit HostLap(sa_iga *h_) : h(h_) {
+    if (h->verbose) t = std::chrono::steady_clock::now();
+  }
+  void mark(int section) {
+    if (!h->verbose) return;
+    const auto n = std::chrono::steady_clock::now();
+    h->host_us[section] += std::chrono::duration<double, std::micro>(n - t).count();
+    t = n;
+  }
+};
+
 void step_batch(sa_iga *h, std::vector<int> pids) {
+  HostLap lap(h);
   const int count = (int)pids.size();
   const int cur = (int)(h->paths[pids[0]].step & 1), nxt = cur ^ 1;
   const int64_t nd = h->nd;
@@ -738,10 +784,12 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     h->stats.net_steps += n_net;
   }
   // T~, grad T~ and load densities at every boundary point (Eqs. 7-8, 10-11)
+  lap.mark(0);
   const hipStream_t as = post_stream(h);
   sum_points(h, tab, h->nq, h->stride, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role,
              h->nx, h->ny, h->nz, h->wdS, false, h->stride, h->Tb, h->Gb, h->LD, net, h->stride, as, true);
   double *Vc = h->V[cur], *Vn = h->V[nxt], *Fc = h->Fb[cur], *Fn = h->Fb[nxt];
+  lap.mark(1);
   if (h->overlap) {
     // F^{n+1} and the Dirichlet values of u^{n+1} overwrite F^{n-1} and
     // entries of u^{n-1}: wait until the right-hand side of step n of these
@@ -810,6 +858,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     }
   }
   // the theta-step of these paths: on the solver stream
+  lap.mark(2);
   const hipStream_t bsx = solve_stream(h);
   if (h->overlap) {
     const hipEvent_t e = h->ev_src[h->ev_next % (int64_t)h->ev_src.size()];
@@ -869,6 +918,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       }
     }
     rhs_done();
+    lap.mark(3);
     StageScope s(h, SA_STAGE_PCG, bsx);
     sa::FusedPcg f = h->fp;
     f.x = Vn;
@@ -985,6 +1035,136 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
   hip_check(hipGetLastError(), "kernel launch");
   for (int s = 0; s < count; ++s) h->paths[pids[s]].step++;
   h->stats.steps += count;
+  lap.mark(4);
+}
+
+// K steps of the paths `pids` (one step parity, none finishing inside the
+// block) with the source side once for the block (the blocked-source-side
+// members of sa_iga): slot k L + l of the source launches is step k of path
+// pids[l].  Same results, bit for bit, as K one-step calls.
+void step_block(sa_iga *h, const std::vector<int> &pids, int K) {
+  HostLap lap(h);
+  const int L = (int)pids.size(), KL = K * L;
+  if (L <= 0 || K <= 0 || KL > kBlockSlots) throw sa::SaError{SA_EINVAL, "internal: block size"};
+  const int64_t nd = h->nd, st = h->stride, nDa = h->nDa;
+  const int sb = h->blk_next;
+  h->blk_next ^= 1;
+  sa::PathTab tab{};
+  tab.count = KL;
+  for (int k = 0; k < K; ++k)
+    for (int l = 0; l < L; ++l) {
+      const PathState &P = h->paths[pids[l]];
+      if ((P.step & 1) != (h->paths[pids[0]].step & 1) || P.step + K > P.n_steps)
+        throw sa::SaError{SA_EINVAL, "internal: paths of a block"};
+      fill_slot(h, tab, k * L + l, pids[l], P.step + 1 + k);
+      if (tab.now[k * L + l] > h->age_max) throw sa::SaError{SA_EINVAL, "internal: block beyond the age tables"};
+    }
+  sa::SlotMap si{};   // slot s -> staging entry s
+  si.count = KL;
+  for (int s = 0; s < KL; ++s) si.path[s] = s;
+  const hipStream_t as = post_stream(h);
+  // staging set sb is free once the theta-steps of the block that used it last are done
+  if (h->blk_live[sb]) hip_check(hipStreamWaitEvent(as, h->ev_blk_done[sb], 0), "stream wait");
+  lap.mark(0);
+  // T~, grad T~ and load densities of every step of the block (Eqs. 7-8, 10-11)
+  sum_points(h, tab, h->nq, st, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role, h->nx, h->ny,
+             h->nz, h->wdS, true, st, h->bT[sb], h->bG[sb], h->bLD, nullptr, 0, as, true, L);
+  lap.mark(1);
+  {
+    // F^{n+1..n+K} (Eq. 18) and the projection right-hand sides (Eq. 11)
+    StageScope s(h, SA_STAGE_LOAD, as);
+    if (h->nD > 0)
+      sa::launch_gather_rows2(as, si, h->grows, h->bF[sb], nd, h->drows, h->bbD, nDa, h->bLD, st);
+    else
+      sa::launch_gather_rows(as, si, h->grows, h->bLD, st, h->bF[sb], nd, 0, nullptr, nullptr);
+  }
+  if (h->nD > 0) {
+    StageScope s(h, SA_STAGE_DIRICHLET, as);
+    sa::DirDirect a = h->ddir;
+    a.b = h->bbD;
+    a.vD = h->bvD[sb];
+    a.vs = nDa;
+    a.xfull = nullptr;   // scattered into u^{n+1} by its theta-step
+    a.tmp = h->ddir.tmp ? h->btmp : nullptr;
+    sa::launch_dir_direct(as, si, a);
+  }
+  const hipStream_t bsx = solve_stream(h);
+  hip_check(hipEventRecord(h->ev_blk_src, as), "event record");
+  hip_check(hipStreamWaitEvent(bsx, h->ev_blk_src, 0), "stream wait");
+  lap.mark(2);
+  sa::SlotMap sm{};
+  sm.count = L;
+  for (int l = 0; l < L; ++l) sm.path[l] = pids[l];
+  for (int k = 0; k < K; ++k) {
+    const int cur = (int)(h->paths[pids[0]].step & 1), nxt = cur ^ 1;
+    double *Vc = h->V[cur], *Vn = h->V[nxt];
+    {
+      // theta-scheme right-hand side (Eq. 20), first iterate with the
+      // Dirichlet values, and the residual check of the previous step
+      StageScope s(h, SA_STAGE_RHS, bsx);
+      sa::KronArgs ka = h->kargs;
+      ka.x = Vn;
+      ka.v = Vc;
+      ka.F1 = h->bF[sb] + (int64_t)k * L * nd;
+      ka.f1_slot = 1;
+      ka.f1s = nd;
+      if (k == 0) {
+        ka.F0 = h->Fb[cur];
+      } else {
+        ka.F0 = h->bF[sb] + (int64_t)(k - 1) * L * nd;
+        ka.f0_slot = 1;
+        ka.f0s = nd;
+      }
+      ka.out = h->r;
+      ka.part = h->part_b2;
+      ka.sc = nullptr;
+      ka.sc_w = h->sc;
+      ka.init_x = 1;
+      ka.x_init = Vn;
+      ka.check = 1;
+      if (h->nD > 0) {
+        ka.dv = h->bvD[sb] + (int64_t)k * L * nDa;
+        ka.dvs = nDa;
+        ka.didx = h->didx;
+      }
+      sa::launch_kron(bsx, sm, ka, true);
+    }
+    lap.mark(3);
+    {
+      StageScope s(h, SA_STAGE_PCG, bsx);
+      sa::FusedPcg f = h->fp;
+      f.x = Vn;
+      f.status = next_status(h, L, 1);
+      f.update_x = 1;
+      f.check_mask = 0;
+      for (int l = 0; l < L; ++l)
+        if (h->chk_pending[pids[l]]) f.check_mask |= 1ull << l;
+      f.part_chk = h->part_chk;
+      f.np_chk = h->np_st;
+      f.chk_rtol2 = h->force_rollback ? 0.0 : f.rtol2;
+      f.chk_bw2 = h->force_rollback ? 0.0 : f.bw2;
+      sa::launch_fd_pass(bsx, sm, f, 0, true, false);
+    }
+    for (int l = 0; l < L; ++l) {
+      h->chk_pending[pids[l]] = 1;
+      h->paths[pids[l]].step++;
+    }
+    h->stats.steps += L;
+    lap.mark(4);
+  }
+  // the block's last F, Dirichlet values, T~ and grad T~ into the paths' state
+  const int fin = (int)(h->paths[pids[0]].step & 1);
+  const int64_t last = (int64_t)(K - 1) * L;
+  sa::CopyJob jobs[4];
+  int nj = 0;
+  jobs[nj++] = sa::CopyJob{h->bF[sb] + last * nd, h->Fb[fin], nd, nd, nd};
+  jobs[nj++] = sa::CopyJob{h->bT[sb] + last * st, h->Tb, st, st, st};
+  jobs[nj++] = sa::CopyJob{h->bG[sb] + last * 3 * st, h->Gb, 3 * st, 3 * st, 3 * st};
+  if (h->nD > 0) jobs[nj++] = sa::CopyJob{h->bvD[sb] + last * nDa, h->vD, nDa, nDa, nDa};
+  sa::launch_copy_jobs(bsx, sm, jobs, nj);
+  hip_check(hipEventRecord(h->ev_blk_done[sb], bsx), "event record");
+  h->blk_live[sb] = true;
+  lap.mark(4);
 }
 
 // the residual checks of checked updates still pending at the end of a call:
@@ -1550,6 +1730,27 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   h->c64 = dev_alloc<double>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
   h->c32 = dev_alloc<float>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
   build_tensor_faces(h);
+  if (h->use_tensor) {
+    // Eq. 8 coefficients of the tensor sum by source age: with
+    // D(a) = a delta + r^2/(8 alpha), c = -1/(4 alpha D) and
+    // ln A = ln(s E) - ln(rho c_p (4 pi alpha D)^{3/2}); the age runs to the
+    // last step of the longest path
+    int64_t steps = 0;
+    for (int p = 0; p < S; ++p) steps = std::max<int64_t>(steps, scan->n_steps[p]);
+    h->age_max = steps * h->ns;
+    std::vector<double> ac((size_t)h->age_max + 1), al((size_t)h->age_max + 1), le((size_t)std::max<int64_t>(N, 1));
+    for (int64_t a = 0; a <= h->age_max; ++a) {
+      const double D = (double)a * h->delta + h->shift;
+      ac[a] = -1.0 / (4.0 * h->alpha * D);
+      al[a] = -std::log(h->rc * std::pow(4.0 * M_PI * h->alpha * D, 1.5));
+    }
+    for (int64_t i = 0; i < N; ++i) le[i] = std::log(m.opt.kernel_scale * scan->energy[i]);
+    h->tens.tick = h->stick;
+    h->tens.age_c = dev_upload(h->owned, ac, h->stream);
+    h->tens.age_l = dev_upload(h->owned, al, h->stream);
+    h->tens.src_le = dev_upload(h->owned, le, h->stream);
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+  }
 
   // per-path state: u = T0 (v = 0), F = 0, Dirichlet values 0
   h->paths.resize(S);
@@ -1798,15 +1999,41 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     }
     h->path_rhs.assign(S, -1);
   }
+  // the blocked source side: the matrix-core sum with age tables alone, no
+  // network, the checked one-application theta-step, exact Dirichlet data
+  h->blk_ok = h->overlap && h->pcg_fused && h->kron && h->fd_exact && h->use_tensor && h->n_gen == 0 && !h->net &&
+              (h->nD == 0 || h->dir_direct) && h->age_max >= 0 && !std::getenv("SA_IGA_NO_BLOCK");
+  if (h->blk_ok && h->nD > 0) {
+    std::vector<int32_t> di((size_t)nd, -1);
+    for (int64_t i = 0; i < h->nD; ++i) di[(size_t)h->m.dir_dofs[i]] = (int32_t)i;
+    for (int64_t r = 0; r < nd; ++r)
+      if (!h->m.free_mask[r] && di[r] < 0) h->blk_ok = false;
+    if (h->blk_ok) h->didx = dev_upload(h->owned, di, h->stream);
+  }
+  if (h->blk_ok) {
+    const size_t KL = kBlockSlots, st = (size_t)h->stride;
+    for (int b = 0; b < 2; ++b) {
+      h->bF[b] = dev_zeros<double>(h, KL * nd);   // rows the load vector never touches stay zero
+      h->bT[b] = dev_zeros<double>(h, KL * st);
+      h->bG[b] = dev_zeros<double>(h, KL * 3 * st);
+      h->bvD[b] = dev_zeros<double>(h, KL * h->nDa);
+      hip_check(hipEventCreateWithFlags(&h->ev_blk_done[b], hipEventDisableTiming), "event");
+    }
+    h->bLD = dev_zeros<double>(h, KL * st);
+    h->bbD = dev_zeros<double>(h, KL * h->nDa);
+    if (h->nD > 0 && h->ddir.tmp) h->btmp = dev_zeros<double>(h, KL * (size_t)h->ddir.na * h->ddir.nb);
+    hip_check(hipEventCreateWithFlags(&h->ev_blk_src, hipEventDisableTiming), "event");
+  }
   hip_check(hipStreamSynchronize(h->stream), "sync");
   h->verbose = std::getenv("SA_IGA_VERBOSE") != nullptr;
   if (h->verbose)
     std::fprintf(stderr,
                  "[sa_iga] paths %d ndof %lld nq %lld nD %lld | lds/block %zu | dirichlet: exact %d direct %d one-wg %d | "
-                 "theta-step: fused %d fd-exact %d budget %d kron %d | tensor tiles %d, generic points %lld\n",
+                 "theta-step: fused %d fd-exact %d budget %d kron %d | tensor tiles %d, generic points %lld | "
+                 "blocked source side %d\n",
                  S, (long long)nd, (long long)h->nq, (long long)h->nD, h->lds_per_block, (int)h->dir_exact, (int)h->dir_direct,
                  (int)h->dir_fused, (int)h->pcg_fused, (int)h->fd_exact, h->pcg_budget, (int)h->kron,
-                 h->use_tensor ? h->tens.n_tiles : 0, (long long)(h->use_tensor ? h->n_gen : h->nq));
+                 h->use_tensor ? h->tens.n_tiles : 0, (long long)(h->use_tensor ? h->n_gen : h->nq), (int)h->blk_ok);
 }
 
 // parametric query points -> device CSR rows of basis values (and gradients)
@@ -1946,11 +2173,41 @@ void run_steps(sa_iga *h, int32_t n_steps) {
       std::fill(h->path_rhs.begin(), h->path_rhs.end(), -1);
     }
     const auto t0 = std::chrono::steady_clock::now();
-    for (int32_t s = 0; s < n_steps; ++s) step_all(h);
+    // a call of one path (or a few at one step parity) runs in blocks of up
+    // to kBlockSlots / paths steps
+    std::vector<int> live;
+    int64_t rem = INT64_MAX;
+    for (int p = 0; p < (int)h->paths.size(); ++p)
+      if (h->paths[p].step < h->paths[p].n_steps) live.push_back(p);
+    bool blocked = h->blk_ok && h->pcg_budget == 1 && !live.empty() && 2 * (int)live.size() <= kBlockSlots;
+    for (int p : live) blocked = blocked && (h->paths[p].step & 1) == (h->paths[live[0]].step & 1);
+    for (int32_t s = 0; s < n_steps;) {
+      if (!blocked) {
+        step_all(h);
+        ++s;
+        continue;
+      }
+      live.clear();
+      rem = INT64_MAX;
+      for (int p = 0; p < (int)h->paths.size(); ++p)
+        if (h->paths[p].step < h->paths[p].n_steps) {
+          live.push_back(p);
+          rem = std::min<int64_t>(rem, h->paths[p].n_steps - h->paths[p].step);
+        }
+      if (live.empty()) break;
+      const int K = (int)std::min<int64_t>({rem, (int64_t)(n_steps - s), (int64_t)(kBlockSlots / (int)live.size())});
+      step_block(h, live, K);
+      s += K;
+    }
     flush_checks(h);
     if (h->verbose && n_steps > 0) {
       const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-      std::fprintf(stderr, "[sa_iga] %d steps enqueued in %.1f us per step\n", n_steps, us / n_steps);
+      std::fprintf(stderr,
+                   "[sa_iga] %d steps enqueued in %.1f us per step (slots %.1f, sum %.1f, load+Dirichlet %.1f, "
+                   "rhs %.1f, solve %.1f)\n",
+                   n_steps, us / n_steps, h->host_us[0] / n_steps, h->host_us[1] / n_steps,
+                   h->host_us[2] / n_steps, h->host_us[3] / n_steps, h->host_us[4] / n_steps);
+      for (double &x : h->host_us) x = 0.0;
     }
     if (h->overlap) {
       hip_check(hipEventRecord(h->ev_end, h->ss), "event record");
@@ -2278,6 +2535,7 @@ int sa_iga_get_info(sa_iga *h, sa_info *info) {
     for (int f = 0; f < 7; ++f) info->face_offset[f] = h->m.bt.face_off[f];
     info->n_paths = (int32_t)h->paths.size();
     info->n_sources = (int64_t)h->h_tick.size();
+    info->blocked_steps = h->blk_ok ? kBlockSlots : 1;
     info->n_dirichlet = h->nD;
     info->tensor_faces = h->use_tensor ? h->n_tfaces : 0;
     info->generic_points = h->use_tensor ? h->n_gen : h->nq;

@@ -119,6 +119,15 @@ struct KronArgs {
   int check, check_only;
   double *bprev;          // [paths][vs]
   double *part_chk;       // [paths][3][np]
+  // theta: F1 / F0 of launch slot s at F1 + s * f1s (f1_slot) instead of at
+  // F1 + path * vs; the same for F0
+  int f1_slot, f0_slot;
+  int64_t f1s, f0s;
+  // theta with init_x: the Dirichlet values of u^{n+1} taken from dv (slot s
+  // at dv + s * dvs, value didx[i] for DOF i) into x in the x pass
+  const double *dv;
+  int64_t dvs;
+  const int32_t *didx;
 };
 void launch_kron(hipStream_t st, const SlotMap &sm, const KronArgs &a, bool theta);
 // status records from the check partials of KronArgs (check_only pass): one
@@ -184,7 +193,16 @@ struct DirDirect {
   double *tmp;             // optional [path][na nb] scratch: two passes over many workgroups
 };
 size_t dir_direct_lds(int na, int nb);
+// (xfull == nullptr: the values are not scattered)
 bool dir_direct_prepare(size_t lds);   // allow that much dynamic LDS for the kernel
 void launch_dir_direct(hipStream_t st, const SlotMap &sm, const DirDirect &a);
+
+// per slot s (path p = path[s]) and job j: dst[p * ds + i] = src[s * ss + i], i < n
+struct CopyJob {
+  const double *src;
+  double *dst;
+  int64_t n, ss, ds;
+};
+void launch_copy_jobs(hipStream_t st, const SlotMap &sm, const CopyJob *jobs, int njobs);
 
 }  // namespace sa

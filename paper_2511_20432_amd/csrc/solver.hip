@@ -395,14 +395,15 @@ __device__ __forceinline__ double band_dot(const double *__restrict__ band, int 
 // values) on the others
 __device__ __forceinline__ void band_dot_init(const double *__restrict__ Mb, const double *__restrict__ Kb, int p,
                                               int i, int n, const uint8_t *__restrict__ mask,
-                                              const double *__restrict__ v, const double *x, int64_t base,
-                                              double &sm_, double &sk) {
+                                              const double *__restrict__ v, const double *x,
+                                              const double *__restrict__ dv, const int32_t *__restrict__ didx,
+                                              int64_t base, double &sm_, double &sk) {
   const double *bm = Mb + (int64_t)i * (2 * p + 1), *bk = Kb + (int64_t)i * (2 * p + 1);
   const int j0 = i - p < 0 ? 0 : i - p, j1 = i + p > n - 1 ? n - 1 : i + p;
   double s0 = 0.0, s1 = 0.0;
   for (int j = j0; j <= j1; ++j) {
     const int64_t q = base + (j - i);
-    const double xv = mask[q] ? v[q] : x[q];
+    const double xv = mask[q] ? v[q] : (dv ? dv[didx[q]] : x[q]);
     s0 = fma(bm[j - i + p], xv, s0);
     s1 = fma(bk[j - i + p], xv, s1);
   }
@@ -425,11 +426,13 @@ __global__ void k_kron_x(SlotMap sm, KronArgs a) {
     // first iterate formed here: no thread reads x at a free DOF, where it is written
     double *x = a.x_init + pth * a.vs;
     const double *v = a.v + pth * a.vs;
+    const double *dv = a.dv ? a.dv + (int64_t)blockIdx.y * a.dvs : nullptr;
     double s0, s1;
-    band_dot_init(a.op.Mb[0], a.op.Kb[0], p, i0, n0, a.mask, v, x, r, s0, s1);
+    band_dot_init(a.op.Mb[0], a.op.Kb[0], p, i0, n0, a.mask, v, x, dv, a.didx, r, s0, s1);
     t[r] = s0;
     t[N + r] = s1;
     if (a.mask[r]) x[r] = v[r];
+    else if (dv) x[r] = dv[a.didx[r]];
   } else {
     const double *x = a.x + pth * a.vs;
     t[r] = band_dot(a.op.Mb[0], p, i0, n0, x, r, 1);
@@ -502,7 +505,9 @@ __global__ __launch_bounds__(kB) void k_kron_z(SlotMap sm, KronArgs a) {
                           band_dot(a.op.Kb[2], p, i2, n2, t + 5 * N, r, n01);
         const double bv = band_dot(a.op.Mb[2], p, i2, n2, t + 6 * N, r, n01) +
                           band_dot(a.op.Kb[2], p, i2, n2, t + 7 * N, r, n01);
-        rhs = bv + a.theta * a.F1[g] + (1.0 - a.theta) * a.F0[g];
+        const double f1 = a.F1[a.f1_slot ? (int64_t)blockIdx.y * a.f1s + r : g];
+        const double f0 = a.F0[a.f0_slot ? (int64_t)blockIdx.y * a.f0s + r : g];
+        rhs = bv + a.theta * f1 + (1.0 - a.theta) * f0;
         part = rhs * rhs;
         rv = rhs - ax;
       }
@@ -854,6 +859,28 @@ void launch_check_status(hipStream_t st, const SlotMap &sm, const double *part_c
                      status);
 }
 
+__global__ void k_copy_jobs(SlotMap sm, CopyJob j0, CopyJob j1, CopyJob j2, CopyJob j3) {
+  const CopyJob j = blockIdx.z == 0 ? j0 : (blockIdx.z == 1 ? j1 : (blockIdx.z == 2 ? j2 : j3));
+  const int64_t s = blockIdx.y, p = sm.path[s];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < j.n; i += (int64_t)gridDim.x * blockDim.x)
+    j.dst[p * j.ds + i] = j.src[s * j.ss + i];
+}
+
+void launch_copy_jobs(hipStream_t st, const SlotMap &sm, const CopyJob *jobs, int njobs) {
+  if (sm.count <= 0 || njobs <= 0 || njobs > 4) return;
+  CopyJob j[4] = {};
+  int64_t n = 0;
+  for (int k = 0; k < njobs; ++k) {
+    j[k] = jobs[k];
+    n = std::max(n, jobs[k].n);
+  }
+  int64_t blocks = (n + kB - 1) / kB;
+  if (blocks > 256) blocks = 256;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy_jobs, dim3((unsigned)blocks, (unsigned)sm.count, (unsigned)njobs), dim3(kB), 0, st, sm,
+                     j[0], j[1], j[2], j[3]);
+}
+
 void launch_pcg_last_update(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k) {
   if (sm.count <= 0) return;
   const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
@@ -883,14 +910,14 @@ __global__ __launch_bounds__(kDD) void k_dir_direct(SlotMap sm, DirDirect a) {
     T[i] = s;
   }
   __syncthreads();
-  double *vD = a.vD + pth * a.vs, *x = a.xfull + pth * a.xs;
+  double *vD = a.vD + pth * a.vs, *x = a.xfull ? a.xfull + pth * a.xs : nullptr;
   for (int i = threadIdx.x; i < n; i += kDD) {          // along the second, scaled
     const int j0 = i % na, j1 = i / na;
     double s = 0.0;
     for (int k1 = 0; k1 < nb; ++k1) s = fma(Ib[j1 * nb + k1], T[j0 + na * k1], s);
     s *= a.inv_area;
     vD[i] = s;
-    x[a.dofs[i]] = s;
+    if (a.xfull) x[a.dofs[i]] = s;
   }
 }
 
@@ -918,14 +945,14 @@ __global__ __launch_bounds__(64) void k_dir_rows(SlotMap sm, DirDirect a) {
   const double *T = a.tmp + pth * (int64_t)na * nb;
   for (int k = threadIdx.x; k < nb; k += 64) row[k] = T[j0 + (int64_t)na * k];
   __syncthreads();
-  double *vD = a.vD + pth * a.vs, *x = a.xfull + pth * a.xs;
+  double *vD = a.vD + pth * a.vs, *x = a.xfull ? a.xfull + pth * a.xs : nullptr;
   for (int j1 = threadIdx.x; j1 < nb; j1 += 64) {
     double s = 0.0;
     for (int k1 = 0; k1 < nb; ++k1) s = fma(a.Ib[j1 * nb + k1], row[k1], s);
     s *= a.inv_area;
     const int64_t i = j0 + (int64_t)na * j1;
     vD[i] = s;
-    x[a.dofs[i]] = s;
+    if (a.xfull) x[a.dofs[i]] = s;
   }
 }
 

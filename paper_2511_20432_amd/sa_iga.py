@@ -54,7 +54,8 @@ class sa_scan_path(C.Structure):
 class sa_info(C.Structure):
     _fields_ = [("n_ctrl", C.c_int32 * 3), ("n_dof", C.c_int64), ("n_bpts", C.c_int64),
                 ("face_offset", C.c_int64 * 7), ("n_paths", C.c_int32), ("n_sources", C.c_int64),
-                ("n_dirichlet", C.c_int64), ("tensor_faces", C.c_int32), ("generic_points", C.c_int64)]
+                ("n_dirichlet", C.c_int64), ("tensor_faces", C.c_int32), ("generic_points", C.c_int64),
+                ("blocked_steps", C.c_int32)]
 
 
 class sa_stats(C.Structure):
