@@ -90,7 +90,11 @@ struct TensorArgs {
   int64_t stride;
   int max_groups;                // workgroups of a launch of one to three paths (0: one per work item)
   int max_groups_batch;          // ... of four paths or more, where the sum dominates the step
+  int lds_pad;                   // extra LDS bytes per workgroup: fewer groups per compute unit, room
+                                 // for the kernels that run beside the sum
 };
+// allow lds_pad bytes of dynamic LDS for the tensor sum
+bool sum_tensor_prepare(int lds_pad);
 constexpr int kTensorTile = 32;
 // the kernel sum at the points of the tensor faces as matrix products over
 // the sources (matrix cores): FP32 for the far chunks, FP64 for the near

@@ -384,8 +384,13 @@ void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, co
   const int64_t items = (int64_t)a.n_tiles * nch * tab.count;
   const int cap = tab.count >= 4 ? a.max_groups_batch : a.max_groups;
   const unsigned grid = (unsigned)(cap > 0 && items > cap ? cap : items);
-  hipLaunchKernelGGL(k_sum_tensor, dim3(grid), dim3(256), 0, st, a, tab, pl.n_chunks_far, nch, pl.chunk_far,
-                     pl.chunk_near);
+  hipLaunchKernelGGL(k_sum_tensor, dim3(grid), dim3(256), (size_t)a.lds_pad, st, a, tab, pl.n_chunks_far, nch,
+                     pl.chunk_far, pl.chunk_near);
+}
+
+bool sum_tensor_prepare(int lds_pad) {
+  return hipFuncSetAttribute((const void *)k_sum_tensor, hipFuncAttributeMaxDynamicSharedMemorySize, lds_pad) ==
+         hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -179,6 +179,7 @@ struct sa_iga {
   sa::FusedPcg fp{};
   double bw2 = 0.0;                      // (64 eps |A|_inf)^2, attainable-accuracy test
   bool kron = false;                     // matrix-free Kronecker A and B (affine patch)
+  bool zx_ok = false;                    // x-rows short enough for the fused z pass of the checked update
   sa::KronArgs kargs{};
   // Checked update (exact FD solve on a Kronecker operator, one iteration):
   // the theta-step is u^{n+1} = x0 + P r0, and its residual b - A u^{n+1} is
@@ -195,6 +196,7 @@ struct sa_iga {
   // At the block's end the last step's F, Dirichlet values, T~ and grad T~
   // are copied into the paths' state.
   bool blk_ok = false;
+  int blk_groups = 0, blk_pad = 0;         // sum grid cap (0: one group per item) and LDS padding
   double *bF[2] = {nullptr, nullptr}, *bT[2] = {nullptr, nullptr}, *bG[2] = {nullptr, nullptr};
   double *bvD[2] = {nullptr, nullptr};
   double *bLD = nullptr, *bbD = nullptr, *btmp = nullptr;
@@ -482,8 +484,10 @@ void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, c
       sa::TensorArgs ta = h->tens;
       ta.c64 = h->c64;
       if (!tables) ta.age_c = nullptr;
-      // a blocked call of one to three paths keeps their grid size
-      if (plan_count > 0 && plan_count < 4) ta.max_groups_batch = ta.max_groups;
+      if (plan_count > 0 && plan_count < 4) {   // a blocked call of one to three paths
+        ta.max_groups = ta.max_groups_batch = h->blk_groups;
+        ta.lds_pad = h->blk_pad;
+      }
       ta.part = part;
       ta.stride = stride;
       sa::launch_sum_tensor(st, pl, tab, ta);
@@ -876,7 +880,7 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     hip_check(hipEventRecord(h->ev_rhs[ev_slot], bsx), "event record");
     for (int s = 0; s < count; ++s) h->path_rhs[pids[s]] = ev_slot;
   };
-  const bool checked = h->pcg_fused && h->kron && h->fd_exact && h->pcg_budget == 1;
+  const bool checked = h->pcg_fused && h->kron && h->fd_exact && h->pcg_budget == 1 && h->zx_ok;
   if (h->pcg_fused) {
     {
       StageScope s(h, SA_STAGE_RHS, bsx);
@@ -911,8 +915,12 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
         k.sc_w = h->sc;
         k.init_x = 1;
         k.x_init = Vn;
-        k.check = checked ? 1 : 0;
-        sa::launch_kron(bsx, sm, k, true);
+        if (checked) {
+          k.check = 1;
+          sa::launch_theta_checked_rhs(bsx, sm, k, h->fp);
+        } else {
+          sa::launch_kron(bsx, sm, k, true);
+        }
       } else {
         sa::launch_stencil_sl(bsx, sm, a, h->hw0, true);
       }
@@ -948,17 +956,17 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
       else sa::launch_stencil_sl(bsx, sm, ap, h->hw0, false);
     };
     if (checked) {
-      // x += P r; the first pass also writes the record of the previous
-      // step's residual check of each path that has one pending
+      // x += P r; the first plane block also writes the record of the
+      // previous step's residual check of each path that has one pending
       f.update_x = 1;
       f.check_mask = 0;
       for (int s = 0; s < count; ++s)
         if (h->chk_pending[pids[s]]) f.check_mask |= 1ull << s;
       f.part_chk = h->part_chk;
-      f.np_chk = h->np_st;
+      f.np_chk = sa::zx_blocks(h->kargs.op);
       f.chk_rtol2 = h->force_rollback ? 0.0 : f.rtol2;   // forced: every check fails
       f.chk_bw2 = h->force_rollback ? 0.0 : f.bw2;
-      sa::launch_fd_pass(bsx, sm, f, 0, true, false);
+      sa::launch_theta_checked_solve(bsx, sm, f);
       for (int s = 0; s < count; ++s) h->chk_pending[pids[s]] = 1;
     } else {
       sa::launch_fd_pass(bsx, sm, f, 0, true, false);
@@ -1095,55 +1103,62 @@ void step_block(sa_iga *h, const std::vector<int> &pids, int K) {
   sa::SlotMap sm{};
   sm.count = L;
   for (int l = 0; l < L; ++l) sm.path[l] = pids[l];
+  const int par0 = (int)(h->paths[pids[0]].step & 1);
+  // theta arguments of step k of the block (u^{n+k} in V[(n+k) & 1])
+  auto step_args = [&](int k) {
+    const int cur = (par0 + k) & 1, nxt = cur ^ 1;
+    sa::KronArgs ka = h->kargs;
+    ka.x = h->V[nxt];
+    ka.v = h->V[cur];
+    ka.F1 = h->bF[sb] + (int64_t)k * L * nd;
+    ka.f1_slot = 1;
+    ka.f1s = nd;
+    if (k == 0) {
+      ka.F0 = h->Fb[cur];
+    } else {
+      ka.F0 = h->bF[sb] + (int64_t)(k - 1) * L * nd;
+      ka.f0_slot = 1;
+      ka.f0s = nd;
+    }
+    ka.out = h->r;
+    ka.part = h->part_b2;
+    ka.sc = nullptr;
+    ka.sc_w = h->sc;
+    ka.init_x = 1;
+    ka.x_init = h->V[nxt];
+    ka.check = 1;
+    if (h->nD > 0) {
+      ka.dv = h->bvD[sb] + (int64_t)k * L * nDa;
+      ka.dvs = nDa;
+      ka.didx = h->didx;
+    }
+    return ka;
+  };
   for (int k = 0; k < K; ++k) {
-    const int cur = (int)(h->paths[pids[0]].step & 1), nxt = cur ^ 1;
-    double *Vc = h->V[cur], *Vn = h->V[nxt];
+    const sa::KronArgs ka = step_args(k);
     {
       // theta-scheme right-hand side (Eq. 20), first iterate with the
-      // Dirichlet values, and the residual check of the previous step
+      // Dirichlet values, and the residual check of the previous step (the
+      // x pass of steps after the first ran fused with the previous solve)
       StageScope s(h, SA_STAGE_RHS, bsx);
-      sa::KronArgs ka = h->kargs;
-      ka.x = Vn;
-      ka.v = Vc;
-      ka.F1 = h->bF[sb] + (int64_t)k * L * nd;
-      ka.f1_slot = 1;
-      ka.f1s = nd;
-      if (k == 0) {
-        ka.F0 = h->Fb[cur];
-      } else {
-        ka.F0 = h->bF[sb] + (int64_t)(k - 1) * L * nd;
-        ka.f0_slot = 1;
-        ka.f0s = nd;
-      }
-      ka.out = h->r;
-      ka.part = h->part_b2;
-      ka.sc = nullptr;
-      ka.sc_w = h->sc;
-      ka.init_x = 1;
-      ka.x_init = Vn;
-      ka.check = 1;
-      if (h->nD > 0) {
-        ka.dv = h->bvD[sb] + (int64_t)k * L * nDa;
-        ka.dvs = nDa;
-        ka.didx = h->didx;
-      }
-      sa::launch_kron(bsx, sm, ka, true);
+      sa::launch_theta_checked_rhs(bsx, sm, ka, h->fp, k == 0);
     }
     lap.mark(3);
     {
       StageScope s(h, SA_STAGE_PCG, bsx);
       sa::FusedPcg f = h->fp;
-      f.x = Vn;
+      f.x = h->V[(par0 + k + 1) & 1];
       f.status = next_status(h, L, 1);
       f.update_x = 1;
       f.check_mask = 0;
       for (int l = 0; l < L; ++l)
         if (h->chk_pending[pids[l]]) f.check_mask |= 1ull << l;
       f.part_chk = h->part_chk;
-      f.np_chk = h->np_st;
+      f.np_chk = sa::zx_blocks(h->kargs.op);
       f.chk_rtol2 = h->force_rollback ? 0.0 : f.rtol2;
       f.chk_bw2 = h->force_rollback ? 0.0 : f.bw2;
-      sa::launch_fd_pass(bsx, sm, f, 0, true, false);
+      sa::launch_theta_checked_solve(bsx, sm, f, k + 1 == K);
+      if (k + 1 < K) sa::launch_xbwd_x(bsx, sm, f, step_args(k + 1));
     }
     for (int l = 0; l < L; ++l) {
       h->chk_pending[pids[l]] = 1;
@@ -1338,12 +1353,13 @@ void build_kron(sa_iga *h) {
   k.np = h->np_st;
   k.mask = h->free_mask;
   k.theta = th;
-  const bool chk = h->fd_exact;
+  h->zx_ok = sa::zx_fits(n[0]);
+  const bool chk = h->fd_exact && h->zx_ok;
   k.ts = (chk ? 10 : 8) * N;
   k.t = dev_zeros<double>(h, (size_t)h->S * k.ts);
   if (chk) {
     h->bprev = dev_zeros<double>(h, (size_t)h->S * N);
-    h->part_chk = dev_zeros<double>(h, (size_t)h->S * 3 * h->np_st);
+    h->part_chk = dev_zeros<double>(h, (size_t)h->S * 3 * std::max<int64_t>(h->np_st, sa::zx_blocks(k.op)));
     k.bprev = h->bprev;
     k.part_chk = h->part_chk;
   }
@@ -1558,6 +1574,15 @@ void build_tensor_faces(sa_iga *h) {
     const char *gb = std::getenv("SA_IGA_SUM_GROUPS_PER_CU_BATCH");
     h->tens.max_groups = (int)((g ? std::max(0.0, std::atof(g)) : 2.0) * prop.multiProcessorCount);
     h->tens.max_groups_batch = (gb ? std::max(0, std::atoi(gb)) : 8) * prop.multiProcessorCount;
+    // a blocked call's sum: one workgroup per work item (they retire often,
+    // so the solver kernels beside the sum get compute units), with LDS
+    // padding that leaves two per compute unit
+    const char *bg = std::getenv("SA_IGA_BLOCK_SUM_GROUPS_PER_CU");
+    const char *pad = std::getenv("SA_IGA_BLOCK_SUM_LDS_PAD");
+    h->blk_groups = (int)((bg ? std::max(0.0, std::atof(bg)) : 0.0) * prop.multiProcessorCount);
+    h->blk_pad = pad ? std::max(0, std::min(96 * 1024, std::atoi(pad))) : 36000;
+    if (h->blk_pad > 0 && !sa::sum_tensor_prepare(h->blk_pad)) h->blk_pad = 0;
+    h->tens.lds_pad = 0;
   }
   h->n_gen = (int64_t)gen.size();
   h->n_tfaces = (int)faces.size();
@@ -1938,6 +1963,13 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
       f.m[d] = FM.m[d];
     }
     f.U0 = h->fd_main.op.U[0];
+    {
+      const int mm = FM.m[0];
+      std::vector<double> ut((size_t)mm * mm);
+      for (int i = 0; i < mm; ++i)
+        for (int j = 0; j < mm; ++j) ut[(size_t)j * mm + i] = FM.U[0][(size_t)i * mm + j];
+      f.U0T = dev_upload(h->owned, ut, h->stream);
+    }
     f.U1 = h->fd_main.op.U[1];
     f.U2 = h->fd_main.op.U[2];
     f.inv = h->fd_main.op.inv_diag;
@@ -2001,7 +2033,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   }
   // the blocked source side: the matrix-core sum with age tables alone, no
   // network, the checked one-application theta-step, exact Dirichlet data
-  h->blk_ok = h->overlap && h->pcg_fused && h->kron && h->fd_exact && h->use_tensor && h->n_gen == 0 && !h->net &&
+  h->blk_ok = h->overlap && h->pcg_fused && h->kron && h->zx_ok && h->fd_exact && h->use_tensor && h->n_gen == 0 && !h->net &&
               (h->nD == 0 || h->dir_direct) && h->age_max >= 0 && !std::getenv("SA_IGA_NO_BLOCK");
   if (h->blk_ok && h->nD > 0) {
     std::vector<int32_t> di((size_t)nd, -1);

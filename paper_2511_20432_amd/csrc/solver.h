@@ -142,6 +142,7 @@ void launch_check_status(hipStream_t st, const SlotMap &sm, const double *part_c
 struct FusedPcg {
   int n[3], lo[3], m[3];
   const double *U0, *U1, *U2, *inv;
+  const double *U0T;      // optional: U0 transposed (coalesced back transform; same sums)
   double *x, *r, *z, *p, *q, *t;
   int64_t vs, ts;
   double *part_rz;        // [2][np_rz] per path
@@ -167,6 +168,26 @@ struct FusedPcg {
   double chk_rtol2, chk_bw2;
 };
 bool fused_fits(const int m[3]);
+// Checked update of a theta-step on a Kronecker operator with the exact FD
+// solve (u^{n+1} = x0 + P r0), in two launches sequences:
+//   rhs:   the x and y passes of the right-hand side (a: theta arguments with
+//          check), the z pass fused with the first FD transform into f.t (r
+//          is not stored; the residual-check partials, zx_blocks(op) per kind
+//          and path, go to a.part_chk)
+//   solve: the plane transforms, whose first block writes the status record
+//          of the previous step's residual check (f.update_x, check_mask,
+//          part_chk, np_chk = zx_blocks(op)), and the last transform, which
+//          adds P r0 to x
+bool zx_fits(int n0);
+int zx_blocks(const KronOp &op);
+void launch_theta_checked_rhs(hipStream_t st, const SlotMap &sm, const KronArgs &a, const FusedPcg &f,
+                              bool with_x = true);
+void launch_theta_checked_solve(hipStream_t st, const SlotMap &sm, const FusedPcg &f, bool with_xbwd = true);
+// the last FD transform of a checked step n (f: x = u^{n+1} being formed) and
+// the x pass of step n+1's right-hand side (a: its theta arguments with
+// init_x; v = u^{n+1}), fused per x-row: what launch_theta_checked_solve's
+// last launch and launch_theta_checked_rhs's first do, with the same sums
+void launch_xbwd_x(hipStream_t st, const SlotMap &sm, const FusedPcg &f, const KronArgs &a);
 // LDS bytes of the plane pass of the FD solve (two planes, the y and z eigenvectors)
 size_t fd_plane_lds(const int m[3]);
 void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update);

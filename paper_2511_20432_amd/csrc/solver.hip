@@ -686,16 +686,6 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k
     }
     if (first == 2) return;                 // last iteration: no preconditioned residual needed
   } else {
-    if (f.update_x && b == 0 && f.status) {
-      // checked update: the record of this path's previous theta-step
-      if ((f.check_mask >> blockIdx.y) & 1) {
-        check_record(f.part_chk, f.np_chk, f.chk_rtol2, f.chk_bw2, f.status, sh);
-      } else if (threadIdx.x == 0) {
-        f.status->iter = -1;               // nothing to check
-        f.status->done = 1;
-        f.status->relres2 = 0.0;
-      }
-    }
     for (int i = threadIdx.x; i < m0; i += blockDim.x) fib[i] = f.r[base + i];
     __syncthreads();
   }
@@ -708,8 +698,19 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k
 
 __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
   extern __shared__ double lds[];
+  __shared__ double sh[16];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
   if (f.sc->done) return;
+  if (f.update_x && blockIdx.x == 0 && f.status) {
+    // checked update: the record of this path's previous theta-step
+    if ((f.check_mask >> blockIdx.y) & 1) {
+      check_record(f.part_chk, f.np_chk, f.chk_rtol2, f.chk_bw2, f.status, sh);
+    } else if (threadIdx.x == 0) {
+      f.status->iter = -1;                 // nothing to check
+      f.status->done = 1;
+      f.status->relres2 = 0.0;
+    }
+  }
   const int m0 = f.m[0], m1 = f.m[1], m2 = f.m[2];
   const int P = m1 * m2;
   const int j0 = blockIdx.x;
@@ -764,7 +765,10 @@ __global__ __launch_bounds__(kFib) void k_fd_xbwd(SlotMap sm, FusedPcg f0, int s
   if (f.update_x) {   // x += P r: one application of the exact inverse
     for (int k0 = threadIdx.x; k0 < m0; k0 += blockDim.x) {
       double s = 0.0;
-      for (int j = 0; j < m0; ++j) s = fma(f.U0[k0 * m0 + j], fib[j], s);
+      if (f.U0T)
+        for (int j = 0; j < m0; ++j) s = fma(f.U0T[j * m0 + k0], fib[j], s);
+      else
+        for (int j = 0; j < m0; ++j) s = fma(f.U0[k0 * m0 + j], fib[j], s);
       f.x[base + k0] += s;
     }
     return;
@@ -825,6 +829,187 @@ bool fused_fits(const int m[3]) { return m[0] <= 256 && (int64_t)m[1] * m[2] <= 
 
 size_t fd_plane_lds(const int m[3]) {
   return ((size_t)2 * m[1] * m[2] + (size_t)m[1] * m[1] + (size_t)m[2] * m[2]) * sizeof(double);
+}
+
+// Checked update, first part: the z pass of the theta right-hand side and
+// residual r (as k_kron_z<true> with check) for whole x-rows, R = kZxThreads /
+// n0 rows per block, then the first FD transform t = U0^T r of the rows in
+// the free box (as k_fd_xfwd); r stays in LDS.  The residual-check partials
+// are summed per block (part_chk: gridDim.x of each kind per path).
+constexpr int kZxThreads = 320;
+constexpr int kZxMaxRow = 640;
+
+__global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, FusedPcg f0) {
+  __shared__ double fib[kZxMaxRow];
+  __shared__ double sh[16];
+  const int64_t pth = sm.path[blockIdx.y];
+  const FusedPcg f = at_path(f0, sm, blockIdx.y);
+  const int n0 = a.op.n[0], n1 = a.op.n[1], n2 = a.op.n[2], p = a.op.p[2];
+  const int64_t n01 = (int64_t)n0 * n1, nrows = (int64_t)n1 * n2;
+  const int R = n0 <= kZxThreads ? kZxThreads / n0 : 1;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int ne = R * n0;
+  const double *t = a.t + pth * a.ts;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int64_t row = row0 + e / n0;
+    double rv = 0.0;
+    if (row < nrows) {
+      const int64_t r = row * n0 + e % n0;
+      const int i2 = (int)(r / n01);
+      const int64_t g = pth * a.vs + r;
+      if (a.mask[r]) {
+        const double ax = band_dot(a.op.Mb[2], p, i2, n2, t + 4 * a.nrow, r, n01) +
+                          band_dot(a.op.Kb[2], p, i2, n2, t + 5 * a.nrow, r, n01);
+        const double bv = band_dot(a.op.Mb[2], p, i2, n2, t + 6 * a.nrow, r, n01) +
+                          band_dot(a.op.Kb[2], p, i2, n2, t + 7 * a.nrow, r, n01);
+        const double f1 = a.F1[a.f1_slot ? (int64_t)blockIdx.y * a.f1s + r : g];
+        const double f0 = a.F0[a.f0_slot ? (int64_t)blockIdx.y * a.f0s + r : g];
+        const double rhs = bv + a.theta * f1 + (1.0 - a.theta) * f0;
+        rv = rhs - ax;
+        const double av = band_dot(a.op.Mb[2], p, i2, n2, t + 8 * a.nrow, r, n01) +
+                          band_dot(a.op.Kb[2], p, i2, n2, t + 9 * a.nrow, r, n01);
+        const double bp = a.bprev[g], vv = a.v[g], d = bp - av;
+        c0 = fma(d, d, c0);
+        c1 = fma(bp, bp, c1);
+        c2 = fma(vv, vv, c2);
+        a.bprev[g] = rhs;
+      }
+    }
+    fib[e] = rv;
+  }
+  c0 = bsum(c0, sh);
+  c1 = bsum(c1, sh);
+  c2 = bsum(c2, sh);
+  if (threadIdx.x == 0) {
+    double *pc = a.part_chk + pth * 3 * a.np + blockIdx.x;
+    pc[0] = c0;
+    pc[a.np] = c1;
+    pc[2 * a.np] = c2;
+    if (blockIdx.x == 0 && a.sc_w) a.sc_w[pth].done = 0;
+  }
+  // (bsum ends with a barrier: fib is complete)
+  const int m0 = f.m[0], m1 = f.m[1];
+  const int64_t P = (int64_t)m1 * f.m[2];
+  for (int o = threadIdx.x; o < R * m0; o += blockDim.x) {
+    const int j = o / m0, j0 = o % m0;
+    const int64_t row = row0 + j;
+    if (row >= nrows) continue;
+    const int k1 = (int)(row % n1) - f.lo[1], k2 = (int)(row / n1) - f.lo[2];
+    if (k1 < 0 || k1 >= m1 || k2 < 0 || k2 >= f.m[2]) continue;
+    const double *fr = fib + j * n0 + f.lo[0];
+    double s = 0.0;
+    for (int kk = 0; kk < m0; ++kk) s = fma(f.U0[kk * m0 + j0], fr[kk], s);
+    f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1] = s;
+  }
+}
+
+bool zx_fits(int n0) { return n0 <= kZxMaxRow; }
+
+int zx_blocks(const KronOp &op) {
+  const int n0 = op.n[0];
+  const int R = n0 <= kZxThreads ? kZxThreads / n0 : 1;
+  return (int)(((int64_t)op.n[1] * op.n[2] + R - 1) / R);
+}
+
+void launch_theta_checked_rhs(hipStream_t st, const SlotMap &sm, const KronArgs &a0, const FusedPcg &f,
+                              bool with_x) {
+  if (sm.count <= 0 || a0.nrow <= 0) return;
+  KronArgs a = a0;
+  a.np = zx_blocks(a.op);
+  dim3 g((unsigned)((a.nrow + kB - 1) / kB), (unsigned)sm.count), b(kB);
+  if (with_x) hipLaunchKernelGGL(k_kron_x<true>, g, b, 0, st, sm, a);
+  hipLaunchKernelGGL(k_kron_y<true>, g, b, 0, st, sm, a);
+  hipLaunchKernelGGL(k_kron_zx, dim3((unsigned)a.np, (unsigned)sm.count), dim3(kZxThreads), 0, st, sm, a, f);
+}
+
+void launch_theta_checked_solve(hipStream_t st, const SlotMap &sm, const FusedPcg &f, bool with_xbwd) {
+  if (sm.count <= 0) return;
+  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(kB), fd_plane_lds(f.m), st, sm, f);
+  const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
+  if (with_xbwd) hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, 0, 1);
+}
+
+// x-rows as in k_kron_zx: the box part of each row's t fiber into LDS, then
+// u^{n+1} = x0 + U0 t on the box (stored, and kept in LDS for the row), then
+// the band products along x of step n+1's first iterate (u^{n+1} on the free
+// DOFs, its Dirichlet values elsewhere) and of u^{n+1}
+__global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, KronArgs a) {
+  __shared__ double tf[kZxMaxRow];
+  __shared__ double u[kZxMaxRow];
+  const int64_t pth = sm.path[blockIdx.y];
+  const FusedPcg f = at_path(f0, sm, blockIdx.y);
+  const int n0 = a.op.n[0], n1 = a.op.n[1], p = a.op.p[0];
+  const int64_t nrows = (int64_t)n1 * a.op.n[2], N = a.nrow;
+  const int R = n0 <= kZxThreads ? kZxThreads / n0 : 1;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int ne = R * n0;
+  const int m0 = f.m[0], m1 = f.m[1];
+  const int64_t P = (int64_t)m1 * f.m[2];
+  for (int o = threadIdx.x; o < R * m0; o += blockDim.x) {
+    const int j = o / m0, j0 = o % m0;
+    const int64_t row = row0 + j;
+    double tv = 0.0;
+    if (row < nrows) {
+      const int k1 = (int)(row % n1) - f.lo[1], k2 = (int)(row / n1) - f.lo[2];
+      if (k1 >= 0 && k1 < m1 && k2 >= 0 && k2 < f.m[2]) tv = f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1];
+    }
+    tf[o] = tv;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int j = e / n0, i0 = e % n0;
+    const int64_t row = row0 + j;
+    double xv = 0.0;
+    if (row < nrows) {
+      const int64_t r = row * n0 + i0;
+      xv = f.x[r];
+      const int k0 = i0 - f.lo[0], k1 = (int)(row % n1) - f.lo[1], k2 = (int)(row / n1) - f.lo[2];
+      if (k0 >= 0 && k0 < m0 && k1 >= 0 && k1 < m1 && k2 >= 0 && k2 < f.m[2]) {
+        const double *tr = tf + j * m0;
+        double s = 0.0;
+        for (int jj = 0; jj < m0; ++jj) s = fma(f.U0T[jj * m0 + k0], tr[jj], s);
+        xv += s;
+        f.x[r] = xv;
+      }
+    }
+    u[e] = xv;
+  }
+  __syncthreads();
+  double *t = a.t + pth * a.ts;
+  double *xi = a.x_init + pth * a.vs;
+  const double *dv = a.dv ? a.dv + (int64_t)blockIdx.y * a.dvs : nullptr;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int j = e / n0, i0 = e % n0;
+    const int64_t row = row0 + j;
+    if (row >= nrows) continue;
+    const int64_t r = row * n0 + i0;
+    const double *bm = a.op.Mb[0] + (int64_t)i0 * (2 * p + 1), *bk = a.op.Kb[0] + (int64_t)i0 * (2 * p + 1);
+    const int j0 = i0 - p < 0 ? 0 : i0 - p, j1 = i0 + p > n0 - 1 ? n0 - 1 : i0 + p;
+    double s0 = 0.0, s1 = 0.0;
+    for (int jj = j0; jj <= j1; ++jj) {
+      const int64_t q = r + (jj - i0);
+      const double uq = u[j * n0 + jj];
+      const double x0 = a.mask[q] ? uq : (dv ? dv[a.didx[q]] : xi[q]);
+      s0 = fma(bm[jj - i0 + p], x0, s0);
+      s1 = fma(bk[jj - i0 + p], x0, s1);
+    }
+    double s2 = 0.0, s3 = 0.0;
+    for (int jj = j0; jj <= j1; ++jj) s2 = fma(bm[jj - i0 + p], u[j * n0 + jj], s2);
+    for (int jj = j0; jj <= j1; ++jj) s3 = fma(bk[jj - i0 + p], u[j * n0 + jj], s3);
+    t[r] = s0;
+    t[N + r] = s1;
+    t[2 * N + r] = s2;
+    t[3 * N + r] = s3;
+    if (a.mask[r]) xi[r] = u[e];
+    else if (dv) xi[r] = dv[a.didx[r]];
+  }
+}
+
+void launch_xbwd_x(hipStream_t st, const SlotMap &sm, const FusedPcg &f, const KronArgs &a) {
+  if (sm.count <= 0) return;
+  hipLaunchKernelGGL(k_xbwd_x, dim3((unsigned)zx_blocks(a.op), (unsigned)sm.count), dim3(kZxThreads), 0, st, sm, f,
+                     a);
 }
 
 void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update) {
