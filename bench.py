@@ -39,14 +39,15 @@ METRIC = "source×point pairs/s + θ-steps/s; mixed+surrogate vs FP64 GPU at ≤
 MFMA_FP32 = 157.3e12
 MFMA_FP64 = 78.6e12
 FLOPS_PER_PAIR = 8
-# HBM bytes per step of the sum kernel (one k_sum_tensor launch: far and near
-# items) of this workload's FP32 far-field form, from rocprofv3
-# FETCH_SIZE / WRITE_SIZE over steps 1480..1779, scaled by the same counters
-# on a 256 MiB copy (profiles/k_sum_tensor_raster_fp32far.md).  Valid for the
+# HBM bytes per step of the sum kernel (k_sum_tensor: far and near items of
+# eight steps per launch) of this workload's FP32 far-field form, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE over the profiled run, scaled by the same
+# counters on a 256 MiB copy (bench.py --copy-calibration), divided by the
+# steps per launch (profiles/k_sum_tensor_raster_fp32far.md).  Valid for the
 # kernels as profiled; a changed sum kernel must set this to None until the
 # counters are taken again.  The written bytes are the FP64 chunk partials
 # (5 x 8 B per point and chunk) that k_finalize reads.
-K_SUM_TRAFFIC = {"read_bytes": 3.56e6, "written_bytes": 36.09e6}
+K_SUM_TRAFFIC = {"read_bytes": 1.37e6, "written_bytes": 35.89e6}
 
 
 def _k_sum_traffic(form):
@@ -292,7 +293,20 @@ def main():
                     help="timed steps of the 128-strategy batch (0: skip)")
     ap.add_argument("--surrogate-window", type=int, default=60,
                     help="timed steps of the surrogate form on held-out strategies (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device five times (the reference kernel of the HBM "
+                         "counter scale) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        torch.cuda.set_device(0)
+        a = torch.ones(64 * 1024 * 1024, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("copied 5 x 256 MiB", flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's sharding plan is "
               "described in DESIGN.md", file=sys.stderr)

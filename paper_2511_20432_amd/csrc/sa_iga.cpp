@@ -196,12 +196,18 @@ struct sa_iga {
   // At the block's end the last step's F, Dirichlet values, T~ and grad T~
   // are copied into the paths' state.
   bool blk_ok = false;
+  int blk_steps = kBlockSlots;             // steps x paths per block (<= kBlockSlots)
   int blk_groups = 0, blk_pad = 0;         // sum grid cap (0: one group per item) and LDS padding
   double *bF[2] = {nullptr, nullptr}, *bT[2] = {nullptr, nullptr}, *bG[2] = {nullptr, nullptr};
   double *bvD[2] = {nullptr, nullptr};
   double *bLD = nullptr, *bbD = nullptr, *btmp = nullptr;
   int32_t *didx = nullptr;                 // DOF -> index of its Dirichlet value (-1: free)
   hipEvent_t ev_blk_src = nullptr, ev_blk_done[2] = {nullptr, nullptr};
+  // the sum of a block starts once the theta-steps of the previous block are
+  // done but blk_overlap (its last blk_overlap steps run beside the sum)
+  hipEvent_t ev_blk_mid = nullptr;
+  bool blk_mid_live = false;
+  int blk_overlap = kBlockSlots;
   bool blk_live[2] = {false, false};
   int blk_next = 0;
   int hw0 = 1;
@@ -247,6 +253,7 @@ sa_iga::~sa_iga() {
   for (hipEvent_t e : ev_part) if (e) (void)hipEventDestroy(e);
   if (ev_end) (void)hipEventDestroy(ev_end);
   if (ev_blk_src) (void)hipEventDestroy(ev_blk_src);
+  if (ev_blk_mid) (void)hipEventDestroy(ev_blk_mid);
   for (hipEvent_t e : ev_blk_done) if (e) (void)hipEventDestroy(e);
   for (auto &s : ev) {
     for (auto &pr : s.pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
@@ -1073,6 +1080,8 @@ void step_block(sa_iga *h, const std::vector<int> &pids, int K) {
   const hipStream_t as = post_stream(h);
   // staging set sb is free once the theta-steps of the block that used it last are done
   if (h->blk_live[sb]) hip_check(hipStreamWaitEvent(as, h->ev_blk_done[sb], 0), "stream wait");
+  if (h->blk_mid_live) hip_check(hipStreamWaitEvent(src_stream(h), h->ev_blk_mid, 0), "stream wait");
+  h->blk_mid_live = false;
   lap.mark(0);
   // T~, grad T~ and load densities of every step of the block (Eqs. 7-8, 10-11)
   sum_points(h, tab, h->nq, st, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->role, h->nx, h->ny,
@@ -1165,6 +1174,10 @@ void step_block(sa_iga *h, const std::vector<int> &pids, int K) {
       h->paths[pids[l]].step++;
     }
     h->stats.steps += L;
+    if (h->blk_overlap < K && k + 1 == std::max(1, K - h->blk_overlap)) {
+      hip_check(hipEventRecord(h->ev_blk_mid, bsx), "event record");
+      h->blk_mid_live = true;
+    }
     lap.mark(4);
   }
   // the block's last F, Dirichlet values, T~ and grad T~ into the paths' state
@@ -2055,6 +2068,9 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
     h->bbD = dev_zeros<double>(h, KL * h->nDa);
     if (h->nD > 0 && h->ddir.tmp) h->btmp = dev_zeros<double>(h, KL * (size_t)h->ddir.na * h->ddir.nb);
     hip_check(hipEventCreateWithFlags(&h->ev_blk_src, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&h->ev_blk_mid, hipEventDisableTiming), "event");
+    if (const char *e = std::getenv("SA_IGA_BLOCK_SUM_OVERLAP")) h->blk_overlap = std::max(0, std::atoi(e));
+    if (const char *e = std::getenv("SA_IGA_BLOCK_STEPS")) h->blk_steps = std::max(1, std::min(kBlockSlots, std::atoi(e)));
   }
   hip_check(hipStreamSynchronize(h->stream), "sync");
   h->verbose = std::getenv("SA_IGA_VERBOSE") != nullptr;
@@ -2211,7 +2227,7 @@ void run_steps(sa_iga *h, int32_t n_steps) {
     int64_t rem = INT64_MAX;
     for (int p = 0; p < (int)h->paths.size(); ++p)
       if (h->paths[p].step < h->paths[p].n_steps) live.push_back(p);
-    bool blocked = h->blk_ok && h->pcg_budget == 1 && !live.empty() && 2 * (int)live.size() <= kBlockSlots;
+    bool blocked = h->blk_ok && h->pcg_budget == 1 && !live.empty() && 2 * (int)live.size() <= h->blk_steps;
     for (int p : live) blocked = blocked && (h->paths[p].step & 1) == (h->paths[live[0]].step & 1);
     for (int32_t s = 0; s < n_steps;) {
       if (!blocked) {
@@ -2227,7 +2243,7 @@ void run_steps(sa_iga *h, int32_t n_steps) {
           rem = std::min<int64_t>(rem, h->paths[p].n_steps - h->paths[p].step);
         }
       if (live.empty()) break;
-      const int K = (int)std::min<int64_t>({rem, (int64_t)(n_steps - s), (int64_t)(kBlockSlots / (int)live.size())});
+      const int K = (int)std::min<int64_t>({rem, (int64_t)(n_steps - s), (int64_t)(h->blk_steps / (int)live.size())});
       step_block(h, live, K);
       s += K;
     }
@@ -2567,7 +2583,7 @@ int sa_iga_get_info(sa_iga *h, sa_info *info) {
     for (int f = 0; f < 7; ++f) info->face_offset[f] = h->m.bt.face_off[f];
     info->n_paths = (int32_t)h->paths.size();
     info->n_sources = (int64_t)h->h_tick.size();
-    info->blocked_steps = h->blk_ok ? kBlockSlots : 1;
+    info->blocked_steps = h->blk_ok ? h->blk_steps : 1;
     info->n_dirichlet = h->nD;
     info->tensor_faces = h->use_tensor ? h->n_tfaces : 0;
     info->generic_points = h->use_tensor ? h->n_gen : h->nq;

@@ -382,9 +382,30 @@ __global__ void k_stencil_sl(SlotMap sm, SlArgs a) {
 // thread per row
 // ---------------------------------------------------------------------------
 // sum_j f[i][j] in[base + (j - i) stride] over the band j in [i - p, i + p] of 0..n-1
+// the band of half-width P unrolled, so that its loads issue together; the
+// same terms in the same order as the loop below
+template <int P>
+__device__ __forceinline__ double band_dot_p(const double *__restrict__ b, int i, int n,
+                                             const double *__restrict__ in, int64_t base, int64_t stride) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k <= 2 * P; ++k) {
+    const int j = i - P + k;
+    if (j >= 0 && j < n) s = fma(b[k], in[base + (int64_t)(k - P) * stride], s);
+  }
+  return s;
+}
+
 __device__ __forceinline__ double band_dot(const double *__restrict__ band, int p, int i, int n,
                                            const double *__restrict__ in, int64_t base, int64_t stride) {
   const double *b = band + (int64_t)i * (2 * p + 1);
+  switch (p) {
+    case 1: return band_dot_p<1>(b, i, n, in, base, stride);
+    case 2: return band_dot_p<2>(b, i, n, in, base, stride);
+    case 3: return band_dot_p<3>(b, i, n, in, base, stride);
+    case 4: return band_dot_p<4>(b, i, n, in, base, stride);
+    default: break;
+  }
   const int j0 = i - p < 0 ? 0 : i - p, j1 = i + p > n - 1 ? n - 1 : i + p;
   double s = 0.0;
   for (int j = j0; j <= j1; ++j) s = fma(b[j - i + p], in[base + (int64_t)(j - i) * stride], s);
@@ -691,6 +712,7 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k
   }
   for (int j0 = threadIdx.x; j0 < m0; j0 += blockDim.x) {
     double s = 0.0;
+    #pragma unroll 8
     for (int kk = 0; kk < m0; ++kk) s = fma(f.U0[kk * m0 + j0], fib[kk], s);
     f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1] = s;
   }
@@ -724,6 +746,7 @@ __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 1: U1^T along y
     const int j1 = i % m1, k2 = i / m1;
     double s = 0.0;
+    #pragma unroll 8
     for (int kk = 0; kk < m1; ++kk) s = fma(U1[kk * m1 + j1], A[k2 * m1 + kk], s);
     Bv[i] = s;
   }
@@ -731,6 +754,7 @@ __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 2: U2^T along z, scale
     const int j1 = i % m1, j2 = i / m1;
     double s = 0.0;
+    #pragma unroll 8
     for (int kk = 0; kk < m2; ++kk) s = fma(U2[kk * m2 + j2], Bv[kk * m1 + j1], s);
     A[i] = s * f.inv[j0 + (int64_t)m0 * (j1 + (int64_t)m1 * j2)];
   }
@@ -738,6 +762,7 @@ __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 2 back
     const int j1 = i % m1, k2 = i / m1;
     double s = 0.0;
+    #pragma unroll 8
     for (int j = 0; j < m2; ++j) s = fma(U2[k2 * m2 + j], A[j * m1 + j1], s);
     Bv[i] = s;
   }
@@ -745,6 +770,7 @@ __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
   for (int i = threadIdx.x; i < P; i += blockDim.x) {       // mode 1 back
     const int k1 = i % m1, k2 = i / m1;
     double s = 0.0;
+    #pragma unroll 8
     for (int j = 0; j < m1; ++j) s = fma(U1[k1 * m1 + j], Bv[k2 * m1 + j], s);
     t[i] = s;
   }
@@ -766,8 +792,10 @@ __global__ __launch_bounds__(kFib) void k_fd_xbwd(SlotMap sm, FusedPcg f0, int s
     for (int k0 = threadIdx.x; k0 < m0; k0 += blockDim.x) {
       double s = 0.0;
       if (f.U0T)
+        #pragma unroll 8
         for (int j = 0; j < m0; ++j) s = fma(f.U0T[j * m0 + k0], fib[j], s);
       else
+        #pragma unroll 8
         for (int j = 0; j < m0; ++j) s = fma(f.U0[k0 * m0 + j], fib[j], s);
       f.x[base + k0] += s;
     }
@@ -776,6 +804,7 @@ __global__ __launch_bounds__(kFib) void k_fd_xbwd(SlotMap sm, FusedPcg f0, int s
   double rz = 0.0;
   for (int k0 = threadIdx.x; k0 < m0; k0 += blockDim.x) {
     double s = 0.0;
+    #pragma unroll 8
     for (int j = 0; j < m0; ++j) s = fma(f.U0[k0 * m0 + j], fib[j], s);
     const int64_t g = base + k0;
     f.z[g] = s;
@@ -899,6 +928,7 @@ __global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, 
     if (k1 < 0 || k1 >= m1 || k2 < 0 || k2 >= f.m[2]) continue;
     const double *fr = fib + j * n0 + f.lo[0];
     double s = 0.0;
+    #pragma unroll 8
     for (int kk = 0; kk < m0; ++kk) s = fma(f.U0[kk * m0 + j0], fr[kk], s);
     f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1] = s;
   }
@@ -928,6 +958,44 @@ void launch_theta_checked_solve(hipStream_t st, const SlotMap &sm, const FusedPc
   hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(kB), fd_plane_lds(f.m), st, sm, f);
   const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
   if (with_xbwd) hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, 0, 1);
+}
+
+// band products along x of one row (u: the row's values of u^{n+1}) for the
+// first iterate (u on the free DOFs, Dirichlet values dv or xi elsewhere)
+// and for u; each sum over the band in ascending order.  P < 0: half-width p
+// at run time.
+template <int P>
+__device__ __forceinline__ void xrow_products(const double *__restrict__ bm, const double *__restrict__ bk, int i0,
+                                              int n0, const double *u, const uint8_t *__restrict__ mask,
+                                              int64_t r, const double *__restrict__ dv,
+                                              const int32_t *__restrict__ didx, const double *xi, double &s0,
+                                              double &s1, double &s2, double &s3, int p = P) {
+  s0 = s1 = s2 = s3 = 0.0;
+  if (P >= 0) {
+#pragma unroll
+    for (int k = 0; k <= 2 * (P < 0 ? 0 : P); ++k) {
+      const int jj = i0 - P + k;
+      if (jj < 0 || jj >= n0) continue;
+      const int64_t q = r + (k - P);
+      const double uq = u[jj];
+      const double x0 = mask[q] ? uq : (dv ? dv[didx[q]] : xi[q]);
+      s0 = fma(bm[k], x0, s0);
+      s1 = fma(bk[k], x0, s1);
+      s2 = fma(bm[k], uq, s2);
+      s3 = fma(bk[k], uq, s3);
+    }
+  } else {
+    const int j0 = i0 - p < 0 ? 0 : i0 - p, j1 = i0 + p > n0 - 1 ? n0 - 1 : i0 + p;
+    for (int jj = j0; jj <= j1; ++jj) {
+      const int64_t q = r + (jj - i0);
+      const double uq = u[jj];
+      const double x0 = mask[q] ? uq : (dv ? dv[didx[q]] : xi[q]);
+      s0 = fma(bm[jj - i0 + p], x0, s0);
+      s1 = fma(bk[jj - i0 + p], x0, s1);
+      s2 = fma(bm[jj - i0 + p], uq, s2);
+      s3 = fma(bk[jj - i0 + p], uq, s3);
+    }
+  }
 }
 
 // x-rows as in k_kron_zx: the box part of each row's t fiber into LDS, then
@@ -968,6 +1036,7 @@ __global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, 
       if (k0 >= 0 && k0 < m0 && k1 >= 0 && k1 < m1 && k2 >= 0 && k2 < f.m[2]) {
         const double *tr = tf + j * m0;
         double s = 0.0;
+        #pragma unroll 8
         for (int jj = 0; jj < m0; ++jj) s = fma(f.U0T[jj * m0 + k0], tr[jj], s);
         xv += s;
         f.x[r] = xv;
@@ -985,18 +1054,14 @@ __global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, 
     if (row >= nrows) continue;
     const int64_t r = row * n0 + i0;
     const double *bm = a.op.Mb[0] + (int64_t)i0 * (2 * p + 1), *bk = a.op.Kb[0] + (int64_t)i0 * (2 * p + 1);
-    const int j0 = i0 - p < 0 ? 0 : i0 - p, j1 = i0 + p > n0 - 1 ? n0 - 1 : i0 + p;
-    double s0 = 0.0, s1 = 0.0;
-    for (int jj = j0; jj <= j1; ++jj) {
-      const int64_t q = r + (jj - i0);
-      const double uq = u[j * n0 + jj];
-      const double x0 = a.mask[q] ? uq : (dv ? dv[a.didx[q]] : xi[q]);
-      s0 = fma(bm[jj - i0 + p], x0, s0);
-      s1 = fma(bk[jj - i0 + p], x0, s1);
+    double s0, s1, s2, s3;
+    switch (p) {
+      case 1: xrow_products<1>(bm, bk, i0, n0, u + j * n0, a.mask, r, dv, a.didx, xi, s0, s1, s2, s3); break;
+      case 2: xrow_products<2>(bm, bk, i0, n0, u + j * n0, a.mask, r, dv, a.didx, xi, s0, s1, s2, s3); break;
+      case 3: xrow_products<3>(bm, bk, i0, n0, u + j * n0, a.mask, r, dv, a.didx, xi, s0, s1, s2, s3); break;
+      case 4: xrow_products<4>(bm, bk, i0, n0, u + j * n0, a.mask, r, dv, a.didx, xi, s0, s1, s2, s3); break;
+      default: xrow_products<-1>(bm, bk, i0, n0, u + j * n0, a.mask, r, dv, a.didx, xi, s0, s1, s2, s3, p);
     }
-    double s2 = 0.0, s3 = 0.0;
-    for (int jj = j0; jj <= j1; ++jj) s2 = fma(bm[jj - i0 + p], u[j * n0 + jj], s2);
-    for (int jj = j0; jj <= j1; ++jj) s3 = fma(bk[jj - i0 + p], u[j * n0 + jj], s3);
     t[r] = s0;
     t[N + r] = s1;
     t[2 * N + r] = s2;
