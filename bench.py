@@ -364,7 +364,7 @@ def main():
         "steps_per_s": steps / r["seconds"],
         "roofline": dict(roof, traffic=_k_sum_traffic(main_form),
                          traffic_unit="HBM bytes per step of the sum kernels (read + written)",
-                         kernel="k_sum_tensor (far chunks FP32, near chunks FP64, one launch)",
+                         kernel="k_sum_tensor (far chunks FP32, near chunks FP64; one launch per block of up to 8 steps)",
                          avg_ms_per_step=sum_ms / steps, launches_per_step=launches / steps,
                          pairs_per_step=st["pairs"] / steps),
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
