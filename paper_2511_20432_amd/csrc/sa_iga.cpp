@@ -1589,11 +1589,11 @@ void build_tensor_faces(sa_iga *h) {
     h->tens.max_groups_batch = (gb ? std::max(0, std::atoi(gb)) : 8) * prop.multiProcessorCount;
     // a blocked call's sum: one workgroup per work item (they retire often,
     // so the solver kernels beside the sum get compute units), with LDS
-    // padding that leaves two per compute unit
+    // padding that leaves three per compute unit and room for a solver block
     const char *bg = std::getenv("SA_IGA_BLOCK_SUM_GROUPS_PER_CU");
     const char *pad = std::getenv("SA_IGA_BLOCK_SUM_LDS_PAD");
     h->blk_groups = (int)((bg ? std::max(0.0, std::atof(bg)) : 0.0) * prop.multiProcessorCount);
-    h->blk_pad = pad ? std::max(0, std::min(96 * 1024, std::atoi(pad))) : 36000;
+    h->blk_pad = pad ? std::max(0, std::min(96 * 1024, std::atoi(pad))) : 24000;
     if (h->blk_pad > 0 && !sa::sum_tensor_prepare(h->blk_pad)) h->blk_pad = 0;
     h->tens.lds_pad = 0;
   }

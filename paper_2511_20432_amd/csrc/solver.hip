@@ -31,6 +31,11 @@ namespace {
 
 constexpr int kB = 256;
 
+// The theta-step kernels form a chain of short dependent launches that runs
+// beside the long kernel sum; their waves take the SIMD's issue slots first
+// (wave priority), so the chain is not stretched by the sum's instructions.
+__device__ __forceinline__ void issue_first() { __builtin_amdgcn_s_setprio(3); }
+
 __device__ __forceinline__ double wsum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
@@ -434,6 +439,7 @@ __device__ __forceinline__ void band_dot_init(const double *__restrict__ Mb, con
 
 template <bool THETA>
 __global__ void k_kron_x(SlotMap sm, KronArgs a) {
+  issue_first();
   const int64_t pth = sm.path[blockIdx.y];
   if (!THETA && a.sc && a.sc[pth].done) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -468,6 +474,7 @@ __global__ void k_kron_x(SlotMap sm, KronArgs a) {
 
 template <bool THETA>
 __global__ void k_kron_y(SlotMap sm, KronArgs a) {
+  issue_first();
   const int64_t pth = sm.path[blockIdx.y];
   if (!THETA && a.sc && a.sc[pth].done) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -506,6 +513,7 @@ __global__ void k_kron_y(SlotMap sm, KronArgs a) {
 
 template <bool THETA>
 __global__ __launch_bounds__(kB) void k_kron_z(SlotMap sm, KronArgs a) {
+  issue_first();
   const int64_t pth = sm.path[blockIdx.y];
   if (!THETA && a.sc && a.sc[pth].done) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -661,6 +669,7 @@ __device__ __forceinline__ int64_t full_index(const FusedPcg &f, int j0, int j1,
 constexpr int kFib = 64;
 
 __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k, int first) {
+  issue_first();
   __shared__ double fib[256];
   __shared__ double sh[16];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
@@ -719,6 +728,7 @@ __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k
 }
 
 __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
+  issue_first();
   extern __shared__ double lds[];
   __shared__ double sh[16];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
@@ -777,6 +787,7 @@ __global__ void k_fd_plane(SlotMap sm, FusedPcg f0) {
 }
 
 __global__ __launch_bounds__(kFib) void k_fd_xbwd(SlotMap sm, FusedPcg f0, int slot, int first) {
+  issue_first();
   __shared__ double fib[256];
   __shared__ double sh[16];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
@@ -869,6 +880,7 @@ constexpr int kZxThreads = 320;
 constexpr int kZxMaxRow = 640;
 
 __global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, FusedPcg f0) {
+  issue_first();
   __shared__ double fib[kZxMaxRow];
   __shared__ double sh[16];
   const int64_t pth = sm.path[blockIdx.y];
@@ -1003,6 +1015,7 @@ __device__ __forceinline__ void xrow_products(const double *__restrict__ bm, con
 // the band products along x of step n+1's first iterate (u^{n+1} on the free
 // DOFs, its Dirichlet values elsewhere) and of u^{n+1}
 __global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, KronArgs a) {
+  issue_first();
   __shared__ double tf[kZxMaxRow];
   __shared__ double u[kZxMaxRow];
   const int64_t pth = sm.path[blockIdx.y];
