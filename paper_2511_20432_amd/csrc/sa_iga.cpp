@@ -1091,7 +1091,7 @@ void step_block(sa_iga *h, const std::vector<int> &pids, int K) {
     // F^{n+1..n+K} (Eq. 18) and the projection right-hand sides (Eq. 11)
     StageScope s(h, SA_STAGE_LOAD, as);
     if (h->nD > 0)
-      sa::launch_gather_rows2(as, si, h->grows, h->bF[sb], nd, h->drows, h->bbD, nDa, h->bLD, st, true);
+      sa::launch_gather_rows2(as, si, h->grows, h->bF[sb], nd, h->drows, h->bbD, nDa, h->bLD, st);
     else
       sa::launch_gather_rows(as, si, h->grows, h->bLD, st, h->bF[sb], nd, 0, nullptr, nullptr);
   }

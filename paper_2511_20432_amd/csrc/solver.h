@@ -34,11 +34,9 @@ struct GatherRows {
 void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, const double *ld, int64_t ls,
                         double *F, int64_t fs, int64_t ncopy, const double *v, double *x);
 
-// two gathers of the same densities in one launch: F1 from g1, F2 from g2;
-// all_slots: each block takes every slot in turn (one read of the matrices)
+// two gathers of the same densities in one launch: F1 from g1, F2 from g2
 void launch_gather_rows2(hipStream_t st, const SlotMap &sm, const GatherRows &g1, double *F1, int64_t fs1,
-                         const GatherRows &g2, double *F2, int64_t fs2, const double *ld, int64_t ls,
-                         bool all_slots = false);
+                         const GatherRows &g2, double *F2, int64_t fs2, const double *ld, int64_t ls);
 
 // per slot (path p): x[p*n + i] = v[p*n + i] for the free DOFs i (mask[i] != 0);
 // the entries of the Dirichlet DOFs of x are left as they are

@@ -92,38 +92,32 @@ __global__ void k_gather_rows(SlotMap sm, int64_t nrows, const int32_t *__restri
 
 // two gathers of the same densities in one launch: the first blocks1 blocks
 // take g1 -> F1, the rest g2 -> F2
-// slot blockIdx.y, or (all_slots) every slot in turn, so that the rows'
-// matrix entries come from HBM once and from the caches for the other slots
 __global__ void k_gather_rows2(SlotMap sm, int64_t blocks1, GatherRows g1, double *__restrict__ F1b, int64_t fs1,
                                GatherRows g2, double *__restrict__ F2b, int64_t fs2,
-                               const double *__restrict__ ldb, int64_t ls, int all_slots) {
+                               const double *__restrict__ ldb, int64_t ls) {
+  const int64_t pth = sm.path[blockIdx.y];
+  const double *ld = ldb + pth * ls;
   const bool second = (int64_t)blockIdx.x >= blocks1;
   const GatherRows &g = second ? g2 : g1;
+  double *F = second ? F2b + pth * fs2 : F1b + pth * fs1;
   const int64_t gt = ((int64_t)blockIdx.x - (second ? blocks1 : 0)) * blockDim.x + threadIdx.x;
   const int sub = threadIdx.x & 15;
   const int64_t r = gt >> 4;
-  const int s0 = all_slots ? 0 : (int)blockIdx.y, s1 = all_slots ? sm.count : s0 + 1;
-  for (int slot = s0; slot < s1; ++slot) {
-    const int64_t pth = sm.path[slot];
-    const double *ld = ldb + pth * ls;
-    double *F = second ? F2b + pth * fs2 : F1b + pth * fs1;
-    double s = 0.0;
-    if (r < g.nrows) {
-      for (int64_t e = g.rowptr[r] + sub; e < g.rowptr[r + 1]; e += 16) s = fma(g.val[e], ld[g.col[e]], s);
-    }
-    for (int off = 8; off > 0; off >>= 1) s += __shfl_down(s, off, 16);
-    if (r < g.nrows && sub == 0) F[g.rows[r]] = s;
+  double s = 0.0;
+  if (r < g.nrows) {
+    for (int64_t e = g.rowptr[r] + sub; e < g.rowptr[r + 1]; e += 16) s = fma(g.val[e], ld[g.col[e]], s);
   }
+  for (int off = 8; off > 0; off >>= 1) s += __shfl_down(s, off, 16);
+  if (r < g.nrows && sub == 0) F[g.rows[r]] = s;
 }
 
 void launch_gather_rows2(hipStream_t st, const SlotMap &sm, const GatherRows &g1, double *F1, int64_t fs1,
-                         const GatherRows &g2, double *F2, int64_t fs2, const double *ld, int64_t ls,
-                         bool all_slots) {
+                         const GatherRows &g2, double *F2, int64_t fs2, const double *ld, int64_t ls) {
   if (sm.count <= 0) return;
   const int64_t b1 = std::max<int64_t>(1, (g1.nrows * 16 + kB - 1) / kB);
   const int64_t b2 = std::max<int64_t>(1, (g2.nrows * 16 + kB - 1) / kB);
-  hipLaunchKernelGGL(k_gather_rows2, dim3((unsigned)(b1 + b2), all_slots ? 1u : (unsigned)sm.count), dim3(kB), 0, st,
-                     sm, b1, g1, F1, fs1, g2, F2, fs2, ld, ls, all_slots ? 1 : 0);
+  hipLaunchKernelGGL(k_gather_rows2, dim3((unsigned)(b1 + b2), (unsigned)sm.count), dim3(kB), 0, st, sm, b1, g1, F1,
+                     fs1, g2, F2, fs2, ld, ls);
 }
 
 void launch_gather_rows(hipStream_t st, const SlotMap &sm, const GatherRows &g, const double *ld, int64_t ls,
