@@ -205,7 +205,10 @@ int sa_iga_setup(const sa_patch *patch, const sa_material *mat, const sa_scan_pa
  * vector and Dirichlet data) runs on two internal streams, one step ahead of
  * the theta-step solves on the object's stream; the results are bitwise those
  * of the serial order (environment variable SA_IGA_SERIAL at set-up selects
- * that order).  Where the fast-diagonalisation solve is exact (an affine
+ * that order).  A call that advances one path (or up to four at one step
+ * parity) on the matrix-core sum runs in blocks of sa_info.blocked_steps
+ * steps, whose sums, load vectors and Dirichlet data go through one launch
+ * each; the results are bitwise those of one step at a time.  Where the fast-diagonalisation solve is exact (an affine
  * axis-aligned block with the FD preconditioner) a theta-step is one
  * application of it, u^{n+1} = x0 + P r0; its residual against the tolerance
  * is formed by the next step's right-hand side passes or, for a path's last

@@ -73,3 +73,30 @@ def test_blocked_two_paths_equal_serial_bitwise(monkeypatch):
     ser.step(30)
     blk.step(30)
     _equal(ser, blk, [0, 1])
+
+
+def test_blocked_without_dirichlet_faces(monkeypatch):
+    """No Dirichlet face (the bottom face Neumann as well): the blocked
+    schedule without Dirichlet data matches the serial order bitwise and the
+    oracle to 1e-9."""
+    from oracle import solver
+    roles = (W.FACE_NEUMANN,) * 5 + (W.FACE_SOURCE_PLANE,)
+    patch = W.small_block(roles=roles)
+    scan = W.make_scan([_track(3)], 1e-5, 5, n_steps=[19])
+    monkeypatch.setenv("SA_IGA_SERIAL", "1")
+    ser = _model(patch, scan)
+    monkeypatch.delenv("SA_IGA_SERIAL")
+    blk = _model(patch, scan)
+    assert blk.info.n_dirichlet == 0 and blk.info.blocked_steps == 8
+    for k in (7, 12):
+        ser.step(k)
+        blk.step(k)
+    _equal(ser, blk, [0])
+    om = solver.Model(patch, W.MAT_CFG, scan)
+    om.advance(19)
+    T, G, F, du = blk.boundary_fields()
+    Tr, Gr = om.boundary_field(19)
+    for a, b in ((T, Tr), (G, Gr), (F, om.F), (du, om.w)):
+        b = np.asarray(b)
+        err = float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+        assert err <= 1e-9, err
