@@ -865,6 +865,13 @@ __global__ void k_pcg_dir(SlotMap sm, FusedPcg f0, int k, int last) {
   }
 }
 
+// one thread per plane entry (up to 1024): each transform is one dot product per thread
+unsigned plane_threads(const int m[3]) {
+  const int64_t P = (int64_t)m[1] * m[2];
+  const int64_t t = (P + 63) / 64 * 64;
+  return (unsigned)(t > 1024 ? 1024 : (t < 64 ? 64 : t));
+}
+
 bool fused_fits(const int m[3]) { return m[0] <= 256 && (int64_t)m[1] * m[2] <= 4096; }
 
 size_t fd_plane_lds(const int m[3]) {
@@ -967,7 +974,8 @@ void launch_theta_checked_rhs(hipStream_t st, const SlotMap &sm, const KronArgs 
 
 void launch_theta_checked_solve(hipStream_t st, const SlotMap &sm, const FusedPcg &f, bool with_xbwd) {
   if (sm.count <= 0) return;
-  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(kB), fd_plane_lds(f.m), st, sm, f);
+  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(plane_threads(f.m)),
+                     fd_plane_lds(f.m), st, sm, f);
   const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
   if (with_xbwd) hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, 0, 1);
 }
@@ -1094,7 +1102,8 @@ void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k,
   if (sm.count <= 0) return;
   const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
   hipLaunchKernelGGL(k_fd_xfwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, k, update ? 0 : 1);
-  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(kB), fd_plane_lds(f.m), st, sm, f);
+  hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(plane_threads(f.m)),
+                     fd_plane_lds(f.m), st, sm, f);
   const int slot = first ? 0 : ((k + 1) & 1);
   hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, slot, first ? 1 : 0);
 }
