@@ -308,8 +308,8 @@ def main():
         print("copied 5 x 256 MiB", flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's sharding plan is "
-              "described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): the path is not sharded over several GPUs",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "no GPU"
