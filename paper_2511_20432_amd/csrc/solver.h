@@ -89,8 +89,8 @@ void launch_stencil_sl(hipStream_t st, const SlotMap &sm, const SlArgs &a, int h
 //   K_0-term = M2 x M1 x K0, K_1-term = M2 x K1 x M0, K_2-term = K2 x M1 x M0
 // with banded 1-D factors (band[d][i][k] = factor[i][i - p_d + k]).  Applied in
 // three passes (x, y, z), each a banded product along one axis, through the
-// scratch t (8 vectors per path).  Same outputs and partials as
-// launch_stencil_sl (theta: r = B v + theta F1 + (1-theta) F0 - A x on the
+// scratch t (8 vectors per path, 10 with the residual check).  Same outputs
+// and partials as launch_stencil_sl (theta: r = B v + theta F1 + (1-theta) F0 - A x on the
 // free rows, partial sums of rhs^2; apply: q = A p, partial sums of p.q; one
 // partial per 64 rows).
 struct KronOp {
@@ -105,7 +105,7 @@ struct KronArgs {
   const uint8_t *mask;
   const double *x, *v, *F1, *F0;
   double theta;
-  double *t;  int64_t ts; // scratch, stride per path (>= 8 nrow)
+  double *t;  int64_t ts; // scratch, stride per path (>= 8 nrow; 10 nrow with check)
   double *out, *part;
   const PcgScalars *sc;   // apply: skip when done
   PcgScalars *sc_w;       // theta: resets the done flags

@@ -665,7 +665,10 @@ __device__ __forceinline__ int64_t full_index(const FusedPcg &f, int j0, int j1,
 //               t[:, k1, k2] = U0^T r[:, k1, k2]
 //   k_fd_plane  block = plane j0: modes 1 and 2, eigenvalue scaling, back
 //   k_fd_xbwd   block = x-fiber: z = U0 t, partial r.z, p = z on the first pass
-// t is stored plane-major: t[j0 * (m1 m2) + k2 * m1 + k1].
+//               (checked update: x += z)
+// t is stored plane-major: t[j0 * (m1 m2) + k2 * m1 + k1].  The checked
+// update uses k_kron_zx in place of k_fd_xfwd and, inside a block of steps,
+// k_xbwd_x in place of k_fd_xbwd (both further below).
 constexpr int kFib = 64;
 
 __global__ __launch_bounds__(kFib) void k_fd_xfwd(SlotMap sm, FusedPcg f0, int k, int first) {
