@@ -50,11 +50,12 @@ FLOPS_PER_PAIR = 8
 K_SUM_TRAFFIC = {"read_bytes": 1.37e6, "written_bytes": 35.89e6}
 
 
-def _k_sum_traffic(form):
+def _k_sum_traffic(form, steps_per_launch=1.0):
+    """HBM bytes (read + written) of one k_sum_tensor launch, or None."""
     t = K_SUM_TRAFFIC
     if not t or form != "fp32far":
         return None
-    return t["read_bytes"] + t["written_bytes"]
+    return (t["read_bytes"] + t["written_bytes"]) * steps_per_launch
 
 
 def _sum_roofline(st, sum_ms):
@@ -362,8 +363,9 @@ def main():
                    "form": main_form, "tau_near_s": 2e-4, "theta": 0.5, "pcg_rtol": 1e-13,
                    "preconditioner": "fast diagonalisation"},
         "steps_per_s": steps / r["seconds"],
-        "roofline": dict(roof, traffic=_k_sum_traffic(main_form),
-                         traffic_unit="HBM bytes per step of the sum kernels (read + written)",
+        "roofline": dict(roof, traffic=_k_sum_traffic(main_form, steps / max(1, launches)),
+                         traffic_unit="HBM bytes per k_sum_tensor launch (read + written)",
+                         traffic_per_step=_k_sum_traffic(main_form),
                          kernel="k_sum_tensor (far chunks FP32, near chunks FP64; one launch per block of up to 8 steps)",
                          avg_ms_per_step=sum_ms / steps, launches_per_step=launches / steps,
                          pairs_per_step=st["pairs"] / steps),
