@@ -22,7 +22,8 @@
  * their previous state unless stated otherwise.  No C++ exception crosses
  * this boundary.
  *
- * Conventions fixed by this interface (shared with the CPU reference):
+ * Conventions fixed by this interface (the FP64 oracle used by the tests
+ * follows the same ones):
  *   - Units are SI (m, s, W, J, K).
  *   - Parametric faces f = 0..5 are xi0=0, xi0=1, xi1=0, xi1=1, xi2=0, xi2=1.
  *   - DOF (control point) index A = a0 + n0*(a1 + n1*a2).

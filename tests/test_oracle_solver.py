@@ -139,3 +139,51 @@ def test_converges_to_image_lattice_solution():
         errs.append(np.abs((uh - MAT.T0) - ex).max() / np.abs(ex).max())
     assert errs[2] < 0.6 * errs[1] < 0.6 * 0.6 * errs[0]
     assert errs[2] < 0.05
+
+
+def _affine_and_random_cases():
+    return [
+        ("block", W.block_patch((0, 0, 0), (0.5e-3, 0.4e-3, 0.3e-3), (3, 2, 2), 2)),
+        ("annulus", W.annulus_patch(2e-3, 4e-3, 1e-3, n_el=(5, 3, 2), degree=2)),
+        ("e1", W.e1_patch()),
+    ]
+
+
+@pytest.mark.parametrize("name,patch", _affine_and_random_cases(), ids=lambda v: v if isinstance(v, str) else "")
+def test_evaluate_reproduces_affine_fields(name, patch):
+    """NURBS reproduce affine functions of the geometry (sum_A R_A = 1 and
+    sum_A R_A P_A = x(xi)), so control values u_A = T_c + a.P_A + b give
+    T^ = T_c + a.x(xi) + b and grad T^ = a exactly (Eq. 21 with the
+    isoparametric gradients of Eq. 14).  A transposed or wrong J^{-1} fails
+    on the curved patches, whose Jacobian is not symmetric."""
+    m = solver.Model(patch, MAT, _empty_scan(1), assemble=False)
+    a = np.array([3.0e4, -1.7e4, 2.2e4])
+    b = 4.5
+    P = patch.ctrl[..., :3].reshape(-1, 3)
+    u = MAT.T0 + P @ a + b
+    xi = np.random.default_rng(11).random((60, 3))
+    uh, gx, x = m.evaluate(xi, u=u, correction_only=True)
+    scale = np.abs(P @ a).max() + b
+    np.testing.assert_allclose(uh - MAT.T0, x @ a + b, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(gx, np.broadcast_to(a, gx.shape), rtol=0, atol=1e-9 * np.abs(a).max())
+
+
+@pytest.mark.parametrize("name,patch", _affine_and_random_cases(), ids=lambda v: v if isinstance(v, str) else "")
+def test_evaluate_gradient_matches_physical_differences(name, patch):
+    """For random control values the physical gradient returned by evaluate
+    predicts the change of T^ between two nearby points from their physical
+    offset: grad T^ . (x(xi + h e_j) - x(xi - h e_j)) = T^(xi + h e_j) -
+    T^(xi - h e_j) + O(h^3), for each parametric direction j.  The offsets
+    come from the geometry map alone, not from the Jacobian."""
+    m = solver.Model(patch, MAT, _empty_scan(1), assemble=False)
+    u = MAT.T0 + np.random.default_rng(12).normal(size=patch.n_dof)
+    xi = 0.05 + 0.9 * np.random.default_rng(13).random((40, 3))
+    _, gx, _ = m.evaluate(xi, u=u, correction_only=True)
+    h = 1e-6
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        up, _, xp = m.evaluate(xi + e, u=u, correction_only=True)
+        um, _, xm = m.evaluate(xi - e, u=u, correction_only=True)
+        pred = np.einsum("qi,qi->q", gx, xp - xm)
+        np.testing.assert_allclose(pred, up - um, rtol=0, atol=1e-7 * np.abs(up - um).max() + 1e-12)
