@@ -1,17 +1,27 @@
 """Benchmark of the semi-analytical IGA hot path on one MI355X.
 
-A step is one theta-step of the whole path: source coefficients, kernel sum
-at every boundary quadrature point (T~ and grad T~), flux and Dirichlet
-densities, load-vector and projection gathers, Dirichlet projection solve,
-theta-scheme right-hand side and PCG solve.
+A step is one theta-step of the whole path for every scan strategy of the
+workload: kernel sum at every boundary quadrature point (T~ and grad T~,
+Eqs. 7-8), flux and Dirichlet densities, load-vector and projection gathers
+(Eqs. 10-11, 18), Dirichlet projection, theta-scheme right-hand side and
+solve (Eq. 20).
 
-Workload: the raster scan on the 4 x 2 x 1 mm cubic B-spline block
-(64 x 32 x 16 elements, 64,512 boundary points, 10 boustrophedon tracks,
-80 W, 1 m/s, 5 sources per 10 us step).  Both forms run over the same steps:
-the FP64 form and the FP32 far-field form (sources older than 0.2 ms in
-FP32).  `value` is the source x point pair rate of the FP32 far-field form
-with inputs resident in HBM; the FP64 form, the step rates, the speedup and
-the temperature difference between the forms are reported beside it.
+Headline (`value`, `ms_per_step`): the learned far-history form with its
+audits ("mixed+surrogate") on the held-out batch: 128 scan strategies
+(seed 1) on the 4 x 2 x 1 mm cubic block (64 x 32 x 16 elements, 64,512
+boundary points), every strategy started at a seeded mid-scan step with a
+zeroed state, `--warmup` untimed and `--steps` timed batched steps.  The
+FP64 form runs the same window; `speedup_vs_fp64` and `max_err_K_vs_fp64`
+compare the two.  `value` counts every switched-on source x boundary point
+pair of the timed steps, whether summed or replaced by the network.
+
+Beside it: the seed-0 batch in the FP32 far-field and FP64 forms (same
+window rules), the raster scan (one path, all 3,788 steps) in both forms,
+the quarter annulus (one path, mid-scan window) in both forms with the
+pair-by-pair kernel's rate against its VALU roofline, and the small block
+(all 150 steps).  `cpu_baseline` is the FP64 oracle's kernel sum on sampled
+slots of the headline window, on every host core of the process's CPU share
+and on one core.
 
 Prints one JSON line.
 """
@@ -39,23 +49,29 @@ METRIC = "source×point pairs/s + θ-steps/s; mixed+surrogate vs FP64 GPU at ≤
 MFMA_FP32 = 157.3e12
 MFMA_FP64 = 78.6e12
 FLOPS_PER_PAIR = 8
-# HBM bytes per step of the sum kernel (k_sum_tensor: far and near items of
-# eight steps per launch) of this workload's FP32 far-field form, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE over the profiled run, scaled by the same
-# counters on a 256 MiB copy (bench.py --copy-calibration), divided by the
-# steps per launch (profiles/k_sum_tensor_raster_fp32far.md).  Valid for the
-# kernels as profiled; a changed sum kernel must set this to None until the
-# counters are taken again.  The written bytes are the FP64 chunk partials
-# (5 x 8 B per point and chunk) that k_finalize reads.
-K_SUM_TRAFFIC = {"read_bytes": 1.37e6, "written_bytes": 35.89e6}
+# The pair-by-pair kernel (curved faces) is bound by VALU issue: 256 compute
+# units x 64 lanes x 2.4 GHz lane-operations per second; an FP32 far pair
+# takes 9 VALU operations and one v_exp_f32 at a quarter of the VALU rate
+# (4 issue slots), an FP64 near pair about 28 FP64 operations (the exponent
+# chain and the Cody-Waite exponential), at the full FP64 vector rate.
+LANE_OPS = 256 * 64 * 2.4e9
+SLOTS_FP32_PAIR = 13
+SLOTS_FP64_PAIR = 28
+# HBM bytes per k_sum_tensor launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by the same counters on a 256 MiB copy (bench.py --copy-calibration),
+# per batched step of the headline window.  None until the counters are taken
+# on the kernel as it now is.
+K_SUM_TRAFFIC = None
+
+WINDOW_START = "each strategy at a seeded step in [0, L - warmup - steps) with a zeroed state (u = T_c, F = 0)"
 
 
-def _k_sum_traffic(form, steps_per_launch=1.0):
+def _k_sum_traffic(launches_per_step=1.0):
     """HBM bytes (read + written) of one k_sum_tensor launch, or None."""
     t = K_SUM_TRAFFIC
-    if not t or form != "fp32far":
+    if not t:
         return None
-    return (t["read_bytes"] + t["written_bytes"]) * steps_per_launch
+    return (t["read_bytes"] + t["written_bytes"]) / launches_per_step
 
 
 def _sum_roofline(st, sum_ms):
@@ -72,69 +88,23 @@ def _sum_roofline(st, sum_ms):
             "frac": t_peak / t}
 
 
-def _timed_run(model, warmup, steps, n_total):
-    """Advance warmup steps, then time `steps` theta-steps.  Reaching the end
-    of the scan restores the initial state (a checkpoint taken at step 0)."""
-    import torch
-    initial = model.save()
-    done = 0
-
-    def advance(n):
-        nonlocal done
-        while n > 0:
-            left = n_total - (done % n_total) if n_total > 0 else n
-            k = min(n, left)
-            model.step(k)
-            done += k
-            n -= k
-            if n_total > 0 and done % n_total == 0:
-                model.load(initial)
-
-    advance(warmup)
-    model.reset_stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    advance(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dt, model.stats()
-
-
-def run_form(w, precision, warmup, steps, tile=None):
-    """The timed steps run twice from the same state: without per-stage
-    events (the throughput) and with them (the stage times and the kernel-sum
-    launch durations of the roofline)."""
-    from paper_2511_20432_amd import sa_iga
-    from paper_2511_20432_amd import workloads as W
-    opts = W.Options(precision=precision, tau_near=2e-4)
-    t0 = time.perf_counter()
-    shape = {} if tile is None else {"points_per_lane": tile[0], "waves_per_group": tile[1]}
-    m = sa_iga.Model(w.patch, w.material, w.scan, opts, timing=0, **shape)
-    setup_s = time.perf_counter() - t0
-    tune = m.autotune(reps=16) if tile is None else {"points_per_lane": tile[0], "waves_per_group": tile[1],
-                                                      "ms_per_step": None, "fixed": True}
-    n_total = int(w.scan.n_steps[0])
-    initial = m.save()
-    dt, st = _timed_run(m, warmup, steps, n_total)
-    final = m.save()
-    m.load(initial)
-    m.set_timing(True)
-    dt_ev, st_ev = _timed_run(m, warmup, steps, n_total)
-    m.set_timing(False)
-    st["stage_ms"] = st_ev["stage_ms"]
-    st["stage_launches"] = st_ev["stage_launches"]
-    st["seconds_with_events"] = dt_ev
-    st["autotune"] = tune
-    m.load(final)
-    return m, dt, st, setup_s
+def _valu_roofline(st, sum_ms):
+    """VALU roofline of the pair-by-pair sum: pairs per second against the
+    issue-slot peak of the mix of FP32 far and FP64 near pairs."""
+    pairs, near = st["pairs"], st["pairs_near"]
+    t_peak = ((pairs - near) * SLOTS_FP32_PAIR + near * SLOTS_FP64_PAIR) / LANE_OPS
+    if sum_ms <= 0 or pairs <= 0:
+        return {"bound": "alu", "achieved": None, "peak": None, "unit": "pairs/s", "frac": None}
+    t = sum_ms * 1e-3
+    return {"bound": "alu", "achieved": pairs / t, "peak": pairs / t_peak, "unit": "pairs/s", "frac": t_peak / t}
 
 
 def jump_to_steps(model, steps):
     """Put path p at step steps[p] with a zeroed state (u = T_c, F = 0, no
-    source field yet): the steps timed from there do the full work of a
+    source field yet): the steps run from there do the full work of a
     mid-scan step (every switched-on source of every path is summed).  Uses
-    the checkpoint layout: a 32-byte header, then per path its step (int64)
-    followed by its arrays."""
+    the checkpoint layout: a 32-byte header, then per path its step (int64),
+    its audit state (two int64) and its arrays."""
     blob = bytearray(model.save())
     per = (len(blob) - 32) // len(steps)
     for p, st in enumerate(steps):
@@ -143,61 +113,71 @@ def jump_to_steps(model, steps):
     model.load(bytes(blob))
 
 
-def _batched_window(w, precision, window, start, **kw):
-    """Time `window` steps of every strategy of w from the given start steps."""
+def _start_steps(w, span, seed):
+    L = w.scan.n_steps.astype(np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    return (rng.random(len(L)) * np.maximum(L - span, 0)).astype(np.int64)
+
+
+def _timed(model, n):
     import torch
+    model.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model.step(n)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, model.stats()
+
+
+def _window(w, precision, start, warmup, steps, tune=True, **kw):
+    """A model of w at the given start steps (zeroed state), tuned, advanced
+    `warmup` untimed steps; then `steps` steps timed twice from the same
+    state: without per-stage events (the throughput) and with them (stage
+    times and kernel-sum launch durations).  The model is left after the
+    timed steps."""
     from paper_2511_20432_amd import sa_iga
     from paper_2511_20432_amd import workloads as W
     t0 = time.perf_counter()
-    m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=precision, tau_near=2e-4), timing=1, **kw)
+    m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=precision, tau_near=2e-4), timing=0, **kw)
     setup_s = time.perf_counter() - t0
-    jump_to_steps(m, start)
-    tune = m.autotune(reps=2)
-    m.reset_stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    m.step(window)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = m.stats()
-    return m, dt, st, tune, setup_s
+    if start is not None:
+        jump_to_steps(m, start)
+    tuned = m.autotune(reps=2) if tune else None
+    if warmup > 0:
+        m.step(warmup)
+    ck = m.save()
+    dt, st = _timed(m, steps)
+    final = m.save()
+    m.load(ck)
+    m.set_timing(True)
+    dt_ev, st_ev = _timed(m, steps)
+    m.set_timing(False)
+    m.load(final)
+    st["stage_ms"] = st_ev["stage_ms"]
+    st["stage_launches"] = st_ev["stage_launches"]
+    st["seconds_with_events"] = dt_ev
+    st["autotune"] = tuned
+    st["setup_s"] = setup_s
+    return m, dt, st
 
 
-def _window_report(w, form, window, dt, st, tune, setup_s, seed):
+def _report(st, dt, steps):
     sum_ms = st["stage_ms"]["sum"]
+    covered = st["pairs"] + st["pairs_net"]
     return {
-        "workload": f"{w.scan.n_paths} strategies on the raster block (64x32x16 cubic, 64512 boundary points), "
-                    f"lengths U[500,4000] steps (sum {int(w.scan.n_steps.sum())}), {len(w.scan.tick)} sources, "
-                    f"seed {seed}",
-        "form": form, "window_steps": window,
-        "start": "each strategy at a seeded step in [0, L - window) with a zeroed state; full work per step",
-        "pairs_per_s": st["pairs"] / dt, "path_steps_per_s": st["steps"] / dt,
-        "ms_per_batched_step": 1e3 * dt / window, "path_steps": st["steps"],
+        "pairs_per_s": covered / dt, "pairs_summed_per_s": st["pairs"] / dt,
+        "path_steps_per_s": st["steps"] / dt, "ms_per_step": 1e3 * dt / steps,
+        "pairs_per_step": covered / steps, "path_steps": st["steps"],
         "sum_gpair_s": st["pairs"] / (sum_ms * 1e-3) / 1e9 if sum_ms > 0 else None,
-        "stage_ms_per_batched_step": {k: v / window for k, v in st["stage_ms"].items()},
-        "rollbacks": st["rollbacks"],
-        "autotune": tune, "setup_s": setup_s,
+        "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
+        "ms_per_step_with_stage_events": 1e3 * st["seconds_with_events"] / steps,
+        "rollbacks": st["rollbacks"], "autotune": st["autotune"], "setup_s": st["setup_s"],
     }
 
 
-def _start_steps(w, window, seed):
-    L = w.scan.n_steps.astype(np.int64)
-    rng = np.random.Generator(np.random.PCG64(seed + 7))
-    return (rng.random(len(L)) * np.maximum(L - window, 0)).astype(np.int64)
-
-
-def run_batched(window, form, seed=0):
-    """The batch of 128 scan strategies on the raster block: every strategy
-    starts the timed window at a seeded step in [0, L - window)."""
-    from paper_2511_20432_amd import workloads as W
-    w = W.cfg4(seed=seed)
-    prec = {"fp32far": W.PRECISION_FP32_FAR, "fp64": W.PRECISION_FP64}[form]
-    m, dt, st, tune, setup_s = _batched_window(w, prec, window, _start_steps(w, window, seed))
-    return _window_report(w, form, window, dt, st, tune, setup_s, seed)
-
-
 def _max_err(a, b):
-    """Bound of max |T - T_ref| at the boundary points over all paths (R_A >= 0, sum R_A = 1)."""
+    """Bound of max |T - T_ref| at the boundary points over all paths:
+    |dT~| + max |du| (R_A >= 0 and sum_A R_A = 1 at every point)."""
     worst = 0.0
     for p in range(a.info.n_paths):
         Ta, _, _, ua = a.boundary_fields(p)
@@ -206,18 +186,15 @@ def _max_err(a, b):
     return worst
 
 
-def run_surrogate(window, n_train=2_000_000, epochs=4, seed=1):
-    """Surrogate form on held-out strategies (seed 1) of the batched workload:
-    the network is trained here, on the GPU, on exact far sums of strategies
-    with seeds 1000..1063; then the audited form, the network forced on every
-    step (audit tolerance infinite) and the FP64 form run the same window."""
+def train_network(n_train=2_000_000, epochs=4, e_scale=0.1):
+    """The far-history network, trained here on the GPU by the library's
+    kernels on exact far sums of 64 strategies with seeds 1000..1063."""
     import torch
     from paper_2511_20432_amd import sa_iga, surrogate
     from paper_2511_20432_amd import workloads as W
     t0 = time.perf_counter()
-    w = W.cfg4(seed=seed)
-    e_scale = 0.1
-    X, T, G = surrogate.training_set(w.patch, surrogate.strategy_scan(range(1000, 1064)), n_train, e_scale, seed=0)
+    patch = W.cfg2().patch
+    X, T, G = surrogate.training_set(patch, surrogate.strategy_scan(range(1000, 1064)), n_train, e_scale, seed=0)
     ts, gs = surrogate.scales_of(T, G)
     Y = surrogate.targets(T, G, ts, gs)
     del T, G
@@ -226,74 +203,197 @@ def run_surrogate(window, n_train=2_000_000, epochs=4, seed=1):
     blob = surrogate.weights_blob(net.params(), ts, gs, e_scale)
     del X, Y, net
     torch.cuda.empty_cache()
-    train_s = time.perf_counter() - t0
-    start = _start_steps(w, window, seed)
-    out = {"training": {"samples": n_train, "epochs": epochs, "loss_per_epoch": hist, "seconds": train_s,
-                        "t_scale_K": ts, "g_scale_K_per_m": gs, "e_scale_J": e_scale,
-                        "train_seeds": "1000..1063", "eval_seed": seed}}
-    ref, dt, st, tune, su = _batched_window(w, W.PRECISION_FP64, window, start)
-    out["fp64"] = _window_report(w, "fp64", window, dt, st, tune, su, seed)
+    info = {"samples": n_train, "epochs": epochs, "loss_per_epoch": hist, "seconds": time.perf_counter() - t0,
+            "t_scale_K": ts, "g_scale_K_per_m": gs, "e_scale_J": e_scale, "train_seeds": "1000..1063"}
+    return blob, info
+
+
+def _batch_desc(w, seed):
+    return (f"{w.scan.n_paths} scan strategies (seed {seed}) on the 4x2x1 mm block, cubic B-splines 64x32x16, "
+            f"64512 boundary points; hatch angle from {{0,45,67,90}} deg, 0.1 mm hatch, power U[40,120] W, "
+            f"speed U[0.6,1.5] m/s, lengths U[500,4000] steps (sum {int(w.scan.n_steps.sum())}), "
+            f"{len(w.scan.tick)} sources, dt 10 us, 5 sources/step")
+
+
+def run_headline(warmup, steps, blob):
+    """The audited learned far-history form and the FP64 form on the held-out
+    batch (seed 1), same window; also the network forced on every step."""
+    from paper_2511_20432_amd import workloads as W
+    seed = 1
+    w = W.cfg4(seed=seed)
+    start = _start_steps(w, warmup + steps, seed)
+    out = {"workload": _batch_desc(w, seed), "start": WINDOW_START}
+    print(f"[bench] headline fp64: {warmup} + {steps} steps of {w.scan.n_paths} strategies", file=sys.stderr,
+          flush=True)
+    ref, dt, st = _window(w, W.PRECISION_FP64, start, warmup, steps)
+    out["fp64"] = _report(st, dt, steps)
+    out["fp64"]["sum_roofline"] = _sum_roofline(st, st["stage_ms"]["sum"])
     for form, kw in (("surrogate_audited", {}), ("surrogate_forced", {"audit_tol": 1e30})):
-        print(f"[bench] {form}: {window} steps of {w.scan.n_paths} strategies", file=sys.stderr, flush=True)
-        m, dt, st, tune, su = _batched_window(w, W.PRECISION_SURROGATE, window, start, surrogate_weights=blob, **kw)
-        r = _window_report(w, form, window, dt, st, tune, su, seed)
+        print(f"[bench] headline {form}", file=sys.stderr, flush=True)
+        m, dt, st = _window(w, W.PRECISION_SURROGATE, start, warmup, steps, surrogate_weights=blob, **kw)
+        r = _report(st, dt, steps)
         r.update({k: st[k] for k in ("net_steps", "pairs_net", "audits", "audit_failures", "audit_max_err")})
-        # network stage against the dense bf16 matrix-core peak: hidden-layer
-        # flops (3 layers of 256 x 256 per point) over the stage's device time
+        r["sum_roofline"] = _sum_roofline(st, st["stage_ms"]["sum"])
+        r["sum_launches_per_step"] = st["stage_launches"]["sum"] / steps
+        r["sum_ms_per_launch"] = (st["stage_ms"]["sum"] / st["stage_launches"]["sum"]
+                                  if st["stage_launches"]["sum"] else None)
         net_ms = st["stage_ms"]["net"]
         flops = st["net_steps"] * 64512 * 3 * 2 * 256 * 256
         if net_ms > 0 and flops > 0:
-            r["net_roofline"] = {"bound": "mfma", "achieved": flops / (net_ms * 1e-3) / 1e12,
-                                 "peak": 2500.0, "unit": "TFLOP/s",
-                                 "frac": flops / (net_ms * 1e-3) / 2.5e15,
+            r["net_roofline"] = {"bound": "mfma", "achieved": flops / (net_ms * 1e-3) / 1e12, "peak": 2500.0,
+                                 "unit": "TFLOP/s", "frac": flops / (net_ms * 1e-3) / 2.5e15,
                                  "note": "stage time includes the far-energy bins, first-layer constants and audits"}
         r["max_err_K_vs_fp64"] = _max_err(m, ref)
-        r["speedup_vs_fp64"] = out["fp64"]["ms_per_batched_step"] / r["ms_per_batched_step"]
+        r["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / r["ms_per_step"]
         out[form] = r
-        del m
+        m.close()
+    ref.close()
+    return w, start, out
+
+
+def run_batch(warmup, steps, seed=0):
+    from paper_2511_20432_amd import workloads as W
+    w = W.cfg4(seed=seed)
+    start = _start_steps(w, warmup + steps, seed)
+    out = {"workload": _batch_desc(w, seed), "start": WINDOW_START}
+    models = {}
+    for form, prec in (("fp32far", W.PRECISION_FP32_FAR), ("fp64", W.PRECISION_FP64)):
+        print(f"[bench] batch seed {seed} {form}", file=sys.stderr, flush=True)
+        m, dt, st = _window(w, prec, start, warmup, steps)
+        out[form] = _report(st, dt, steps)
+        out[form]["sum_roofline"] = _sum_roofline(st, st["stage_ms"]["sum"])
+        models[form] = m
+    out["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32far"]["ms_per_step"]
+    out["max_err_K_vs_fp64"] = _max_err(models["fp32far"], models["fp64"])
+    for m in models.values():
+        m.close()
     return out
 
 
-def cpu_baseline(w, step, n_steps=16, threads=None):
-    """The oracle's kernel sum (Eqs. 7-8) at every boundary point over a
-    window of n_steps consecutive steps."""
-    from oracle import iga, pointsource
-    bt = iga.boundary_tables(w.patch)
-    x = bt["x"]
-    sc = w.scan
-    nthr = threads or pointsource.default_threads()
-    pairs = 0
-    t0 = time.perf_counter()
-    for s in range(step, step + n_steps):
-        pointsource.field(x, sc.xyz, sc.tick, sc.energy, s, sc, w.material, threads=nthr)
-        pairs += len(x) * int(np.searchsorted(sc.tick, s * sc.sources_per_step, side="right"))
-    dt = time.perf_counter() - t0
+def run_raster(warmup):
+    """The raster scan, one path: every one of its steps timed, both forms."""
+    from paper_2511_20432_amd import sa_iga
+    from paper_2511_20432_amd import workloads as W
+    w = W.cfg2(seed=0)
+    n = int(w.scan.n_steps[0])
+    out = {"workload": "raster: 4x2x1 mm block, cubic B-splines 64x32x16, 64512 boundary points, 10 tracks "
+                       f"x 0.1 mm hatch, 80 W, 1 m/s, dt 10 us, 5 sources/step, {len(w.scan.tick)} sources, "
+                       f"all {n} steps timed from step 0", "steps": n}
+    models = {}
+    for form, prec in (("fp32far", W.PRECISION_FP32_FAR), ("fp64", W.PRECISION_FP64)):
+        print(f"[bench] raster {form}: {n} steps", file=sys.stderr, flush=True)
+        if warmup > 0:      # warm-up steps on an object of their own
+            m0 = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=prec, tau_near=2e-4))
+            m0.step(warmup)
+            m0.close()
+        m, dt, st = _window(w, prec, None, 0, n)
+        out[form] = _report(st, dt, n)
+        out[form]["sum_roofline"] = _sum_roofline(st, st["stage_ms"]["sum"])
+        models[form] = m
+    out["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32far"]["ms_per_step"]
+    out["max_err_K_vs_fp64"] = _max_err(models["fp32far"], models["fp64"])
+    for m in models.values():
+        m.close()
+    return out
+
+
+def run_annulus(warmup, steps):
+    """The quarter annulus, one path, from the middle of its scan: both forms
+    as the library runs them (matrix-core sum on the two planar ends, the
+    pair-by-pair kernel on the curved and annular faces), and the FP32
+    far-field form with the pair-by-pair kernel on every face for that
+    kernel's roofline."""
+    from paper_2511_20432_amd import workloads as W
+    w = W.cfg3(seed=0)
+    n = int(w.scan.n_steps[0])
+    s0 = n // 2
+    out = {"workload": "quarter annulus r in [2,4] mm x 1 mm, quadratic NURBS 48x24x12, 36288 boundary points; "
+                       "contour at r = 3.5 mm then 45 deg hatches, U[60,100] W, 0.8 m/s, dt 10 us, 8 sources/step, "
+                       f"{len(w.scan.tick)} sources, {n} steps",
+           "start": f"step {s0} with a zeroed state, {warmup} untimed steps", "steps": steps}
+    models = {}
+    for form, prec in (("fp32far", W.PRECISION_FP32_FAR), ("fp64", W.PRECISION_FP64)):
+        print(f"[bench] annulus {form}", file=sys.stderr, flush=True)
+        m, dt, st = _window(w, prec, [s0], warmup, steps)
+        out[form] = _report(st, dt, steps)
+        models[form] = m
+    out["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32far"]["ms_per_step"]
+    out["max_err_K_vs_fp64"] = _max_err(models["fp32far"], models["fp64"])
+    for m in models.values():
+        m.close()
+    os.environ["SA_IGA_NO_TENSOR"] = "1"
+    try:
+        print("[bench] annulus fp32far, pair-by-pair kernel on every face", file=sys.stderr, flush=True)
+        m, dt, st = _window(w, W.PRECISION_FP32_FAR, [s0], warmup, steps)
+    finally:
+        del os.environ["SA_IGA_NO_TENSOR"]
+    r = _report(st, dt, steps)
+    r["k_sum_roofline"] = _valu_roofline(st, st["stage_ms"]["sum"])
+    r["k_sum_roofline"]["kernel"] = "k_sum (pair by pair; far pairs FP32, near pairs FP64)"
+    out["fp32far_pair_by_pair"] = r
+    m.close()
+    return out
+
+
+def run_small():
+    from paper_2511_20432_amd import workloads as W
+    w = W.cfg1()
+    n = int(w.scan.n_steps[0])
+    m, dt, st = _window(w, W.PRECISION_FP64, None, 0, n, tune=False)
+    r = _report(st, dt, n)
+    m.close()
+    r["workload"] = (f"small block 2x1x1 mm, quadratic B-splines 16x8x8, one track, 40 W, 1 m/s, 10 sources/step, "
+                     f"all {n} steps, FP64")
+    return r
+
+
+def _cpu_model():
     cpu = platform.processor() or platform.machine()
     try:
         for ln in open("/proc/cpuinfo"):
             if ln.startswith("model name"):
-                cpu = ln.split(":", 1)[1].strip()
-                break
+                return ln.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": pairs / dt, "unit": "pairs/s", "cores": nthr, "kind": "oracle",
-            "sample": f"numpy FP64 kernel sum over steps {step}..{step + n_steps - 1} of the raster run at all "
-                      f"{len(x)} boundary points: {pairs:.3e} pairs in {dt:.1f} s on {nthr} threads ({cpu})"}
+    return cpu
+
+
+def cpu_baseline(w, start, warmup, n_slots=24, n_slots_1core=2):
+    """The oracle's FP64 kernel sum (Eqs. 7-8) at every boundary point for
+    sampled slots (strategy, step) of the headline window: the first timed
+    step of the first strategies, on every core of the process's CPU share
+    and on one core."""
+    from oracle import iga, pointsource
+    bt = iga.boundary_tables(w.patch)
+    x = bt["x"]
+    res = {}
+    for label, nthr, k in (("all", pointsource.default_threads(), n_slots), ("one", 1, n_slots_1core)):
+        pairs = 0
+        t0 = time.perf_counter()
+        for p in range(k):
+            sc = w.scan.path(p)
+            s = int(start[p]) + warmup + 1
+            pointsource.field(x, sc.xyz, sc.tick, sc.energy, s, sc, w.material, threads=nthr)
+            pairs += len(x) * int(np.searchsorted(sc.tick, s * sc.sources_per_step, side="right"))
+        res[label] = (pairs, time.perf_counter() - t0, nthr, k)
+    pa, ta, na, ka = res["all"]
+    p1, t1, _, k1 = res["one"]
+    return {"value": pa / ta, "unit": "pairs/s", "cores": na, "kind": "oracle",
+            "sample": f"numpy FP64 kernel sum at all {len(x)} boundary points for the first timed step of "
+                      f"strategies 0..{ka - 1} of the headline window: {pa:.3e} pairs in {ta:.1f} s on {na} "
+                      f"threads ({_cpu_model()}, {os.cpu_count()} logical CPUs on the host)",
+            "one_core": {"value": p1 / t1, "unit": "pairs/s", "cores": 1,
+                         "sample": f"strategies 0..{k1 - 1}: {p1:.3e} pairs in {t1:.1f} s"}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=60, help="timed batched steps of the headline window")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
+    ap.add_argument("--legs", default="headline,batch,raster,annulus,small",
+                    help="comma-separated subset of headline,batch,raster,annulus,small")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32far,fp64")
-    ap.add_argument("--tile", default=None,
-                    help="kernel-sum tile shape 'P,W' (points per lane, waves per group) instead of the tuner")
-    ap.add_argument("--batched-window", type=int, default=60,
-                    help="timed steps of the 128-strategy batch (0: skip)")
-    ap.add_argument("--surrogate-window", type=int, default=60,
-                    help="timed steps of the surrogate form on held-out strategies (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device five times (the reference kernel of the HBM "
                          "counter scale) and exit")
@@ -315,98 +415,47 @@ def main():
     import torch
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
-    from paper_2511_20432_amd import workloads as W
-
-    w = W.cfg2(seed=0)
-    n_total = int(w.scan.n_steps[0])
-    # by default the run stops one step short of the scan's end, where the
-    # forms are compared (reaching the end would restore the initial state)
-    steps = args.steps if args.steps is not None else max(1, n_total - args.warmup - 1)
-    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    res = {}
-    models = {}
-    for f in forms:
-        prec = {"fp32far": W.PRECISION_FP32_FAR, "fp64": W.PRECISION_FP64}[f]
-        print(f"[bench] form {f}: setup + {args.warmup} warmup + {steps} timed steps", file=sys.stderr, flush=True)
-        tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-        m, dt, st, setup_s = run_form(w, prec, args.warmup, steps, tile)
-        res[f] = {"seconds": dt, "stats": st, "setup_s": setup_s}
-        models[f] = m
-        print(f"[bench] form {f}: {dt:.3f} s, {st['pairs'] / dt:.3e} pairs/s, "
-              f"sum {st['stage_ms']['sum']:.1f} ms, pcg {st['stage_ms']['pcg']:.1f} ms", file=sys.stderr, flush=True)
-
-    # temperature difference between the forms at the end of the timed steps
-    max_err = err_step = None
-    if "fp32far" in models and "fp64" in models:
-        Ta, _, _, ua = models["fp32far"].boundary_fields()
-        Tb, _, _, ub = models["fp64"].boundary_fields()
-        # R_A >= 0 and sum_A R_A = 1 at every boundary point, so this bounds the
-        # difference of T = T~ + sum_A R_A u_A at the points
-        max_err = float(np.abs(Ta - Tb).max() + np.abs(ua - ub).max())
-        err_step = models["fp64"].get_step()
-
-    main_form = "fp32far" if "fp32far" in res else forms[0]
-    r = res[main_form]
-    st = r["stats"]
-    pairs_s = st["pairs"] / r["seconds"]
-    sum_ms = st["stage_ms"]["sum"]
-    launches = max(1, st["stage_launches"]["sum"])
-    roof = _sum_roofline(st, sum_ms)
-    out = {
-        "metric": METRIC, "value": pairs_s, "unit": "pairs/s", "n_gpus": 1, "steps": steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * r["seconds"] / steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if main_form == "fp32far" else "f64", "data": "synthetic",
-        "config": {"workload": "raster: 4x2x1 mm block, cubic B-splines 64x32x16 elements, 64512 boundary "
-                               "points, 10 tracks x 0.1 mm hatch, 80 W, 1 m/s, dt 10 us, 5 sources/step, "
-                               f"{n_total} steps, {len(w.scan.tick)} sources, seed 0",
-                   "form": main_form, "tau_near_s": 2e-4, "theta": 0.5, "pcg_rtol": 1e-13,
-                   "preconditioner": "fast diagonalisation"},
-        "steps_per_s": steps / r["seconds"],
-        "roofline": dict(roof, traffic=_k_sum_traffic(main_form, steps / max(1, launches)),
-                         traffic_unit="HBM bytes per k_sum_tensor launch (read + written)",
-                         traffic_per_step=_k_sum_traffic(main_form),
-                         kernel="k_sum_tensor (far chunks FP32, near chunks FP64; one launch per block of up to 8 steps)",
-                         avg_ms_per_step=sum_ms / steps, launches_per_step=launches / steps,
-                         pairs_per_step=st["pairs"] / steps),
-        "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
-        "ms_per_step_with_stage_events": 1e3 * st["seconds_with_events"] / steps,
-        "rollbacks": st["rollbacks"],
-        "setup_s": r["setup_s"],
-        "autotune": st["autotune"],
-    }
-    if "fp64" in res and main_form != "fp64":
-        s64 = res["fp64"]["stats"]
-        t64 = res["fp64"]["seconds"]
-        out["fp64"] = {"value": s64["pairs"] / t64, "unit": "pairs/s", "steps_per_s": steps / t64,
-                       "ms_per_step": 1e3 * t64 / steps,
-                       "sum_gpair_s": s64["pairs"] / (s64["stage_ms"]["sum"] * 1e-3) / 1e9
-                       if s64["stage_ms"]["sum"] > 0 else None,
-                       "sum_roofline": _sum_roofline(s64, s64["stage_ms"]["sum"]),
-                       "stage_ms_per_step": {k: v / steps for k, v in s64["stage_ms"].items()},
-                       "rollbacks": s64["rollbacks"],
-                       "autotune": s64["autotune"]}
-        out["speedup_vs_fp64"] = t64 / r["seconds"]
-        out["max_err_K_vs_fp64"] = max_err
-        out["max_err_at_step"] = err_step
-    if args.batched_window > 0:
-        out["batched"] = {}
-        for f in forms:
-            print(f"[bench] batched form {f}: {args.batched_window} steps of 128 strategies", file=sys.stderr,
-                  flush=True)
-            b = run_batched(args.batched_window, f)
-            out["batched"][f] = b
-            print(f"[bench] batched {f}: {b['pairs_per_s']:.3e} pairs/s, {b['path_steps_per_s']:.1f} path-steps/s",
-                  file=sys.stderr, flush=True)
-        if "fp32far" in out["batched"] and "fp64" in out["batched"]:
-            out["batched"]["speedup_vs_fp64"] = (out["batched"]["fp32far"]["path_steps_per_s"]
-                                                 / out["batched"]["fp64"]["path_steps_per_s"])
-    if args.surrogate_window > 0:
-        print("[bench] surrogate form: training the far-history network", file=sys.stderr, flush=True)
-        out["surrogate"] = run_surrogate(args.surrogate_window)
-    if not args.no_cpu_baseline:
+    legs = {s.strip() for s in args.legs.split(",") if s.strip()}
+    steps, warmup = max(1, args.steps), max(0, args.warmup)
+    out = {}
+    if "headline" in legs:
+        print("[bench] training the far-history network", file=sys.stderr, flush=True)
+        blob, training = train_network()
+        w5, start, head = run_headline(warmup, steps, blob)
+        head["training"] = training
+        a = head["surrogate_audited"]
+        roof = dict(a["sum_roofline"])
+        roof.update({"traffic": _k_sum_traffic(a["sum_launches_per_step"]),
+                     "traffic_unit": "HBM bytes per k_sum_tensor launch (read + written)",
+                     "kernel": "k_sum_tensor (far chunks FP32, near chunks FP64), the dominant kernel of the window",
+                     "avg_ms_per_launch": a["sum_ms_per_launch"], "launches_per_step": a["sum_launches_per_step"],
+                     "pairs_per_launch": a["pairs_per_step"] / max(a["sum_launches_per_step"], 1e-30)})
+        out.update({
+            "metric": METRIC, "value": a["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": a["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64+bf16", "data": "synthetic",
+            "config": {"workload": "learned far-history form with audits on the held-out batch: " + head["workload"]
+                       + f"; window: {WINDOW_START}, {warmup} untimed + {steps} timed batched steps",
+                       "form": "surrogate_audited (network far field where its audit passed, else FP32 far "
+                               "sum; near sources, loads and solves FP64)",
+                       "tau_near_s": 2e-4, "theta": 0.5, "audit_every": 50, "audit_frac": 0.01,
+                       "audit_tol_K": 0.5, "preconditioner": "fast diagonalisation"},
+            "steps_per_s": a["path_steps_per_s"],
+            "speedup_vs_fp64": a["speedup_vs_fp64"], "max_err_K_vs_fp64": a["max_err_K_vs_fp64"],
+            "roofline": roof,
+            "headline": head,
+        })
+    if "batch" in legs:
+        out["batch"] = run_batch(warmup, steps)
+    if "raster" in legs:
+        out["raster"] = run_raster(warmup)
+    if "annulus" in legs:
+        out["annulus"] = run_annulus(warmup, max(steps, 200))
+    if "small" in legs:
+        out["small"] = run_small()
+    if "headline" in legs and not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle kernel sum)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, step=min(n_total - 16, 1900))
+        out["cpu_baseline"] = cpu_baseline(w5, start, warmup)
     print(json.dumps(out), flush=True)
 
 

@@ -75,7 +75,11 @@ enum sa_precision {
                                 FP32 tile partials accumulated in FP64; near
                                 sources, loads and the solve in FP64 */
   SA_PREC_SURROGATE = 2      /* far sources replaced by the learned network (sa_mlp), near
-                                sources in FP64; audited against the exact far sum */
+                                sources in FP64.  A path's network is audited against the
+                                exact FP64 far sum on the first step with far sources and
+                                then every audit_every steps; before its first passing
+                                audit, and after a failing one, the path sums its far
+                                sources as SA_PREC_FP32_FAR does */
 };
 
 enum sa_precond {
@@ -118,9 +122,10 @@ typedef struct {
    * E_scale (J), then the sa_mlp_n_params() FP32 parameters}; copied at set-up. */
   const float *surrogate_weights;
   int64_t surrogate_len;
-  int32_t audit_every;         /* audit a path's network every this many steps; default 50 */
+  int32_t audit_every;         /* audit a path's network on its first step with far sources,
+                                  then every this many steps (>= 1); default 50 */
   double audit_frac;           /* fraction of the boundary points audited; default 0.01 */
-  double audit_tol;            /* K: fall back to the exact far sum above this error; default 0.5 */
+  double audit_tol;            /* K: largest far-temperature error an audit passes; default 0.5 */
 } sa_solver_options;
 
 typedef struct {
@@ -178,7 +183,7 @@ typedef struct {
   int64_t net_steps;           /* path-steps whose far part came from the network */
   int64_t pairs_net;           /* far source x point pairs the network replaced */
   int64_t audits;              /* audits run */
-  int64_t audit_failures;      /* audits above audit_tol (the path then uses the exact sum) */
+  int64_t audit_failures;      /* audits above audit_tol (the path then sums its far sources) */
   double audit_max_err;        /* largest audited error of the far temperature (K) */
   int64_t rollbacks;           /* calls whose steps were run again with a second PCG iteration
                                   (one iteration did not reach the tolerance on some step) */
@@ -289,7 +294,9 @@ int sa_iga_reset_stats(sa_iga *h);
 
 /*
  * Checkpoint of the mutable state of every path: its step, u^n, F^n, the
- * Dirichlet values, and T~, grad T~ at the boundary points.  With
+ * Dirichlet values, T~, grad T~ at the boundary points and, in the
+ * surrogate form, its audit state (whether its far part comes from the
+ * network or the exact sum, and the step of its next audit).  With
  * buf == NULL, *len receives the size needed.  sa_iga_load restores a
  * checkpoint taken from an object with the same patch and number of paths
  * (SA_EINVAL if the sizes differ or a step exceeds that path's n_steps) and

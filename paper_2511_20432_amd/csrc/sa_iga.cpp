@@ -231,7 +231,10 @@ struct sa_iga {
   double *netf = nullptr;               // [kMaxBatch][4][stride] network far field
   sa::bf16_t *hA = nullptr, *hB = nullptr;  // [net_rows][256] activations
   int64_t net_rows = 0;
-  std::vector<uint8_t> use_exact;       // per path: the last audit failed
+  // per path: 1 while its far part comes from the exact sum (no audit yet,
+  // or the last audit failed), 0 while it comes from the network
+  std::vector<uint8_t> use_exact;
+  std::vector<int64_t> next_audit;      // per path: step of its next audit; -1 = the first step with far sources
   // audit points: a fixed seeded subset of the boundary points
   int64_t na = 0, stride_a = 0;
   double *ax = nullptr, *ay = nullptr, *az = nullptr, *aq2 = nullptr;
@@ -768,8 +771,14 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     at.count = count;
     std::vector<int> aud;
     for (int s = 0; s < count; ++s) {
-      fill_slot(h, at, s, pids[s], h->paths[pids[s]].step + 1);
-      if ((h->paths[pids[s]].step + 1) % h->m.opt.audit_every == 0) aud.push_back(s);
+      const int p = pids[s];
+      const int64_t st1 = h->paths[p].step + 1;
+      fill_slot(h, at, s, p, st1);
+      // the first step with far sources, then every audit_every steps
+      if (at.n_far[s] > 0 && (h->next_audit[p] < 0 || st1 >= h->next_audit[p])) {
+        aud.push_back(s);
+        h->next_audit[p] = st1 + h->m.opt.audit_every;
+      }
     }
     audit_slots(h, at, aud);
     // paths on the network first: their slots index the network's output
@@ -782,8 +791,9 @@ void step_batch(sa_iga *h, std::vector<int> pids) {
     sm.path[s] = pids[s];
     fill_slot(h, tab, s, pids[s], P.step + 1);
     if (h->net) {
+      // the other paths sum their far history as the precision form does
+      // (FP32 terms in FP64 block sums)
       if (s < n_net) tab.mode[s] = 1;
-      else tab.n_far[s] = 0;               // exact fallback: every source in FP64
     }
   }
   const double *net = nullptr;
@@ -1441,7 +1451,9 @@ void build_network_state(sa_iga *h, const sa_patch *patch, const sa_scan_path *s
   h->net_rows = std::min<int64_t>(131072, (int64_t)sa::kMaxBatch * h->stride);
   h->hA = dev_alloc<sa::bf16_t>(h->owned, (size_t)h->net_rows * sa::kMlpHid);
   h->hB = dev_alloc<sa::bf16_t>(h->owned, (size_t)h->net_rows * sa::kMlpHid);
-  h->use_exact.assign(h->paths.size(), 0);
+  // no path uses the network before an audit has passed
+  h->use_exact.assign(h->paths.size(), 1);
+  h->next_audit.assign(h->paths.size(), -1);
   // audit points: ceil(audit_frac nq) of the boundary points, drawn once
   const int64_t nq = bt.nq;
   h->na = std::min<int64_t>(nq, std::max<int64_t>(1, (int64_t)std::ceil(m.opt.audit_frac * (double)nq)));
@@ -2196,7 +2208,7 @@ int path_index(sa_iga *h, int32_t path) {
   return path;
 }
 
-constexpr uint64_t kMagic = 0x5341494741434b32ull;  // checkpoint tag
+constexpr uint64_t kMagic = 0x5341494741434b33ull;  // checkpoint tag (with the audit state)
 
 }  // namespace
 
@@ -2278,6 +2290,7 @@ struct HostState {
   std::vector<int64_t> steps;
   sa_stats stats{};
   std::vector<uint8_t> use_exact;
+  std::vector<int64_t> next_audit;
 };
 
 void save_state(sa_iga *h, HostState &c) {
@@ -2292,6 +2305,7 @@ void save_state(sa_iga *h, HostState &c) {
   for (size_t p = 0; p < h->paths.size(); ++p) c.steps[p] = h->paths[p].step;
   c.stats = h->stats;
   c.use_exact = h->use_exact;
+  c.next_audit = h->next_audit;
 }
 
 void restore_state(sa_iga *h, const HostState &c) {
@@ -2304,6 +2318,7 @@ void restore_state(sa_iga *h, const HostState &c) {
   for (size_t p = 0; p < h->paths.size(); ++p) h->paths[p].step = c.steps[p];
   h->stats = c.stats;
   h->use_exact = c.use_exact;
+  h->next_audit = c.next_audit;
   std::fill(h->chk_pending.begin(), h->chk_pending.end(), 0);
 }
 
@@ -2509,11 +2524,13 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
       for (int p = 0; p < S; ++p) steps[p] = h->paths[p].step;
       const sa_stats stats = h->stats;
       const std::vector<uint8_t> use_exact = h->use_exact;
+      const std::vector<int64_t> next_audit = h->next_audit;
       const int keep_timing = o.timing;
       auto restore = [&]() {
         for (int p = 0; p < S; ++p) h->paths[p].step = steps[p];
         h->stats = stats;
         h->use_exact = use_exact;
+        h->next_audit = next_audit;
         o.timing = keep_timing;
         for (size_t k = 0; k < keep.size(); ++k)
           hip_check(hipMemcpyAsync(arr[k].dst, keep[k], arr[k].n * sizeof(double), hipMemcpyDeviceToDevice,
@@ -2611,7 +2628,7 @@ int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
   return guarded([&]() -> int {
     if (!h || !len) throw sa::SaError{SA_EINVAL, "NULL argument"};
     const int64_t nd = h->nd, nDa = h->nDa, nq = h->nq;
-    const size_t per = sizeof(int64_t) + (2 * nd + nDa + 4 * nq) * sizeof(double);
+    const size_t per = 3 * sizeof(int64_t) + (2 * nd + nDa + 4 * nq) * sizeof(double);
     const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
     if (!buf) {
       *len = need;
@@ -2623,8 +2640,11 @@ int sa_iga_save(sa_iga *h, void *buf, size_t *len) {
     std::memcpy(b, hdr, sizeof(hdr));
     b += sizeof(hdr);
     for (int p = 0; p < (int)h->paths.size(); ++p) {
-      std::memcpy(b, &h->paths[p].step, sizeof(int64_t));
-      b += sizeof(int64_t);
+      // step, then the surrogate form's audit state (1, -1 without a network)
+      const int64_t rec[3] = {h->paths[p].step, h->net ? (int64_t)h->use_exact[p] : 1,
+                              h->net ? h->next_audit[p] : -1};
+      std::memcpy(b, rec, sizeof(rec));
+      b += sizeof(rec);
       hip_check(hipMemcpyAsync(b, path_v(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
       b += nd * sizeof(double);
       hip_check(hipMemcpyAsync(b, path_F(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
@@ -2650,7 +2670,7 @@ int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
   return guarded([&]() -> int {
     if (!h || !buf) throw sa::SaError{SA_EINVAL, "NULL argument"};
     const int64_t nd = h->nd, nDa = h->nDa, nq = h->nq;
-    const size_t per = sizeof(int64_t) + (2 * nd + nDa + 4 * nq) * sizeof(double);
+    const size_t per = 3 * sizeof(int64_t) + (2 * nd + nDa + 4 * nq) * sizeof(double);
     const size_t need = 4 * sizeof(uint64_t) + h->paths.size() * per;
     if (len < need) throw sa::SaError{SA_EINVAL, "checkpoint too short"};
     const char *b = (const char *)buf;
@@ -2660,15 +2680,22 @@ int sa_iga_load(sa_iga *h, const void *buf, size_t len) {
       throw sa::SaError{SA_EINVAL, "checkpoint does not match this object"};
     b += sizeof(hdr);
     for (auto &P : h->paths) {
-      int64_t st;
-      std::memcpy(&st, b, sizeof(int64_t));
-      if (st < 0 || st > P.n_steps) throw sa::SaError{SA_EINVAL, "checkpoint step out of range"};
+      int64_t rec[3];
+      std::memcpy(rec, b, sizeof(rec));
+      if (rec[0] < 0 || rec[0] > P.n_steps) throw sa::SaError{SA_EINVAL, "checkpoint step out of range"};
+      if ((rec[1] != 0 && rec[1] != 1) || rec[2] < -1) throw sa::SaError{SA_EINVAL, "checkpoint audit state invalid"};
       b += per;
     }
     b = (const char *)buf + sizeof(hdr);
     for (int p = 0; p < (int)h->paths.size(); ++p) {
-      std::memcpy(&h->paths[p].step, b, sizeof(int64_t));
-      b += sizeof(int64_t);
+      int64_t rec[3];
+      std::memcpy(rec, b, sizeof(rec));
+      b += sizeof(rec);
+      h->paths[p].step = rec[0];
+      if (h->net) {
+        h->use_exact[p] = (uint8_t)rec[1];
+        h->next_audit[p] = rec[2];
+      }
       hip_check(hipMemcpyAsync(path_v(h, p), b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");
       b += nd * sizeof(double);
       hip_check(hipMemcpyAsync(path_F(h, p), b, nd * sizeof(double), hipMemcpyHostToDevice, h->stream), "upload");

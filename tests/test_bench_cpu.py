@@ -1,9 +1,10 @@
-"""Host logic of bench.py: the roofline of the sum stage, the traffic per
-launch, and the refusal of several GPUs (no GPU needed)."""
+"""Host logic of bench.py: the rooflines of the two kernel sums, the traffic
+per launch, the window starts and the refusal of several GPUs (no GPU needed)."""
 import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -36,11 +37,36 @@ def test_roofline_without_time_or_work():
     assert bench._sum_roofline({"pairs": 10, "pairs_near": 0}, 0.0)["achieved"] is None
 
 
-def test_traffic_per_launch_scales_the_per_step_counters():
-    per_step = bench._k_sum_traffic("fp32far")
-    assert per_step == pytest.approx(bench.K_SUM_TRAFFIC["read_bytes"] + bench.K_SUM_TRAFFIC["written_bytes"])
-    assert bench._k_sum_traffic("fp32far", 8.0) == pytest.approx(8 * per_step)
-    assert bench._k_sum_traffic("fp64", 8.0) is None
+def test_traffic_per_launch_divides_the_per_step_counters(monkeypatch):
+    monkeypatch.setattr(bench, "K_SUM_TRAFFIC", None)
+    assert bench._k_sum_traffic(2.0) is None
+    monkeypatch.setattr(bench, "K_SUM_TRAFFIC", {"read_bytes": 3e6, "written_bytes": 5e6})
+    assert bench._k_sum_traffic(1.0) == pytest.approx(8e6)
+    assert bench._k_sum_traffic(2.0) == pytest.approx(4e6)
+
+
+def test_valu_roofline_of_the_pair_by_pair_sum():
+    # all pairs FP32: 13 issue slots each over 256 CUs x 64 lanes x 2.4 GHz
+    r = bench._valu_roofline({"pairs": 1e9, "pairs_near": 0}, 1.0)
+    assert r["bound"] == "alu" and r["unit"] == "pairs/s"
+    assert r["peak"] == pytest.approx(256 * 64 * 2.4e9 / 13)
+    assert r["achieved"] == pytest.approx(1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    # a quarter of the pairs FP64 at 28 slots: the time-weighted peak lies between
+    r = bench._valu_roofline({"pairs": 1e9, "pairs_near": 2.5e8}, 1.0)
+    assert 256 * 64 * 2.4e9 / 28 < r["peak"] < 256 * 64 * 2.4e9 / 13
+    assert bench._valu_roofline({"pairs": 0, "pairs_near": 0}, 1.0)["frac"] is None
+
+
+def test_start_steps_leave_room_for_the_window():
+    class Sc:
+        n_steps = np.array([500, 4000, 120, 64])
+
+    class Wl:
+        scan = Sc()
+    s = bench._start_steps(Wl(), 65, seed=1)
+    assert (s >= 0).all() and (s + 65 <= np.maximum(Sc.n_steps, 65)).all()
+    assert np.array_equal(s, bench._start_steps(Wl(), 65, seed=1))
 
 
 def test_several_gpus_are_refused():

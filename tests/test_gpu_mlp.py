@@ -134,7 +134,9 @@ def test_surrogate_step_uses_network_far_field():
     gm = _surrogate_model(scan, p, tau, audit_tol=1e30, audit_every=7)
     gm.step(30)
     st = gm.stats()
-    assert st["net_steps"] == 30 and st["audits"] == 4 and st["audit_failures"] == 0
+    # far sources from step 6 on (tick < 5 step - 25): audits at steps 6, 13,
+    # 20 and 27, the network from the first passing one
+    assert st["net_steps"] == 25 and st["audits"] == 4 and st["audit_failures"] == 0
     assert st["pairs_net"] > 0
     T, G, F, du = gm.boundary_fields()
     patch = W.small_block()
@@ -154,24 +156,79 @@ def test_surrogate_step_uses_network_far_field():
 
 
 def test_surrogate_audit_falls_back_to_exact():
-    """An untrained network fails its first audit; from then on the path is
-    summed exactly and matches the FP64 form bitwise."""
+    """An untrained network fails every audit, so no step uses it: the path
+    sums its far sources as the FP32 far-field form does, bitwise."""
     from paper_2511_20432_amd import sa_iga
     tr = surrogate_track()
     scan = W.make_scan([tr], 1e-5, 5, n_steps=[24])
     tau = 5e-5
     _, p = _net(7)
     gm = _surrogate_model(scan, p, tau, t_scale=1e4, audit_every=1)   # off by ~1000 K
-    ref = sa_iga.Model(W.small_block(), W.MAT_CFG, scan, W.Options(tau_near=tau))
+    ref = sa_iga.Model(W.small_block(), W.MAT_CFG, scan, W.Options(precision=W.PRECISION_FP32_FAR, tau_near=tau))
     gm.step(24)
     ref.step(24)
     st = gm.stats()
     print("surrogate stats", {k: st[k] for k in ("net_steps", "audits", "audit_failures", "audit_max_err")},
           flush=True)
-    assert st["audits"] == 24 and st["audit_failures"] == 24 and st["net_steps"] == 0
-    # after the failed audits the far part is exact: the last step is the FP64 form's
+    # far sources from step 6 on: one audit per step from there
+    assert st["audits"] == 19 and st["audit_failures"] == 19 and st["net_steps"] == 0
     for a, b in zip(gm.boundary_fields(), ref.boundary_fields()):
         assert np.array_equal(a, b)
+
+
+def test_surrogate_never_runs_unaudited():
+    """With the default audit period (50 steps) an untrained network is
+    audited on the path's first step with far sources, before it is used:
+    it fails, and every step equals the FP32 far-field form's bitwise."""
+    from paper_2511_20432_amd import sa_iga
+    tr = surrogate_track()
+    scan = W.make_scan([tr], 1e-5, 5, n_steps=[40])
+    tau = 5e-5
+    _, p = _net(8)
+    gm = _surrogate_model(scan, p, tau, t_scale=1e4)
+    ref = sa_iga.Model(W.small_block(), W.MAT_CFG, scan, W.Options(precision=W.PRECISION_FP32_FAR, tau_near=tau))
+    for k in (3, 4, 33):
+        gm.step(k)
+        ref.step(k)
+        for a, b in zip(gm.boundary_fields(), ref.boundary_fields()):
+            assert np.array_equal(a, b)
+    st = gm.stats()
+    assert st["audits"] == 1 and st["audit_failures"] == 1 and st["net_steps"] == 0
+
+
+def test_surrogate_checkpoint_keeps_audit_state():
+    """A checkpoint holds each path's audit state (network or exact far sum,
+    step of the next audit): a run resumed from it in another object, whose
+    own state differs, continues bitwise as the uninterrupted run, with the
+    same audits.  Far sources start at step 6, so with audits every 5 steps
+    the uninterrupted run audits at 6, 11, 16, 21; a resumed run that lost
+    the state would audit at 13, 18, 23 instead."""
+    tracks = [surrogate_track(), W.sources_from_segments(
+        [W.Segment("line", 60.0, 0.8, p0=np.array([0.2e-3, 0.1e-3, 0.5e-3]),
+                   p1=np.array([0.8e-3, 0.5e-3, 0.5e-3]))], 2e-6)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=[30, 22])
+    tau = 5e-5
+    _, p = _net(11)
+    a = _surrogate_model(scan, p, tau, audit_every=5, audit_tol=40.0)
+    a.step(12)
+    ck = a.save()
+    s0 = a.stats()
+    a.step(12)
+    b = _surrogate_model(scan, p, tau, audit_every=5, audit_tol=40.0)
+    b.step(2)                      # an unaudited state in memory
+    b.load(ck)
+    t0 = b.stats()
+    b.step(12)
+    s1, t1 = a.stats(), b.stats()
+    d_a = {k: s1[k] - s0[k] for k in ("audits", "audit_failures", "net_steps", "pairs", "pairs_net")}
+    d_b = {k: t1[k] - t0[k] for k in d_a}
+    print("after the checkpoint", d_a, d_b, "; before", {k: s0[k] for k in ("audits", "audit_failures", "net_steps")},
+          flush=True)
+    assert d_a == d_b
+    assert d_a["audits"] == 4
+    for path in range(2):
+        for x, y in zip(a.boundary_fields(path), b.boundary_fields(path)):
+            assert np.array_equal(x, y)
 
 
 def test_fused_network_matches_layerwise(monkeypatch):

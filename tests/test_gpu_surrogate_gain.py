@@ -106,3 +106,32 @@ def test_surrogate_form_sums_far_fewer_pairs_exactly(trained):
     assert st_n["net_steps"] > 0 and st_n["audit_failures"] == 0
     assert ratio < 0.2
     assert all(np.isfinite(a).all() for a in f_n)
+
+
+def test_audited_surrogate_form_within_half_kelvin_of_fp64(trained):
+    """The audited form with its default audits (first step with far
+    sources, then every 50 steps, 1 % of the points, 0.5 K) on held-out
+    strategies: the boundary temperature stays within 0.5 K of the FP64
+    form's, |dT~| + max |du| at every boundary point (R_A >= 0, sum R_A = 1)."""
+    from paper_2511_20432_amd import sa_iga
+    patch, net, ts, gs = trained
+    held = surrogate.strategy_scan(range(1, 5))
+    steps = 600
+    blob = surrogate.weights_blob(net.params(), ts, gs, E_SCALE)
+    ref = sa_iga.Model(patch, W.MAT_CFG, held, W.Options(precision=W.PRECISION_FP64, tau_near=TAU))
+    sur = sa_iga.Model(patch, W.MAT_CFG, held, W.Options(precision=W.PRECISION_SURROGATE, tau_near=TAU),
+                       surrogate_weights=blob)
+    worst = 0.0
+    for k in (150, 150, 300):
+        ref.step(k)
+        sur.step(k)
+        for p in range(held.n_paths):
+            Ta, _, _, ua = sur.boundary_fields(p)
+            Tb, _, _, ub = ref.boundary_fields(p)
+            worst = max(worst, float(np.abs(Ta - Tb).max() + np.abs(ua - ub).max()))
+    st = sur.stats()
+    print(f"audited surrogate form, {steps} steps of {held.n_paths} held-out strategies: max error {worst:.3e} K; "
+          f"audits {st['audits']}, failed {st['audit_failures']}, network steps {st['net_steps']}, "
+          f"largest audited error {st['audit_max_err']:.2f} K", flush=True)
+    assert st["audits"] >= held.n_paths * (steps // 50)
+    assert worst <= 0.5
