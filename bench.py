@@ -120,13 +120,19 @@ def _start_steps(w, span, seed):
 
 
 def _timed(model, n):
+    """Time n steps; the stats carry the pass's bounds on the boot-time clock
+    (the clock of the profiler's kernel timestamps)."""
     import torch
     model.reset_stats()
     torch.cuda.synchronize()
+    b0 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
     t0 = time.perf_counter()
     model.step(n)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, model.stats()
+    dt = time.perf_counter() - t0
+    st = model.stats()
+    st["window_ns"] = [b0, time.clock_gettime_ns(time.CLOCK_BOOTTIME)]
+    return dt, st
 
 
 def _window(w, precision, start, warmup, steps, tune=True, **kw):
@@ -156,6 +162,7 @@ def _window(w, precision, start, warmup, steps, tune=True, **kw):
     st["stage_ms"] = st_ev["stage_ms"]
     st["stage_launches"] = st_ev["stage_launches"]
     st["seconds_with_events"] = dt_ev
+    st["window_ns_with_events"] = st_ev["window_ns"]
     st["autotune"] = tuned
     st["setup_s"] = setup_s
     return m, dt, st
@@ -172,6 +179,7 @@ def _report(st, dt, steps):
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
         "ms_per_step_with_stage_events": 1e3 * st["seconds_with_events"] / steps,
         "rollbacks": st["rollbacks"], "autotune": st["autotune"], "setup_s": st["setup_s"],
+        "window_boottime_ns": {"plain": st["window_ns"], "with_events": st["window_ns_with_events"]},
     }
 
 
@@ -386,7 +394,38 @@ def cpu_baseline(w, start, warmup, n_slots=24, n_slots_1core=2):
                          "sample": f"strategies 0..{k1 - 1}: {p1:.3e} pairs in {t1:.1f} s"}}
 
 
+def trace_summary(trace_csv, bench_json, leg="headline", form="surrogate_audited"):
+    """Markdown table of the kernels a rocprofv3 kernel trace (csv) records
+    inside the timed pass (without stage events) of one window of a bench
+    line: dispatches whose start lies between the pass's bounds on the
+    boot-time clock."""
+    import csv
+    line = [ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1]
+    rep = json.loads(line)[leg][form]
+    t0, t1 = rep["window_boottime_ns"]["plain"]
+    per = {}
+    with open(trace_csv) as f:
+        for row in csv.DictReader(f):
+            a, b = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+            if t0 <= a <= t1:
+                k = row["Kernel_Name"]
+                c = per.setdefault(k, [0, 0.0])
+                c[0] += 1
+                c[1] += (b - a) * 1e-3
+    steps = round(1e-6 * (t1 - t0) / rep["ms_per_step"])
+    total = sum(v[1] for v in per.values())
+    out = [f"Timed pass of `{leg}.{form}` under the profiler: {(t1 - t0) * 1e-6:.1f} ms of wall time, {steps} "
+           f"steps, {rep['ms_per_step']:.3f} ms per step in the profiled run's bench line.", "",
+           "| kernel | calls | average (us) | per step (us) | share of kernel time |", "|---|---:|---:|---:|---:|"]
+    for k, (n, us) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| `{k[:70]}` | {n} | {us / n:.1f} | {us / max(steps, 1):.1f} | {100 * us / total:.1f} % |")
+    return "\n".join(out)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--trace-summary":
+        print(trace_summary(*sys.argv[2:]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60, help="timed batched steps of the headline window")
