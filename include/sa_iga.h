@@ -266,6 +266,26 @@ int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n,
                              const double *x, double *T, double *grad);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * evaluation of sa_iga_eval_source_field with DEVICE arrays x [n][3],
+ * T [n] and grad [3][n] (component-major; may be NULL), n <= 4096 points
+ * per call (SA_EINVAL beyond: split the query).  It calls no allocating
+ * routine: everything besides the inputs and outputs lives in a fixed
+ * 11 MiB device scratch area that the library holds on each GPU it runs on
+ * until the process ends.  The work is enqueued on the object's stream
+ * (sa_iga_set_stream) and the call returns without waiting; order the use
+ * of T and grad after that stream.  Every call on a GPU, of any object,
+ * shares that GPU's scratch area, so calls that can run at the same time on
+ * one GPU race: keep them on one stream.  The source history is split into
+ * at most 64 chunks, so the sums agree with sa_iga_eval_source_field's to
+ * rounding (not bitwise).  SA_EDEVICE if the scratch area could not be
+ * located at set-up.
+ */
+int sa_iga_eval_source_field_noalloc(sa_iga *h, int32_t path, int64_t step, int64_t n, const double *x,
+                                     double *T, double *grad);
+
+/*
  * Tile-shape tuner of the kernel sum (Eqs. 7-8).  For every tile shape
  * (points per lane 1, 2, 4 x waves per workgroup 1, 2, 4, 8) it runs one
  * untimed and `reps` timed theta-steps (reps >= 1) of all paths from the

@@ -18,6 +18,7 @@
 
 #include "kernels.h"
 #include "mlp.h"
+#include "noalloc.h"
 #include "sa_internal.h"
 #include "solver.h"
 
@@ -81,6 +82,7 @@ constexpr int kBlockSlots = 8;
 struct sa_iga {
   sa::Model m;
   int device = 0;
+  void *scratch = nullptr;       // this device's fixed scratch area (allocation-free evaluation)
   hipStream_t own_stream = nullptr, stream = nullptr;   // own_stream: the device's shared solve stream
   // The source side of a step (coefficients, kernel sum, load vector,
   // Dirichlet data) runs on its own stream `ss`, one step ahead of the
@@ -1650,6 +1652,9 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     throw sa::SaError{SA_EDEVICE, std::string("device is ") + prop.gcnArchName + ", built for gfx950"};
   const DeviceStreams &ds = device_streams(h->device);
+  // the fixed scratch area's device address, taken once per device (nullptr:
+  // the allocation-free evaluation reports an error)
+  h->scratch = sa::noalloc_scratch(h->device);
   h->own_stream = ds.solve;
   h->stream = h->own_stream;
   h->lds_per_block = prop.sharedMemPerBlock;
@@ -2203,6 +2208,48 @@ void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *
   hip_check(hipGetLastError(), "kernel launch");
 }
 
+// T~ and grad T~ of path p at time step*dt at n <= kNoAllocMaxPoints
+// physical points, device arrays in and out, with the fixed scratch area for
+// everything else: enqueued on the object's stream, no allocation, no wait.
+// The source history is cut into at most kNoAllocMaxChunks chunks (the
+// chunks of a call with more sources are longer than those of
+// source_field_host, so the sums agree to rounding, not bitwise).
+void source_field_noalloc(sa_iga *h, int p, int64_t step, int64_t n, const double *x, double *T, double *grad) {
+  if (n <= 0) return;
+  const hipStream_t st = h->stream;
+  sa::PathTab tab{};
+  tab.count = 1;
+  fill_slot(h, tab, 0, p, step);
+  const int64_t n_act = tab.n_act[0], n_far = tab.n_far[0];
+  sa::SumPlan pl = make_plan(h, n, 1, n_far, n_act - n_far);
+  while (pl.n_chunks_far + pl.n_chunks_near > sa::kNoAllocMaxChunks) {
+    // far chunks stay multiples of the FP32 record block
+    if (pl.n_chunks_far >= pl.n_chunks_near) {
+      pl.chunk_far *= 2;
+      pl.n_chunks_far = (int)((n_far + pl.chunk_far - 1) / pl.chunk_far);
+    } else {
+      pl.chunk_near *= 2;
+      pl.n_chunks_near = (int)((n_act - n_far + pl.chunk_near - 1) / pl.chunk_near);
+    }
+  }
+  const int nch = pl.n_chunks_far + pl.n_chunks_near;
+  const sa::NoAllocLayout L = sa::noalloc_layout(h->scratch, n, std::max(nch, 1));
+  if (L.bytes > sa::kNoAllocScratchBytes) throw sa::SaError{SA_EINVAL, "internal: scratch layout too large"};
+  pl.nq = n;
+  pl.part_stride = L.stride;
+  sa::launch_noalloc_points(st, n, x, h->m.P.center, L);
+  if (n_act > 0) {
+    sa::CoeffParams cp{h->delta, h->shift, h->alpha, h->rc, h->m.opt.kernel_scale};
+    sa::launch_coeff(st, tab, n_act, h->stick, h->sx, h->sy, h->sz, h->sE, cp, h->c64, h->c32);
+  }
+  if (nch > 0)
+    sa::launch_sum(st, pl, tab, L.px, L.py, L.pz, L.pq2, L.fx, L.fy, L.fz, L.fq2, h->c64, h->c32, L.part);
+  // query points: role SOURCE_PLANE, so the normals and weights are not read
+  sa::launch_finalize(st, tab, true, n, nch, L.stride, L.part, L.px, L.py, L.pz, L.px, L.py, L.pz, L.px, L.role,
+                      h->m.mat.k, n, T, grad ? grad : L.G, L.ld, nullptr, 0);
+  hip_check(hipGetLastError(), "kernel launch");
+}
+
 int path_index(sa_iga *h, int32_t path) {
   if (path < 0 || path >= (int32_t)h->paths.size()) throw sa::SaError{SA_ERANGE, "path index out of range"};
   return path;
@@ -2420,6 +2467,25 @@ int sa_iga_eval_source_field(sa_iga *h, int32_t path, int64_t step, int64_t n, c
     if (!h || (n > 0 && (!x || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
     if (n < 0 || step < 0) throw sa::SaError{SA_EINVAL, "negative size or step"};
     source_field_host(h, path_index(h, path), step, n, x, T, grad);
+    return SA_OK;
+  });
+}
+
+int sa_iga_eval_source_field_noalloc(sa_iga *h, int32_t path, int64_t step, int64_t n, const double *x, double *T,
+                                     double *grad) {
+  return guarded([&]() -> int {
+    if (!h || (n > 0 && (!x || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (n < 0 || step < 0) throw sa::SaError{SA_EINVAL, "negative size or step"};
+    if (n > sa::kNoAllocMaxPoints) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "%lld points: the allocation-free evaluation takes at most %lld per call",
+                    (long long)n, (long long)sa::kNoAllocMaxPoints);
+      throw sa::SaError{SA_EINVAL, msg};
+    }
+    const int p = path_index(h, path);
+    if (n == 0) return SA_OK;
+    if (!h->scratch) throw sa::SaError{SA_EDEVICE, "the device scratch area is not available"};
+    source_field_noalloc(h, p, step, n, x, T, grad);
     return SA_OK;
   });
 }

@@ -78,6 +78,8 @@ EXPORTS = {
     "sa_iga_get_boundary_points": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "sa_iga_apply_operator": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp]),
     "sa_iga_eval_source_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, _dp, _dp, _dp]),
+    "sa_iga_eval_source_field_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p,
+                                                   C.c_void_p, C.c_void_p]),
     "sa_iga_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_double)]),
     "sa_iga_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -289,6 +291,23 @@ class Model:
         check(self._lib.sa_iga_eval_source_field(self.h, path, step, n, _ptr(x, C.c_double),
                                                  _ptr(T, C.c_double), _ptr(G, C.c_double)))
         return T, G.T.copy()
+
+    def source_field_noalloc(self, x, step: int, path: int = 0, T=None, grad=None):
+        """sa_iga_eval_source_field_noalloc on device tensors: x [n, 3]
+        float64; T [n] and grad [3, n] float64 device tensors are allocated
+        here when not given (grad=False: none).  The work is enqueued on the
+        object's stream; synchronise before reading T or grad."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()
+        n = x.shape[0]
+        if T is None:
+            T = torch.empty(n, dtype=torch.float64, device=x.device)
+        if grad is None:
+            grad = torch.empty((3, n), dtype=torch.float64, device=x.device)
+        gp = None if grad is False else C.c_void_p(grad.data_ptr())
+        check(self._lib.sa_iga_eval_source_field_noalloc(self.h, path, step, n, C.c_void_p(x.data_ptr()),
+                                                         C.c_void_p(T.data_ptr()), gp))
+        return T, (None if grad is False else grad)
 
     def eval_temperature(self, xi: np.ndarray, path: int = 0):
         xi = np.ascontiguousarray(xi, np.float64).reshape(-1, 3)
