@@ -17,6 +17,11 @@ Per theta-step n -> n+1 (t = (n+1) dt) for one scan path:
      move to the right-hand side).  The reduced matrix is constant, so it is
      factorised once by scipy's sparse LU (library primitive).
   5. T = T~ + T^ (Eq. 21) for evaluation.
+  6. Net heat-loss rate along a boundary curve (Sec. 3.1, the diagnostic of
+     the adiabatic condition): q~ + q^ = -k dT/dn = -k (grad T~ + grad T^) . n
+     at Gauss points of the edge where a face meets a neighbouring face, with
+     n the outward unit normal of the first face, and the line integrals of
+     |q~ + q^| and |q~| over the edge.
 
 Initial state: u^0 = T_c (T^(x, 0) = T_c, and T~(x, 0) = 0), F^0 = 0.
 
@@ -138,3 +143,37 @@ class Model:
         sc = self.scan
         Tt, Gt = pointsource.field(x, sc.xyz, sc.tick, sc.energy, step, sc, self.mat, self.s)
         return Tt + uh, Gt + gx, x
+
+    # -- Sec. 3.1: net heat-loss rate along an edge of a face ----------------
+    def heat_loss(self, face, edge_face, quad=4, u=None, step=None):
+        """q~ = -k grad T~ . n and q^ = -k grad T^ . n at `quad` Gauss points
+        per element of the edge where face `face` meets face `edge_face`,
+        n the outward unit normal of `face`; with the arc-length weights ds
+        and the integrals of |q~ + q^| ds and |q~| ds."""
+        d, e_d = face // 2, edge_face // 2
+        if d == e_d:
+            raise ValueError("the faces must meet along an edge")
+        e = 3 - d - e_d                                  # parametric direction along the edge
+        t, tw = iga.gauss_1d(self.patch.knots[e], quad)
+        xi = np.zeros((len(t), 3))
+        xi[:, d] = float(face % 2)
+        xi[:, e_d] = float(edge_face % 2)
+        xi[:, e] = t
+        x, J, _, _, _ = bspline.geometry(self.patch, xi)
+        ds = np.linalg.norm(J[:, :, e], axis=1) * tw
+        # outward normal: cross product of the face's tangents, oriented so
+        # that it points along the parametric direction leaving the patch
+        a, b = [c for c in range(3) if c != d]
+        n = np.cross(J[:, :, a], J[:, :, b])
+        n /= np.linalg.norm(n, axis=1)[:, None]
+        out = 1.0 if face % 2 else -1.0
+        n *= np.sign(np.einsum("qi,qi->q", n, J[:, :, d]) * out)[:, None]
+        step = self.step if step is None else step
+        sc = self.scan
+        _, Gt = pointsource.field(x, sc.xyz, sc.tick, sc.energy, step, sc, self.mat, self.s)
+        _, Gh, _ = self.evaluate(xi, u=u, step=step, correction_only=True)
+        k = self.mat.k
+        qt = -k * np.einsum("qi,qi->q", Gt, n)
+        qh = -k * np.einsum("qi,qi->q", Gh, n)
+        return {"xi": xi, "x": x, "n": n, "ds": ds, "q_tilde": qt, "q_hat": qh,
+                "net": float(np.sum(np.abs(qt + qh) * ds)), "tilde": float(np.sum(np.abs(qt) * ds))}
