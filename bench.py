@@ -179,6 +179,8 @@ def _report(st, dt, steps):
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
         "ms_per_step_with_stage_events": 1e3 * st["seconds_with_events"] / steps,
         "rollbacks": st["rollbacks"], "autotune": st["autotune"], "setup_s": st["setup_s"],
+        "pcg_iterations_per_path_step": st["pcg_iterations"] / max(st["steps"], 1),
+        "dirichlet_iterations_per_path_step": st["dirichlet_iterations"] / max(st["steps"], 1),
         "window_boottime_ns": {"plain": st["window_ns"], "with_events": st["window_ns_with_events"]},
     }
 
@@ -300,8 +302,23 @@ def run_raster(warmup):
         models[form] = m
     out["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32far"]["ms_per_step"]
     out["max_err_K_vs_fp64"] = _max_err(models["fp32far"], models["fp64"])
+    out["heat_loss_fp64"] = _heat_loss(models["fp64"])
     for m in models.values():
         m.close()
+    return out
+
+
+def _heat_loss(m, faces=(0, 1, 2, 3), top=5):
+    """The net heat-loss diagnostic (Sec. 3.1) along the top edge of each
+    lateral face at the model's current time: integrals of |q~ + q^| ds and
+    |q~| ds (W/m) and their ratio."""
+    out = {}
+    for f in faces:
+        t0 = time.perf_counter()
+        r = m.heat_loss(f, top, quad=4)
+        out[f"face{f}"] = {"net_W_per_m": r["net"], "tilde_W_per_m": r["tilde"],
+                           "ratio": r["net"] / r["tilde"] if r["tilde"] > 0 else None, "points": len(r["ds"]),
+                           "ms": 1e3 * (time.perf_counter() - t0)}
     return out
 
 
@@ -349,6 +366,7 @@ def run_small():
     n = int(w.scan.n_steps[0])
     m, dt, st = _window(w, W.PRECISION_FP64, None, 0, n, tune=False)
     r = _report(st, dt, n)
+    r["heat_loss"] = _heat_loss(m)
     m.close()
     r["workload"] = (f"small block 2x1x1 mm, quadratic B-splines 16x8x8, one track, 40 W, 1 m/s, 10 sources/step, "
                      f"all {n} steps, FP64")

@@ -239,6 +239,24 @@ int sa_iga_eval_temperature(sa_iga *h, int32_t path, int64_t n, const double *xi
                             double *T, double *gradT);
 
 /*
+ * Net heat-loss rate along a boundary edge (Sec. 3.1, the check of the
+ * adiabatic condition, Tables 3-4): at `quad` (1..16) Gauss points per
+ * element of the edge where parametric face `face` meets face `edge_face`
+ * (faces of different directions, e.g. a lateral face and the top), at path
+ * `path`'s current time,
+ *   q~ = -k grad T~ . n,  q^ = -k grad T^ . n      (n: outward unit normal of `face`)
+ * and the line integrals integrals[0] = int |q~ + q^| ds, integrals[1] =
+ * int |q~| ds over the edge.  Host outputs, any may be NULL: x [n][3] the
+ * points, normal [n][3], ds [n] the arc-length weights, q_tilde [n], q_hat [n].
+ * *n_pts: on input the capacity of the per-point arrays, on output the
+ * number of points n (elements along the edge x quad); with every output
+ * NULL the call only sets *n_pts.  SA_EINVAL for faces that do not meet,
+ * quad out of range or arrays shorter than n (*n_pts is then set to n).
+ */
+int sa_iga_heat_loss(sa_iga *h, int32_t path, int32_t face, int32_t edge_face, int32_t quad, int64_t *n_pts,
+                     double *x, double *normal, double *ds, double *q_tilde, double *q_hat, double *integrals);
+
+/*
  * Copy the current fields of path `path` to host arrays (any may be NULL):
  * T_gp [n_bpts] and grad_gp [3][n_bpts] (component-major) = T~ and
  * grad T~ at the boundary points at the path's current time (as summed by

@@ -113,6 +113,16 @@ void launch_finalize(hipStream_t st, const PathTab &tab, bool by_slot, int64_t n
                      const int8_t *role, double kcond, int64_t ostride, double *T, double *g, double *ld,
                      const double *net, int64_t net_stride);
 
+// net heat-loss rate at n edge points: grad T^ = sum_e (gx, gy, gz)[e] u[col[e]]
+// over the CSR row of each point, q~ = -k G . n (G [3][gstride], the source
+// field's gradient), q^ = -k grad T^ . n (nrm [n][3]); qt, qh [n]; the
+// integrands |q~ + q^| ds and |q~| ds in fnet, ftil [n] and their sums, in a
+// fixed order, in integrals [2]
+void launch_heat_loss(hipStream_t st, int64_t n, const int64_t *rowptr, const int32_t *col, const double *gx,
+                      const double *gy, const double *gz, const double *u, const double *G, int64_t gstride,
+                      const double *nrm, const double *ds, double kcond, double *qt, double *qh, double *fnet,
+                      double *ftil, double *integrals);
+
 // out[r] = sum_e val[e] * in[col[e]] over rows [0, nrow) of a CSR
 void launch_gather(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,
                    const double *val, const double *in, double *out);

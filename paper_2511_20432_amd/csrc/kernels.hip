@@ -589,6 +589,59 @@ __global__ void k_finalize(PathTab tab, int by_slot, int64_t nq, int n_chunks, i
   ld[q] = d;
 }
 
+// net heat-loss rate at edge points (Sec. 3.1): grad T^ from the CSR rows of
+// basis gradients and the control values u, q~ = -k grad T~ . n,
+// q^ = -k grad T^ . n, and the integrands |q~ + q^| ds, |q~| ds
+__global__ void k_heat_loss(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ gx, const double *__restrict__ gy,
+                            const double *__restrict__ gz, const double *__restrict__ u,
+                            const double *__restrict__ G, int64_t gstride, const double *__restrict__ nrm,
+                            const double *__restrict__ ds, double kcond, double *__restrict__ qt,
+                            double *__restrict__ qh, double *__restrict__ fnet, double *__restrict__ ftil) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const double w = u[col[e]];
+    g0 = fma(gx[e], w, g0);
+    g1 = fma(gy[e], w, g1);
+    g2 = fma(gz[e], w, g2);
+  }
+  const double n0 = nrm[3 * i], n1 = nrm[3 * i + 1], n2 = nrm[3 * i + 2];
+  const double a = -kcond * (G[i] * n0 + G[gstride + i] * n1 + G[2 * gstride + i] * n2);
+  const double b = -kcond * (g0 * n0 + g1 * n1 + g2 * n2);
+  qt[i] = a;
+  qh[i] = b;
+  fnet[i] = fabs(a + b) * ds[i];
+  ftil[i] = fabs(a) * ds[i];
+}
+
+// out[0] = sum a[0..n), out[1] = sum b[0..n) by one block in a fixed order
+__global__ void k_sum_pair(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                           double *__restrict__ out) {
+  double sa = 0.0, sb = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    sa += a[i];
+    sb += b[i];
+  }
+  sa = block_sum(sa);
+  sb = block_sum(sb);
+  if (threadIdx.x == 0) {
+    out[0] = sa;
+    out[1] = sb;
+  }
+}
+
+void launch_heat_loss(hipStream_t st, int64_t n, const int64_t *rowptr, const int32_t *col, const double *gx,
+                      const double *gy, const double *gz, const double *u, const double *G, int64_t gstride,
+                      const double *nrm, const double *ds, double kcond, double *qt, double *qh, double *fnet,
+                      double *ftil, double *integrals) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_heat_loss, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, rowptr, col,
+                     gx, gy, gz, u, G, gstride, nrm, ds, kcond, qt, qh, fnet, ftil);
+  hipLaunchKernelGGL(k_sum_pair, dim3(1), dim3(kBlock), 0, st, n, fnet, ftil, integrals);
+}
+
 void launch_finalize(hipStream_t st, const PathTab &tab, bool by_slot, int64_t nq, int n_chunks,
                      int64_t part_stride, const double *part, const double *px, const double *py,
                      const double *pz, const double *nx, const double *ny, const double *nz, const double *wdS,

@@ -1641,6 +1641,110 @@ const DeviceStreams &device_streams(int device) {
   return pool.emplace(device, d).first->second;
 }
 
+// inverse of a dense SPD matrix (row-major, n x n) by Gauss-Jordan
+// elimination with partial pivoting; false if a pivot vanishes
+bool invert_dense(std::vector<double> &a, int n) {
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+    if (!(std::fabs(a[(size_t)piv * n + c]) > 0.0)) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[(size_t)piv * n + k], a[(size_t)c * n + k]);
+        std::swap(inv[(size_t)piv * n + k], inv[(size_t)c * n + k]);
+      }
+    const double d = 1.0 / a[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      a[(size_t)c * n + k] *= d;
+      inv[(size_t)c * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+        inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+      }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+// The trace mass matrix of a single DIRICHLET face whose surface measure and
+// weights factor over its two parametric directions (the annular bottom face
+// of the quarter annulus: dS = r r'(xi1) theta'(xi0) dxi0 dxi1, weights along
+// the arc only) is a Kronecker product A (x) B of two 1-D matrices.  The
+// factors are read off the assembled matrix (A from the rows of the first
+// layer along b, B from those of the first point along a, scaled by their
+// common entry) and every entry is checked; the projection (Eq. 11) is then
+// solved exactly by the dense inverses, A^{-1} (x) B^{-1}.
+void try_kronecker_trace_mass(sa_iga *h) {
+  const sa::Model &m = h->m;
+  int nf = 0, face = -1;
+  for (int f = 0; f < 6; ++f)
+    if (m.P.role[f] == SA_FACE_DIRICHLET) {
+      nf++;
+      face = f;
+    }
+  if (nf != 1 || std::getenv("SA_IGA_NO_KRON_DIRICHLET")) return;
+  const int d = face / 2, da = (d == 0) ? 1 : 0, db = (d == 2) ? 1 : 2;
+  const int na = m.P.n[da], nb = m.P.n[db];
+  if ((int64_t)na * nb != h->nD) return;
+  const sa::Csr &M = m.mass_dir;
+  auto entry = [&](int64_t r, int64_t c) {
+    for (int64_t e = M.rowptr[r]; e < M.rowptr[r + 1]; ++e)
+      if (M.col[e] == c) return M.val[e];
+    return 0.0;
+  };
+  const double piv = entry(0, 0);
+  if (!(piv > 0.0)) return;
+  std::vector<double> A((size_t)na * na), B((size_t)nb * nb);
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < na; ++j) A[(size_t)i * na + j] = entry(i, j) / piv;
+  for (int k = 0; k < nb; ++k)
+    for (int l = 0; l < nb; ++l) B[(size_t)k * nb + l] = entry((int64_t)na * k, (int64_t)na * l);
+  double worst = 0.0, big = 0.0;
+  int64_t nnz_ab = 0;
+  for (int64_t r = 0; r < h->nD; ++r)
+    for (int64_t e = M.rowptr[r]; e < M.rowptr[r + 1]; ++e) {
+      const int64_t c = M.col[e];
+      const double v = A[(size_t)(r % na) * na + (c % na)] * B[(size_t)(r / na) * nb + (c / na)];
+      worst = std::max(worst, std::fabs(M.val[e] - v));
+      big = std::max(big, std::fabs(M.val[e]));
+    }
+  for (double a : A)
+    if (a != 0.0) nnz_ab++;
+  int64_t nnz_b = 0;
+  for (double b : B)
+    if (b != 0.0) nnz_b++;
+  nnz_ab *= nnz_b;
+  // every product entry must be an assembled entry (the matrix's pattern)
+  if (!(big > 0.0) || worst > 1e-13 * big || nnz_ab != M.rowptr[h->nD]) return;
+  if (!invert_dense(A, na) || !invert_dense(B, nb)) return;
+  if (!(sa::dir_direct_lds(na, nb) + 1024 <= h->lds_per_block && sa::dir_direct_prepare(sa::dir_direct_lds(na, nb))))
+    return;
+  const int64_t S = h->S;
+  sa::DirDirect &a = h->ddir;
+  a.na = na;
+  a.nb = nb;
+  a.Ia = dev_upload(h->owned, A, h->stream);
+  a.Ib = dev_upload(h->owned, B, h->stream);
+  a.inv_area = 1.0;
+  a.b = h->bD;
+  a.vD = h->vD;
+  a.vs = h->nDa;
+  a.dofs = h->dir_dofs;
+  a.xs = h->nd;
+  a.tmp = dev_zeros<double>(h, (size_t)S * na * nb);
+  h->dir_direct = true;
+  h->dir_exact = true;   // the projection right-hand side goes with the load gather
+}
+
 void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan) {
   sa::Model &m = h->m;
   // device and stream
@@ -1951,6 +2055,7 @@ void build_object(sa_iga *h, const sa_patch *patch, const sa_material *mat, cons
         }
       }
     }
+    if (!h->dir_exact) try_kronecker_trace_mass(h);
     if (!h->dir_exact && sa::dirichlet_fits(h->nD)) {
       sa::DirArgs &a = h->dargs;
       a = sa::DirArgs{};
@@ -2172,9 +2277,11 @@ struct TempBufs {
   }
 };
 
-// T~ and grad T~ of path p at time step*dt at n physical points (host in / host out)
-void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *x, double *T, double *grad) {
-  if (n <= 0) return;
+// T~ and grad T~ of path p at time step*dt at n physical points (host in),
+// into device arrays dT [stride] and dG [3][stride] that tb owns, on the
+// object's stream; returns the stride
+int64_t source_field_dev(sa_iga *h, TempBufs &tb, int p, int64_t step, int64_t n, const double *x, double **pT,
+                         double **pG) {
   const int64_t stride = (n + 63) / 64 * 64;
   std::vector<double> cx(n), cy(n), cz(n), q2(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -2183,7 +2290,6 @@ void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *
     cz[i] = x[3 * i + 2] - h->m.P.center[2];
     q2[i] = cx[i] * cx[i] + cy[i] * cy[i] + cz[i] * cz[i];
   }
-  TempBufs tb;
   double *dx = tb.up(cx, h->stream), *dy = tb.up(cy, h->stream), *dz = tb.up(cz, h->stream),
          *dq = tb.up(q2, h->stream);
   float *fx = tb.up(to_float(cx), h->stream), *fy = tb.up(to_float(cy), h->stream),
@@ -2199,6 +2305,17 @@ void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *
              dld);
   h->stats.pairs = keep.pairs;
   h->stats.pairs_near = keep.pairs_near;
+  *pT = dT;
+  *pG = dg;
+  return stride;
+}
+
+// T~ and grad T~ of path p at time step*dt at n physical points (host in / host out)
+void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *x, double *T, double *grad) {
+  if (n <= 0) return;
+  TempBufs tb;
+  double *dT = nullptr, *dg = nullptr;
+  const int64_t stride = source_field_dev(h, tb, p, step, n, x, &dT, &dg);
   hip_check(hipMemcpyAsync(T, dT, n * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
   if (grad)
     for (int c = 0; c < 3; ++c)
@@ -2486,6 +2603,89 @@ int sa_iga_eval_source_field_noalloc(sa_iga *h, int32_t path, int64_t step, int6
     if (n == 0) return SA_OK;
     if (!h->scratch) throw sa::SaError{SA_EDEVICE, "the device scratch area is not available"};
     source_field_noalloc(h, p, step, n, x, T, grad);
+    return SA_OK;
+  });
+}
+
+int sa_iga_heat_loss(sa_iga *h, int32_t path, int32_t face, int32_t edge_face, int32_t quad, int64_t *n_pts,
+                     double *x, double *normal, double *ds, double *q_tilde, double *q_hat, double *integrals) {
+  return guarded([&]() -> int {
+    if (!h || !n_pts) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (face < 0 || face > 5 || edge_face < 0 || edge_face > 5 || face / 2 == edge_face / 2)
+      throw sa::SaError{SA_EINVAL, "face and edge_face must be parametric faces 0..5 that meet along an edge"};
+    if (quad < 1 || quad > 16) throw sa::SaError{SA_EINVAL, "quad must be 1..16"};
+    const int p = path_index(h, path);
+    const sa::PatchData &P = h->m.P;
+    const int d = face / 2, de = edge_face / 2, e = 3 - d - de;
+    const int64_t n = (int64_t)P.b[e].n_el() * quad;
+    const bool per_point = x || normal || ds || q_tilde || q_hat;
+    if (!per_point && !integrals) {
+      *n_pts = n;
+      return SA_OK;
+    }
+    if (per_point && *n_pts < n) {
+      *n_pts = n;
+      throw sa::SaError{SA_EINVAL, "point arrays shorter than the number of edge points (returned in *n_pts)"};
+    }
+    // Gauss points of the elements along the edge, ordered by element
+    std::vector<double> g, gw;
+    sa::gauss_legendre(quad, g, gw);
+    std::vector<double> xi((size_t)3 * n), w((size_t)n), nrm((size_t)3 * n), dsv((size_t)n);
+    const sa::Basis1D &B = P.b[e];
+    for (int el = 0; el < B.n_el(); ++el) {
+      const double lo = B.t[B.span[el]], hi = B.t[B.span[el] + 1];
+      for (int k = 0; k < quad; ++k) {
+        const int64_t i = (int64_t)el * quad + k;
+        xi[3 * i + d] = (double)(face % 2);
+        xi[3 * i + de] = (double)(edge_face % 2);
+        xi[3 * i + e] = lo + 0.5 * (hi - lo) * (g[k] + 1.0);
+        w[i] = 0.5 * (hi - lo) * gw[k];
+      }
+    }
+    // arc length along the edge and the face's outward normal: the gradient
+    // of xi_d (row d of J^{-1}), signed by the side of the face
+    sa::PointEval pe;
+    for (int64_t i = 0; i < n; ++i) {
+      int span[3];
+      for (int c = 0; c < 3; ++c) span[c] = P.b[c].find_span(xi[3 * i + c]);
+      sa::eval_point(P, &xi[3 * i], span, pe);
+      const double(&J)[3][3] = pe.J;
+      dsv[i] = std::sqrt(J[0][e] * J[0][e] + J[1][e] * J[1][e] + J[2][e] * J[2][e]) * w[i];
+      // row d of J^{-1}: the cross product of the other two columns of J over det J
+      const int a = (d + 1) % 3, b = (d + 2) % 3;
+      double gd[3] = {J[1][a] * J[2][b] - J[2][a] * J[1][b], J[2][a] * J[0][b] - J[0][a] * J[2][b],
+                      J[0][a] * J[1][b] - J[1][a] * J[0][b]};
+      const double det = gd[0] * J[0][d] + gd[1] * J[1][d] + gd[2] * J[2][d];
+      const double len = std::sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
+      const double sg = ((face % 2) ? 1.0 : -1.0) * (det > 0 ? 1.0 : -1.0) / len;
+      for (int c = 0; c < 3; ++c) nrm[3 * i + c] = sg * gd[c];
+    }
+    EvalTables t = eval_tables(P, n, xi.data());
+    const hipStream_t st = h->stream;
+    TempBufs tb;
+    double *dT = nullptr, *dG = nullptr;
+    const int64_t gs = source_field_dev(h, tb, p, h->paths[p].step, n, t.x.data(), &dT, &dG);
+    int64_t *rp = tb.up(t.rowptr, st);
+    int32_t *cl = tb.up(t.col, st);
+    double *gx = tb.up(t.gx, st), *gy = tb.up(t.gy, st), *gz = tb.up(t.gz, st);
+    double *dn = tb.up(nrm, st), *dds = tb.up(dsv, st);
+    double *out = tb.alloc<double>((size_t)4 * n + 2);
+    sa::launch_heat_loss(st, n, rp, cl, gx, gy, gz, path_v(h, p), dG, gs, dn, dds, h->m.mat.k, out, out + n,
+                         out + 2 * n, out + 3 * n, out + 4 * n);
+    hip_check(hipGetLastError(), "kernel launch");
+    std::vector<double> hv((size_t)4 * n + 2);
+    hip_check(hipMemcpyAsync(hv.data(), out, hv.size() * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    hip_check(hipStreamSynchronize(st), "sync");
+    if (x) std::memcpy(x, t.x.data(), (size_t)3 * n * sizeof(double));
+    if (normal) std::memcpy(normal, nrm.data(), (size_t)3 * n * sizeof(double));
+    if (ds) std::memcpy(ds, dsv.data(), (size_t)n * sizeof(double));
+    if (q_tilde) std::memcpy(q_tilde, hv.data(), (size_t)n * sizeof(double));
+    if (q_hat) std::memcpy(q_hat, hv.data() + n, (size_t)n * sizeof(double));
+    if (integrals) {
+      integrals[0] = hv[(size_t)4 * n];
+      integrals[1] = hv[(size_t)4 * n + 1];
+    }
+    *n_pts = n;
     return SA_OK;
   });
 }

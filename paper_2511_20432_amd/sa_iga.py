@@ -80,6 +80,8 @@ EXPORTS = {
     "sa_iga_eval_source_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, _dp, _dp, _dp]),
     "sa_iga_eval_source_field_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p,
                                                    C.c_void_p, C.c_void_p]),
+    "sa_iga_heat_loss": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp, _dp,
+                                   _dp, _dp, _dp]),
     "sa_iga_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_double)]),
     "sa_iga_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -308,6 +310,21 @@ class Model:
         check(self._lib.sa_iga_eval_source_field_noalloc(self.h, path, step, n, C.c_void_p(x.data_ptr()),
                                                          C.c_void_p(T.data_ptr()), gp))
         return T, (None if grad is False else grad)
+
+    def heat_loss(self, face: int, edge_face: int, quad: int = 4, path: int = 0) -> dict:
+        """Net heat-loss rate along the edge where `face` meets `edge_face`:
+        points x, outward normals n, arc-length weights ds, q_tilde, q_hat
+        and the integrals of |q~ + q^| ds (net) and |q~| ds (tilde)."""
+        n = C.c_int64(0)
+        check(self._lib.sa_iga_heat_loss(self.h, path, face, edge_face, quad, C.byref(n), None, None, None, None,
+                                         None, None))
+        x, nrm = np.empty((n.value, 3)), np.empty((n.value, 3))
+        ds, qt, qh, integ = np.empty(n.value), np.empty(n.value), np.empty(n.value), np.empty(2)
+        check(self._lib.sa_iga_heat_loss(self.h, path, face, edge_face, quad, C.byref(n), _ptr(x, C.c_double),
+                                         _ptr(nrm, C.c_double), _ptr(ds, C.c_double), _ptr(qt, C.c_double),
+                                         _ptr(qh, C.c_double), _ptr(integ, C.c_double)))
+        return {"x": x, "n": nrm, "ds": ds, "q_tilde": qt, "q_hat": qh, "net": float(integ[0]),
+                "tilde": float(integ[1])}
 
     def eval_temperature(self, xi: np.ndarray, path: int = 0):
         xi = np.ascontiguousarray(xi, np.float64).reshape(-1, 3)
