@@ -18,8 +18,10 @@ pair of the timed steps, whether summed or replaced by the network.
 Beside it: the seed-0 batch in the FP32 far-field and FP64 forms (same
 window rules), the raster scan (one path, all 3,788 steps) in both forms,
 the quarter annulus (one path, mid-scan window) in both forms with the
-pair-by-pair kernel's rate against its VALU roofline, and the small block
-(all 150 steps).  `cpu_baseline` is the FP64 oracle's kernel sum on sampled
+pair-by-pair kernel's rate against its VALU roofline, the small block
+(all 150 steps), and the paper's own experiments on the part of Table 2
+(single source and contour scan, with the net heat-loss diagnostic along the
+top arc beside the values of Tables 3-4).  `cpu_baseline` is the FP64 oracle's kernel sum on sampled
 slots of the headline window, on every host core of the process's CPU share
 and on one core.
 
@@ -373,6 +375,57 @@ def run_small():
     return r
 
 
+# Tables 3 and 4: the paper's integrated net heat-loss rate along the top arc
+# (J s^-1 m^-1) and its percentage of the analytical field's, IGA meshes with
+# minimum element sizes 100, 68 and 50 um (context: an FEM reference decides
+# accuracy there, which is not reproduced)
+PAPER_TABLE3_IGA = {"100um": (974.0, 27.64), "68um": (323.0, 9.17), "50um": (167.0, 4.75)}
+PAPER_TABLE4_IGA_100UM = {"2ms": (2.41e4, 14.94), "3ms": (1.34e4, 8.03)}
+
+
+def run_paper_parts():
+    """The paper's experiments on the part of Table 2 (s = 2, Ti-6Al-4V), on
+    uniformly h-refined quadratic meshes named by their nominal smallest
+    element (along the arc): the single source of Sec. 3.1 after 20 steps
+    (age 1.9e-4 s) and the contour scan of Sec. 3.2 at 2 and 3 ms, with the
+    net heat-loss diagnostic along the top arc."""
+    from paper_2511_20432_amd import sa_iga
+    from paper_2511_20432_amd import workloads as W
+    meshes = {"100um": (8, 10, 20), "68um": (12, 15, 30), "50um": (16, 20, 40)}
+    out = {"e1": {}, "e2": {}}
+    for name, sp in meshes.items():
+        w = W.e1(sp)
+        t0 = time.perf_counter()
+        m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=W.PRECISION_FP64, kernel_scale=2.0))
+        t1 = time.perf_counter()
+        m.step(20)
+        t2 = time.perf_counter()
+        r = m.heat_loss(2, 5, quad=4)
+        st = m.stats()
+        out["e1"][name] = {"splits": sp, "n_dof": m.info.n_dof, "setup_s": t1 - t0, "ms_per_step": 1e3 * (t2 - t1) / 20,
+                           "pcg_iterations_per_step": st["pcg_iterations"] / 20,
+                           "net_W_per_m": r["net"], "tilde_W_per_m": r["tilde"],
+                           "percent": 100 * r["net"] / r["tilde"], "paper_iga": PAPER_TABLE3_IGA[name]}
+        m.close()
+    for name in ("100um", "50um"):
+        sp = meshes[name]
+        w = W.e2(sp)
+        m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=W.PRECISION_FP64, kernel_scale=2.0))
+        res = {"splits": sp, "n_dof": m.info.n_dof}
+        done = 0
+        t0 = time.perf_counter()
+        for tag, step in (("2ms", 200), ("3ms", 300)):
+            m.step(step - done)
+            done = step
+            r = m.heat_loss(2, 5, quad=4)
+            res[tag] = {"net_W_per_m": r["net"], "tilde_W_per_m": r["tilde"], "percent": 100 * r["net"] / r["tilde"]}
+        res["ms_per_step"] = 1e3 * (time.perf_counter() - t0) / 300
+        res["paper_iga_100um"] = PAPER_TABLE4_IGA_100UM
+        out["e2"][name] = res
+        m.close()
+    return out
+
+
 def _cpu_model():
     cpu = platform.processor() or platform.machine()
     try:
@@ -448,8 +501,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60, help="timed batched steps of the headline window")
     ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
-    ap.add_argument("--legs", default="headline,batch,raster,annulus,small",
-                    help="comma-separated subset of headline,batch,raster,annulus,small")
+    ap.add_argument("--legs", default="headline,batch,raster,annulus,small,paper",
+                    help="comma-separated subset of headline,batch,raster,annulus,small,paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device five times (the reference kernel of the HBM "
@@ -510,6 +563,9 @@ def main():
         out["annulus"] = run_annulus(warmup, max(steps, 200))
     if "small" in legs:
         out["small"] = run_small()
+    if "paper" in legs:
+        print("[bench] the paper's experiments on the Table 2 part", file=sys.stderr, flush=True)
+        out["paper_parts"] = run_paper_parts()
     if "headline" in legs and not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle kernel sum)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w5, start, warmup)
