@@ -17,7 +17,10 @@ Per theta-step n -> n+1 (t = (n+1) dt) for one scan path:
      move to the right-hand side).  The reduced matrix is constant, so it is
      factorised once by scipy's sparse LU (library primitive).
   5. T = T~ + T^ (Eq. 21) for evaluation.
-  6. Net heat-loss rate along a boundary curve (Sec. 3.1, the diagnostic of
+  6. Evaluation at physical points: the parametric point of x is the root
+     of x(xi) = x (Newton's method on the geometry map from the nearest
+     element centre, kept in [0,1]^3); points not reached are outside.
+  7. Net heat-loss rate along a boundary curve (Sec. 3.1, the diagnostic of
      the adiabatic condition): q~ + q^ = -k dT/dn = -k (grad T~ + grad T^) . n
      at Gauss points of the edge where a face meets a neighbouring face, with
      n the outward unit normal of the first face, and the line integrals of
@@ -177,3 +180,42 @@ class Model:
         qh = -k * np.einsum("qi,qi->q", Gh, n)
         return {"xi": xi, "x": x, "n": n, "ds": ds, "q_tilde": qt, "q_hat": qh,
                 "net": float(np.sum(np.abs(qt + qh) * ds)), "tilde": float(np.sum(np.abs(qt) * ds))}
+
+    # -- inverse of the geometry map and evaluation at physical points -------
+    def locate(self, x, tol=1e-13, iters=60):
+        """Parametric points xi [Q, 3] with x(xi) = x [Q, 3]; NaN where the
+        Newton iteration from the nearest element centre does not reach x
+        (the point lies outside the patch)."""
+        x = np.atleast_2d(np.asarray(x, float))
+        ctr = []
+        for e2 in bspline.elements(self.patch.knots[2]):
+            for e1 in bspline.elements(self.patch.knots[1]):
+                for e0 in bspline.elements(self.patch.knots[0]):
+                    ctr.append([0.5 * (e0[0] + e0[1]), 0.5 * (e1[0] + e1[1]), 0.5 * (e2[0] + e2[1])])
+        ctr = np.array(ctr)
+        xc = bspline.geometry(self.patch, ctr)[0]
+        P = self.patch.ctrl[..., :3].reshape(-1, 3)
+        ext = np.abs(P - 0.5 * (P.min(axis=0) + P.max(axis=0))).max()
+        d2 = ((x[:, None, :] - xc[None, :, :]) ** 2).sum(axis=-1)
+        xi = ctr[np.argmin(d2, axis=1)].copy()
+        done = np.zeros(len(x), bool)
+        for _ in range(iters):
+            xx, J, _, _, _ = bspline.geometry(self.patch, xi)
+            r = x - xx
+            done = np.linalg.norm(r, axis=1) <= tol * ext
+            if done.all():
+                break
+            step = np.linalg.solve(J, r[:, :, None])[:, :, 0]
+            xi = np.where(done[:, None], xi, np.clip(xi + step, 0.0, 1.0))
+        xi[~done] = np.nan
+        return xi
+
+    def evaluate_at(self, x, u=None, step=None):
+        """T and grad T at physical points x [Q, 3] (NaN outside the patch)."""
+        xi = self.locate(x)
+        ok = ~np.isnan(xi[:, 0])
+        T = np.full(len(xi), np.nan)
+        G = np.full((len(xi), 3), np.nan)
+        if ok.any():
+            T[ok], G[ok], _ = self.evaluate(xi[ok], u=u, step=step)
+        return T, G, xi
