@@ -413,13 +413,23 @@ def run_paper_parts():
         m = sa_iga.Model(w.patch, w.material, w.scan, W.Options(precision=W.PRECISION_FP64, kernel_scale=2.0))
         res = {"splits": sp, "n_dof": m.info.n_dof}
         done = 0
-        t0 = time.perf_counter()
+        step_s = 0.0
         for tag, step in (("2ms", 200), ("3ms", 300)):
+            t0 = time.perf_counter()
             m.step(step - done)
+            step_s += time.perf_counter() - t0
             done = step
             r = m.heat_loss(2, 5, quad=4)
             res[tag] = {"net_W_per_m": r["net"], "tilde_W_per_m": r["tilde"], "percent": 100 * r["net"] / r["tilde"]}
-        res["ms_per_step"] = 1e3 * (time.perf_counter() - t0) / 300
+            if name == "100um" and tag == "3ms":
+                # snapshots: the top surface and 50 um below it (Ti-6Al-4V liquidus 1923 K as the threshold)
+                from paper_2511_20432_amd import snapshots
+                t0s = time.perf_counter()
+                for lab, z in (("top", 2e-3), ("50um_below", 2e-3 - 50e-6)):
+                    xs, ys, T = snapshots.plane(m, z, (0.0, 0.0), (2e-3, 2e-3), (160, 160))
+                    res[f"snapshot_{lab}"] = snapshots.summary(xs, ys, T, 1923.0)
+                res["snapshot_seconds"] = time.perf_counter() - t0s
+        res["ms_per_step"] = 1e3 * step_s / 300
         res["paper_iga_100um"] = PAPER_TABLE4_IGA_100UM
         out["e2"][name] = res
         m.close()

@@ -239,6 +239,19 @@ int sa_iga_eval_temperature(sa_iga *h, int32_t path, int64_t n, const double *xi
                             double *T, double *gradT);
 
 /*
+ * T = T~ + T^ (Eq. 21) and optionally its gradient at n PHYSICAL points
+ * x [n][3] (m, host) of path `path` at its current time: each point is first
+ * mapped back to the parametric domain (the inverse of the geometry map:
+ * the nearest element centre, then Newton steps on x(xi) = x kept in
+ * [0,1]^3, to 1e-13 of the patch size).  A point that is not reached lies
+ * outside the patch and gets NaN in T, gradT and xi.  T [n], gradT [n][3]
+ * and xi [n][3] (the parametric points) are host arrays; gradT and xi may be
+ * NULL.
+ */
+int sa_iga_eval_temperature_at(sa_iga *h, int32_t path, int64_t n, const double *x, double *T, double *gradT,
+                               double *xi);
+
+/*
  * Net heat-loss rate along a boundary edge (Sec. 3.1, the check of the
  * adiabatic condition, Tables 3-4): at `quad` (1..16) Gauss points per
  * element of the edge where parametric face `face` meets face `edge_face`

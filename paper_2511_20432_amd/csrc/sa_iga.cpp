@@ -83,6 +83,7 @@ struct sa_iga {
   sa::Model m;
   int device = 0;
   void *scratch = nullptr;       // this device's fixed scratch area (allocation-free evaluation)
+  std::vector<double> el_centre, el_xi;   // element centres (physical, parametric) for the inverse map
   hipStream_t own_stream = nullptr, stream = nullptr;   // own_stream: the device's shared solve stream
   // The source side of a step (coefficients, kernel sum, load vector,
   // Dirichlet data) runs on its own stream `ss`, one step ahead of the
@@ -2686,6 +2687,117 @@ int sa_iga_heat_loss(sa_iga *h, int32_t path, int32_t face, int32_t edge_face, i
       integrals[1] = hv[(size_t)4 * n + 1];
     }
     *n_pts = n;
+    return SA_OK;
+  });
+}
+
+// Parametric point of the physical point x (inverse of the geometry map):
+// the element centre nearest to x, then Newton steps xi <- xi + J^{-1}
+// (x - x(xi)) kept in [0,1]^3, until |x - x(xi)| <= tol.  false if x is
+// not reached (it lies outside the patch).
+bool locate_point(const sa::PatchData &P, const std::vector<double> &centres, const std::vector<double> &cxi,
+                  const double x[3], double tol, double xi[3]) {
+  int64_t best = -1;
+  double bd = INFINITY;
+  for (int64_t e = 0; e < (int64_t)centres.size() / 3; ++e) {
+    const double d0 = centres[3 * e] - x[0], d1 = centres[3 * e + 1] - x[1], d2 = centres[3 * e + 2] - x[2];
+    const double d = d0 * d0 + d1 * d1 + d2 * d2;
+    if (d < bd) {
+      bd = d;
+      best = e;
+    }
+  }
+  if (best < 0) return false;
+  for (int c = 0; c < 3; ++c) xi[c] = cxi[3 * best + c];
+  sa::PointEval pe;
+  for (int it = 0; it < 60; ++it) {
+    int span[3];
+    for (int c = 0; c < 3; ++c) span[c] = P.b[c].find_span(xi[c]);
+    sa::eval_point(P, xi, span, pe);
+    const double r[3] = {x[0] - pe.x[0], x[1] - pe.x[1], x[2] - pe.x[2]};
+    const double res = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (res <= tol) return true;
+    const double(&J)[3][3] = pe.J;
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(std::fabs(det) > 0.0)) return false;
+    // J^{-1} r by Cramer's rule
+    double d[3];
+    for (int c = 0; c < 3; ++c) {
+      double M[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i][j] = (j == c) ? r[i] : J[i][j];
+      d[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+              M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) /
+             det;
+    }
+    for (int c = 0; c < 3; ++c) xi[c] = std::min(1.0, std::max(0.0, xi[c] + d[c]));
+  }
+  return false;
+}
+
+int sa_iga_eval_temperature_at(sa_iga *h, int32_t path, int64_t n, const double *x, double *T, double *gradT,
+                               double *xi_out) {
+  return guarded([&]() -> int {
+    if (!h || (n > 0 && (!x || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
+    const int p = path_index(h, path);
+    if (n == 0) return SA_OK;
+    const sa::PatchData &P = h->m.P;
+    // element centres (parametric and physical), built once per object
+    if (h->el_centre.empty()) {
+      sa::PointEval pe;
+      for (int e2 = 0; e2 < P.b[2].n_el(); ++e2)
+        for (int e1 = 0; e1 < P.b[1].n_el(); ++e1)
+          for (int e0 = 0; e0 < P.b[0].n_el(); ++e0) {
+            const int es[3] = {e0, e1, e2};
+            double c[3];
+            int span[3];
+            for (int d = 0; d < 3; ++d) {
+              span[d] = P.b[d].span[es[d]];
+              c[d] = 0.5 * (P.b[d].t[span[d]] + P.b[d].t[span[d] + 1]);
+            }
+            sa::eval_point(P, c, span, pe);
+            for (int d = 0; d < 3; ++d) {
+              h->el_xi.push_back(c[d]);
+              h->el_centre.push_back(pe.x[d]);
+            }
+          }
+    }
+    double ext = 0.0;
+    for (int64_t A = 0; A < P.ndof; ++A)
+      for (int c = 0; c < 3; ++c) ext = std::max(ext, std::fabs(P.ctrl[4 * A + c] - P.center[c]));
+    const double tol = 1e-13 * std::max(ext, 1e-300);
+    std::vector<double> xi((size_t)3 * n);
+    std::vector<int64_t> inside;
+    std::vector<double> xin;
+    for (int64_t i = 0; i < n; ++i) {
+      if (locate_point(P, h->el_centre, h->el_xi, x + 3 * i, tol, &xi[3 * i])) {
+        inside.push_back(i);
+        for (int c = 0; c < 3; ++c) xin.push_back(xi[3 * i + c]);
+      } else {
+        for (int c = 0; c < 3; ++c) xi[3 * i + c] = NAN;
+      }
+    }
+    const int64_t m = (int64_t)inside.size();
+    std::vector<double> Ti((size_t)m), Gi((size_t)3 * m);
+    if (m > 0) {
+      const int rc = sa_iga_eval_temperature(h, p, m, xin.data(), Ti.data(), Gi.data());
+      if (rc != SA_OK) throw sa::SaError{rc, sa_iga_last_error()};
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      T[i] = NAN;
+      if (gradT)
+        for (int c = 0; c < 3; ++c) gradT[3 * i + c] = NAN;
+    }
+    for (int64_t k = 0; k < m; ++k) {
+      const int64_t i = inside[k];
+      T[i] = Ti[k];
+      if (gradT)
+        for (int c = 0; c < 3; ++c) gradT[3 * i + c] = Gi[3 * k + c];
+    }
+    if (xi_out) std::memcpy(xi_out, xi.data(), xi.size() * sizeof(double));
     return SA_OK;
   });
 }

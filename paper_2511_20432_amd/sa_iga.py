@@ -80,6 +80,7 @@ EXPORTS = {
     "sa_iga_eval_source_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, _dp, _dp, _dp]),
     "sa_iga_eval_source_field_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p,
                                                    C.c_void_p, C.c_void_p]),
+    "sa_iga_eval_temperature_at": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, _dp, _dp, _dp, _dp]),
     "sa_iga_heat_loss": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp, _dp,
                                    _dp, _dp, _dp]),
     "sa_iga_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -310,6 +311,16 @@ class Model:
         check(self._lib.sa_iga_eval_source_field_noalloc(self.h, path, step, n, C.c_void_p(x.data_ptr()),
                                                          C.c_void_p(T.data_ptr()), gp))
         return T, (None if grad is False else grad)
+
+    def eval_temperature_at(self, x: np.ndarray, path: int = 0):
+        """T, grad T and the parametric points at physical points x [n, 3]
+        (NaN outside the patch)."""
+        x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        n = len(x)
+        T, G, xi = np.empty(n), np.empty((n, 3)), np.empty((n, 3))
+        check(self._lib.sa_iga_eval_temperature_at(self.h, path, n, _ptr(x, C.c_double), _ptr(T, C.c_double),
+                                                   _ptr(G, C.c_double), _ptr(xi, C.c_double)))
+        return T, G, xi
 
     def heat_loss(self, face: int, edge_face: int, quad: int = 4, path: int = 0) -> dict:
         """Net heat-loss rate along the edge where `face` meets `edge_face`:
