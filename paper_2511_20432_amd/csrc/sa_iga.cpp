@@ -201,6 +201,8 @@ struct sa_iga {
   bool blk_ok = false;
   int blk_steps = kBlockSlots;             // steps x paths per block (<= kBlockSlots)
   int blk_groups = 0, blk_pad = 0;         // sum grid cap (0: one group per item) and LDS padding
+  int n_cu = 0;                            // compute units of the device
+  int sum_groups_per_cu_batch = 8;         // matrix-core sum workgroups per compute unit, launches of >= 4 paths
   double *bF[2] = {nullptr, nullptr}, *bT[2] = {nullptr, nullptr}, *bG[2] = {nullptr, nullptr};
   double *bvD[2] = {nullptr, nullptr};
   double *bLD = nullptr, *bbD = nullptr, *btmp = nullptr;
@@ -1601,7 +1603,9 @@ void build_tensor_faces(sa_iga *h) {
     const char *g = std::getenv("SA_IGA_SUM_GROUPS_PER_CU");
     const char *gb = std::getenv("SA_IGA_SUM_GROUPS_PER_CU_BATCH");
     h->tens.max_groups = (int)((g ? std::max(0.0, std::atof(g)) : 2.0) * prop.multiProcessorCount);
-    h->tens.max_groups_batch = (gb ? std::max(0, std::atoi(gb)) : 8) * prop.multiProcessorCount;
+    h->n_cu = prop.multiProcessorCount;
+    h->sum_groups_per_cu_batch = gb ? std::max(0, std::atoi(gb)) : 8;
+    h->tens.max_groups_batch = h->sum_groups_per_cu_batch * prop.multiProcessorCount;
     // a blocked call's sum: one workgroup per work item (they retire often,
     // so the solver kernels beside the sum get compute units), with LDS
     // padding that leaves three per compute unit and room for a solver block
@@ -2943,14 +2947,91 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
               bw = w;
             }
           }
+        o.points_per_lane = bp;
+        o.waves_per_group = bw;
+        // the matrix-core sum's launch shape (tensor faces): for launches of
+        // four paths or more the workgroups per compute unit of its grid;
+        // for a blocked call its LDS padding (how many of its workgroups
+        // share a compute unit with the solver kernels beside it) and the
+        // block length.  Neither changes how the histories are chunked, so
+        // results stay bitwise the same.
+        if (h->use_tensor && S >= 4) {
+          static const int kG[4] = {8, 4, 6, 12};
+          int bg = h->sum_groups_per_cu_batch;
+          double bt = -1.0, base = -1.0;
+          for (int g : kG) {
+            h->tens.max_groups_batch = g * h->n_cu;
+            for (int p = 0; p < S; ++p)
+              h->paths[p].step = std::max<int64_t>(0, h->paths[p].n_steps / 2 - 1 - reps);
+            run_steps_checked(h, 1);
+            const auto t0 = std::chrono::steady_clock::now();
+            run_steps_checked(h, reps);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (base < 0) {
+              base = bt = ms;
+              bg = g;
+            } else if (ms < 0.97 * base && ms < bt) {
+              bt = ms;
+              bg = g;
+            }
+          }
+          h->sum_groups_per_cu_batch = bg;
+          h->tens.max_groups_batch = bg * h->n_cu;
+          best = bt;
+        }
+        if (h->use_tensor && h->blk_ok && S <= 4) {
+          // short blocked steps time noisily, and the sum's share of a step
+          // grows along a scan: each shape is timed at a quarter, half and
+          // three quarters of every path's scan, the better of two runs of
+          // 48 steps at each, and the set-up shape (the first) is left only
+          // for one at least 3 % faster
+          static const int kPad[3] = {24000, 0, 48000}, kBs[2] = {8, 4};
+          const int rb = std::max(reps, 48);
+          int bpad = h->blk_pad, bbs = h->blk_steps;
+          double bt = -1.0, base = -1.0;
+          const bool big_pad = sa::sum_tensor_prepare(48000);
+          for (int pad : kPad)
+            for (int bs : kBs) {
+              if ((pad > 24000 && !big_pad) || 2 * S > bs) continue;
+              h->blk_pad = pad;
+              h->blk_steps = bs;
+              double ms = 0.0;
+              for (int q = 1; q <= 3; ++q) {
+                double mq = -1.0;
+                for (int rep = 0; rep < 2; ++rep) {
+                  for (int p = 0; p < S; ++p)
+                    h->paths[p].step = std::max<int64_t>(0, h->paths[p].n_steps * q / 4 - 1 - rb);
+                  run_steps_checked(h, bs);
+                  const auto t0 = std::chrono::steady_clock::now();
+                  run_steps_checked(h, rb);
+                  const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                                       .count() * reps / rb;
+                  mq = mq < 0 ? t : std::min(mq, t);
+                }
+                ms += mq / 3.0;
+              }
+              if (base < 0) {
+                base = bt = ms;
+                bpad = pad;
+                bbs = bs;
+              } else if (ms < 0.97 * base && ms < bt) {
+                bt = ms;
+                bpad = pad;
+                bbs = bs;
+              }
+            }
+          if (bt >= 0) {
+            h->blk_pad = bpad;
+            h->blk_steps = bbs;
+            best = bt;
+          }
+        }
       } catch (...) {
         abandon_steps(h);
         restore();
         throw;
       }
       restore();
-      o.points_per_lane = bp;
-      o.waves_per_group = bw;
       best_ms = best / reps;
     }
     if (points_per_lane) *points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
@@ -2979,6 +3060,8 @@ int sa_iga_get_info(sa_iga *h, sa_info *info) {
     info->n_paths = (int32_t)h->paths.size();
     info->n_sources = (int64_t)h->h_tick.size();
     info->blocked_steps = h->blk_ok ? h->blk_steps : 1;
+    info->sum_groups_per_cu_batch = h->use_tensor ? h->sum_groups_per_cu_batch : 0;
+    info->block_lds_pad = h->blk_ok ? h->blk_pad : 0;
     info->n_dirichlet = h->nD;
     info->tensor_faces = h->use_tensor ? h->n_tfaces : 0;
     info->generic_points = h->use_tensor ? h->n_gen : h->nq;

@@ -177,6 +177,30 @@ def test_tile_shapes_bitwise_equal_and_autotune(monkeypatch):
                 assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("n_paths", [1, 5])
+def test_tensor_launch_shape_tuning_changes_no_bit(n_paths):
+    """The tuner's choice of the matrix-core sum's launch shape (workgroups
+    per compute unit with five paths; LDS padding and block length for the
+    blocked one-path calls) is a valid one and changes no result bit."""
+    tracks = [_track(i) for i in range(n_paths)]
+    scan = W.make_scan(tracks, 1e-5, 5, n_steps=[60] * n_paths)
+    opts = W.Options(precision=W.PRECISION_FP32_FAR, tau_near=5e-5)
+    a = _model(W.cfg1().patch, scan, options=opts)
+    b = _model(W.cfg1().patch, scan, options=opts)
+    t = b.autotune(reps=2)
+    print("tuned", n_paths, "paths:", t, flush=True)
+    if n_paths >= 4:
+        assert t["sum_groups_per_cu_batch"] in (4, 6, 8, 12)
+    else:
+        assert t["block_lds_pad"] in (0, 24000, 48000) and t["blocked_steps"] in (4, 8)
+    for k in (7, 30, 23):
+        a.step(k)
+        b.step(k)
+        for p in range(n_paths):
+            for x, y in zip(a.boundary_fields(p), b.boundary_fields(p)):
+                assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("prec", [W.PRECISION_FP64, W.PRECISION_FP32_FAR])
 def test_overlapped_steps_equal_serial_bitwise(monkeypatch, prec):
     """The source side of step n+2 (sum, load vector, Dirichlet data) runs on
