@@ -181,6 +181,7 @@ def _report(st, dt, steps):
         "stage_ms_per_step": {k: v / steps for k, v in st["stage_ms"].items()},
         "ms_per_step_with_stage_events": 1e3 * st["seconds_with_events"] / steps,
         "rollbacks": st["rollbacks"], "autotune": st["autotune"], "setup_s": st["setup_s"],
+        "host_enqueue_ms_per_step": st["host_enqueue_ms"] / steps,
         "pcg_iterations_per_path_step": st["pcg_iterations"] / max(st["steps"], 1),
         "dirichlet_iterations_per_path_step": st["dirichlet_iterations"] / max(st["steps"], 1),
         "window_boottime_ns": {"plain": st["window_ns"], "with_events": st["window_ns_with_events"]},
@@ -503,7 +504,49 @@ def trace_summary(trace_csv, bench_json, leg="headline", form="surrogate_audited
     return "\n".join(out)
 
 
+def graph_probe(kernels=12, reps=2000):
+    """Host cost on this system of issuing `kernels` small kernels as stream
+    launches and as one replay of a captured HIP graph (torch's graph capture
+    of the same elementwise kernels; no memset nodes): microseconds of host
+    time per issue of the whole set, and the device-inclusive time per set."""
+    import torch
+    torch.cuda.set_device(0)
+    xs = [torch.zeros(1024, device="cuda") for _ in range(kernels)]
+
+    def issue():
+        for x in xs:
+            x.add_(1.0)
+
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(3):
+            issue()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        issue()
+    torch.cuda.synchronize()
+    out = {}
+    for label, fn in (("stream_launches", issue), ("graph_replay", g.replay)):
+        with torch.cuda.stream(st):
+            for _ in range(50):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            t1 = time.perf_counter()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        out[label] = {"host_us_per_set": 1e6 * (t1 - t0) / reps, "us_per_set_incl_device": 1e6 * (t2 - t0) / reps}
+    out["kernels_per_set"] = kernels
+    return out
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--graph-probe":
+        print(json.dumps(graph_probe()))
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--trace-summary":
         print(trace_summary(*sys.argv[2:]))
         return

@@ -455,12 +455,38 @@ void fill_slot(const sa_iga *h, sa::PathTab &tab, int s, int p, int64_t step) {
 // T~ and grad T~ of the slots of `tab` (each at its own time) at nq points
 // (centred arrays); outputs indexed by path (boundary tables) or by slot
 // (query points)
-void sum_points(sa_iga *h, const sa::PathTab &tab, int64_t nq, int64_t stride, const double *px,
+// slots of `tab` ordered by decreasing far (then switched-on) history: the
+// sum's work items go slot by slot to the workgroups in launch order, so the
+// longest run first and the short ones fill the end of the launch
+sa::PathTab longest_first(const sa::PathTab &tab) {
+  int ord[sa::kMaxBatch];
+  for (int s = 0; s < tab.count; ++s) ord[s] = s;
+  std::stable_sort(ord, ord + tab.count, [&](int a, int b) {
+    return tab.n_far[a] != tab.n_far[b] ? tab.n_far[a] > tab.n_far[b] : tab.n_act[a] > tab.n_act[b];
+  });
+  sa::PathTab t = tab;
+  for (int s = 0; s < tab.count; ++s) {
+    const int o = ord[s];
+    t.path[s] = tab.path[o];
+    t.src0[s] = tab.src0[o];
+    t.n_act[s] = tab.n_act[o];
+    t.n_far[s] = tab.n_far[o];
+    t.now[s] = tab.now[o];
+    t.mode[s] = tab.mode[o];
+  }
+  return t;
+}
+
+void sum_points(sa_iga *h, const sa::PathTab &tab_in, int64_t nq, int64_t stride, const double *px,
                 const double *py, const double *pz, const double *pq2, const float *fx, const float *fy,
                 const float *fz, const float *fq2, const int8_t *role, const double *nx, const double *ny,
                 const double *nz, const double *wdS, bool by_slot, int64_t ostride, double *T, double *G,
                 double *ld, const double *net = nullptr, int64_t net_stride = 0, hipStream_t post = nullptr,
                 bool boundary = false, int plan_count = 0) {
+  // outputs indexed by path (not slot) and no network output indexed by
+  // slot: the slots may be taken in any order, with the same results
+  const bool reorder = !by_slot && !net && tab_in.count > 1 && !std::getenv("SA_IGA_SLOT_ORDER_AS_GIVEN");
+  const sa::PathTab tab = reorder ? longest_first(tab_in) : tab_in;
   int64_t max_act = 0, max_far = 0, max_near = 0;
   for (int s = 0; s < tab.count; ++s) {
     const int64_t nf = tab.mode[s] ? 0 : tab.n_far[s];      // far sources summed here
@@ -2429,6 +2455,7 @@ void run_steps(sa_iga *h, int32_t n_steps) {
       s += K;
     }
     flush_checks(h);
+    h->stats.host_enqueue_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (h->verbose && n_steps > 0) {
       const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
       std::fprintf(stderr,

@@ -64,7 +64,8 @@ class sa_stats(C.Structure):
                 ("pcg_last_relres", C.c_double), ("dirichlet_iterations", C.c_int64),
                 ("stage_ms", C.c_double * 8), ("stage_launches", C.c_int64 * 8),
                 ("net_steps", C.c_int64), ("pairs_net", C.c_int64), ("audits", C.c_int64),
-                ("audit_failures", C.c_int64), ("audit_max_err", C.c_double), ("rollbacks", C.c_int64)]
+                ("audit_failures", C.c_int64), ("audit_max_err", C.c_double), ("rollbacks", C.c_int64),
+                ("host_enqueue_ms", C.c_double)]
 
 
 EXPORTS = {
