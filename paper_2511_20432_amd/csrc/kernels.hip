@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -388,9 +389,20 @@ void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, co
                      pl.chunk_far, pl.chunk_near);
 }
 
+// the allowance only grows (per device), so a later object asking for less
+// never takes room from the launches of one set up before it
 bool sum_tensor_prepare(int lds_pad) {
-  return hipFuncSetAttribute((const void *)k_sum_tensor, hipFuncAttributeMaxDynamicSharedMemorySize, lds_pad) ==
-         hipSuccess;
+  static std::mutex mu;
+  static int granted[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lk(mu);
+  if (lds_pad <= granted[dev]) return true;
+  if (hipFuncSetAttribute((const void *)k_sum_tensor, hipFuncAttributeMaxDynamicSharedMemorySize, lds_pad) !=
+      hipSuccess)
+    return false;
+  granted[dev] = lds_pad;
+  return true;
 }
 
 // ---------------------------------------------------------------------------

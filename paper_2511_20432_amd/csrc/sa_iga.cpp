@@ -1640,7 +1640,11 @@ void build_tensor_faces(sa_iga *h) {
     h->blk_groups = (int)((bg ? std::max(0.0, std::atof(bg)) : 0.0) * prop.multiProcessorCount);
     h->blk_pad = pad ? std::max(0, std::min(96 * 1024, std::atoi(pad))) : 24000;
     if (h->blk_pad > 0 && !sa::sum_tensor_prepare(h->blk_pad)) h->blk_pad = 0;
-    h->tens.lds_pad = 0;
+    // launches of several paths per step: LDS padding that leaves compute
+    // units to the theta-step kernels beside the sum
+    const char *bpad = std::getenv("SA_IGA_BATCH_SUM_LDS_PAD");
+    h->tens.lds_pad = bpad ? std::max(0, std::min(96 * 1024, std::atoi(bpad))) : 24000;
+    if (h->tens.lds_pad > 0 && !sa::sum_tensor_prepare(std::max(h->tens.lds_pad, h->blk_pad))) h->tens.lds_pad = 0;
   }
   h->n_gen = (int64_t)gen.size();
   h->n_tfaces = (int)faces.size();
@@ -2983,17 +2987,22 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
         // block length.  Neither changes how the histories are chunked, so
         // results stay bitwise the same.
         if (h->use_tensor && S >= 4) {
-          static const int kG[4] = {8, 4, 6, 12};
-          int bg = h->sum_groups_per_cu_batch;
+          // workgroups per compute unit, then the LDS padding that leaves
+          // compute units to the theta-step kernels beside the sum
+          static const int kG[4] = {8, 4, 6, 12}, kBp[3] = {24000, 0, 40000};
+          int bg = h->sum_groups_per_cu_batch, bbp = h->tens.lds_pad;
           double bt = -1.0, base = -1.0;
-          for (int g : kG) {
-            h->tens.max_groups_batch = g * h->n_cu;
+          auto time_shape = [&]() {
             for (int p = 0; p < S; ++p)
               h->paths[p].step = std::max<int64_t>(0, h->paths[p].n_steps / 2 - 1 - reps);
             run_steps_checked(h, 1);
             const auto t0 = std::chrono::steady_clock::now();
             run_steps_checked(h, reps);
-            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          };
+          for (int g : kG) {
+            h->tens.max_groups_batch = g * h->n_cu;
+            const double ms = time_shape();
             if (base < 0) {
               base = bt = ms;
               bg = g;
@@ -3002,8 +3011,19 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
               bg = g;
             }
           }
-          h->sum_groups_per_cu_batch = bg;
           h->tens.max_groups_batch = bg * h->n_cu;
+          const double base_g = bt;
+          for (int pad : kBp) {
+            if (pad == bbp || !sa::sum_tensor_prepare(pad)) continue;
+            h->tens.lds_pad = pad;
+            const double ms = time_shape();
+            if (ms < 0.97 * base_g && ms < bt) {
+              bt = ms;
+              bbp = pad;
+            }
+          }
+          h->sum_groups_per_cu_batch = bg;
+          h->tens.lds_pad = bbp;
           best = bt;
         }
         if (h->use_tensor && h->blk_ok && S <= 4) {
@@ -3089,6 +3109,7 @@ int sa_iga_get_info(sa_iga *h, sa_info *info) {
     info->blocked_steps = h->blk_ok ? h->blk_steps : 1;
     info->sum_groups_per_cu_batch = h->use_tensor ? h->sum_groups_per_cu_batch : 0;
     info->block_lds_pad = h->blk_ok ? h->blk_pad : 0;
+    info->batch_lds_pad = h->use_tensor ? h->tens.lds_pad : 0;
     info->n_dirichlet = h->nD;
     info->tensor_faces = h->use_tensor ? h->n_tfaces : 0;
     info->generic_points = h->use_tensor ? h->n_gen : h->nq;

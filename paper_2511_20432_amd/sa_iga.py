@@ -55,7 +55,8 @@ class sa_info(C.Structure):
     _fields_ = [("n_ctrl", C.c_int32 * 3), ("n_dof", C.c_int64), ("n_bpts", C.c_int64),
                 ("face_offset", C.c_int64 * 7), ("n_paths", C.c_int32), ("n_sources", C.c_int64),
                 ("n_dirichlet", C.c_int64), ("tensor_faces", C.c_int32), ("generic_points", C.c_int64),
-                ("blocked_steps", C.c_int32), ("sum_groups_per_cu_batch", C.c_int32), ("block_lds_pad", C.c_int32)]
+                ("blocked_steps", C.c_int32), ("sum_groups_per_cu_batch", C.c_int32), ("block_lds_pad", C.c_int32),
+                ("batch_lds_pad", C.c_int32)]
 
 
 class sa_stats(C.Structure):
@@ -261,7 +262,8 @@ class Model:
         self.info = self.get_info()
         return {"points_per_lane": p.value, "waves_per_group": w.value, "ms_per_step": ms.value,
                 "sum_groups_per_cu_batch": self.info.sum_groups_per_cu_batch,
-                "block_lds_pad": self.info.block_lds_pad, "blocked_steps": self.info.blocked_steps}
+                "batch_lds_pad": self.info.batch_lds_pad, "block_lds_pad": self.info.block_lds_pad,
+                "blocked_steps": self.info.blocked_steps}
 
     def boundary_fields(self, path: int = 0):
         """T~ [nq], grad T~ [nq, 3] at the boundary points, F [n_dof] and
