@@ -59,7 +59,8 @@ FLOPS_PER_PAIR = 8
 LANE_OPS = 256 * 64 * 2.4e9
 SLOTS_FP32_PAIR = 13
 SLOTS_FP64_PAIR = 28
-# HBM bytes per k_sum_tensor launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# HBM bytes per sum-stage launch (k_sum_tensor_far + k_sum_tensor_near) from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a 256 MiB copy (bench.py --copy-calibration),
 # per batched step of the headline window.  None until the counters are taken
 # on the kernel as it now is.
@@ -69,7 +70,7 @@ WINDOW_START = "each strategy at a seeded step in [0, L - warmup - steps) with a
 
 
 def _k_sum_traffic(launches_per_step=1.0):
-    """HBM bytes (read + written) of one k_sum_tensor launch, or None."""
+    """HBM bytes (read + written) of one sum-stage launch, or None."""
     t = K_SUM_TRAFFIC
     if not t:
         return None
@@ -589,8 +590,9 @@ def main():
         a = head["surrogate_audited"]
         roof = dict(a["sum_roofline"])
         roof.update({"traffic": _k_sum_traffic(a["sum_launches_per_step"]),
-                     "traffic_unit": "HBM bytes per k_sum_tensor launch (read + written)",
-                     "kernel": "k_sum_tensor (far chunks FP32, near chunks FP64), the dominant kernel of the window",
+                     "traffic_unit": "HBM bytes per sum-stage launch (read + written)",
+                     "kernel": "the matrix-core kernel sum (k_sum_tensor_far: far chunks FP32; k_sum_tensor_near: "
+                               "near chunks FP64), the dominant stage of the window",
                      "avg_ms_per_launch": a["sum_ms_per_launch"], "launches_per_step": a["sum_launches_per_step"],
                      "pairs_per_launch": a["pairs_per_step"] / max(a["sum_launches_per_step"], 1e-30)})
         out.update({

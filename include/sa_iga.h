@@ -159,8 +159,8 @@ typedef struct {
                                   paths or more (0: no tensor faces) */
   int32_t block_lds_pad;       /* matrix-core sum of a blocked call: extra LDS bytes per workgroup, which
                                   leaves compute-unit room to the solver kernels beside it */
-  int32_t batch_lds_pad;       /* the same for a launch of four paths or more (default 24000; 0: no
-                                  tensor faces) */
+  int32_t batch_lds_pad;       /* the same for a launch of four paths or more (default 10000; 0
+                                  without tensor faces) */
 } sa_info;
 
 enum sa_stage {
@@ -339,9 +339,10 @@ int sa_iga_eval_source_field_noalloc(sa_iga *h, int32_t path, int64_t step, int6
  * == 0) the pair-by-pair kernel does not run and only the default shape
  * (2 points per lane, 4 waves) is timed.  With tensor faces the launch shape
  * of the matrix-core sum is tuned the same way: with four paths or more its
- * workgroups per compute unit (4, 6, 8, 12), then its LDS padding (0, 24000,
- * 40000 bytes), and for the blocked calls of up
- * to four paths its LDS padding (0, 24000, 48000 bytes) and block length
+ * workgroups per compute unit (4, 6, 8, 12), then its LDS padding (0, 10000,
+ * 38000 bytes: three, two or one workgroup per compute unit), and for the
+ * blocked calls of up to four paths its LDS padding (the same three) and
+ * block length
  * (4, 8 steps; timed at a quarter, half and three quarters of the scans, the
  * better of two runs of at least 48 steps at each); the set-up shape is kept
  * unless another is at least 3 % faster.  The choice is reported in

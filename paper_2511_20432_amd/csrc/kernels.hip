@@ -159,34 +159,230 @@ void launch_coeff(hipStream_t st, const PathTab &tab, int64_t max_act, const int
 // and its gradient A e^{c r^2} 2c (x - x_i) has the components
 //   along a: L (2c da R),  along b: (2c db L) R,  along n: (2c dn L) R.
 // Over the sources of a chunk the four sums at the points of a 32 x 32 tile
-// are therefore matrix products [b x i] [i x a]: 16 x 16 x 4 matrix-core
-// steps, 4 sources per step, with the operands formed in the lanes (one
-// exponential per row or column and source instead of one per pair).  The
-// four waves of a workgroup take the four 16 x 16 blocks of a tile and share
-// the chunk's sources, staged in LDS 256 at a time.
-// Operand layout of the 16 x 16 x 4 steps: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16]; element r of lane l is D[4 (l / 16) + r][l % 16] for
-// FP32 and D[4 r + l / 16][l % 16] for FP64 (checked on the device).
+// are therefore matrix products [b x i] [i x a] on the matrix cores, with the
+// operands formed in the lanes (one exponential per row or column and source
+// instead of one per pair), the chunk's sources staged in LDS 256 at a time.
 // Far chunks: FP32 operands (coordinates relative to the tile) and
-// accumulation, folded into FP64 every 16 steps; near chunks: FP64.
+// accumulation over 64 sources, then FP64 (32 x 32 x 2 steps); near chunks:
+// FP64 (16 x 16 x 4 steps).  The operand layouts are given at each kind of
+// item (checked on the device).
 // ---------------------------------------------------------------------------
 typedef double dx4 __attribute__((ext_vector_type(4)));
-typedef float fx4 __attribute__((ext_vector_type(4)));
+typedef float fx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kStage = 256;   // sources staged in LDS at a time
 
-// one work item (tile, chunk of this kind, slot).  Staged per source in
-// LDS.  FP64 steps: c, x_a, x_b, 2 c dn, ln A + c dn^2.  FP32 steps (base 2,
-// coordinates relative to the tile's first point, where they are small for
-// the sources near the tile, the ones that matter), one 32-byte record per
-// source: c log2 e, x_a - o_a, x_b - o_b, 2 c dn, (ln A + c dn^2) log2 e, 2 c.
-template <bool FAR>
-__device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
-                                            int n_chunks, int chunk_far, int chunk_near, double (*src)[kStage],
-                                            float4 (*srf)[2]) {
+// Shared by the two kinds of work item (tile, chunk, slot): the chunk's
+// source range, the source arrays along the face's axes, and the loads of
+// one source's data (coefficients and position), issued a block ahead.
+struct ItemSrc {
+  int slot, lo, hi;
+  int64_t s0, now;
+  const double *c64, *pa, *pb, *pn;
+};
+
+__device__ __forceinline__ ItemSrc item_sources(const TensorArgs &ta, const PathTab &tab, const TFace &F, int slot,
+                                                int lo, int hi) {
+  ItemSrc r;
+  r.slot = slot;
+  r.lo = lo;
+  r.hi = hi;
+  r.s0 = tab.src0[slot];
+  r.now = tab.now[slot];
+  r.c64 = ta.c64 + r.s0 * kCoefStride;
+  r.pa = (F.ax_a == 0 ? ta.sx : (F.ax_a == 1 ? ta.sy : ta.sz)) + r.s0;
+  r.pb = (F.ax_b == 0 ? ta.sx : (F.ax_b == 1 ? ta.sy : ta.sz)) + r.s0;
+  r.pn = (F.ax_n == 0 ? ta.sx : (F.ax_n == 1 ? ta.sy : ta.sz)) + r.s0;
+  return r;
+}
+
+struct SrcRegs {
+  double c, lnA, xa, xb, xn;
+};
+
+__device__ __forceinline__ void fetch_source(const TensorArgs &ta, const ItemSrc &is, int blk, SrcRegs &v) {
+  const int i = blk + (int)threadIdx.x;
+  if (i < is.hi) {
+    if (ta.age_c) {
+      const int64_t a = is.now - ta.tick[is.s0 + i];
+      v.c = ta.age_c[a];
+      v.lnA = ta.src_le[is.s0 + i] + ta.age_l[a];
+    } else {
+      v.c = is.c64[(int64_t)i * kCoefStride];
+      v.lnA = is.c64[(int64_t)i * kCoefStride + 5];
+    }
+    v.xa = is.pa[i];
+    v.xb = is.pb[i];
+    v.xn = is.pn[i];
+  }
+}
+
+// Far item: FP32 32 x 32 x 2 matrix-core steps.  The workgroup's tile is
+// 32 x 32 points (rows b, columns a); each wave takes a quarter of every
+// staged block of 256 sources (2 sources per step, 32 steps) for the whole
+// tile, so every L row and R column value is formed once per source.  After
+// each block the waves' FP32 sums (64 sources each) go to LDS and every
+// thread adds the four of each of its 16 outputs, in wave order, to its FP64
+// accumulators (the same summation at every launch shape).  Staged record
+// per source (base 2, coordinates relative to the tile's first point, where
+// they are small for the sources near the tile, the ones that matter):
+// c log2 e, x_a - o_a, x_b - o_b, 2 c dn | (ln A + c dn^2) log2 e, 2 c.
+// Layout of a 32 x 32 x 2 step: lane l holds A[l % 32][l / 32] and
+// B[l / 32][l % 32]; element r of lane l is D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+constexpr int kFarPad = 36;                              // LDS column stride of the wave sums (floats)
+constexpr int kFarSumBytes = 4 * 2 * 32 * kFarPad * 4;   // 4 waves x 2 kinds x 32 columns (one pass)
+constexpr int kTensorLds = kStage * 32 + kFarSumBytes;   // far: records + wave sums; near: 5 kStage doubles
+static_assert(kTensorLds >= 5 * kStage * 8, "near items stage 5 doubles per source");
+
+__device__ __forceinline__ void tensor_far(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
+                                           int n_chunks, int chunk_far, unsigned char *lds) {
+  float4 (*srf)[2] = (float4(*)[2])lds;
+  float *wsum = (float *)(lds + kStage * 32);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 31, k = lane >> 5;
+  const int tile = item % ta.n_tiles;
+  const int ck = (item / ta.n_tiles) % n_chunks_far;
+  const int slot = item / (ta.n_tiles * n_chunks_far);
+  const int4 tl = ta.tiles[tile];
+  const TFace F = ta.faces[tl.x];
+  const int lo = ck * chunk_far;
+  const int e = lo + chunk_far < tab.n_far[slot] ? lo + chunk_far : tab.n_far[slot];
+  const ItemSrc is = item_sources(ta, tab, F, slot, lo, tab.mode[slot] ? lo : e);
+  const int bi = tl.y + i, ai = tl.z + i;
+  const bool vb = bi < F.nb, va = ai < F.na;
+  const double ob = F.sb[tl.y], oa = F.sa[tl.z];
+  const float sbr = (float)(F.sb[vb ? bi : tl.y] - ob), sar = (float)(F.sa[va ? ai : tl.z] - oa);
+  const bool full_tile = tl.y + 32 <= F.nb && tl.z + 32 <= F.na;
+  // this thread's outputs: column rc, rows rr .. rr + 3, of each sum
+  const int rc = threadIdx.x & 31, rr = 4 * (threadIdx.x >> 5);
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  fx16 accf[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accf[g][r] = 0.f;
+  const double l2e = 1.4426950408889634;
+  SrcRegs nx{0.0, 0.0, 0.0, 0.0, 0.0};
+  if (is.lo < is.hi) fetch_source(ta, is, is.lo, nx);
+  for (int blk = is.lo; blk < is.hi; blk += kStage) {
+    const int n_in = is.hi - blk < kStage ? is.hi - blk : kStage;
+    __syncthreads();
+    if ((int)threadIdx.x < n_in) {
+      const double c = nx.c, dn = F.sn - nx.xn;
+      const double base = fma(c * dn, dn, nx.lnA);
+      srf[threadIdx.x][0] = make_float4((float)(c * l2e), (float)(nx.xa - oa), (float)(nx.xb - ob),
+                                        (float)(2.0 * c * dn));
+      srf[threadIdx.x][1] = make_float4((float)(base * l2e), (float)(2.0 * c), 0.f, 0.f);
+    }
+    if (blk + kStage < is.hi) fetch_source(ta, is, blk + kStage, nx);
+    __syncthreads();
+    if (n_in == kStage && full_tile) {
+      const int w0 = 64 * wave;
+      // every source and every point valid: no masks
+#pragma unroll
+      for (int st = 0; st < 32; ++st) {
+        const int t = w0 + 2 * st + k;
+        const float4 u0 = srf[t][0], u1 = srf[t][1];
+        const float cl = u0.x, xa = u0.y, xb = u0.z, tn = u0.w, base = u1.x, c2 = u1.y;
+        const float db = sbr - xb, da = sar - xa;
+        const float L0 = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
+        const float Lb = L0 * (c2 * db);
+        const float Ln = L0 * tn;
+        const float R0 = __builtin_amdgcn_exp2f(cl * (da * da));
+        const float Ra = R0 * (c2 * da);
+        accf[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(L0, R0, accf[0], 0, 0, 0);
+        accf[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(L0, Ra, accf[1], 0, 0, 0);
+        accf[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(Lb, R0, accf[2], 0, 0, 0);
+        accf[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(Ln, R0, accf[3], 0, 0, 0);
+      }
+    } else {
+      // a part block: its source pairs spread evenly over the waves; the
+      // sources past the block and the points past the face contribute zeros
+      const int pairs = (n_in + 1) / 2, per = (pairs + 3) / 4;
+      const int p0 = wave * per, p1 = p0 + per < pairs ? p0 + per : pairs;
+      for (int st = p0; st < p1; ++st) {
+        int t = 2 * st + k;
+        const bool vi = t < n_in;
+        t = vi ? t : n_in - 1;
+        const float4 u0 = srf[t][0], u1 = srf[t][1];
+        const float cl = u0.x, xa = u0.y, xb = u0.z, tn = u0.w, base = u1.x, c2 = u1.y;
+        const float db = sbr - xb, da = sar - xa;
+        const float el = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
+        const float L0 = (vi && vb) ? el : 0.f;
+        const float Lb = L0 * (c2 * db);
+        const float Ln = L0 * tn;
+        const float er = __builtin_amdgcn_exp2f(cl * (da * da));
+        const float R0 = va ? er : 0.f;
+        const float Ra = R0 * (c2 * da);
+        accf[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(L0, R0, accf[0], 0, 0, 0);
+        accf[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(L0, Ra, accf[1], 0, 0, 0);
+        accf[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(Lb, R0, accf[2], 0, 0, 0);
+        accf[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(Ln, R0, accf[3], 0, 0, 0);
+      }
+    }
+    // fold, two sums at a time: the waves' FP32 sums into LDS ([wave][sum]
+    // [column][row], 4 consecutive rows per lane and element group), then
+    // each thread's outputs in FP64, wave 0 first
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) __syncthreads();
+#pragma unroll
+      for (int gg = 0; gg < 2; ++gg) {
+        const int g = 2 * h + gg;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          *(float4 *)(wsum + ((wave * 2 + gg) * 32 + i) * kFarPad + 8 * m + 4 * k) =
+              make_float4(accf[g][4 * m], accf[g][4 * m + 1], accf[g][4 * m + 2], accf[g][4 * m + 3]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accf[g][r] = 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int gg = 0; gg < 2; ++gg) {
+        const int g = 2 * h + gg;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const float4 v = *(const float4 *)(wsum + ((w * 2 + gg) * 32 + rc) * kFarPad + rr);
+          acc[4 * g] += (double)v.x;
+          acc[4 * g + 1] += (double)v.y;
+          acc[4 * g + 2] += (double)v.z;
+          acc[4 * g + 3] += (double)v.w;
+        }
+      }
+    }
+  }
+  // a wave's threads write 32 consecutive points of each of two rows
+  double *o = ta.part + ((int64_t)slot * n_chunks + ck) * 5 * ta.stride;
+  const int64_t S = ta.stride;
+  const int ac = tl.z + rc;
+  if (ac < F.na) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int br = tl.y + rr + r;
+      if (br >= F.nb) continue;
+      const int64_t q = F.off + (int64_t)br * F.na + ac;
+      o[q] = acc[r];
+      o[S + q] = 0.0;
+      o[(2 + F.ax_a) * S + q] = acc[4 + r];
+      o[(2 + F.ax_b) * S + q] = acc[8 + r];
+      o[(2 + F.ax_n) * S + q] = acc[12 + r];
+    }
+  }
+  __syncthreads();   // the staged sources and sums of this item are no longer read
+}
+
+// Near item: FP64 16 x 16 x 4 matrix-core steps, the four waves on the four
+// 16 x 16 blocks of the tile, 4 sources per step.  Staged per source: c,
+// x_a, x_b, 2 c dn, ln A + c dn^2.  Element r of lane l of a step is
+// D[4 r + l / 16][l % 16].
+__device__ __forceinline__ void tensor_near(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
+                                            int n_chunks, int chunk_near, unsigned char *lds) {
+  double(*src)[kStage] = (double(*)[kStage])lds;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, k = lane >> 4;
-  const int n_kind = FAR ? n_chunks_far : n_chunks - n_chunks_far;
+  const int n_kind = n_chunks - n_chunks_far;
   const int tile = item % ta.n_tiles;
   const int ck = (item / ta.n_tiles) % n_kind;
   const int slot = item / (ta.n_tiles * n_kind);
@@ -194,163 +390,55 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
   const TFace F = ta.faces[tl.x];
   // this wave's 16 x 16 block of the tile: rows b, columns a
   const int b0 = tl.y + 16 * (wave >> 1), a0 = tl.z + 16 * (wave & 1);
-  const int chunk = FAR ? ck : n_chunks_far + ck;
-  int lo, hi;
-  if (FAR) {
-    lo = ck * chunk_far;
-    const int e = lo + chunk_far < tab.n_far[slot] ? lo + chunk_far : tab.n_far[slot];
-    hi = tab.mode[slot] ? lo : e;
-  } else {
-    lo = tab.n_far[slot] + ck * chunk_near;
-    hi = lo + chunk_near < tab.n_act[slot] ? lo + chunk_near : tab.n_act[slot];
-  }
-  const int64_t s0 = tab.src0[slot], now = tab.now[slot];
-  const double *c64 = ta.c64 + s0 * kCoefStride;
-  const double *pa = (F.ax_a == 0 ? ta.sx : (F.ax_a == 1 ? ta.sy : ta.sz)) + s0;
-  const double *pb = (F.ax_b == 0 ? ta.sx : (F.ax_b == 1 ? ta.sy : ta.sz)) + s0;
-  const double *pn = (F.ax_n == 0 ? ta.sx : (F.ax_n == 1 ? ta.sy : ta.sz)) + s0;
+  const int lo = tab.n_far[slot] + ck * chunk_near;
+  const ItemSrc is = item_sources(ta, tab, F, slot, lo,
+                                  lo + chunk_near < tab.n_act[slot] ? lo + chunk_near : tab.n_act[slot]);
   const int bi = b0 + j, ai = a0 + j;
   const bool vb = bi < F.nb, va = ai < F.na;
   const double sb = F.sb[vb ? bi : 0], sa = F.sa[va ? ai : 0];
-  const double ob = F.sb[tl.y], oa = F.sa[tl.z];
-  const float sbr = (float)(sb - ob), sar = (float)(sa - oa);
-  const bool full_tile = b0 + 16 <= F.nb && a0 + 16 <= F.na;
-  // acc[g]: g = 0 T, 1 along a, 2 along b, 3 along n
   dx4 acc[4];
-  fx4 accf[4];
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    acc[g] = dx4{0.0, 0.0, 0.0, 0.0};
-    accf[g] = fx4{0.f, 0.f, 0.f, 0.f};
-  }
-  const double l2e = 1.4426950408889634;
-  // the next block's source data is loaded into registers while the current
-  // block is summed
-  double pc = 0.0, plnA = 0.0, ppa = 0.0, ppb = 0.0, ppn = 0.0;
-  auto fetch = [&](int blk) {
-    const int i = blk + (int)threadIdx.x;
-    if (i < hi) {
-      if (ta.age_c) {
-        const int64_t a = now - ta.tick[s0 + i];
-        pc = ta.age_c[a];
-        plnA = ta.src_le[s0 + i] + ta.age_l[a];
-      } else {
-        pc = c64[(int64_t)i * kCoefStride];
-        plnA = c64[(int64_t)i * kCoefStride + 5];
-      }
-      ppa = pa[i];
-      ppb = pb[i];
-      ppn = pn[i];
-    }
-  };
-  if (lo < hi) fetch(lo);
-  for (int blk = lo; blk < hi; blk += kStage) {
-    const int n_in = hi - blk < kStage ? hi - blk : kStage;
+  for (int g = 0; g < 4; ++g) acc[g] = dx4{0.0, 0.0, 0.0, 0.0};
+  SrcRegs nx{0.0, 0.0, 0.0, 0.0, 0.0};
+  if (is.lo < is.hi) fetch_source(ta, is, is.lo, nx);
+  for (int blk = is.lo; blk < is.hi; blk += kStage) {
+    const int n_in = is.hi - blk < kStage ? is.hi - blk : kStage;
     __syncthreads();
     if ((int)threadIdx.x < n_in) {
-      const double c = pc, lnA = plnA;
-      const double dn = F.sn - ppn;
-      const double base = fma(c * dn, dn, lnA);
-      if (FAR) {
-        srf[threadIdx.x][0] = make_float4((float)(c * l2e), (float)(ppa - oa), (float)(ppb - ob),
-                                          (float)(2.0 * c * dn));
-        srf[threadIdx.x][1] = make_float4((float)(base * l2e), (float)(2.0 * c), 0.f, 0.f);
-      } else {
-        src[0][threadIdx.x] = c;
-        src[1][threadIdx.x] = ppa;
-        src[2][threadIdx.x] = ppb;
-        src[3][threadIdx.x] = 2.0 * c * dn;
-        src[4][threadIdx.x] = base;
-      }
+      const double c = nx.c, dn = F.sn - nx.xn;
+      src[0][threadIdx.x] = c;
+      src[1][threadIdx.x] = nx.xa;
+      src[2][threadIdx.x] = nx.xb;
+      src[3][threadIdx.x] = 2.0 * c * dn;
+      src[4][threadIdx.x] = fma(c * dn, dn, nx.lnA);
     }
-    if (blk + kStage < hi) fetch(blk + kStage);
+    if (blk + kStage < is.hi) fetch_source(ta, is, blk + kStage, nx);
     __syncthreads();
-    if (FAR) {
-      // groups of 16 steps (64 sources), then into FP64; the steps past the
-      // staged sources contribute zeros
-      for (int g16 = 0; g16 < n_in; g16 += 64) {
-        if (g16 + 64 <= n_in && full_tile) {
-          // every source and every point of the block valid: no masks
-#pragma unroll
-          for (int s16 = 0; s16 < 16; ++s16) {
-            const int t = g16 + 4 * s16 + k;
-            const float4 u0 = srf[t][0], u1 = srf[t][1];
-            const float cl = u0.x, xa = u0.y, xb = u0.z, tn = u0.w, base = u1.x, c2 = u1.y;
-            const float db = sbr - xb, da = sar - xa;
-            const float L0 = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
-            const float Lb = L0 * (c2 * db);
-            const float Ln = L0 * tn;
-            const float R0 = __builtin_amdgcn_exp2f(cl * (da * da));
-            const float Ra = R0 * (c2 * da);
-            accf[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, R0, accf[0], 0, 0, 0);
-            accf[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, Ra, accf[1], 0, 0, 0);
-            accf[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(Lb, R0, accf[2], 0, 0, 0);
-            accf[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ln, R0, accf[3], 0, 0, 0);
-          }
-          // scheduling: each matrix-core step interleaved with three VALU
-          // operations of the steps that follow
-#pragma unroll
-          for (int q = 0; q < 64; ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
-          }
-        } else {
-#pragma unroll
-        for (int s16 = 0; s16 < 16; ++s16) {
-          int t = g16 + 4 * s16 + k;
-          const bool vi = t < n_in;
-          t = vi ? t : n_in - 1;
-          const float4 u0 = srf[t][0], u1 = srf[t][1];
-          const float cl = u0.x, xa = u0.y, xb = u0.z, tn = u0.w, base = u1.x, c2 = u1.y;
-          const float db = sbr - xb, da = sar - xa;
-          const float e = __builtin_amdgcn_exp2f(fmaf(cl, db * db, base));
-          const float L0 = (vi && vb) ? e : 0.f;
-          const float Lb = L0 * (c2 * db);
-          const float Ln = L0 * tn;
-          const float r = __builtin_amdgcn_exp2f(cl * (da * da));
-          const float R0 = va ? r : 0.f;
-          const float Ra = R0 * (c2 * da);
-          accf[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, R0, accf[0], 0, 0, 0);
-          accf[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(L0, Ra, accf[1], 0, 0, 0);
-          accf[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(Lb, R0, accf[2], 0, 0, 0);
-          accf[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ln, R0, accf[3], 0, 0, 0);
-        }
-        }
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-#pragma unroll
-          for (int r2 = 0; r2 < 4; ++r2) acc[g][r2] += (double)accf[g][r2];
-          accf[g] = fx4{0.f, 0.f, 0.f, 0.f};
-        }
-      }
-    } else {
-      const int n_steps = (n_in + 3) / 4;
-      for (int st = 0; st < n_steps; ++st) {
-        int t = 4 * st + k;
-        const bool vi = t < n_in;
-        t = vi ? t : n_in - 1;
-        const double c = src[0][t], xa = src[1][t], xb = src[2][t], tn = src[3][t], base = src[4][t];
-        const double db = sb - xb, da = sa - xa;
-        const double e = exp_f64(fma(c * db, db, base));
-        const double L0 = (vi && vb) ? e : 0.0;
-        const double Lb = L0 * (2.0 * c * db);
-        const double Ln = L0 * tn;
-        const double r = exp_f64(c * da * da);
-        const double R0 = va ? r : 0.0;
-        const double Ra = R0 * (2.0 * c * da);
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, R0, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, Ra, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lb, R0, acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ln, R0, acc[3], 0, 0, 0);
-      }
+    const int n_steps = (n_in + 3) / 4;
+    for (int st = 0; st < n_steps; ++st) {
+      int t = 4 * st + k;
+      const bool vi = t < n_in;
+      t = vi ? t : n_in - 1;
+      const double c = src[0][t], xa = src[1][t], xb = src[2][t], tn = src[3][t], base = src[4][t];
+      const double db = sb - xb, da = sa - xa;
+      const double e = exp_f64(fma(c * db, db, base));
+      const double L0 = (vi && vb) ? e : 0.0;
+      const double Lb = L0 * (2.0 * c * db);
+      const double Ln = L0 * tn;
+      const double r = exp_f64(c * da * da);
+      const double R0 = va ? r : 0.0;
+      const double Ra = R0 * (2.0 * c * da);
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, R0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, Ra, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lb, R0, acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ln, R0, acc[3], 0, 0, 0);
     }
   }
-  double *o = ta.part + ((int64_t)slot * n_chunks + chunk) * 5 * ta.stride;
+  double *o = ta.part + ((int64_t)slot * n_chunks + n_chunks_far + ck) * 5 * ta.stride;
   const int64_t S = ta.stride;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    // row of element r of this lane: 4 (l / 16) + r for FP32 steps, 4 r + l / 16 for FP64 steps
-    const int br = b0 + (FAR ? 4 * k + r : 4 * r + k);
+    const int br = b0 + 4 * r + k;
     if (br >= F.nb || !va) continue;
     const int64_t q = F.off + (int64_t)br * F.na + ai;
     o[q] = acc[0][r];
@@ -362,31 +450,42 @@ __device__ __forceinline__ void tensor_item(const TensorArgs &ta, const PathTab 
   __syncthreads();   // the staged sources of this item are no longer read
 }
 
-// the far items (FP32) first, then the near ones (FP64), taken in turn by the
-// workgroups of a grid sized to leave room on the compute units
-__global__ __launch_bounds__(256) void k_sum_tensor(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
-                                                    int chunk_far, int chunk_near) {
-  __shared__ double src[5][kStage];
-  __shared__ float4 srf[kStage][2];
-  const int n_far_items = ta.n_tiles * n_chunks_far * tab.count;
-  const int n_items = ta.n_tiles * n_chunks * tab.count;
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-    if (item < n_far_items)
-      tensor_item<true>(ta, tab, item, n_chunks_far, n_chunks, chunk_far, chunk_near, src, srf);
-    else
-      tensor_item<false>(ta, tab, item - n_far_items, n_chunks_far, n_chunks, chunk_far, chunk_near, src, srf);
-  }
+// The far items (FP32), slot by slot in the order of the path table (longest
+// far history first), taken in turn by the workgroups of a grid sized to
+// leave room on the compute units (at most 168 registers: three waves per
+// SIMD); then, in a launch of their own (fewer registers), the near items
+// (FP64) with the same LDS per workgroup.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sum_tensor_far(
+    TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks, int chunk_far) {
+  __shared__ __align__(16) unsigned char lds[kTensorLds];
+  const int n_items = ta.n_tiles * n_chunks_far * tab.count;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x)
+    tensor_far(ta, tab, item, n_chunks_far, n_chunks, chunk_far, lds);
+}
+
+constexpr int kNearLds = 5 * kStage * 8;
+
+__global__ __launch_bounds__(256) void k_sum_tensor_near(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
+                                                         int chunk_near) {
+  __shared__ __align__(16) unsigned char lds[kNearLds];
+  const int n_items = ta.n_tiles * (n_chunks - n_chunks_far) * tab.count;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x)
+    tensor_near(ta, tab, item, n_chunks_far, n_chunks, chunk_near, lds);
 }
 
 void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, const TensorArgs &a) {
   if (a.n_tiles <= 0 || tab.count <= 0) return;
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
-  if (nch <= 0) return;
-  const int64_t items = (int64_t)a.n_tiles * nch * tab.count;
   const int cap = tab.count >= 4 ? a.max_groups_batch : a.max_groups;
-  const unsigned grid = (unsigned)(cap > 0 && items > cap ? cap : items);
-  hipLaunchKernelGGL(k_sum_tensor, dim3(grid), dim3(256), (size_t)a.lds_pad, st, a, tab, pl.n_chunks_far, nch,
-                     pl.chunk_far, pl.chunk_near);
+  auto grid = [&](int64_t items) { return (unsigned)(cap > 0 && items > cap ? cap : items); };
+  const int64_t far_items = (int64_t)a.n_tiles * pl.n_chunks_far * tab.count;
+  const int64_t near_items = (int64_t)a.n_tiles * pl.n_chunks_near * tab.count;
+  if (far_items > 0)
+    hipLaunchKernelGGL(k_sum_tensor_far, dim3(grid(far_items)), dim3(256), (size_t)a.lds_pad, st, a, tab,
+                       pl.n_chunks_far, nch, pl.chunk_far);
+  if (near_items > 0)
+    hipLaunchKernelGGL(k_sum_tensor_near, dim3(grid(near_items)), dim3(256),
+                       (size_t)(a.lds_pad + kTensorLds - kNearLds), st, a, tab, pl.n_chunks_far, nch, pl.chunk_near);
 }
 
 // the allowance only grows (per device), so a later object asking for less
@@ -398,8 +497,10 @@ bool sum_tensor_prepare(int lds_pad) {
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
   std::lock_guard<std::mutex> lk(mu);
   if (lds_pad <= granted[dev]) return true;
-  if (hipFuncSetAttribute((const void *)k_sum_tensor, hipFuncAttributeMaxDynamicSharedMemorySize, lds_pad) !=
-      hipSuccess)
+  if (hipFuncSetAttribute((const void *)k_sum_tensor_far, hipFuncAttributeMaxDynamicSharedMemorySize, lds_pad) !=
+          hipSuccess ||
+      hipFuncSetAttribute((const void *)k_sum_tensor_near, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          lds_pad + kTensorLds - kNearLds) != hipSuccess)
     return false;
   granted[dev] = lds_pad;
   return true;

@@ -1633,17 +1633,17 @@ void build_tensor_faces(sa_iga *h) {
     h->sum_groups_per_cu_batch = gb ? std::max(0, std::atoi(gb)) : 8;
     h->tens.max_groups_batch = h->sum_groups_per_cu_batch * prop.multiProcessorCount;
     // a blocked call's sum: one workgroup per work item (they retire often,
-    // so the solver kernels beside the sum get compute units), with LDS
-    // padding that leaves three per compute unit and room for a solver block
+    // so the solver kernels beside the sum get compute units), three per
+    // compute unit (no LDS padding: its registers allow three)
     const char *bg = std::getenv("SA_IGA_BLOCK_SUM_GROUPS_PER_CU");
     const char *pad = std::getenv("SA_IGA_BLOCK_SUM_LDS_PAD");
     h->blk_groups = (int)((bg ? std::max(0.0, std::atof(bg)) : 0.0) * prop.multiProcessorCount);
-    h->blk_pad = pad ? std::max(0, std::min(96 * 1024, std::atoi(pad))) : 24000;
+    h->blk_pad = pad ? std::max(0, std::min(96 * 1024, std::atoi(pad))) : 0;
     if (h->blk_pad > 0 && !sa::sum_tensor_prepare(h->blk_pad)) h->blk_pad = 0;
-    // launches of several paths per step: LDS padding that leaves compute
-    // units to the theta-step kernels beside the sum
+    // launches of several paths per step: LDS padding that leaves two per
+    // compute unit and room for the theta-step kernels beside the sum
     const char *bpad = std::getenv("SA_IGA_BATCH_SUM_LDS_PAD");
-    h->tens.lds_pad = bpad ? std::max(0, std::min(96 * 1024, std::atoi(bpad))) : 24000;
+    h->tens.lds_pad = bpad ? std::max(0, std::min(96 * 1024, std::atoi(bpad))) : 10000;
     if (h->tens.lds_pad > 0 && !sa::sum_tensor_prepare(std::max(h->tens.lds_pad, h->blk_pad))) h->tens.lds_pad = 0;
   }
   h->n_gen = (int64_t)gen.size();
@@ -2989,7 +2989,7 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
         if (h->use_tensor && S >= 4) {
           // workgroups per compute unit, then the LDS padding that leaves
           // compute units to the theta-step kernels beside the sum
-          static const int kG[4] = {8, 4, 6, 12}, kBp[3] = {24000, 0, 40000};
+          static const int kG[4] = {8, 4, 6, 12}, kBp[3] = {10000, 0, 38000};
           int bg = h->sum_groups_per_cu_batch, bbp = h->tens.lds_pad;
           double bt = -1.0, base = -1.0;
           auto time_shape = [&]() {
@@ -3032,14 +3032,14 @@ int sa_iga_autotune(sa_iga *h, int32_t reps, int32_t *points_per_lane, int32_t *
           // three quarters of every path's scan, the better of two runs of
           // 48 steps at each, and the set-up shape (the first) is left only
           // for one at least 3 % faster
-          static const int kPad[3] = {24000, 0, 48000}, kBs[2] = {8, 4};
+          static const int kPad[3] = {0, 10000, 38000}, kBs[2] = {8, 4};
           const int rb = std::max(reps, 48);
           int bpad = h->blk_pad, bbs = h->blk_steps;
           double bt = -1.0, base = -1.0;
-          const bool big_pad = sa::sum_tensor_prepare(48000);
+          const bool big_pad = sa::sum_tensor_prepare(38000);
           for (int pad : kPad)
             for (int bs : kBs) {
-              if ((pad > 24000 && !big_pad) || 2 * S > bs) continue;
+              if ((pad > 0 && !big_pad) || 2 * S > bs) continue;
               h->blk_pad = pad;
               h->blk_steps = bs;
               double ms = 0.0;
