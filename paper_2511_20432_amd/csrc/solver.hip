@@ -882,24 +882,83 @@ size_t fd_plane_lds(const int m[3]) {
 }
 
 // Checked update, first part: the z pass of the theta right-hand side and
-// residual r (as k_kron_z<true> with check) for whole x-rows, R = kZxThreads /
-// n0 rows per block, then the first FD transform t = U0^T r of the rows in
-// the free box (as k_fd_xfwd); r stays in LDS.  The residual-check partials
-// are summed per block (part_chk: gridDim.x of each kind per path).
+// residual r (as k_kron_z<true> with check) for whole x-rows, R rows per
+// block (zx_rows), then the first FD transform t = U0^T r of the rows in the
+// free box (as k_fd_xfwd); r stays in LDS.  The residual-check partials are
+// summed per block (part_chk: gridDim.x of each kind per path).
+//
+// The x transforms of these kernels (here and in k_xbwd_x, k_fd_xbwd_rows)
+// take U0 (or U0^T) from LDS in launches of four paths or more (m0 <= kU0Lds),
+// staged once per block, each thread forming one transform output for four
+// rows (one U0 value, four row values per term); otherwise one output per
+// thread with U0 read through the caches.  Each sum over kk in ascending
+// order, as in the fiber kernels.  Rows of
+// a block are consecutive, so each transform output's four rows are four
+// consecutive entries of t's plane (plane-major t: t[j0 P + k2 m1 + k1]).
 constexpr int kZxThreads = 320;
 constexpr int kZxMaxRow = 640;
+constexpr int kZxRowsMax = 16;
+constexpr int kZxFib = 1280;     // LDS row buffer (doubles): R n0 <= kZxFib
+constexpr int kU0Lds = 72;       // U0 in LDS up to m0 = 72 (41 KB; with the row buffers under 64 KB)
 
-__global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, FusedPcg f0) {
+__host__ __device__ inline int zx_rows(int n0) {
+  const int r = n0 > 0 ? kZxFib / n0 : 1;
+  return r < 1 ? 1 : (r > kZxRowsMax ? kZxRowsMax : r);
+}
+
+// rows per block: up to 16 (U0 staged in LDS) for launches of four paths or
+// more; four for fewer paths (more blocks for the latency-bound small grids,
+// U0 read through the caches)
+static int rows_for(int n0, int count) {
+  const int r = zx_rows(n0);
+  return count >= 4 ? r : (r < 4 ? r : 4);
+}
+
+// s[q] = sum_kk U(kk, j) v[q][kk] for the four rows q of group rg (rows past
+// nr contribute nothing), U(kk, j) = U[kk * m + j]
+__device__ __forceinline__ void xform4(const double *U, int m, int j, const double *v, int ldv, int q0, int nq,
+                                       double s[4]) {
+  s[0] = s[1] = s[2] = s[3] = 0.0;
+  const double *v0 = v + (int64_t)q0 * ldv;
+  if (nq == 1) {
+#pragma unroll 8
+    for (int kk = 0; kk < m; ++kk) s[0] = fma(U[kk * m + j], v0[kk], s[0]);
+  } else if (nq == 4) {
+#pragma unroll 4
+    for (int kk = 0; kk < m; ++kk) {
+      const double u = U[kk * m + j];
+      s[0] = fma(u, v0[kk], s[0]);
+      s[1] = fma(u, v0[ldv + kk], s[1]);
+      s[2] = fma(u, v0[2 * ldv + kk], s[2]);
+      s[3] = fma(u, v0[3 * ldv + kk], s[3]);
+    }
+  } else {
+    for (int kk = 0; kk < m; ++kk) {
+      const double u = U[kk * m + j];
+      for (int q = 0; q < nq; ++q) s[q] = fma(u, v0[q * ldv + kk], s[q]);
+    }
+  }
+}
+
+__device__ __forceinline__ const double *stage_u0(const double *U, int m, double *lds, int use_lds) {
+  if (!use_lds) return U;
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) lds[i] = U[i];
+  return lds;   // read after a barrier
+}
+
+__global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, FusedPcg f0, int R, int use_lds) {
   issue_first();
-  __shared__ double fib[kZxMaxRow];
+  __shared__ double fib[kZxFib];
   __shared__ double sh[16];
+  extern __shared__ double u0s[];
   const int64_t pth = sm.path[blockIdx.y];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
   const int n0 = a.op.n[0], n1 = a.op.n[1], n2 = a.op.n[2], p = a.op.p[2];
   const int64_t n01 = (int64_t)n0 * n1, nrows = (int64_t)n1 * n2;
-  const int R = n0 <= kZxThreads ? kZxThreads / n0 : 1;
   const int64_t row0 = (int64_t)blockIdx.x * R;
   const int ne = R * n0;
+  const int m0 = f.m[0], m1 = f.m[1];
+  const double *U0 = stage_u0(f.U0, m0, u0s, use_lds);
   const double *t = a.t + pth * a.ts;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
@@ -933,36 +992,44 @@ __global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, 
   c1 = bsum(c1, sh);
   c2 = bsum(c2, sh);
   if (threadIdx.x == 0) {
-    double *pc = a.part_chk + pth * 3 * a.np + blockIdx.x;
-    pc[0] = c0;
-    pc[a.np] = c1;
-    pc[2 * a.np] = c2;
+    // a.np partials per kind whatever the grid (blocks past it: zeros), so
+    // that a later launch of another size reads this step's check
+    double *pc = a.part_chk + pth * 3 * a.np;
+    pc[blockIdx.x] = c0;
+    pc[a.np + blockIdx.x] = c1;
+    pc[2 * a.np + blockIdx.x] = c2;
+    for (int j = blockIdx.x + gridDim.x; j < a.np; j += gridDim.x) pc[j] = pc[a.np + j] = pc[2 * a.np + j] = 0.0;
     if (blockIdx.x == 0 && a.sc_w) a.sc_w[pth].done = 0;
   }
-  // (bsum ends with a barrier: fib is complete)
-  const int m0 = f.m[0], m1 = f.m[1];
+  // (bsum ends with a barrier: fib and the staged U0 are complete)
   const int64_t P = (int64_t)m1 * f.m[2];
-  for (int o = threadIdx.x; o < R * m0; o += blockDim.x) {
-    const int j = o / m0, j0 = o % m0;
-    const int64_t row = row0 + j;
-    if (row >= nrows) continue;
-    const int k1 = (int)(row % n1) - f.lo[1], k2 = (int)(row / n1) - f.lo[2];
-    if (k1 < 0 || k1 >= m1 || k2 < 0 || k2 >= f.m[2]) continue;
-    const double *fr = fib + j * n0 + f.lo[0];
-    double s = 0.0;
-    #pragma unroll 8
-    for (int kk = 0; kk < m0; ++kk) s = fma(f.U0[kk * m0 + j0], fr[kk], s);
-    f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1] = s;
+  const int G = use_lds ? 4 : 1;   // rows per output thread
+  const int ng = (R + G - 1) / G;
+  for (int o = threadIdx.x; o < ng * m0; o += blockDim.x) {
+    const int j0 = o % m0, q0 = G * (o / m0);
+    const int nq = R - q0 < G ? R - q0 : G;
+    double sv[4];
+    xform4(U0, m0, j0, fib + f.lo[0], n0, q0, nq, sv);
+    for (int q = 0; q < nq; ++q) {
+      const int64_t row = row0 + q0 + q;
+      if (row >= nrows) break;
+      const int k1 = (int)(row % n1) - f.lo[1], k2 = (int)(row / n1) - f.lo[2];
+      if (k1 < 0 || k1 >= m1 || k2 < 0 || k2 >= f.m[2]) continue;
+      f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1] = sv[q];
+    }
   }
 }
 
 bool zx_fits(int n0) { return n0 <= kZxMaxRow; }
 
+// partials per kind of the residual check: the blocks of the smallest rows
+// per block
 int zx_blocks(const KronOp &op) {
-  const int n0 = op.n[0];
-  const int R = n0 <= kZxThreads ? kZxThreads / n0 : 1;
+  const int R = rows_for(op.n[0], 1);
   return (int)(((int64_t)op.n[1] * op.n[2] + R - 1) / R);
 }
+
+static size_t u0_lds(int m0, int R) { return R >= 8 && m0 <= kU0Lds ? (size_t)m0 * m0 * sizeof(double) : 0; }
 
 void launch_theta_checked_rhs(hipStream_t st, const SlotMap &sm, const KronArgs &a0, const FusedPcg &f,
                               bool with_x) {
@@ -972,15 +1039,62 @@ void launch_theta_checked_rhs(hipStream_t st, const SlotMap &sm, const KronArgs 
   dim3 g((unsigned)((a.nrow + kB - 1) / kB), (unsigned)sm.count), b(kB);
   if (with_x) hipLaunchKernelGGL(k_kron_x<true>, g, b, 0, st, sm, a);
   hipLaunchKernelGGL(k_kron_y<true>, g, b, 0, st, sm, a);
-  hipLaunchKernelGGL(k_kron_zx, dim3((unsigned)a.np, (unsigned)sm.count), dim3(kZxThreads), 0, st, sm, a, f);
+  const int R = rows_for(a.op.n[0], sm.count);
+  const size_t lds = u0_lds(f.m[0], R);
+  const unsigned nb = (unsigned)(((int64_t)a.op.n[1] * a.op.n[2] + R - 1) / R);
+  hipLaunchKernelGGL(k_kron_zx, dim3(nb, (unsigned)sm.count), dim3(kZxThreads), lds, st, sm, a, f, R,
+                     lds > 0 ? 1 : 0);
+}
+
+// Checked update, last transform: x += U0 t' on R consecutive rows of the
+// free box per block (t' read as R consecutive entries of each plane)
+__global__ __launch_bounds__(kZxThreads) void k_fd_xbwd_rows(SlotMap sm, FusedPcg f0, int R, int use_lds) {
+  issue_first();
+  __shared__ double tf[kZxFib];
+  extern __shared__ double u0s[];
+  const FusedPcg f = at_path(f0, sm, blockIdx.y);
+  if (f.sc->done) return;
+  const int m0 = f.m[0], m1 = f.m[1];
+  const int64_t P = (int64_t)m1 * f.m[2];
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int nr = P - row0 < R ? (int)(P - row0) : R;
+  const double *U0T = stage_u0(f.U0T, m0, u0s, use_lds);
+  // tf[q * m0 + j] = t[j P + row0 + q]
+  for (int e = threadIdx.x; e < m0 * R; e += blockDim.x) {
+    const int j = e / R, q = e % R;
+    tf[q * m0 + j] = q < nr ? f.t[(int64_t)j * P + row0 + q] : 0.0;
+  }
+  __syncthreads();
+  const int G = use_lds ? 4 : 1;
+  const int ng = (nr + G - 1) / G;
+  for (int o = threadIdx.x; o < ng * m0; o += blockDim.x) {
+    const int k0 = o % m0, q0 = G * (o / m0);
+    const int nq = nr - q0 < G ? nr - q0 : G;
+    double sv[4];
+    xform4(U0T, m0, k0, tf, m0, q0, nq, sv);
+    for (int q = 0; q < nq; ++q) {
+      const int64_t row = row0 + q0 + q;
+      const int k1 = (int)(row % m1), k2 = (int)(row / m1);
+      f.x[full_index(f, k0, k1, k2)] += sv[q];
+    }
+  }
 }
 
 void launch_theta_checked_solve(hipStream_t st, const SlotMap &sm, const FusedPcg &f, bool with_xbwd) {
   if (sm.count <= 0) return;
   hipLaunchKernelGGL(k_fd_plane, dim3((unsigned)f.m[0], (unsigned)sm.count), dim3(plane_threads(f.m)),
                      fd_plane_lds(f.m), st, sm, f);
-  const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
-  if (with_xbwd) hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, 0, 1);
+  if (!with_xbwd) return;
+  if (!f.U0T) {
+    const unsigned nfib = (unsigned)(f.m[1] * f.m[2]);
+    hipLaunchKernelGGL(k_fd_xbwd, dim3(nfib, (unsigned)sm.count), dim3(kFib), 0, st, sm, f, 0, 1);
+    return;
+  }
+  const int64_t P = (int64_t)f.m[1] * f.m[2];
+  const int R = rows_for(f.m[0], sm.count);
+  const size_t lds = u0_lds(f.m[0], R);
+  hipLaunchKernelGGL(k_fd_xbwd_rows, dim3((unsigned)((P + R - 1) / R), (unsigned)sm.count), dim3(kZxThreads), lds,
+                     st, sm, f, R, lds > 0 ? 1 : 0);
 }
 
 // band products along x of one row (u: the row's values of u^{n+1}) for the
@@ -1025,48 +1139,55 @@ __device__ __forceinline__ void xrow_products(const double *__restrict__ bm, con
 // u^{n+1} = x0 + U0 t on the box (stored, and kept in LDS for the row), then
 // the band products along x of step n+1's first iterate (u^{n+1} on the free
 // DOFs, its Dirichlet values elsewhere) and of u^{n+1}
-__global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, KronArgs a) {
+__global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, KronArgs a, int R, int use_lds) {
   issue_first();
-  __shared__ double tf[kZxMaxRow];
-  __shared__ double u[kZxMaxRow];
+  __shared__ double tf[kZxFib];
+  __shared__ double u[kZxFib];
+  extern __shared__ double u0s[];
   const int64_t pth = sm.path[blockIdx.y];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
   const int n0 = a.op.n[0], n1 = a.op.n[1], p = a.op.p[0];
   const int64_t nrows = (int64_t)n1 * a.op.n[2], N = a.nrow;
-  const int R = n0 <= kZxThreads ? kZxThreads / n0 : 1;
   const int64_t row0 = (int64_t)blockIdx.x * R;
   const int ne = R * n0;
   const int m0 = f.m[0], m1 = f.m[1];
   const int64_t P = (int64_t)m1 * f.m[2];
+  const double *U0T = stage_u0(f.U0T, m0, u0s, use_lds);
+  auto in_box = [&](int64_t row, int &k1, int &k2) {
+    k1 = (int)(row % n1) - f.lo[1];
+    k2 = (int)(row / n1) - f.lo[2];
+    return row < nrows && k1 >= 0 && k1 < m1 && k2 >= 0 && k2 < f.m[2];
+  };
+  // tf[j m0 + j0] = t[j0 P + (k1, k2 of row j)]: consecutive threads, consecutive rows
   for (int o = threadIdx.x; o < R * m0; o += blockDim.x) {
-    const int j = o / m0, j0 = o % m0;
+    const int j0 = o / R, j = o % R;
+    int k1, k2;
+    tf[j * m0 + j0] = in_box(row0 + j, k1, k2) ? f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1] : 0.0;
+  }
+  // the entries outside the box keep x
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int j = e / n0, k0 = e % n0 - f.lo[0];
+    int k1, k2;
     const int64_t row = row0 + j;
-    double tv = 0.0;
-    if (row < nrows) {
-      const int k1 = (int)(row % n1) - f.lo[1], k2 = (int)(row / n1) - f.lo[2];
-      if (k1 >= 0 && k1 < m1 && k2 >= 0 && k2 < f.m[2]) tv = f.t[(int64_t)j0 * P + (int64_t)k2 * m1 + k1];
-    }
-    tf[o] = tv;
+    if (row < nrows && !(in_box(row, k1, k2) && k0 >= 0 && k0 < m0)) u[e] = f.x[row * n0 + e % n0];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-    const int j = e / n0, i0 = e % n0;
-    const int64_t row = row0 + j;
-    double xv = 0.0;
-    if (row < nrows) {
-      const int64_t r = row * n0 + i0;
-      xv = f.x[r];
-      const int k0 = i0 - f.lo[0], k1 = (int)(row % n1) - f.lo[1], k2 = (int)(row / n1) - f.lo[2];
-      if (k0 >= 0 && k0 < m0 && k1 >= 0 && k1 < m1 && k2 >= 0 && k2 < f.m[2]) {
-        const double *tr = tf + j * m0;
-        double s = 0.0;
-        #pragma unroll 8
-        for (int jj = 0; jj < m0; ++jj) s = fma(f.U0T[jj * m0 + k0], tr[jj], s);
-        xv += s;
-        f.x[r] = xv;
-      }
+  const int G = use_lds ? 4 : 1;
+  const int ng = (R + G - 1) / G;
+  for (int o = threadIdx.x; o < ng * m0; o += blockDim.x) {
+    const int k0 = o % m0, q0 = G * (o / m0);
+    const int nq = R - q0 < G ? R - q0 : G;
+    double sv[4];
+    xform4(U0T, m0, k0, tf, m0, q0, nq, sv);
+    for (int q = 0; q < nq; ++q) {
+      int k1, k2;
+      const int64_t row = row0 + q0 + q;
+      if (!in_box(row, k1, k2)) continue;
+      const int64_t r = row * n0 + f.lo[0] + k0;
+      const double xv = f.x[r] + sv[q];
+      f.x[r] = xv;
+      u[(q0 + q) * n0 + f.lo[0] + k0] = xv;
     }
-    u[e] = xv;
   }
   __syncthreads();
   double *t = a.t + pth * a.ts;
@@ -1097,8 +1218,11 @@ __global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, 
 
 void launch_xbwd_x(hipStream_t st, const SlotMap &sm, const FusedPcg &f, const KronArgs &a) {
   if (sm.count <= 0) return;
-  hipLaunchKernelGGL(k_xbwd_x, dim3((unsigned)zx_blocks(a.op), (unsigned)sm.count), dim3(kZxThreads), 0, st, sm, f,
-                     a);
+  const int R = rows_for(a.op.n[0], sm.count);
+  const size_t lds = u0_lds(f.m[0], R);
+  const unsigned nb = (unsigned)(((int64_t)a.op.n[1] * a.op.n[2] + R - 1) / R);
+  hipLaunchKernelGGL(k_xbwd_x, dim3(nb, (unsigned)sm.count), dim3(kZxThreads), lds, st, sm, f, a, R,
+                     lds > 0 ? 1 : 0);
 }
 
 void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update) {
