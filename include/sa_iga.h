@@ -193,9 +193,12 @@ typedef struct {
   double audit_max_err;        /* largest audited error of the far temperature (K) */
   int64_t rollbacks;           /* calls whose steps were run again with a second PCG iteration
                                   (one iteration did not reach the tolerance on some step) */
-  double host_enqueue_ms;      /* host time sa_iga_step spent issuing the steps' launches, copies and
-                                  events (before waiting for them); the device cannot wait on the host
-                                  while this stays below the device time of the same steps */
+  double host_enqueue_ms;      /* host time sa_iga_step spent from its first launch to its last one
+                                  (before the final status check and synchronisation): issuing the
+                                  launches, copies and events, and any wait inside the call (audits,
+                                  a PCG fallback's synchronisation); an upper bound of the host's
+                                  share, on which the device need not wait while it stays below the
+                                  device time of the same steps */
 } sa_stats;
 
 /* Fill *opt with the defaults listed above. */

@@ -888,27 +888,26 @@ size_t fd_plane_lds(const int m[3]) {
 // summed per block (part_chk: gridDim.x of each kind per path).
 //
 // The x transforms of these kernels (here and in k_xbwd_x, k_fd_xbwd_rows)
-// take U0 (or U0^T) from LDS in launches of four paths or more (m0 <= kU0Lds),
-// staged once per block, each thread forming one transform output for four
-// rows (one U0 value, four row values per term); otherwise one output per
-// thread with U0 read through the caches.  Each sum over kk in ascending
-// order, as in the fiber kernels.  Rows of
+// form, in launches of four paths or more, one transform output for four
+// rows per thread (one U0 value, four row values per term), otherwise one
+// output per thread; U0 (or U0^T) is read through the caches (staged in LDS,
+// its 36 KB per block kept these blocks off the compute units shared with
+// the kernel sum, for no gain).  Each sum over kk in ascending order, as in
+// the fiber kernels.  Rows of
 // a block are consecutive, so each transform output's four rows are four
 // consecutive entries of t's plane (plane-major t: t[j0 P + k2 m1 + k1]).
 constexpr int kZxThreads = 320;
 constexpr int kZxMaxRow = 640;
 constexpr int kZxRowsMax = 16;
 constexpr int kZxFib = 1280;     // LDS row buffer (doubles): R n0 <= kZxFib
-constexpr int kU0Lds = 72;       // U0 in LDS up to m0 = 72 (41 KB; with the row buffers under 64 KB)
 
 __host__ __device__ inline int zx_rows(int n0) {
   const int r = n0 > 0 ? kZxFib / n0 : 1;
   return r < 1 ? 1 : (r > kZxRowsMax ? kZxRowsMax : r);
 }
 
-// rows per block: up to 16 (U0 staged in LDS) for launches of four paths or
-// more; four for fewer paths (more blocks for the latency-bound small grids,
-// U0 read through the caches)
+// rows per block: up to 16 for launches of four paths or more; four for fewer
+// paths (more blocks for the latency-bound small grids)
 static int rows_for(int n0, int count) {
   const int r = zx_rows(n0);
   return count >= 4 ? r : (r < 4 ? r : 4);
@@ -940,17 +939,10 @@ __device__ __forceinline__ void xform4(const double *U, int m, int j, const doub
   }
 }
 
-__device__ __forceinline__ const double *stage_u0(const double *U, int m, double *lds, int use_lds) {
-  if (!use_lds) return U;
-  for (int i = threadIdx.x; i < m * m; i += blockDim.x) lds[i] = U[i];
-  return lds;   // read after a barrier
-}
-
-__global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, FusedPcg f0, int R, int use_lds) {
+__global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, FusedPcg f0, int R, int G) {
   issue_first();
   __shared__ double fib[kZxFib];
   __shared__ double sh[16];
-  extern __shared__ double u0s[];
   const int64_t pth = sm.path[blockIdx.y];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
   const int n0 = a.op.n[0], n1 = a.op.n[1], n2 = a.op.n[2], p = a.op.p[2];
@@ -958,7 +950,7 @@ __global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, 
   const int64_t row0 = (int64_t)blockIdx.x * R;
   const int ne = R * n0;
   const int m0 = f.m[0], m1 = f.m[1];
-  const double *U0 = stage_u0(f.U0, m0, u0s, use_lds);
+  const double *U0 = f.U0;
   const double *t = a.t + pth * a.ts;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
@@ -1001,9 +993,8 @@ __global__ __launch_bounds__(kZxThreads) void k_kron_zx(SlotMap sm, KronArgs a, 
     for (int j = blockIdx.x + gridDim.x; j < a.np; j += gridDim.x) pc[j] = pc[a.np + j] = pc[2 * a.np + j] = 0.0;
     if (blockIdx.x == 0 && a.sc_w) a.sc_w[pth].done = 0;
   }
-  // (bsum ends with a barrier: fib and the staged U0 are complete)
+  // (bsum ends with a barrier: fib is complete)
   const int64_t P = (int64_t)m1 * f.m[2];
-  const int G = use_lds ? 4 : 1;   // rows per output thread
   const int ng = (R + G - 1) / G;
   for (int o = threadIdx.x; o < ng * m0; o += blockDim.x) {
     const int j0 = o % m0, q0 = G * (o / m0);
@@ -1029,7 +1020,8 @@ int zx_blocks(const KronOp &op) {
   return (int)(((int64_t)op.n[1] * op.n[2] + R - 1) / R);
 }
 
-static size_t u0_lds(int m0, int R) { return R >= 8 && m0 <= kU0Lds ? (size_t)m0 * m0 * sizeof(double) : 0; }
+// outputs per thread: four rows with the larger blocks, one otherwise
+static int rows_per_output(int R) { return R >= 8 ? 4 : 1; }
 
 void launch_theta_checked_rhs(hipStream_t st, const SlotMap &sm, const KronArgs &a0, const FusedPcg &f,
                               bool with_x) {
@@ -1040,32 +1032,29 @@ void launch_theta_checked_rhs(hipStream_t st, const SlotMap &sm, const KronArgs 
   if (with_x) hipLaunchKernelGGL(k_kron_x<true>, g, b, 0, st, sm, a);
   hipLaunchKernelGGL(k_kron_y<true>, g, b, 0, st, sm, a);
   const int R = rows_for(a.op.n[0], sm.count);
-  const size_t lds = u0_lds(f.m[0], R);
   const unsigned nb = (unsigned)(((int64_t)a.op.n[1] * a.op.n[2] + R - 1) / R);
-  hipLaunchKernelGGL(k_kron_zx, dim3(nb, (unsigned)sm.count), dim3(kZxThreads), lds, st, sm, a, f, R,
-                     lds > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_kron_zx, dim3(nb, (unsigned)sm.count), dim3(kZxThreads), 0, st, sm, a, f, R,
+                     rows_per_output(R));
 }
 
 // Checked update, last transform: x += U0 t' on R consecutive rows of the
 // free box per block (t' read as R consecutive entries of each plane)
-__global__ __launch_bounds__(kZxThreads) void k_fd_xbwd_rows(SlotMap sm, FusedPcg f0, int R, int use_lds) {
+__global__ __launch_bounds__(kZxThreads) void k_fd_xbwd_rows(SlotMap sm, FusedPcg f0, int R, int G) {
   issue_first();
   __shared__ double tf[kZxFib];
-  extern __shared__ double u0s[];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
   if (f.sc->done) return;
   const int m0 = f.m[0], m1 = f.m[1];
   const int64_t P = (int64_t)m1 * f.m[2];
   const int64_t row0 = (int64_t)blockIdx.x * R;
   const int nr = P - row0 < R ? (int)(P - row0) : R;
-  const double *U0T = stage_u0(f.U0T, m0, u0s, use_lds);
+  const double *U0T = f.U0T;
   // tf[q * m0 + j] = t[j P + row0 + q]
   for (int e = threadIdx.x; e < m0 * R; e += blockDim.x) {
     const int j = e / R, q = e % R;
     tf[q * m0 + j] = q < nr ? f.t[(int64_t)j * P + row0 + q] : 0.0;
   }
   __syncthreads();
-  const int G = use_lds ? 4 : 1;
   const int ng = (nr + G - 1) / G;
   for (int o = threadIdx.x; o < ng * m0; o += blockDim.x) {
     const int k0 = o % m0, q0 = G * (o / m0);
@@ -1092,9 +1081,8 @@ void launch_theta_checked_solve(hipStream_t st, const SlotMap &sm, const FusedPc
   }
   const int64_t P = (int64_t)f.m[1] * f.m[2];
   const int R = rows_for(f.m[0], sm.count);
-  const size_t lds = u0_lds(f.m[0], R);
-  hipLaunchKernelGGL(k_fd_xbwd_rows, dim3((unsigned)((P + R - 1) / R), (unsigned)sm.count), dim3(kZxThreads), lds,
-                     st, sm, f, R, lds > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_fd_xbwd_rows, dim3((unsigned)((P + R - 1) / R), (unsigned)sm.count), dim3(kZxThreads), 0,
+                     st, sm, f, R, rows_per_output(R));
 }
 
 // band products along x of one row (u: the row's values of u^{n+1}) for the
@@ -1139,11 +1127,10 @@ __device__ __forceinline__ void xrow_products(const double *__restrict__ bm, con
 // u^{n+1} = x0 + U0 t on the box (stored, and kept in LDS for the row), then
 // the band products along x of step n+1's first iterate (u^{n+1} on the free
 // DOFs, its Dirichlet values elsewhere) and of u^{n+1}
-__global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, KronArgs a, int R, int use_lds) {
+__global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, KronArgs a, int R, int G) {
   issue_first();
   __shared__ double tf[kZxFib];
   __shared__ double u[kZxFib];
-  extern __shared__ double u0s[];
   const int64_t pth = sm.path[blockIdx.y];
   const FusedPcg f = at_path(f0, sm, blockIdx.y);
   const int n0 = a.op.n[0], n1 = a.op.n[1], p = a.op.p[0];
@@ -1152,7 +1139,7 @@ __global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, 
   const int ne = R * n0;
   const int m0 = f.m[0], m1 = f.m[1];
   const int64_t P = (int64_t)m1 * f.m[2];
-  const double *U0T = stage_u0(f.U0T, m0, u0s, use_lds);
+  const double *U0T = f.U0T;
   auto in_box = [&](int64_t row, int &k1, int &k2) {
     k1 = (int)(row % n1) - f.lo[1];
     k2 = (int)(row / n1) - f.lo[2];
@@ -1172,7 +1159,6 @@ __global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, 
     if (row < nrows && !(in_box(row, k1, k2) && k0 >= 0 && k0 < m0)) u[e] = f.x[row * n0 + e % n0];
   }
   __syncthreads();
-  const int G = use_lds ? 4 : 1;
   const int ng = (R + G - 1) / G;
   for (int o = threadIdx.x; o < ng * m0; o += blockDim.x) {
     const int k0 = o % m0, q0 = G * (o / m0);
@@ -1219,10 +1205,9 @@ __global__ __launch_bounds__(kZxThreads) void k_xbwd_x(SlotMap sm, FusedPcg f0, 
 void launch_xbwd_x(hipStream_t st, const SlotMap &sm, const FusedPcg &f, const KronArgs &a) {
   if (sm.count <= 0) return;
   const int R = rows_for(a.op.n[0], sm.count);
-  const size_t lds = u0_lds(f.m[0], R);
   const unsigned nb = (unsigned)(((int64_t)a.op.n[1] * a.op.n[2] + R - 1) / R);
-  hipLaunchKernelGGL(k_xbwd_x, dim3(nb, (unsigned)sm.count), dim3(kZxThreads), lds, st, sm, f, a, R,
-                     lds > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_xbwd_x, dim3(nb, (unsigned)sm.count), dim3(kZxThreads), 0, st, sm, f, a, R,
+                     rows_per_output(R));
 }
 
 void launch_fd_pass(hipStream_t st, const SlotMap &sm, const FusedPcg &f, int k, bool first, bool update) {
