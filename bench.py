@@ -59,22 +59,24 @@ FLOPS_PER_PAIR = 8
 LANE_OPS = 256 * 64 * 2.4e9
 SLOTS_FP32_PAIR = 13
 SLOTS_FP64_PAIR = 28
-# HBM bytes per sum-stage launch (k_sum_tensor_far + k_sum_tensor_near) from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# scaled by the same counters on a 256 MiB copy (bench.py --copy-calibration),
-# per batched step of the headline window.  None until the counters are taken
-# on the kernel as it now is.
-K_SUM_TRAFFIC = None
+# HBM bytes per sum-stage launch (one k_sum_tensor_far and one
+# k_sum_tensor_near launch) from rocprofv3 FETCH_SIZE / WRITE_SIZE per
+# dispatch over the headline leg, scaled by the same counters on a 256 MiB
+# copy (bench.py --copy-calibration: FETCH x 2.000, WRITE x 1.000); the
+# commands and counts are in profiles/k_sum_tensor_far_headline_traffic.md.
+# Set to None when the kernels change until the counters are taken again.
+K_SUM_TRAFFIC = {"far": {"read_bytes": 78.94e6, "written_bytes": 110.10e6},
+                 "near": {"read_bytes": 16.06e6, "written_bytes": 79.80e6}}
 
 WINDOW_START = "each strategy at a seeded step in [0, L - warmup - steps) with a zeroed state (u = T_c, F = 0)"
 
 
-def _k_sum_traffic(launches_per_step=1.0):
+def _k_sum_traffic():
     """HBM bytes (read + written) of one sum-stage launch, or None."""
     t = K_SUM_TRAFFIC
     if not t:
         return None
-    return (t["read_bytes"] + t["written_bytes"]) / launches_per_step
+    return sum(k["read_bytes"] + k["written_bytes"] for k in t.values())
 
 
 def _sum_roofline(st, sum_ms):
@@ -589,7 +591,7 @@ def main():
         head["training"] = training
         a = head["surrogate_audited"]
         roof = dict(a["sum_roofline"])
-        roof.update({"traffic": _k_sum_traffic(a["sum_launches_per_step"]),
+        roof.update({"traffic": _k_sum_traffic(),
                      "traffic_unit": "HBM bytes per sum-stage launch (read + written)",
                      "kernel": "the matrix-core kernel sum (k_sum_tensor_far: far chunks FP32; k_sum_tensor_near: "
                                "near chunks FP64), the dominant stage of the window",

@@ -37,12 +37,12 @@ def test_roofline_without_time_or_work():
     assert bench._sum_roofline({"pairs": 10, "pairs_near": 0}, 0.0)["achieved"] is None
 
 
-def test_traffic_per_launch_divides_the_per_step_counters(monkeypatch):
+def test_traffic_per_launch_adds_the_kernels_of_the_stage(monkeypatch):
     monkeypatch.setattr(bench, "K_SUM_TRAFFIC", None)
-    assert bench._k_sum_traffic(2.0) is None
-    monkeypatch.setattr(bench, "K_SUM_TRAFFIC", {"read_bytes": 3e6, "written_bytes": 5e6})
-    assert bench._k_sum_traffic(1.0) == pytest.approx(8e6)
-    assert bench._k_sum_traffic(2.0) == pytest.approx(4e6)
+    assert bench._k_sum_traffic() is None
+    monkeypatch.setattr(bench, "K_SUM_TRAFFIC", {"far": {"read_bytes": 3e6, "written_bytes": 5e6},
+                                                 "near": {"read_bytes": 1e6, "written_bytes": 2e6}})
+    assert bench._k_sum_traffic() == pytest.approx(11e6)
 
 
 def test_valu_roofline_of_the_pair_by_pair_sum():
