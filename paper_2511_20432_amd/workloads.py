@@ -35,6 +35,7 @@ import numpy as np
 FACE_NEUMANN = 0        # lateral, adiabatic: receives the transferred flux load
 FACE_DIRICHLET = 1      # bottom, build platform: T = T_c
 FACE_SOURCE_PLANE = 2   # top: adiabatic by construction of the point-source kernel
+FACE_INTERFACE = 3      # glued to a face of another patch: no boundary points, no load
 
 PRECISION_FP64 = 0
 PRECISION_FP32_FAR = 1
@@ -583,6 +584,88 @@ def e2(splits=(8, 10, 20), options: Optional[Options] = None) -> Workload:
                   ang1=math.pi / 2, z=2e-3)
     scan = make_scan([sources_from_segments([seg], 1e-5)], 1e-5, 1)
     return Workload("e2_contour_scan", patch, MAT_TI64, scan, options or Options(kernel_scale=2.0))
+
+
+# ----------------------------------------------------------------------------
+# several patches glued conformingly (multi-patch parts)
+# ----------------------------------------------------------------------------
+
+def block_patch_knots(lo, hi, knots, degree, roles, quad_vol=None, quad_face=3) -> Patch:
+    """Axis-aligned box [lo, hi] on the given knot vectors (control points at
+    their Greville abscissae, so the map is affine)."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    if np.isscalar(degree):
+        degree = (degree,) * 3
+    knots = tuple(np.asarray(k, float) for k in knots)
+    g = [lo[d] + (hi[d] - lo[d]) * greville(knots[d], degree[d]) for d in range(3)]
+    X2, X1, X0 = np.meshgrid(g[2], g[1], g[0], indexing="ij")
+    ctrl = np.stack([X0, X1, X2, np.ones_like(X0)], axis=-1)
+    if quad_vol is None:
+        quad_vol = tuple(d + 1 for d in degree)
+    return Patch(tuple(degree), knots, ctrl, tuple(roles), tuple(quad_vol), quad_face)
+
+
+def glue(patches, rel_tol=1e-9):
+    """Global numbering of the control points of patches that meet face to
+    face with matching control points: points of different patches at the
+    same position (within rel_tol of the part's extent) share one index.
+    Returns the index map of each patch (control point order of the patch)
+    and the number of global control points.  Shared points must carry the
+    same weight."""
+    P = np.concatenate([p.ctrl.reshape(-1, 4) for p in patches])
+    ext = float(np.abs(P[:, :3] - P[:, :3].mean(axis=0)).max())
+    key = np.round(P[:, :3] / (rel_tol * ext)).astype(np.int64)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    inv = inv.reshape(-1)
+    if not np.allclose(P[:, 3], P[first[inv], 3], rtol=1e-12, atol=0.0):
+        raise ValueError("shared control points carry different weights")
+    # global indices in order of first appearance
+    order = np.argsort(first)
+    rank = np.empty_like(order)
+    rank[order] = np.arange(len(order))
+    g = rank[inv]
+    maps, o = [], 0
+    for p in patches:
+        maps.append(g[o:o + p.n_dof].astype(np.int64))
+        o += p.n_dof
+    return maps, int(len(first))
+
+
+@dataclasses.dataclass
+class MultiWorkload:
+    name: str
+    patches: List[Patch]
+    maps: List[np.ndarray]
+    material: Material
+    scan: ScanPath
+    options: Options
+
+
+def l_part(n_el=(8, 8, 4), degree=2, size=(1e-3, 1e-3, 0.5e-3), power=80.0, speed=1.0,
+           options: Optional[Options] = None) -> MultiWorkload:
+    """L-shaped plan from three conforming patches: the corner square
+    [0, a]^2 and the arms [a, a+b] x [0, a] and [0, a] x [a, a+b], height h
+    (size = (a, b, h)); n_el = elements along a, along b and along h.  The
+    faces where the patches meet are interfaces; bottom Dirichlet, top
+    source plane, the outer sides adiabatic.  One track along the L's centre
+    line, from the end of the x arm through the corner to the end of the y
+    arm (0.2 mm from the ends), 10 us steps, 5 sources per step."""
+    a, b, h = size
+    na, nb, nz = n_el
+    ka, kb, kz = (open_uniform_knots(n, degree) for n in (na, nb, nz))
+    N, D, S, I = FACE_NEUMANN, FACE_DIRICHLET, FACE_SOURCE_PLANE, FACE_INTERFACE
+    corner = block_patch_knots((0, 0, 0), (a, a, h), (ka, ka, kz), degree, (N, I, N, I, D, S))
+    arm_x = block_patch_knots((a, 0, 0), (a + b, a, h), (kb, ka, kz), degree, (I, N, N, N, D, S))
+    arm_y = block_patch_knots((0, a, 0), (a, a + b, h), (ka, kb, kz), degree, (N, N, I, N, D, S))
+    patches = [corner, arm_x, arm_y]
+    maps, _ = glue(patches)
+    c = 0.5 * a
+    segs = [Segment("line", power, speed, p0=np.array([a + b - 0.2e-3, c, h]), p1=np.array([c, c, h])),
+            Segment("line", power, speed, p0=np.array([c, c, h]), p1=np.array([c, a + b - 0.2e-3, h]))]
+    dt, n_s = 1e-5, 5
+    scan = make_scan([sources_from_segments(segs, dt / n_s)], dt, n_s)
+    return MultiWorkload("l_part_three_patches", patches, maps, MAT_CFG, scan, options or Options())
 
 
 WORKLOADS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4, "e1": e1, "e2": e2}
