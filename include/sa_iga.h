@@ -66,7 +66,9 @@ enum sa_status {
 enum sa_face_role {
   SA_FACE_NEUMANN = 0,       /* lateral, adiabatic: takes the flux load F (Eq. 10) */
   SA_FACE_DIRICHLET = 1,     /* bottom: T = T_c (Eq. 11) */
-  SA_FACE_SOURCE_PLANE = 2   /* top: holds the sources; adiabatic by Eq. 8, no load */
+  SA_FACE_SOURCE_PLANE = 2,  /* top: holds the sources; adiabatic by Eq. 8, no load */
+  SA_FACE_INTERFACE = 3      /* multi-patch models only (sa_mp_setup): glued to a face of another
+                                patch; no boundary points, no load */
 };
 
 enum sa_precision {
@@ -435,6 +437,81 @@ int sa_mlp_gradients(sa_mlp *h, int64_t B, const float *X, const float *T, float
 int sa_mlp_train_step(sa_mlp *h, int64_t B, const float *X, const float *T, float lr, double *loss);
 int sa_mlp_set_stream(sa_mlp *h, void *hip_stream);
 void sa_mlp_destroy(sa_mlp *h);
+
+/*
+ * Multi-patch models (the parts of Sec. 3.3 built from several patches).
+ * NURBS patches meet face to face with matching knot vectors and control
+ * points along the shared faces, which carry the role SA_FACE_INTERFACE on
+ * both sides.  The caller numbers the control points globally; a shared
+ * control point has one index, so the spline space is continuous (C0)
+ * across the interfaces.  Eqs. 16-18 and 11 are assembled patch by patch
+ * into the global numbering (every element and every boundary point belongs
+ * to one patch); the kernel sum (Eqs. 7-8), the transferred data (Eqs.
+ * 10-11) and the theta-scheme (Eq. 20) are those of the single-patch model.
+ * On the device: the kernel sum pair by pair at every boundary point (FP64,
+ * or FP32 for the sources older than tau_near), the load vector and the
+ * projection right-hand side as CSR gathers, the Dirichlet projection and
+ * the theta-step as CSR operators solved by Jacobi-preconditioned CG to
+ * pcg_rtol (the theta-step on the free unknowns, the Dirichlet columns moved
+ * to the right-hand side).  One scan path per object.
+ */
+typedef struct sa_multipatch sa_multipatch;   /* opaque; owns its device memory */
+
+typedef struct {
+  int32_t n_patches;
+  int64_t n_dof;               /* global control points */
+  int64_t n_bpts;              /* boundary points (the non-interface faces of every patch, patch by
+                                  patch, each patch's in the single-patch order) */
+  int64_t n_dirichlet;         /* control variables fixed by DIRICHLET faces */
+  int64_t n_free;
+  int64_t nnz;                 /* non-zeros of the global M (and K) */
+  int64_t step;                /* steps taken */
+  int64_t pcg_iterations;      /* total over the steps taken (theta-steps) */
+  int64_t dirichlet_iterations;  /* total over the steps taken (projections) */
+  double pcg_last_relres;      /* |r| / |b| of the last theta-step */
+} sa_mp_info;
+
+/*
+ * Build a multi-patch model on the current HIP device.
+ *   patches [n_patches]: as for sa_iga_setup, with SA_FACE_INTERFACE allowed;
+ *   index_map: the global index of every control point, patch after patch,
+ *     each patch's control points in the order A = a0 + n0 (a1 + n1 a2);
+ *     the indices cover 0 .. n_dof - 1, every one used;
+ *   scan: exactly one path; its options (scan->opt, NULL = defaults) take
+ *     precision SA_PREC_FP64 or SA_PREC_FP32_FAR (the preconditioner
+ *     setting is ignored: Jacobi).
+ * All input arrays are copied.  Errors: SA_EINVAL (invalid patch, role,
+ * index map, scan or options), SA_ENOMEM, SA_EDEVICE.
+ */
+int sa_mp_setup(const sa_patch *patches, int32_t n_patches, const int64_t *index_map, const sa_material *mat,
+                const sa_scan_path *scan, sa_multipatch **out);
+
+/* Advance n_steps theta-steps (fewer at the end of the scan).  SA_ENOCONV if
+ * a CG solve does not reach pcg_rtol within pcg_max_iter iterations (the
+ * object then keeps the state of the last completed step). */
+int sa_mp_step(sa_multipatch *h, int32_t n_steps);
+
+int sa_mp_get_info(const sa_multipatch *h, sa_mp_info *info);
+
+/* Host copies of the current fields (any may be NULL), as
+ * sa_iga_get_boundary_fields: T_gp [n_bpts], grad_gp [3][n_bpts]
+ * (component-major), F [n_dof], du [n_dof] (global numbering). */
+int sa_mp_get_boundary_fields(sa_multipatch *h, double *T_gp, double *grad_gp, double *F, double *du);
+
+/* Boundary quadrature tables (host arrays, any may be NULL): x [n_bpts][3],
+ * outward unit normals [n_bpts][3], weights w dS [n_bpts]. */
+int sa_mp_get_boundary_points(sa_multipatch *h, double *x, double *normal, double *wdS);
+
+/* T and grad T (Eq. 21) at n parametric points xi [n][3] of patch `patch`
+ * (host arrays: T [n], grad [n][3]) at the current step: the basis
+ * contraction with the control values and the kernel sum at the mapped
+ * points on the device.  SA_ERANGE if a point lies outside [0,1]^3 or the
+ * patch index is out of range. */
+int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const double *xi, double *T,
+                           double *grad);
+
+/* Free the object and its device memory.  NULL is ignored. */
+void sa_mp_destroy(sa_multipatch *h);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@
 #include <map>
 #include <thread>
 
+#include "kernels.h"
 #include "sa_internal.h"
 
 namespace sa {
@@ -103,7 +104,7 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
 // validation and patch loading
 // ---------------------------------------------------------------------------
 void validate_inputs(const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan,
-                     const sa_solver_options &opt) {
+                     const sa_solver_options &opt, bool interfaces) {
   if (!patch || !mat || !scan) fail(SA_EINVAL, "NULL patch, material or scan path");
   for (int d = 0; d < 3; ++d) {
     int p = patch->degree[d], n = patch->n_ctrl[d];
@@ -130,8 +131,9 @@ void validate_inputs(const sa_patch *patch, const sa_material *mat, const sa_sca
     for (int c = 0; c < 3; ++c)
       if (!std::isfinite(patch->ctrl_xyzw[4 * i + c])) fail(SA_EINVAL, "non-finite control point");
   }
+  const int max_role = interfaces ? SA_FACE_INTERFACE : SA_FACE_SOURCE_PLANE;
   for (int f = 0; f < 6; ++f)
-    if (patch->face_role[f] < 0 || patch->face_role[f] > 2) fail(SA_EINVAL, "bad face role");
+    if (patch->face_role[f] < 0 || patch->face_role[f] > max_role) fail(SA_EINVAL, "bad face role");
   if (!(mat->k > 0) || !(mat->rho > 0) || !(mat->cp > 0) || !std::isfinite(mat->T0))
     fail(SA_EINVAL, "material constants must be positive and finite");
   if (scan->n_paths < 1) fail(SA_EINVAL, "n_paths must be >= 1");
@@ -408,6 +410,87 @@ void assemble_volume(Model &m) {
 // ---------------------------------------------------------------------------
 // boundary tables (Eq. 18) and Dirichlet trace data (Eq. 11)
 // ---------------------------------------------------------------------------
+// Load gather (rows = DOFs, columns = NEUMANN points), the Dirichlet DOFs
+// (free_mask 0, ascending), the projection right-hand side gather (rows =
+// Dirichlet DOFs, columns = DIRICHLET points) and the trace mass matrix on
+// the Dirichlet DOFs, from the boundary tables of nd DOFs.
+void build_transfer(const BoundaryTables &bt, int64_t nd, const std::vector<uint8_t> &free_mask, Csr &L,
+                    std::vector<int64_t> &dir_dofs, Csr &Dp, Csr &Md) {
+  const int64_t q = bt.nq;
+  // load gather: F_A = sum over NEUMANN points of R_A(x_q) * flux density_q
+  L.nrow = nd;
+  L.rowptr.assign(nd + 1, 0);
+  for (int64_t i = 0; i < q; ++i)
+    if (bt.role[i] == SA_FACE_NEUMANN)
+      for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) L.rowptr[bt.fidx[e] + 1]++;
+  for (int64_t A = 0; A < nd; ++A) L.rowptr[A + 1] += L.rowptr[A];
+  L.col.assign(L.rowptr[nd], 0);
+  L.val.assign(L.rowptr[nd], 0.0);
+  {
+    std::vector<int64_t> pos(L.rowptr.begin(), L.rowptr.end() - 1);
+    for (int64_t i = 0; i < q; ++i)
+      if (bt.role[i] == SA_FACE_NEUMANN)
+        for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) {
+          int64_t A = bt.fidx[e];
+          L.col[pos[A]] = (int32_t)i;
+          L.val[pos[A]] = bt.fval[e];
+          pos[A]++;
+        }
+  }
+  dir_dofs.clear();
+  std::vector<int64_t> dpos(nd, -1);
+  for (int64_t A = 0; A < nd; ++A)
+    if (!free_mask[A]) {
+      dpos[A] = (int64_t)dir_dofs.size();
+      dir_dofs.push_back(A);
+    }
+  const int64_t nD = (int64_t)dir_dofs.size();
+  // projection right-hand side gather and trace mass matrix
+  Dp.nrow = nD;
+  Dp.rowptr.assign(nD + 1, 0);
+  std::vector<std::map<int64_t, double>> mrows(nD);
+  for (int64_t i = 0; i < q; ++i) {
+    if (bt.role[i] != SA_FACE_DIRICHLET) continue;
+    for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) {
+      int64_t j = dpos[bt.fidx[e]];
+      if (j < 0) continue;
+      Dp.rowptr[j + 1]++;
+      for (int64_t e2 = bt.fptr[i]; e2 < bt.fptr[i + 1]; ++e2) {
+        int64_t k = dpos[bt.fidx[e2]];
+        if (k < 0) continue;
+        mrows[j][k] += bt.fval[e] * bt.fval[e2] * bt.wdS[i];
+      }
+    }
+  }
+  for (int64_t j = 0; j < nD; ++j) Dp.rowptr[j + 1] += Dp.rowptr[j];
+  Dp.col.assign(Dp.rowptr[nD], 0);
+  Dp.val.assign(Dp.rowptr[nD], 0.0);
+  {
+    std::vector<int64_t> pos(Dp.rowptr.begin(), Dp.rowptr.end() - 1);
+    for (int64_t i = 0; i < q; ++i) {
+      if (bt.role[i] != SA_FACE_DIRICHLET) continue;
+      for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) {
+        int64_t j = dpos[bt.fidx[e]];
+        if (j < 0) continue;
+        Dp.col[pos[j]] = (int32_t)i;
+        Dp.val[pos[j]] = bt.fval[e];  // the per-point density already carries w dS
+        pos[j]++;
+      }
+    }
+  }
+  Md.nrow = nD;
+  Md.rowptr.assign(nD + 1, 0);
+  Md.col.clear();
+  Md.val.clear();
+  for (int64_t j = 0; j < nD; ++j) {
+    for (auto &kv : mrows[j]) {
+      Md.col.push_back((int32_t)kv.first);
+      Md.val.push_back(kv.second);
+    }
+    Md.rowptr[j + 1] = (int64_t)Md.col.size();
+  }
+}
+
 void build_boundary(Model &m) {
   PatchData &P = m.P;
   BoundaryTables &bt = m.bt;
@@ -419,6 +502,7 @@ void build_boundary(Model &m) {
   PointEval pe;
   for (int f = 0; f < 6; ++f) {
     bt.face_off[f] = q;
+    if (P.role[f] == SA_FACE_INTERFACE) continue;   // glued to another patch: no points
     const int d = f / 2, side = f % 2;
     int a = (d == 0) ? 1 : 0, b = (d == 2) ? 1 : 2;
     const Basis1D &Ba = P.b[a], &Bb = P.b[b];
@@ -465,99 +549,19 @@ void build_boundary(Model &m) {
   bt.face_off[6] = q;
   bt.nq = q;
 
-  // load gather: F_A = sum over NEUMANN points of R_A(x_q) * flux density_q
-  const int64_t nd = P.ndof;
-  Csr &L = m.load;
-  L.nrow = nd;
-  L.rowptr.assign(nd + 1, 0);
-  for (int64_t i = 0; i < q; ++i)
-    if (bt.role[i] == SA_FACE_NEUMANN)
-      for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) L.rowptr[bt.fidx[e] + 1]++;
-  for (int64_t A = 0; A < nd; ++A) L.rowptr[A + 1] += L.rowptr[A];
-  L.col.assign(L.rowptr[nd], 0);
-  L.val.assign(L.rowptr[nd], 0.0);
-  {
-    std::vector<int64_t> pos(L.rowptr.begin(), L.rowptr.end() - 1);
-    for (int64_t i = 0; i < q; ++i)
-      if (bt.role[i] == SA_FACE_NEUMANN)
-        for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) {
-          int64_t A = bt.fidx[e];
-          L.col[pos[A]] = (int32_t)i;
-          L.val[pos[A]] = bt.fval[e];
-          pos[A]++;
-        }
-  }
-
   // Dirichlet DOFs: the end layers of the DIRICHLET faces
+  const int64_t nd = P.ndof;
   m.free_mask.assign(nd, 1);
-  int n_dir_faces = 0, dir_face = -1;
   for (int f = 0; f < 6; ++f) {
     if (P.role[f] != SA_FACE_DIRICHLET) continue;
-    n_dir_faces++;
-    dir_face = f;
     const int d = f / 2, side = f % 2, layer = side ? P.n[d] - 1 : 0;
     for (int64_t A = 0; A < nd; ++A) {
       int a[3] = {(int)(A % P.n[0]), (int)((A / P.n[0]) % P.n[1]), (int)(A / ((int64_t)P.n[0] * P.n[1]))};
       if (a[d] == layer) m.free_mask[A] = 0;
     }
   }
-  m.dir_dofs.clear();
-  std::vector<int64_t> dpos(nd, -1);
-  for (int64_t A = 0; A < nd; ++A)
-    if (!m.free_mask[A]) {
-      dpos[A] = (int64_t)m.dir_dofs.size();
-      m.dir_dofs.push_back(A);
-    }
-  const int64_t nD = (int64_t)m.dir_dofs.size();
-  // projection right-hand side gather and trace mass matrix
-  Csr &Dp = m.dproj;
-  Dp.nrow = nD;
-  Dp.rowptr.assign(nD + 1, 0);
-  std::vector<std::map<int64_t, double>> mrows(nD);
-  for (int64_t i = 0; i < q; ++i) {
-    if (bt.role[i] != SA_FACE_DIRICHLET) continue;
-    for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) {
-      int64_t j = dpos[bt.fidx[e]];
-      if (j < 0) continue;
-      Dp.rowptr[j + 1]++;
-      for (int64_t e2 = bt.fptr[i]; e2 < bt.fptr[i + 1]; ++e2) {
-        int64_t k = dpos[bt.fidx[e2]];
-        if (k < 0) continue;
-        mrows[j][k] += bt.fval[e] * bt.fval[e2] * bt.wdS[i];
-      }
-    }
-  }
-  for (int64_t j = 0; j < nD; ++j) Dp.rowptr[j + 1] += Dp.rowptr[j];
-  Dp.col.assign(Dp.rowptr[nD], 0);
-  Dp.val.assign(Dp.rowptr[nD], 0.0);
-  {
-    std::vector<int64_t> pos(Dp.rowptr.begin(), Dp.rowptr.end() - 1);
-    for (int64_t i = 0; i < q; ++i) {
-      if (bt.role[i] != SA_FACE_DIRICHLET) continue;
-      for (int64_t e = bt.fptr[i]; e < bt.fptr[i + 1]; ++e) {
-        int64_t j = dpos[bt.fidx[e]];
-        if (j < 0) continue;
-        Dp.col[pos[j]] = (int32_t)i;
-        Dp.val[pos[j]] = bt.fval[e];  // the per-point density already carries w dS
-        pos[j]++;
-      }
-    }
-  }
-  Csr &Md = m.mass_dir;
-  Md.nrow = nD;
-  Md.rowptr.assign(nD + 1, 0);
-  Md.col.clear();
-  Md.val.clear();
-  for (int64_t j = 0; j < nD; ++j) {
-    for (auto &kv : mrows[j]) {
-      Md.col.push_back((int32_t)kv.first);
-      Md.val.push_back(kv.second);
-    }
-    Md.rowptr[j + 1] = (int64_t)Md.col.size();
-  }
+  build_transfer(bt, nd, m.free_mask, m.load, m.dir_dofs, m.dproj, m.mass_dir);
   m.free_box_ok = 1;
-  (void)n_dir_faces;
-  (void)dir_face;
 }
 
 // ---------------------------------------------------------------------------
@@ -830,6 +834,56 @@ double fd_inverse_defect(const FdData &F, const Stencil &S, const std::vector<do
       den = std::max(den, std::fabs(y[i]));
     }
   return den > 0 ? num / den : 0.0;
+}
+
+
+// ---------------------------------------------------------------------------
+// chunking of the source history of the kernel sum: enough workgroups to fill
+// the chip, the FP64 sources weighted by their cost.  The chunk lengths
+// depend on the point count, the batch and the source counts only, never on
+// the tile shape (points per lane, waves per group), so every tile shape
+// gives bitwise the same sums.
+// ---------------------------------------------------------------------------
+SumPlan plan_sum(const sa_solver_options &o, int64_t nq, int count, int64_t max_far, int64_t max_near) {
+  constexpr int64_t kRefBlockPoints = 512;
+  constexpr int64_t kTargetGroups = 2048;
+  SumPlan pl{};
+  pl.points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
+  pl.waves = o.waves_per_group ? std::min(o.waves_per_group, 8) : 4;
+  pl.nq = nq;
+  pl.chunk_far = pl.chunk_near = 1;
+  auto tile_up = [](int64_t n) { return (n + kTile32 - 1) / kTile32 * kTile32; };
+  if (o.chunk_sources > 0) {
+    pl.chunk_near = o.chunk_sources;
+    pl.chunk_far = (int)tile_up(o.chunk_sources);   // far chunks start on FP32 record blocks
+    pl.n_chunks_far = (int)((max_far + pl.chunk_far - 1) / pl.chunk_far);
+    pl.n_chunks_near = (int)((max_near + pl.chunk_near - 1) / pl.chunk_near);
+    return pl;
+  }
+  const int64_t n_ref = std::max<int64_t>(1, (nq + kRefBlockPoints - 1) / kRefBlockPoints);
+  const int64_t C = std::max<int64_t>(1, (kTargetGroups + n_ref * count - 1) / (n_ref * count));
+  const double wf = (double)max_far, wn = 3.0 * (double)max_near;
+  int64_t cf = 0, cn = 0;
+  if (max_far > 0 && max_near > 0) {
+    cf = std::max<int64_t>(1, (int64_t)std::llround(C * wf / (wf + wn)));
+    cn = std::max<int64_t>(1, C - cf);
+  } else if (max_far > 0) {
+    cf = C;
+  } else if (max_near > 0) {
+    cn = C;
+  }
+  const int64_t min_chunk = 32;
+  if (cf) {
+    const int64_t len = tile_up(std::max<int64_t>(min_chunk, (max_far + cf - 1) / cf));
+    pl.chunk_far = (int)len;
+    pl.n_chunks_far = (int)((max_far + len - 1) / len);
+  }
+  if (cn) {
+    const int64_t len = std::max<int64_t>(min_chunk, (max_near + cn - 1) / cn);
+    pl.chunk_near = (int)len;
+    pl.n_chunks_near = (int)((max_near + len - 1) / len);
+  }
+  return pl;
 }
 
 }  // namespace sa

@@ -1,0 +1,746 @@
+// Multi-patch models (C ABI sa_mp_*): NURBS patches glued conformingly by a
+// global numbering of their control points (shared control points on the
+// interfaces, C0 across them), the parts of Sec. 3.3 built from several
+// patches.  Set-up on the host: each patch's matrices (Eqs. 16-17) and
+// boundary tables (Eq. 18) as for one patch, scattered to the global
+// numbering; the load gather and the Dirichlet projection data (Eqs. 10-11)
+// from the joined tables.  A step on the device, one scan path:
+//   coefficients of the switched-on sources (Eq. 8), the kernel sum pair by
+//   pair at every boundary point (Eqs. 7-8), the reduction to T~, grad T~
+//   and the load densities, the load vector and the projection right-hand
+//   side as CSR gathers, the projection M_D u_D = b_D and the theta-step
+//   (Eq. 20) on the free unknowns with the Dirichlet columns moved to the
+//   right-hand side, both by Jacobi-preconditioned conjugate gradients.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "multipatch.h"
+#include "sa_internal.h"
+
+namespace {
+
+struct MpHipFail {
+  hipError_t e;
+  const char *what;
+};
+
+inline void mp_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) throw MpHipFail{e, what};
+}
+
+template <class T>
+T *mp_alloc(std::vector<void *> &owned, size_t n) {
+  void *p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) throw sa::SaError{SA_ENOMEM, "hipMalloc failed"};
+  owned.push_back(p);
+  return (T *)p;
+}
+
+template <class T>
+T *mp_upload(std::vector<void *> &owned, const std::vector<T> &h, hipStream_t st) {
+  T *p = mp_alloc<T>(owned, h.size());
+  if (!h.empty()) mp_check(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+  return p;
+}
+
+struct MpCsr {
+  int64_t nrow = 0;
+  int64_t *rowptr = nullptr;
+  int32_t *col = nullptr;
+  double *val = nullptr;
+  sa::CsrOp op() const { return sa::CsrOp{nrow, rowptr, col, val}; }
+};
+
+MpCsr upload_csr(std::vector<void *> &owned, const sa::Csr &c, hipStream_t st) {
+  MpCsr d;
+  d.nrow = c.nrow;
+  d.rowptr = mp_upload(owned, c.rowptr, st);
+  d.col = mp_upload(owned, c.col, st);
+  d.val = mp_upload(owned, c.val, st);
+  return d;
+}
+
+// global CSR from (row, col, value) triples, duplicates summed in input order
+sa::Csr csr_from_triples(int64_t nrow, std::vector<int64_t> &r, std::vector<int64_t> &c, std::vector<double> &v) {
+  std::vector<size_t> ord(r.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return r[a] != r[b] ? r[a] < r[b] : c[a] < c[b]; });
+  sa::Csr m;
+  m.nrow = nrow;
+  m.rowptr.assign(nrow + 1, 0);
+  int64_t pr = -1, pc = -1;
+  for (size_t k : ord) {
+    if (r[k] == pr && c[k] == pc) {
+      m.val.back() += v[k];
+      continue;
+    }
+    pr = r[k];
+    pc = c[k];
+    m.col.push_back((int32_t)c[k]);
+    m.val.push_back(v[k]);
+    m.rowptr[r[k] + 1]++;
+  }
+  for (int64_t i = 0; i < nrow; ++i) m.rowptr[i + 1] += m.rowptr[i];
+  return m;
+}
+
+}  // namespace
+
+struct sa_multipatch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<void *> owned;
+  std::vector<sa::PatchData> P;
+  std::vector<std::vector<int64_t>> gmap;
+  sa_material mat{};
+  sa_solver_options opt{};
+  double center[3] = {0, 0, 0};
+  int64_t nd = 0, nq = 0, stride = 0, nD = 0, nI = 0, nnz = 0;
+  sa::BoundaryTables bt;
+  // scan
+  std::vector<int64_t> tick;
+  int64_t n_src = 0, n_steps = 0, step = 0, tau_ticks = 0;
+  int ns = 1;
+  sa::CoeffParams cp{};
+  // device: points and sources
+  double *px = nullptr, *py = nullptr, *pz = nullptr, *pq2 = nullptr, *nx = nullptr, *ny = nullptr, *nz = nullptr,
+         *wdS = nullptr;
+  float *fx = nullptr, *fy = nullptr, *fz = nullptr, *fq2 = nullptr;
+  int8_t *role = nullptr;
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *sE = nullptr, *c64 = nullptr;
+  int64_t *stick = nullptr;
+  float *c32 = nullptr;
+  double *part = nullptr;
+  int64_t part_cap = 0;
+  // device: fields and state
+  double *T = nullptr, *G = nullptr, *LD = nullptr;
+  double *w = nullptr, *F = nullptr, *F1 = nullptr, *vD = nullptr, *vDn = nullptr, *bD = nullptr;
+  double *Bw = nullptr, *AIDvD = nullptr, *bI = nullptr, *xI = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *part_b = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_rr = nullptr;
+  sa::PcgScalars *sc = nullptr, *h_sc = nullptr;
+  MpCsr load, dproj, mdir, Bop, AII, AID;
+  int64_t *I_idx = nullptr, *D_idx = nullptr;
+  double *aii_inv = nullptr, *mdir_inv = nullptr;
+  // statistics
+  int64_t pcg_its = 0, dir_its = 0;
+  double last_relres = 0.0;
+
+  ~sa_multipatch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void *x : owned) (void)hipFree(x);
+    if (h_sc) (void)hipHostFree(h_sc);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+template <class F>
+int mp_guarded(F &&f) {
+  try {
+    return f();
+  } catch (const sa::SaError &e) {
+    sa::set_last_error(e.msg);
+    return e.code;
+  } catch (const MpHipFail &e) {
+    sa::set_last_error(std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return SA_EDEVICE;
+  } catch (const std::bad_alloc &) {
+    sa::set_last_error("host allocation failed");
+    return SA_ENOMEM;
+  } catch (...) {
+    sa::set_last_error("unexpected failure");
+    return SA_EINVAL;
+  }
+}
+
+// conjugate gradients with the Jacobi preconditioner on A x = b (device
+// arrays of n values; x holds the first iterate), to |r| <= rtol |b|
+int cg_jacobi(sa_multipatch *h, const sa::CsrOp &A, const double *inv_diag, const double *b, double *x,
+              double *relres) {
+  const hipStream_t st = h->stream;
+  const int64_t n = A.nrow;
+  if (n <= 0) {
+    *relres = 0.0;
+    return 0;
+  }
+  const int np = sa::parts_for(n);
+  sa::launch_csr_init(st, A, b, x, h->r, h->part_b);
+  sa::launch_jacobi(st, n, inv_diag, h->r, h->z, h->part_rz, nullptr);
+  sa::launch_pcg_start(st, n, np, h->part_b, np, h->part_rz, h->z, h->p, h->sc, h->opt.pcg_rtol);
+  int chunk = 8;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      sa::launch_csr_apply_dot(st, A, h->p, h->q, h->part_pq, h->sc);
+      sa::launch_pcg_update(st, n, np, h->part_pq, h->p, h->q, x, h->r, h->part_rr, h->sc);
+      sa::launch_jacobi(st, n, inv_diag, h->r, h->z, h->part_rz, h->sc);
+      sa::launch_pcg_direction(st, n, np, np, h->part_rr, h->part_rz, h->z, h->p, h->sc);
+    }
+    mp_check(hipMemcpyAsync(h->h_sc, h->sc, sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, st), "status copy");
+    mp_check(hipStreamSynchronize(st), "sync");
+    const sa::PcgScalars s = *h->h_sc;
+    // converged; or |b| at the FP64 underflow edge, where no relative test
+    // can pass and the solution is zero to that precision
+    if (s.done == 1 || s.bnorm2 <= 1e-280) {
+      *relres = s.bnorm2 > 0 ? std::sqrt(std::max(s.rr, 0.0) / s.bnorm2) : 0.0;
+      return s.iter;
+    }
+    if (s.done == 2) throw sa::SaError{SA_ENOCONV, "CG breakdown (operator not positive definite)"};
+    if (!std::isfinite(s.rz) || !std::isfinite(s.rr)) throw sa::SaError{SA_ENOCONV, "CG produced NaN/Inf"};
+    if (s.iter >= h->opt.pcg_max_iter) throw sa::SaError{SA_ENOCONV, "CG did not converge within pcg_max_iter"};
+    chunk = std::min({chunk * 2, 64, std::max(1, h->opt.pcg_max_iter - s.iter)});
+  }
+}
+
+void ensure_part(sa_multipatch *h, int64_t doubles) {
+  if (doubles <= h->part_cap) return;
+  mp_check(hipStreamSynchronize(h->stream), "sync");
+  if (h->part) {
+    mp_check(hipFree(h->part), "free");
+    h->owned.erase(std::find(h->owned.begin(), h->owned.end(), (void *)h->part));
+  }
+  h->part_cap = std::max<int64_t>(doubles, 2 * h->part_cap);
+  h->part = mp_alloc<double>(h->owned, (size_t)h->part_cap);
+}
+
+// one theta-step n -> n+1
+void mp_step_one(sa_multipatch *h) {
+  const hipStream_t st = h->stream;
+  const int64_t s1 = h->step + 1, now = s1 * h->ns;
+  sa::PathTab tab{};
+  tab.count = 1;
+  tab.path[0] = 0;
+  tab.src0[0] = 0;
+  tab.now[0] = now;
+  const int64_t a = (int64_t)(std::upper_bound(h->tick.begin(), h->tick.end(), now) - h->tick.begin());
+  int64_t f = 0;
+  if (h->opt.precision == SA_PREC_FP32_FAR && a > 0)
+    f = std::min<int64_t>(a, (int64_t)(std::lower_bound(h->tick.begin(), h->tick.begin() + a, now - h->tau_ticks) -
+                                       h->tick.begin()));
+  tab.n_act[0] = (int32_t)a;
+  tab.n_far[0] = (int32_t)f;
+  tab.mode[0] = 0;
+  // Eqs. 7-8 at the boundary points, their reduction and the load densities
+  if (a > 0) sa::launch_coeff(st, tab, a, h->stick, h->sx, h->sy, h->sz, h->sE, h->cp, h->c64, h->c32);
+  sa::SumPlan pl = sa::plan_sum(h->opt, h->nq, 1, f, a - f);
+  pl.part_stride = h->stride;
+  const int nch = pl.n_chunks_far + pl.n_chunks_near;
+  ensure_part(h, (int64_t)std::max(nch, 1) * 5 * h->stride);
+  if (nch > 0)
+    sa::launch_sum(st, pl, tab, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->c64, h->c32, h->part);
+  sa::launch_finalize(st, tab, true, h->nq, nch, h->stride, h->part, h->px, h->py, h->pz, h->nx, h->ny, h->nz, h->wdS,
+                      h->role, h->mat.k, h->stride, h->T, h->G, h->LD, nullptr, 0);
+  // load vector (Eq. 18) and the Dirichlet projection (Eq. 11)
+  sa::launch_gather(st, h->load.nrow, h->load.rowptr, h->load.col, h->load.val, h->LD, h->F1);
+  double rel = 0.0;
+  if (h->nD > 0) {
+    sa::launch_gather(st, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->LD, h->bD);
+    mp_check(hipMemcpyAsync(h->vDn, h->vD, h->nD * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+    h->dir_its += cg_jacobi(h, h->mdir.op(), h->mdir_inv, h->bD, h->vDn, &rel);
+  }
+  // theta-scheme (Eq. 20) on the free unknowns
+  sa::launch_csr_eval(st, h->nd, h->Bop.rowptr, h->Bop.col, h->Bop.val, h->w, h->Bw);
+  if (h->nD > 0) sa::launch_csr_eval(st, h->nI, h->AID.rowptr, h->AID.col, h->AID.val, h->vDn, h->AIDvD);
+  sa::launch_mp_rhs(st, h->nI, h->I_idx, h->Bw, h->F1, h->F, h->opt.theta, h->nD > 0 ? h->AIDvD : nullptr, h->w, h->bI,
+                    h->xI);
+  h->pcg_its += cg_jacobi(h, h->AII.op(), h->aii_inv, h->bI, h->xI, &rel);
+  h->last_relres = rel;
+  // commit: u^{n+1}, F^{n+1}, the Dirichlet values
+  sa::launch_mp_commit(st, h->nI, h->I_idx, h->xI, h->nD, h->D_idx, h->vDn, h->w);
+  std::swap(h->F, h->F1);
+  std::swap(h->vD, h->vDn);
+  mp_check(hipGetLastError(), "kernel launch");
+  h->step = s1;
+}
+
+void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const int64_t *index_map,
+           const sa_material *mat, const sa_scan_path *scan, const sa_solver_options &opt) {
+  if (n_patches < 1 || !patches || !index_map) throw sa::SaError{SA_EINVAL, "need at least one patch and the index map"};
+  for (int32_t p = 0; p < n_patches; ++p) sa::validate_inputs(&patches[p], mat, scan, opt, true);
+  if (scan->n_paths != 1) throw sa::SaError{SA_EINVAL, "a multi-patch model takes exactly one scan path"};
+  if (opt.precision != SA_PREC_FP64 && opt.precision != SA_PREC_FP32_FAR)
+    throw sa::SaError{SA_EINVAL, "multi-patch models take SA_PREC_FP64 or SA_PREC_FP32_FAR"};
+  h->mat = *mat;
+  h->opt = opt;
+  const double dt = scan->dt;
+  // per patch: matrices and boundary tables in its own numbering
+  std::vector<sa::Model> pm(n_patches);
+  int64_t off = 0, nd = 0;
+  h->P.resize(n_patches);
+  h->gmap.resize(n_patches);
+  for (int32_t p = 0; p < n_patches; ++p) {
+    sa::Model &m = pm[p];
+    m.mat = *mat;
+    m.opt = opt;
+    m.dt = dt;
+    sa::load_patch(&patches[p], m.P);
+    h->gmap[p].assign(index_map + off, index_map + off + m.P.ndof);
+    off += m.P.ndof;
+    for (int64_t g : h->gmap[p]) {
+      if (g < 0) throw sa::SaError{SA_EINVAL, "negative global index"};
+      nd = std::max(nd, g + 1);
+    }
+  }
+  // the index map: every global index used, joined control points coincide
+  {
+    std::vector<int64_t> first(nd, -1);
+    std::vector<double> ref(4 * nd, 0.0);
+    double ext = 0.0;
+    for (int32_t p = 0; p < n_patches; ++p)
+      for (int64_t A = 0; A < pm[p].P.ndof; ++A)
+        for (int c = 0; c < 3; ++c) ext = std::max(ext, std::fabs(pm[p].P.ctrl[4 * A + c]));
+    for (int32_t p = 0; p < n_patches; ++p)
+      for (int64_t A = 0; A < pm[p].P.ndof; ++A) {
+        const int64_t g = h->gmap[p][A];
+        const double *c = &pm[p].P.ctrl[4 * A];
+        if (first[g] < 0) {
+          first[g] = 1;
+          std::copy(c, c + 4, &ref[4 * g]);
+          continue;
+        }
+        for (int k = 0; k < 3; ++k)
+          if (std::fabs(c[k] - ref[4 * g + k]) > 1e-12 * ext)
+            throw sa::SaError{SA_EINVAL, "the index map joins control points at different positions"};
+        if (std::fabs(c[3] - ref[4 * g + 3]) > 1e-12 * std::fabs(ref[4 * g + 3]))
+          throw sa::SaError{SA_EINVAL, "the index map joins control points of different weights"};
+      }
+    for (int64_t g = 0; g < nd; ++g)
+      if (first[g] < 0) throw sa::SaError{SA_EINVAL, "the index map leaves a global index unused"};
+  }
+  h->nd = nd;
+  // the inputs are valid: from here on the device
+  mp_check(hipGetDevice(&h->device), "device");
+  mp_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "stream");
+  const hipStream_t st = h->stream;
+  for (int c = 0; c < 3; ++c) {
+    double lo = 1e300, hi = -1e300;
+    for (auto &m : pm)
+      for (int64_t A = 0; A < m.P.ndof; ++A) {
+        lo = std::min(lo, m.P.ctrl[4 * A + c]);
+        hi = std::max(hi, m.P.ctrl[4 * A + c]);
+      }
+    h->center[c] = 0.5 * (lo + hi);
+  }
+  // Eqs. 16-17 patch by patch, scattered to the global numbering
+  std::vector<int64_t> rM, cM;
+  std::vector<double> vM, vK;
+  std::vector<uint8_t> free_mask(nd, 1);
+  sa::BoundaryTables &bt = h->bt;
+  bt.nq = 0;
+  bt.fptr.assign(1, 0);
+  for (int32_t p = 0; p < n_patches; ++p) {
+    sa::Model &m = pm[p];
+    sa::assemble_volume(m);
+    sa::build_boundary(m);
+    const auto &g = h->gmap[p];
+    const sa::Stencil &S = m.M;
+    for (int o = 0; o < S.n_off; ++o) {
+      const int d0 = o % (2 * S.hw[0] + 1) - S.hw[0];
+      const int d1 = (o / (2 * S.hw[0] + 1)) % (2 * S.hw[1] + 1) - S.hw[1];
+      const int d2 = o / ((2 * S.hw[0] + 1) * (2 * S.hw[1] + 1)) - S.hw[2];
+      for (int64_t A = 0; A < S.nrow; ++A) {
+        const double mv = S.val[(size_t)o * S.nrow + A], kv = m.K.val[(size_t)o * S.nrow + A];
+        if (mv == 0.0 && kv == 0.0) continue;
+        const int a0 = (int)(A % S.n[0]) + d0, a1 = (int)((A / S.n[0]) % S.n[1]) + d1,
+                  a2 = (int)(A / ((int64_t)S.n[0] * S.n[1])) + d2;
+        if (a0 < 0 || a0 >= S.n[0] || a1 < 0 || a1 >= S.n[1] || a2 < 0 || a2 >= S.n[2]) continue;
+        const int64_t B = a0 + (int64_t)S.n[0] * (a1 + (int64_t)S.n[1] * a2);
+        rM.push_back(g[A]);
+        cM.push_back(g[B]);
+        vM.push_back(mv);
+        vK.push_back(kv);
+      }
+    }
+    // boundary points of the patch's non-interface faces, basis indices global
+    const sa::BoundaryTables &b = m.bt;
+    const int64_t base = bt.nq;
+    bt.x.insert(bt.x.end(), b.x.begin(), b.x.end());
+    bt.nrm.insert(bt.nrm.end(), b.nrm.begin(), b.nrm.end());
+    bt.wdS.insert(bt.wdS.end(), b.wdS.begin(), b.wdS.end());
+    bt.role.insert(bt.role.end(), b.role.begin(), b.role.end());
+    for (int64_t i = 0; i < b.nq; ++i) {
+      for (int64_t e = b.fptr[i]; e < b.fptr[i + 1]; ++e) {
+        bt.fidx.push_back(g[b.fidx[e]]);
+        bt.fval.push_back(b.fval[e]);
+      }
+      bt.fptr.push_back((int64_t)bt.fidx.size());
+    }
+    bt.nq = base + b.nq;
+    for (int64_t A = 0; A < m.P.ndof; ++A)
+      if (!m.free_mask[A]) free_mask[g[A]] = 0;
+    h->P[p] = m.P;
+  }
+  for (int f = 0; f <= 6; ++f) bt.face_off[f] = 0;
+  std::vector<int64_t> cK = cM, rK = rM;
+  sa::Csr Mg = csr_from_triples(nd, rM, cM, vM);
+  sa::Csr Kg = csr_from_triples(nd, rK, cK, vK);
+  h->nnz = (int64_t)Mg.col.size();
+  // A = M/dt + theta K, B = M/dt - (1 - theta) K (same sparsity)
+  const double th = opt.theta;
+  sa::Csr Bc = Mg, Ac = Mg;
+  for (size_t e = 0; e < Mg.val.size(); ++e) {
+    Ac.val[e] = Mg.val[e] / dt + th * Kg.val[e];
+    Bc.val[e] = Mg.val[e] / dt - (1.0 - th) * Kg.val[e];
+  }
+  // load gather, Dirichlet unknowns, projection data from the joined tables
+  sa::Csr L, Dp, Md;
+  std::vector<int64_t> dir_dofs;
+  sa::build_transfer(bt, nd, free_mask, L, dir_dofs, Dp, Md);
+  h->nD = (int64_t)dir_dofs.size();
+  std::vector<int64_t> I, pos(nd, -1), dpos(nd, -1);
+  for (int64_t A = 0; A < nd; ++A)
+    if (free_mask[A]) {
+      pos[A] = (int64_t)I.size();
+      I.push_back(A);
+    }
+  for (int64_t j = 0; j < h->nD; ++j) dpos[dir_dofs[j]] = j;
+  h->nI = (int64_t)I.size();
+  sa::Csr AII, AID;
+  AII.nrow = AID.nrow = h->nI;
+  AII.rowptr.assign(1, 0);
+  AID.rowptr.assign(1, 0);
+  std::vector<double> aii_inv(std::max<int64_t>(h->nI, 1), 1.0);
+  for (int64_t i = 0; i < h->nI; ++i) {
+    const int64_t A = I[i];
+    for (int64_t e = Ac.rowptr[A]; e < Ac.rowptr[A + 1]; ++e) {
+      const int64_t B = Ac.col[e];
+      if (pos[B] >= 0) {
+        AII.col.push_back((int32_t)pos[B]);
+        AII.val.push_back(Ac.val[e]);
+        if (B == A) aii_inv[i] = 1.0 / Ac.val[e];
+      } else {
+        AID.col.push_back((int32_t)dpos[B]);
+        AID.val.push_back(Ac.val[e]);
+      }
+    }
+    AII.rowptr.push_back((int64_t)AII.col.size());
+    AID.rowptr.push_back((int64_t)AID.col.size());
+  }
+  std::vector<double> md_inv(std::max<int64_t>(h->nD, 1), 1.0);
+  for (int64_t j = 0; j < h->nD; ++j)
+    for (int64_t e = Md.rowptr[j]; e < Md.rowptr[j + 1]; ++e)
+      if (Md.col[e] == j) md_inv[j] = 1.0 / Md.val[e];
+  // device: operators and index lists
+  h->Bop = upload_csr(h->owned, Bc, st);
+  h->AII = upload_csr(h->owned, AII, st);
+  h->AID = upload_csr(h->owned, AID, st);
+  h->load = upload_csr(h->owned, L, st);
+  h->dproj = upload_csr(h->owned, Dp, st);
+  h->mdir = upload_csr(h->owned, Md, st);
+  h->I_idx = mp_upload(h->owned, I, st);
+  h->D_idx = mp_upload(h->owned, dir_dofs, st);
+  h->aii_inv = mp_upload(h->owned, aii_inv, st);
+  h->mdir_inv = mp_upload(h->owned, md_inv, st);
+  // boundary points (centred coordinates)
+  h->nq = bt.nq;
+  h->stride = (bt.nq + 63) / 64 * 64;
+  {
+    const int64_t n = bt.nq;
+    std::vector<double> x(n), y(n), zz(n), q2(n), nx(n), ny(n), nz(n);
+    std::vector<float> fx(n), fy(n), fz(n), fq(n);
+    for (int64_t i = 0; i < n; ++i) {
+      x[i] = bt.x[3 * i] - h->center[0];
+      y[i] = bt.x[3 * i + 1] - h->center[1];
+      zz[i] = bt.x[3 * i + 2] - h->center[2];
+      q2[i] = x[i] * x[i] + y[i] * y[i] + zz[i] * zz[i];
+      nx[i] = bt.nrm[3 * i];
+      ny[i] = bt.nrm[3 * i + 1];
+      nz[i] = bt.nrm[3 * i + 2];
+      fx[i] = (float)x[i];
+      fy[i] = (float)y[i];
+      fz[i] = (float)zz[i];
+      fq[i] = (float)q2[i];
+    }
+    h->px = mp_upload(h->owned, x, st);
+    h->py = mp_upload(h->owned, y, st);
+    h->pz = mp_upload(h->owned, zz, st);
+    h->pq2 = mp_upload(h->owned, q2, st);
+    h->fx = mp_upload(h->owned, fx, st);
+    h->fy = mp_upload(h->owned, fy, st);
+    h->fz = mp_upload(h->owned, fz, st);
+    h->fq2 = mp_upload(h->owned, fq, st);
+    h->nx = mp_upload(h->owned, nx, st);
+    h->ny = mp_upload(h->owned, ny, st);
+    h->nz = mp_upload(h->owned, nz, st);
+    h->wdS = mp_upload(h->owned, bt.wdS, st);
+    h->role = mp_upload(h->owned, bt.role, st);
+    mp_check(hipStreamSynchronize(st), "sync");
+  }
+  // sources (centred)
+  const int64_t N = scan->src_offset[1];
+  if (N > 2000000000) throw sa::SaError{SA_EINVAL, "the path holds more than 2e9 sources"};
+  h->n_src = N;
+  h->n_steps = scan->n_steps[0];
+  h->tick.assign(scan->tick, scan->tick + N);
+  {
+    std::vector<double> x(N), y(N), zz(N), E(N);
+    for (int64_t i = 0; i < N; ++i) {
+      x[i] = scan->xyz[3 * i] - h->center[0];
+      y[i] = scan->xyz[3 * i + 1] - h->center[1];
+      zz[i] = scan->xyz[3 * i + 2] - h->center[2];
+      E[i] = scan->energy[i];
+    }
+    h->sx = mp_upload(h->owned, x, st);
+    h->sy = mp_upload(h->owned, y, st);
+    h->sz = mp_upload(h->owned, zz, st);
+    h->sE = mp_upload(h->owned, E, st);
+    h->stick = mp_upload(h->owned, h->tick, st);
+  }
+  h->ns = scan->sources_per_step;
+  const double rc = mat->rho * mat->cp, alpha = mat->k / rc;
+  h->cp = sa::CoeffParams{dt / scan->sources_per_step, scan->spot_radius * scan->spot_radius / (8.0 * alpha), alpha, rc,
+                          opt.kernel_scale};
+  h->tau_ticks = (int64_t)std::floor(opt.tau_near / h->cp.delta + 1e-9);
+  h->c64 = mp_alloc<double>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
+  h->c32 = mp_alloc<float>(h->owned, (size_t)std::max<int64_t>(N, 1) * sa::kCoefStride);
+  // fields, state (u = T_c: w = 0, F = 0, Dirichlet deviations 0) and work
+  auto zeros = [&](int64_t n) {
+    double *d = mp_alloc<double>(h->owned, (size_t)std::max<int64_t>(n, 1));
+    mp_check(hipMemsetAsync(d, 0, std::max<int64_t>(n, 1) * sizeof(double), st), "memset");
+    return d;
+  };
+  h->T = zeros(h->stride);
+  h->G = zeros(3 * h->stride);
+  h->LD = zeros(h->stride);
+  h->w = zeros(nd);
+  h->F = zeros(nd);
+  h->F1 = zeros(nd);
+  h->Bw = zeros(nd);
+  h->vD = zeros(h->nD);
+  h->vDn = zeros(h->nD);
+  h->bD = zeros(h->nD);
+  h->AIDvD = zeros(h->nI);
+  h->bI = zeros(h->nI);
+  h->xI = zeros(h->nI);
+  const int64_t nmax = std::max(h->nI, h->nD);
+  h->r = zeros(nmax);
+  h->z = zeros(nmax);
+  h->p = zeros(nmax);
+  h->q = zeros(nmax);
+  const int npart = sa::parts_for(nmax);
+  h->part_b = zeros(npart);
+  h->part_rz = zeros(npart);
+  h->part_pq = zeros(npart);
+  h->part_rr = zeros(npart);
+  h->sc = mp_alloc<sa::PcgScalars>(h->owned, 1);
+  mp_check(hipHostMalloc((void **)&h->h_sc, sizeof(sa::PcgScalars), hipHostMallocDefault), "pinned allocation");
+  mp_check(hipStreamSynchronize(st), "sync");
+}
+
+}  // namespace
+
+extern "C" {
+
+int sa_mp_setup(const sa_patch *patches, int32_t n_patches, const int64_t *index_map, const sa_material *mat,
+                const sa_scan_path *scan, sa_multipatch **out) {
+  return mp_guarded([&]() -> int {
+    if (!out) throw sa::SaError{SA_EINVAL, "NULL out"};
+    *out = nullptr;
+    if (!scan || !mat) throw sa::SaError{SA_EINVAL, "NULL material or scan path"};
+    sa_solver_options o{};
+    if (scan->opt) {
+      o = *scan->opt;
+    } else {
+      sa_iga_default_options(&o);
+    }
+    auto *h = new sa_multipatch();
+    try {
+      setup(h, patches, n_patches, index_map, mat, scan, o);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return SA_OK;
+  });
+}
+
+int sa_mp_step(sa_multipatch *h, int32_t n_steps) {
+  return mp_guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    if (n_steps < 0) throw sa::SaError{SA_EINVAL, "negative step count"};
+    for (int32_t k = 0; k < n_steps && h->step < h->n_steps; ++k) {
+      // the state of the last completed step survives a failing solve
+      try {
+        mp_step_one(h);
+      } catch (const sa::SaError &) {
+        (void)hipStreamSynchronize(h->stream);
+        throw;
+      }
+    }
+    mp_check(hipStreamSynchronize(h->stream), "sync");
+    return SA_OK;
+  });
+}
+
+int sa_mp_get_info(const sa_multipatch *h, sa_mp_info *info) {
+  return mp_guarded([&]() -> int {
+    if (!h || !info) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    *info = sa_mp_info{};
+    info->n_patches = (int32_t)h->P.size();
+    info->n_dof = h->nd;
+    info->n_bpts = h->nq;
+    info->n_dirichlet = h->nD;
+    info->n_free = h->nI;
+    info->nnz = h->nnz;
+    info->step = h->step;
+    info->pcg_iterations = h->pcg_its;
+    info->dirichlet_iterations = h->dir_its;
+    info->pcg_last_relres = h->last_relres;
+    return SA_OK;
+  });
+}
+
+int sa_mp_get_boundary_fields(sa_multipatch *h, double *T_gp, double *grad_gp, double *F, double *du) {
+  return mp_guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    const hipStream_t st = h->stream;
+    if (T_gp) mp_check(hipMemcpyAsync(T_gp, h->T, h->nq * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    if (grad_gp)
+      for (int c = 0; c < 3; ++c)
+        mp_check(hipMemcpyAsync(grad_gp + c * h->nq, h->G + c * h->stride, h->nq * sizeof(double),
+                                hipMemcpyDeviceToHost, st),
+                 "download");
+    if (F) mp_check(hipMemcpyAsync(F, h->F, h->nd * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    if (du) mp_check(hipMemcpyAsync(du, h->w, h->nd * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    mp_check(hipStreamSynchronize(st), "sync");
+    return SA_OK;
+  });
+}
+
+int sa_mp_get_boundary_points(sa_multipatch *h, double *x, double *normal, double *wdS) {
+  return mp_guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    if (x) std::memcpy(x, h->bt.x.data(), h->bt.x.size() * sizeof(double));
+    if (normal) std::memcpy(normal, h->bt.nrm.data(), h->bt.nrm.size() * sizeof(double));
+    if (wdS) std::memcpy(wdS, h->bt.wdS.data(), h->bt.wdS.size() * sizeof(double));
+    return SA_OK;
+  });
+}
+
+int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const double *xi, double *T, double *grad) {
+  return mp_guarded([&]() -> int {
+    if (!h || (n > 0 && (!xi || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
+    if (patch < 0 || patch >= (int32_t)h->P.size()) throw sa::SaError{SA_ERANGE, "patch index out of range"};
+    if (n == 0) return SA_OK;
+    const sa::PatchData &P = h->P[patch];
+    const auto &g = h->gmap[patch];
+    // host basis tables of the points (global column indices), physical points
+    std::vector<int64_t> rowptr(1, 0);
+    std::vector<int32_t> col;
+    std::vector<double> R, gx, gy, gz, xp(3 * n);
+    sa::PointEval pe;
+    for (int64_t i = 0; i < n; ++i) {
+      double u[3];
+      int span[3];
+      for (int d = 0; d < 3; ++d) {
+        u[d] = xi[3 * i + d];
+        if (!(u[d] >= 0.0 && u[d] <= 1.0)) throw sa::SaError{SA_ERANGE, "query point outside [0,1]^3"};
+        span[d] = P.b[d].find_span(u[d]);
+      }
+      sa::eval_point(P, u, span, pe);
+      const double(&J)[3][3] = pe.J;
+      const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      const double id = 1.0 / det;
+      double Ji[3][3];
+      Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+      Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+      Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+      Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+      Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+      Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+      Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+      Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+      Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+      for (int l = 0; l < pe.L; ++l) {
+        col.push_back((int32_t)g[pe.idx[l]]);
+        R.push_back(pe.R[l]);
+        double gg[3];
+        for (int c = 0; c < 3; ++c) gg[c] = pe.dR[l][0] * Ji[0][c] + pe.dR[l][1] * Ji[1][c] + pe.dR[l][2] * Ji[2][c];
+        gx.push_back(gg[0]);
+        gy.push_back(gg[1]);
+        gz.push_back(gg[2]);
+      }
+      rowptr.push_back((int64_t)col.size());
+      for (int c = 0; c < 3; ++c) xp[3 * i + c] = pe.x[c] - h->center[c];
+    }
+    const hipStream_t st = h->stream;
+    std::vector<void *> tmp;
+    struct Free {
+      std::vector<void *> &v;
+      ~Free() {
+        for (void *p : v) (void)hipFree(p);
+      }
+    } fr{tmp};
+    // T^ and its gradient: the contractions with the control values
+    int64_t *rp = mp_upload(tmp, rowptr, st);
+    int32_t *cl = mp_upload(tmp, col, st);
+    double *vals[4] = {mp_upload(tmp, R, st), mp_upload(tmp, gx, st), mp_upload(tmp, gy, st), mp_upload(tmp, gz, st)};
+    double *hat = mp_alloc<double>(tmp, 4 * n);
+    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(st, n, rp, cl, vals[k], h->w, hat + k * n);
+    // T~ and its gradient at the mapped points (the sources of the current step)
+    const int64_t stride = (n + 63) / 64 * 64;
+    std::vector<double> qx(n), qy(n), qz(n), q2(n);
+    std::vector<float> fx(n), fy(n), fz(n), fq(n);
+    for (int64_t i = 0; i < n; ++i) {
+      qx[i] = xp[3 * i];
+      qy[i] = xp[3 * i + 1];
+      qz[i] = xp[3 * i + 2];
+      q2[i] = qx[i] * qx[i] + qy[i] * qy[i] + qz[i] * qz[i];
+      fx[i] = (float)qx[i];
+      fy[i] = (float)qy[i];
+      fz[i] = (float)qz[i];
+      fq[i] = (float)q2[i];
+    }
+    double *dx = mp_upload(tmp, qx, st), *dy = mp_upload(tmp, qy, st), *dz = mp_upload(tmp, qz, st),
+           *dq = mp_upload(tmp, q2, st);
+    float *ex = mp_upload(tmp, fx, st), *ey = mp_upload(tmp, fy, st), *ez = mp_upload(tmp, fz, st),
+          *eq = mp_upload(tmp, fq, st);
+    std::vector<int8_t> rl(n, (int8_t)SA_FACE_SOURCE_PLANE);   // no load density at query points
+    int8_t *drl = mp_upload(tmp, rl, st);
+    double *dT = mp_alloc<double>(tmp, stride), *dG = mp_alloc<double>(tmp, 3 * stride),
+           *dLD = mp_alloc<double>(tmp, stride);
+    sa::PathTab tab{};
+    tab.count = 1;
+    tab.now[0] = h->step * h->ns;
+    tab.n_act[0] = (int32_t)(std::upper_bound(h->tick.begin(), h->tick.end(), tab.now[0]) - h->tick.begin());
+    tab.n_far[0] = 0;
+    const int64_t a = tab.n_act[0];
+    if (a > 0) sa::launch_coeff(st, tab, a, h->stick, h->sx, h->sy, h->sz, h->sE, h->cp, h->c64, h->c32);
+    sa::SumPlan pl = sa::plan_sum(h->opt, n, 1, 0, a);
+    pl.part_stride = stride;
+    const int nch = pl.n_chunks_far + pl.n_chunks_near;
+    double *part = mp_alloc<double>(tmp, (size_t)std::max(nch, 1) * 5 * stride);
+    if (nch > 0) sa::launch_sum(st, pl, tab, dx, dy, dz, dq, ex, ey, ez, eq, h->c64, h->c32, part);
+    sa::launch_finalize(st, tab, true, n, nch, stride, part, dx, dy, dz, dx, dy, dz, dq, drl, h->mat.k, stride, dT, dG,
+                        dLD, nullptr, 0);
+    std::vector<double> hv(4 * n), tt(n), tg(3 * n);
+    mp_check(hipMemcpyAsync(hv.data(), hat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    mp_check(hipMemcpyAsync(tt.data(), dT, n * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    for (int c = 0; c < 3; ++c)
+      mp_check(hipMemcpyAsync(tg.data() + c * n, dG + c * stride, n * sizeof(double), hipMemcpyDeviceToHost, st),
+               "download");
+    mp_check(hipStreamSynchronize(st), "sync");
+    mp_check(hipGetLastError(), "kernel launch");
+    for (int64_t i = 0; i < n; ++i) {
+      T[i] = h->mat.T0 + hv[i] + tt[i];
+      if (grad)
+        for (int c = 0; c < 3; ++c) grad[3 * i + c] = hv[(c + 1) * n + i] + tg[c * n + i];
+    }
+    return SA_OK;
+  });
+}
+
+void sa_mp_destroy(sa_multipatch *h) { delete h; }
+
+}  // extern "C"

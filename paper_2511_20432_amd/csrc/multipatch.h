@@ -1,0 +1,19 @@
+// Element-wise kernels of the multi-patch theta-step (multipatch_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sa {
+
+// bI[i] = Bw[I[i]] + theta F1[I[i]] + (1 - theta) F0[I[i]] - AIDvD[i]
+// (AIDvD may be NULL) and xI[i] = w[I[i]], for i < nI
+void launch_mp_rhs(hipStream_t st, int64_t nI, const int64_t *I, const double *Bw, const double *F1, const double *F0,
+                   double theta, const double *AIDvD, const double *w, double *bI, double *xI);
+
+// w[I[i]] = xI[i] (i < nI), w[D[j]] = vD[j] (j < nD)
+void launch_mp_commit(hipStream_t st, int64_t nI, const int64_t *I, const double *xI, int64_t nD, const int64_t *D,
+                      const double *vD, double *w);
+
+}  // namespace sa

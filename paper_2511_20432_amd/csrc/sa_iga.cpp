@@ -368,53 +368,9 @@ void collect_timing(sa_iga *h) {
 }
 
 // ---- kernel sum --------------------------------------------------------------
-// chunking of the source history: enough workgroups to fill the chip, the
-// FP64 sources weighted by their cost.  The chunk lengths depend on the point
-// count, the batch and the source counts only, never on the tile shape
-// (points per lane, waves per group), so every tile shape gives bitwise the
-// same sums.
-constexpr int64_t kRefBlockPoints = 512;
-constexpr int64_t kTargetGroups = 2048;
-
+// chunking of the source history (sa::plan_sum)
 sa::SumPlan make_plan(const sa_iga *h, int64_t nq, int count, int64_t max_far, int64_t max_near) {
-  sa::SumPlan pl{};
-  const auto &o = h->m.opt;
-  pl.points_per_lane = o.points_per_lane ? o.points_per_lane : 2;
-  pl.waves = o.waves_per_group ? std::min(o.waves_per_group, 8) : 4;
-  pl.nq = nq;
-  pl.chunk_far = pl.chunk_near = 1;
-  auto tile_up = [](int64_t n) { return (n + sa::kTile32 - 1) / sa::kTile32 * sa::kTile32; };
-  if (o.chunk_sources > 0) {
-    pl.chunk_near = o.chunk_sources;
-    pl.chunk_far = (int)tile_up(o.chunk_sources);   // far chunks start on FP32 record blocks
-    pl.n_chunks_far = (int)((max_far + pl.chunk_far - 1) / pl.chunk_far);
-    pl.n_chunks_near = (int)((max_near + pl.chunk_near - 1) / pl.chunk_near);
-    return pl;
-  }
-  const int64_t n_ref = std::max<int64_t>(1, (nq + kRefBlockPoints - 1) / kRefBlockPoints);
-  const int64_t C = std::max<int64_t>(1, (kTargetGroups + n_ref * count - 1) / (n_ref * count));
-  const double wf = (double)max_far, wn = 3.0 * (double)max_near;
-  int64_t cf = 0, cn = 0;
-  if (max_far > 0 && max_near > 0) {
-    cf = std::max<int64_t>(1, (int64_t)std::llround(C * wf / (wf + wn)));
-    cn = std::max<int64_t>(1, C - cf);
-  } else if (max_far > 0) {
-    cf = C;
-  } else if (max_near > 0) {
-    cn = C;
-  }
-  const int64_t min_chunk = 32;
-  if (cf) {
-    const int64_t len = tile_up(std::max<int64_t>(min_chunk, (max_far + cf - 1) / cf));
-    pl.chunk_far = (int)len;
-    pl.n_chunks_far = (int)((max_far + len - 1) / len);
-  }
-  if (cn) {
-    const int64_t len = std::max<int64_t>(min_chunk, (max_near + cn - 1) / cn);
-    pl.chunk_near = (int)len;
-    pl.n_chunks_near = (int)((max_near + len - 1) / len);
-  }
-  return pl;
+  return sa::plan_sum(h->m.opt, nq, count, max_far, max_near);
 }
 
 void ensure_part(sa_iga *h, int64_t doubles) {

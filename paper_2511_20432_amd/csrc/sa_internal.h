@@ -117,13 +117,21 @@ struct Model {
   int free_box_ok = 0;             // Dirichlet set is a union of end layers (box of free DOFs)
 };
 
+// interfaces: SA_FACE_INTERFACE is a valid face role (patches of a multi-patch model)
 void validate_inputs(const sa_patch *patch, const sa_material *mat, const sa_scan_path *scan,
-                     const sa_solver_options &opt);
+                     const sa_solver_options &opt, bool interfaces = false);
 void load_patch(const sa_patch *patch, PatchData &P);
 void assemble_volume(Model &m);
-void build_boundary(Model &m);
+void build_boundary(Model &m);       // faces with role SA_FACE_INTERFACE get no points
+void build_transfer(const BoundaryTables &bt, int64_t nd, const std::vector<uint8_t> &free_mask, Csr &load,
+                    std::vector<int64_t> &dir_dofs, Csr &dproj, Csr &mass_dir);
 void build_fd(Model &m);
 void fd_apply_host(const FdData &F, const double *r, double *z, int64_t n_full);
+
+// chunking of the kernel sum's source history for nq points and count paths
+// whose longest far and near histories are max_far and max_near sources
+struct SumPlan;
+SumPlan plan_sum(const sa_solver_options &o, int64_t nq, int count, int64_t max_far, int64_t max_near);
 
 // parameters of the far-history network (layout in mlp.h)
 constexpr int64_t kNetParams = 256 * 70 + 256 + 3 * (256 * 256 + 256) + 4 * 256 + 4;

@@ -69,6 +69,12 @@ class sa_stats(C.Structure):
                 ("host_enqueue_ms", C.c_double)]
 
 
+class sa_mp_info(C.Structure):
+    _fields_ = [("n_patches", C.c_int32), ("n_dof", C.c_int64), ("n_bpts", C.c_int64), ("n_dirichlet", C.c_int64),
+                ("n_free", C.c_int64), ("nnz", C.c_int64), ("step", C.c_int64), ("pcg_iterations", C.c_int64),
+                ("dirichlet_iterations", C.c_int64), ("pcg_last_relres", C.c_double)]
+
+
 EXPORTS = {
     "sa_iga_default_options": (C.c_int, [C.POINTER(sa_solver_options)]),
     "sa_iga_setup": (C.c_int, [C.POINTER(sa_patch), C.POINTER(sa_material), C.POINTER(sa_scan_path),
@@ -106,6 +112,14 @@ EXPORTS = {
                                     C.POINTER(C.c_double)]),
     "sa_mlp_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sa_mlp_destroy": (None, [C.c_void_p]),
+    "sa_mp_setup": (C.c_int, [C.POINTER(sa_patch), C.c_int32, _i64p, C.POINTER(sa_material),
+                              C.POINTER(sa_scan_path), C.POINTER(C.c_void_p)]),
+    "sa_mp_step": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sa_mp_get_info": (C.c_int, [C.c_void_p, C.POINTER(sa_mp_info)]),
+    "sa_mp_get_boundary_fields": (C.c_int, [C.c_void_p, _dp, _dp, _dp, _dp]),
+    "sa_mp_get_boundary_points": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
+    "sa_mp_eval_temperature": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, _dp, _dp, _dp]),
+    "sa_mp_destroy": (None, [C.c_void_p]),
     "sa_iga_last_error": (C.c_char_p, []),
     "sa_iga_destroy": (None, [C.c_void_p]),
 }
@@ -154,6 +168,56 @@ def default_options() -> sa_solver_options:
     return o
 
 
+def _patch_struct(patch: W.Patch, keep) -> sa_patch:
+    p = sa_patch()
+    for d in range(3):
+        p.degree[d] = patch.degree[d]
+        p.n_ctrl[d] = patch.n_ctrl[d]
+        p.knots[d] = _ptr(keep(patch.knots[d], np.float64), C.c_double)
+        p.quad_vol[d] = patch.quad_vol[d]
+    p.ctrl_xyzw = _ptr(keep(patch.ctrl, np.float64), C.c_double)
+    for f in range(6):
+        p.face_role[f] = patch.face_role[f]
+    p.quad_face = patch.quad_face
+    return p
+
+
+def _options_struct(options: Optional[W.Options], overrides: dict, keep) -> sa_solver_options:
+    o = default_options()
+    if options is not None:
+        o.theta = options.theta
+        o.kernel_scale = options.kernel_scale
+        o.precision = options.precision
+        o.tau_near = options.tau_near
+        o.pcg_rtol = options.pcg_rtol
+        o.pcg_max_iter = options.pcg_max_iter
+        o.preconditioner = options.preconditioner
+    overrides = dict(overrides)
+    weights = overrides.pop("surrogate_weights", None)
+    if weights is not None:
+        weights = keep(weights, np.float32)
+        o.surrogate_weights = _ptr(weights, C.c_float)
+        o.surrogate_len = len(weights)
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def _scan_struct(scan: W.ScanPath, o: sa_solver_options, keep) -> sa_scan_path:
+    s = sa_scan_path()
+    s.n_paths = scan.n_paths
+    s.src_offset = _ptr(keep(scan.src_offset, np.int64), C.c_int64)
+    s.xyz = _ptr(keep(scan.xyz.reshape(-1, 3) if len(scan.xyz) else np.zeros((1, 3)), np.float64), C.c_double)
+    s.tick = _ptr(keep(scan.tick if len(scan.tick) else np.ones(1, np.int64), np.int64), C.c_int64)
+    s.energy = _ptr(keep(scan.energy if len(scan.energy) else np.zeros(1), np.float64), C.c_double)
+    s.n_steps = _ptr(keep(scan.n_steps, np.int32), C.c_int32)
+    s.dt = scan.dt
+    s.sources_per_step = scan.sources_per_step
+    s.spot_radius = scan.spot_radius
+    s.opt = C.pointer(o)
+    return s
+
+
 class Model:
     """Owner of one sa_iga handle built from a workload description."""
 
@@ -168,45 +232,11 @@ class Model:
             self._keep.append(a)
             return a
 
-        p = sa_patch()
-        for d in range(3):
-            p.degree[d] = patch.degree[d]
-            p.n_ctrl[d] = patch.n_ctrl[d]
-            p.knots[d] = _ptr(keep(patch.knots[d], np.float64), C.c_double)
-            p.quad_vol[d] = patch.quad_vol[d]
-        p.ctrl_xyzw = _ptr(keep(patch.ctrl, np.float64), C.c_double)
-        for f in range(6):
-            p.face_role[f] = patch.face_role[f]
-        p.quad_face = patch.quad_face
+        p = _patch_struct(patch, keep)
         m = sa_material(material.k, material.rho, material.cp, material.T0)
-        o = default_options()
-        if options is not None:
-            o.theta = options.theta
-            o.kernel_scale = options.kernel_scale
-            o.precision = options.precision
-            o.tau_near = options.tau_near
-            o.pcg_rtol = options.pcg_rtol
-            o.pcg_max_iter = options.pcg_max_iter
-            o.preconditioner = options.preconditioner
-        weights = opt_overrides.pop("surrogate_weights", None)
-        if weights is not None:
-            weights = keep(weights, np.float32)
-            o.surrogate_weights = _ptr(weights, C.c_float)
-            o.surrogate_len = len(weights)
-        for k, v in opt_overrides.items():
-            setattr(o, k, v)
+        o = _options_struct(options, opt_overrides, keep)
         self.options = o
-        s = sa_scan_path()
-        s.n_paths = scan.n_paths
-        s.src_offset = _ptr(keep(scan.src_offset, np.int64), C.c_int64)
-        s.xyz = _ptr(keep(scan.xyz.reshape(-1, 3) if len(scan.xyz) else np.zeros((1, 3)), np.float64), C.c_double)
-        s.tick = _ptr(keep(scan.tick if len(scan.tick) else np.ones(1, np.int64), np.int64), C.c_int64)
-        s.energy = _ptr(keep(scan.energy if len(scan.energy) else np.zeros(1), np.float64), C.c_double)
-        s.n_steps = _ptr(keep(scan.n_steps, np.int32), C.c_int32)
-        s.dt = scan.dt
-        s.sources_per_step = scan.sources_per_step
-        s.spot_radius = scan.spot_radius
-        s.opt = C.pointer(o)
+        s = _scan_struct(scan, o, keep)
         h = C.c_void_p()
         check(lib.sa_iga_setup(C.byref(p), C.byref(m), C.byref(s), C.byref(h)))
         self._keep = []
@@ -443,3 +473,83 @@ class Mlp:
 
 def from_workload(w: W.Workload, **opt_overrides) -> Model:
     return Model(w.patch, w.material, w.scan, w.options, **opt_overrides)
+
+
+class MultiPatchModel:
+    """Owner of one sa_multipatch handle: patches glued by the global index
+    maps of their control points (workloads.glue), one scan path."""
+
+    def __init__(self, patches, maps, material: W.Material, scan: W.ScanPath,
+                 options: Optional[W.Options] = None, **opt_overrides):
+        lib = load_library()
+        self._lib = lib
+        keep_list = []
+
+        def keep(a, dtype):
+            a = np.ascontiguousarray(a, dtype=dtype)
+            keep_list.append(a)
+            return a
+
+        arr = (sa_patch * len(patches))()
+        for i, P in enumerate(patches):
+            arr[i] = _patch_struct(P, keep)
+        imap = keep(np.concatenate([np.asarray(g, np.int64) for g in maps]), np.int64)
+        m = sa_material(material.k, material.rho, material.cp, material.T0)
+        o = _options_struct(options, opt_overrides, keep)
+        s = _scan_struct(scan, o, keep)
+        h = C.c_void_p()
+        check(lib.sa_mp_setup(arr, len(patches), _ptr(imap, C.c_int64), C.byref(m), C.byref(s), C.byref(h)))
+        self.h = h
+        self.T0 = material.T0
+        self.info = self.get_info()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.sa_mp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        check(self._lib.sa_mp_step(self.h, n))
+
+    def get_info(self) -> sa_mp_info:
+        i = sa_mp_info()
+        check(self._lib.sa_mp_get_info(self.h, C.byref(i)))
+        return i
+
+    def boundary_fields(self):
+        """T~ [nq], grad T~ [nq, 3] at the boundary points, F [n_dof] and
+        du [n_dof] = T^ - T_c at the global control points."""
+        self.info = self.get_info()
+        nq, nd = self.info.n_bpts, self.info.n_dof
+        T = np.empty(nq)
+        G = np.empty((3, nq))
+        F = np.empty(nd)
+        u = np.empty(nd)
+        check(self._lib.sa_mp_get_boundary_fields(self.h, _ptr(T, C.c_double), _ptr(G, C.c_double),
+                                                  _ptr(F, C.c_double), _ptr(u, C.c_double)))
+        return T, G.T.copy(), F, u
+
+    def boundary_points(self):
+        nq = self.info.n_bpts
+        x = np.empty((nq, 3))
+        n = np.empty((nq, 3))
+        w = np.empty(nq)
+        check(self._lib.sa_mp_get_boundary_points(self.h, _ptr(x, C.c_double), _ptr(n, C.c_double),
+                                                  _ptr(w, C.c_double)))
+        return x, n, w
+
+    def eval_temperature(self, patch: int, xi: np.ndarray):
+        """T [n] and grad T [n, 3] at parametric points xi [n, 3] of one patch."""
+        xi = np.ascontiguousarray(np.atleast_2d(xi), np.float64)
+        n = len(xi)
+        T = np.empty(n)
+        G = np.empty((n, 3))
+        check(self._lib.sa_mp_eval_temperature(self.h, patch, n, _ptr(xi, C.c_double), _ptr(T, C.c_double),
+                                               _ptr(G, C.c_double)))
+        return T, G

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sa
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sa_(?:iga|mlp)_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(sa_(?:iga|mlp|mp)_\w+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -120,3 +120,38 @@ def test_null_arguments():
     assert lib.sa_mlp_train_step(None, 1, None, None, 1e-3, None) == sa_iga.SA_EINVAL
     assert lib.sa_mlp_gradients(None, 1, None, None, None, None) == sa_iga.SA_EINVAL
     lib.sa_mlp_destroy(None)
+
+
+def test_multipatch_inputs_rejected_before_device():
+    """sa_mp_setup checks its patches, roles, index map, scan and options on
+    the host before it touches a device."""
+    w = W.l_part()
+
+    def expect(code, patches, maps, scan=w.scan, **kw):
+        with pytest.raises(sa_iga.SaError) as e:
+            sa_iga.MultiPatchModel(patches, maps, w.material, scan, **kw)
+        assert e.value.code == code
+
+    # the single-patch model takes no interface faces
+    with pytest.raises(sa_iga.SaError) as e:
+        sa_iga.Model(w.patches[0], w.material, w.scan)
+    assert e.value.code == sa_iga.SA_EINVAL
+    bad = [p for p in w.patches]
+    bad[1] = W.block_patch_knots((1e-3, 0, 0), (2e-3, 1e-3, 0.5e-3), bad[1].knots, 2, (4, 0, 0, 0, 1, 2))
+    expect(sa_iga.SA_EINVAL, bad, w.maps)
+    # an index map that joins control points at different positions
+    maps = [m.copy() for m in w.maps]
+    maps[1][0], maps[1][1] = maps[1][1], maps[1][0]
+    expect(sa_iga.SA_EINVAL, w.patches, maps)
+    # an unused global index, a negative one
+    maps = [m.copy() for m in w.maps]
+    maps[2] = maps[2] + 1
+    expect(sa_iga.SA_EINVAL, w.patches, maps)
+    maps = [m.copy() for m in w.maps]
+    maps[0][3] = -1
+    expect(sa_iga.SA_EINVAL, w.patches, maps)
+    # one path only; FP64 or FP32 far field only
+    two = W.make_scan([(w.scan.xyz, w.scan.tick, w.scan.energy)] * 2, w.scan.dt, w.scan.sources_per_step,
+                      n_steps=[10, 10])
+    expect(sa_iga.SA_EINVAL, w.patches, w.maps, scan=two)
+    expect(sa_iga.SA_EINVAL, w.patches, w.maps, precision=2)

@@ -1,0 +1,105 @@
+"""Multi-patch models through the C ABI (sa_mp_*) against the FP64 oracle's
+multi-patch model: the three-patch L-shaped part with a track that crosses
+both interfaces.
+
+  * FP64: T~ and grad T~ at the boundary points, the load vector and the
+    control values after 40 and 150 steps within 1e-9 (normwise), and T,
+    grad T at 100 parametric points of each patch (20 on the top face)
+    within 1e-9 of the fields' scale;
+  * FP32 far field: within 0.05 K of the oracle over the same steps;
+  * a finer L-shaped part (9,360 unknowns) over 60 steps within 1e-9.
+"""
+import numpy as np
+import pytest
+
+from oracle import multipatch
+from paper_2511_20432_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _models(w, precision=W.PRECISION_FP64):
+    from paper_2511_20432_amd import sa_iga
+    gm = sa_iga.MultiPatchModel(w.patches, w.maps, w.material, w.scan,
+                                W.Options(precision=precision, tau_near=2e-4))
+    om = multipatch.MultiPatchModel(w.patches, w.maps, w.material, w.scan)
+    return gm, om
+
+
+def test_l_part_fp64_matches_oracle():
+    w = W.l_part()
+    gm, om = _models(w)
+    info = gm.get_info()
+    assert info.n_patches == 3 and info.n_dof == om.n_dof and info.n_bpts == len(om.bt["wdS"])
+    assert info.n_dirichlet == len(om.D)
+    x, n, wdS = gm.boundary_points()
+    assert np.abs(x - om.bt["x"]).max() <= 1e-15 and np.abs(wdS - om.bt["wdS"]).max() <= 1e-13 * wdS.max()
+    done = 0
+    for s in (40, 150):
+        gm.step(s - done)
+        om.advance(s - done)
+        done = s
+        T, G, F, du = gm.boundary_fields()
+        Tr, Gr = om.boundary_field(s)
+        errs = {"T": rel(T, Tr), "grad": rel(G, Gr), "F": rel(F, om.F), "du": rel(du, om.w)}
+        print(f"L part, {info.n_dof} DOFs, step {s}: max |w| {np.abs(om.w).max():.3e} K, worst rel "
+              f"{max(errs.values()):.2e}, CG iterations per step {gm.get_info().pcg_iterations / s:.1f}", flush=True)
+        assert max(errs.values()) <= TOL, errs
+    # T and grad T at 100 parametric points of each patch, 20 on the top
+    # face, on the scale of the fields (the control values and the boundary
+    # gradients): most random points lie where T^ and T~ are small, and the
+    # control values' solve error (~1e-12 of max |w|) grows by 1/h in grad T^
+    rng = np.random.default_rng(3)
+    scale_T = np.abs(om.w).max()
+    scale_G = np.abs(Gr).max()
+    for p in range(3):
+        xi = rng.uniform(0, 1, (100, 3))
+        xi[:20, 2] = 1.0
+        T, G = gm.eval_temperature(p, xi)
+        Tr_p, Gr_p, _ = om.evaluate(p, xi)
+        assert np.abs(T - Tr_p).max() <= TOL * max(scale_T, np.abs(Tr_p - w.material.T0).max())
+        assert np.abs(G - Gr_p).max() <= TOL * max(scale_G, np.abs(Gr_p).max())
+
+
+def test_l_part_fp32_far_within_005K():
+    w = W.l_part()
+    gm, om = _models(w, W.PRECISION_FP32_FAR)
+    om.advance(150)
+    gm.step(150)
+    T, _, _, du = gm.boundary_fields()
+    Tr, _ = om.boundary_field(150)
+    e = float(np.abs(T - Tr).max() + np.abs(du - om.w).max())
+    print(f"L part FP32 far field, step 150: |dT~| + |dw| = {e:.2e} K", flush=True)
+    assert e <= 0.05
+
+
+def test_finer_l_part_matches_oracle():
+    w = W.l_part(n_el=(16, 16, 8))
+    gm, om = _models(w)
+    gm.step(60)
+    om.advance(60)
+    _, _, F, du = gm.boundary_fields()
+    errs = {"F": rel(F, om.F), "du": rel(du, om.w)}
+    print(f"finer L part, {gm.get_info().n_dof} DOFs, step 60: worst rel {max(errs.values()):.2e}", flush=True)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_steps_stop_at_the_end_of_the_scan():
+    from paper_2511_20432_amd import sa_iga
+    w = W.l_part()
+    scan = W.make_scan([(w.scan.xyz[:20], w.scan.tick[:20], w.scan.energy[:20])], w.scan.dt,
+                       w.scan.sources_per_step, n_steps=[4])
+    gm = sa_iga.MultiPatchModel(w.patches, w.maps, w.material, scan)
+    gm.step(10)
+    assert gm.get_info().step == 4
+    with pytest.raises(sa_iga.SaError):
+        gm.eval_temperature(3, np.zeros((1, 3)))
+    with pytest.raises(sa_iga.SaError):
+        gm.eval_temperature(0, np.array([[0.5, 0.5, 1.5]]))
