@@ -379,6 +379,47 @@ def run_small():
     return r
 
 
+def run_multipatch():
+    """A multi-patch part: the three-patch L-shaped part (the corner square
+    and two arms, 24 x 24 x 12 quadratic elements per patch), all steps of
+    its track through both interfaces, FP64 and FP32 far field (one path,
+    pair-by-pair sum, Jacobi CG)."""
+    import torch
+    from paper_2511_20432_amd import sa_iga
+    from paper_2511_20432_amd import workloads as W
+    w = W.l_part(n_el=(24, 24, 12))
+    n = int(w.scan.n_steps[0])
+    ns = w.scan.sources_per_step
+    act = np.searchsorted(w.scan.tick, ns * np.arange(1, n + 1), side="right")
+    out = {"workload": (f"L-shaped part of three conforming patches (1 mm corner square and two 1 mm arms, "
+                        f"0.5 mm high, quadratic, 24x24x12 elements each), one track of {n} steps through both "
+                        f"interfaces, 80 W, 1 m/s, 5 sources/step")}
+    ref = None
+    for name, prec in (("fp64", W.PRECISION_FP64), ("fp32far", W.PRECISION_FP32_FAR)):
+        t0 = time.perf_counter()
+        m = sa_iga.MultiPatchModel(w.patches, w.maps, w.material, w.scan, W.Options(precision=prec, tau_near=2e-4))
+        setup_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m.step(n)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        info = m.get_info()
+        T, _, _, du = m.boundary_fields()
+        pairs = float(act.sum()) * info.n_bpts
+        r = {"n_dof": info.n_dof, "n_bpts": info.n_bpts, "nnz": info.nnz, "setup_s": setup_s,
+             "ms_per_step": 1e3 * dt / n, "pairs_per_s": pairs / dt, "steps": n,
+             "cg_iterations_per_step": info.pcg_iterations / n,
+             "projection_cg_iterations_per_step": info.dirichlet_iterations / n}
+        if ref is None:
+            ref = (T, du)
+        else:
+            r["max_err_K_vs_fp64"] = float(np.abs(T - ref[0]).max() + np.abs(du - ref[1]).max())
+        out[name] = r
+        m.close()
+    return out
+
+
 # Tables 3 and 4: the paper's integrated net heat-loss rate along the top arc
 # (J s^-1 m^-1) and its percentage of the analytical field's, IGA meshes with
 # minimum element sizes 100, 68 and 50 um (context: an FEM reference decides
@@ -557,7 +598,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60, help="timed batched steps of the headline window")
     ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
-    ap.add_argument("--legs", default="headline,batch,raster,annulus,small,paper",
+    ap.add_argument("--legs", default="headline,batch,raster,annulus,small,paper,multipatch",
                     help="comma-separated subset of headline,batch,raster,annulus,small,paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -623,6 +664,9 @@ def main():
     if "paper" in legs:
         print("[bench] the paper's experiments on the Table 2 part", file=sys.stderr, flush=True)
         out["paper_parts"] = run_paper_parts()
+    if "multipatch" in legs:
+        print("[bench] a multi-patch part", file=sys.stderr, flush=True)
+        out["multipatch"] = run_multipatch()
     if "headline" in legs and not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle kernel sum)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w5, start, warmup)
