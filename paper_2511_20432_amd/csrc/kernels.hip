@@ -163,7 +163,7 @@ void launch_coeff(hipStream_t st, const PathTab &tab, int64_t max_act, const int
 // operands formed in the lanes (one exponential per row or column and source
 // instead of one per pair), the chunk's sources staged in LDS 256 at a time.
 // Far chunks: FP32 operands (coordinates relative to the tile) and
-// accumulation over 64 sources, then FP64 (32 x 32 x 2 steps); near chunks:
+// accumulation over 128 sources, then FP64 (32 x 32 x 2 steps); near chunks:
 // FP64 (16 x 16 x 4 steps).  The operand layouts are given at each kind of
 // item (checked on the device).
 // ---------------------------------------------------------------------------
@@ -219,9 +219,9 @@ __device__ __forceinline__ void fetch_source(const TensorArgs &ta, const ItemSrc
 
 // Far item: FP32 32 x 32 x 2 matrix-core steps.  The workgroup's tile is
 // 32 x 32 points (rows b, columns a); each wave takes a quarter of every
-// staged block of 256 sources (2 sources per step, 32 steps) for the whole
+// staged block of 512 sources (2 sources per step, 64 steps) for the whole
 // tile, so every L row and R column value is formed once per source.  After
-// each block the waves' FP32 sums (64 sources each) go to LDS and every
+// each block the waves' FP32 sums (128 sources each) go to LDS and every
 // thread adds the four of each of its 16 outputs, in wave order, to its FP64
 // accumulators (the same summation at every launch shape).  Staged record
 // per source (base 2, coordinates relative to the tile's first point, where
@@ -231,13 +231,14 @@ __device__ __forceinline__ void fetch_source(const TensorArgs &ta, const ItemSrc
 // B[l / 32][l % 32]; element r of lane l is D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 constexpr int kFarPad = 36;                              // LDS column stride of the wave sums (floats)
 constexpr int kFarSumBytes = 4 * 2 * 32 * kFarPad * 4;   // 4 waves x 2 kinds x 32 columns (one pass)
-constexpr int kTensorLds = kStage * 32 + kFarSumBytes;   // far: records + wave sums; near: 5 kStage doubles
+constexpr int kStageFar = 512;                          // far items: sources staged at a time (128 per wave)
+constexpr int kTensorLds = kStageFar * 32 + kFarSumBytes;   // far: records + wave sums; near: 5 kStage doubles
 static_assert(kTensorLds >= 5 * kStage * 8, "near items stage 5 doubles per source");
 
 __device__ __forceinline__ void tensor_far(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
                                            int n_chunks, int chunk_far, unsigned char *lds) {
   float4 (*srf)[2] = (float4(*)[2])lds;
-  float *wsum = (float *)(lds + kStage * 32);
+  float *wsum = (float *)(lds + kStageFar * 32);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 31, k = lane >> 5;
   const int tile = item % ta.n_tiles;
@@ -264,25 +265,33 @@ __device__ __forceinline__ void tensor_far(const TensorArgs &ta, const PathTab &
 #pragma unroll
     for (int r = 0; r < 16; ++r) accf[g][r] = 0.f;
   const double l2e = 1.4426950408889634;
-  SrcRegs nx{0.0, 0.0, 0.0, 0.0, 0.0};
-  if (is.lo < is.hi) fetch_source(ta, is, is.lo, nx);
-  for (int blk = is.lo; blk < is.hi; blk += kStage) {
-    const int n_in = is.hi - blk < kStage ? is.hi - blk : kStage;
+  // each thread stages two sources of a block: t and t + 256
+  SrcRegs nx0{0.0, 0.0, 0.0, 0.0, 0.0}, nx1{0.0, 0.0, 0.0, 0.0, 0.0};
+  auto stage = [&](const SrcRegs &v, int t) {
+    const double c = v.c, dn = F.sn - v.xn;
+    const double base = fma(c * dn, dn, v.lnA);
+    srf[t][0] = make_float4((float)(c * l2e), (float)(v.xa - oa), (float)(v.xb - ob), (float)(2.0 * c * dn));
+    srf[t][1] = make_float4((float)(base * l2e), (float)(2.0 * c), 0.f, 0.f);
+  };
+  if (is.lo < is.hi) {
+    fetch_source(ta, is, is.lo, nx0);
+    fetch_source(ta, is, is.lo + kStage, nx1);
+  }
+  for (int blk = is.lo; blk < is.hi; blk += kStageFar) {
+    const int n_in = is.hi - blk < kStageFar ? is.hi - blk : kStageFar;
     __syncthreads();
-    if ((int)threadIdx.x < n_in) {
-      const double c = nx.c, dn = F.sn - nx.xn;
-      const double base = fma(c * dn, dn, nx.lnA);
-      srf[threadIdx.x][0] = make_float4((float)(c * l2e), (float)(nx.xa - oa), (float)(nx.xb - ob),
-                                        (float)(2.0 * c * dn));
-      srf[threadIdx.x][1] = make_float4((float)(base * l2e), (float)(2.0 * c), 0.f, 0.f);
+    if ((int)threadIdx.x < n_in) stage(nx0, threadIdx.x);
+    if ((int)threadIdx.x + kStage < n_in) stage(nx1, threadIdx.x + kStage);
+    if (blk + kStageFar < is.hi) {
+      fetch_source(ta, is, blk + kStageFar, nx0);
+      fetch_source(ta, is, blk + kStageFar + kStage, nx1);
     }
-    if (blk + kStage < is.hi) fetch_source(ta, is, blk + kStage, nx);
     __syncthreads();
-    if (n_in == kStage && full_tile) {
-      const int w0 = 64 * wave;
+    if (n_in == kStageFar && full_tile) {
+      const int w0 = 128 * wave;
       // every source and every point valid: no masks
 #pragma unroll
-      for (int st = 0; st < 32; ++st) {
+      for (int st = 0; st < 64; ++st) {
         const int t = w0 + 2 * st + k;
         const float4 u0 = srf[t][0], u1 = srf[t][1];
         const float cl = u0.x, xa = u0.y, xb = u0.z, tn = u0.w, base = u1.x, c2 = u1.y;
