@@ -416,7 +416,10 @@ void sa_iga_destroy(sa_iga *h);
  *   z1 = W1 x + b1, h1 = gelu(z1)            W1 [256][70], FP32
  *   z_l = W_l h_{l-1} + b_l, h_l = gelu(z_l)  l = 2, 3, 4; W_l [256][256]
  *   y = W5 h4 + b5                           W5 [4][256], FP32
- * gelu(z) = z (1 + erf(z / sqrt 2)) / 2.  The layers 2..4 run on the matrix
+ * gelu(z) = z (1 + erf(z / sqrt 2)) / 2, evaluated in the tanh form of
+ * Hendrycks & Gimpel (2016), z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))) / 2,
+ * within 4.7e-4 of it everywhere; the backward pass differentiates that same
+ * tanh form.  The layers 2..4 run on the matrix
  * cores with bfloat16 operands (h_{l-1} and W_l rounded to nearest even) and
  * FP32 accumulation, h1..h4 are stored in bfloat16.  Parameters are one FP32
  * vector in the order W1, b1, W2, b2, W3, b3, W4, b4, W5, b5 (row-major,

@@ -24,7 +24,9 @@ sides implement:
         targets t scaled the same way.
 
 Precision of the GPU network, which `forward(..., bf16=True)` reproduces
-value for value (so the comparison measures only accumulation order):
+at the same rounding points (so the comparison measures accumulation order
+and the GPU's GELU, the tanh form of Hendrycks & Gimpel, within 4.7e-4 of
+the erf form defined here):
 the hidden products W_l h_{l-1} (l = 2..4) take both operands rounded to
 bfloat16 and accumulate in FP32; the activations h1..h4 are stored in
 bfloat16; the first and the output layer use FP32 weights.  In the backward

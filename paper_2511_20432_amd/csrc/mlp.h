@@ -41,7 +41,9 @@ struct MlpLayout {
 // C(m, n) = act(sum_k A(m, k) B(k, n) + bias[n]) with A(m, k) = A[m a_sm + k a_sk],
 // B(k, n) = B[k b_sk + n b_sn] in bfloat16, FP32 accumulation.  Outputs (each
 // optional): z = the pre-activation (FP32), out = act(.) in bfloat16, outf =
-// act(.) in FP32.
+// act(.) in FP32.  ws (may be NULL) of ws_floats floats: a workspace that lets
+// a product with few output tiles and a long k range split that range over
+// workgroups (FP32 partials added in a fixed order).
 struct GemmArgs {
   int64_t M, N, K;
   const bf16_t *A;
@@ -53,7 +55,10 @@ struct GemmArgs {
   float *z;  int64_t ldz;
   bf16_t *out;  int64_t ldo;
   float *outf;  int64_t ldf;
+  float *ws;  int64_t ws_floats;
 };
+// workspace the trainer's products and batch sums need (floats)
+int64_t trainer_ws_floats();
 void launch_gemm_bf16(hipStream_t st, const GemmArgs &g);
 
 // FP32 <-> bfloat16 (round to nearest, ties to even)
@@ -81,18 +86,19 @@ void launch_layer_out_field(hipStream_t st, int64_t r0, int64_t rows, int64_t nq
 // backward pieces (training)
 // dy = 2 (y - t) / (B * 4); sum of (y - t)^2 per 256 rows in loss_part
 // [(B + 255) / 256]; dh4 = W5^T dy; dz4 = bf16(dh4 gelu'(z4));
-// dW5 = dy^T h4, db5 = sum dy (FP32, fixed order)
+// dW5 = dy^T h4, db5 = sum dy (FP32; the rows in at most 64 chunks, each
+// summed in row order, the chunks in order).  ws: trainer_ws_floats() floats
 int loss_parts(int64_t B);
 void launch_out_backward(hipStream_t st, int64_t B, const float *y, const float *t, const bf16_t *h4,
                          const float *z4, const float *W5, float *dy, double *loss_part, bf16_t *dz4, float *dW5,
-                         float *db5);
+                         float *db5, float *ws);
 // dz = bf16(dh gelu'(z)) over B x 256
 void launch_gelu_backward(hipStream_t st, int64_t n, const float *dh, const float *z, bf16_t *dz);
-// db[n] = sum_b dz[b][n] (bfloat16 rows, FP32 sums in fixed order)
-void launch_colsum_bf16(hipStream_t st, int64_t B, int64_t N, const bf16_t *dz, float *db);
+// db[n] = sum_b dz[b][n] (bfloat16 rows, FP32 sums in the fixed order above)
+void launch_colsum_bf16(hipStream_t st, int64_t B, int64_t N, const bf16_t *dz, float *db, float *ws);
 // first layer: dz1 = dh1 gelu'(z1) (FP32); dW1 = dz1^T X, db1 = sum dz1
 void launch_layer1_backward(hipStream_t st, int64_t B, const float *dh1, const float *z1, const float *X,
-                            float *dz1, float *dW1, float *db1);
+                            float *dz1, float *dW1, float *db1, float *ws);
 double reduce_loss_host(hipStream_t st, const double *loss_part, int n);
 
 // Adam on the FP32 master vector (bias-corrected, step t >= 1)
@@ -101,8 +107,9 @@ void launch_adam(hipStream_t st, int64_t n, float *w, const float *g, float *m, 
 
 // Whole network on boundary rows r0 .. r0+rows of the slot-major row space
 // (row r: slot r / nq, point r % nq), activations kept in registers: each
-// wave computes D = W H^T for 64 points (two 32-point MFMA column tiles),
-// and the 32 x 32 accumulator layout of one layer is the next layer's B
+// wave computes D = W H^T for 32 points (one MFMA column tile), the 8 waves
+// of a workgroup sharing the weight matrix staged in LDS, and the 32 x 32
+// accumulator layout of one layer is the next layer's B
 // operand once the columns of W3 and W4 are permuted within 16-blocks
 // (launch_net_permute).  Writes the scaled far field like
 // launch_layer_out_field.

@@ -3,6 +3,7 @@
 // output layers, the backward pieces, Adam, and the far-energy summary.
 #include "mlp.h"
 
+#include <algorithm>
 #include <vector>
 
 namespace sa {
@@ -19,23 +20,29 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26:
-// erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2), t = 1 / (1 + p x),
-// |error| <= 1.5e-7 for x >= 0; odd extension for x < 0
-__device__ __forceinline__ float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-  const float poly =
-      fmaf(fmaf(fmaf(fmaf(1.061405429f, t, -1.453152027f), t, 1.421413741f), t, -0.284496736f), t, 0.254829592f) * t;
-  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * ax * ax);
-  return copysignf(fmaf(-poly, e, 1.0f), x);
+// GELU in the tanh form of Hendrycks & Gimpel, "Gaussian Error Linear Units"
+// (2016): gelu(z) ~ z (1 + tanh(c (z + k z^3))) / 2 with c = sqrt(2 / pi),
+// k = 0.044715.  Since (1 + tanh v) / 2 = 1 / (1 + exp(-2 v)), it takes one
+// exp2 and one reciprocal: z / (1 + 2^(z (a + b z^2))) with a = -2 c log2(e),
+// b = k a.  Its largest distance from the erf form is 4.7e-4 (near z = 2.7,
+// where the bfloat16 step of the stored activation is 1.6e-2); for z -> -inf
+// the exp2 overflows to +inf and the result is -0.
+constexpr float kGeluA = -2.302208198144325f;
+constexpr float kGeluB = -0.1029432395800235f;
+constexpr float kGeluC2 = 1.5957691216057308f;    // 2 c
+constexpr float kGeluC2K3 = 0.21406444881780076f; // 6 c k
+
+__device__ __forceinline__ float gelu_sig(float z) {
+  const float z2 = z * z;
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * fmaf(kGeluB, z2, kGeluA)));
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z) { return z * gelu_sig(z); }
 
+// derivative of the same function: s + z s (1 - s) 2 c (1 + 3 k z^2), s = 1 / (1 + exp(-2 v))
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
-         z * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
+  const float s = gelu_sig(z);
+  return fmaf(z * s * (1.0f - s), fmaf(kGeluC2K3, z * z, kGeluC2), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -43,19 +50,61 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // 32 x 32 x 16 product per wave: lane l supplies row (A) / column (B) l % 32
 // and the 8 consecutive k values 8 (l / 32) .. 8 (l / 32) + 7; the 16 FP32
 // results of lane l are column l % 32, rows 8 (r / 4) + 4 (l / 32) + r % 4.
-// A workgroup of 4 waves computes a 128 x 64 tile: wave w rows 32 w .. 32 w + 31,
-// two 32-column tiles; operands come straight from global memory (the B
-// operand, the weights, is shared by every workgroup and stays in cache).
+// A workgroup of 4 waves computes a 64 x 64 tile (wave w the 32 x 32 block
+// (w & 1, w >> 1)); per 64-wide k-slab both operand tiles are staged in LDS
+// as [row][k] with coalesced global reads whatever the operand's layout (a
+// row-contiguous operand is read along k, a column-contiguous one along its
+// rows and transposed on the way in), the next slab's loads in flight during
+// the current slab's products.  Split-K: workgroup z of gridDim.z sums the
+// k range [z kc, (z + 1) kc) into FP32 partials, added in z order by
+// k_gemm_reduce, which applies the epilogue.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ u16x8_t load8(const bf16_t *p, bool valid, int64_t base, int64_t kk, int64_t sk,
-                                         int64_t K, bool vec) {
-  u16x8_t r = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (!valid) return r;
-  if (vec && kk + 8 <= K) return *reinterpret_cast<const u16x8_t *>(p + base + kk);
+constexpr int kGT = 64;                 // tile rows / columns / k per slab
+constexpr int kGLd = kGT + 8;           // bfloat16 per LDS row (16 B padding)
+
+// 8 consecutive bfloat16 of one operand tile row along k (kcontig) or 8
+// consecutive rows at one k (!kcontig), zero outside [0, R) x [0, K); vec:
+// the 8 values are one aligned 16-byte word (unit stride along them)
+struct Chunk {
+  u16x8_t v;
+};
+
+__device__ __forceinline__ Chunk fetch_chunk(const bf16_t *__restrict__ p, int64_t sr, int64_t sk, int64_t R,
+                                             int64_t K, int64_t r0, int64_t k0, int c, bool kcontig, bool vec) {
+  Chunk ch;
+  ch.v = u16x8_t{0, 0, 0, 0, 0, 0, 0, 0};
+  if (kcontig) {
+    const int64_t r = r0 + (c >> 3), k = k0 + 8 * (c & 7);
+    if (r >= R) return ch;
+    if (vec && k + 8 <= K) {
+      ch.v = *reinterpret_cast<const u16x8_t *>(p + r * sr + k);
+      return ch;
+    }
 #pragma unroll
-  for (int e = 0; e < 8; ++e)
-    if (kk + e < K) r[e] = p[base + (kk + e) * sk];
-  return r;
+    for (int e = 0; e < 8; ++e)
+      if (k + e < K) ch.v[e] = p[r * sr + (k + e) * sk];
+  } else {
+    const int64_t k = k0 + (c >> 3), r = r0 + 8 * (c & 7);
+    if (k >= K) return ch;
+    if (vec && r + 8 <= R) {
+      ch.v = *reinterpret_cast<const u16x8_t *>(p + r + k * sk);
+      return ch;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (r + e < R) ch.v[e] = p[(r + e) * sr + k * sk];
+  }
+  return ch;
+}
+
+__device__ __forceinline__ void put_chunk(bf16_t *l, const Chunk &ch, int c, bool kcontig) {
+  if (kcontig) {
+    *reinterpret_cast<u16x8_t *>(l + (c >> 3) * kGLd + 8 * (c & 7)) = ch.v;
+  } else {
+    const int k = c >> 3, r = 8 * (c & 7);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) l[(r + e) * kGLd + k] = ch.v[e];
+  }
 }
 
 __device__ __forceinline__ void gemm_store(const GemmArgs &g, int64_t row, int64_t col, float v) {
@@ -67,31 +116,104 @@ __device__ __forceinline__ void gemm_store(const GemmArgs &g, int64_t row, int64
   if (g.outf) g.outf[row * g.ldf + col] = v;
 }
 
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int vec_a, int vec_b) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// ak / bk: A row-contiguous along k (a_sk == 1), B column-contiguous along k
+// (b_sk == 1); kc: k range per split (a multiple of 64)
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int ak, int bk, int va, int vb, int64_t kc) {
+  __shared__ __align__(16) bf16_t lA[kGT * kGLd];
+  __shared__ __align__(16) bf16_t lB[kGT * kGLd];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 31, hh = lane >> 5;
-  const int64_t m0 = (int64_t)blockIdx.y * 128 + 32 * w;
-  const int64_t n0 = (int64_t)blockIdx.x * 64;
-  if (m0 >= g.M) return;
-  const int64_t am = m0 + li, bn0 = n0 + li, bn1 = n0 + 32 + li;
-  const bool va = am < g.M, vb0 = bn0 < g.N, vb1 = bn1 < g.N;
-  const int64_t abase = am * g.a_sm, b0base = bn0 * g.b_sn, b1base = bn1 * g.b_sn;
-  f32x16_t acc0 = {}, acc1 = {};
-  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
-    const int64_t kk = k0 + 8 * hh;
-    const u16x8_t a = load8(g.A, va, abase, kk, g.a_sk, g.K, vec_a);
-    const u16x8_t b0 = load8(g.B, vb0, b0base, kk, g.b_sk, g.K, vec_b);
-    const u16x8_t b1 = load8(g.B, vb1, b1base, kk, g.b_sk, g.K, vec_b);
-    const bf16x8_t av = __builtin_bit_cast(bf16x8_t, a);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, b0), acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, b1), acc1, 0, 0, 0);
+  const int64_t m0 = (int64_t)blockIdx.y * kGT, n0 = (int64_t)blockIdx.x * kGT;
+  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t ke = kb + kc < g.K ? kb + kc : g.K;
+  // chunks of 8 values: 512 per operand tile, two per thread
+  Chunk a[2], b[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    a[u] = fetch_chunk(g.A, g.a_sm, g.a_sk, g.M, ke, m0, kb, tid + 256 * u, ak, va);
+    b[u] = fetch_chunk(g.B, g.b_sn, g.b_sk, g.N, ke, n0, kb, tid + 256 * u, bk, vb);
   }
+  f32x16_t acc = {};
+  const bf16_t *ra = lA + (32 * (w & 1) + li) * kGLd + 8 * hh;
+  const bf16_t *rb = lB + (32 * (w >> 1) + li) * kGLd + 8 * hh;
+  for (int64_t k0 = kb; k0 < ke; k0 += kGT) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      put_chunk(lA, a[u], tid + 256 * u, ak);
+      put_chunk(lB, b[u], tid + 256 * u, bk);
+    }
+    __syncthreads();
+    if (k0 + kGT < ke) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        a[u] = fetch_chunk(g.A, g.a_sm, g.a_sk, g.M, ke, m0, k0 + kGT, tid + 256 * u, ak, va);
+        b[u] = fetch_chunk(g.B, g.b_sn, g.b_sk, g.N, ke, n0, k0 + kGT, tid + 256 * u, bk, vb);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kGT / 16; ++s) {
+      const u16x8_t av = *reinterpret_cast<const u16x8_t *>(ra + 16 * s);
+      const u16x8_t bv = *reinterpret_cast<const u16x8_t *>(rb + 16 * s);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                    __builtin_bit_cast(bf16x8_t, bv), acc, 0, 0, 0);
+    }
+  }
+  const int64_t col = n0 + 32 * (w >> 1) + li;
+  float *part = gridDim.z > 1 ? g.ws + (int64_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int64_t row = m0 + 8 * (r >> 2) + 4 * hh + (r & 3);
-    gemm_store(g, row, bn0, acc0[r]);
-    gemm_store(g, row, bn1, acc1[r]);
+    const int64_t row = m0 + 32 * (w & 1) + 8 * (r >> 2) + 4 * hh + (r & 3);
+    if (part) {
+      if (row < g.M && col < g.N) part[row * g.N + col] = acc[r];
+    } else {
+      gemm_store(g, row, col, acc[r]);
+    }
   }
+}
+
+// sum of the split-K partials in split order, then the epilogue
+__global__ void k_gemm_reduce(GemmArgs g, int splits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.M * g.N) return;
+  float v = 0.f;
+  for (int z = 0; z < splits; ++z) v += g.ws[(int64_t)z * g.M * g.N + i];
+  gemm_store(g, i / g.N, i % g.N, v);
+}
+
+// ---------------------------------------------------------------------------
+// sums over the batch rows (bias and FP32-layer weight gradients):
+// out[i][j] = sum_b P[b][i] Q[b][j] (Q NULL: 1), the rows split into at most
+// kRedChunks chunks of R rows, each summed in row order into a partial, the
+// partials added in chunk order (k_part_sum): a fixed order for a given B
+// ---------------------------------------------------------------------------
+constexpr int kRedChunks = 64;
+
+__device__ __forceinline__ float ldf(const float *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ldf(const bf16_t *p, int64_t i) { return bf2f(p[i]); }
+
+template <typename TP, typename TQ>
+__global__ void k_atb_part(int64_t B, int64_t R, int I, int64_t ldp, const TP *__restrict__ P, int J, int64_t ldq,
+                           const TQ *__restrict__ Q, float *__restrict__ part) {
+  const int64_t ij = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ij >= (int64_t)I * J) return;
+  const int i = (int)(ij / J), j = (int)(ij % J);
+  const int64_t b0 = (int64_t)blockIdx.y * R, b1 = b0 + R < B ? b0 + R : B;
+  float s = 0.f;
+  if (Q) {
+    for (int64_t b = b0; b < b1; ++b) s = fmaf(ldf(P, b * ldp + i), ldf(Q, b * ldq + j), s);
+  } else {
+    for (int64_t b = b0; b < b1; ++b) s += ldf(P, b * ldp + i);
+  }
+  part[(int64_t)blockIdx.y * I * J + ij] = s;
+}
+
+__global__ void k_part_sum(int chunks, int64_t n, const float *__restrict__ part, float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + i];
+  out[i] = s;
 }
 
 __global__ void k_to_bf16(int64_t n, const float *__restrict__ x, bf16_t *__restrict__ y) {
@@ -242,56 +364,16 @@ __global__ void k_out_dz4(int64_t B, const float *__restrict__ dy, const float *
   dz4[i] = f2bf(dh * gelu_grad(z4[i]));
 }
 
-__global__ void k_out_dW5(int64_t B, const float *__restrict__ dy, const bf16_t *__restrict__ h4,
-                          float *__restrict__ dW5, float *__restrict__ db5) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kMlpOut * kMlpHid) {
-    const int o = i / kMlpHid, k = i % kMlpHid;
-    float s = 0.f;
-    for (int64_t b = 0; b < B; ++b) s = fmaf(dy[b * kMlpOut + o], bf2f(h4[b * kMlpHid + k]), s);
-    dW5[i] = s;
-  } else if (i < kMlpOut * kMlpHid + kMlpOut) {
-    const int o = i - kMlpOut * kMlpHid;
-    float s = 0.f;
-    for (int64_t b = 0; b < B; ++b) s += dy[b * kMlpOut + o];
-    db5[o] = s;
-  }
-}
-
 __global__ void k_gelu_backward(int64_t n, const float *__restrict__ dh, const float *__restrict__ z,
                                 bf16_t *__restrict__ dz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dz[i] = f2bf(dh[i] * gelu_grad(z[i]));
 }
 
-__global__ void k_colsum_bf16(int64_t B, int64_t N, const bf16_t *__restrict__ dz, float *__restrict__ db) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int64_t b = 0; b < B; ++b) s += bf2f(dz[b * N + n]);
-  db[n] = s;
-}
-
 __global__ void k_layer1_dz(int64_t n, const float *__restrict__ dh, const float *__restrict__ z,
                             float *__restrict__ dz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dz[i] = dh[i] * gelu_grad(z[i]);
-}
-
-__global__ void k_layer1_dW(int64_t B, const float *__restrict__ dz1, const float *__restrict__ X,
-                            float *__restrict__ dW1, float *__restrict__ db1) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kMlpHid * kMlpIn) {
-    const int f = i / kMlpIn, j = i % kMlpIn;
-    float s = 0.f;
-    for (int64_t b = 0; b < B; ++b) s = fmaf(dz1[b * kMlpHid + f], X[b * kMlpIn + j], s);
-    dW1[i] = s;
-  } else if (i < kMlpHid * kMlpIn + kMlpHid) {
-    const int f = i - kMlpHid * kMlpIn;
-    float s = 0.f;
-    for (int64_t b = 0; b < B; ++b) s += dz1[b * kMlpHid + f];
-    db1[f] = s;
-  }
 }
 
 __global__ void k_adam(int64_t n, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
@@ -342,7 +424,7 @@ __global__ void k_net_inputs(int64_t nq, const float *__restrict__ pf, const flo
 // ---------------------------------------------------------------------------
 // fused network: registers hold the activations, LDS holds one weight matrix
 // ---------------------------------------------------------------------------
-constexpr int kNW = 4;                  // waves per workgroup (one per SIMD: 444 registers per wave)
+constexpr int kNW = 8;                  // waves per workgroup (two per SIMD, at most 256 registers each)
 constexpr int kNRows = kNW * 32;        // rows per workgroup: 32 points per wave
 constexpr int kLdsLd = kMlpHid + 8;     // bfloat16 per LDS row of W (16 B padding)
 
@@ -368,67 +450,124 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t pack2(float lo, float hi) { return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16); }
 
-// two 32-row output tiles t, t + 1 of a hidden layer: W rows 32 t .. 32 t + 63
-// times the 32 points' activations B (16 k-slices of 8 bfloat16 as 4 packed
-// words); two independent accumulator chains keep the matrix pipe busy
-__device__ __forceinline__ void net_tiles(const bf16_t *lw, const u32x4_t (&B)[16], int t, int li, int hh,
-                                          f32x16_t &acc0, f32x16_t &acc1) {
-  acc0 = f32x16_t{};
-  acc1 = f32x16_t{};
-#pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const u16x8_t a0 = *reinterpret_cast<const u16x8_t *>(lw + (32 * t + li) * kLdsLd + 16 * s + 8 * hh);
-    const u16x8_t a1 = *reinterpret_cast<const u16x8_t *>(lw + (32 * t + 32 + li) * kLdsLd + 16 * s + 8 * hh);
-    const bf16x8_t b = __builtin_bit_cast(bf16x8_t, B[s]);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a0), b, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a1), b, acc1, 0, 0, 0);
-  }
+// materialise a packed activation word where it is made: keeps the compiler
+// from carrying its two FP32 factors to the next layer's first product
+__device__ __forceinline__ uint32_t pinned(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
 }
 
-// bias + GELU + bfloat16 of tile t into the next layer's B operand: element
-// 4 ((r/4) & 1) + r % 4 of slice 2 t + r / 8 holds feature 32 t + 8 (r/4) + 4 hh + r % 4
-// (the order the permuted W3, W4 columns expect)
-__device__ __forceinline__ void net_store(const f32x16_t &acc, const float *__restrict__ bias, int t, int hh,
-                                          u32x4_t (&Bn)[16]) {
-#pragma unroll
-  for (int r = 0; r < 16; r += 2) {
-    const int f = 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3);
-    Bn[2 * t + (r >> 3)][(4 * ((r >> 2) & 1) + (r & 3)) >> 1] =
-        pack2(gelu(acc[r] + bias[f]), gelu(acc[r + 1] + bias[f + 1]));
-  }
+// The 256 outputs of a layer are 8 tiles of 32 rows, taken in pairs: the
+// 32 products of pair t (W rows 32 t .. 32 t + 63 times the 32 points'
+// activations B, 16 k-slices of 8 bfloat16 as 4 packed words, two
+// independent accumulator chains), then the pair's epilogue (bias, GELU,
+// bfloat16).  Two waves share each SIMD, so one wave's products run beside
+// the other's epilogue.
+__device__ __forceinline__ void pair_products(const bf16_t *lw, const u32x4_t (&B)[16], int t, int s, int li, int hh,
+                                              f32x16_t &c0, f32x16_t &c1) {
+  const u16x8_t a0 = *reinterpret_cast<const u16x8_t *>(lw + (32 * t + li) * kLdsLd + 16 * s + 8 * hh);
+  const u16x8_t a1 = *reinterpret_cast<const u16x8_t *>(lw + (32 * t + 32 + li) * kLdsLd + 16 * s + 8 * hh);
+  const bf16x8_t b = __builtin_bit_cast(bf16x8_t, B[s]);
+  c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a0), b, c0, 0, 0, 0);
+  c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a1), b, c1, 0, 0, 0);
 }
 
-__device__ __forceinline__ void net_hidden(const bf16_t *lw, const u32x4_t (&B)[16], const float *__restrict__ bias,
-                                           int li, int hh, u32x4_t (&Bn)[16]) {
+// one k-slice's schedule: its two A-operand reads from LDS, then its two
+// products (the reads are issued just before their use, which bounds the
+// registers in flight)
+__device__ __forceinline__ void slice_schedule() {
+  __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // LDS reads
+  __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+}
+
+// elements r, r + 1 (r even) of tile t: bias + GELU + bfloat16 into the next
+// layer's B operand.  Element 4 ((r/4) & 1) + r % 4 of slice 2 t + r / 8
+// holds feature 32 t + 8 (r/4) + 4 hh + r % 4 (the order the permuted W3, W4
+// columns expect)
+__device__ __forceinline__ void epi2(const f32x16_t &acc, const float *__restrict__ bias, int t, int r, int hh,
+                                     u32x4_t (&Bn)[16]) {
+  const int f = 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3);
+  Bn[2 * t + (r >> 3)][(4 * ((r >> 2) & 1) + (r & 3)) >> 1] =
+      pinned(pack2(gelu(acc[r] + bias[f]), gelu(acc[r + 1] + bias[f + 1])));
+}
+
+// a hidden layer: per pair of output tiles the 32 products, then the
+// epilogue of both tiles (the other wave of the SIMD runs meanwhile)
+__device__ __forceinline__ void net_hidden(const bf16_t *lw, const u32x4_t (&B)[16], const float *bias, int li,
+                                           int hh, u32x4_t (&Bn)[16]) {
 #pragma unroll
   for (int t = 0; t < 8; t += 2) {
-    f32x16_t acc0, acc1;
-    net_tiles(lw, B, t, li, hh, acc0, acc1);
-    net_store(acc0, bias, t, hh, Bn);
-    net_store(acc1, bias, t + 1, hh, Bn);
+    f32x16_t c0 = {}, c1 = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      pair_products(lw, B, t, s, li, hh, c0, c1);
+      slice_schedule();
+    }
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) epi2(c0, bias, t, r, hh, Bn);
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) epi2(c1, bias, t + 1, r, hh, Bn);
+    __builtin_amdgcn_sched_barrier(0);   // one tile pair's values in flight at a time
   }
 }
 
-// last hidden layer: h4 = bf16(gelu(z4)) of tile t into the FP32 output layer
-__device__ __forceinline__ void net_out_acc(const f32x16_t &acc, const float *__restrict__ b4,
-                                            const float *__restrict__ W5, int t, int hh, float (&y)[4]) {
+// last hidden layer, elements r, r + 1 of tile t: h4 = bf16(gelu(z4)) into
+// the FP32 output layer (w5t [256][4] in LDS: W5 transposed)
+__device__ __forceinline__ void out2(const f32x16_t &acc, const float *__restrict__ b4, const float *w5t, int t,
+                                     int r, int hh, float (&y)[4]) {
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
+  for (int k = 0; k < 2; ++k) {
+    const int rr = r + k;
     const int f = 32 * t + 8 * (rr >> 2) + 4 * hh + (rr & 3);
     const float h = bf2f(f2bf(gelu(acc[rr] + b4[f])));
-#pragma unroll
-    for (int o = 0; o < 4; ++o) y[o] = fmaf(W5[o * kMlpHid + f], h, y[o]);
+    const float4 w = *reinterpret_cast<const float4 *>(w5t + 4 * f);
+    y[0] = fmaf(w.x, h, y[0]);
+    y[1] = fmaf(w.y, h, y[1]);
+    y[2] = fmaf(w.z, h, y[2]);
+    y[3] = fmaf(w.w, h, y[3]);
   }
 }
+
+__device__ __forceinline__ void net_last(const bf16_t *lw, const u32x4_t (&B)[16], const float *b4,
+                                         const float *w5t, int li, int hh, float (&y)[4]) {
+#pragma unroll 1
+  for (int t = 0; t < 8; t += 2) {
+    f32x16_t c0 = {}, c1 = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      pair_products(lw, B, t, s, li, hh, c0, c1);
+      slice_schedule();
+    }
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) out2(c0, b4, w5t, t, r, hh, y);
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) out2(c1, b4, w5t, t + 1, r, hh, y);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+constexpr size_t kNetLdsW = (size_t)kMlpHid * kLdsLd * sizeof(bf16_t);
+constexpr size_t kNetLdsW1 = (size_t)kMlpHid * kMlpPoint * sizeof(float);
+constexpr size_t kNetLdsW5 = (size_t)kMlpHid * kMlpOut * sizeof(float);
+constexpr size_t kNetLdsBias = (size_t)3 * kMlpHid * sizeof(float);
 
 __global__ __launch_bounds__(kNW * 64, 1) void k_net_fused(NetArgs a) {
   extern __shared__ __align__(16) unsigned char net_lds[];
   bf16_t *lw = reinterpret_cast<bf16_t *>(net_lds);
-  float *w1 = reinterpret_cast<float *>(net_lds + (size_t)kMlpHid * kLdsLd * sizeof(bf16_t));   // [256][6]
+  float *w1 = reinterpret_cast<float *>(net_lds + kNetLdsW);               // [256][6]
+  float *w5t = reinterpret_cast<float *>(net_lds + kNetLdsW + kNetLdsW1);  // [256][4]
+  float *lb = reinterpret_cast<float *>(net_lds + kNetLdsW + kNetLdsW1 + kNetLdsW5);  // b2, b3, b4
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 31, hh = lane >> 5;
   for (int i = threadIdx.x; i < kMlpHid * kMlpPoint; i += blockDim.x)
     w1[i] = a.W1[(i / kMlpPoint) * kMlpIn + i % kMlpPoint];
+  for (int i = threadIdx.x; i < kMlpHid * kMlpOut; i += blockDim.x)
+    w5t[i] = a.W5[(i % kMlpOut) * kMlpHid + i / kMlpOut];
+  for (int i = threadIdx.x; i < kMlpHid; i += blockDim.x) {
+    lb[i] = a.b2[i];
+    lb[kMlpHid + i] = a.b3[i];
+    lb[2 * kMlpHid + i] = a.b4[i];
+  }
   __syncthreads();
 
   // first layer (FP32): lane holds features 16 s + 8 hh + e of its point
@@ -453,23 +592,17 @@ __global__ __launch_bounds__(kNW * 64, 1) void k_net_fused(NetArgs a) {
 #pragma unroll
         for (int d = 0; d < kMlpPoint; ++d) v[k] = fmaf(w1[f * kMlpPoint + d], x[d], v[k]);
       }
-      B[sl][e >> 1] = pack2(gelu(v[0]), gelu(v[1]));
+      B[sl][e >> 1] = pinned(pack2(gelu(v[0]), gelu(v[1])));
+      if (e & 2) __builtin_amdgcn_sched_barrier(0);   // bound the registers in flight
     }
 
   stage_w(a.W2, lw);
-  net_hidden(lw, B, a.b2, li, hh, Bn);
+  net_hidden(lw, B, lb, li, hh, Bn);
   stage_w(a.W3p, lw);
-  net_hidden(lw, Bn, a.b3, li, hh, B);
+  net_hidden(lw, Bn, lb + kMlpHid, li, hh, B);
   stage_w(a.W4p, lw);
-  // last hidden layer: h4 = bf16(gelu(z4)) straight into the FP32 output layer
   float y[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-  for (int t = 0; t < 8; t += 2) {
-    f32x16_t acc0, acc1;
-    net_tiles(lw, B, t, li, hh, acc0, acc1);
-    net_out_acc(acc0, a.b4, a.W5, t, hh, y);
-    net_out_acc(acc1, a.b4, a.W5, t + 1, hh, y);
-  }
+  net_last(lw, B, lb + 2 * kMlpHid, w5t, li, hh, y);
 #pragma unroll
   for (int o = 0; o < 4; ++o) y[o] += __shfl_xor(y[o], 32, 64);   // the two lane halves hold one point
   if (hh == 0 && valid) {
@@ -487,10 +620,27 @@ inline unsigned nblk(int64_t n, int b = kT) { return (unsigned)((n + b - 1) / b)
 
 void launch_gemm_bf16(hipStream_t st, const GemmArgs &g) {
   if (g.M <= 0 || g.N <= 0) return;
-  const bool va = g.a_sk == 1 && g.a_sm % 8 == 0 && ((uintptr_t)g.A % 16) == 0;
-  const bool vb = g.b_sk == 1 && g.b_sn % 8 == 0 && ((uintptr_t)g.B % 16) == 0;
-  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 127) / 128));
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g, va ? 1 : 0, vb ? 1 : 0);
+  const bool ak = g.a_sk == 1, bk = g.b_sk == 1;
+  const bool va = ((uintptr_t)g.A % 16) == 0 && (ak ? g.a_sm % 8 == 0 : (g.a_sm == 1 && g.a_sk % 8 == 0));
+  const bool vb = ((uintptr_t)g.B % 16) == 0 && (bk ? g.b_sn % 8 == 0 : (g.b_sn == 1 && g.b_sk % 8 == 0));
+  const int64_t tm = (g.M + kGT - 1) / kGT, tn = (g.N + kGT - 1) / kGT;
+  // split the k range when the tiles alone cannot fill the chip
+  int64_t splits = 1;
+  if (g.ws && g.K > 4 * kGT && tm * tn < 256) {
+    splits = std::min<int64_t>((g.K + 4 * kGT - 1) / (4 * kGT), std::max<int64_t>(1, 256 / (tm * tn)));
+    splits = std::min<int64_t>(splits, g.ws_floats / (g.M * g.N));
+    splits = std::max<int64_t>(splits, 1);
+  }
+  int64_t kc = (g.K + splits - 1) / splits;
+  kc = std::max<int64_t>(kGT, (kc + kGT - 1) / kGT * kGT);
+  splits = std::max<int64_t>(1, (g.K + kc - 1) / kc);
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)tn, (unsigned)tm, (unsigned)splits), dim3(256), 0, st, g, ak ? 1 : 0,
+                     bk ? 1 : 0, va ? 1 : 0, vb ? 1 : 0, kc);
+  if (splits > 1) hipLaunchKernelGGL(k_gemm_reduce, dim3(nblk(g.M * g.N)), dim3(kT), 0, st, g, (int)splits);
+}
+
+int64_t trainer_ws_floats() {
+  return std::max<int64_t>((int64_t)kRedChunks * kMlpHid * kMlpIn, (int64_t)16 * kMlpHid * kMlpHid);
 }
 
 void launch_to_bf16(hipStream_t st, int64_t n, const float *x, bf16_t *y) {
@@ -530,28 +680,47 @@ void launch_layer_out_field(hipStream_t st, int64_t r0, int64_t rows, int64_t nq
 
 int loss_parts(int64_t B) { return (int)((B + kT - 1) / kT); }
 
+namespace {
+
+// out[i][j] = sum_b P[b][i] Q[b][j] (Q NULL: 1) through the chunk partials in ws
+template <typename TP, typename TQ>
+void atb(hipStream_t st, int64_t B, int I, int64_t ldp, const TP *P, int J, int64_t ldq, const TQ *Q, float *ws,
+         float *out) {
+  const int64_t R = std::max<int64_t>(1, (B + kRedChunks - 1) / kRedChunks);
+  const int chunks = B > 0 ? (int)((B + R - 1) / R) : 0;
+  const int64_t n = (int64_t)I * J;
+  if (chunks > 0)
+    hipLaunchKernelGGL((k_atb_part<TP, TQ>), dim3(nblk(n), (unsigned)chunks), dim3(kT), 0, st, B, R, I, ldp, P, J,
+                       ldq, Q, ws);
+  hipLaunchKernelGGL(k_part_sum, dim3(nblk(n)), dim3(kT), 0, st, chunks, n, ws, out);
+}
+
+}  // namespace
+
 void launch_out_backward(hipStream_t st, int64_t B, const float *y, const float *t, const bf16_t *h4,
                          const float *z4, const float *W5, float *dy, double *loss_part, bf16_t *dz4, float *dW5,
-                         float *db5) {
+                         float *db5, float *ws) {
   if (B <= 0) return;
   hipLaunchKernelGGL(k_out_dy, dim3(nblk(B)), dim3(kT), 0, st, B, y, t, dy, loss_part);
   hipLaunchKernelGGL(k_out_dz4, dim3(nblk(B * kMlpHid)), dim3(kT), 0, st, B, dy, z4, W5, dz4);
-  hipLaunchKernelGGL(k_out_dW5, dim3(nblk(kMlpOut * kMlpHid + kMlpOut)), dim3(kT), 0, st, B, dy, h4, dW5, db5);
+  atb(st, B, kMlpOut, kMlpOut, dy, kMlpHid, kMlpHid, h4, ws, dW5);
+  atb(st, B, kMlpOut, kMlpOut, dy, 1, 0, (const float *)nullptr, ws, db5);
 }
 
 void launch_gelu_backward(hipStream_t st, int64_t n, const float *dh, const float *z, bf16_t *dz) {
   if (n > 0) hipLaunchKernelGGL(k_gelu_backward, dim3(nblk(n)), dim3(kT), 0, st, n, dh, z, dz);
 }
 
-void launch_colsum_bf16(hipStream_t st, int64_t B, int64_t N, const bf16_t *dz, float *db) {
-  if (N > 0) hipLaunchKernelGGL(k_colsum_bf16, dim3(nblk(N)), dim3(kT), 0, st, B, N, dz, db);
+void launch_colsum_bf16(hipStream_t st, int64_t B, int64_t N, const bf16_t *dz, float *db, float *ws) {
+  if (N > 0) atb(st, B, (int)N, N, dz, 1, 0, (const float *)nullptr, ws, db);
 }
 
 void launch_layer1_backward(hipStream_t st, int64_t B, const float *dh1, const float *z1, const float *X,
-                            float *dz1, float *dW1, float *db1) {
+                            float *dz1, float *dW1, float *db1, float *ws) {
   if (B <= 0) return;
   hipLaunchKernelGGL(k_layer1_dz, dim3(nblk(B * kMlpHid)), dim3(kT), 0, st, B * kMlpHid, dh1, z1, dz1);
-  hipLaunchKernelGGL(k_layer1_dW, dim3(nblk(kMlpHid * kMlpIn + kMlpHid)), dim3(kT), 0, st, B, dz1, X, dW1, db1);
+  atb(st, B, kMlpHid, kMlpHid, dz1, kMlpIn, kMlpIn, X, ws, dW1);
+  atb(st, B, kMlpHid, kMlpHid, dz1, 1, 0, (const float *)nullptr, ws, db1);
 }
 
 double reduce_loss_host(hipStream_t st, const double *loss_part, int n) {
@@ -569,9 +738,7 @@ void launch_adam(hipStream_t st, int64_t n, float *w, const float *g, float *m, 
   if (n > 0) hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(kT), 0, st, n, w, g, m, v, lr, b1, b2, eps, c1, c2);
 }
 
-size_t net_fused_lds() {
-  return (size_t)kMlpHid * kLdsLd * sizeof(bf16_t) + (size_t)kMlpHid * kMlpPoint * sizeof(float);
-}
+size_t net_fused_lds() { return kNetLdsW + kNetLdsW1 + kNetLdsW5 + kNetLdsBias; }
 
 bool net_fused_prepare() {
   return hipFuncSetAttribute((const void *)k_net_fused, hipFuncAttributeMaxDynamicSharedMemorySize,

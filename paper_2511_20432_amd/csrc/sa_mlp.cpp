@@ -29,6 +29,7 @@ struct sa_mlp {
   float *y = nullptr, *dy = nullptr, *dh = nullptr, *dz1 = nullptr;
   bf16_t *dz = nullptr;
   double *loss_part = nullptr;
+  float *ws = nullptr;                                            // workspace of the products and batch sums
   ~sa_mlp() {
     if (stream) (void)hipStreamSynchronize(stream);
     for (void *p : owned) (void)hipFree(p);
@@ -97,6 +98,7 @@ void ensure_cap(sa_mlp *h, int64_t B) {
   h->dz1 = alloc<float>(h, c * H);
   h->dz = alloc<bf16_t>(h, c * H);
   h->loss_part = alloc<double>(h, sa::loss_parts(c));
+  if (!h->ws) h->ws = alloc<float>(h, sa::trainer_ws_floats());
   h->cap = c;
 }
 
@@ -130,7 +132,7 @@ void forward(sa_mlp *h, int64_t B, const float *X) {
 double backward(sa_mlp *h, int64_t B, const float *X, const float *T) {
   const int64_t H = sa::kMlpHid;
   sa::launch_out_backward(h->stream, B, h->y, T, h->hb[4], h->z[4], h->w + MlpLayout::W5, h->dy, h->loss_part,
-                          h->dz, h->g + MlpLayout::W5, h->g + MlpLayout::b5);
+                          h->dz, h->g + MlpLayout::W5, h->g + MlpLayout::b5, h->ws);
   for (int l = 4; l >= 2; --l) {
     // dW_l[n][k] = sum_b dz[b][n] h_{l-1}[b][k]
     sa::GemmArgs gw{};
@@ -145,8 +147,10 @@ double backward(sa_mlp *h, int64_t B, const float *X, const float *T) {
     gw.b_sn = 1;
     gw.outf = h->g + kOff[l - 2];
     gw.ldf = H;
+    gw.ws = h->ws;
+    gw.ws_floats = sa::trainer_ws_floats();
     sa::launch_gemm_bf16(h->stream, gw);
-    sa::launch_colsum_bf16(h->stream, B, H, h->dz, h->g + kBias[l - 2]);
+    sa::launch_colsum_bf16(h->stream, B, H, h->dz, h->g + kBias[l - 2], h->ws);
     // dh_{l-1}[b][k] = sum_n dz[b][n] W_l[n][k]
     sa::GemmArgs gd{};
     gd.M = B;
@@ -163,7 +167,8 @@ double backward(sa_mlp *h, int64_t B, const float *X, const float *T) {
     sa::launch_gemm_bf16(h->stream, gd);
     if (l > 2) sa::launch_gelu_backward(h->stream, B * H, h->dh, h->z[l - 1], h->dz);
   }
-  sa::launch_layer1_backward(h->stream, B, h->dh, h->z[1], X, h->dz1, h->g + MlpLayout::W1, h->g + MlpLayout::b1);
+  sa::launch_layer1_backward(h->stream, B, h->dh, h->z[1], X, h->dz1, h->g + MlpLayout::W1, h->g + MlpLayout::b1,
+                             h->ws);
   hck(hipGetLastError(), "kernel launch");
   return sa::reduce_loss_host(h->stream, h->loss_part, sa::loss_parts(B)) / (double)(B * sa::kMlpOut);
 }
