@@ -294,6 +294,29 @@ int sa_iga_heat_loss(sa_iga *h, int32_t path, int32_t face, int32_t edge_face, i
 int sa_iga_get_boundary_fields(sa_iga *h, int32_t path, double *T_gp, double *grad_gp,
                                double *F, double *du);
 
+/*
+ * Device-pointer variants of the two queries above, for zero-copy use of
+ * caller-owned device memory (e.g. torch tensors): every array argument is
+ * a DEVICE pointer with the layout of the host version, the work is
+ * enqueued on the object's stream (sa_iga_set_stream) after the steps
+ * already queued there, and the call returns without waiting; order the use
+ * of the outputs after that stream.
+ *
+ * sa_iga_eval_temperature_device: T = T~ + T^ (Eq. 21) and optionally its
+ * gradient at n parametric points xi [n][3] of path `path` at its current
+ * time; T [n], gradT [n][3] (may be NULL).  The basis functions are
+ * evaluated on the device, so a point outside [0,1]^3 cannot be refused: it
+ * gets NaN in T and gradT.  The call may allocate device memory (a
+ * workspace the object keeps and grows to the largest query).
+ * sa_iga_get_boundary_fields_device: the copies of
+ * sa_iga_get_boundary_fields (T_gp [n_bpts], grad_gp [3][n_bpts], F
+ * [n_dof], du [n_dof], any may be NULL), device to device.
+ */
+int sa_iga_eval_temperature_device(sa_iga *h, int32_t path, int64_t n, const double *xi, double *T,
+                                   double *gradT);
+int sa_iga_get_boundary_fields_device(sa_iga *h, int32_t path, double *T_gp, double *grad_gp, double *F,
+                                      double *du);
+
 /* Boundary quadrature tables (host arrays, any may be NULL): x [n_bpts][3],
  * outward unit normals n [n_bpts][3], weights w dS [n_bpts]. */
 int sa_iga_get_boundary_points(sa_iga *h, double *x, double *normal, double *wdS);

@@ -11,8 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libsa_iga.so")
 
-SOURCES = ["kernels.hip", "solver.hip", "mlp.hip", "noalloc.hip", "multipatch_kernels.hip", "sa_iga.cpp", "sa_mlp.cpp",
-           "host_setup.cpp", "multipatch.cpp"]
+SOURCES = ["kernels.hip", "solver.hip", "mlp.hip", "noalloc.hip", "multipatch_kernels.hip", "eval_device.hip",
+           "sa_iga.cpp", "sa_mlp.cpp", "host_setup.cpp", "multipatch.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -31,7 +31,8 @@ struct NoAllocLayout {
 // device address of the scratch area on `device` (the current device),
 // taken once per device; nullptr if it cannot be had
 void *noalloc_scratch(int device);
-// the sub-arrays of the area for n points and n_chunks chunks (host arithmetic only)
+// the sub-arrays of the area for n points and n_chunks chunks (host arithmetic
+// only; base NULL gives the bytes alone)
 NoAllocLayout noalloc_layout(void *base, int64_t n, int n_chunks);
 // centred coordinates (FP64, FP32), |x|^2 and roles of x [n][3] (device)
 void launch_noalloc_points(hipStream_t st, int64_t n, const double *x, const double center[3],

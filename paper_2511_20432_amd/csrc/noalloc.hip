@@ -58,10 +58,12 @@ void *noalloc_scratch(int device) {
 
 NoAllocLayout noalloc_layout(void *base, int64_t n, int n_chunks) {
   NoAllocLayout L{};
-  unsigned char *b = (unsigned char *)base;
+  // address arithmetic on integers: a null base gives the sizes alone
+  const uintptr_t b0 = (uintptr_t)base;
+  uintptr_t b = b0;
   const int64_t s = (n + 63) / 64 * 64;
   auto take = [&](size_t bytes) {
-    unsigned char *p = b;
+    void *p = (void *)b;
     b += (bytes + 255) / 256 * 256;
     return p;
   };
@@ -78,7 +80,7 @@ NoAllocLayout noalloc_layout(void *base, int64_t n, int n_chunks) {
   L.G = (double *)take(3 * s * sizeof(double));
   L.ld = (double *)take(s * sizeof(double));
   L.role = (int8_t *)take(s);
-  L.bytes = (size_t)(b - (unsigned char *)base);
+  L.bytes = (size_t)(b - b0);
   return L;
 }
 

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "eval_device.h"
 #include "kernels.h"
 #include "mlp.h"
 #include "noalloc.h"
@@ -247,6 +248,12 @@ struct sa_iga {
   int8_t *arole = nullptr;
   float *apf = nullptr;
   double *aT = nullptr, *aG = nullptr, *aLD = nullptr, *anet = nullptr;
+  // device-pointer queries: the patch geometry on the device (uploaded on
+  // first use) and a workspace that grows to the largest query
+  sa::GeoDev geo{};
+  bool geo_ready = false;
+  void *evw = nullptr;
+  size_t evw_bytes = 0;
   ~sa_iga();
 };
 
@@ -2316,22 +2323,13 @@ void source_field_host(sa_iga *h, int p, int64_t step, int64_t n, const double *
   hip_check(hipGetLastError(), "kernel launch");
 }
 
-// T~ and grad T~ of path p at time step*dt at n <= kNoAllocMaxPoints
-// physical points, device arrays in and out, with the fixed scratch area for
-// everything else: enqueued on the object's stream, no allocation, no wait.
-// The source history is cut into at most kNoAllocMaxChunks chunks (the
-// chunks of a call with more sources are longer than those of
-// source_field_host, so the sums agree to rounding, not bitwise).
-void source_field_noalloc(sa_iga *h, int p, int64_t step, int64_t n, const double *x, double *T, double *grad) {
-  if (n <= 0) return;
-  const hipStream_t st = h->stream;
-  sa::PathTab tab{};
-  tab.count = 1;
-  fill_slot(h, tab, 0, p, step);
+// Plan of the source-field sum for n query points in the slot of `tab`, its
+// chunks lengthened (far chunks kept multiples of the FP32 record block)
+// until there are at most max_chunks of them (0: no limit).
+sa::SumPlan query_plan(sa_iga *h, const sa::PathTab &tab, int64_t n, int max_chunks) {
   const int64_t n_act = tab.n_act[0], n_far = tab.n_far[0];
   sa::SumPlan pl = make_plan(h, n, 1, n_far, n_act - n_far);
-  while (pl.n_chunks_far + pl.n_chunks_near > sa::kNoAllocMaxChunks) {
-    // far chunks stay multiples of the FP32 record block
+  while (max_chunks > 0 && pl.n_chunks_far + pl.n_chunks_near > max_chunks) {
     if (pl.n_chunks_far >= pl.n_chunks_near) {
       pl.chunk_far *= 2;
       pl.n_chunks_far = (int)((n_far + pl.chunk_far - 1) / pl.chunk_far);
@@ -2340,9 +2338,18 @@ void source_field_noalloc(sa_iga *h, int p, int64_t step, int64_t n, const doubl
       pl.n_chunks_near = (int)((n_act - n_far + pl.chunk_near - 1) / pl.chunk_near);
     }
   }
+  return pl;
+}
+
+// T [n] and grad [3][n] (may be NULL) = T~ and grad T~ at the device points
+// x [n][3] for the slot of `tab` with plan pl, every intermediate in the
+// layout L; enqueued on the object's stream, no allocation, no wait
+void source_field_in(sa_iga *h, const sa::PathTab &tab, sa::SumPlan pl, int64_t n, const double *x, double *T,
+                     double *grad, const sa::NoAllocLayout &L) {
+  if (n <= 0) return;
+  const hipStream_t st = h->stream;
+  const int64_t n_act = tab.n_act[0];
   const int nch = pl.n_chunks_far + pl.n_chunks_near;
-  const sa::NoAllocLayout L = sa::noalloc_layout(h->scratch, n, std::max(nch, 1));
-  if (L.bytes > sa::kNoAllocScratchBytes) throw sa::SaError{SA_EINVAL, "internal: scratch layout too large"};
   pl.nq = n;
   pl.part_stride = L.stride;
   sa::launch_noalloc_points(st, n, x, h->m.P.center, L);
@@ -2356,6 +2363,55 @@ void source_field_noalloc(sa_iga *h, int p, int64_t step, int64_t n, const doubl
   sa::launch_finalize(st, tab, true, n, nch, L.stride, L.part, L.px, L.py, L.pz, L.px, L.py, L.pz, L.px, L.role,
                       h->m.mat.k, n, T, grad ? grad : L.G, L.ld, nullptr, 0);
   hip_check(hipGetLastError(), "kernel launch");
+}
+
+// T~ and grad T~ of path p at time step*dt at n <= kNoAllocMaxPoints
+// physical points, device arrays in and out, with the fixed scratch area for
+// everything else: enqueued on the object's stream, no allocation, no wait.
+// The source history is cut into at most kNoAllocMaxChunks chunks (the
+// chunks of a call with more sources are longer than those of
+// source_field_host, so the sums agree to rounding, not bitwise).
+void source_field_noalloc(sa_iga *h, int p, int64_t step, int64_t n, const double *x, double *T, double *grad) {
+  if (n <= 0) return;
+  sa::PathTab tab{};
+  tab.count = 1;
+  fill_slot(h, tab, 0, p, step);
+  const sa::SumPlan pl = query_plan(h, tab, n, sa::kNoAllocMaxChunks);
+  const int nch = pl.n_chunks_far + pl.n_chunks_near;
+  const sa::NoAllocLayout L = sa::noalloc_layout(h->scratch, n, std::max(nch, 1));
+  if (L.bytes > sa::kNoAllocScratchBytes) throw sa::SaError{SA_EINVAL, "internal: scratch layout too large"};
+  source_field_in(h, tab, pl, n, x, T, grad, L);
+}
+
+// the object's device-query workspace, at least `bytes` (grown after the
+// work queued on its streams has finished)
+void *query_workspace(sa_iga *h, size_t bytes) {
+  if (bytes <= h->evw_bytes) return h->evw;
+  sync_all(h);
+  if (h->evw) {
+    hip_check(hipFree(h->evw), "free");
+    h->owned.erase(std::find(h->owned.begin(), h->owned.end(), h->evw));
+    h->evw = nullptr;
+    h->evw_bytes = 0;
+  }
+  const size_t cap = std::max(bytes, 2 * h->evw_bytes);
+  h->evw = dev_alloc<unsigned char>(h->owned, cap);
+  h->evw_bytes = cap;
+  return h->evw;
+}
+
+// the patch geometry on the device, uploaded once
+const sa::GeoDev &geometry_on_device(sa_iga *h) {
+  if (h->geo_ready) return h->geo;
+  const sa::PatchData &P = h->m.P;
+  for (int d = 0; d < 3; ++d) {
+    h->geo.t[d] = dev_upload(h->owned, P.b[d].t, h->stream);
+    h->geo.p[d] = P.b[d].p;
+    h->geo.n[d] = P.b[d].n;
+  }
+  h->geo.ctrl = dev_upload(h->owned, P.ctrl, h->stream);
+  h->geo_ready = true;
+  return h->geo;
 }
 
 int path_index(sa_iga *h, int32_t path) {
@@ -2835,6 +2891,53 @@ int sa_iga_get_boundary_fields(sa_iga *h, int32_t path, double *T_gp, double *gr
     if (F) hip_check(hipMemcpyAsync(F, path_F(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
     if (du) hip_check(hipMemcpyAsync(du, path_v(h, p), nd * sizeof(double), hipMemcpyDeviceToHost, h->stream), "download");
     hip_check(hipStreamSynchronize(h->stream), "sync");
+    return SA_OK;
+  });
+}
+
+int sa_iga_eval_temperature_device(sa_iga *h, int32_t path, int64_t n, const double *xi, double *T,
+                                   double *gradT) {
+  return guarded([&]() -> int {
+    if (!h || (n > 0 && (!xi || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
+    const int p = path_index(h, path);
+    if (n == 0) return SA_OK;
+    const sa::GeoDev &g = geometry_on_device(h);
+    sa::PathTab tab{};
+    tab.count = 1;
+    fill_slot(h, tab, 0, p, h->paths[p].step);
+    const sa::SumPlan pl = query_plan(h, tab, n, 0);
+    const int nch = std::max(pl.n_chunks_far + pl.n_chunks_near, 1);
+    const size_t sum_bytes = sa::noalloc_layout(nullptr, n, nch).bytes;
+    // after the sum's area: x [n][3], Th [n], Gh [3][n], Tt [n], Gt [3][n]
+    const size_t vec = ((size_t)n * sizeof(double) + 255) / 256 * 256;
+    unsigned char *base = (unsigned char *)query_workspace(h, sum_bytes + 11 * vec);
+    const sa::NoAllocLayout L = sa::noalloc_layout(base, n, nch);
+    double *x = (double *)(base + sum_bytes), *Th = (double *)(base + sum_bytes + 3 * vec),
+           *Gh = (double *)(base + sum_bytes + 4 * vec), *Tt = (double *)(base + sum_bytes + 7 * vec),
+           *Gt = (double *)(base + sum_bytes + 8 * vec);
+    sa::launch_eval_hat(h->stream, n, xi, g, path_v(h, p), x, Th, Gh);
+    source_field_in(h, tab, pl, n, x, Tt, Gt, L);
+    sa::launch_eval_combine(h->stream, n, h->m.mat.T0, Th, Gh, Tt, Gt, T, gradT);
+    hip_check(hipGetLastError(), "kernel launch");
+    return SA_OK;
+  });
+}
+
+int sa_iga_get_boundary_fields_device(sa_iga *h, int32_t path, double *T_gp, double *grad_gp, double *F,
+                                      double *du) {
+  return guarded([&]() -> int {
+    if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    const int p = path_index(h, path);
+    const int64_t nq = h->nq, nd = h->nd;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    if (T_gp) hip_check(hipMemcpyAsync(T_gp, path_T(h, p), nq * sizeof(double), k, h->stream), "copy");
+    if (grad_gp)
+      for (int c = 0; c < 3; ++c)
+        hip_check(hipMemcpyAsync(grad_gp + c * nq, path_G(h, p) + c * h->stride, nq * sizeof(double), k, h->stream),
+                  "copy");
+    if (F) hip_check(hipMemcpyAsync(F, path_F(h, p), nd * sizeof(double), k, h->stream), "copy");
+    if (du) hip_check(hipMemcpyAsync(du, path_v(h, p), nd * sizeof(double), k, h->stream), "copy");
     return SA_OK;
   });
 }

@@ -89,6 +89,10 @@ EXPORTS = {
     "sa_iga_eval_source_field_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p,
                                                    C.c_void_p, C.c_void_p]),
     "sa_iga_eval_temperature_at": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, _dp, _dp, _dp, _dp]),
+    "sa_iga_eval_temperature_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p]),
+    "sa_iga_get_boundary_fields_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                    C.c_void_p]),
     "sa_iga_heat_loss": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp, _dp,
                                    _dp, _dp, _dp]),
     "sa_iga_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -381,6 +385,33 @@ class Model:
         check(self._lib.sa_iga_eval_temperature(self.h, path, n, _ptr(xi, C.c_double), _ptr(T, C.c_double),
                                                 _ptr(G, C.c_double)))
         return T, G
+
+    def eval_temperature_device(self, xi, path: int = 0, gradient: bool = True):
+        """sa_iga_eval_temperature_device on device tensors: xi [n, 3]
+        float64 (contiguous); returns T [n] and grad [n, 3] (None when
+        gradient is False) as new device tensors.  The work is enqueued on
+        the object's stream; synchronise before reading them."""
+        import torch
+        assert xi.is_cuda and xi.dtype == torch.float64 and xi.is_contiguous() and xi.dim() == 2
+        n = xi.shape[0]
+        T = torch.empty(n, dtype=torch.float64, device=xi.device)
+        G = torch.empty((n, 3), dtype=torch.float64, device=xi.device) if gradient else None
+        check(self._lib.sa_iga_eval_temperature_device(self.h, path, n, C.c_void_p(xi.data_ptr()),
+                                                       C.c_void_p(T.data_ptr()),
+                                                       C.c_void_p(G.data_ptr()) if gradient else None))
+        return T, G
+
+    def boundary_fields_device(self, path: int = 0):
+        """sa_iga_get_boundary_fields_device into new device tensors: T~ [nq],
+        grad T~ [3, nq], F [n_dof], du [n_dof], enqueued on the object's
+        stream; synchronise before reading them."""
+        import torch
+        nq, nd = self.info.n_bpts, self.info.n_dof
+        kw = {"dtype": torch.float64, "device": "cuda"}
+        T, G, F, u = torch.empty(nq, **kw), torch.empty((3, nq), **kw), torch.empty(nd, **kw), torch.empty(nd, **kw)
+        check(self._lib.sa_iga_get_boundary_fields_device(self.h, path, *(C.c_void_p(t.data_ptr())
+                                                                          for t in (T, G, F, u))))
+        return T, G, F, u
 
     def save(self) -> bytes:
         n = C.c_size_t(0)
