@@ -191,6 +191,21 @@ def _report(st, dt, steps):
     }
 
 
+def load_point_share(patch):
+    """Share of the boundary points whose T~ and grad T~ feed the step: the
+    Neumann faces (the load vector, Eq. 18) and the Dirichlet face (its
+    data).  The source-plane face's points are summed for the outputs (the
+    surface temperature), which the step itself does not use."""
+    from paper_2511_20432_amd import workloads as W
+    per_face = []
+    for f in range(6):
+        d = f // 2
+        m = [patch.n_elem(k) * patch.quad_face for k in range(3) if k != d]
+        per_face.append(m[0] * m[1])
+    used = sum(n for f, n in enumerate(per_face) if patch.face_role[f] != W.FACE_SOURCE_PLANE)
+    return used / sum(per_face)
+
+
 def _max_err(a, b):
     """Bound of max |T - T_ref| at the boundary points over all paths:
     |dT~| + max |du| (R_A >= 0 and sum_A R_A = 1 at every point)."""
@@ -649,6 +664,7 @@ def main():
                        "tau_near_s": 2e-4, "theta": 0.5, "audit_every": 50, "audit_frac": 0.01,
                        "audit_tol_K": 0.5, "preconditioner": "fast diagonalisation"},
             "steps_per_s": a["path_steps_per_s"],
+            "pairs_feeding_the_step_per_s": a["pairs_per_s"] * load_point_share(w5.patch),
             "speedup_vs_fp64": a["speedup_vs_fp64"], "max_err_K_vs_fp64": a["max_err_K_vs_fp64"],
             "roofline": roof,
             "headline": head,

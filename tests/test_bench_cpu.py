@@ -74,3 +74,11 @@ def test_several_gpus_are_refused():
                        text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_load_point_share_counts_the_faces_that_feed_the_step():
+    from paper_2511_20432_amd import workloads as W
+    # 64 x 32 x 16 elements, 3 x 3 points per face element: the top face
+    # (64 x 32 elements) holds 2 of the 7 parts of the boundary points
+    patch = W.block_patch((0, 0, 0), (4e-3, 2e-3, 1e-3), (64, 32, 16), 3)
+    assert bench.load_point_share(patch) == pytest.approx(5.0 / 7.0, rel=1e-15)
