@@ -477,9 +477,13 @@ void sa_mlp_destroy(sa_mlp *h);
  * On the device: the kernel sum pair by pair at every boundary point (FP64,
  * or FP32 for the sources older than tau_near), the load vector and the
  * projection right-hand side as CSR gathers, the Dirichlet projection and
- * the theta-step as CSR operators solved by Jacobi-preconditioned CG to
- * pcg_rtol (the theta-step on the free unknowns, the Dirichlet columns moved
- * to the right-hand side).  One scan path per object.
+ * the theta-step as CSR operators solved by preconditioned CG to pcg_rtol
+ * (the theta-step on the free unknowns, the Dirichlet columns moved to the
+ * right-hand side).  The preconditioner is additive Schwarz over the
+ * patches, z = sum_p S_p^T A_p^-1 S_p r with A_p^-1 the fast-diagonalisation
+ * solve of patch p's own operator (exact on an affine patch) and S_p the
+ * restriction to its control points, with SA_PRECOND_FD (the default; else
+ * where a patch has no such solve) or Jacobi.  One scan path per object.
  */
 typedef struct sa_multipatch sa_multipatch;   /* opaque; owns its device memory */
 
@@ -504,8 +508,8 @@ typedef struct {
  *     each patch's control points in the order A = a0 + n0 (a1 + n1 a2);
  *     the indices cover 0 .. n_dof - 1, every one used;
  *   scan: exactly one path; its options (scan->opt, NULL = defaults) take
- *     precision SA_PREC_FP64 or SA_PREC_FP32_FAR (the preconditioner
- *     setting is ignored: Jacobi).
+ *     precision SA_PREC_FP64 or SA_PREC_FP32_FAR; preconditioner
+ *     SA_PRECOND_FD (additive Schwarz) or SA_PRECOND_JACOBI.
  * All input arrays are copied.  Errors: SA_EINVAL (invalid patch, role,
  * index map, scan or options), SA_ENOMEM, SA_EDEVICE.
  */

@@ -49,6 +49,21 @@ T *mp_upload(std::vector<void *> &owned, const std::vector<T> &h, hipStream_t st
   return p;
 }
 
+// Additive Schwarz preconditioner z = sum_p S_p^T A_p^-1 S_p r over the
+// patches, A_p^-1 the fast-diagonalisation solve of patch p's own operator
+// (its 1-D factors; exact on an affine patch), S_p the restriction of the
+// system's unknowns to the patch's grid (zero where the patch's grid holds no
+// unknown of the system).
+struct Schwarz {
+  bool on = false;
+  std::vector<sa::FdOp> fd;        // per patch, device tables
+  std::vector<int64_t> off, len;   // per patch: its slice of the concatenated vectors
+  int64_t total = 0;
+  int64_t *gidx = nullptr;         // [total]: unknown of the system or -1
+  int64_t *rowptr = nullptr, *pos = nullptr;   // per unknown: its entries in the concatenated vectors
+  double *rp = nullptr, *zp = nullptr;         // [total]
+};
+
 struct MpCsr {
   int64_t nrow = 0;
   int64_t *rowptr = nullptr;
@@ -128,6 +143,8 @@ struct sa_multipatch {
   MpCsr load, dproj, mdir, Bop, AII, AID;
   int64_t *I_idx = nullptr, *D_idx = nullptr;
   double *aii_inv = nullptr, *mdir_inv = nullptr;
+  // additive Schwarz over the patches (SA_PRECOND_FD): one per system
+  Schwarz as_main, as_dir;
   // statistics
   int64_t pcg_its = 0, dir_its = 0;
   double last_relres = 0.0;
@@ -161,10 +178,26 @@ int mp_guarded(F &&f) {
   }
 }
 
-// conjugate gradients with the Jacobi preconditioner on A x = b (device
-// arrays of n values; x holds the first iterate), to |r| <= rtol |b|
-int cg_jacobi(sa_multipatch *h, const sa::CsrOp &A, const double *inv_diag, const double *b, double *x,
-              double *relres) {
+// z = M^-1 r and the partials of r . z (parts_for(n) of them): the additive
+// Schwarz solve when it is set up, else Jacobi
+void precondition(sa_multipatch *h, const Schwarz &as, const double *inv_diag, int64_t n, const double *r,
+                  double *z, double *part, const sa::PcgScalars *sc) {
+  const hipStream_t st = h->stream;
+  if (!as.on) {
+    sa::launch_jacobi(st, n, inv_diag, r, z, part, const_cast<sa::PcgScalars *>(sc));
+    return;
+  }
+  sa::launch_mp_as_gather(st, as.total, as.gidx, r, as.rp, sc);
+  for (size_t p = 0; p < as.fd.size(); ++p)
+    sa::launch_fd(st, as.fd[p], as.len[p], as.rp + as.off[p], as.zp + as.off[p], nullptr,
+                  const_cast<sa::PcgScalars *>(sc));
+  sa::launch_mp_as_combine(st, n, as.rowptr, as.pos, as.zp, r, z, part, sc);
+}
+
+// preconditioned conjugate gradients on A x = b (device arrays of n values;
+// x holds the first iterate), to |r| <= rtol |b|
+int cg_solve(sa_multipatch *h, const sa::CsrOp &A, const Schwarz &as, const double *inv_diag, const double *b,
+             double *x, double *relres) {
   const hipStream_t st = h->stream;
   const int64_t n = A.nrow;
   if (n <= 0) {
@@ -173,14 +206,14 @@ int cg_jacobi(sa_multipatch *h, const sa::CsrOp &A, const double *inv_diag, cons
   }
   const int np = sa::parts_for(n);
   sa::launch_csr_init(st, A, b, x, h->r, h->part_b);
-  sa::launch_jacobi(st, n, inv_diag, h->r, h->z, h->part_rz, nullptr);
+  precondition(h, as, inv_diag, n, h->r, h->z, h->part_rz, nullptr);
   sa::launch_pcg_start(st, n, np, h->part_b, np, h->part_rz, h->z, h->p, h->sc, h->opt.pcg_rtol);
-  int chunk = 8;
+  int chunk = as.on ? 4 : 8;
   for (;;) {
     for (int k = 0; k < chunk; ++k) {
       sa::launch_csr_apply_dot(st, A, h->p, h->q, h->part_pq, h->sc);
       sa::launch_pcg_update(st, n, np, h->part_pq, h->p, h->q, x, h->r, h->part_rr, h->sc);
-      sa::launch_jacobi(st, n, inv_diag, h->r, h->z, h->part_rz, h->sc);
+      precondition(h, as, inv_diag, n, h->r, h->z, h->part_rz, h->sc);
       sa::launch_pcg_direction(st, n, np, np, h->part_rr, h->part_rz, h->z, h->p, h->sc);
     }
     mp_check(hipMemcpyAsync(h->h_sc, h->sc, sizeof(sa::PcgScalars), hipMemcpyDeviceToHost, st), "status copy");
@@ -197,6 +230,64 @@ int cg_jacobi(sa_multipatch *h, const sa::CsrOp &A, const double *inv_diag, cons
     if (s.iter >= h->opt.pcg_max_iter) throw sa::SaError{SA_ENOCONV, "CG did not converge within pcg_max_iter"};
     chunk = std::min({chunk * 2, 64, std::max(1, h->opt.pcg_max_iter - s.iter)});
   }
+}
+
+// the device side of a Schwarz preconditioner: per patch its FD tables and
+// the map from its grid (`len` entries, entry k of patch p -> unknown
+// unk[p][k] of the system, or -1 outside the system or the patch's FD box)
+// to the n unknowns.  Left off (Jacobi) if an unknown lies in no patch's box.
+void setup_schwarz(sa_multipatch *h, Schwarz &as, const std::vector<const sa::FdData *> &fds,
+                   const std::vector<std::vector<int64_t>> &unk, int64_t n) {
+  as.on = false;
+  if (n <= 0 || fds.empty()) return;
+  const hipStream_t st = h->stream;
+  const size_t np = fds.size();
+  as.fd.resize(np);
+  as.off.resize(np);
+  as.len.resize(np);
+  as.total = 0;
+  for (size_t p = 0; p < np; ++p) {
+    as.off[p] = as.total;
+    as.len[p] = (int64_t)unk[p].size();
+    as.total += as.len[p];
+  }
+  std::vector<int64_t> gidx((size_t)as.total), count((size_t)n + 1, 0);
+  for (size_t p = 0; p < np; ++p)
+    for (int64_t k = 0; k < as.len[p]; ++k) {
+      const int64_t u = unk[p][k];
+      gidx[as.off[p] + k] = u;
+      if (u >= 0) count[u + 1]++;
+    }
+  std::vector<int64_t> rowptr((size_t)n + 1, 0), fill((size_t)n, 0);
+  for (int64_t i = 0; i < n; ++i) rowptr[i + 1] = rowptr[i] + count[i + 1];
+  std::vector<int64_t> pos((size_t)std::max<int64_t>(rowptr[n], 1));
+  for (size_t p = 0; p < np; ++p)   // patch order within each unknown's entries
+    for (int64_t k = 0; k < as.len[p]; ++k) {
+      const int64_t u = unk[p][k];
+      if (u >= 0) pos[rowptr[u] + fill[u]++] = as.off[p] + k;
+    }
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] == rowptr[i]) return;
+  as.gidx = mp_upload(h->owned, gidx, st);
+  as.rowptr = mp_upload(h->owned, rowptr, st);
+  as.pos = mp_upload(h->owned, pos, st);
+  as.rp = mp_alloc<double>(h->owned, (size_t)as.total);
+  as.zp = mp_alloc<double>(h->owned, (size_t)as.total);
+  for (size_t p = 0; p < np; ++p) {
+    const sa::FdData &D = *fds[p];
+    sa::FdOp &F = as.fd[p];
+    const int64_t nbox = (int64_t)D.m[0] * D.m[1] * D.m[2];
+    for (int d = 0; d < 3; ++d) {
+      F.n[d] = D.n[d];
+      F.lo[d] = D.lo[d];
+      F.m[d] = D.m[d];
+      F.U[d] = mp_upload(h->owned, D.U[d], st);
+    }
+    F.inv_diag = mp_upload(h->owned, D.inv_diag, st);
+    F.t1 = mp_alloc<double>(h->owned, (size_t)nbox);
+    F.t2 = mp_alloc<double>(h->owned, (size_t)nbox);
+  }
+  as.on = true;
 }
 
 void ensure_part(sa_multipatch *h, int64_t doubles) {
@@ -243,14 +334,14 @@ void mp_step_one(sa_multipatch *h) {
   if (h->nD > 0) {
     sa::launch_gather(st, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->LD, h->bD);
     mp_check(hipMemcpyAsync(h->vDn, h->vD, h->nD * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
-    h->dir_its += cg_jacobi(h, h->mdir.op(), h->mdir_inv, h->bD, h->vDn, &rel);
+    h->dir_its += cg_solve(h, h->mdir.op(), h->as_dir, h->mdir_inv, h->bD, h->vDn, &rel);
   }
   // theta-scheme (Eq. 20) on the free unknowns
   sa::launch_csr_eval(st, h->nd, h->Bop.rowptr, h->Bop.col, h->Bop.val, h->w, h->Bw);
   if (h->nD > 0) sa::launch_csr_eval(st, h->nI, h->AID.rowptr, h->AID.col, h->AID.val, h->vDn, h->AIDvD);
   sa::launch_mp_rhs(st, h->nI, h->I_idx, h->Bw, h->F1, h->F, h->opt.theta, h->nD > 0 ? h->AIDvD : nullptr, h->w, h->bI,
                     h->xI);
-  h->pcg_its += cg_jacobi(h, h->AII.op(), h->aii_inv, h->bI, h->xI, &rel);
+  h->pcg_its += cg_solve(h, h->AII.op(), h->as_main, h->aii_inv, h->bI, h->xI, &rel);
   h->last_relres = rel;
   // commit: u^{n+1}, F^{n+1}, the Dirichlet values
   sa::launch_mp_commit(st, h->nI, h->I_idx, h->xI, h->nD, h->D_idx, h->vDn, h->w);
@@ -427,6 +518,70 @@ void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const i
   for (int64_t j = 0; j < h->nD; ++j)
     for (int64_t e = Md.rowptr[j]; e < Md.rowptr[j + 1]; ++e)
       if (Md.col[e] == j) md_inv[j] = 1.0 / Md.val[e];
+  // additive Schwarz: each patch's FD solve of its own operator (A = M/dt +
+  // theta K on its box of free control points; the trace mass matrix on its
+  // Dirichlet face)
+  if (opt.preconditioner == SA_PRECOND_FD) {
+    bool fd_ok = true;
+    for (auto &m : pm) {
+      try {
+        sa::build_fd(m);
+      } catch (const sa::SaError &) {
+        fd_ok = false;
+      }
+    }
+    if (fd_ok) {
+      std::vector<const sa::FdData *> fds;
+      std::vector<std::vector<int64_t>> unk;
+      for (int32_t p = 0; p < n_patches; ++p) {
+        const sa::FdData &D = pm[p].fd_main;
+        const int *n3 = pm[p].P.n;
+        std::vector<int64_t> u((size_t)pm[p].P.ndof, -1);
+        for (int64_t A = 0; A < pm[p].P.ndof; ++A) {
+          const int i[3] = {(int)(A % n3[0]), (int)((A / n3[0]) % n3[1]), (int)(A / ((int64_t)n3[0] * n3[1]))};
+          bool inside = true;
+          for (int d = 0; d < 3; ++d) inside = inside && i[d] >= D.lo[d] && i[d] < D.lo[d] + D.m[d];
+          if (inside) u[A] = pos[h->gmap[p][A]];
+        }
+        fds.push_back(&D);
+        unk.push_back(std::move(u));
+      }
+      setup_schwarz(h, h->as_main, fds, unk, h->nI);
+      // the Dirichlet projection: patches with one Dirichlet face
+      fds.clear();
+      unk.clear();
+      bool dir_ok = h->nD > 0;
+      for (int32_t p = 0; p < n_patches && dir_ok; ++p) {
+        const sa::PatchData &P = pm[p].P;
+        int nf = 0, face = -1;
+        for (int f = 0; f < 6; ++f)
+          if (P.role[f] == SA_FACE_DIRICHLET) {
+            nf++;
+            face = f;
+          }
+        if (nf == 0) continue;
+        if (!pm[p].fd_dir_ok) {
+          dir_ok = false;
+          break;
+        }
+        const int d = face / 2, a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        const int layer = face % 2 == 0 ? 0 : P.n[d] - 1;
+        std::vector<int64_t> u((size_t)P.n[a] * P.n[b], -1);
+        for (int ib = 0; ib < P.n[b]; ++ib)
+          for (int ia = 0; ia < P.n[a]; ++ia) {
+            int i[3];
+            i[d] = layer;
+            i[a] = ia;
+            i[b] = ib;
+            const int64_t A = i[0] + (int64_t)P.n[0] * (i[1] + (int64_t)P.n[1] * i[2]);
+            u[ia + (size_t)P.n[a] * ib] = dpos[h->gmap[p][A]];
+          }
+        fds.push_back(&pm[p].fd_dir);
+        unk.push_back(std::move(u));
+      }
+      if (dir_ok) setup_schwarz(h, h->as_dir, fds, unk, h->nD);
+    }
+  }
   // device: operators and index lists
   h->Bop = upload_csr(h->owned, Bc, st);
   h->AII = upload_csr(h->owned, AII, st);

@@ -16,4 +16,18 @@ void launch_mp_rhs(hipStream_t st, int64_t nI, const int64_t *I, const double *B
 void launch_mp_commit(hipStream_t st, int64_t nI, const int64_t *I, const double *xI, int64_t nD, const int64_t *D,
                       const double *vD, double *w);
 
+struct PcgScalars;
+
+// additive Schwarz over the patches, the two ends (the local solves are
+// launch_fd on each patch's vector in between):
+//   gather:  rp[k] = r[gidx[k]] (gidx[k] >= 0), else 0, over the patches'
+//            concatenated vectors (n entries)
+//   combine: z[i] = sum of zp[pos[e]] over e in [rowptr[i], rowptr[i+1])
+//            (the patches holding unknown i, in patch order), and partials of
+//            r . z in parts_for(n) blocks
+void launch_mp_as_gather(hipStream_t st, int64_t n, const int64_t *gidx, const double *r, double *rp,
+                         const PcgScalars *sc);
+void launch_mp_as_combine(hipStream_t st, int64_t n, const int64_t *rowptr, const int64_t *pos, const double *zp,
+                          const double *r, double *z, double *part, const PcgScalars *sc);
+
 }  // namespace sa
