@@ -179,6 +179,17 @@ void launch_jacobi(hipStream_t st, int64_t n, const double *inv_diag, const doub
                    double *part, PcgScalars *sc);
 void launch_fd(hipStream_t st, const FdOp &F, int64_t n, const double *r, double *z, double *part,
                PcgScalars *sc);
+// several FD solves in the same launches: solve b reads the full vector
+// r + off[b] (its grid n[0] n[1] n[2]) and writes z + off[b]; z is zeroed
+// over its n_total entries first (outside the boxes it stays zero)
+constexpr int kFdBatchMax = 8;
+struct FdBatch {
+  int count;
+  FdOp f[kFdBatchMax];
+  int64_t off[kFdBatchMax];
+};
+void launch_fd_batch(hipStream_t st, const FdBatch &B, int64_t n_total, const double *r, double *z,
+                     const PcgScalars *sc);
 void launch_pcg_start(hipStream_t st, int64_t n, int n_part_b, const double *part_b, int n_part_rz,
                       const double *part_rz, const double *z, double *p, PcgScalars *sc, double rtol);
 void launch_stencil_apply_dot(hipStream_t st, const StencilOp &A, const double *p, double *q, double *part,

@@ -16,6 +16,7 @@
 //                says the solve has converged.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 
@@ -906,16 +907,14 @@ void launch_jacobi(hipStream_t st, int64_t n, const double *inv_diag, const doub
 // "compact" ones the m-box.  out[j along dim] = sum_k W[k, j] in[k along dim]
 // with W = U (transposed use: TR) ; optional scaling by inv_diag.
 template <bool IN_FULL, bool OUT_FULL, bool TR>
-__global__ void k_fd_mode(FdOp F, int dim, const double *__restrict__ in, double *__restrict__ out,
-                          const double *__restrict__ U, bool scale, const double *__restrict__ rdot,
-                          double *__restrict__ part, const PcgScalars *sc) {
-  if (sc && sc->done) return;
+__device__ __forceinline__ double fd_mode_body(const FdOp &F, int dim, const double *__restrict__ in,
+                                               double *__restrict__ out, const double *__restrict__ U, bool scale,
+                                               const double *__restrict__ rdot, int64_t t0, int64_t tstep) {
   const int m0 = F.m[0], m1 = F.m[1], m2 = F.m[2];
   const int64_t nbox = (int64_t)m0 * m1 * m2;
   const int md = F.m[dim];
   double acc = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nbox;
-       t += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t t = t0; t < nbox; t += tstep) {
     int j[3] = {(int)(t % m0), (int)((t / m0) % m1), (int)(t / ((int64_t)m0 * m1))};
     const int jd = j[dim];
     double s = 0.0;
@@ -939,16 +938,59 @@ __global__ void k_fd_mode(FdOp F, int dim, const double *__restrict__ in, double
     out[dst] = s;
     if (rdot) acc = fma(rdot[dst], s, acc);
   }
+  return acc;
+}
+
+template <bool IN_FULL, bool OUT_FULL, bool TR>
+__global__ void k_fd_mode(FdOp F, int dim, const double *__restrict__ in, double *__restrict__ out,
+                          const double *__restrict__ U, bool scale, const double *__restrict__ rdot,
+                          double *__restrict__ part, const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  const double acc = fd_mode_body<IN_FULL, OUT_FULL, TR>(F, dim, in, out, U, scale, rdot,
+                                                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                                                         (int64_t)gridDim.x * blockDim.x);
   if (part) {
     const double s = block_sum(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
   }
 }
 
+// the same mode product for every solve of a batch (blockIdx.y): stage 0
+// reads the full vector r + off[b] into t1, stages 1..4 run between t1 and
+// t2, stage 5 writes the full vector z + off[b]
+template <bool IN_FULL, bool OUT_FULL, bool TR>
+__global__ void k_fd_mode_batch(FdBatch B, int dim, int stage, const double *__restrict__ r, double *__restrict__ z,
+                                bool scale, const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  const FdOp &F = B.f[blockIdx.y];
+  const double *in = stage == 0 ? r + B.off[blockIdx.y] : ((stage & 1) ? F.t1 : F.t2);
+  double *out = stage == 5 ? z + B.off[blockIdx.y] : ((stage & 1) ? F.t2 : F.t1);
+  (void)fd_mode_body<IN_FULL, OUT_FULL, TR>(F, dim, in, out, F.U[dim], scale, nullptr,
+                                            (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                                            (int64_t)gridDim.x * blockDim.x);
+}
+
 __global__ void k_fill(int64_t n, double *__restrict__ z, double v, const PcgScalars *sc) {
   if (sc && sc->done) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     z[i] = v;
+}
+
+void launch_fd_batch(hipStream_t st, const FdBatch &B, int64_t n_total, const double *r, double *z,
+                     const PcgScalars *sc) {
+  if (B.count <= 0) return;
+  int64_t nbox = 1;
+  for (int b = 0; b < B.count; ++b) nbox = std::max<int64_t>(nbox, (int64_t)B.f[b].m[0] * B.f[b].m[1] * B.f[b].m[2]);
+  dim3 b(kBlock), g((unsigned)parts_for(nbox), (unsigned)B.count);
+  // z outside the boxes stays zero
+  hipLaunchKernelGGL(k_fill, dim3(parts_for(n_total)), b, 0, st, n_total, z, 0.0, sc);
+  // forward: t1 = U0^T r, t2 = U1^T t1, t1 = D^{-1} U2^T t2; backward: t2 = U2 t1, t1 = U1 t2, z = U0 t1
+  hipLaunchKernelGGL((k_fd_mode_batch<true, false, true>), g, b, 0, st, B, 0, 0, r, z, false, sc);
+  hipLaunchKernelGGL((k_fd_mode_batch<false, false, true>), g, b, 0, st, B, 1, 1, r, z, false, sc);
+  hipLaunchKernelGGL((k_fd_mode_batch<false, false, true>), g, b, 0, st, B, 2, 2, r, z, true, sc);
+  hipLaunchKernelGGL((k_fd_mode_batch<false, false, false>), g, b, 0, st, B, 2, 3, r, z, false, sc);
+  hipLaunchKernelGGL((k_fd_mode_batch<false, false, false>), g, b, 0, st, B, 1, 4, r, z, false, sc);
+  hipLaunchKernelGGL((k_fd_mode_batch<false, true, false>), g, b, 0, st, B, 0, 5, r, z, false, sc);
 }
 
 void launch_fd(hipStream_t st, const FdOp &F, int64_t n, const double *r, double *z, double *part,
@@ -1027,16 +1069,26 @@ void launch_stencil_apply_dot(hipStream_t st, const StencilOp &A, const double *
   hipLaunchKernelGGL(k_stencil_apply_dot, g, dim3(kBlock), 0, st, A, p, q, part, sc);
 }
 
+// q = A p and partials of p . q: 32 lanes per row, each lane every 32nd
+// entry of the row (coalesced reads along it), the lanes' sums added by a
+// fixed butterfly; lane 0 of the row's group carries the row into the dot
+constexpr int kCsrLanes = 32;
 __global__ void k_csr_apply_dot(CsrOp A, const double *__restrict__ p, double *__restrict__ q,
                                 double *__restrict__ part, const PcgScalars *sc) {
   if (sc->done) return;
+  const int sub = threadIdx.x & (kCsrLanes - 1);
+  const int64_t rows_per_pass = (int64_t)gridDim.x * (blockDim.x / kCsrLanes);
   double acc = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.nrow;
-       row += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t row = (int64_t)blockIdx.x * (blockDim.x / kCsrLanes) + threadIdx.x / kCsrLanes; row < A.nrow;
+       row += rows_per_pass) {
     double s = 0.0;
-    for (int64_t e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) s = fma(A.val[e], p[A.col[e]], s);
-    q[row] = s;
-    acc = fma(p[row], s, acc);
+    for (int64_t e = A.rowptr[row] + sub; e < A.rowptr[row + 1]; e += kCsrLanes) s = fma(A.val[e], p[A.col[e]], s);
+#pragma unroll
+    for (int off = kCsrLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kCsrLanes);
+    if (sub == 0) {
+      q[row] = s;
+      acc = fma(p[row], s, acc);
+    }
   }
   const double s = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.x] = s;

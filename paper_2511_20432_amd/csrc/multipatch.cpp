@@ -62,6 +62,8 @@ struct Schwarz {
   int64_t *gidx = nullptr;         // [total]: unknown of the system or -1
   int64_t *rowptr = nullptr, *pos = nullptr;   // per unknown: its entries in the concatenated vectors
   double *rp = nullptr, *zp = nullptr;         // [total]
+  sa::FdBatch batch{};             // all patches' solves in one launch per mode product (up to kFdBatchMax)
+  bool batched = false;
 };
 
 struct MpCsr {
@@ -188,9 +190,13 @@ void precondition(sa_multipatch *h, const Schwarz &as, const double *inv_diag, i
     return;
   }
   sa::launch_mp_as_gather(st, as.total, as.gidx, r, as.rp, sc);
-  for (size_t p = 0; p < as.fd.size(); ++p)
-    sa::launch_fd(st, as.fd[p], as.len[p], as.rp + as.off[p], as.zp + as.off[p], nullptr,
-                  const_cast<sa::PcgScalars *>(sc));
+  if (as.batched) {
+    sa::launch_fd_batch(st, as.batch, as.total, as.rp, as.zp, sc);
+  } else {
+    for (size_t p = 0; p < as.fd.size(); ++p)
+      sa::launch_fd(st, as.fd[p], as.len[p], as.rp + as.off[p], as.zp + as.off[p], nullptr,
+                    const_cast<sa::PcgScalars *>(sc));
+  }
   sa::launch_mp_as_combine(st, n, as.rowptr, as.pos, as.zp, r, z, part, sc);
 }
 
@@ -286,6 +292,14 @@ void setup_schwarz(sa_multipatch *h, Schwarz &as, const std::vector<const sa::Fd
     F.inv_diag = mp_upload(h->owned, D.inv_diag, st);
     F.t1 = mp_alloc<double>(h->owned, (size_t)nbox);
     F.t2 = mp_alloc<double>(h->owned, (size_t)nbox);
+  }
+  as.batched = np <= (size_t)sa::kFdBatchMax;
+  if (as.batched) {
+    as.batch.count = (int)np;
+    for (size_t p = 0; p < np; ++p) {
+      as.batch.f[p] = as.fd[p];
+      as.batch.off[p] = as.off[p];
+    }
   }
   as.on = true;
 }
