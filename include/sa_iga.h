@@ -540,6 +540,27 @@ int sa_mp_get_boundary_points(sa_multipatch *h, double *x, double *normal, doubl
 int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const double *xi, double *T,
                            double *grad);
 
+/* T and grad T (Eq. 21) at n PHYSICAL points x [n][3] (m) at the current
+ * step: each point is mapped back to the parametric domain of the first
+ * patch (in patch order) that holds it, by the inverse map of
+ * sa_iga_eval_temperature_at (nearest element centre, then Newton steps in
+ * [0,1]^3 to 1e-13 of the patch size), then evaluated as by
+ * sa_mp_eval_temperature.  A point on an interface goes to the lower patch
+ * index (T is continuous there; grad T is the one-sided value of that
+ * patch).  A point in no patch gets NaN in T and grad, -1 in patch.  Host
+ * arrays: T [n], grad [n][3], patch [n], xi [n][3] (the parametric points);
+ * grad, patch and xi may be NULL. */
+int sa_mp_eval_temperature_at(sa_multipatch *h, int64_t n, const double *x, double *T, double *grad,
+                              int32_t *patch, double *xi);
+
+/* The net heat-loss rate of sa_iga_heat_loss (Sec. 3.1, Tables 3-4) along
+ * an edge of patch `patch`: the edge where its parametric face `face` meets
+ * its face `edge_face`, at `quad` Gauss points per element, at the current
+ * step; T^ from the global control values.  Arguments, outputs and errors as
+ * for sa_iga_heat_loss (SA_ERANGE for a patch index out of range). */
+int sa_mp_heat_loss(sa_multipatch *h, int32_t patch, int32_t face, int32_t edge_face, int32_t quad, int64_t *n_pts,
+                    double *x, double *normal, double *ds, double *q_tilde, double *q_hat, double *integrals);
+
 /* Free the object and its device memory.  NULL is ignored. */
 void sa_mp_destroy(sa_multipatch *h);
 

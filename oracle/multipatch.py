@@ -107,8 +107,40 @@ class MultiPatchModel(Model):
         Tt, Gt = pointsource.field(x, sc.xyz, sc.tick, sc.energy, step, sc, self.mat, self.s)
         return Tt + uh, Gt + gx, x
 
-    def heat_loss(self, *args, **kwargs):
-        raise NotImplementedError("the heat-loss diagnostic is defined on one patch's edges")
+    def heat_loss(self, patch_index, face, edge_face, quad=4, u=None, step=None):
+        """Net heat-loss rate (Sec. 3.1) along an edge of patch `patch_index`:
+        at `quad` Gauss points per element of the edge where its face `face`
+        meets its face `edge_face`, q~ = -k grad T~ . n and q^ = -k grad T^ . n
+        with n the outward unit normal of `face`, T^ from the global control
+        values; the arc-length weights ds and the integrals of |q~ + q^| ds and
+        |q~| ds (the diagnostic of solver.Model.heat_loss on that patch)."""
+        P, g = self.patches[patch_index], self.maps[patch_index]
+        d, de = face // 2, edge_face // 2
+        if d == de:
+            raise ValueError("the faces must meet along an edge")
+        e = 3 - d - de
+        t, tw = iga.gauss_1d(P.knots[e], quad)
+        xi = np.zeros((len(t), 3))
+        xi[:, d] = float(face % 2)
+        xi[:, de] = float(edge_face % 2)
+        xi[:, e] = t
+        x, J, idx, R, dR = bspline.geometry(P, xi)
+        ds = np.linalg.norm(J[:, :, e], axis=1) * tw
+        a, b = [c for c in range(3) if c != d]
+        n = np.cross(J[:, :, a], J[:, :, b])
+        n /= np.linalg.norm(n, axis=1)[:, None]
+        n *= np.sign(np.einsum("qi,qi->q", n, J[:, :, d]) * (1.0 if face % 2 else -1.0))[:, None]
+        u = self.u if u is None else u
+        step = self.step if step is None else step
+        w = (u - self.mat.T0)[g]
+        Gh = np.einsum("qji,qj->qi", np.linalg.inv(J), np.einsum("qlj,ql->qj", dR, w[idx]))
+        sc = self.scan
+        _, Gt = pointsource.field(x, sc.xyz, sc.tick, sc.energy, step, sc, self.mat, self.s)
+        k = self.mat.k
+        qt = -k * np.einsum("qi,qi->q", Gt, n)
+        qh = -k * np.einsum("qi,qi->q", Gh, n)
+        return {"xi": xi, "x": x, "n": n, "ds": ds, "q_tilde": qt, "q_hat": qh,
+                "net": float(np.sum(np.abs(qt + qh) * ds)), "tilde": float(np.sum(np.abs(qt) * ds))}
 
     def locate(self, *args, **kwargs):
         raise NotImplementedError("locate on the patch that holds the point (solver.Model of that patch)")

@@ -886,4 +886,128 @@ SumPlan plan_sum(const sa_solver_options &o, int64_t nq, int count, int64_t max_
   return pl;
 }
 
+// Parametric point of the physical point x (inverse of the geometry map):
+// the element centre nearest to x, then Newton steps xi <- xi + J^{-1}
+// (x - x(xi)) kept in [0,1]^3, until |x - x(xi)| <= tol.  false if x is
+// not reached (it lies outside the patch).
+bool locate_point(const PatchData &P, const std::vector<double> &centres, const std::vector<double> &cxi,
+                  const double x[3], double tol, double xi[3]) {
+  int64_t best = -1;
+  double bd = INFINITY;
+  for (int64_t e = 0; e < (int64_t)centres.size() / 3; ++e) {
+    const double d0 = centres[3 * e] - x[0], d1 = centres[3 * e + 1] - x[1], d2 = centres[3 * e + 2] - x[2];
+    const double d = d0 * d0 + d1 * d1 + d2 * d2;
+    if (d < bd) {
+      bd = d;
+      best = e;
+    }
+  }
+  if (best < 0) return false;
+  for (int c = 0; c < 3; ++c) xi[c] = cxi[3 * best + c];
+  PointEval pe;
+  for (int it = 0; it < 60; ++it) {
+    int span[3];
+    for (int c = 0; c < 3; ++c) span[c] = P.b[c].find_span(xi[c]);
+    eval_point(P, xi, span, pe);
+    const double r[3] = {x[0] - pe.x[0], x[1] - pe.x[1], x[2] - pe.x[2]};
+    const double res = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (res <= tol) return true;
+    const double(&J)[3][3] = pe.J;
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(std::fabs(det) > 0.0)) return false;
+    // J^{-1} r by Cramer's rule
+    double d[3];
+    for (int c = 0; c < 3; ++c) {
+      double M[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i][j] = (j == c) ? r[i] : J[i][j];
+      d[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+              M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) /
+             det;
+    }
+    for (int c = 0; c < 3; ++c) xi[c] = std::min(1.0, std::max(0.0, xi[c] + d[c]));
+  }
+  return false;
+}
+
+// physical and parametric centres of the patch's elements ([n_el][3] each)
+void element_centres(const PatchData &P, std::vector<double> &centres, std::vector<double> &cxi) {
+  centres.clear();
+  cxi.clear();
+  PointEval pe;
+  for (int e2 = 0; e2 < P.b[2].n_el(); ++e2)
+    for (int e1 = 0; e1 < P.b[1].n_el(); ++e1)
+      for (int e0 = 0; e0 < P.b[0].n_el(); ++e0) {
+        const int es[3] = {e0, e1, e2};
+        double c[3];
+        int span[3];
+        for (int d = 0; d < 3; ++d) {
+          span[d] = P.b[d].span[es[d]];
+          c[d] = 0.5 * (P.b[d].t[span[d]] + P.b[d].t[span[d] + 1]);
+        }
+        eval_point(P, c, span, pe);
+        for (int d = 0; d < 3; ++d) {
+          cxi.push_back(c[d]);
+          centres.push_back(pe.x[d]);
+        }
+      }
+}
+
+// 1e-13 of the control net's extent about its centre
+double locate_tolerance(const PatchData &P) {
+  double ext = 0.0;
+  for (int64_t A = 0; A < P.ndof; ++A)
+    for (int c = 0; c < 3; ++c) ext = std::max(ext, std::fabs(P.ctrl[4 * A + c] - P.center[c]));
+  return 1e-13 * std::max(ext, 1e-300);
+}
+
+// Gauss points (quad per element) of the edge where parametric face `face`
+// meets face `edge_face` (faces of different directions), ordered by element:
+// their parametric points xi [n][3], the outward unit normals of `face`
+// [n][3] and the arc-length weights ds [n]; returns n
+int64_t edge_points(const PatchData &P, int face, int edge_face, int quad, std::vector<double> &xi,
+                    std::vector<double> &nrm, std::vector<double> &dsv) {
+  const int d = face / 2, de = edge_face / 2, e = 3 - d - de;
+  const int64_t n = (int64_t)P.b[e].n_el() * quad;
+  // Gauss points of the elements along the edge, ordered by element
+  std::vector<double> g, gw;
+  gauss_legendre(quad, g, gw);
+  std::vector<double> w((size_t)n);
+  xi.assign((size_t)3 * n, 0.0);
+  nrm.assign((size_t)3 * n, 0.0);
+  dsv.assign((size_t)n, 0.0);
+  const Basis1D &B = P.b[e];
+  for (int el = 0; el < B.n_el(); ++el) {
+    const double lo = B.t[B.span[el]], hi = B.t[B.span[el] + 1];
+    for (int k = 0; k < quad; ++k) {
+      const int64_t i = (int64_t)el * quad + k;
+      xi[3 * i + d] = (double)(face % 2);
+      xi[3 * i + de] = (double)(edge_face % 2);
+      xi[3 * i + e] = lo + 0.5 * (hi - lo) * (g[k] + 1.0);
+      w[i] = 0.5 * (hi - lo) * gw[k];
+    }
+  }
+  // arc length along the edge and the face's outward normal: the gradient
+  // of xi_d (row d of J^{-1}), signed by the side of the face
+  PointEval pe;
+  for (int64_t i = 0; i < n; ++i) {
+    int span[3];
+    for (int c = 0; c < 3; ++c) span[c] = P.b[c].find_span(xi[3 * i + c]);
+    eval_point(P, &xi[3 * i], span, pe);
+    const double(&J)[3][3] = pe.J;
+    dsv[i] = std::sqrt(J[0][e] * J[0][e] + J[1][e] * J[1][e] + J[2][e] * J[2][e]) * w[i];
+    // row d of J^{-1}: the cross product of the other two columns of J over det J
+    const int a = (d + 1) % 3, b = (d + 2) % 3;
+    double gd[3] = {J[1][a] * J[2][b] - J[2][a] * J[1][b], J[2][a] * J[0][b] - J[0][a] * J[2][b],
+                    J[0][a] * J[1][b] - J[1][a] * J[0][b]};
+    const double det = gd[0] * J[0][d] + gd[1] * J[1][d] + gd[2] * J[2][d];
+    const double len = std::sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
+    const double sg = ((face % 2) ? 1.0 : -1.0) * (det > 0 ? 1.0 : -1.0) / len;
+    for (int c = 0; c < 3; ++c) nrm[3 * i + c] = sg * gd[c];
+  }
+  return n;
+}
+
 }  // namespace sa

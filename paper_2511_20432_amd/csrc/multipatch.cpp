@@ -114,6 +114,7 @@ struct sa_multipatch {
   hipStream_t stream = nullptr;
   std::vector<void *> owned;
   std::vector<sa::PatchData> P;
+  std::vector<std::vector<double>> el_centre, el_xi;   // per patch, for the inverse map (built on first use)
   std::vector<std::vector<int64_t>> gmap;
   sa_material mat{};
   sa_solver_options opt{};
@@ -703,6 +704,123 @@ void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const i
   mp_check(hipStreamSynchronize(st), "sync");
 }
 
+// At n parametric points xi [n][3] of patch `patch` (SA_ERANGE outside
+// [0,1]^3): the physical points x [n][3], and on the device (buffers in
+// tmp, work on the object's stream) the basis rows with global columns
+// (R and the physical gradients) and the source field T~, grad T~ [3][stride]
+struct MpPoints {
+  int64_t stride = 0;
+  std::vector<double> x;
+  int64_t *rp = nullptr;
+  int32_t *cl = nullptr;
+  double *vals[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *dT = nullptr, *dG = nullptr;
+};
+
+MpPoints mp_points(sa_multipatch *h, int32_t patch, int64_t n, const double *xi, std::vector<void *> &tmp) {
+  MpPoints out;
+  const sa::PatchData &P = h->P[patch];
+  const auto &g = h->gmap[patch];
+  // host basis tables of the points (global column indices), physical points
+  std::vector<int64_t> rowptr(1, 0);
+  std::vector<int32_t> col;
+  std::vector<double> R, gx, gy, gz, xp(3 * n);
+  sa::PointEval pe;
+  for (int64_t i = 0; i < n; ++i) {
+    double u[3];
+    int span[3];
+    for (int d = 0; d < 3; ++d) {
+      u[d] = xi[3 * i + d];
+      if (!(u[d] >= 0.0 && u[d] <= 1.0)) throw sa::SaError{SA_ERANGE, "query point outside [0,1]^3"};
+      span[d] = P.b[d].find_span(u[d]);
+    }
+    sa::eval_point(P, u, span, pe);
+    const double(&J)[3][3] = pe.J;
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    const double id = 1.0 / det;
+    double Ji[3][3];
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    for (int l = 0; l < pe.L; ++l) {
+      col.push_back((int32_t)g[pe.idx[l]]);
+      R.push_back(pe.R[l]);
+      double gg[3];
+      for (int c = 0; c < 3; ++c) gg[c] = pe.dR[l][0] * Ji[0][c] + pe.dR[l][1] * Ji[1][c] + pe.dR[l][2] * Ji[2][c];
+      gx.push_back(gg[0]);
+      gy.push_back(gg[1]);
+      gz.push_back(gg[2]);
+    }
+    rowptr.push_back((int64_t)col.size());
+    for (int c = 0; c < 3; ++c) xp[3 * i + c] = pe.x[c] - h->center[c];
+  }
+  const hipStream_t st = h->stream;
+  // the basis rows on the device
+  out.rp = mp_upload(tmp, rowptr, st);
+  out.cl = mp_upload(tmp, col, st);
+  out.vals[0] = mp_upload(tmp, R, st);
+  out.vals[1] = mp_upload(tmp, gx, st);
+  out.vals[2] = mp_upload(tmp, gy, st);
+  out.vals[3] = mp_upload(tmp, gz, st);
+  // T~ and its gradient at the mapped points (the sources of the current step)
+  const int64_t stride = (n + 63) / 64 * 64;
+  std::vector<double> qx(n), qy(n), qz(n), q2(n);
+  std::vector<float> fx(n), fy(n), fz(n), fq(n);
+  for (int64_t i = 0; i < n; ++i) {
+    qx[i] = xp[3 * i];
+    qy[i] = xp[3 * i + 1];
+    qz[i] = xp[3 * i + 2];
+    q2[i] = qx[i] * qx[i] + qy[i] * qy[i] + qz[i] * qz[i];
+    fx[i] = (float)qx[i];
+    fy[i] = (float)qy[i];
+    fz[i] = (float)qz[i];
+    fq[i] = (float)q2[i];
+  }
+  double *dx = mp_upload(tmp, qx, st), *dy = mp_upload(tmp, qy, st), *dz = mp_upload(tmp, qz, st),
+         *dq = mp_upload(tmp, q2, st);
+  float *ex = mp_upload(tmp, fx, st), *ey = mp_upload(tmp, fy, st), *ez = mp_upload(tmp, fz, st),
+        *eq = mp_upload(tmp, fq, st);
+  std::vector<int8_t> rl(n, (int8_t)SA_FACE_SOURCE_PLANE);   // no load density at query points
+  int8_t *drl = mp_upload(tmp, rl, st);
+  double *dT = mp_alloc<double>(tmp, stride), *dG = mp_alloc<double>(tmp, 3 * stride),
+         *dLD = mp_alloc<double>(tmp, stride);
+  out.dT = dT;
+  out.dG = dG;
+  out.stride = stride;
+  sa::PathTab tab{};
+  tab.count = 1;
+  tab.now[0] = h->step * h->ns;
+  tab.n_act[0] = (int32_t)(std::upper_bound(h->tick.begin(), h->tick.end(), tab.now[0]) - h->tick.begin());
+  tab.n_far[0] = 0;
+  const int64_t a = tab.n_act[0];
+  if (a > 0) sa::launch_coeff(st, tab, a, h->stick, h->sx, h->sy, h->sz, h->sE, h->cp, h->c64, h->c32);
+  sa::SumPlan pl = sa::plan_sum(h->opt, n, 1, 0, a);
+  pl.part_stride = stride;
+  const int nch = pl.n_chunks_far + pl.n_chunks_near;
+  double *part = mp_alloc<double>(tmp, (size_t)std::max(nch, 1) * 5 * stride);
+  if (nch > 0) sa::launch_sum(st, pl, tab, dx, dy, dz, dq, ex, ey, ez, eq, h->c64, h->c32, part);
+  sa::launch_finalize(st, tab, true, n, nch, stride, part, dx, dy, dz, dx, dy, dz, dq, drl, h->mat.k, stride, dT, dG,
+                      dLD, nullptr, 0);  out.x.resize((size_t)3 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) out.x[3 * i + c] = xp[3 * i + c] + h->center[c];
+  return out;
+}
+
+struct TmpFree {
+  std::vector<void *> v;
+  ~TmpFree() {
+    for (void *p : v) (void)hipFree(p);
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -784,6 +902,62 @@ int sa_mp_get_boundary_fields(sa_multipatch *h, double *T_gp, double *grad_gp, d
   });
 }
 
+int sa_mp_eval_temperature_at(sa_multipatch *h, int64_t n, const double *x, double *T, double *grad,
+                              int32_t *patch, double *xi_out) {
+  return mp_guarded([&]() -> int {
+    if (!h || (n > 0 && (!x || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
+    if (n == 0) return SA_OK;
+    const int np = (int)h->P.size();
+    if (h->el_centre.empty()) {
+      h->el_centre.resize(np);
+      h->el_xi.resize(np);
+      for (int p = 0; p < np; ++p) sa::element_centres(h->P[p], h->el_centre[p], h->el_xi[p]);
+    }
+    // the first patch (in order) whose inverse map reaches the point
+    std::vector<int32_t> owner((size_t)n, -1);
+    std::vector<double> xi((size_t)3 * n, NAN);
+    for (int p = 0; p < np; ++p) {
+      const double tol = sa::locate_tolerance(h->P[p]);
+      for (int64_t i = 0; i < n; ++i) {
+        if (owner[i] >= 0) continue;
+        double q[3];
+        if (sa::locate_point(h->P[p], h->el_centre[p], h->el_xi[p], x + 3 * i, tol, q)) {
+          owner[i] = p;
+          for (int c = 0; c < 3; ++c) xi[3 * i + c] = q[c];
+        }
+      }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      T[i] = NAN;
+      if (grad)
+        for (int c = 0; c < 3; ++c) grad[3 * i + c] = NAN;
+    }
+    for (int p = 0; p < np; ++p) {
+      std::vector<int64_t> idx;
+      std::vector<double> q;
+      for (int64_t i = 0; i < n; ++i)
+        if (owner[i] == p) {
+          idx.push_back(i);
+          for (int c = 0; c < 3; ++c) q.push_back(xi[3 * i + c]);
+        }
+      if (idx.empty()) continue;
+      const int64_t m = (int64_t)idx.size();
+      std::vector<double> Tp((size_t)m), Gp((size_t)3 * m);
+      const int rc = sa_mp_eval_temperature(h, p, m, q.data(), Tp.data(), Gp.data());
+      if (rc != SA_OK) throw sa::SaError{rc, sa_iga_last_error()};
+      for (int64_t k = 0; k < m; ++k) {
+        T[idx[k]] = Tp[k];
+        if (grad)
+          for (int c = 0; c < 3; ++c) grad[3 * idx[k] + c] = Gp[3 * k + c];
+      }
+    }
+    if (patch) std::copy(owner.begin(), owner.end(), patch);
+    if (xi_out) std::copy(xi.begin(), xi.end(), xi_out);
+    return SA_OK;
+  });
+}
+
 int sa_mp_get_boundary_points(sa_multipatch *h, double *x, double *normal, double *wdS) {
   return mp_guarded([&]() -> int {
     if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
@@ -800,99 +974,14 @@ int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const dou
     if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
     if (patch < 0 || patch >= (int32_t)h->P.size()) throw sa::SaError{SA_ERANGE, "patch index out of range"};
     if (n == 0) return SA_OK;
-    const sa::PatchData &P = h->P[patch];
-    const auto &g = h->gmap[patch];
-    // host basis tables of the points (global column indices), physical points
-    std::vector<int64_t> rowptr(1, 0);
-    std::vector<int32_t> col;
-    std::vector<double> R, gx, gy, gz, xp(3 * n);
-    sa::PointEval pe;
-    for (int64_t i = 0; i < n; ++i) {
-      double u[3];
-      int span[3];
-      for (int d = 0; d < 3; ++d) {
-        u[d] = xi[3 * i + d];
-        if (!(u[d] >= 0.0 && u[d] <= 1.0)) throw sa::SaError{SA_ERANGE, "query point outside [0,1]^3"};
-        span[d] = P.b[d].find_span(u[d]);
-      }
-      sa::eval_point(P, u, span, pe);
-      const double(&J)[3][3] = pe.J;
-      const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-      const double id = 1.0 / det;
-      double Ji[3][3];
-      Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
-      Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-      Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-      Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
-      Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-      Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-      Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
-      Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-      Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-      for (int l = 0; l < pe.L; ++l) {
-        col.push_back((int32_t)g[pe.idx[l]]);
-        R.push_back(pe.R[l]);
-        double gg[3];
-        for (int c = 0; c < 3; ++c) gg[c] = pe.dR[l][0] * Ji[0][c] + pe.dR[l][1] * Ji[1][c] + pe.dR[l][2] * Ji[2][c];
-        gx.push_back(gg[0]);
-        gy.push_back(gg[1]);
-        gz.push_back(gg[2]);
-      }
-      rowptr.push_back((int64_t)col.size());
-      for (int c = 0; c < 3; ++c) xp[3 * i + c] = pe.x[c] - h->center[c];
-    }
     const hipStream_t st = h->stream;
-    std::vector<void *> tmp;
-    struct Free {
-      std::vector<void *> &v;
-      ~Free() {
-        for (void *p : v) (void)hipFree(p);
-      }
-    } fr{tmp};
+    TmpFree tf;
+    const MpPoints pts = mp_points(h, patch, n, xi, tf.v);
     // T^ and its gradient: the contractions with the control values
-    int64_t *rp = mp_upload(tmp, rowptr, st);
-    int32_t *cl = mp_upload(tmp, col, st);
-    double *vals[4] = {mp_upload(tmp, R, st), mp_upload(tmp, gx, st), mp_upload(tmp, gy, st), mp_upload(tmp, gz, st)};
-    double *hat = mp_alloc<double>(tmp, 4 * n);
-    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(st, n, rp, cl, vals[k], h->w, hat + k * n);
-    // T~ and its gradient at the mapped points (the sources of the current step)
-    const int64_t stride = (n + 63) / 64 * 64;
-    std::vector<double> qx(n), qy(n), qz(n), q2(n);
-    std::vector<float> fx(n), fy(n), fz(n), fq(n);
-    for (int64_t i = 0; i < n; ++i) {
-      qx[i] = xp[3 * i];
-      qy[i] = xp[3 * i + 1];
-      qz[i] = xp[3 * i + 2];
-      q2[i] = qx[i] * qx[i] + qy[i] * qy[i] + qz[i] * qz[i];
-      fx[i] = (float)qx[i];
-      fy[i] = (float)qy[i];
-      fz[i] = (float)qz[i];
-      fq[i] = (float)q2[i];
-    }
-    double *dx = mp_upload(tmp, qx, st), *dy = mp_upload(tmp, qy, st), *dz = mp_upload(tmp, qz, st),
-           *dq = mp_upload(tmp, q2, st);
-    float *ex = mp_upload(tmp, fx, st), *ey = mp_upload(tmp, fy, st), *ez = mp_upload(tmp, fz, st),
-          *eq = mp_upload(tmp, fq, st);
-    std::vector<int8_t> rl(n, (int8_t)SA_FACE_SOURCE_PLANE);   // no load density at query points
-    int8_t *drl = mp_upload(tmp, rl, st);
-    double *dT = mp_alloc<double>(tmp, stride), *dG = mp_alloc<double>(tmp, 3 * stride),
-           *dLD = mp_alloc<double>(tmp, stride);
-    sa::PathTab tab{};
-    tab.count = 1;
-    tab.now[0] = h->step * h->ns;
-    tab.n_act[0] = (int32_t)(std::upper_bound(h->tick.begin(), h->tick.end(), tab.now[0]) - h->tick.begin());
-    tab.n_far[0] = 0;
-    const int64_t a = tab.n_act[0];
-    if (a > 0) sa::launch_coeff(st, tab, a, h->stick, h->sx, h->sy, h->sz, h->sE, h->cp, h->c64, h->c32);
-    sa::SumPlan pl = sa::plan_sum(h->opt, n, 1, 0, a);
-    pl.part_stride = stride;
-    const int nch = pl.n_chunks_far + pl.n_chunks_near;
-    double *part = mp_alloc<double>(tmp, (size_t)std::max(nch, 1) * 5 * stride);
-    if (nch > 0) sa::launch_sum(st, pl, tab, dx, dy, dz, dq, ex, ey, ez, eq, h->c64, h->c32, part);
-    sa::launch_finalize(st, tab, true, n, nch, stride, part, dx, dy, dz, dx, dy, dz, dq, drl, h->mat.k, stride, dT, dG,
-                        dLD, nullptr, 0);
+    double *hat = mp_alloc<double>(tf.v, 4 * n);
+    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(st, n, pts.rp, pts.cl, pts.vals[k], h->w, hat + k * n);
+    const double *dT = pts.dT, *dG = pts.dG;
+    const int64_t stride = pts.stride;
     std::vector<double> hv(4 * n), tt(n), tg(3 * n);
     mp_check(hipMemcpyAsync(hv.data(), hat, 4 * n * sizeof(double), hipMemcpyDeviceToHost, st), "download");
     mp_check(hipMemcpyAsync(tt.data(), dT, n * sizeof(double), hipMemcpyDeviceToHost, st), "download");
@@ -906,6 +995,53 @@ int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const dou
       if (grad)
         for (int c = 0; c < 3; ++c) grad[3 * i + c] = hv[(c + 1) * n + i] + tg[c * n + i];
     }
+    return SA_OK;
+  });
+}
+
+int sa_mp_heat_loss(sa_multipatch *h, int32_t patch, int32_t face, int32_t edge_face, int32_t quad, int64_t *n_pts,
+                    double *x, double *normal, double *ds, double *q_tilde, double *q_hat, double *integrals) {
+  return mp_guarded([&]() -> int {
+    if (!h || !n_pts) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    if (patch < 0 || patch >= (int32_t)h->P.size()) throw sa::SaError{SA_ERANGE, "patch index out of range"};
+    if (face < 0 || face > 5 || edge_face < 0 || edge_face > 5 || face / 2 == edge_face / 2)
+      throw sa::SaError{SA_EINVAL, "face and edge_face must be parametric faces 0..5 that meet along an edge"};
+    if (quad < 1 || quad > 16) throw sa::SaError{SA_EINVAL, "quad must be 1..16"};
+    const sa::PatchData &P = h->P[patch];
+    const int e = 3 - face / 2 - edge_face / 2;
+    const int64_t n = (int64_t)P.b[e].n_el() * quad;
+    const bool per_point = x || normal || ds || q_tilde || q_hat;
+    if (!per_point && !integrals) {
+      *n_pts = n;
+      return SA_OK;
+    }
+    if (per_point && *n_pts < n) {
+      *n_pts = n;
+      throw sa::SaError{SA_EINVAL, "point arrays shorter than the number of edge points (returned in *n_pts)"};
+    }
+    std::vector<double> xi, nrm, dsv;
+    sa::edge_points(P, face, edge_face, quad, xi, nrm, dsv);
+    const hipStream_t st = h->stream;
+    TmpFree tf;
+    const MpPoints pts = mp_points(h, patch, n, xi.data(), tf.v);
+    double *dn = mp_upload(tf.v, nrm, st), *dds = mp_upload(tf.v, dsv, st);
+    double *out = mp_alloc<double>(tf.v, (size_t)4 * n + 2);
+    sa::launch_heat_loss(st, n, pts.rp, pts.cl, pts.vals[1], pts.vals[2], pts.vals[3], h->w, pts.dG, pts.stride, dn,
+                         dds, h->mat.k, out, out + n, out + 2 * n, out + 3 * n, out + 4 * n);
+    mp_check(hipGetLastError(), "kernel launch");
+    std::vector<double> hv((size_t)4 * n + 2);
+    mp_check(hipMemcpyAsync(hv.data(), out, hv.size() * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    mp_check(hipStreamSynchronize(st), "sync");
+    if (x) std::copy(pts.x.begin(), pts.x.end(), x);
+    if (normal) std::copy(nrm.begin(), nrm.end(), normal);
+    if (ds) std::copy(dsv.begin(), dsv.end(), ds);
+    if (q_tilde) std::copy(hv.begin(), hv.begin() + n, q_tilde);
+    if (q_hat) std::copy(hv.begin() + n, hv.begin() + 2 * n, q_hat);
+    if (integrals) {
+      integrals[0] = hv[(size_t)4 * n];
+      integrals[1] = hv[(size_t)4 * n + 1];
+    }
+    *n_pts = n;
     return SA_OK;
   });
 }

@@ -2675,39 +2675,8 @@ int sa_iga_heat_loss(sa_iga *h, int32_t path, int32_t face, int32_t edge_face, i
       *n_pts = n;
       throw sa::SaError{SA_EINVAL, "point arrays shorter than the number of edge points (returned in *n_pts)"};
     }
-    // Gauss points of the elements along the edge, ordered by element
-    std::vector<double> g, gw;
-    sa::gauss_legendre(quad, g, gw);
-    std::vector<double> xi((size_t)3 * n), w((size_t)n), nrm((size_t)3 * n), dsv((size_t)n);
-    const sa::Basis1D &B = P.b[e];
-    for (int el = 0; el < B.n_el(); ++el) {
-      const double lo = B.t[B.span[el]], hi = B.t[B.span[el] + 1];
-      for (int k = 0; k < quad; ++k) {
-        const int64_t i = (int64_t)el * quad + k;
-        xi[3 * i + d] = (double)(face % 2);
-        xi[3 * i + de] = (double)(edge_face % 2);
-        xi[3 * i + e] = lo + 0.5 * (hi - lo) * (g[k] + 1.0);
-        w[i] = 0.5 * (hi - lo) * gw[k];
-      }
-    }
-    // arc length along the edge and the face's outward normal: the gradient
-    // of xi_d (row d of J^{-1}), signed by the side of the face
-    sa::PointEval pe;
-    for (int64_t i = 0; i < n; ++i) {
-      int span[3];
-      for (int c = 0; c < 3; ++c) span[c] = P.b[c].find_span(xi[3 * i + c]);
-      sa::eval_point(P, &xi[3 * i], span, pe);
-      const double(&J)[3][3] = pe.J;
-      dsv[i] = std::sqrt(J[0][e] * J[0][e] + J[1][e] * J[1][e] + J[2][e] * J[2][e]) * w[i];
-      // row d of J^{-1}: the cross product of the other two columns of J over det J
-      const int a = (d + 1) % 3, b = (d + 2) % 3;
-      double gd[3] = {J[1][a] * J[2][b] - J[2][a] * J[1][b], J[2][a] * J[0][b] - J[0][a] * J[2][b],
-                      J[0][a] * J[1][b] - J[1][a] * J[0][b]};
-      const double det = gd[0] * J[0][d] + gd[1] * J[1][d] + gd[2] * J[2][d];
-      const double len = std::sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
-      const double sg = ((face % 2) ? 1.0 : -1.0) * (det > 0 ? 1.0 : -1.0) / len;
-      for (int c = 0; c < 3; ++c) nrm[3 * i + c] = sg * gd[c];
-    }
+    std::vector<double> xi, nrm, dsv;
+    sa::edge_points(P, face, edge_face, quad, xi, nrm, dsv);
     EvalTables t = eval_tables(P, n, xi.data());
     const hipStream_t st = h->stream;
     TempBufs tb;
@@ -2738,52 +2707,6 @@ int sa_iga_heat_loss(sa_iga *h, int32_t path, int32_t face, int32_t edge_face, i
   });
 }
 
-// Parametric point of the physical point x (inverse of the geometry map):
-// the element centre nearest to x, then Newton steps xi <- xi + J^{-1}
-// (x - x(xi)) kept in [0,1]^3, until |x - x(xi)| <= tol.  false if x is
-// not reached (it lies outside the patch).
-bool locate_point(const sa::PatchData &P, const std::vector<double> &centres, const std::vector<double> &cxi,
-                  const double x[3], double tol, double xi[3]) {
-  int64_t best = -1;
-  double bd = INFINITY;
-  for (int64_t e = 0; e < (int64_t)centres.size() / 3; ++e) {
-    const double d0 = centres[3 * e] - x[0], d1 = centres[3 * e + 1] - x[1], d2 = centres[3 * e + 2] - x[2];
-    const double d = d0 * d0 + d1 * d1 + d2 * d2;
-    if (d < bd) {
-      bd = d;
-      best = e;
-    }
-  }
-  if (best < 0) return false;
-  for (int c = 0; c < 3; ++c) xi[c] = cxi[3 * best + c];
-  sa::PointEval pe;
-  for (int it = 0; it < 60; ++it) {
-    int span[3];
-    for (int c = 0; c < 3; ++c) span[c] = P.b[c].find_span(xi[c]);
-    sa::eval_point(P, xi, span, pe);
-    const double r[3] = {x[0] - pe.x[0], x[1] - pe.x[1], x[2] - pe.x[2]};
-    const double res = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    if (res <= tol) return true;
-    const double(&J)[3][3] = pe.J;
-    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-    if (!(std::fabs(det) > 0.0)) return false;
-    // J^{-1} r by Cramer's rule
-    double d[3];
-    for (int c = 0; c < 3; ++c) {
-      double M[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M[i][j] = (j == c) ? r[i] : J[i][j];
-      d[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
-              M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) /
-             det;
-    }
-    for (int c = 0; c < 3; ++c) xi[c] = std::min(1.0, std::max(0.0, xi[c] + d[c]));
-  }
-  return false;
-}
-
 int sa_iga_eval_temperature_at(sa_iga *h, int32_t path, int64_t n, const double *x, double *T, double *gradT,
                                double *xi_out) {
   return guarded([&]() -> int {
@@ -2793,34 +2716,13 @@ int sa_iga_eval_temperature_at(sa_iga *h, int32_t path, int64_t n, const double 
     if (n == 0) return SA_OK;
     const sa::PatchData &P = h->m.P;
     // element centres (parametric and physical), built once per object
-    if (h->el_centre.empty()) {
-      sa::PointEval pe;
-      for (int e2 = 0; e2 < P.b[2].n_el(); ++e2)
-        for (int e1 = 0; e1 < P.b[1].n_el(); ++e1)
-          for (int e0 = 0; e0 < P.b[0].n_el(); ++e0) {
-            const int es[3] = {e0, e1, e2};
-            double c[3];
-            int span[3];
-            for (int d = 0; d < 3; ++d) {
-              span[d] = P.b[d].span[es[d]];
-              c[d] = 0.5 * (P.b[d].t[span[d]] + P.b[d].t[span[d] + 1]);
-            }
-            sa::eval_point(P, c, span, pe);
-            for (int d = 0; d < 3; ++d) {
-              h->el_xi.push_back(c[d]);
-              h->el_centre.push_back(pe.x[d]);
-            }
-          }
-    }
-    double ext = 0.0;
-    for (int64_t A = 0; A < P.ndof; ++A)
-      for (int c = 0; c < 3; ++c) ext = std::max(ext, std::fabs(P.ctrl[4 * A + c] - P.center[c]));
-    const double tol = 1e-13 * std::max(ext, 1e-300);
+    if (h->el_centre.empty()) sa::element_centres(P, h->el_centre, h->el_xi);
+    const double tol = sa::locate_tolerance(P);
     std::vector<double> xi((size_t)3 * n);
     std::vector<int64_t> inside;
     std::vector<double> xin;
     for (int64_t i = 0; i < n; ++i) {
-      if (locate_point(P, h->el_centre, h->el_xi, x + 3 * i, tol, &xi[3 * i])) {
+      if (sa::locate_point(P, h->el_centre, h->el_xi, x + 3 * i, tol, &xi[3 * i])) {
         inside.push_back(i);
         for (int c = 0; c < 3; ++c) xin.push_back(xi[3 * i + c]);
       } else {

@@ -53,6 +53,19 @@ struct PointEval {
 
 void eval_point(const PatchData &P, const double xi[3], const int span[3], PointEval &out);
 
+// inverse of the geometry map: the parametric point xi of the physical point
+// x, from the nearest element centre by Newton steps kept in [0,1]^3, to
+// |x - x(xi)| <= tol; false if x is not reached (outside the patch)
+bool locate_point(const PatchData &P, const std::vector<double> &centres, const std::vector<double> &cxi,
+                  const double x[3], double tol, double xi[3]);
+void element_centres(const PatchData &P, std::vector<double> &centres, std::vector<double> &cxi);
+double locate_tolerance(const PatchData &P);   // 1e-13 of the control net's extent
+// Gauss points (quad per element) of the edge where parametric face `face`
+// meets face `edge_face`: parametric points xi [n][3], the outward unit
+// normals of `face` [n][3], arc-length weights ds [n]; returns n
+int64_t edge_points(const PatchData &P, int face, int edge_face, int quad, std::vector<double> &xi,
+                    std::vector<double> &nrm, std::vector<double> &ds);
+
 // Banded matrix on the control-point grid: row A, offset o <-> (d0, d1, d2)
 // in [-hw0, hw0] x [-hw1, hw1] x [-hw2, hw2], value val[o * nrow + A].
 struct Stencil {

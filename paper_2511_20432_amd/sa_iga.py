@@ -123,6 +123,9 @@ EXPORTS = {
     "sa_mp_get_boundary_fields": (C.c_int, [C.c_void_p, _dp, _dp, _dp, _dp]),
     "sa_mp_get_boundary_points": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "sa_mp_eval_temperature": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, _dp, _dp, _dp]),
+    "sa_mp_eval_temperature_at": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp, _dp, _i32p, _dp]),
+    "sa_mp_heat_loss": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp, _dp, _dp,
+                                  _dp, _dp]),
     "sa_mp_destroy": (None, [C.c_void_p]),
     "sa_iga_last_error": (C.c_char_p, []),
     "sa_iga_destroy": (None, [C.c_void_p]),
@@ -584,3 +587,31 @@ class MultiPatchModel:
         check(self._lib.sa_mp_eval_temperature(self.h, patch, n, _ptr(xi, C.c_double), _ptr(T, C.c_double),
                                                _ptr(G, C.c_double)))
         return T, G
+
+    def heat_loss(self, patch: int, face: int, edge_face: int, quad: int = 4):
+        """sa_mp_heat_loss: per-point x, n, ds, q~, q^ and the integrals of
+        |q~ + q^| ds ("net") and |q~| ds ("tilde") along an edge of a patch."""
+        n = C.c_int64(0)
+        check(self._lib.sa_mp_heat_loss(self.h, patch, face, edge_face, quad, C.byref(n), None, None, None, None,
+                                        None, None))
+        m = n.value
+        x, nrm, ds, qt, qh, integ = (np.empty((m, 3)), np.empty((m, 3)), np.empty(m), np.empty(m), np.empty(m),
+                                     np.empty(2))
+        check(self._lib.sa_mp_heat_loss(self.h, patch, face, edge_face, quad, C.byref(n), _ptr(x, C.c_double),
+                                        _ptr(nrm, C.c_double), _ptr(ds, C.c_double), _ptr(qt, C.c_double),
+                                        _ptr(qh, C.c_double), _ptr(integ, C.c_double)))
+        return {"x": x, "n": nrm, "ds": ds, "q_tilde": qt, "q_hat": qh, "net": float(integ[0]),
+                "tilde": float(integ[1])}
+
+    def eval_temperature_at(self, x: np.ndarray):
+        """T [n], grad T [n, 3], the patch [n] (-1: in none) and the
+        parametric point [n, 3] of physical points x [n, 3] (m)."""
+        x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
+        n = len(x)
+        T = np.empty(n)
+        G = np.empty((n, 3))
+        patch = np.empty(n, np.int32)
+        xi = np.empty((n, 3))
+        check(self._lib.sa_mp_eval_temperature_at(self.h, n, _ptr(x, C.c_double), _ptr(T, C.c_double),
+                                                  _ptr(G, C.c_double), _ptr(patch, C.c_int32), _ptr(xi, C.c_double)))
+        return T, G, patch, xi

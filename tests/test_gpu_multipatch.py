@@ -5,7 +5,8 @@ both interfaces.
   * FP64: T~ and grad T~ at the boundary points, the load vector and the
     control values after 40 and 150 steps within 1e-9 (normwise), and T,
     grad T at 100 parametric points of each patch (20 on the top face)
-    within 1e-9 of the fields' scale;
+    within 1e-9 of the fields' scale, and at physical points found by the
+    inverse map; the heat-loss diagnostic along edges of each patch;
   * FP32 far field: within 0.05 K of the oracle over the same steps;
   * a finer L-shaped part (9,360 unknowns) over 60 steps within 1e-9;
   * the additive Schwarz and the Jacobi preconditioners on the same steps.
@@ -67,6 +68,65 @@ def test_l_part_fp64_matches_oracle():
         Tr_p, Gr_p, _ = om.evaluate(p, xi)
         assert np.abs(T - Tr_p).max() <= TOL * max(scale_T, np.abs(Tr_p - w.material.T0).max())
         assert np.abs(G - Gr_p).max() <= TOL * max(scale_G, np.abs(Gr_p).max())
+
+
+def test_l_part_physical_points():
+    """T and grad T at physical points: each point found in its patch by the
+    inverse map (parametric point within 1e-9), the values those of the
+    oracle at the parametric point; points in no patch give NaN and -1."""
+    w = W.l_part()
+    gm, om = _models(w)
+    gm.step(50)
+    om.advance(50)
+    rng = np.random.default_rng(5)
+    xs, owners, xis, Trs, Grs = [], [], [], [], []
+    for p in range(3):
+        xi = rng.uniform(0.02, 0.98, (40, 3))
+        xi[:10, 2] = 1.0                   # on the top face
+        Tr, Gr, x = om.evaluate(p, xi)
+        xs.append(x)
+        owners.append(np.full(len(xi), p))
+        xis.append(xi)
+        Trs.append(Tr)
+        Grs.append(Gr)
+    x = np.concatenate(xs + [np.array([[1.5e-3, 1.5e-3, 0.25e-3], [-1e-4, 0.5e-3, 0.25e-3]])])
+    T, G, patch, xi = gm.eval_temperature_at(x)
+    n = len(x) - 2
+    Tr, Gr = np.concatenate(Trs), np.concatenate(Grs)
+    assert np.array_equal(patch[:n], np.concatenate(owners))
+    assert np.abs(xi[:n] - np.concatenate(xis)).max() <= 1e-9
+    T0 = w.material.T0
+    assert np.abs(T[:n] - Tr).max() <= TOL * np.abs(Tr - T0).max()
+    assert np.abs(G[:n] - Gr).max() <= 1e-8 * np.abs(Gr).max()
+    # the notch of the L and a point beside the part: in no patch
+    assert (patch[n:] == -1).all() and np.isnan(T[n:]).all() and np.isnan(G[n:]).all()
+
+
+def test_l_part_heat_loss_matches_oracle():
+    """The heat-loss diagnostic along the top edges of an outer lateral face
+    of each patch against the oracle's.  The edges' fluxes span eleven
+    orders (the track starts 0.2 mm from the face x = 2 mm of the arm along
+    x), so every edge is judged on the scale of the largest: its largest
+    |q| and integral, at 1e-9."""
+    w = W.l_part()
+    gm, om = _models(w)
+    gm.step(80)
+    om.advance(80)
+    edges = ((0, 2), (1, 1), (2, 3))
+    ref = {e: om.heat_loss(e[0], e[1], 5, quad=4) for e in edges}
+    qs = max(max(np.abs(r["q_tilde"]).max(), np.abs(r["q_hat"]).max()) for r in ref.values())
+    ints = max(max(r["net"], r["tilde"]) for r in ref.values())
+    assert qs > 1e3 and ints > 1.0
+    for (p, face), r in ref.items():
+        g = gm.heat_loss(p, face, 5, quad=4)
+        errs = {"q_tilde": np.abs(g["q_tilde"] - r["q_tilde"]).max() / qs,
+                "q_hat": np.abs(g["q_hat"] - r["q_hat"]).max() / qs,
+                "net": abs(g["net"] - r["net"]) / ints, "tilde": abs(g["tilde"] - r["tilde"]) / ints}
+        print(f"patch {p} face {face}: net {g['net']:.6e} (oracle {r['net']:.6e}); worst rel "
+              f"{max(errs.values()):.2e}", flush=True)
+        assert np.abs(g["x"] - r["x"]).max() <= 1e-15 and np.abs(g["n"] - r["n"]).max() <= 1e-14
+        assert np.abs(g["ds"] - r["ds"]).max() <= 1e-13 * r["ds"].max()
+        assert max(errs.values()) <= TOL, errs
 
 
 def test_l_part_fp32_far_within_005K():

@@ -9,7 +9,9 @@
   * the constant field is in the kernel of K and 1^T M 1 = rho c_p times
     the part's volume;
   * interface faces carry no boundary points, and shared control points get
-    one global index.
+    one global index;
+  * the heat-loss diagnostic along an edge of each half equals the single
+    patch's along the same half of the edge.
 """
 import numpy as np
 import pytest
@@ -107,6 +109,28 @@ def test_split_block_trajectory_equals_the_c0_patch():
     np.testing.assert_allclose(x, x1, rtol=0, atol=1e-15)
     np.testing.assert_allclose(T, T1, rtol=1e-12)
     np.testing.assert_allclose(G, G1, rtol=1e-9, atol=1e-9 * np.abs(G1).max())
+
+
+def test_split_block_heat_loss_equals_the_c0_patch():
+    """The heat-loss diagnostic along the top edge of the y- face of each
+    half equals the single patch's along the same half of its edge (same
+    Gauss points; T^ of the same spline space)."""
+    patches, one = _split_and_single()
+    maps, _ = W.glue(patches)
+    mp = multipatch.MultiPatchModel(patches, maps, MAT, _track())
+    om = solver.Model(one, MAT, _track())
+    mp.advance(20)
+    om.advance(20)
+    ref = om.heat_loss(2, 5, quad=3)
+    half = len(ref["ds"]) // 2
+    for p, sl in ((0, slice(0, half)), (1, slice(half, None))):
+        h = mp.heat_loss(p, 2, 5, quad=3)
+        np.testing.assert_allclose(h["x"], ref["x"][sl], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(h["ds"], ref["ds"][sl], rtol=1e-13)
+        scale = np.abs(ref["q_tilde"]).max()
+        assert scale > 0
+        assert np.abs(h["q_tilde"] - ref["q_tilde"][sl]).max() <= 1e-12 * scale
+        assert np.abs(h["q_hat"] - ref["q_hat"][sl]).max() <= 1e-9 * scale
 
 
 def test_l_part_constant_kernel_volume_and_points():
