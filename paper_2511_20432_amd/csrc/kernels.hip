@@ -776,20 +776,26 @@ void launch_finalize(hipStream_t st, const PathTab &tab, bool by_slot, int64_t n
                      px, py, pz, nx, ny, nz, wdS, role, kcond, ostride, T, g, ld, net, net_stride);
 }
 
+// 32 lanes per row (coalesced along the row), a fixed butterfly sum
+constexpr int kRowLanes = 32;
 __global__ void k_gather(int64_t nrow, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                          const double *__restrict__ val, const double *__restrict__ in,
                          double *__restrict__ out) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrow) return;
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
+  if (r >= nrow) return;   // whole 32-lane groups leave together
   double s = 0.0;
-  for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) s = fma(val[e], in[col[e]], s);
-  out[r] = s;
+  for (int64_t e = rowptr[r] + sub; e < rowptr[r + 1]; e += kRowLanes) s = fma(val[e], in[col[e]], s);
+#pragma unroll
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kRowLanes);
+  if (sub == 0) out[r] = s;
 }
 
 void launch_gather(hipStream_t st, int64_t nrow, const int64_t *rowptr, const int32_t *col,
                    const double *val, const double *in, double *out) {
   if (nrow <= 0) return;
-  dim3 g((unsigned)((nrow + kBlock - 1) / kBlock));
+  const int64_t rows_per_group = kBlock / kRowLanes;
+  dim3 g((unsigned)((nrow + rows_per_group - 1) / rows_per_group));
   hipLaunchKernelGGL(k_gather, g, dim3(kBlock), 0, st, nrow, rowptr, col, val, in, out);
 }
 
@@ -860,24 +866,34 @@ void launch_scatter_dirichlet(hipStream_t st, int64_t nD, const int64_t *dofs, c
   hipLaunchKernelGGL(k_scatter, g, dim3(kBlock), 0, st, nD, dofs, vals, x);
 }
 
-__global__ void k_csr_init(CsrOp A, const double *__restrict__ b, const double *__restrict__ x,
-                           double *__restrict__ r, double *__restrict__ part) {
+// r = b - A x (32 lanes per row) and partials of |b|^2
+__global__ void k_csr_residual(CsrOp A, const double *__restrict__ b, const double *__restrict__ x,
+                               double *__restrict__ r) {
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
+  if (row >= A.nrow) return;
+  double s = 0.0;
+  for (int64_t e = A.rowptr[row] + sub; e < A.rowptr[row + 1]; e += kRowLanes) s = fma(A.val[e], x[A.col[e]], s);
+#pragma unroll
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kRowLanes);
+  if (sub == 0) r[row] = b[row] - s;
+}
+
+__global__ void k_sq_parts(int64_t n, const double *__restrict__ b, double *__restrict__ part) {
   double acc = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.nrow;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int64_t e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) s = fma(A.val[e], x[A.col[e]], s);
-    r[row] = b[row] - s;
-    acc += b[row] * b[row];
-  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += b[i] * b[i];
   const double s = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 void launch_csr_init(hipStream_t st, const CsrOp &A, const double *b, const double *x, double *r,
                      double *part) {
-  dim3 g((unsigned)parts_for(A.nrow));
-  hipLaunchKernelGGL(k_csr_init, g, dim3(kBlock), 0, st, A, b, x, r, part);
+  const int64_t rows_per_group = kBlock / kRowLanes;
+  if (A.nrow > 0)
+    hipLaunchKernelGGL(k_csr_residual, dim3((unsigned)((A.nrow + rows_per_group - 1) / rows_per_group)), dim3(kBlock),
+                       0, st, A, b, x, r);
+  hipLaunchKernelGGL(k_sq_parts, dim3((unsigned)parts_for(A.nrow)), dim3(kBlock), 0, st, A.nrow, b, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1069,35 +1085,40 @@ void launch_stencil_apply_dot(hipStream_t st, const StencilOp &A, const double *
   hipLaunchKernelGGL(k_stencil_apply_dot, g, dim3(kBlock), 0, st, A, p, q, part, sc);
 }
 
-// q = A p and partials of p . q: 32 lanes per row, each lane every 32nd
-// entry of the row (coalesced reads along it), the lanes' sums added by a
-// fixed butterfly; lane 0 of the row's group carries the row into the dot
-constexpr int kCsrLanes = 32;
-__global__ void k_csr_apply_dot(CsrOp A, const double *__restrict__ p, double *__restrict__ q,
-                                double *__restrict__ part, const PcgScalars *sc) {
+// q = A p: 32 lanes per row, each lane every 32nd entry of the row
+// (coalesced reads along it), the lanes' sums added by a fixed butterfly;
+// one workgroup per 8 rows, so that every compute unit takes part
+constexpr int kCsrLanes = kRowLanes;
+__global__ void k_csr_apply(CsrOp A, const double *__restrict__ p, double *__restrict__ q, const PcgScalars *sc) {
   if (sc->done) return;
   const int sub = threadIdx.x & (kCsrLanes - 1);
-  const int64_t rows_per_pass = (int64_t)gridDim.x * (blockDim.x / kCsrLanes);
-  double acc = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * (blockDim.x / kCsrLanes) + threadIdx.x / kCsrLanes; row < A.nrow;
-       row += rows_per_pass) {
-    double s = 0.0;
-    for (int64_t e = A.rowptr[row] + sub; e < A.rowptr[row + 1]; e += kCsrLanes) s = fma(A.val[e], p[A.col[e]], s);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kCsrLanes) + threadIdx.x / kCsrLanes;
+  if (row >= A.nrow) return;   // whole 32-lane groups leave together
+  double s = 0.0;
+  for (int64_t e = A.rowptr[row] + sub; e < A.rowptr[row + 1]; e += kCsrLanes) s = fma(A.val[e], p[A.col[e]], s);
 #pragma unroll
-    for (int off = kCsrLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kCsrLanes);
-    if (sub == 0) {
-      q[row] = s;
-      acc = fma(p[row], s, acc);
-    }
-  }
+  for (int off = kCsrLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kCsrLanes);
+  if (sub == 0) q[row] = s;
+}
+
+// partials of a . b over n entries, parts_for(n) of them
+__global__ void k_dot_parts(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                            double *__restrict__ part, const PcgScalars *sc) {
+  if (sc->done) return;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc = fma(a[i], b[i], acc);
   const double s = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 void launch_csr_apply_dot(hipStream_t st, const CsrOp &A, const double *p, double *q, double *part,
                           PcgScalars *sc) {
-  dim3 g((unsigned)parts_for(A.nrow));
-  hipLaunchKernelGGL(k_csr_apply_dot, g, dim3(kBlock), 0, st, A, p, q, part, sc);
+  const int64_t rows_per_group = kBlock / kCsrLanes;
+  if (A.nrow > 0)
+    hipLaunchKernelGGL(k_csr_apply, dim3((unsigned)((A.nrow + rows_per_group - 1) / rows_per_group)), dim3(kBlock),
+                       0, st, A, p, q, sc);
+  hipLaunchKernelGGL(k_dot_parts, dim3((unsigned)parts_for(A.nrow)), dim3(kBlock), 0, st, A.nrow, p, q, part, sc);
 }
 
 __global__ void k_pcg_update(int64_t n, int n_part, const double *__restrict__ part_pq,
