@@ -992,6 +992,68 @@ __global__ void k_fill(int64_t n, double *__restrict__ z, double v, const PcgSca
     z[i] = v;
 }
 
+// The same mode products with the fibres along `dim` staged in LDS: a
+// workgroup takes 256 / m_d consecutive fibres (the other two indices in
+// order, the lower one fastest) and the m_d x m_d factor, reads each input
+// once (along the fibre for dim 0, across fibres otherwise, so that the
+// reads are coalesced), and each thread forms one output with the sum in the
+// order of fd_mode_body (the results are bitwise those of k_fd_mode_batch).
+// For factors up to kFdLdsMax (m_d <= 64).
+constexpr int kFdLdsMax = 64;
+template <bool IN_FULL, bool OUT_FULL, bool TR>
+__global__ __launch_bounds__(256) void k_fd_mode_lds(FdBatch B, int dim, int stage, const double *__restrict__ r,
+                                                     double *__restrict__ z, bool scale, const PcgScalars *sc) {
+  if (sc && sc->done) return;
+  __shared__ double lu[kFdLdsMax * kFdLdsMax];
+  __shared__ double lin[256];
+  const FdOp &F = B.f[blockIdx.y];
+  const double *in = stage == 0 ? r + B.off[blockIdx.y] : ((stage & 1) ? F.t1 : F.t2);
+  double *out = stage == 5 ? z + B.off[blockIdx.y] : ((stage & 1) ? F.t2 : F.t1);
+  const int md = F.m[dim];
+  const int da = dim == 0 ? 1 : 0, dc = dim == 2 ? 1 : 2;   // the other two directions, da < dc
+  const int ma = F.m[da];
+  const int64_t nfib = (int64_t)ma * F.m[dc];
+  const int fb = 256 / md;                                  // fibres per workgroup
+  const int64_t f0 = (int64_t)blockIdx.x * fb;
+  if (f0 >= nfib) return;                                   // the whole workgroup
+  const double *U = F.U[dim];
+  for (int i = threadIdx.x; i < md * md; i += blockDim.x) lu[i] = U[i];
+  // element of thread t: fibre f and index k along dim
+  const int t = threadIdx.x;
+  const bool act = t < fb * md;
+  const int f = dim == 0 ? t / md : t % fb, k = dim == 0 ? t % md : t / fb;
+  const int64_t fib = f0 + f;
+  const bool ok = act && fib < nfib;
+  int j[3];
+  j[dim] = k;
+  j[da] = (int)(fib % ma);
+  j[dc] = (int)(fib / ma);
+  if (act) {
+    double v = 0.0;
+    if (ok) {
+      const int64_t src = IN_FULL ? (int64_t)(j[0] + F.lo[0]) +
+                                        (int64_t)F.n[0] * ((j[1] + F.lo[1]) + (int64_t)F.n[1] * (j[2] + F.lo[2]))
+                                  : (int64_t)j[0] + (int64_t)F.m[0] * (j[1] + (int64_t)F.m[1] * j[2]);
+      v = in[src];
+    }
+    lin[f * md + k] = v;
+  }
+  __syncthreads();
+  if (!ok) return;
+  // output k of fibre f
+  double s = 0.0;
+  for (int q = 0; q < md; ++q) {
+    const double w = TR ? lu[q * md + k] : lu[k * md + q];
+    s = fma(w, lin[f * md + q], s);
+  }
+  const int64_t tb = (int64_t)j[0] + (int64_t)F.m[0] * (j[1] + (int64_t)F.m[1] * j[2]);
+  if (scale) s *= F.inv_diag[tb];
+  const int64_t dst = OUT_FULL ? (int64_t)(j[0] + F.lo[0]) +
+                                     (int64_t)F.n[0] * ((j[1] + F.lo[1]) + (int64_t)F.n[1] * (j[2] + F.lo[2]))
+                               : tb;
+  out[dst] = s;
+}
+
 void launch_fd_batch(hipStream_t st, const FdBatch &B, int64_t n_total, const double *r, double *z,
                      const PcgScalars *sc) {
   if (B.count <= 0) return;
@@ -1001,6 +1063,28 @@ void launch_fd_batch(hipStream_t st, const FdBatch &B, int64_t n_total, const do
   // z outside the boxes stays zero
   hipLaunchKernelGGL(k_fill, dim3(parts_for(n_total)), b, 0, st, n_total, z, 0.0, sc);
   // forward: t1 = U0^T r, t2 = U1^T t1, t1 = D^{-1} U2^T t2; backward: t2 = U2 t1, t1 = U1 t2, z = U0 t1
+  int mmax = 0;
+  for (int q = 0; q < B.count; ++q)
+    for (int d = 0; d < 3; ++d) mmax = std::max(mmax, B.f[q].m[d]);
+  if (mmax <= kFdLdsMax) {
+    // workgroups per mode product: the most any solve needs
+    unsigned gx[3] = {1, 1, 1};
+    for (int d = 0; d < 3; ++d)
+      for (int q = 0; q < B.count; ++q) {
+        const FdOp &F = B.f[q];
+        const int64_t nfib = (int64_t)F.m[0] * F.m[1] * F.m[2] / F.m[d];
+        const int fb = 256 / F.m[d];
+        gx[d] = std::max(gx[d], (unsigned)((nfib + fb - 1) / fb));
+      }
+    auto gd = [&](int d) { return dim3(gx[d], (unsigned)B.count); };
+    hipLaunchKernelGGL((k_fd_mode_lds<true, false, true>), gd(0), b, 0, st, B, 0, 0, r, z, false, sc);
+    hipLaunchKernelGGL((k_fd_mode_lds<false, false, true>), gd(1), b, 0, st, B, 1, 1, r, z, false, sc);
+    hipLaunchKernelGGL((k_fd_mode_lds<false, false, true>), gd(2), b, 0, st, B, 2, 2, r, z, true, sc);
+    hipLaunchKernelGGL((k_fd_mode_lds<false, false, false>), gd(2), b, 0, st, B, 2, 3, r, z, false, sc);
+    hipLaunchKernelGGL((k_fd_mode_lds<false, false, false>), gd(1), b, 0, st, B, 1, 4, r, z, false, sc);
+    hipLaunchKernelGGL((k_fd_mode_lds<false, true, false>), gd(0), b, 0, st, B, 0, 5, r, z, false, sc);
+    return;
+  }
   hipLaunchKernelGGL((k_fd_mode_batch<true, false, true>), g, b, 0, st, B, 0, 0, r, z, false, sc);
   hipLaunchKernelGGL((k_fd_mode_batch<false, false, true>), g, b, 0, st, B, 1, 1, r, z, false, sc);
   hipLaunchKernelGGL((k_fd_mode_batch<false, false, true>), g, b, 0, st, B, 2, 2, r, z, true, sc);
