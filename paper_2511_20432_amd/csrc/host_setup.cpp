@@ -852,7 +852,7 @@ SumPlan plan_sum(const sa_solver_options &o, int64_t nq, int count, int64_t max_
   pl.waves = o.waves_per_group ? std::min(o.waves_per_group, 8) : 4;
   pl.nq = nq;
   pl.chunk_far = pl.chunk_near = 1;
-  auto tile_up = [](int64_t n) { return (n + kTile32 - 1) / kTile32 * kTile32; };
+  auto tile_up = [](int64_t n) { return (n + kFarChunkQuantum - 1) / kFarChunkQuantum * kFarChunkQuantum; };
   if (o.chunk_sources > 0) {
     pl.chunk_near = o.chunk_sources;
     pl.chunk_far = (int)tile_up(o.chunk_sources);   // far chunks start on FP32 record blocks

@@ -18,6 +18,11 @@ constexpr int kCoefStride = 8;
 // and the aligned block whose first source is the origin of its FP32 records.
 // Far-field chunks start at multiples of it.
 constexpr int kTile32 = 128;
+// far-chunk lengths: multiples of the sources the matrix-core far kernel
+// stages at a time (512), so that only a slot's last chunk ends in a part
+// block
+constexpr int kFarChunkQuantum = 512;
+static_assert(kFarChunkQuantum % kTile32 == 0, "far chunks start on FP32 record blocks");
 
 // Paths advanced by one launch (by value in the kernel arguments).  Slot s
 // holds path `path[s]`, whose sources start at row src0[s] of the global
