@@ -383,13 +383,19 @@ __device__ __forceinline__ void tensor_far(const TensorArgs &ta, const PathTab &
   __syncthreads();   // the staged sources and sums of this item are no longer read
 }
 
-// Near item: FP64 16 x 16 x 4 matrix-core steps, the four waves on the four
-// 16 x 16 blocks of the tile, 4 sources per step.  Staged per source: c,
-// x_a, x_b, 2 c dn, ln A + c dn^2.  Element r of lane l of a step is
-// D[4 r + l / 16][l % 16].
+// Near item: FP64 16 x 16 x 4 matrix-core steps, 4 sources per step.  The
+// four waves split every staged block of 256 sources (64 each); a wave forms
+// the L values of the tile's 32 rows and the R values of its 32 columns for
+// its sources (two of each per lane) and runs the 16 products of the four
+// 16 x 16 blocks and four sums, so every exponential is formed once per
+// source and row or column.  At the end of the item the waves' sums are
+// added in wave order through LDS.  Staged per source: c, x_a, x_b, 2 c dn,
+// ln A + c dn^2.  Element r of lane l of a step is D[4 r + l / 16][l % 16].
+constexpr int kNearRed = 4 * 32 * 32;   // doubles: the waves' sums of one kind for the tile
 __device__ __forceinline__ void tensor_near(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
                                             int n_chunks, int chunk_near, unsigned char *lds) {
   double(*src)[kStage] = (double(*)[kStage])lds;
+  double *red = (double *)(lds + 5 * kStage * 8);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, k = lane >> 4;
   const int n_kind = n_chunks - n_chunks_far;
@@ -398,17 +404,25 @@ __device__ __forceinline__ void tensor_near(const TensorArgs &ta, const PathTab 
   const int slot = item / (ta.n_tiles * n_kind);
   const int4 tl = ta.tiles[tile];
   const TFace F = ta.faces[tl.x];
-  // this wave's 16 x 16 block of the tile: rows b, columns a
-  const int b0 = tl.y + 16 * (wave >> 1), a0 = tl.z + 16 * (wave & 1);
   const int lo = tab.n_far[slot] + ck * chunk_near;
   const ItemSrc is = item_sources(ta, tab, F, slot, lo,
                                   lo + chunk_near < tab.n_act[slot] ? lo + chunk_near : tab.n_act[slot]);
-  const int bi = b0 + j, ai = a0 + j;
-  const bool vb = bi < F.nb, va = ai < F.na;
-  const double sb = F.sb[vb ? bi : 0], sa = F.sa[va ? ai : 0];
-  dx4 acc[4];
+  // rows b (two halves) and columns a (two halves) of this lane
+  bool vb[2], va[2];
+  double sb[2], sa[2];
 #pragma unroll
-  for (int g = 0; g < 4; ++g) acc[g] = dx4{0.0, 0.0, 0.0, 0.0};
+  for (int h = 0; h < 2; ++h) {
+    const int bi = tl.y + 16 * h + j, ai = tl.z + 16 * h + j;
+    vb[h] = bi < F.nb;
+    va[h] = ai < F.na;
+    sb[h] = F.sb[vb[h] ? bi : 0];
+    sa[h] = F.sa[va[h] ? ai : 0];
+  }
+  dx4 acc[4][4];   // [block 2 bh + ah][sum]
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[q][g] = dx4{0.0, 0.0, 0.0, 0.0};
   SrcRegs nx{0.0, 0.0, 0.0, 0.0, 0.0};
   if (is.lo < is.hi) fetch_source(ta, is, is.lo, nx);
   for (int blk = is.lo; blk < is.hi; blk += kStage) {
@@ -424,40 +438,74 @@ __device__ __forceinline__ void tensor_near(const TensorArgs &ta, const PathTab 
     }
     if (blk + kStage < is.hi) fetch_source(ta, is, blk + kStage, nx);
     __syncthreads();
-    const int n_steps = (n_in + 3) / 4;
-    for (int st = 0; st < n_steps; ++st) {
-      int t = 4 * st + k;
-      const bool vi = t < n_in;
-      t = vi ? t : n_in - 1;
+    const int s0 = 64 * wave, s1 = s0 + 64 < n_in ? s0 + 64 : n_in;
+    for (int st = s0; st < s1; st += 4) {
+      int t = st + k;
+      const bool vi = t < s1;
+      t = vi ? t : s1 - 1;
       const double c = src[0][t], xa = src[1][t], xb = src[2][t], tn = src[3][t], base = src[4][t];
-      const double db = sb - xb, da = sa - xa;
-      const double e = exp_f64(fma(c * db, db, base));
-      const double L0 = (vi && vb) ? e : 0.0;
-      const double Lb = L0 * (2.0 * c * db);
-      const double Ln = L0 * tn;
-      const double r = exp_f64(c * da * da);
-      const double R0 = va ? r : 0.0;
-      const double Ra = R0 * (2.0 * c * da);
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, R0, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, Ra, acc[1], 0, 0, 0);
-      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lb, R0, acc[2], 0, 0, 0);
-      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ln, R0, acc[3], 0, 0, 0);
+      double L0[2], Lb[2], Ln[2], R0[2], Ra[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double db = sb[h] - xb, da = sa[h] - xa;
+        const double e = exp_f64(fma(c * db, db, base));
+        L0[h] = (vi && vb[h]) ? e : 0.0;
+        Lb[h] = L0[h] * (2.0 * c * db);
+        Ln[h] = L0[h] * tn;
+        const double r = exp_f64(c * da * da);
+        R0[h] = va[h] ? r : 0.0;
+        Ra[h] = R0[h] * (2.0 * c * da);
+      }
+#pragma unroll
+      for (int bh = 0; bh < 2; ++bh)
+#pragma unroll
+        for (int ah = 0; ah < 2; ++ah) {
+          dx4(&a4)[4] = acc[2 * bh + ah];
+          a4[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0[bh], R0[ah], a4[0], 0, 0, 0);
+          a4[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0[bh], Ra[ah], a4[1], 0, 0, 0);
+          a4[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lb[bh], R0[ah], a4[2], 0, 0, 0);
+          a4[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ln[bh], R0[ah], a4[3], 0, 0, 0);
+        }
+    }
+  }
+  // the waves' sums, one kind at a time, added in wave order: thread t then
+  // holds the 4 consecutive points 4 t .. 4 t + 3 of the tile (row-major)
+  double out[4][4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    __syncthreads();
+#pragma unroll
+    for (int bh = 0; bh < 2; ++bh)
+#pragma unroll
+      for (int ah = 0; ah < 2; ++ah)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          red[wave * 1024 + (16 * bh + 4 * r + k) * 32 + 16 * ah + j] = acc[2 * bh + ah][g][r];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = 4 * threadIdx.x + e;
+      out[g][e] = ((red[idx] + red[1024 + idx]) + red[2048 + idx]) + red[3072 + idx];
     }
   }
   double *o = ta.part + ((int64_t)slot * n_chunks + n_chunks_far + ck) * 5 * ta.stride;
   const int64_t S = ta.stride;
+  const int row = (4 * threadIdx.x) >> 5, col0 = (4 * threadIdx.x) & 31;
+  const int br = tl.y + row;
+  if (br < F.nb) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int br = b0 + 4 * r + k;
-    if (br >= F.nb || !va) continue;
-    const int64_t q = F.off + (int64_t)br * F.na + ai;
-    o[q] = acc[0][r];
-    o[S + q] = 0.0;
-    o[(2 + F.ax_a) * S + q] = acc[1][r];
-    o[(2 + F.ax_b) * S + q] = acc[2][r];
-    o[(2 + F.ax_n) * S + q] = acc[3][r];
+    for (int e = 0; e < 4; ++e) {
+      const int ac = tl.z + col0 + e;
+      if (ac >= F.na) break;
+      const int64_t q = F.off + (int64_t)br * F.na + ac;
+      o[q] = out[0][e];
+      o[S + q] = 0.0;
+      o[(2 + F.ax_a) * S + q] = out[1][e];
+      o[(2 + F.ax_b) * S + q] = out[2][e];
+      o[(2 + F.ax_n) * S + q] = out[3][e];
+    }
   }
-  __syncthreads();   // the staged sources of this item are no longer read
+  __syncthreads();   // the staged sources and sums of this item are no longer read
 }
 
 // The far items (FP32), slot by slot in the order of the path table (longest
@@ -473,9 +521,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     tensor_far(ta, tab, item, n_chunks_far, n_chunks, chunk_far, lds);
 }
 
-constexpr int kNearLds = 5 * kStage * 8;
+constexpr int kNearLds = 5 * kStage * 8 + kNearRed * 8;   // staged sources + the waves' sums of one kind
+static_assert(kNearLds <= kTensorLds, "the near kernel's LDS within the far kernel's footprint");
 
-__global__ __launch_bounds__(256) void k_sum_tensor_near(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_sum_tensor_near(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
                                                          int chunk_near) {
   __shared__ __align__(16) unsigned char lds[kNearLds];
   const int n_items = ta.n_tiles * (n_chunks - n_chunks_far) * tab.count;
