@@ -383,8 +383,87 @@ __device__ __forceinline__ void tensor_far(const TensorArgs &ta, const PathTab &
   __syncthreads();   // the staged sources and sums of this item are no longer read
 }
 
-// Near item: FP64 16 x 16 x 4 matrix-core steps, 4 sources per step.  The
-// four waves split every staged block of 256 sources (64 each); a wave forms
+// Near item of a short chunk (under 256 sources): FP64 16 x 16 x 4
+// matrix-core steps, the four waves on the four 16 x 16 blocks of the tile
+// (each forms the exponentials of its block's rows and columns), 4 sources
+// per step.  Staged per source: c,
+// x_a, x_b, 2 c dn, ln A + c dn^2.  Element r of lane l of a step is
+// D[4 r + l / 16][l % 16].
+__device__ __forceinline__ void tensor_near_blocks(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
+                                            int n_chunks, int chunk_near, unsigned char *lds) {
+  double(*src)[kStage] = (double(*)[kStage])lds;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, k = lane >> 4;
+  const int n_kind = n_chunks - n_chunks_far;
+  const int tile = item % ta.n_tiles;
+  const int ck = (item / ta.n_tiles) % n_kind;
+  const int slot = item / (ta.n_tiles * n_kind);
+  const int4 tl = ta.tiles[tile];
+  const TFace F = ta.faces[tl.x];
+  // this wave's 16 x 16 block of the tile: rows b, columns a
+  const int b0 = tl.y + 16 * (wave >> 1), a0 = tl.z + 16 * (wave & 1);
+  const int lo = tab.n_far[slot] + ck * chunk_near;
+  const ItemSrc is = item_sources(ta, tab, F, slot, lo,
+                                  lo + chunk_near < tab.n_act[slot] ? lo + chunk_near : tab.n_act[slot]);
+  const int bi = b0 + j, ai = a0 + j;
+  const bool vb = bi < F.nb, va = ai < F.na;
+  const double sb = F.sb[vb ? bi : 0], sa = F.sa[va ? ai : 0];
+  dx4 acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = dx4{0.0, 0.0, 0.0, 0.0};
+  SrcRegs nx{0.0, 0.0, 0.0, 0.0, 0.0};
+  if (is.lo < is.hi) fetch_source(ta, is, is.lo, nx);
+  for (int blk = is.lo; blk < is.hi; blk += kStage) {
+    const int n_in = is.hi - blk < kStage ? is.hi - blk : kStage;
+    __syncthreads();
+    if ((int)threadIdx.x < n_in) {
+      const double c = nx.c, dn = F.sn - nx.xn;
+      src[0][threadIdx.x] = c;
+      src[1][threadIdx.x] = nx.xa;
+      src[2][threadIdx.x] = nx.xb;
+      src[3][threadIdx.x] = 2.0 * c * dn;
+      src[4][threadIdx.x] = fma(c * dn, dn, nx.lnA);
+    }
+    if (blk + kStage < is.hi) fetch_source(ta, is, blk + kStage, nx);
+    __syncthreads();
+    const int n_steps = (n_in + 3) / 4;
+    for (int st = 0; st < n_steps; ++st) {
+      int t = 4 * st + k;
+      const bool vi = t < n_in;
+      t = vi ? t : n_in - 1;
+      const double c = src[0][t], xa = src[1][t], xb = src[2][t], tn = src[3][t], base = src[4][t];
+      const double db = sb - xb, da = sa - xa;
+      const double e = exp_f64(fma(c * db, db, base));
+      const double L0 = (vi && vb) ? e : 0.0;
+      const double Lb = L0 * (2.0 * c * db);
+      const double Ln = L0 * tn;
+      const double r = exp_f64(c * da * da);
+      const double R0 = va ? r : 0.0;
+      const double Ra = R0 * (2.0 * c * da);
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, R0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(L0, Ra, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lb, R0, acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ln, R0, acc[3], 0, 0, 0);
+    }
+  }
+  double *o = ta.part + ((int64_t)slot * n_chunks + n_chunks_far + ck) * 5 * ta.stride;
+  const int64_t S = ta.stride;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int br = b0 + 4 * r + k;
+    if (br >= F.nb || !va) continue;
+    const int64_t q = F.off + (int64_t)br * F.na + ai;
+    o[q] = acc[0][r];
+    o[S + q] = 0.0;
+    o[(2 + F.ax_a) * S + q] = acc[1][r];
+    o[(2 + F.ax_b) * S + q] = acc[2][r];
+    o[(2 + F.ax_n) * S + q] = acc[3][r];
+  }
+  __syncthreads();   // the staged sources of this item are no longer read
+}
+
+// Near item of a long chunk: FP64 16 x 16 x 4 matrix-core steps, 4 sources
+// per step.  The four waves split every staged block of 256 sources (64 each); a wave forms
 // the L values of the tile's 32 rows and the R values of its 32 columns for
 // its sources (two of each per lane) and runs the 16 products of the four
 // 16 x 16 blocks and four sums, so every exponential is formed once per
@@ -392,7 +471,7 @@ __device__ __forceinline__ void tensor_far(const TensorArgs &ta, const PathTab &
 // added in wave order through LDS.  Staged per source: c, x_a, x_b, 2 c dn,
 // ln A + c dn^2.  Element r of lane l of a step is D[4 r + l / 16][l % 16].
 constexpr int kNearRed = 4 * 32 * 32;   // doubles: the waves' sums of one kind for the tile
-__device__ __forceinline__ void tensor_near(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
+__device__ __forceinline__ void tensor_near_split(const TensorArgs &ta, const PathTab &tab, int item, int n_chunks_far,
                                             int n_chunks, int chunk_near, unsigned char *lds) {
   double(*src)[kStage] = (double(*)[kStage])lds;
   double *red = (double *)(lds + 5 * kStage * 8);
@@ -521,15 +600,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     tensor_far(ta, tab, item, n_chunks_far, n_chunks, chunk_far, lds);
 }
 
-constexpr int kNearLds = 5 * kStage * 8 + kNearRed * 8;   // staged sources + the waves' sums of one kind
-static_assert(kNearLds <= kTensorLds, "the near kernel's LDS within the far kernel's footprint");
+constexpr int kNearLds = 5 * kStage * 8;                      // staged sources
+constexpr int kNearSplitLds = kNearLds + kNearRed * 8;        // + the waves' sums of one kind
+static_assert(kNearSplitLds <= kTensorLds, "the near kernels' LDS within the far kernel's footprint");
+constexpr int kNearSplitMin = kStage;   // chunks of at least this many sources: the split kernel
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_sum_tensor_near(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
+__global__ __launch_bounds__(256) void k_sum_tensor_near(TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks,
                                                          int chunk_near) {
   __shared__ __align__(16) unsigned char lds[kNearLds];
   const int n_items = ta.n_tiles * (n_chunks - n_chunks_far) * tab.count;
   for (int item = blockIdx.x; item < n_items; item += gridDim.x)
-    tensor_near(ta, tab, item, n_chunks_far, n_chunks, chunk_near, lds);
+    tensor_near_blocks(ta, tab, item, n_chunks_far, n_chunks, chunk_near, lds);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_sum_tensor_near_split(
+    TensorArgs ta, PathTab tab, int n_chunks_far, int n_chunks, int chunk_near) {
+  __shared__ __align__(16) unsigned char lds[kNearSplitLds];
+  const int n_items = ta.n_tiles * (n_chunks - n_chunks_far) * tab.count;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x)
+    tensor_near_split(ta, tab, item, n_chunks_far, n_chunks, chunk_near, lds);
 }
 
 void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, const TensorArgs &a) {
@@ -542,9 +631,17 @@ void launch_sum_tensor(hipStream_t st, const SumPlan &pl, const PathTab &tab, co
   if (far_items > 0)
     hipLaunchKernelGGL(k_sum_tensor_far, dim3(grid(far_items)), dim3(256), (size_t)a.lds_pad, st, a, tab,
                        pl.n_chunks_far, nch, pl.chunk_far);
-  if (near_items > 0)
-    hipLaunchKernelGGL(k_sum_tensor_near, dim3(grid(near_items)), dim3(256),
-                       (size_t)(a.lds_pad + kTensorLds - kNearLds), st, a, tab, pl.n_chunks_far, nch, pl.chunk_near);
+  // near items: long chunks (the FP64 form) on the source-split kernel,
+  // short ones (the recent sources of the FP32 form) on the block kernel
+  if (near_items > 0) {
+    if (pl.chunk_near >= kNearSplitMin)
+      hipLaunchKernelGGL(k_sum_tensor_near_split, dim3(grid(near_items)), dim3(256),
+                         (size_t)(a.lds_pad + kTensorLds - kNearSplitLds), st, a, tab, pl.n_chunks_far, nch,
+                         pl.chunk_near);
+    else
+      hipLaunchKernelGGL(k_sum_tensor_near, dim3(grid(near_items)), dim3(256),
+                         (size_t)(a.lds_pad + kTensorLds - kNearLds), st, a, tab, pl.n_chunks_far, nch, pl.chunk_near);
+  }
 }
 
 // the allowance only grows (per device), so a later object asking for less
@@ -559,7 +656,9 @@ bool sum_tensor_prepare(int lds_pad) {
   if (hipFuncSetAttribute((const void *)k_sum_tensor_far, hipFuncAttributeMaxDynamicSharedMemorySize, lds_pad) !=
           hipSuccess ||
       hipFuncSetAttribute((const void *)k_sum_tensor_near, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          lds_pad + kTensorLds - kNearLds) != hipSuccess)
+                          lds_pad + kTensorLds - kNearLds) != hipSuccess ||
+      hipFuncSetAttribute((const void *)k_sum_tensor_near_split, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          lds_pad + kTensorLds - kNearSplitLds) != hipSuccess)
     return false;
   granted[dev] = lds_pad;
   return true;
