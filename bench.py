@@ -65,8 +65,8 @@ SLOTS_FP64_PAIR = 28
 # copy (bench.py --copy-calibration: FETCH x 2.000, WRITE x 1.000); the
 # commands and counts are in profiles/k_sum_tensor_far_headline_traffic.md.
 # Set to None when the kernels change until the counters are taken again.
-K_SUM_TRAFFIC = {"far": {"read_bytes": 76.64e6, "written_bytes": 110.10e6},
-                 "near": {"read_bytes": 16.07e6, "written_bytes": 80.33e6}}
+K_SUM_TRAFFIC = {"far": {"read_bytes": 76.69e6, "written_bytes": 110.10e6},
+                 "near": {"read_bytes": 16.07e6, "written_bytes": 79.92e6}}
 
 WINDOW_START = "each strategy at a seeded step in [0, L - warmup - steps) with a zeroed state (u = T_c, F = 0)"
 
