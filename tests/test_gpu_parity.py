@@ -194,7 +194,9 @@ def test_source_field_at_points():
         if step == 0:
             assert np.abs(T).max() == 0 and np.abs(G).max() == 0
         else:
-            assert rel(T, Tr) <= TOL64 and rel(G, Gr) <= TOL64
+            # FP64 exponentials and sums: far inside the 1e-9 bar (a guard on the FP64 exp)
+            print(f"source field at points, step {step}: T rel {rel(T, Tr):.2e}, grad rel {rel(G, Gr):.2e}", flush=True)
+            assert rel(T, Tr) <= 1e-12 and rel(G, Gr) <= 1e-12
 
 
 def test_deterministic_and_checkpoint_resume():
