@@ -483,19 +483,25 @@ void sa_mlp_destroy(sa_mlp *h);
  * patches, z = sum_p S_p^T A_p^-1 S_p r with A_p^-1 the fast-diagonalisation
  * solve of patch p's own operator (exact on an affine patch) and S_p the
  * restriction to its control points, with SA_PRECOND_FD (the default; else
- * where a patch has no such solve) or Jacobi.  One scan path per object.
+ * where a patch has no such solve) or Jacobi.  An object holds any number of
+ * scan paths (scan strategies on the same part), each with its own state;
+ * sa_mp_step advances them one after another, and every query names its
+ * path.
  */
 typedef struct sa_multipatch sa_multipatch;   /* opaque; owns its device memory */
 
 typedef struct {
   int32_t n_patches;
+  int32_t n_paths;
   int64_t n_dof;               /* global control points */
   int64_t n_bpts;              /* boundary points (the non-interface faces of every patch, patch by
                                   patch, each patch's in the single-patch order) */
   int64_t n_dirichlet;         /* control variables fixed by DIRICHLET faces */
   int64_t n_free;
   int64_t nnz;                 /* non-zeros of the global M (and K) */
+  /* of the path named in sa_mp_get_info: */
   int64_t step;                /* steps taken */
+  int64_t n_steps;             /* steps of its scan */
   int64_t pcg_iterations;      /* total over the steps taken (theta-steps) */
   int64_t dirichlet_iterations;  /* total over the steps taken (projections) */
   double pcg_last_relres;      /* |r| / |b| of the last theta-step */
@@ -507,7 +513,8 @@ typedef struct {
  *   index_map: the global index of every control point, patch after patch,
  *     each patch's control points in the order A = a0 + n0 (a1 + n1 a2);
  *     the indices cover 0 .. n_dof - 1, every one used;
- *   scan: exactly one path; its options (scan->opt, NULL = defaults) take
+ *   scan: one or more paths, as for sa_iga_setup; the options (scan->opt,
+ *     NULL = defaults) take
  *     precision SA_PREC_FP64 or SA_PREC_FP32_FAR; preconditioner
  *     SA_PRECOND_FD (additive Schwarz) or SA_PRECOND_JACOBI.
  * All input arrays are copied.  Errors: SA_EINVAL (invalid patch, role,
@@ -516,32 +523,37 @@ typedef struct {
 int sa_mp_setup(const sa_patch *patches, int32_t n_patches, const int64_t *index_map, const sa_material *mat,
                 const sa_scan_path *scan, sa_multipatch **out);
 
-/* Advance n_steps theta-steps (fewer at the end of the scan).  SA_ENOCONV if
- * a CG solve does not reach pcg_rtol within pcg_max_iter iterations (the
- * object then keeps the state of the last completed step). */
+/* Advance every path n_steps theta-steps (fewer at the end of its scan),
+ * path 0 first.  SA_ENOCONV if a CG solve does not reach pcg_rtol within
+ * pcg_max_iter iterations: that path keeps the state of its last completed
+ * step, the paths before it have taken their steps, the paths after it none
+ * of them. */
 int sa_mp_step(sa_multipatch *h, int32_t n_steps);
 
-int sa_mp_get_info(const sa_multipatch *h, sa_mp_info *info);
+/* The model's sizes and, for path `path`, its step and solver statistics.
+ * SA_ERANGE if the path index is out of range (here and in the queries
+ * below). */
+int sa_mp_get_info(const sa_multipatch *h, int32_t path, sa_mp_info *info);
 
-/* Host copies of the current fields (any may be NULL), as
+/* Host copies of path `path`'s current fields (any may be NULL), as
  * sa_iga_get_boundary_fields: T_gp [n_bpts], grad_gp [3][n_bpts]
  * (component-major), F [n_dof], du [n_dof] (global numbering). */
-int sa_mp_get_boundary_fields(sa_multipatch *h, double *T_gp, double *grad_gp, double *F, double *du);
+int sa_mp_get_boundary_fields(sa_multipatch *h, int32_t path, double *T_gp, double *grad_gp, double *F, double *du);
 
 /* Boundary quadrature tables (host arrays, any may be NULL): x [n_bpts][3],
  * outward unit normals [n_bpts][3], weights w dS [n_bpts]. */
 int sa_mp_get_boundary_points(sa_multipatch *h, double *x, double *normal, double *wdS);
 
-/* T and grad T (Eq. 21) at n parametric points xi [n][3] of patch `patch`
- * (host arrays: T [n], grad [n][3]) at the current step: the basis
+/* T and grad T (Eq. 21) of path `path` at n parametric points xi [n][3] of
+ * patch `patch` (host arrays: T [n], grad [n][3]) at its current step: the basis
  * contraction with the control values and the kernel sum at the mapped
  * points on the device.  SA_ERANGE if a point lies outside [0,1]^3 or the
  * patch index is out of range. */
-int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const double *xi, double *T,
+int sa_mp_eval_temperature(sa_multipatch *h, int32_t path, int32_t patch, int64_t n, const double *xi, double *T,
                            double *grad);
 
-/* T and grad T (Eq. 21) at n PHYSICAL points x [n][3] (m) at the current
- * step: each point is mapped back to the parametric domain of the first
+/* T and grad T (Eq. 21) of path `path` at n PHYSICAL points x [n][3] (m) at
+ * its current step: each point is mapped back to the parametric domain of the first
  * patch (in patch order) that holds it, by the inverse map of
  * sa_iga_eval_temperature_at (nearest element centre, then Newton steps in
  * [0,1]^3 to 1e-13 of the patch size), then evaluated as by
@@ -550,16 +562,17 @@ int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const dou
  * patch).  A point in no patch gets NaN in T and grad, -1 in patch.  Host
  * arrays: T [n], grad [n][3], patch [n], xi [n][3] (the parametric points);
  * grad, patch and xi may be NULL. */
-int sa_mp_eval_temperature_at(sa_multipatch *h, int64_t n, const double *x, double *T, double *grad,
+int sa_mp_eval_temperature_at(sa_multipatch *h, int32_t path, int64_t n, const double *x, double *T, double *grad,
                               int32_t *patch, double *xi);
 
 /* The net heat-loss rate of sa_iga_heat_loss (Sec. 3.1, Tables 3-4) along
  * an edge of patch `patch`: the edge where its parametric face `face` meets
- * its face `edge_face`, at `quad` Gauss points per element, at the current
- * step; T^ from the global control values.  Arguments, outputs and errors as
+ * its face `edge_face`, at `quad` Gauss points per element, for path `path`
+ * at its current step; T^ from the global control values.  Arguments, outputs and errors as
  * for sa_iga_heat_loss (SA_ERANGE for a patch index out of range). */
-int sa_mp_heat_loss(sa_multipatch *h, int32_t patch, int32_t face, int32_t edge_face, int32_t quad, int64_t *n_pts,
-                    double *x, double *normal, double *ds, double *q_tilde, double *q_hat, double *integrals);
+int sa_mp_heat_loss(sa_multipatch *h, int32_t path, int32_t patch, int32_t face, int32_t edge_face, int32_t quad,
+                    int64_t *n_pts, double *x, double *normal, double *ds, double *q_tilde, double *q_hat,
+                    double *integrals);
 
 /* Free the object and its device memory.  NULL is ignored. */
 void sa_mp_destroy(sa_multipatch *h);

@@ -109,6 +109,16 @@ sa::Csr csr_from_triples(int64_t nrow, std::vector<int64_t> &r, std::vector<int6
 
 }  // namespace
 
+// one scan path: its sources (rows src0 .. src0 + n_src - 1 of the source
+// arrays, ticks non-decreasing), its step, its state and its statistics
+struct MpPath {
+  int64_t src0 = 0, n_src = 0, n_steps = 0, step = 0;
+  double *T = nullptr, *G = nullptr, *LD = nullptr;   // boundary fields of the last step
+  double *w = nullptr, *F = nullptr, *F1 = nullptr, *vD = nullptr, *vDn = nullptr;
+  int64_t pcg_its = 0, dir_its = 0;
+  double last_relres = 0.0;
+};
+
 struct sa_multipatch {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -123,7 +133,8 @@ struct sa_multipatch {
   sa::BoundaryTables bt;
   // scan
   std::vector<int64_t> tick;
-  int64_t n_src = 0, n_steps = 0, step = 0, tau_ticks = 0;
+  int64_t tau_ticks = 0;
+  std::vector<MpPath> paths;
   int ns = 1;
   sa::CoeffParams cp{};
   // device: points and sources
@@ -136,9 +147,8 @@ struct sa_multipatch {
   float *c32 = nullptr;
   double *part = nullptr;
   int64_t part_cap = 0;
-  // device: fields and state
-  double *T = nullptr, *G = nullptr, *LD = nullptr;
-  double *w = nullptr, *F = nullptr, *F1 = nullptr, *vD = nullptr, *vDn = nullptr, *bD = nullptr;
+  // device: work shared by the paths (the state is per path)
+  double *bD = nullptr;
   double *Bw = nullptr, *AIDvD = nullptr, *bI = nullptr, *xI = nullptr;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double *part_b = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_rr = nullptr;
@@ -148,10 +158,6 @@ struct sa_multipatch {
   double *aii_inv = nullptr, *mdir_inv = nullptr;
   // additive Schwarz over the patches (SA_PRECOND_FD): one per system
   Schwarz as_main, as_dir;
-  // statistics
-  int64_t pcg_its = 0, dir_its = 0;
-  double last_relres = 0.0;
-
   ~sa_multipatch() {
     if (stream) (void)hipStreamSynchronize(stream);
     for (void *x : owned) (void)hipFree(x);
@@ -316,20 +322,27 @@ void ensure_part(sa_multipatch *h, int64_t doubles) {
   h->part = mp_alloc<double>(h->owned, (size_t)h->part_cap);
 }
 
-// one theta-step n -> n+1
-void mp_step_one(sa_multipatch *h) {
+// sources of path P switched on at tick `now`
+int64_t active_sources(const sa_multipatch *h, const MpPath &P, int64_t now) {
+  const auto t0 = h->tick.begin() + P.src0;
+  return (int64_t)(std::upper_bound(t0, t0 + P.n_src, now) - t0);
+}
+
+// one theta-step n -> n+1 of path P
+void mp_step_one(sa_multipatch *h, MpPath &P) {
   const hipStream_t st = h->stream;
-  const int64_t s1 = h->step + 1, now = s1 * h->ns;
+  const int64_t s1 = P.step + 1, now = s1 * h->ns;
   sa::PathTab tab{};
   tab.count = 1;
   tab.path[0] = 0;
-  tab.src0[0] = 0;
+  tab.src0[0] = P.src0;
   tab.now[0] = now;
-  const int64_t a = (int64_t)(std::upper_bound(h->tick.begin(), h->tick.end(), now) - h->tick.begin());
+  const int64_t a = active_sources(h, P, now);
   int64_t f = 0;
-  if (h->opt.precision == SA_PREC_FP32_FAR && a > 0)
-    f = std::min<int64_t>(a, (int64_t)(std::lower_bound(h->tick.begin(), h->tick.begin() + a, now - h->tau_ticks) -
-                                       h->tick.begin()));
+  if (h->opt.precision == SA_PREC_FP32_FAR && a > 0) {
+    const auto t0 = h->tick.begin() + P.src0;
+    f = std::min<int64_t>(a, (int64_t)(std::lower_bound(t0, t0 + a, now - h->tau_ticks) - t0));
+  }
   tab.n_act[0] = (int32_t)a;
   tab.n_far[0] = (int32_t)f;
   tab.mode[0] = 0;
@@ -342,35 +355,34 @@ void mp_step_one(sa_multipatch *h) {
   if (nch > 0)
     sa::launch_sum(st, pl, tab, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->c64, h->c32, h->part);
   sa::launch_finalize(st, tab, true, h->nq, nch, h->stride, h->part, h->px, h->py, h->pz, h->nx, h->ny, h->nz, h->wdS,
-                      h->role, h->mat.k, h->stride, h->T, h->G, h->LD, nullptr, 0);
+                      h->role, h->mat.k, h->stride, P.T, P.G, P.LD, nullptr, 0);
   // load vector (Eq. 18) and the Dirichlet projection (Eq. 11)
-  sa::launch_gather(st, h->load.nrow, h->load.rowptr, h->load.col, h->load.val, h->LD, h->F1);
+  sa::launch_gather(st, h->load.nrow, h->load.rowptr, h->load.col, h->load.val, P.LD, P.F1);
   double rel = 0.0;
   if (h->nD > 0) {
-    sa::launch_gather(st, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->LD, h->bD);
-    mp_check(hipMemcpyAsync(h->vDn, h->vD, h->nD * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
-    h->dir_its += cg_solve(h, h->mdir.op(), h->as_dir, h->mdir_inv, h->bD, h->vDn, &rel);
+    sa::launch_gather(st, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, P.LD, h->bD);
+    mp_check(hipMemcpyAsync(P.vDn, P.vD, h->nD * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+    P.dir_its += cg_solve(h, h->mdir.op(), h->as_dir, h->mdir_inv, h->bD, P.vDn, &rel);
   }
   // theta-scheme (Eq. 20) on the free unknowns
-  sa::launch_csr_eval(st, h->nd, h->Bop.rowptr, h->Bop.col, h->Bop.val, h->w, h->Bw);
-  if (h->nD > 0) sa::launch_csr_eval(st, h->nI, h->AID.rowptr, h->AID.col, h->AID.val, h->vDn, h->AIDvD);
-  sa::launch_mp_rhs(st, h->nI, h->I_idx, h->Bw, h->F1, h->F, h->opt.theta, h->nD > 0 ? h->AIDvD : nullptr, h->w, h->bI,
+  sa::launch_csr_eval(st, h->nd, h->Bop.rowptr, h->Bop.col, h->Bop.val, P.w, h->Bw);
+  if (h->nD > 0) sa::launch_csr_eval(st, h->nI, h->AID.rowptr, h->AID.col, h->AID.val, P.vDn, h->AIDvD);
+  sa::launch_mp_rhs(st, h->nI, h->I_idx, h->Bw, P.F1, P.F, h->opt.theta, h->nD > 0 ? h->AIDvD : nullptr, P.w, h->bI,
                     h->xI);
-  h->pcg_its += cg_solve(h, h->AII.op(), h->as_main, h->aii_inv, h->bI, h->xI, &rel);
-  h->last_relres = rel;
+  P.pcg_its += cg_solve(h, h->AII.op(), h->as_main, h->aii_inv, h->bI, h->xI, &rel);
+  P.last_relres = rel;
   // commit: u^{n+1}, F^{n+1}, the Dirichlet values
-  sa::launch_mp_commit(st, h->nI, h->I_idx, h->xI, h->nD, h->D_idx, h->vDn, h->w);
-  std::swap(h->F, h->F1);
-  std::swap(h->vD, h->vDn);
+  sa::launch_mp_commit(st, h->nI, h->I_idx, h->xI, h->nD, h->D_idx, P.vDn, P.w);
+  std::swap(P.F, P.F1);
+  std::swap(P.vD, P.vDn);
   mp_check(hipGetLastError(), "kernel launch");
-  h->step = s1;
+  P.step = s1;
 }
 
 void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const int64_t *index_map,
            const sa_material *mat, const sa_scan_path *scan, const sa_solver_options &opt) {
   if (n_patches < 1 || !patches || !index_map) throw sa::SaError{SA_EINVAL, "need at least one patch and the index map"};
   for (int32_t p = 0; p < n_patches; ++p) sa::validate_inputs(&patches[p], mat, scan, opt, true);
-  if (scan->n_paths != 1) throw sa::SaError{SA_EINVAL, "a multi-patch model takes exactly one scan path"};
   if (opt.precision != SA_PREC_FP64 && opt.precision != SA_PREC_FP32_FAR)
     throw sa::SaError{SA_EINVAL, "multi-patch models take SA_PREC_FP64 or SA_PREC_FP32_FAR"};
   h->mat = *mat;
@@ -643,11 +655,16 @@ void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const i
     h->role = mp_upload(h->owned, bt.role, st);
     mp_check(hipStreamSynchronize(st), "sync");
   }
-  // sources (centred)
-  const int64_t N = scan->src_offset[1];
-  if (N > 2000000000) throw sa::SaError{SA_EINVAL, "the path holds more than 2e9 sources"};
-  h->n_src = N;
-  h->n_steps = scan->n_steps[0];
+  // sources (centred), the paths' one after another
+  const int64_t N = scan->src_offset[scan->n_paths];
+  h->paths.resize(scan->n_paths);
+  for (int k = 0; k < scan->n_paths; ++k) {
+    MpPath &P = h->paths[k];
+    P.src0 = scan->src_offset[k];
+    P.n_src = scan->src_offset[k + 1] - P.src0;
+    P.n_steps = scan->n_steps[k];
+    if (P.n_src > 2000000000) throw sa::SaError{SA_EINVAL, "a path holds more than 2e9 sources"};
+  }
   h->tick.assign(scan->tick, scan->tick + N);
   {
     std::vector<double> x(N), y(N), zz(N), E(N);
@@ -676,15 +693,17 @@ void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const i
     mp_check(hipMemsetAsync(d, 0, std::max<int64_t>(n, 1) * sizeof(double), st), "memset");
     return d;
   };
-  h->T = zeros(h->stride);
-  h->G = zeros(3 * h->stride);
-  h->LD = zeros(h->stride);
-  h->w = zeros(nd);
-  h->F = zeros(nd);
-  h->F1 = zeros(nd);
+  for (MpPath &P : h->paths) {
+    P.T = zeros(h->stride);
+    P.G = zeros(3 * h->stride);
+    P.LD = zeros(h->stride);
+    P.w = zeros(nd);
+    P.F = zeros(nd);
+    P.F1 = zeros(nd);
+    P.vD = zeros(h->nD);
+    P.vDn = zeros(h->nD);
+  }
   h->Bw = zeros(nd);
-  h->vD = zeros(h->nD);
-  h->vDn = zeros(h->nD);
   h->bD = zeros(h->nD);
   h->AIDvD = zeros(h->nI);
   h->bI = zeros(h->nI);
@@ -708,6 +727,7 @@ void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const i
 // [0,1]^3): the physical points x [n][3], and on the device (buffers in
 // tmp, work on the object's stream) the basis rows with global columns
 // (R and the physical gradients) and the source field T~, grad T~ [3][stride]
+// of path `path` at its current step
 struct MpPoints {
   int64_t stride = 0;
   std::vector<double> x;
@@ -717,7 +737,8 @@ struct MpPoints {
   double *dT = nullptr, *dG = nullptr;
 };
 
-MpPoints mp_points(sa_multipatch *h, int32_t patch, int64_t n, const double *xi, std::vector<void *> &tmp) {
+MpPoints mp_points(sa_multipatch *h, const MpPath &path, int32_t patch, int64_t n, const double *xi,
+                   std::vector<void *> &tmp) {
   MpPoints out;
   const sa::PatchData &P = h->P[patch];
   const auto &g = h->gmap[patch];
@@ -797,8 +818,9 @@ MpPoints mp_points(sa_multipatch *h, int32_t patch, int64_t n, const double *xi,
   out.stride = stride;
   sa::PathTab tab{};
   tab.count = 1;
-  tab.now[0] = h->step * h->ns;
-  tab.n_act[0] = (int32_t)(std::upper_bound(h->tick.begin(), h->tick.end(), tab.now[0]) - h->tick.begin());
+  tab.src0[0] = path.src0;
+  tab.now[0] = path.step * h->ns;
+  tab.n_act[0] = (int32_t)active_sources(h, path, tab.now[0]);
   tab.n_far[0] = 0;
   const int64_t a = tab.n_act[0];
   if (a > 0) sa::launch_coeff(st, tab, a, h->stick, h->sx, h->sy, h->sz, h->sE, h->cp, h->c64, h->c32);
@@ -812,6 +834,11 @@ MpPoints mp_points(sa_multipatch *h, int32_t patch, int64_t n, const double *xi,
   for (int64_t i = 0; i < n; ++i)
     for (int c = 0; c < 3; ++c) out.x[3 * i + c] = xp[3 * i + c] + h->center[c];
   return out;
+}
+
+const MpPath &path_at(const sa_multipatch *h, int32_t path) {
+  if (path < 0 || path >= (int32_t)h->paths.size()) throw sa::SaError{SA_ERANGE, "path index out of range"};
+  return h->paths[path];
 }
 
 struct TmpFree {
@@ -853,60 +880,67 @@ int sa_mp_step(sa_multipatch *h, int32_t n_steps) {
   return mp_guarded([&]() -> int {
     if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
     if (n_steps < 0) throw sa::SaError{SA_EINVAL, "negative step count"};
-    for (int32_t k = 0; k < n_steps && h->step < h->n_steps; ++k) {
-      // the state of the last completed step survives a failing solve
-      try {
-        mp_step_one(h);
-      } catch (const sa::SaError &) {
-        (void)hipStreamSynchronize(h->stream);
-        throw;
+    for (MpPath &P : h->paths)
+      for (int32_t k = 0; k < n_steps && P.step < P.n_steps; ++k) {
+        // the state of the last completed step survives a failing solve
+        try {
+          mp_step_one(h, P);
+        } catch (const sa::SaError &) {
+          (void)hipStreamSynchronize(h->stream);
+          throw;
+        }
       }
-    }
     mp_check(hipStreamSynchronize(h->stream), "sync");
     return SA_OK;
   });
 }
 
-int sa_mp_get_info(const sa_multipatch *h, sa_mp_info *info) {
+int sa_mp_get_info(const sa_multipatch *h, int32_t path, sa_mp_info *info) {
   return mp_guarded([&]() -> int {
     if (!h || !info) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    const MpPath &P = path_at(h, path);
     *info = sa_mp_info{};
+    info->n_paths = (int32_t)h->paths.size();
     info->n_patches = (int32_t)h->P.size();
     info->n_dof = h->nd;
     info->n_bpts = h->nq;
     info->n_dirichlet = h->nD;
     info->n_free = h->nI;
     info->nnz = h->nnz;
-    info->step = h->step;
-    info->pcg_iterations = h->pcg_its;
-    info->dirichlet_iterations = h->dir_its;
-    info->pcg_last_relres = h->last_relres;
+    info->step = P.step;
+    info->n_steps = P.n_steps;
+    info->pcg_iterations = P.pcg_its;
+    info->dirichlet_iterations = P.dir_its;
+    info->pcg_last_relres = P.last_relres;
     return SA_OK;
   });
 }
 
-int sa_mp_get_boundary_fields(sa_multipatch *h, double *T_gp, double *grad_gp, double *F, double *du) {
+int sa_mp_get_boundary_fields(sa_multipatch *h, int32_t path, double *T_gp, double *grad_gp, double *F,
+                              double *du) {
   return mp_guarded([&]() -> int {
     if (!h) throw sa::SaError{SA_EINVAL, "NULL object"};
+    const MpPath &P = path_at(h, path);
     const hipStream_t st = h->stream;
-    if (T_gp) mp_check(hipMemcpyAsync(T_gp, h->T, h->nq * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    if (T_gp) mp_check(hipMemcpyAsync(T_gp, P.T, h->nq * sizeof(double), hipMemcpyDeviceToHost, st), "download");
     if (grad_gp)
       for (int c = 0; c < 3; ++c)
-        mp_check(hipMemcpyAsync(grad_gp + c * h->nq, h->G + c * h->stride, h->nq * sizeof(double),
+        mp_check(hipMemcpyAsync(grad_gp + c * h->nq, P.G + c * h->stride, h->nq * sizeof(double),
                                 hipMemcpyDeviceToHost, st),
                  "download");
-    if (F) mp_check(hipMemcpyAsync(F, h->F, h->nd * sizeof(double), hipMemcpyDeviceToHost, st), "download");
-    if (du) mp_check(hipMemcpyAsync(du, h->w, h->nd * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    if (F) mp_check(hipMemcpyAsync(F, P.F, h->nd * sizeof(double), hipMemcpyDeviceToHost, st), "download");
+    if (du) mp_check(hipMemcpyAsync(du, P.w, h->nd * sizeof(double), hipMemcpyDeviceToHost, st), "download");
     mp_check(hipStreamSynchronize(st), "sync");
     return SA_OK;
   });
 }
 
-int sa_mp_eval_temperature_at(sa_multipatch *h, int64_t n, const double *x, double *T, double *grad,
+int sa_mp_eval_temperature_at(sa_multipatch *h, int32_t path, int64_t n, const double *x, double *T, double *grad,
                               int32_t *patch, double *xi_out) {
   return mp_guarded([&]() -> int {
     if (!h || (n > 0 && (!x || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
     if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
+    (void)path_at(h, path);
     if (n == 0) return SA_OK;
     const int np = (int)h->P.size();
     if (h->el_centre.empty()) {
@@ -944,7 +978,7 @@ int sa_mp_eval_temperature_at(sa_multipatch *h, int64_t n, const double *x, doub
       if (idx.empty()) continue;
       const int64_t m = (int64_t)idx.size();
       std::vector<double> Tp((size_t)m), Gp((size_t)3 * m);
-      const int rc = sa_mp_eval_temperature(h, p, m, q.data(), Tp.data(), Gp.data());
+      const int rc = sa_mp_eval_temperature(h, path, p, m, q.data(), Tp.data(), Gp.data());
       if (rc != SA_OK) throw sa::SaError{rc, sa_iga_last_error()};
       for (int64_t k = 0; k < m; ++k) {
         T[idx[k]] = Tp[k];
@@ -968,18 +1002,20 @@ int sa_mp_get_boundary_points(sa_multipatch *h, double *x, double *normal, doubl
   });
 }
 
-int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const double *xi, double *T, double *grad) {
+int sa_mp_eval_temperature(sa_multipatch *h, int32_t path, int32_t patch, int64_t n, const double *xi, double *T,
+                           double *grad) {
   return mp_guarded([&]() -> int {
     if (!h || (n > 0 && (!xi || !T))) throw sa::SaError{SA_EINVAL, "NULL argument"};
     if (n < 0) throw sa::SaError{SA_EINVAL, "negative size"};
+    const MpPath &pth = path_at(h, path);
     if (patch < 0 || patch >= (int32_t)h->P.size()) throw sa::SaError{SA_ERANGE, "patch index out of range"};
     if (n == 0) return SA_OK;
     const hipStream_t st = h->stream;
     TmpFree tf;
-    const MpPoints pts = mp_points(h, patch, n, xi, tf.v);
+    const MpPoints pts = mp_points(h, pth, patch, n, xi, tf.v);
     // T^ and its gradient: the contractions with the control values
     double *hat = mp_alloc<double>(tf.v, 4 * n);
-    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(st, n, pts.rp, pts.cl, pts.vals[k], h->w, hat + k * n);
+    for (int k = 0; k < 4; ++k) sa::launch_csr_eval(st, n, pts.rp, pts.cl, pts.vals[k], pth.w, hat + k * n);
     const double *dT = pts.dT, *dG = pts.dG;
     const int64_t stride = pts.stride;
     std::vector<double> hv(4 * n), tt(n), tg(3 * n);
@@ -999,10 +1035,12 @@ int sa_mp_eval_temperature(sa_multipatch *h, int32_t patch, int64_t n, const dou
   });
 }
 
-int sa_mp_heat_loss(sa_multipatch *h, int32_t patch, int32_t face, int32_t edge_face, int32_t quad, int64_t *n_pts,
-                    double *x, double *normal, double *ds, double *q_tilde, double *q_hat, double *integrals) {
+int sa_mp_heat_loss(sa_multipatch *h, int32_t path, int32_t patch, int32_t face, int32_t edge_face, int32_t quad,
+                    int64_t *n_pts, double *x, double *normal, double *ds, double *q_tilde, double *q_hat,
+                    double *integrals) {
   return mp_guarded([&]() -> int {
     if (!h || !n_pts) throw sa::SaError{SA_EINVAL, "NULL argument"};
+    const MpPath &pth = path_at(h, path);
     if (patch < 0 || patch >= (int32_t)h->P.size()) throw sa::SaError{SA_ERANGE, "patch index out of range"};
     if (face < 0 || face > 5 || edge_face < 0 || edge_face > 5 || face / 2 == edge_face / 2)
       throw sa::SaError{SA_EINVAL, "face and edge_face must be parametric faces 0..5 that meet along an edge"};
@@ -1023,10 +1061,10 @@ int sa_mp_heat_loss(sa_multipatch *h, int32_t patch, int32_t face, int32_t edge_
     sa::edge_points(P, face, edge_face, quad, xi, nrm, dsv);
     const hipStream_t st = h->stream;
     TmpFree tf;
-    const MpPoints pts = mp_points(h, patch, n, xi.data(), tf.v);
+    const MpPoints pts = mp_points(h, pth, patch, n, xi.data(), tf.v);
     double *dn = mp_upload(tf.v, nrm, st), *dds = mp_upload(tf.v, dsv, st);
     double *out = mp_alloc<double>(tf.v, (size_t)4 * n + 2);
-    sa::launch_heat_loss(st, n, pts.rp, pts.cl, pts.vals[1], pts.vals[2], pts.vals[3], h->w, pts.dG, pts.stride, dn,
+    sa::launch_heat_loss(st, n, pts.rp, pts.cl, pts.vals[1], pts.vals[2], pts.vals[3], pth.w, pts.dG, pts.stride, dn,
                          dds, h->mat.k, out, out + n, out + 2 * n, out + 3 * n, out + 4 * n);
     mp_check(hipGetLastError(), "kernel launch");
     std::vector<double> hv((size_t)4 * n + 2);

@@ -70,9 +70,10 @@ class sa_stats(C.Structure):
 
 
 class sa_mp_info(C.Structure):
-    _fields_ = [("n_patches", C.c_int32), ("n_dof", C.c_int64), ("n_bpts", C.c_int64), ("n_dirichlet", C.c_int64),
-                ("n_free", C.c_int64), ("nnz", C.c_int64), ("step", C.c_int64), ("pcg_iterations", C.c_int64),
-                ("dirichlet_iterations", C.c_int64), ("pcg_last_relres", C.c_double)]
+    _fields_ = [("n_patches", C.c_int32), ("n_paths", C.c_int32), ("n_dof", C.c_int64), ("n_bpts", C.c_int64),
+                ("n_dirichlet", C.c_int64), ("n_free", C.c_int64), ("nnz", C.c_int64), ("step", C.c_int64),
+                ("n_steps", C.c_int64), ("pcg_iterations", C.c_int64), ("dirichlet_iterations", C.c_int64),
+                ("pcg_last_relres", C.c_double)]
 
 
 EXPORTS = {
@@ -119,12 +120,12 @@ EXPORTS = {
     "sa_mp_setup": (C.c_int, [C.POINTER(sa_patch), C.c_int32, _i64p, C.POINTER(sa_material),
                               C.POINTER(sa_scan_path), C.POINTER(C.c_void_p)]),
     "sa_mp_step": (C.c_int, [C.c_void_p, C.c_int32]),
-    "sa_mp_get_info": (C.c_int, [C.c_void_p, C.POINTER(sa_mp_info)]),
-    "sa_mp_get_boundary_fields": (C.c_int, [C.c_void_p, _dp, _dp, _dp, _dp]),
+    "sa_mp_get_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sa_mp_info)]),
+    "sa_mp_get_boundary_fields": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, _dp, _dp]),
     "sa_mp_get_boundary_points": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
-    "sa_mp_eval_temperature": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, _dp, _dp, _dp]),
-    "sa_mp_eval_temperature_at": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp, _dp, _i32p, _dp]),
-    "sa_mp_heat_loss": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp, _dp, _dp,
+    "sa_mp_eval_temperature": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, _dp, _dp, _dp]),
+    "sa_mp_eval_temperature_at": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, _dp, _dp, _dp, _i32p, _dp]),
+    "sa_mp_heat_loss": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp, _dp, _dp,
                                   _dp, _dp]),
     "sa_mp_destroy": (None, [C.c_void_p]),
     "sa_iga_last_error": (C.c_char_p, []),
@@ -511,7 +512,8 @@ def from_workload(w: W.Workload, **opt_overrides) -> Model:
 
 class MultiPatchModel:
     """Owner of one sa_multipatch handle: patches glued by the global index
-    maps of their control points (workloads.glue), one scan path."""
+    maps of their control points (workloads.glue), one or more scan paths
+    (every query names its path, 0 by default)."""
 
     def __init__(self, patches, maps, material: W.Material, scan: W.ScanPath,
                  options: Optional[W.Options] = None, **opt_overrides):
@@ -551,12 +553,12 @@ class MultiPatchModel:
     def step(self, n: int = 1):
         check(self._lib.sa_mp_step(self.h, n))
 
-    def get_info(self) -> sa_mp_info:
+    def get_info(self, path: int = 0) -> sa_mp_info:
         i = sa_mp_info()
-        check(self._lib.sa_mp_get_info(self.h, C.byref(i)))
+        check(self._lib.sa_mp_get_info(self.h, path, C.byref(i)))
         return i
 
-    def boundary_fields(self):
+    def boundary_fields(self, path: int = 0):
         """T~ [nq], grad T~ [nq, 3] at the boundary points, F [n_dof] and
         du [n_dof] = T^ - T_c at the global control points."""
         self.info = self.get_info()
@@ -565,7 +567,7 @@ class MultiPatchModel:
         G = np.empty((3, nq))
         F = np.empty(nd)
         u = np.empty(nd)
-        check(self._lib.sa_mp_get_boundary_fields(self.h, _ptr(T, C.c_double), _ptr(G, C.c_double),
+        check(self._lib.sa_mp_get_boundary_fields(self.h, path, _ptr(T, C.c_double), _ptr(G, C.c_double),
                                                   _ptr(F, C.c_double), _ptr(u, C.c_double)))
         return T, G.T.copy(), F, u
 
@@ -578,32 +580,32 @@ class MultiPatchModel:
                                                   _ptr(w, C.c_double)))
         return x, n, w
 
-    def eval_temperature(self, patch: int, xi: np.ndarray):
+    def eval_temperature(self, patch: int, xi: np.ndarray, path: int = 0):
         """T [n] and grad T [n, 3] at parametric points xi [n, 3] of one patch."""
         xi = np.ascontiguousarray(np.atleast_2d(xi), np.float64)
         n = len(xi)
         T = np.empty(n)
         G = np.empty((n, 3))
-        check(self._lib.sa_mp_eval_temperature(self.h, patch, n, _ptr(xi, C.c_double), _ptr(T, C.c_double),
+        check(self._lib.sa_mp_eval_temperature(self.h, path, patch, n, _ptr(xi, C.c_double), _ptr(T, C.c_double),
                                                _ptr(G, C.c_double)))
         return T, G
 
-    def heat_loss(self, patch: int, face: int, edge_face: int, quad: int = 4):
+    def heat_loss(self, patch: int, face: int, edge_face: int, quad: int = 4, path: int = 0):
         """sa_mp_heat_loss: per-point x, n, ds, q~, q^ and the integrals of
         |q~ + q^| ds ("net") and |q~| ds ("tilde") along an edge of a patch."""
         n = C.c_int64(0)
-        check(self._lib.sa_mp_heat_loss(self.h, patch, face, edge_face, quad, C.byref(n), None, None, None, None,
+        check(self._lib.sa_mp_heat_loss(self.h, path, patch, face, edge_face, quad, C.byref(n), None, None, None, None,
                                         None, None))
         m = n.value
         x, nrm, ds, qt, qh, integ = (np.empty((m, 3)), np.empty((m, 3)), np.empty(m), np.empty(m), np.empty(m),
                                      np.empty(2))
-        check(self._lib.sa_mp_heat_loss(self.h, patch, face, edge_face, quad, C.byref(n), _ptr(x, C.c_double),
+        check(self._lib.sa_mp_heat_loss(self.h, path, patch, face, edge_face, quad, C.byref(n), _ptr(x, C.c_double),
                                         _ptr(nrm, C.c_double), _ptr(ds, C.c_double), _ptr(qt, C.c_double),
                                         _ptr(qh, C.c_double), _ptr(integ, C.c_double)))
         return {"x": x, "n": nrm, "ds": ds, "q_tilde": qt, "q_hat": qh, "net": float(integ[0]),
                 "tilde": float(integ[1])}
 
-    def eval_temperature_at(self, x: np.ndarray):
+    def eval_temperature_at(self, x: np.ndarray, path: int = 0):
         """T [n], grad T [n, 3], the patch [n] (-1: in none) and the
         parametric point [n, 3] of physical points x [n, 3] (m)."""
         x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
@@ -612,6 +614,6 @@ class MultiPatchModel:
         G = np.empty((n, 3))
         patch = np.empty(n, np.int32)
         xi = np.empty((n, 3))
-        check(self._lib.sa_mp_eval_temperature_at(self.h, n, _ptr(x, C.c_double), _ptr(T, C.c_double),
+        check(self._lib.sa_mp_eval_temperature_at(self.h, path, n, _ptr(x, C.c_double), _ptr(T, C.c_double),
                                                   _ptr(G, C.c_double), _ptr(patch, C.c_int32), _ptr(xi, C.c_double)))
         return T, G, patch, xi

@@ -150,8 +150,8 @@ def test_multipatch_inputs_rejected_before_device():
     maps = [m.copy() for m in w.maps]
     maps[0][3] = -1
     expect(sa_iga.SA_EINVAL, w.patches, maps)
-    # one path only; FP64 or FP32 far field only
-    two = W.make_scan([(w.scan.xyz, w.scan.tick, w.scan.energy)] * 2, w.scan.dt, w.scan.sources_per_step,
-                      n_steps=[10, 10])
+    # a second path whose ticks decrease; FP64 or FP32 far field only
+    two = W.make_scan([(w.scan.xyz, w.scan.tick, w.scan.energy), (w.scan.xyz, w.scan.tick[::-1], w.scan.energy)],
+                      w.scan.dt, w.scan.sources_per_step, n_steps=[10, 10])
     expect(sa_iga.SA_EINVAL, w.patches, w.maps, scan=two)
     expect(sa_iga.SA_EINVAL, w.patches, w.maps, precision=2)

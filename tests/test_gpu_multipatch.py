@@ -184,3 +184,57 @@ def test_steps_stop_at_the_end_of_the_scan():
         gm.eval_temperature(3, np.zeros((1, 3)))
     with pytest.raises(sa_iga.SaError):
         gm.eval_temperature(0, np.array([[0.5, 0.5, 1.5]]))
+
+
+def test_l_part_several_paths():
+    """Two scan strategies on the L-shaped part in one object, of different
+    lengths (the workload's track, 150 of its 260 steps taken; the track run
+    from its other end, 100 steps): each path's fields equal the oracle's run
+    of that path alone (1e-9), and path 1's queries equal, bit for bit, those
+    of an object that holds path 1 alone (the paths share only the operators
+    and the work buffers)."""
+    from paper_2511_20432_amd import sa_iga
+    w = W.l_part()
+    s = w.scan
+    back = (s.xyz[::-1][:600], s.tick[:600], s.energy[:600])
+    scan = W.make_scan([(s.xyz, s.tick, s.energy), back], s.dt, s.sources_per_step, n_steps=[260, 100])
+    alone = W.make_scan([back], s.dt, s.sources_per_step, n_steps=[100])
+    opts = W.Options(tau_near=2e-4)
+    gm = sa_iga.MultiPatchModel(w.patches, w.maps, w.material, scan, opts)
+    g1 = sa_iga.MultiPatchModel(w.patches, w.maps, w.material, alone, opts)
+    assert gm.get_info().n_paths == 2 and gm.get_info(1).n_steps == 100
+    gm.step(150)
+    g1.step(150)
+    assert gm.get_info(0).step == 150 and gm.get_info(1).step == 100 and g1.get_info().step == 100
+    rng = np.random.default_rng(11)
+    xi = rng.uniform(0, 1, (30, 3))
+    xi[:10, 2] = 1.0
+    for path, steps in ((0, 150), (1, 100)):
+        om = multipatch.MultiPatchModel(w.patches, w.maps, w.material, scan, path=path)
+        om.advance(steps)
+        T, G, F, du = gm.boundary_fields(path)
+        Tr, Gr = om.boundary_field(steps)
+        errs = {"T": rel(T, Tr), "grad": rel(G, Gr), "F": rel(F, om.F), "du": rel(du, om.w)}
+        print(f"path {path}, step {steps}: max |w| {np.abs(om.w).max():.3e} K, worst rel {max(errs.values()):.2e}",
+              flush=True)
+        assert max(errs.values()) <= TOL, errs
+        Tq, Gq = gm.eval_temperature(1, xi, path=path)
+        Tq_r, Gq_r, _ = om.evaluate(1, xi)
+        assert np.abs(Tq - Tq_r).max() <= TOL * max(np.abs(om.w).max(), np.abs(Tq_r - w.material.T0).max())
+        assert np.abs(Gq - Gq_r).max() <= TOL * max(np.abs(Gr).max(), np.abs(Gq_r).max())
+    # path 1 of the two-path object = the one-path object, bit for bit
+    for a, b in zip(gm.boundary_fields(1), g1.boundary_fields()):
+        assert np.array_equal(a, b)
+    for a, b in zip(gm.eval_temperature(2, xi, path=1), g1.eval_temperature(2, xi)):
+        assert np.array_equal(a, b)
+    x = np.array([[0.5e-3, 1.5e-3, 0.5e-3], [1.5e-3, 0.5e-3, 0.4e-3]])
+    for a, b in zip(gm.eval_temperature_at(x, path=1), g1.eval_temperature_at(x)):
+        assert np.array_equal(a, b)
+    h, h1 = gm.heat_loss(2, 3, 5, quad=3, path=1), g1.heat_loss(2, 3, 5, quad=3)
+    assert all(np.array_equal(h[k], h1[k]) for k in h)
+    info, info1 = gm.get_info(1), g1.get_info()
+    assert (info.pcg_iterations, info.dirichlet_iterations) == (info1.pcg_iterations, info1.dirichlet_iterations)
+    for bad in (-1, 2):
+        with pytest.raises(sa_iga.SaError) as e:
+            gm.boundary_fields(bad)
+        assert e.value.code == sa_iga.SA_ERANGE
