@@ -9,7 +9,9 @@ both interfaces.
     inverse map; the heat-loss diagnostic along edges of each patch;
   * FP32 far field: within 0.05 K of the oracle over the same steps;
   * a finer L-shaped part (9,360 unknowns) over 60 steps within 1e-9;
-  * the additive Schwarz and the Jacobi preconditioners on the same steps.
+  * the additive Schwarz and the Jacobi preconditioners on the same steps;
+  * two scan paths in one object, each against the oracle, the second
+    bitwise equal to an object that holds it alone.
 """
 import numpy as np
 import pytest
