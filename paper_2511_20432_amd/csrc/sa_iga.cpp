@@ -2388,13 +2388,13 @@ void source_field_noalloc(sa_iga *h, int p, int64_t step, int64_t n, const doubl
 void *query_workspace(sa_iga *h, size_t bytes) {
   if (bytes <= h->evw_bytes) return h->evw;
   sync_all(h);
+  const size_t cap = std::max(bytes, 2 * h->evw_bytes);
   if (h->evw) {
     hip_check(hipFree(h->evw), "free");
     h->owned.erase(std::find(h->owned.begin(), h->owned.end(), h->evw));
     h->evw = nullptr;
     h->evw_bytes = 0;
   }
-  const size_t cap = std::max(bytes, 2 * h->evw_bytes);
   h->evw = dev_alloc<unsigned char>(h->owned, cap);
   h->evw_bytes = cap;
   return h->evw;
