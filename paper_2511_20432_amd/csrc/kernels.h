@@ -185,16 +185,20 @@ void launch_jacobi(hipStream_t st, int64_t n, const double *inv_diag, const doub
 void launch_fd(hipStream_t st, const FdOp &F, int64_t n, const double *r, double *z, double *part,
                PcgScalars *sc);
 // several FD solves in the same launches: solve b reads the full vector
-// r + off[b] (its grid n[0] n[1] n[2]) and writes z + off[b]; z is zeroed
-// over its n_total entries first (outside the boxes it stays zero)
+// r + off[b] (its grid n[0] n[1] n[2]) and writes the entries of its box in
+// z + off[b]; the other entries of z are not written (the caller zeroes them
+// once).  With gidx set (only where fd_batch_in_lds holds), solve b reads
+// entry k of its grid as r[gidx[off[b] + k]] (0 where that is negative)
+// instead: r is then the vector of the whole system, gathered on the fly.
 constexpr int kFdBatchMax = 8;
 struct FdBatch {
   int count;
   FdOp f[kFdBatchMax];
   int64_t off[kFdBatchMax];
+  const int64_t *gidx;
 };
-void launch_fd_batch(hipStream_t st, const FdBatch &B, int64_t n_total, const double *r, double *z,
-                     const PcgScalars *sc);
+bool fd_batch_in_lds(const FdBatch &B);
+void launch_fd_batch(hipStream_t st, const FdBatch &B, const double *r, double *z, const PcgScalars *sc);
 void launch_pcg_start(hipStream_t st, int64_t n, int n_part_b, const double *part_b, int n_part_rz,
                       const double *part_rz, const double *z, double *p, PcgScalars *sc, double rtol);
 void launch_stencil_apply_dot(hipStream_t st, const StencilOp &A, const double *p, double *q, double *part,

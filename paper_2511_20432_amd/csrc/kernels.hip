@@ -1155,7 +1155,7 @@ __global__ __launch_bounds__(256) void k_fd_mode_lds(FdBatch B, int dim, int sta
   __shared__ double lu[kFdLdsMax * kFdLdsMax];
   __shared__ double lin[256];
   const FdOp &F = B.f[blockIdx.y];
-  const double *in = stage == 0 ? r + B.off[blockIdx.y] : ((stage & 1) ? F.t1 : F.t2);
+  const double *in = stage == 0 ? (B.gidx ? r : r + B.off[blockIdx.y]) : ((stage & 1) ? F.t1 : F.t2);
   double *out = stage == 5 ? z + B.off[blockIdx.y] : ((stage & 1) ? F.t2 : F.t1);
   const int md = F.m[dim];
   const int da = dim == 0 ? 1 : 0, dc = dim == 2 ? 1 : 2;   // the other two directions, da < dc
@@ -1182,7 +1182,12 @@ __global__ __launch_bounds__(256) void k_fd_mode_lds(FdBatch B, int dim, int sta
       const int64_t src = IN_FULL ? (int64_t)(j[0] + F.lo[0]) +
                                         (int64_t)F.n[0] * ((j[1] + F.lo[1]) + (int64_t)F.n[1] * (j[2] + F.lo[2]))
                                   : (int64_t)j[0] + (int64_t)F.m[0] * (j[1] + (int64_t)F.m[1] * j[2]);
-      v = in[src];
+      if (stage == 0 && B.gidx) {
+        const int64_t g = B.gidx[B.off[blockIdx.y] + src];
+        v = g >= 0 ? r[g] : 0.0;
+      } else {
+        v = in[src];
+      }
     }
     lin[f * md + k] = v;
   }
@@ -1202,19 +1207,20 @@ __global__ __launch_bounds__(256) void k_fd_mode_lds(FdBatch B, int dim, int sta
   out[dst] = s;
 }
 
-void launch_fd_batch(hipStream_t st, const FdBatch &B, int64_t n_total, const double *r, double *z,
-                     const PcgScalars *sc) {
+bool fd_batch_in_lds(const FdBatch &B) {
+  for (int q = 0; q < B.count; ++q)
+    for (int d = 0; d < 3; ++d)
+      if (B.f[q].m[d] > kFdLdsMax) return false;
+  return true;
+}
+
+void launch_fd_batch(hipStream_t st, const FdBatch &B, const double *r, double *z, const PcgScalars *sc) {
   if (B.count <= 0) return;
   int64_t nbox = 1;
   for (int b = 0; b < B.count; ++b) nbox = std::max<int64_t>(nbox, (int64_t)B.f[b].m[0] * B.f[b].m[1] * B.f[b].m[2]);
   dim3 b(kBlock), g((unsigned)parts_for(nbox), (unsigned)B.count);
-  // z outside the boxes stays zero
-  hipLaunchKernelGGL(k_fill, dim3(parts_for(n_total)), b, 0, st, n_total, z, 0.0, sc);
   // forward: t1 = U0^T r, t2 = U1^T t1, t1 = D^{-1} U2^T t2; backward: t2 = U2 t1, t1 = U1 t2, z = U0 t1
-  int mmax = 0;
-  for (int q = 0; q < B.count; ++q)
-    for (int d = 0; d < 3; ++d) mmax = std::max(mmax, B.f[q].m[d]);
-  if (mmax <= kFdLdsMax) {
+  if (fd_batch_in_lds(B)) {
     // workgroups per mode product: the most any solve needs
     unsigned gx[3] = {1, 1, 1};
     for (int d = 0; d < 3; ++d)

@@ -196,10 +196,14 @@ void precondition(sa_multipatch *h, const Schwarz &as, const double *inv_diag, i
     sa::launch_jacobi(st, n, inv_diag, r, z, part, const_cast<sa::PcgScalars *>(sc));
     return;
   }
-  sa::launch_mp_as_gather(st, as.total, as.gidx, r, as.rp, sc);
-  if (as.batched) {
-    sa::launch_fd_batch(st, as.batch, as.total, as.rp, as.zp, sc);
+  if (as.batched && as.batch.gidx) {
+    // the batched solves gather their inputs from r themselves
+    sa::launch_fd_batch(st, as.batch, r, as.zp, sc);
+  } else if (as.batched) {
+    sa::launch_mp_as_gather(st, as.total, as.gidx, r, as.rp, sc);
+    sa::launch_fd_batch(st, as.batch, as.rp, as.zp, sc);
   } else {
+    sa::launch_mp_as_gather(st, as.total, as.gidx, r, as.rp, sc);
     for (size_t p = 0; p < as.fd.size(); ++p)
       sa::launch_fd(st, as.fd[p], as.len[p], as.rp + as.off[p], as.zp + as.off[p], nullptr,
                     const_cast<sa::PcgScalars *>(sc));
@@ -286,6 +290,9 @@ void setup_schwarz(sa_multipatch *h, Schwarz &as, const std::vector<const sa::Fd
   as.pos = mp_upload(h->owned, pos, st);
   as.rp = mp_alloc<double>(h->owned, (size_t)as.total);
   as.zp = mp_alloc<double>(h->owned, (size_t)as.total);
+  // the entries outside the patches' boxes: zero for good (the batched
+  // solves write only their boxes; the one-patch solves zero them again)
+  mp_check(hipMemsetAsync(as.zp, 0, (size_t)std::max<int64_t>(as.total, 1) * sizeof(double), st), "memset");
   for (size_t p = 0; p < np; ++p) {
     const sa::FdData &D = *fds[p];
     sa::FdOp &F = as.fd[p];
@@ -307,6 +314,7 @@ void setup_schwarz(sa_multipatch *h, Schwarz &as, const std::vector<const sa::Fd
       as.batch.f[p] = as.fd[p];
       as.batch.off[p] = as.off[p];
     }
+    as.batch.gidx = sa::fd_batch_in_lds(as.batch) ? as.gidx : nullptr;
   }
   as.on = true;
 }
