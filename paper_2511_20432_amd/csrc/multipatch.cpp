@@ -113,7 +113,7 @@ sa::Csr csr_from_triples(int64_t nrow, std::vector<int64_t> &r, std::vector<int6
 // arrays, ticks non-decreasing), its step, its state and its statistics
 struct MpPath {
   int64_t src0 = 0, n_src = 0, n_steps = 0, step = 0;
-  double *T = nullptr, *G = nullptr, *LD = nullptr;   // boundary fields of the last step
+  double *T = nullptr, *G = nullptr;   // boundary fields of the last completed step
   double *w = nullptr, *F = nullptr, *F1 = nullptr, *vD = nullptr, *vDn = nullptr;
   int64_t pcg_its = 0, dir_its = 0;
   double last_relres = 0.0;
@@ -147,8 +147,9 @@ struct sa_multipatch {
   float *c32 = nullptr;
   double *part = nullptr;
   int64_t part_cap = 0;
-  // device: work shared by the paths (the state is per path)
-  double *bD = nullptr;
+  // device: work shared by the paths (the state is per path); the step's
+  // boundary fields go to Tw, Gw and become the path's when the step completes
+  double *Tw = nullptr, *Gw = nullptr, *LD = nullptr, *bD = nullptr;
   double *Bw = nullptr, *AIDvD = nullptr, *bI = nullptr, *xI = nullptr;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double *part_b = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_rr = nullptr;
@@ -363,12 +364,12 @@ void mp_step_one(sa_multipatch *h, MpPath &P) {
   if (nch > 0)
     sa::launch_sum(st, pl, tab, h->px, h->py, h->pz, h->pq2, h->fx, h->fy, h->fz, h->fq2, h->c64, h->c32, h->part);
   sa::launch_finalize(st, tab, true, h->nq, nch, h->stride, h->part, h->px, h->py, h->pz, h->nx, h->ny, h->nz, h->wdS,
-                      h->role, h->mat.k, h->stride, P.T, P.G, P.LD, nullptr, 0);
+                      h->role, h->mat.k, h->stride, h->Tw, h->Gw, h->LD, nullptr, 0);
   // load vector (Eq. 18) and the Dirichlet projection (Eq. 11)
-  sa::launch_gather(st, h->load.nrow, h->load.rowptr, h->load.col, h->load.val, P.LD, P.F1);
+  sa::launch_gather(st, h->load.nrow, h->load.rowptr, h->load.col, h->load.val, h->LD, P.F1);
   double rel = 0.0;
   if (h->nD > 0) {
-    sa::launch_gather(st, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, P.LD, h->bD);
+    sa::launch_gather(st, h->dproj.nrow, h->dproj.rowptr, h->dproj.col, h->dproj.val, h->LD, h->bD);
     mp_check(hipMemcpyAsync(P.vDn, P.vD, h->nD * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
     P.dir_its += cg_solve(h, h->mdir.op(), h->as_dir, h->mdir_inv, h->bD, P.vDn, &rel);
   }
@@ -383,6 +384,8 @@ void mp_step_one(sa_multipatch *h, MpPath &P) {
   sa::launch_mp_commit(st, h->nI, h->I_idx, h->xI, h->nD, h->D_idx, P.vDn, P.w);
   std::swap(P.F, P.F1);
   std::swap(P.vD, P.vDn);
+  std::swap(P.T, h->Tw);
+  std::swap(P.G, h->Gw);
   mp_check(hipGetLastError(), "kernel launch");
   P.step = s1;
 }
@@ -704,13 +707,15 @@ void setup(sa_multipatch *h, const sa_patch *patches, int32_t n_patches, const i
   for (MpPath &P : h->paths) {
     P.T = zeros(h->stride);
     P.G = zeros(3 * h->stride);
-    P.LD = zeros(h->stride);
     P.w = zeros(nd);
     P.F = zeros(nd);
     P.F1 = zeros(nd);
     P.vD = zeros(h->nD);
     P.vDn = zeros(h->nD);
   }
+  h->Tw = zeros(h->stride);
+  h->Gw = zeros(3 * h->stride);
+  h->LD = zeros(h->stride);
   h->Bw = zeros(nd);
   h->bD = zeros(h->nD);
   h->AIDvD = zeros(h->nI);

@@ -11,7 +11,8 @@ both interfaces.
   * a finer L-shaped part (9,360 unknowns) over 60 steps within 1e-9;
   * the additive Schwarz and the Jacobi preconditioners on the same steps;
   * two scan paths in one object, each against the oracle, the second
-    bitwise equal to an object that holds it alone.
+    bitwise equal to an object that holds it alone;
+  * a failed solve leaves the last completed step's state.
 """
 import numpy as np
 import pytest
@@ -240,3 +241,22 @@ def test_l_part_several_paths():
         with pytest.raises(sa_iga.SaError) as e:
             gm.boundary_fields(bad)
         assert e.value.code == sa_iga.SA_ERANGE
+
+
+def test_failed_solve_keeps_the_last_completed_step():
+    """A CG that cannot reach pcg_rtol (1e-30, below FP64 rounding) within
+    pcg_max_iter (8) gives SA_ENOCONV on the first step, and
+    the path keeps the state before it: step 0, zero boundary fields (the
+    step's source field is not published), F, control values and solver
+    statistics."""
+    from paper_2511_20432_amd import sa_iga
+    w = W.l_part()
+    bad = sa_iga.MultiPatchModel(w.patches, w.maps, w.material, w.scan,
+                                 W.Options(tau_near=2e-4, pcg_rtol=1e-30, pcg_max_iter=8))
+    with pytest.raises(sa_iga.SaError) as e:
+        bad.step(1)
+    assert e.value.code == sa_iga.SA_ENOCONV
+    info = bad.get_info()
+    assert info.step == 0 and info.pcg_iterations == 0 and info.dirichlet_iterations == 0
+    for a in bad.boundary_fields():
+        assert np.array_equal(a, np.zeros_like(a))
