@@ -614,7 +614,7 @@ def main():
     ap.add_argument("--steps", type=int, default=60, help="timed batched steps of the headline window")
     ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
     ap.add_argument("--legs", default="headline,batch,raster,annulus,small,paper,multipatch",
-                    help="comma-separated subset of headline,batch,raster,annulus,small,paper")
+                    help="comma-separated subset of headline,batch,raster,annulus,small,paper,multipatch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device five times (the reference kernel of the HBM "
