@@ -206,8 +206,11 @@ void launch_stencil_apply_dot(hipStream_t st, const StencilOp &A, const double *
 void launch_csr_apply_dot(hipStream_t st, const CsrOp &A, const double *p, double *q, double *part,
                           PcgScalars *sc);
 // alpha = rz / sum(part_pq); x += alpha p; r -= alpha q; partials of r.r
-void launch_pcg_update(hipStream_t st, int64_t n, int n_part, const double *part_pq, const double *p,
-                       const double *q, double *x, double *r, double *part_rr, PcgScalars *sc);
+// (rz = sum(part_rz), the partials of the last preconditioning, n_part_rz of
+// them; stored in sc for the direction update that follows)
+void launch_pcg_update(hipStream_t st, int64_t n, int n_part, const double *part_pq, int n_part_rz,
+                       const double *part_rz, const double *p, const double *q, double *x, double *r,
+                       double *part_rr, PcgScalars *sc);
 // convergence check on sum(part_rr); beta = sum(part_rz)/rz; p = z + beta p
 void launch_pcg_direction(hipStream_t st, int64_t n, int n_part_rr, int n_part_rz, const double *part_rr,
                           const double *part_rz, const double *z, double *p, PcgScalars *sc);

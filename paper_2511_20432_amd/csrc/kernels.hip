@@ -1359,16 +1359,22 @@ void launch_csr_apply_dot(hipStream_t st, const CsrOp &A, const double *p, doubl
   hipLaunchKernelGGL(k_dot_parts, dim3((unsigned)parts_for(A.nrow)), dim3(kBlock), 0, st, A.nrow, p, q, part, sc);
 }
 
-__global__ void k_pcg_update(int64_t n, int n_part, const double *__restrict__ part_pq,
-                             const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ x,
-                             double *__restrict__ r, double *__restrict__ part_rr, PcgScalars *sc) {
+// r . z of the iteration is summed here from the preconditioner's partials
+// (the same fixed-order sum as in k_pcg_start) and stored for
+// k_pcg_direction, a later launch: no block of a launch reads what another
+// block of it writes
+__global__ void k_pcg_update(int64_t n, int n_part, const double *__restrict__ part_pq, int n_part_rz,
+                             const double *__restrict__ part_rz, const double *__restrict__ p,
+                             const double *__restrict__ q, double *__restrict__ x, double *__restrict__ r,
+                             double *__restrict__ part_rr, PcgScalars *sc) {
   if (sc->done) return;
   const double pq = reduce_parts(part_pq, n_part);
   if (!(pq > 0.0)) {  // breakdown: the operator is not positive on p
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
     return;
   }
-  const double alpha = sc->rz / pq;
+  const double rz = reduce_parts(part_rz, n_part_rz);
+  const double alpha = rz / pq;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] = fma(alpha, p[i], x[i]);
@@ -1378,13 +1384,18 @@ __global__ void k_pcg_update(int64_t n, int n_part, const double *__restrict__ p
   }
   const double s = block_sum(acc);
   if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->alpha = alpha;
+    sc->rz = rz;
+  }
 }
 
-void launch_pcg_update(hipStream_t st, int64_t n, int n_part, const double *part_pq, const double *p,
-                       const double *q, double *x, double *r, double *part_rr, PcgScalars *sc) {
+void launch_pcg_update(hipStream_t st, int64_t n, int n_part, const double *part_pq, int n_part_rz,
+                       const double *part_rz, const double *p, const double *q, double *x, double *r,
+                       double *part_rr, PcgScalars *sc) {
   dim3 g((unsigned)parts_for(n));
-  hipLaunchKernelGGL(k_pcg_update, g, dim3(kBlock), 0, st, n, n_part, part_pq, p, q, x, r, part_rr, sc);
+  hipLaunchKernelGGL(k_pcg_update, g, dim3(kBlock), 0, st, n, n_part, part_pq, n_part_rz, part_rz, p, q, x, r,
+                     part_rr, sc);
 }
 
 __global__ void k_pcg_direction(int64_t n, int n_part_rr, int n_part_rz, const double *__restrict__ part_rr,
@@ -1394,28 +1405,18 @@ __global__ void k_pcg_direction(int64_t n, int n_part_rr, int n_part_rz, const d
   const double rr = reduce_parts(part_rr, n_part_rr);
   const double rz_new = reduce_parts(part_rz, n_part_rz);
   const bool conv = rr <= sc->rtol2 * sc->bnorm2;
+  // sc->rz (the previous r . z) was stored by k_pcg_update and is not
+  // written here; the next k_pcg_update sums rz_new again from part_rz
   const double beta = rz_new / sc->rz;
   if (!conv) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
       p[i] = fma(beta, p[i], z[i]);
   }
-  // every block has read sc->rz above; make sure before block 0 overwrites it
-  __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->rr = rr;
+    sc->beta = beta;
     sc->iter = sc->iter + 1;
     if (conv) sc->done = 1;
-  }
-}
-
-// Direction update is split so that no block reads sc->rz after block 0 has
-// replaced it: the new r.z is stored into sc by a second tiny kernel.
-__global__ void k_pcg_commit(int n_part, const double *__restrict__ part_rz, PcgScalars *sc) {
-  if (sc->done) return;
-  const double rz_new = reduce_parts(part_rz, n_part);
-  if (threadIdx.x == 0) {
-    sc->beta = rz_new / sc->rz;
-    sc->rz = rz_new;
   }
 }
 
@@ -1424,7 +1425,6 @@ void launch_pcg_direction(hipStream_t st, int64_t n, int n_part_rr, int n_part_r
   dim3 g((unsigned)parts_for(n));
   hipLaunchKernelGGL(k_pcg_direction, g, dim3(kBlock), 0, st, n, n_part_rr, n_part_rz, part_rr, part_rz, z, p,
                      sc);
-  hipLaunchKernelGGL(k_pcg_commit, dim3(1), dim3(kBlock), 0, st, n_part_rz, part_rz, sc);
 }
 
 }  // namespace sa

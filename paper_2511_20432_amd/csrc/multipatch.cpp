@@ -230,7 +230,7 @@ int cg_solve(sa_multipatch *h, const sa::CsrOp &A, const Schwarz &as, const doub
   for (;;) {
     for (int k = 0; k < chunk; ++k) {
       sa::launch_csr_apply_dot(st, A, h->p, h->q, h->part_pq, h->sc);
-      sa::launch_pcg_update(st, n, np, h->part_pq, h->p, h->q, x, h->r, h->part_rr, h->sc);
+      sa::launch_pcg_update(st, n, np, h->part_pq, np, h->part_rz, h->p, h->q, x, h->r, h->part_rr, h->sc);
       precondition(h, as, inv_diag, n, h->r, h->z, h->part_rz, h->sc);
       sa::launch_pcg_direction(st, n, np, np, h->part_rr, h->part_rz, h->z, h->p, h->sc);
     }

@@ -551,7 +551,8 @@ int pcg_run(sa_iga *h, PcgSpec &s, double *relres) {
     for (int k = 0; k < chunk; ++k) {
       if (s.stencil) sa::launch_stencil_apply_dot(h->stream, s.st, s.p, s.q, h->part_pq, h->sc_gen);
       else sa::launch_csr_apply_dot(h->stream, s.csr, s.p, s.q, h->part_pq, h->sc_gen);
-      sa::launch_pcg_update(h->stream, n, np, h->part_pq, s.p, s.q, s.x, s.r, h->part_rr, h->sc_gen);
+      sa::launch_pcg_update(h->stream, n, np, h->part_pq, np_rz, h->part_rz, s.p, s.q, s.x, s.r, h->part_rr,
+                            h->sc_gen);
       np_rz = apply_precond(h, s, s.r, s.z, h->sc_gen);
       sa::launch_pcg_direction(h->stream, n, np, np_rz, h->part_rr, h->part_rz, s.z, s.p, h->sc_gen);
     }
