@@ -18,8 +18,9 @@ void launch_mp_commit(hipStream_t st, int64_t nI, const int64_t *I, const double
 
 struct PcgScalars;
 
-// additive Schwarz over the patches, the two ends (the local solves are
-// launch_fd on each patch's vector in between):
+// additive Schwarz over the patches, the two ends (the local solves run in
+// between: launch_fd_batch, whose in-LDS form reads r through gidx itself
+// and needs no gather, or launch_fd on each patch's vector):
 //   gather:  rp[k] = r[gidx[k]] (gidx[k] >= 0), else 0, over the patches'
 //            concatenated vectors (n entries)
 //   combine: z[i] = sum of zp[pos[e]] over e in [rowptr[i], rowptr[i+1])
